@@ -1,0 +1,269 @@
+/*
+ * fabric.h -- C ABI of the MI355X (gfx950) woven-fabric shading library.
+ *
+ * The library evaluates, per pixel of a G-buffer, the footprint-filtered
+ * reflectance of a woven fabric in two ways:
+ *   - neurally: a material latent z (from an encoder of the weave pattern and
+ *     yarn parameters) and the pixel's query -- pattern-tiled uv, footprint
+ *     radius, light direction wi and view direction wo -- go through a small
+ *     decoder MLP that predicts the four components (C_warp, C_weft, S_warp,
+ *     S_weft) of Chen, Wang and Wang, "Real-time Neural Woven Fabric
+ *     Rendering" (SIGGRAPH 2024), Sec. 4.1 Eq. (7); the reflectance is their
+ *     albedo-weighted sum, Eq. (8);
+ *   - analytically: the point shading model of Eq. (1)-(2) integrated over the
+ *     pixel footprint with the aggregation of Eq. (3)-(5) (visibility V = 1) by
+ *     stratified Monte-Carlo samples.  This produces the decoder's training
+ *     targets (Sec. 4.2, "Loss functions") and serves as its ground truth and
+ *     fallback.
+ *
+ * Conventions shared by every entry point:
+ *   - Frames and units.  The macro surface normal is +z.  u runs along +x
+ *     (the weft direction), v along +y (the warp direction).  uv and the
+ *     footprint radius are in weave cells (one warp x weft crossing = 1).
+ *     Directions are unit vectors with z > 0 (reflection only).
+ *   - Memory.  Pointers named "device" point to GPU memory of the context's
+ *     device; the caller owns them.  "host" pointers are CPU memory.  The
+ *     context owns its weights, latents, optimiser state and scratch.
+ *   - Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream).  Work is enqueued asynchronously on it; only calls that return
+ *     host data synchronise.
+ *   - Errors.  Every call validates its arguments first and, on failure,
+ *     returns a status without enqueuing work.  No C++ exception crosses
+ *     the ABI.  Per-pixel input faults (a non-finite field, wi.z <= 0,
+ *     wo.z <= 0, radius <= 0, fabric_id >= fabrics encoded) do not fail the
+ *     call: the pixel's outputs are written as 0 and a device counter is
+ *     incremented (read it with fabric_error_count).
+ *   - Threading.  A context is not thread-safe; distinct contexts are
+ *     independent.
+ *   - Determinism.  For fixed inputs and seeds every result is bitwise
+ *     repeatable: reductions run in a fixed order.
+ */
+#ifndef FABRIC_H
+#define FABRIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fabric_ctx fabric_ctx;
+
+typedef enum {
+    FABRIC_OK = 0,
+    FABRIC_E_INVAL = 1,      /* NULL required pointer, bad size or value */
+    FABRIC_E_RANGE = 2,      /* a size or count beyond the library's limits */
+    FABRIC_E_NOMEM = 3,      /* device allocation failed */
+    FABRIC_E_DEVICE = 4,     /* a HIP runtime call failed */
+    FABRIC_E_NONFINITE = 5,  /* a training step met a non-finite loss; nothing was updated */
+    FABRIC_E_STATE = 6       /* call order: e.g. shading before any fabric was encoded */
+} fabric_status;
+
+/* Arithmetic of the decoder's dense layers (all accumulate in FP32). */
+typedef enum {
+    FABRIC_FP32 = 0,
+    FABRIC_BF16 = 1,
+    FABRIC_FP16 = 2,
+    FABRIC_FP8_E4M3 = 3      /* OCP E4M3 operands with one scale per layer */
+} fabric_prec;
+
+#define FABRIC_MAX_FABRICS 256
+#define FABRIC_MAX_PERIOD 16
+#define FABRIC_LATENT 32
+#define FABRIC_N_DECODER_PARAMS 13572
+#define FABRIC_N_ENCODER_PARAMS 104352
+#define FABRIC_N_PARAMS (FABRIC_N_DECODER_PARAMS + FABRIC_N_ENCODER_PARAMS)
+#define FABRIC_MAX_SAMPLES 16384
+
+/* One fabric: the weave pattern and the Table 1 parameters per yarn type
+ * ([0] = warp, [1] = weft).  Host memory, copied by fabric_encode.
+ *   wx, wy       pattern period in cells, 1..16 each
+ *   pattern      P[j][i] at pattern[j * wx + i] (first wx*wy bytes):
+ *                1 = the warp yarn is on top at column i, row j; 0 = weft
+ *   alpha        roughness of the fiber microflake (Eq. (2)), in (0, 1]
+ *   beta         height-field scaling, >= 0
+ *   twist        twist angle psi (radians), inclination incl = u (radians)
+ *   gap          fraction of a cell not covered by the yarn, in [0, 0.9]
+ *   wblend       blend weight w of the two Lambertian terms (Eq. (1)), in [0, 1]
+ *   kd, ks       RGB diffuse and specular albedos (Eq. (8)); not network
+ *                inputs, so editing them needs no re-encode (Sec. 4.3). */
+typedef struct {
+    uint8_t wx, wy;
+    uint8_t pattern[256];
+    float alpha[2], beta[2], twist[2], incl[2], gap[2], wblend[2];
+    float kd[2][3], ks[2][3];
+} fabric_material;
+
+/* A G-buffer of n pixels as device structure-of-arrays, one element per pixel
+ * in every array.  fabric_id indexes the fabrics passed to fabric_encode.
+ * The library only reads these arrays. */
+typedef struct {
+    int64_t n;
+    const uint16_t *fabric_id;
+    const float *u, *v, *radius;
+    const float *wi_x, *wi_y, *wi_z, *wo_x, *wo_y, *wo_z;
+} fabric_gbuffer;
+
+/* Mutable G-buffer, the output of fabric_make_batch. */
+typedef struct {
+    int64_t n;
+    uint16_t *fabric_id;
+    float *u, *v, *radius;
+    float *wi_x, *wi_y, *wi_z, *wo_x, *wo_y, *wo_z;
+} fabric_gbuffer_out;
+
+/* One training step's settings (fabric_train_step). */
+typedef struct {
+    int64_t batch;        /* samples drawn when no batch is passed, >= 1 */
+    int32_t gt_samples;   /* footprint samples of the analytic targets (perfect square) */
+    int32_t prec;         /* fabric_prec of the decoder's forward/backward: FP32 or BF16 */
+    uint64_t seed;        /* seed of this step's batch and target samples */
+    double lr;            /* Adam learning rate of this step */
+    double beta1, beta2, eps;   /* Adam constants, e.g. 0.9, 0.999, 1e-8 */
+    float r_lo, r_hi;     /* footprint radius range (cells) of generated batches */
+} fabric_train_cfg;
+
+/* Create a context on HIP device `device`.  Network parameters are drawn
+ * Kaiming-uniform from `seed` (biases 0); Adam moments start at 0.
+ * *out receives the context (NULL on failure). */
+fabric_status fabric_create(fabric_ctx **out, int device, uint64_t seed);
+
+/* Release every device allocation of the context (waits for its device). */
+void fabric_destroy(fabric_ctx *ctx);
+
+/* A static, human-readable name of a status. */
+const char *fabric_status_str(fabric_status s);
+
+/* Set the fabric table and run the encoder (Sec. 4.2 "Encoder", Sec. 4.3
+ * "Rendering": every material is encoded once before shading).  mats: host
+ * array of n_mats (1..FABRIC_MAX_FABRICS) fabrics.  Computes each latent z_f
+ * and the decoder's first-layer bias folded with it, c_f = W1_z z_f + b1.
+ * Returns E_INVAL on an out-of-range field. */
+fabric_status fabric_encode(fabric_ctx *ctx, const fabric_material *mats, int32_t n_mats,
+                            void *stream);
+
+/* Albedo edit without re-encoding (Sec. 4.3 "Editing"): replace kd, ks of
+ * fabric `fabric` (host arrays [2][3]). */
+fabric_status fabric_set_albedo(fabric_ctx *ctx, int32_t fabric, const float kd[2][3],
+                                const float ks[2][3], void *stream);
+
+/* Neural shading of a G-buffer (Sec. 4.3 "Rendering"): per pixel, the
+ * decoder's four outputs decoded as C = max(y, 0), S = max((e^y - 1)/100, 0)
+ * (inverse of the specular mapping of Eq. (9)) and composed with Eq. (8).
+ *   prec              arithmetic of the dense layers
+ *   fallback_samples  0: every pixel is shaded by the decoder.  > 0 (a perfect
+ *                     square <= FABRIC_MAX_SAMPLES): pixels outside the
+ *                     network's range (radius > 1 cell or wo.z < 0.05) are
+ *                     instead shaded in the same launch by the analytic
+ *                     footprint filter with that many samples, keyed by `seed`
+ *                     and the pixel index exactly as fabric_gt_filtered.
+ *   out_rgb           device float [3][n] (R plane, G plane, B plane).
+ * Requires fabric_encode after the last weight change (else E_STATE). */
+fabric_status fabric_shade_gbuffer(fabric_ctx *ctx, const fabric_gbuffer *g, fabric_prec prec,
+                                   int32_t fallback_samples, uint64_t seed, float *out_rgb,
+                                   void *stream);
+
+/* Footprint-filtered analytic shading (Eq. (3)-(5), V = 1; components of
+ * Eq. (7)).  Pixel p's footprint is the disk of radius radius[p] about
+ * (u[p], v[p]) with a uniform kernel; n_samples = m*m stratified samples,
+ * stratum k = ky*m + kx jittered by the (p*n_samples + k)-th output of
+ * SplitMix64 seeded with `seed` (upper 24 bits for x, bits 39..16 for y) and
+ * mapped to the disk with the Shirley-Chiu concentric map.  Per sample:
+ * rho = f * <wi.n_p> and projected area <wo.n_p>/<n_s.n_p> (holes: wo.z);
+ * C_y = sum[yarn = y] rho_d A / sum A, S_y likewise, summed in FP64.
+ *   out_comp  device float [4][n] (C_warp, C_weft, S_warp, S_weft) or NULL
+ *   out_rgb   device float [3][n] (Eq. (8)) or NULL (not both NULL). */
+fabric_status fabric_gt_filtered(fabric_ctx *ctx, const fabric_gbuffer *g, int32_t n_samples,
+                                 uint64_t seed, float *out_rgb, float *out_comp, void *stream);
+
+/* Decoder forward with explicit parameters (for autograd wrappers).
+ *   dec_params  device float [FABRIC_N_DECODER_PARAMS]: W1[64][72] b1[64]
+ *               W2[64][64] b2[64] W3[64][69] b3[64] W4[4][64] b4[4], rows =
+ *               output units; W1's columns are [z(32), s(40)], W3's
+ *               [h2(64), wi.x, wi.y, wi.z, wo.x, wo.y]
+ *   latents     device float [n_mats][32]
+ *   y4          device float [4][n]: raw outputs (C_warp, C_weft, S_warp, S_weft
+ *               in the log-mapped domain of Eq. (9)).
+ * prec is FABRIC_FP32 or FABRIC_BF16.  Uses the fabric table of the last
+ * fabric_encode for the pattern periods. */
+fabric_status fabric_decoder_forward(fabric_ctx *ctx, const fabric_gbuffer *g, fabric_prec prec,
+                                     const float *dec_params, const float *latents, float *y4,
+                                     void *stream);
+
+/* Decoder backward: given dL/dy4 (device [4][n]), write dL/d(dec_params)
+ * (device float [FABRIC_N_DECODER_PARAMS], overwritten) and dL/dlatents
+ * (device float [n_mats][32], overwritten).  FP32 arithmetic; the sums over
+ * pixels are reduced in a fixed order. */
+fabric_status fabric_decoder_backward(fabric_ctx *ctx, const fabric_gbuffer *g,
+                                      const float *dec_params, const float *latents,
+                                      const float *grad_y4, float *grad_params,
+                                      float *grad_latents, void *stream);
+
+/* Encoder forward with explicit parameters over the encoded fabric table:
+ * enc_params device float [FABRIC_N_ENCODER_PARAMS]; latents device [n_mats][32]. */
+fabric_status fabric_encoder_forward(fabric_ctx *ctx, const float *enc_params, float *latents,
+                                     void *stream);
+
+/* Encoder backward: dL/dlatents (device [n_mats][32]) -> dL/d(enc_params)
+ * (device float [FABRIC_N_ENCODER_PARAMS], overwritten). */
+fabric_status fabric_encoder_backward(fabric_ctx *ctx, const float *enc_params,
+                                      const float *grad_latents, float *grad_enc_params,
+                                      void *stream);
+
+/* Draw a training batch: sample q takes the outputs 8q..8q+4 of SplitMix64
+ * seeded with `seed`: fabric id = (z >> 32) mod n_mats; (u, v) = 8 * two
+ * 24-bit uniforms; radius log-uniform on [r_lo, r_hi]; wi and wo
+ * cosine-weighted from two 24-bit uniforms each.  out arrays: device, n each. */
+fabric_status fabric_make_batch(fabric_ctx *ctx, uint64_t seed, int64_t n, float r_lo,
+                                float r_hi, const fabric_gbuffer_out *out, void *stream);
+
+/* One optimisation step of encoder + decoder on the encoded fabric table:
+ * loss of Eq. (9)-(11) (lambda_S = 0.4, lambda_C = 0.1, k = 100), gradients
+ * by hand-written backward kernels, Adam with FP64 moments on FP32 masters.
+ *   batch        device G-buffer, or NULL to draw cfg->batch samples with
+ *                fabric_make_batch(cfg->seed)
+ *   targets      device float [4][n] components (only with a batch), or NULL
+ *                to compute them with the analytic filter (cfg->gt_samples
+ *                samples, seed cfg->seed ^ 1)
+ *   out_loss     host float, or NULL for no synchronisation
+ * A non-finite loss leaves weights and moments unchanged and returns
+ * E_NONFINITE (only detectable when out_loss is given).  After a step,
+ * shading needs fabric_encode again (E_STATE otherwise). */
+fabric_status fabric_train_step(fabric_ctx *ctx, const fabric_gbuffer *batch,
+                                const float *targets, const fabric_train_cfg *cfg,
+                                float *out_loss, void *stream);
+
+/* Loss of Eq. (9)-(11) and its gradient with respect to all parameters,
+ * without an update: the first half of fabric_train_step (same arguments and
+ * batch/target rules).  grad: device float [FABRIC_N_PARAMS] (overwritten),
+ * laid out like fabric_get_params.  out_loss: host float or NULL. */
+fabric_status fabric_loss_grad(fabric_ctx *ctx, const fabric_gbuffer *batch, const float *targets,
+                               const fabric_train_cfg *cfg, float *grad, float *out_loss,
+                               void *stream);
+
+/* Parameters as one FP32 vector [FABRIC_N_PARAMS] = [decoder | encoder]
+ * (layouts as in fabric_decoder_forward and fabric_encoder_forward; encoder:
+ * E1[128][524] c1 E2[128][128] c2 E3[128][128] c3 E4[32][128] c4).  host
+ * memory; both synchronise.  set resets nothing else (Adam state persists). */
+fabric_status fabric_get_params(fabric_ctx *ctx, float *host, size_t count);
+fabric_status fabric_set_params(fabric_ctx *ctx, const float *host, size_t count);
+
+/* Latents of the encoded fabrics, host float [n_mats][32] (synchronises). */
+fabric_status fabric_get_latents(fabric_ctx *ctx, float *host, int32_t n_mats);
+
+/* Checkpoint: parameters, Adam moments and step as one little-endian blob
+ * (magic "FABRICK1", version, counts).  With host == NULL, *bytes receives the
+ * size needed; otherwise *bytes must hold at least that.  Both synchronise. */
+fabric_status fabric_save(fabric_ctx *ctx, void *host, size_t *bytes);
+fabric_status fabric_load(fabric_ctx *ctx, const void *host, size_t bytes);
+
+/* Number of pixel faults counted since the last reset (synchronises);
+ * reset != 0 clears the counter. */
+int64_t fabric_error_count(fabric_ctx *ctx, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FABRIC_H */

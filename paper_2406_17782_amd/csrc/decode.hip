@@ -1,0 +1,343 @@
+// Neural shading (Sec. 4.2 decoder, Sec. 4.3 rendering) on MFMA.
+//
+// Each wavefront keeps the whole packed decoder in registers and walks
+// 16-pixel tiles of the G-buffer.  Per tile it loads the pixels' SoA fields,
+// builds the spatial encoding (8 Fourier frequencies of the pattern-tiled uv,
+// one-blob of the footprint size) directly in the MFMA B-operand layout, runs
+// the four dense layers as 16x16xK MFMA tiles (M = neurons, N = pixels) with
+// the per-fabric first-layer bias c_f (latent folded in) read from LDS, and
+// finally decodes and albedo-composes the four components (Eq. (8)).  A
+// layer's accumulators feed the next layer's B operand in place (see the slot
+// convention in common.hpp), so no data moves between lanes or through LDS
+// between layers.
+//
+// With fallback routing, pixels outside the network's training range are
+// shaded in the same launch by the analytic footprint filter: the wave that
+// owns the tile evaluates them one at a time with all 64 lanes.
+#include "kernels.hpp"
+#include "mlp_tile.hpp"
+
+namespace fab {
+
+namespace {
+
+constexpr int kFabConsts = 16;   // per fabric in LDS: fwx fwy 1/wx 1/wy kd[2][3] ks[2][3]
+
+// Out-of-range rule of the hybrid frame: footprint above one cell or a
+// grazing view.
+__device__ inline bool out_of_range(float r, float wo_z) { return r > 1.0f || wo_z < 0.05f; }
+
+template <int P, bool RAW, bool HYBRID>
+__global__ __launch_bounds__(256) void decode_kernel(
+    fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
+    const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ frags,
+    const f32x4 *__restrict__ bias, int fb_samples, int fb_side, float fb_inv_side,
+    uint64_t seed, float *__restrict__ out, unsigned long long *err, int64_t n_tiles)
+{
+    using T = Tile<P>;
+    using Frag = typename T::Frag;
+    using S = typename T::S;
+
+    extern __shared__ float smem[];
+    float *s_cf = smem;                       // [n_fabrics][64]
+    float *s_fc = smem + n_fabrics * 64;      // [n_fabrics][kFabConsts]
+    for (int k = threadIdx.x; k < n_fabrics * 64; k += blockDim.x)
+        s_cf[k] = cfold[k];
+    for (int k = threadIdx.x; k < n_fabrics * kFabConsts; k += blockDim.x) {
+        const DevFabric &f = fabrics[k / kFabConsts];
+        int c = k % kFabConsts;
+        float val;
+        if (c == 0) val = f.fwx;
+        else if (c == 1) val = f.fwy;
+        else if (c == 2) val = f.inv_wx;
+        else if (c == 3) val = f.inv_wy;
+        else if (c < 10) val = f.kd[(c - 4) / 3][(c - 4) % 3];
+        else val = f.ks[(c - 10) / 3][(c - 10) % 3];
+        s_fc[k] = val;
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 4;
+    const int col = lane & 15;
+
+    Frag A[S::NFRAG];
+#pragma unroll
+    for (int q = 0; q < S::NFRAG; q++)
+        A[q] = frags[q * 64 + lane];
+    f32x4 bb[kBiasFrags];
+#pragma unroll
+    for (int q = 0; q < kBiasFrags; q++)
+        bb[q] = bias[q * 64 + lane];
+    auto getA = [&](int q) { return A[q]; };
+    auto getBias = [&](int q) { return bb[q]; };
+
+    const int64_t n = g.n;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+
+    for (int64_t tile = wave_id; tile < n_tiles; tile += waves) {
+        const int64_t p = tile * 16 + col;
+        const bool valid = p < n;
+        const int64_t pc = valid ? p : n - 1;
+        int fid = g.fabric_id[pc];
+        float u = g.u[pc], v = g.v[pc], r = g.radius[pc];
+        float3 wi = make_float3(g.wi_x[pc], g.wi_y[pc], g.wi_z[pc]);
+        float3 wo = make_float3(g.wo_x[pc], g.wo_y[pc], g.wo_z[pc]);
+        const bool fault = pixel_fault(fid, n_fabrics, u, v, r, wi, wo);
+        if (fault) {   // keep the arithmetic finite; the outputs are zeroed below
+            fid = 0;
+            u = v = 0.0f;
+            r = 1.0f;
+            wi = wo = make_float3(0.0f, 0.0f, 1.0f);
+        }
+        const float *fc = s_fc + fid * kFabConsts;
+
+        float s1[T::NS1];
+        T::spatial_slots(u, v, r, fc[0], fc[1], fc[2], fc[3], grp, s1);
+        f32x4 cf[4];
+#pragma unroll
+        for (int mb = 0; mb < 4; mb++)
+            cf[mb] = *(const f32x4 *)(s_cf + fid * 64 + 16 * mb + 4 * grp);
+        float ang0, ang1;
+        angular_slots(grp, wi, wo, &ang0, &ang1);
+        f32x4 a1[4], a2[4], a3[4], y;
+        T::forward(getA, getBias, cf, s1, ang0, ang1, a1, a2, a3, y);
+
+        // Lanes 0..15 hold y[0..3] of pixel tile*16 + lane.
+        const bool oor = HYBRID && !fault && out_of_range(r, wo.z);
+        if (grp == 0 && valid && !oor) {
+            if (RAW) {
+#pragma unroll
+                for (int c = 0; c < 4; c++)
+                    out[c * n + p] = fault ? 0.0f : y[c];
+            } else {
+                float cw = fmaxf(y[0], 0.0f), cwf = fmaxf(y[1], 0.0f);
+                float sw = fmaxf(expm1f(y[2]) * (1.0f / kSpec), 0.0f);
+                float sf = fmaxf(expm1f(y[3]) * (1.0f / kSpec), 0.0f);
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    float rgb = fc[4 + c] * cw + fc[7 + c] * cwf + fc[10 + c] * sw + fc[13 + c] * sf;
+                    out[c * n + p] = fault ? 0.0f : rgb;
+                }
+            }
+        }
+        const unsigned long long bad = __ballot(grp == 0 && valid && fault);
+        if (lane == 0 && bad)
+            atomicAdd(err, (unsigned long long)__popcll(bad));
+
+        if (HYBRID) {
+            // Analytic footprint filter for this tile's out-of-range pixels.
+            unsigned long long todo = __ballot(grp == 0 && valid && oor);
+            while (todo) {
+                const int c = __builtin_ctzll(todo);
+                todo &= todo - 1;
+                const int64_t pp = tile * 16 + c;
+                const int ff = __shfl(fid, c, 64);
+                const float uu = __shfl(u, c, 64), vv = __shfl(v, c, 64), rr = __shfl(r, c, 64);
+                const float3 wwi = make_float3(__shfl(wi.x, c, 64), __shfl(wi.y, c, 64),
+                                               __shfl(wi.z, c, 64));
+                const float3 wwo = make_float3(__shfl(wo.x, c, 64), __shfl(wo.y, c, 64),
+                                               __shfl(wo.z, c, 64));
+                double comp[4];
+                filter_pixel_wave(fabrics[ff], seed, (uint64_t)pp, fb_samples, fb_side,
+                                  fb_inv_side, uu, vv, rr, wwi, wwo, lane, comp);
+                if (lane == 0) {
+                    const DevFabric &f = fabrics[ff];
+                    for (int ch = 0; ch < 3; ch++) {
+                        double rgb = (double)f.kd[0][ch] * comp[0] + (double)f.kd[1][ch] * comp[1] +
+                                     (double)f.ks[0][ch] * comp[2] + (double)f.ks[1][ch] * comp[3];
+                        out[ch * n + pp] = (float)rgb;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Fill the fragment image of precision P from FP32 decoder parameters.
+template <int P>
+__global__ void pack_decoder_kernel(const float *__restrict__ params,
+                                    typename Mfma<P>::Frag *__restrict__ frags,
+                                    f32x4 *__restrict__ bias)
+{
+    using M = Mfma<P>;
+    using S = DecShape<M::KPL>;
+    constexpr int KPL = M::KPL;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < S::NFRAG * 64) {
+        const int fr = idx / 64, lane = idx % 64;
+        const int row = lane & 15, grp = lane >> 4;
+        int layer, mb, ks;
+        if (fr < S::FRAG_L2) { layer = 1; mb = (fr - S::FRAG_L1) / S::KS1; ks = (fr - S::FRAG_L1) % S::KS1; }
+        else if (fr < S::FRAG_L3) { layer = 2; mb = (fr - S::FRAG_L2) / S::KS2; ks = (fr - S::FRAG_L2) % S::KS2; }
+        else if (fr < S::FRAG_L4) { layer = 3; mb = (fr - S::FRAG_L3) / S::KS3; ks = (fr - S::FRAG_L3) % S::KS3; }
+        else { layer = 4; mb = 0; ks = fr - S::FRAG_L4; }
+        const int m = 16 * mb + row;
+        typename M::Frag f = M::zero();
+        for (int j = 0; j < KPL; j++) {
+            const int c = ks * KPL + j;
+            float w = 0.0f;
+            if (layer == 1) {
+                int feat = l1_feature(grp, c);
+                if (feat >= 0) w = params[kOffW1 + m * 72 + kLatent + feat];
+            } else if (layer == 2) {
+                if (c < kChainSlots) w = params[kOffW2 + m * 64 + chain_neuron(grp, c)];
+            } else if (layer == 3) {
+                if (c < kChainSlots) {
+                    w = params[kOffW3 + m * 69 + chain_neuron(grp, c)];
+                } else if (c < kL3Slots) {
+                    int a = l3_angular(grp, c - kChainSlots);
+                    if (a >= 0) w = params[kOffW3 + m * 69 + 64 + a];
+                }
+            } else {
+                if (m < 4 && c < kChainSlots) w = params[kOffW4 + m * 64 + chain_neuron(grp, c)];
+            }
+            M::set(f, j, w);
+        }
+        frags[idx] = f;
+    }
+    if (idx < kBiasFrags * 64) {
+        const int bf = idx / 64, lane = idx % 64, grp = lane >> 4;
+        f32x4 b;
+        for (int i = 0; i < 4; i++) {
+            float val;
+            if (bf < 4) val = params[kOffB2 + 16 * bf + 4 * grp + i];
+            else if (bf < 8) val = params[kOffB3 + 16 * (bf - 4) + 4 * grp + i];
+            else val = (4 * grp + i) < 4 ? params[kOffB4 + 4 * grp + i] : 0.0f;
+            b[i] = val;
+        }
+        bias[idx] = b;
+    }
+}
+
+__global__ void fold_latents_kernel(const float *__restrict__ params,
+                                    const float *__restrict__ latents, int n_fabrics,
+                                    float *__restrict__ cfold)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_fabrics * 64)
+        return;
+    const int f = idx / 64, o = idx % 64;
+    float acc = params[kOffB1 + o];
+    for (int k = 0; k < kLatent; k++)
+        acc = fmaf(params[kOffW1 + o * 72 + k], latents[f * kLatent + k], acc);
+    cfold[idx] = acc;
+}
+
+template <int P> size_t image_bytes()
+{
+    using M = Mfma<P>;
+    using S = DecShape<M::KPL>;
+    return (size_t)S::NFRAG * 64 * sizeof(typename M::Frag) + (size_t)kBiasFrags * 64 * sizeof(f32x4);
+}
+
+template <int P> hipError_t pack(const float *params, void *image, hipStream_t stream)
+{
+    using M = Mfma<P>;
+    using S = DecShape<M::KPL>;
+    auto *frags = (typename M::Frag *)image;
+    auto *bias = (f32x4 *)((char *)image + (size_t)S::NFRAG * 64 * sizeof(typename M::Frag));
+    const int total = S::NFRAG * 64 > kBiasFrags * 64 ? S::NFRAG * 64 : kBiasFrags * 64;
+    hipLaunchKernelGGL(pack_decoder_kernel<P>, dim3((total + 255) / 256), dim3(256), 0, stream,
+                       params, frags, bias);
+    return hipGetLastError();
+}
+
+int device_cus()
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+template <int P, bool RAW, bool HYBRID>
+hipError_t decode(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
+                  const float *cfold, const void *image, int fb_samples, uint64_t seed,
+                  float *out, unsigned long long *err, hipStream_t stream)
+{
+    using M = Mfma<P>;
+    using S = DecShape<M::KPL>;
+    const auto *frags = (const typename M::Frag *)image;
+    const auto *bias =
+        (const f32x4 *)((const char *)image + (size_t)S::NFRAG * 64 * sizeof(typename M::Frag));
+    const int64_t n_tiles = (g.n + 15) / 16;
+    const int64_t waves_wanted = n_tiles;
+    int64_t blocks = (waves_wanted + 3) / 4;
+    const int64_t cap = (int64_t)device_cus() * 2;
+    if (blocks > cap)
+        blocks = cap;
+    int side = 1;
+    while (side * side < fb_samples)
+        side++;
+    const size_t lds = (size_t)n_fabrics * (64 + kFabConsts) * sizeof(float);
+    hipLaunchKernelGGL((decode_kernel<P, RAW, HYBRID>), dim3((unsigned)blocks), dim3(256), lds,
+                       stream, g, fabrics, n_fabrics, cfold, frags, bias, fb_samples, side,
+                       1.0f / (float)side, seed, out, err, n_tiles);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t decoder_image_bytes(int prec)
+{
+    switch (prec) {
+    case FABRIC_FP32: return image_bytes<FABRIC_FP32>();
+    case FABRIC_BF16: return image_bytes<FABRIC_BF16>();
+    case FABRIC_FP16: return image_bytes<FABRIC_FP16>();
+    default: return 0;
+    }
+}
+
+hipError_t launch_pack_decoder(int prec, const float *dec_params, void *image, hipStream_t stream)
+{
+    switch (prec) {
+    case FABRIC_FP32: return pack<FABRIC_FP32>(dec_params, image, stream);
+    case FABRIC_BF16: return pack<FABRIC_BF16>(dec_params, image, stream);
+    case FABRIC_FP16: return pack<FABRIC_FP16>(dec_params, image, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fold_latents(const float *dec_params, const float *latents, int n_fabrics,
+                               float *cfold, hipStream_t stream)
+{
+    const int total = n_fabrics * 64;
+    hipLaunchKernelGGL(fold_latents_kernel, dim3((total + 255) / 256), dim3(256), 0, stream,
+                       dec_params, latents, n_fabrics, cfold);
+    return hipGetLastError();
+}
+
+hipError_t launch_decode(int prec, bool raw, const fabric_gbuffer &g, const DevFabric *fabrics,
+                         int n_fabrics, const float *cfold, const void *image,
+                         int fallback_samples, uint64_t seed, float *out,
+                         unsigned long long *err, hipStream_t stream)
+{
+    if (g.n == 0)
+        return hipSuccess;
+    const bool hybrid = !raw && fallback_samples > 0;
+#define FAB_DECODE(PREC)                                                                        \
+    if (raw)                                                                                    \
+        return decode<PREC, true, false>(g, fabrics, n_fabrics, cfold, image, 0, seed, out, err, \
+                                         stream);                                               \
+    if (hybrid)                                                                                 \
+        return decode<PREC, false, true>(g, fabrics, n_fabrics, cfold, image, fallback_samples, \
+                                         seed, out, err, stream);                               \
+    return decode<PREC, false, false>(g, fabrics, n_fabrics, cfold, image, 0, seed, out, err,   \
+                                      stream);
+    switch (prec) {
+    case FABRIC_FP32: { FAB_DECODE(FABRIC_FP32) }
+    case FABRIC_BF16: { FAB_DECODE(FABRIC_BF16) }
+    case FABRIC_FP16: { FAB_DECODE(FABRIC_FP16) }
+    default: return hipErrorInvalidValue;
+    }
+#undef FAB_DECODE
+}
+
+}  // namespace fab

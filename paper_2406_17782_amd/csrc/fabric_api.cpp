@@ -1,0 +1,733 @@
+// C ABI of the fabric library (declared in include/fabric.h): context
+// lifetime, argument validation, host-side fabric tables and the launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.hpp"
+#include "train.hpp"
+
+using namespace fab;
+
+struct fabric_ctx {
+    int device = 0;
+    float *params = nullptr;          // FP32 masters [decoder | encoder]
+    double *adam_m = nullptr;         // FP64 first moments
+    double *adam_v = nullptr;         // FP64 second moments
+    int64_t step = 0;
+    uint64_t weights_version = 1;     // bumped on every parameter change
+
+    int n_mats = 0;
+    std::vector<fabric_material> mats;
+    DevFabric *fabrics = nullptr;     // [FABRIC_MAX_FABRICS]
+    float *enc_inputs = nullptr;      // [FABRIC_MAX_FABRICS][524]
+    float *latents = nullptr;         // [FABRIC_MAX_FABRICS][32]
+    float *cfold = nullptr;           // [FABRIC_MAX_FABRICS][64]
+    uint64_t encoded_version = 0;     // weights_version of the last encode
+
+    void *image[4] = {nullptr, nullptr, nullptr, nullptr};   // packed decoders
+    uint64_t image_version[4] = {0, 0, 0, 0};
+    void *tmp_image = nullptr;        // packing of caller-supplied parameters
+    float *tmp_cfold = nullptr;
+
+    unsigned long long *err = nullptr;
+    TrainScratch train;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess)
+            prev = -1;
+        if (prev != dev)
+            (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0)
+            (void)hipSetDevice(prev);
+    }
+};
+
+hipStream_t as_stream(void *s) { return (hipStream_t)s; }
+
+fabric_status from_hip(hipError_t e)
+{
+    if (e == hipSuccess)
+        return FABRIC_OK;
+    if (e == hipErrorOutOfMemory)
+        return FABRIC_E_NOMEM;
+    return FABRIC_E_DEVICE;
+}
+
+template <typename T> fabric_status dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0)
+        return FABRIC_OK;
+    return from_hip(hipMalloc((void **)p, count * sizeof(T)));
+}
+
+bool finite(float x) { return std::isfinite(x); }
+
+// Validate one fabric; the pattern must hold only 0/1 in its first wx*wy bytes.
+bool valid_material(const fabric_material &m)
+{
+    if (m.wx < 1 || m.wx > FABRIC_MAX_PERIOD || m.wy < 1 || m.wy > FABRIC_MAX_PERIOD)
+        return false;
+    for (int k = 0; k < m.wx * m.wy; k++)
+        if (m.pattern[k] > 1)
+            return false;
+    for (int y = 0; y < 2; y++) {
+        if (!finite(m.alpha[y]) || !(m.alpha[y] > 0.0f) || m.alpha[y] > 1.0f)
+            return false;
+        if (!finite(m.beta[y]) || m.beta[y] < 0.0f)
+            return false;
+        if (!finite(m.twist[y]) || !finite(m.incl[y]) || std::fabs(m.incl[y]) > 1.5f)
+            return false;
+        if (!finite(m.gap[y]) || m.gap[y] < 0.0f || m.gap[y] > 0.9f)
+            return false;
+        if (!finite(m.wblend[y]) || m.wblend[y] < 0.0f || m.wblend[y] > 1.0f)
+            return false;
+        for (int c = 0; c < 3; c++)
+            if (!finite(m.kd[y][c]) || !finite(m.ks[y][c]))
+                return false;
+    }
+    return true;
+}
+
+int top(const fabric_material &m, int i, int j) { return m.pattern[j * m.wx + i]; }
+
+// Per-cell float of the top yarn: run length along the yarn (0 if the yarn
+// never goes under) and the cell's offset from the start of its float.
+void cell_table(const fabric_material &m, uint16_t cell[256])
+{
+    std::memset(cell, 0, 256 * sizeof(uint16_t));
+    const int wx = m.wx, wy = m.wy;
+    for (int j = 0; j < wy; j++) {
+        for (int i = 0; i < wx; i++) {
+            const int warp = top(m, i, j);
+            // Walk along the top yarn: warp floats run over rows of column i,
+            // weft floats over columns of row j.
+            const int period = warp ? wy : wx;
+            auto same = [&](int step) {
+                int ii = warp ? i : ((i + step) % wx + wx) % wx;
+                int jj = warp ? ((j + step) % wy + wy) % wy : j;
+                return top(m, ii, jj) == warp;
+            };
+            int total = 0;
+            for (int s = 0; s < period; s++)
+                total += same(s);
+            int off = 0, len = 0;
+            if (total < period) {
+                while (same(-(off + 1)))
+                    off++;
+                int ahead = 0;
+                while (same(ahead + 1))
+                    ahead++;
+                len = off + ahead + 1;
+            }
+            cell[j * 16 + i] = (uint16_t)((warp ? 0x8000u : 0u) | ((unsigned)len << 5) | (unsigned)off);
+        }
+    }
+}
+
+DevFabric device_fabric(const fabric_material &m)
+{
+    DevFabric d;
+    std::memset(&d, 0, sizeof(d));
+    d.wx = m.wx;
+    d.wy = m.wy;
+    d.fwx = (float)m.wx;
+    d.fwy = (float)m.wy;
+    d.inv_wx = (float)(1.0 / m.wx);
+    d.inv_wy = (float)(1.0 / m.wy);
+    for (int y = 0; y < 2; y++) {
+        const double a = m.alpha[y];
+        d.alpha[y] = m.alpha[y];
+        d.alpha2m1[y] = (float)(1.0 - a * a);
+        d.ia2m1[y] = (float)(1.0 / (a * a) - 1.0);
+        d.inv_pi_alpha[y] = (float)(1.0 / (M_PI * a));
+        d.beta[y] = m.beta[y];
+        d.incl[y] = m.incl[y];
+        d.cos_twist[y] = (float)std::cos((double)m.twist[y]);
+        d.sin_twist[y] = (float)std::sin((double)m.twist[y]);
+        const double half = 0.5 * (1.0 - (double)m.gap[y]);
+        d.half_width[y] = (float)half;
+        d.inv_half_width[y] = (float)(1.0 / half);
+        d.wblend[y] = m.wblend[y];
+        for (int c = 0; c < 3; c++) {
+            d.kd[y][c] = m.kd[y][c];
+            d.ks[y][c] = m.ks[y][c];
+        }
+    }
+    cell_table(m, d.cell);
+    return d;
+}
+
+// Encoder input: per cell (i, j) of a 16x16 grid, [P = 1, P = 0] one-hot inside
+// the pattern and zeros outside, then the yarn scalars (warp, weft pairs of
+// alpha, beta, twist, inclination, gap, blend) scaled to [0, 1] over fixed
+// ranges.
+void encoder_input(const fabric_material &m, float x[kEncIn])
+{
+    std::memset(x, 0, kEncIn * sizeof(float));
+    for (int j = 0; j < m.wy; j++)
+        for (int i = 0; i < m.wx; i++) {
+            const int base = 2 * (16 * j + i);
+            x[base + (top(m, i, j) ? 0 : 1)] = 1.0f;
+        }
+    const double lo[6] = {0.1, 0.0, -M_PI / 6.0, M_PI / 12.0, 0.0, 0.0};
+    const double hi[6] = {1.0, 2.0, M_PI / 6.0, M_PI / 4.0, 0.5, 1.0};
+    const float *src[6] = {m.alpha, m.beta, m.twist, m.incl, m.gap, m.wblend};
+    for (int q = 0; q < 6; q++)
+        for (int y = 0; y < 2; y++)
+            x[512 + 2 * q + y] = (float)(((double)src[q][y] - lo[q]) / (hi[q] - lo[q]));
+}
+
+// Kaiming-uniform weights U(+-sqrt(6/fan_in)), zero biases, from SplitMix64(seed).
+void init_params(uint64_t seed, std::vector<float> &out)
+{
+    out.assign(FABRIC_N_PARAMS, 0.0f);
+    struct Layer { int off, outs, ins; };
+    const Layer layers[8] = {{kOffW1, 64, 72}, {kOffW2, 64, 64}, {kOffW3, 64, 69}, {kOffW4, 4, 64},
+                             {kNDec + kOffE1, 128, 524}, {kNDec + kOffE2, 128, 128},
+                             {kNDec + kOffE3, 128, 128}, {kNDec + kOffE4, 32, 128}};
+    uint64_t state = seed;
+    for (const Layer &L : layers) {
+        const double bound = std::sqrt(6.0 / L.ins);
+        for (int k = 0; k < L.outs * L.ins; k++) {
+            state += 0x9E3779B97F4A7C15ull;
+            uint64_t z = state;
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            z ^= z >> 31;
+            const double u01 = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+            out[L.off + k] = (float)((2.0 * u01 - 1.0) * bound);
+        }
+    }
+}
+
+bool valid_gbuffer(const fabric_gbuffer *g)
+{
+    if (!g || g->n < 0)
+        return false;
+    if (g->n == 0)
+        return true;
+    return g->fabric_id && g->u && g->v && g->radius && g->wi_x && g->wi_y && g->wi_z &&
+           g->wo_x && g->wo_y && g->wo_z;
+}
+
+bool perfect_square(int n)
+{
+    if (n <= 0 || n > FABRIC_MAX_SAMPLES)
+        return false;
+    int s = (int)std::lround(std::sqrt((double)n));
+    return s * s == n;
+}
+
+// The packed decoder of precision prec for the context's current parameters.
+fabric_status ensure_image(fabric_ctx *ctx, int prec, hipStream_t stream)
+{
+    if (!ctx->image[prec]) {
+        const size_t bytes = decoder_image_bytes(prec);
+        if (bytes == 0)
+            return FABRIC_E_INVAL;
+        fabric_status st = from_hip(hipMalloc(&ctx->image[prec], bytes));
+        if (st != FABRIC_OK)
+            return st;
+    }
+    if (ctx->image_version[prec] != ctx->weights_version) {
+        fabric_status st = from_hip(launch_pack_decoder(prec, ctx->params, ctx->image[prec], stream));
+        if (st != FABRIC_OK)
+            return st;
+        ctx->image_version[prec] = ctx->weights_version;
+    }
+    return FABRIC_OK;
+}
+
+bool supported_prec(int prec) { return prec == FABRIC_FP32 || prec == FABRIC_BF16 || prec == FABRIC_FP16; }
+
+}  // namespace
+
+extern "C" {
+
+const char *fabric_status_str(fabric_status s)
+{
+    switch (s) {
+    case FABRIC_OK: return "ok";
+    case FABRIC_E_INVAL: return "invalid argument";
+    case FABRIC_E_RANGE: return "out of range";
+    case FABRIC_E_NOMEM: return "out of device memory";
+    case FABRIC_E_DEVICE: return "HIP runtime error";
+    case FABRIC_E_NONFINITE: return "non-finite loss";
+    case FABRIC_E_STATE: return "invalid call order";
+    }
+    return "unknown status";
+}
+
+void fabric_destroy(fabric_ctx *ctx)
+{
+    if (!ctx)
+        return;
+    DeviceGuard guard(ctx->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ctx->params);
+    (void)hipFree(ctx->adam_m);
+    (void)hipFree(ctx->adam_v);
+    (void)hipFree(ctx->fabrics);
+    (void)hipFree(ctx->enc_inputs);
+    (void)hipFree(ctx->latents);
+    (void)hipFree(ctx->cfold);
+    for (int k = 0; k < 4; k++)
+        (void)hipFree(ctx->image[k]);
+    (void)hipFree(ctx->tmp_image);
+    (void)hipFree(ctx->tmp_cfold);
+    (void)hipFree(ctx->err);
+    train_scratch_free(ctx->train);
+    delete ctx;
+}
+
+fabric_status fabric_create(fabric_ctx **out, int device, uint64_t seed)
+{
+    if (!out)
+        return FABRIC_E_INVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return FABRIC_E_DEVICE;
+    if (device < 0 || device >= count)
+        return FABRIC_E_INVAL;
+    fabric_ctx *ctx = new (std::nothrow) fabric_ctx();
+    if (!ctx)
+        return FABRIC_E_NOMEM;
+    ctx->device = device;
+    DeviceGuard guard(device);
+    fabric_status st = FABRIC_OK;
+    const size_t F = FABRIC_MAX_FABRICS;
+    if (st == FABRIC_OK) st = dalloc(&ctx->params, FABRIC_N_PARAMS);
+    if (st == FABRIC_OK) st = dalloc(&ctx->adam_m, FABRIC_N_PARAMS);
+    if (st == FABRIC_OK) st = dalloc(&ctx->adam_v, FABRIC_N_PARAMS);
+    if (st == FABRIC_OK) st = dalloc(&ctx->fabrics, F);
+    if (st == FABRIC_OK) st = dalloc(&ctx->enc_inputs, F * kEncIn);
+    if (st == FABRIC_OK) st = dalloc(&ctx->latents, F * kLatent);
+    if (st == FABRIC_OK) st = dalloc(&ctx->cfold, F * 64);
+    if (st == FABRIC_OK) st = dalloc(&ctx->tmp_cfold, F * 64);
+    if (st == FABRIC_OK) st = dalloc(&ctx->err, 1);
+    if (st == FABRIC_OK) {
+        const size_t img = decoder_image_bytes(FABRIC_FP32);   // the largest image
+        st = from_hip(hipMalloc(&ctx->tmp_image, img));
+    }
+    if (st == FABRIC_OK) {
+        std::vector<float> p;
+        init_params(seed, p);
+        st = from_hip(hipMemcpy(ctx->params, p.data(), p.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    if (st == FABRIC_OK) st = from_hip(hipMemset(ctx->adam_m, 0, FABRIC_N_PARAMS * sizeof(double)));
+    if (st == FABRIC_OK) st = from_hip(hipMemset(ctx->adam_v, 0, FABRIC_N_PARAMS * sizeof(double)));
+    if (st == FABRIC_OK) st = from_hip(hipMemset(ctx->err, 0, sizeof(unsigned long long)));
+    if (st == FABRIC_OK) st = from_hip(hipDeviceSynchronize());
+    if (st != FABRIC_OK) {
+        fabric_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return FABRIC_OK;
+}
+
+fabric_status fabric_encode(fabric_ctx *ctx, const fabric_material *mats, int32_t n_mats, void *stream)
+{
+    if (!ctx || !mats)
+        return FABRIC_E_INVAL;
+    if (n_mats < 1 || n_mats > FABRIC_MAX_FABRICS)
+        return FABRIC_E_RANGE;
+    for (int k = 0; k < n_mats; k++)
+        if (!valid_material(mats[k]))
+            return FABRIC_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = as_stream(stream);
+    std::vector<DevFabric> dev(n_mats);
+    std::vector<float> inputs((size_t)n_mats * kEncIn);
+    for (int k = 0; k < n_mats; k++) {
+        dev[k] = device_fabric(mats[k]);
+        encoder_input(mats[k], inputs.data() + (size_t)k * kEncIn);
+    }
+    fabric_status st = from_hip(hipMemcpyAsync(ctx->fabrics, dev.data(), dev.size() * sizeof(DevFabric),
+                                               hipMemcpyHostToDevice, s));
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpyAsync(ctx->enc_inputs, inputs.data(), inputs.size() * sizeof(float),
+                                     hipMemcpyHostToDevice, s));
+    // The host staging vectors must outlive the copies.
+    if (st == FABRIC_OK) st = from_hip(hipStreamSynchronize(s));
+    if (st == FABRIC_OK)
+        st = from_hip(launch_encoder_forward(ctx->params + kNDec, ctx->enc_inputs, n_mats, ctx->latents, s));
+    if (st == FABRIC_OK)
+        st = from_hip(launch_fold_latents(ctx->params, ctx->latents, n_mats, ctx->cfold, s));
+    if (st != FABRIC_OK)
+        return st;
+    ctx->mats.assign(mats, mats + n_mats);
+    ctx->n_mats = n_mats;
+    ctx->encoded_version = ctx->weights_version;
+    return FABRIC_OK;
+}
+
+fabric_status fabric_set_albedo(fabric_ctx *ctx, int32_t fabric, const float kd[2][3],
+                                const float ks[2][3], void *stream)
+{
+    if (!ctx || !kd || !ks)
+        return FABRIC_E_INVAL;
+    if (ctx->n_mats == 0)
+        return FABRIC_E_STATE;
+    if (fabric < 0 || fabric >= ctx->n_mats)
+        return FABRIC_E_RANGE;
+    for (int y = 0; y < 2; y++)
+        for (int c = 0; c < 3; c++)
+            if (!finite(kd[y][c]) || !finite(ks[y][c]))
+                return FABRIC_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    fabric_material &m = ctx->mats[fabric];
+    std::memcpy(m.kd, kd, sizeof(m.kd));
+    std::memcpy(m.ks, ks, sizeof(m.ks));
+    DevFabric d = device_fabric(m);
+    hipStream_t s = as_stream(stream);
+    fabric_status st = from_hip(hipMemcpyAsync(ctx->fabrics + fabric, &d, sizeof(DevFabric),
+                                               hipMemcpyHostToDevice, s));
+    if (st == FABRIC_OK)
+        st = from_hip(hipStreamSynchronize(s));
+    return st;
+}
+
+fabric_status fabric_shade_gbuffer(fabric_ctx *ctx, const fabric_gbuffer *g, fabric_prec prec,
+                                   int32_t fallback_samples, uint64_t seed, float *out_rgb,
+                                   void *stream)
+{
+    if (!ctx || !valid_gbuffer(g) || (g->n > 0 && !out_rgb))
+        return FABRIC_E_INVAL;
+    if (!supported_prec(prec))
+        return FABRIC_E_INVAL;
+    if (fallback_samples < 0 || (fallback_samples > 0 && !perfect_square(fallback_samples)))
+        return FABRIC_E_INVAL;
+    if (ctx->n_mats == 0 || ctx->encoded_version != ctx->weights_version)
+        return FABRIC_E_STATE;
+    if (g->n == 0)
+        return FABRIC_OK;
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = as_stream(stream);
+    fabric_status st = ensure_image(ctx, prec, s);
+    if (st != FABRIC_OK)
+        return st;
+    return from_hip(launch_decode(prec, false, *g, ctx->fabrics, ctx->n_mats, ctx->cfold,
+                                  ctx->image[prec], fallback_samples, seed, out_rgb, ctx->err, s));
+}
+
+fabric_status fabric_gt_filtered(fabric_ctx *ctx, const fabric_gbuffer *g, int32_t n_samples,
+                                 uint64_t seed, float *out_rgb, float *out_comp, void *stream)
+{
+    if (!ctx || !valid_gbuffer(g) || (!out_rgb && !out_comp) || !perfect_square(n_samples))
+        return FABRIC_E_INVAL;
+    if (ctx->n_mats == 0)
+        return FABRIC_E_STATE;
+    if (g->n == 0)
+        return FABRIC_OK;
+    DeviceGuard guard(ctx->device);
+    return from_hip(launch_gt_filter(*g, ctx->fabrics, ctx->n_mats, n_samples, seed, out_rgb,
+                                     out_comp, ctx->err, as_stream(stream)));
+}
+
+fabric_status fabric_decoder_forward(fabric_ctx *ctx, const fabric_gbuffer *g, fabric_prec prec,
+                                     const float *dec_params, const float *latents, float *y4,
+                                     void *stream)
+{
+    if (!ctx || !valid_gbuffer(g) || !dec_params || !latents || (g->n > 0 && !y4))
+        return FABRIC_E_INVAL;
+    if (prec != FABRIC_FP32 && prec != FABRIC_BF16)
+        return FABRIC_E_INVAL;
+    if (ctx->n_mats == 0)
+        return FABRIC_E_STATE;
+    if (g->n == 0)
+        return FABRIC_OK;
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = as_stream(stream);
+    fabric_status st = from_hip(launch_pack_decoder(prec, dec_params, ctx->tmp_image, s));
+    if (st == FABRIC_OK)
+        st = from_hip(launch_fold_latents(dec_params, latents, ctx->n_mats, ctx->tmp_cfold, s));
+    if (st == FABRIC_OK)
+        st = from_hip(launch_decode(prec, true, *g, ctx->fabrics, ctx->n_mats, ctx->tmp_cfold,
+                                    ctx->tmp_image, 0, 0, y4, ctx->err, s));
+    // The next shade must repack: tmp buffers are separate, so nothing else is stale.
+    return st;
+}
+
+fabric_status fabric_decoder_backward(fabric_ctx *ctx, const fabric_gbuffer *g,
+                                      const float *dec_params, const float *latents,
+                                      const float *grad_y4, float *grad_params,
+                                      float *grad_latents, void *stream)
+{
+    if (!ctx || !valid_gbuffer(g) || !dec_params || !latents || !grad_params || !grad_latents ||
+        (g->n > 0 && !grad_y4))
+        return FABRIC_E_INVAL;
+    if (ctx->n_mats == 0)
+        return FABRIC_E_STATE;
+    DeviceGuard guard(ctx->device);
+    return from_hip(decoder_backward(ctx->train, *g, ctx->fabrics, ctx->n_mats, dec_params, latents,
+                                     grad_y4, grad_params, grad_latents, as_stream(stream)));
+}
+
+fabric_status fabric_encoder_forward(fabric_ctx *ctx, const float *enc_params, float *latents,
+                                     void *stream)
+{
+    if (!ctx || !enc_params || !latents)
+        return FABRIC_E_INVAL;
+    if (ctx->n_mats == 0)
+        return FABRIC_E_STATE;
+    DeviceGuard guard(ctx->device);
+    return from_hip(launch_encoder_forward(enc_params, ctx->enc_inputs, ctx->n_mats, latents,
+                                           as_stream(stream)));
+}
+
+fabric_status fabric_encoder_backward(fabric_ctx *ctx, const float *enc_params,
+                                      const float *grad_latents, float *grad_enc_params,
+                                      void *stream)
+{
+    if (!ctx || !enc_params || !grad_latents || !grad_enc_params)
+        return FABRIC_E_INVAL;
+    if (ctx->n_mats == 0)
+        return FABRIC_E_STATE;
+    DeviceGuard guard(ctx->device);
+    return from_hip(encoder_backward(ctx->train, enc_params, ctx->enc_inputs, ctx->n_mats,
+                                     grad_latents, grad_enc_params, as_stream(stream)));
+}
+
+fabric_status fabric_make_batch(fabric_ctx *ctx, uint64_t seed, int64_t n, float r_lo, float r_hi,
+                                const fabric_gbuffer_out *out, void *stream)
+{
+    if (!ctx || !out || n < 0 || out->n < n || !(r_lo > 0.0f) || !(r_hi >= r_lo) || !finite(r_hi))
+        return FABRIC_E_INVAL;
+    if (n > 0 && !(out->fabric_id && out->u && out->v && out->radius && out->wi_x && out->wi_y &&
+                   out->wi_z && out->wo_x && out->wo_y && out->wo_z))
+        return FABRIC_E_INVAL;
+    if (ctx->n_mats == 0)
+        return FABRIC_E_STATE;
+    if (n == 0)
+        return FABRIC_OK;
+    DeviceGuard guard(ctx->device);
+    return from_hip(launch_make_batch(seed, n, ctx->n_mats, r_lo, r_hi, *out, as_stream(stream)));
+}
+
+namespace {
+fabric_status check_train_args(fabric_ctx *ctx, const fabric_gbuffer *batch, const float *targets,
+                               const fabric_train_cfg *cfg)
+{
+    if (!ctx || !cfg)
+        return FABRIC_E_INVAL;
+    if (batch && !valid_gbuffer(batch))
+        return FABRIC_E_INVAL;
+    if (targets && !batch)
+        return FABRIC_E_INVAL;
+    if (!batch && (cfg->batch < 1 || cfg->batch > ((int64_t)1 << 26)))
+        return FABRIC_E_RANGE;
+    if (!targets && !perfect_square(cfg->gt_samples))
+        return FABRIC_E_INVAL;
+    if (cfg->prec != FABRIC_FP32 && cfg->prec != FABRIC_BF16)
+        return FABRIC_E_INVAL;
+    if (!std::isfinite(cfg->lr) || cfg->lr < 0.0 || !(cfg->beta1 >= 0.0 && cfg->beta1 < 1.0) ||
+        !(cfg->beta2 >= 0.0 && cfg->beta2 < 1.0) || !(cfg->eps > 0.0))
+        return FABRIC_E_INVAL;
+    if (!batch && (!(cfg->r_lo > 0.0f) || !(cfg->r_hi >= cfg->r_lo) || !finite(cfg->r_hi)))
+        return FABRIC_E_INVAL;
+    if (ctx->n_mats == 0)
+        return FABRIC_E_STATE;
+    return FABRIC_OK;
+}
+
+TrainArgs train_args(fabric_ctx *ctx, const fabric_gbuffer *batch, const float *targets,
+                     const fabric_train_cfg *cfg)
+{
+    TrainArgs a;
+    a.params = ctx->params;
+    a.adam_m = ctx->adam_m;
+    a.adam_v = ctx->adam_v;
+    a.step = ctx->step + 1;
+    a.fabrics = ctx->fabrics;
+    a.enc_inputs = ctx->enc_inputs;
+    a.n_fabrics = ctx->n_mats;
+    a.batch = batch;
+    a.targets = targets;
+    a.cfg = *cfg;
+    a.err = ctx->err;
+    return a;
+}
+}  // namespace
+
+fabric_status fabric_loss_grad(fabric_ctx *ctx, const fabric_gbuffer *batch, const float *targets,
+                               const fabric_train_cfg *cfg, float *grad, float *out_loss,
+                               void *stream)
+{
+    fabric_status st = check_train_args(ctx, batch, targets, cfg);
+    if (st != FABRIC_OK)
+        return st;
+    if (!grad)
+        return FABRIC_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    TrainArgs a = train_args(ctx, batch, targets, cfg);
+    return from_hip(loss_grad(ctx->train, a, grad, out_loss, as_stream(stream)));
+}
+
+fabric_status fabric_train_step(fabric_ctx *ctx, const fabric_gbuffer *batch, const float *targets,
+                                const fabric_train_cfg *cfg, float *out_loss, void *stream)
+{
+    fabric_status st = check_train_args(ctx, batch, targets, cfg);
+    if (st != FABRIC_OK)
+        return st;
+    DeviceGuard guard(ctx->device);
+    TrainArgs a = train_args(ctx, batch, targets, cfg);
+    int updated = 0;
+    hipError_t e = train_step(ctx->train, a, out_loss, &updated, as_stream(stream));
+    if (e != hipSuccess)
+        return from_hip(e);
+    if (!updated)
+        return FABRIC_E_NONFINITE;
+    ctx->step += 1;
+    ctx->weights_version += 1;
+    return FABRIC_OK;
+}
+
+fabric_status fabric_get_params(fabric_ctx *ctx, float *host, size_t count)
+{
+    if (!ctx || !host || count != (size_t)FABRIC_N_PARAMS)
+        return FABRIC_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    fabric_status st = from_hip(hipDeviceSynchronize());
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpy(host, ctx->params, count * sizeof(float), hipMemcpyDeviceToHost));
+    return st;
+}
+
+fabric_status fabric_set_params(fabric_ctx *ctx, const float *host, size_t count)
+{
+    if (!ctx || !host || count != (size_t)FABRIC_N_PARAMS)
+        return FABRIC_E_INVAL;
+    for (size_t k = 0; k < count; k++)
+        if (!std::isfinite(host[k]))
+            return FABRIC_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    fabric_status st = from_hip(hipDeviceSynchronize());
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpy(ctx->params, host, count * sizeof(float), hipMemcpyHostToDevice));
+    if (st == FABRIC_OK)
+        ctx->weights_version += 1;
+    return st;
+}
+
+fabric_status fabric_get_latents(fabric_ctx *ctx, float *host, int32_t n_mats)
+{
+    if (!ctx || !host)
+        return FABRIC_E_INVAL;
+    if (ctx->n_mats == 0)
+        return FABRIC_E_STATE;
+    if (n_mats != ctx->n_mats)
+        return FABRIC_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    fabric_status st = from_hip(hipDeviceSynchronize());
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpy(host, ctx->latents, (size_t)n_mats * kLatent * sizeof(float),
+                                hipMemcpyDeviceToHost));
+    return st;
+}
+
+namespace {
+const char kMagic[8] = {'F', 'A', 'B', 'R', 'I', 'C', 'K', '1'};
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t n_params;
+    int64_t step;
+};
+size_t ckpt_bytes()
+{
+    return sizeof(CkptHeader) + (size_t)FABRIC_N_PARAMS * (sizeof(float) + 2 * sizeof(double));
+}
+}  // namespace
+
+fabric_status fabric_save(fabric_ctx *ctx, void *host, size_t *bytes)
+{
+    if (!ctx || !bytes)
+        return FABRIC_E_INVAL;
+    const size_t need = ckpt_bytes();
+    if (!host) {
+        *bytes = need;
+        return FABRIC_OK;
+    }
+    if (*bytes < need)
+        return FABRIC_E_RANGE;
+    DeviceGuard guard(ctx->device);
+    CkptHeader h;
+    std::memcpy(h.magic, kMagic, 8);
+    h.version = 1;
+    h.n_params = FABRIC_N_PARAMS;
+    h.step = ctx->step;
+    char *p = (char *)host;
+    std::memcpy(p, &h, sizeof(h));
+    p += sizeof(h);
+    fabric_status st = from_hip(hipDeviceSynchronize());
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpy(p, ctx->params, FABRIC_N_PARAMS * sizeof(float), hipMemcpyDeviceToHost));
+    p += FABRIC_N_PARAMS * sizeof(float);
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpy(p, ctx->adam_m, FABRIC_N_PARAMS * sizeof(double), hipMemcpyDeviceToHost));
+    p += FABRIC_N_PARAMS * sizeof(double);
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpy(p, ctx->adam_v, FABRIC_N_PARAMS * sizeof(double), hipMemcpyDeviceToHost));
+    *bytes = need;
+    return st;
+}
+
+fabric_status fabric_load(fabric_ctx *ctx, const void *host, size_t bytes)
+{
+    if (!ctx || !host || bytes < ckpt_bytes())
+        return FABRIC_E_INVAL;
+    CkptHeader h;
+    std::memcpy(&h, host, sizeof(h));
+    if (std::memcmp(h.magic, kMagic, 8) != 0 || h.version != 1 || h.n_params != FABRIC_N_PARAMS ||
+        h.step < 0)
+        return FABRIC_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    const char *p = (const char *)host + sizeof(h);
+    fabric_status st = from_hip(hipDeviceSynchronize());
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpy(ctx->params, p, FABRIC_N_PARAMS * sizeof(float), hipMemcpyHostToDevice));
+    p += FABRIC_N_PARAMS * sizeof(float);
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpy(ctx->adam_m, p, FABRIC_N_PARAMS * sizeof(double), hipMemcpyHostToDevice));
+    p += FABRIC_N_PARAMS * sizeof(double);
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpy(ctx->adam_v, p, FABRIC_N_PARAMS * sizeof(double), hipMemcpyHostToDevice));
+    if (st == FABRIC_OK) {
+        ctx->step = h.step;
+        ctx->weights_version += 1;
+    }
+    return st;
+}
+
+int64_t fabric_error_count(fabric_ctx *ctx, int reset)
+{
+    if (!ctx)
+        return -1;
+    DeviceGuard guard(ctx->device);
+    unsigned long long v = 0;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(&v, ctx->err, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
+        return -1;
+    if (reset && hipMemset(ctx->err, 0, sizeof(v)) != hipSuccess)
+        return -1;
+    return (int64_t)v;
+}
+
+}  // extern "C"

@@ -1,0 +1,38 @@
+// Launchers of the library's kernels (host side), implemented in the .hip
+// files next to this header and called by fabric_api.cpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace fab {
+
+// Footprint filter: one wavefront per pixel.
+hipError_t launch_gt_filter(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
+                            int n_samples, uint64_t seed, float *out_rgb, float *out_comp,
+                            unsigned long long *err, hipStream_t stream);
+
+// Pack FP32 decoder parameters into the MFMA fragment image of precision prec.
+// image must hold decoder_image_bytes(prec).
+size_t decoder_image_bytes(int prec);
+hipError_t launch_pack_decoder(int prec, const float *dec_params, void *image,
+                               hipStream_t stream);
+
+// c_f = b1 + W1[:, 0:32] z_f for every fabric: cfold[n_fabrics][64].
+hipError_t launch_fold_latents(const float *dec_params, const float *latents, int n_fabrics,
+                               float *cfold, hipStream_t stream);
+
+// Neural shading.  raw = true writes the decoder's outputs y[4][n]; otherwise
+// decoded, albedo-composed rgb[3][n].  fallback_samples > 0 routes
+// out-of-range pixels to the footprint filter inside the same launch.
+hipError_t launch_decode(int prec, bool raw, const fabric_gbuffer &g, const DevFabric *fabrics,
+                         int n_fabrics, const float *cfold, const void *image,
+                         int fallback_samples, uint64_t seed, float *out,
+                         unsigned long long *err, hipStream_t stream);
+
+// Encoder forward over n_fabrics fabrics: enc_inputs[n][524] -> latents[n][32].
+hipError_t launch_encoder_forward(const float *enc_params, const float *enc_inputs,
+                                  int n_fabrics, float *latents, hipStream_t stream);
+
+}  // namespace fab

@@ -1,0 +1,199 @@
+// Device-side analytic fabric model in FP32: sample generation over a pixel
+// footprint, the procedural yarn geometry, the point shading model of
+// Eq. (1)-(2) and the per-sample integrand of the footprint aggregation
+// Eq. (3)-(4) with visibility V = 1.
+#pragma once
+
+#include "common.hpp"
+
+namespace fab {
+
+// The index-th output of the SplitMix64 generator started at `seed`
+// (Steele, Lea and Flood 2014): the state advances by the golden gamma and
+// the output is the variant-13 finaliser of the new state.
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t index)
+{
+    uint64_t z = seed + (index + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Upper and middle 24-bit fields of a 64-bit draw as uniforms in [0, 1).
+__device__ inline float u24_hi(uint64_t z) { return (float)(uint32_t)(z >> 40) * 0x1p-24f; }
+__device__ inline float u24_mid(uint64_t z)
+{
+    return (float)(uint32_t)((z >> 16) & 0xFFFFFFull) * 0x1p-24f;
+}
+
+// Shirley-Chiu concentric mapping of [0,1)^2 onto the unit disk.
+__device__ inline float2 concentric_disk(float x, float y)
+{
+    float a = 2.0f * x - 1.0f, b = 2.0f * y - 1.0f;
+    if (a == 0.0f && b == 0.0f)
+        return make_float2(0.0f, 0.0f);
+    bool horiz = fabsf(a) > fabsf(b);
+    float rad = horiz ? a : b;
+    float phi = horiz ? (0.25f * kPi) * (b / a) : 0.5f * kPi - (0.25f * kPi) * (a / b);
+    float s, c;
+    sincosf(phi, &s, &c);
+    return make_float2(rad * c, rad * s);
+}
+
+// x reduced into [0, period) (period a small positive integer as float).
+__device__ inline float wrap_period(float x, float period, float inv_period)
+{
+    float r = x - period * floorf(x * inv_period);
+    r = r < 0.0f ? r + period : r;
+    r = r >= period ? r - period : r;
+    return r;
+}
+
+struct SampleVal {
+    int yarn;       // kWarp, kWeft or kHole
+    float num_c;    // rho_d * A: diffuse numerator of Eq. (3) per unit k_d
+    float num_s;    // rho_s * A: specular numerator per unit k_s
+    float area;     // projected area A(p, wo) of Eq. (4), V = 1
+};
+
+// The integrand of Eq. (3) and weight of Eq. (4) at surface point (us, vs).
+__device__ inline SampleVal eval_surface_point(const DevFabric &f, float us, float vs,
+                                               float3 wi, float3 wo)
+{
+    SampleVal out;
+    float up = wrap_period(us, f.fwx, f.inv_wx);
+    float vp = wrap_period(vs, f.fwy, f.inv_wy);
+    // Clamped so that even a huge finite uv, whose FP32 reduction is inexact,
+    // indexes inside the cell table.
+    int i = min(max((int)up, 0), f.wx - 1);
+    int j = min(max((int)vp, 0), f.wy - 1);
+    float s = up - (float)i, t = vp - (float)j;
+
+    bool cov_warp = fabsf(s - 0.5f) <= f.half_width[0];
+    bool cov_weft = fabsf(t - 0.5f) <= f.half_width[1];
+    uint32_t cell = f.cell[j * 16 + i];
+    bool warp_top = (cell >> 15) != 0;
+    int yarn;
+    if (warp_top)
+        yarn = cov_warp ? kWarp : (cov_weft ? kWeft : kHole);
+    else
+        yarn = cov_weft ? kWeft : (cov_warp ? kWarp : kHole);
+    out.yarn = yarn;
+    if (yarn == kHole) {
+        // The gap between yarns: nothing reflects, the macro plane projects wo.z.
+        out.num_c = 0.0f;
+        out.num_s = 0.0f;
+        out.area = wo.z;
+        return out;
+    }
+    const int y = yarn;
+    const bool is_warp = y == kWarp;
+    bool on_top = is_warp == warp_top;
+
+    // Position across the yarn in [-1, 1] and along its float in [-1, 1).
+    float across = ((is_warp ? s : t) - 0.5f) * f.inv_half_width[y];
+    float along = 0.0f;
+    uint32_t len = (cell >> 5) & 31u;
+    if (on_top && len != 0u) {
+        float off = (float)(cell & 31u);
+        along = 2.0f * (off + (is_warp ? t : s)) / (float)len - 1.0f;
+    }
+    float ma = f.beta[y] * tanf(f.incl[y] * along);
+    float mb = f.beta[y] * tanf(kThetaMax * across);
+
+    // Height-field normal m = (slopes, 1); n_p = m / |m|, n_p.z = 1/|m|.
+    float mx = is_warp ? mb : ma, my = is_warp ? ma : mb;
+    float len2 = 1.0f + ma * ma + mb * mb;
+    float rl = rsqrtf(len2);
+    float jac = len2 * rl;                       // 1 / <n_s . n_p>
+    float3 n = make_float3(mx * rl, my * rl, rl);
+    // Yarn axis t0 (tilted with the float) and its twist about n_p.
+    float re = rsqrtf(1.0f + ma * ma);
+    float3 t0 = is_warp ? make_float3(0.0f, re, -ma * re) : make_float3(re, 0.0f, -ma * re);
+    float3 bx = make_float3(n.y * t0.z - n.z * t0.y, n.z * t0.x - n.x * t0.z,
+                            n.x * t0.y - n.y * t0.x);
+    float ct = f.cos_twist[y], st = f.sin_twist[y];
+    float3 tp = make_float3(ct * t0.x + st * bx.x, ct * t0.y + st * bx.y, ct * t0.z + st * bx.z);
+
+    float ci = wi.x * n.x + wi.y * n.y + wi.z * n.z;
+    float co = wo.x * n.x + wo.y * n.y + wo.z * n.z;
+    out.area = fmaxf(co, 0.0f) * jac;
+    if (!(ci > 0.0f && co > 0.0f)) {
+        out.num_c = 0.0f;
+        out.num_s = 0.0f;
+        return out;
+    }
+    // Specular: fiber SGGX with S = I - (1 - alpha^2) t t^T, so that
+    // h^T S^-1 h = 1 + (1/alpha^2 - 1)(h.t)^2 and w^T S w = 1 - (1 - alpha^2)(w.t)^2.
+    float hx = wi.x + wo.x, hy = wi.y + wo.y, hz = wi.z + wo.z;
+    float hr = rsqrtf(hx * hx + hy * hy + hz * hz);
+    float ht = (hx * tp.x + hy * tp.y + hz * tp.z) * hr;
+    float it = wi.x * tp.x + wi.y * tp.y + wi.z * tp.z;
+    float ot = wo.x * tp.x + wo.y * tp.y + wo.z * tp.z;
+    float q = 1.0f + f.ia2m1[y] * ht * ht;
+    float D = f.inv_pi_alpha[y] / (q * q);
+    float sig_i = sqrtf(fmaxf(1.0f - f.alpha2m1[y] * it * it, 0.0f));
+    float sig_o = sqrtf(fmaxf(1.0f - f.alpha2m1[y] * ot * ot, 0.0f));
+    float L = sig_i / ci + sig_o / co;
+    float G = -expm1f(-kTRho * L) / L;
+    // rho_s * A = D G / (4 ci co) * ci * co * jac
+    out.num_s = 0.25f * D * G * jac;
+    // Blended Lambertian of Eq. (1) per unit k_d, times <wi.n_p> and A.
+    float w = f.wblend[y];
+    float fd = (w * ci / wi.z + (1.0f - w)) * (1.0f / kPi);
+    out.num_c = fd * ci * out.area;
+    return out;
+}
+
+// Footprint sample k of pixel `pixel` (n_samples = side^2): position in cells.
+__device__ inline float2 footprint_sample(uint64_t seed, uint64_t pixel, int n_samples, int side,
+                                          float inv_side, int k, float u, float v, float r)
+{
+    int ky = k / side;
+    int kx = k - ky * side;
+    uint64_t z = splitmix64_at(seed, pixel * (uint64_t)n_samples + (uint64_t)k);
+    float2 d = concentric_disk(((float)kx + u24_hi(z)) * inv_side,
+                               ((float)ky + u24_mid(z)) * inv_side);
+    return make_float2(fmaf(r, d.x, u), fmaf(r, d.y, v));
+}
+
+// A pixel whose inputs fall outside the model's domain (shaded as 0).
+__device__ inline bool pixel_fault(int fid, int n_fabrics, float u, float v, float r, float3 wi,
+                                   float3 wo)
+{
+    bool finite = isfinite(u) && isfinite(v) && isfinite(r) && isfinite(wi.x) &&
+                  isfinite(wi.y) && isfinite(wi.z) && isfinite(wo.x) && isfinite(wo.y) &&
+                  isfinite(wo.z);
+    return !finite || fid >= n_fabrics || !(r > 0.0f) || !(wi.z > 0.0f) || !(wo.z > 0.0f);
+}
+
+// Wave-wide FP64 footprint estimate for one pixel: lanes take samples
+// lane, lane + 64, ...; partial sums are reduced across the wave in a fixed
+// butterfly order.  Every lane returns the four components.
+__device__ inline void filter_pixel_wave(const DevFabric &f, uint64_t seed, uint64_t pixel,
+                                         int n_samples, int side, float inv_side, float u,
+                                         float v, float r, float3 wi, float3 wo, int lane,
+                                         double comp[4])
+{
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int k = lane; k < n_samples; k += 64) {
+        float2 pos = footprint_sample(seed, pixel, n_samples, side, inv_side, k, u, v, r);
+        SampleVal sv = eval_surface_point(f, pos.x, pos.y, wi, wo);
+        double nc = sv.num_c, ns = sv.num_s;
+        acc[0] += sv.yarn == kWarp ? nc : 0.0;
+        acc[1] += sv.yarn == kWeft ? nc : 0.0;
+        acc[2] += sv.yarn == kWarp ? ns : 0.0;
+        acc[3] += sv.yarn == kWeft ? ns : 0.0;
+        acc[4] += (double)sv.area;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 5; c++)
+            acc[c] += __shfl_xor(acc[c], off, 64);
+    }
+    for (int c = 0; c < 4; c++)
+        comp[c] = acc[4] > 0.0 ? acc[c] / acc[4] : 0.0;
+}
+
+}  // namespace fab

@@ -1,0 +1,929 @@
+// Training of the fabric network (Sec. 4.2 "Loss functions", Eq. (9)-(11);
+// Sec. 5.2) with hand-written forward and backward kernels:
+//
+//   fwd_bwd_kernel     one 16-sample tile per wavefront: the MFMA forward of
+//                      the decoder (same code as shading), the loss terms and
+//                      dL/dy, then the backward through the activations as
+//                      MFMA tiles with transposed weight fragments, chained in
+//                      registers exactly like the forward.  Activations and
+//                      activation gradients go to per-sample buffers.
+//   outer_sum_kernel   weight gradients dW = sum_n dh_n x_n^T as split-K FP32
+//                      MFMA tiles over LDS-staged chunks of samples, with a
+//                      fixed-order reduction of the partials (deterministic).
+//   encoder kernels    per-fabric backward through the encoder and its weight
+//                      gradients summed over fabrics in order.
+//   adam_kernel        Adam with FP64 moments on FP32 masters; skipped on the
+//                      device when the loss is not finite.
+#include <cmath>
+#include <cstring>
+
+#include "kernels.hpp"
+#include "mlp_tile.hpp"
+#include "train.hpp"
+
+namespace fab {
+
+namespace {
+
+// Per-sample buffer layout (floats, sample-major rows).
+constexpr int kS = 40, kH1 = 64, kX3 = 72, kH3 = 64, kDY = 4, kDH = 64;
+constexpr int kActFloats = kS + kH1 + kX3 + kH3 + kDY + 3 * kDH;   // 436
+struct ActPtrs {
+    float *S, *H1, *X3, *H3, *DY, *DH1, *DH2, *DH3;
+};
+__host__ __device__ inline ActPtrs act_ptrs(float *base, int64_t cap)
+{
+    ActPtrs a;
+    a.S = base;
+    a.H1 = a.S + cap * kS;
+    a.X3 = a.H1 + cap * kH1;
+    a.H3 = a.X3 + cap * kX3;
+    a.DY = a.H3 + cap * kH3;
+    a.DH1 = a.DY + cap * kDY;
+    a.DH2 = a.DH1 + cap * kDH;
+    a.DH3 = a.DH2 + cap * kDH;
+    return a;
+}
+
+// Per-fabric encoder scratch (floats).
+constexpr int kEncActFloats = kEncIn + 6 * kEncHid + kLatent;
+
+// ---------------------------------------------------------------------------
+// Training batches
+// ---------------------------------------------------------------------------
+
+__global__ void make_batch_kernel(uint64_t seed, int64_t n, int n_fabrics, float log_lo,
+                                  float log_span, fabric_gbuffer_out out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n)
+        return;
+    const uint64_t base = 8ull * (uint64_t)q;
+    const uint64_t z0 = splitmix64_at(seed, base + 0);
+    const uint64_t z1 = splitmix64_at(seed, base + 1);
+    const uint64_t z2 = splitmix64_at(seed, base + 2);
+    const uint64_t z3 = splitmix64_at(seed, base + 3);
+    const uint64_t z4 = splitmix64_at(seed, base + 4);
+    out.fabric_id[q] = (uint16_t)((uint32_t)(z0 >> 32) % (uint32_t)n_fabrics);
+    out.u[q] = 8.0f * u24_hi(z1);
+    out.v[q] = 8.0f * u24_mid(z1);
+    out.radius[q] = expf(fmaf(u24_hi(z2), log_span, log_lo));
+    float s, c, xi;
+    xi = u24_hi(z3);
+    sincospif(2.0f * u24_mid(z3), &s, &c);
+    out.wi_x[q] = sqrtf(xi) * c;
+    out.wi_y[q] = sqrtf(xi) * s;
+    out.wi_z[q] = sqrtf(1.0f - xi);
+    xi = u24_hi(z4);
+    sincospif(2.0f * u24_mid(z4), &s, &c);
+    out.wo_x[q] = sqrtf(xi) * c;
+    out.wo_y[q] = sqrtf(xi) * s;
+    out.wo_z[q] = sqrtf(1.0f - xi);
+}
+
+// ---------------------------------------------------------------------------
+// Transposed weight fragments for the backward pass.
+//   BW4: dh3 = W4^T dy      A[m = h3 neuron][slot] = W4[dy index][m]
+//   BW3: dh2 = W3[:, :64]^T dh3   A[m = h2 neuron][slot c] = W3[chain(c)][m]
+//   BW2: dh1 = W2^T dh2     A[m = h1 neuron][slot c] = W2[chain(c)][m]
+// dy slots: with one K value per lane (FP32) lane group g carries dy[g];
+// with eight (BF16) lane group 0 carries dy[0..3] in positions 0..3.
+// ---------------------------------------------------------------------------
+template <int KPL> struct BwdShape {
+    static constexpr int KS2 = div_up(kChainSlots, KPL);
+    static constexpr int FRAG_W4 = 0;                 // 4 M-blocks x 1 k-step
+    static constexpr int FRAG_W3 = 4;                 // 4 x KS2
+    static constexpr int FRAG_W2 = 4 + 4 * KS2;       // 4 x KS2
+    static constexpr int NFRAG = 4 + 8 * KS2;
+};
+
+__host__ __device__ inline int dy_index(int KPL, int grp, int c)
+{
+    if (KPL == 1)
+        return c == 0 ? grp : -1;
+    return (grp == 0 && c < 4) ? c : -1;
+}
+
+template <int P>
+__global__ void pack_backward_kernel(const float *__restrict__ params,
+                                     typename Mfma<P>::Frag *__restrict__ frags)
+{
+    using M = Mfma<P>;
+    using B = BwdShape<M::KPL>;
+    constexpr int KPL = M::KPL;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= B::NFRAG * 64)
+        return;
+    const int fr = idx / 64, lane = idx % 64, row = lane & 15, grp = lane >> 4;
+    typename M::Frag f = M::zero();
+    for (int j = 0; j < KPL; j++) {
+        float w = 0.0f;
+        if (fr < B::FRAG_W3) {
+            const int mb = fr, m = 16 * mb + row;
+            const int d = dy_index(KPL, grp, j);
+            if (d >= 0) w = params[kOffW4 + d * 64 + m];
+        } else if (fr < B::FRAG_W2) {
+            const int mb = (fr - B::FRAG_W3) / B::KS2, ks = (fr - B::FRAG_W3) % B::KS2;
+            const int m = 16 * mb + row, c = ks * KPL + j;
+            if (c < kChainSlots) w = params[kOffW3 + chain_neuron(grp, c) * 69 + m];
+        } else {
+            const int mb = (fr - B::FRAG_W2) / B::KS2, ks = (fr - B::FRAG_W2) % B::KS2;
+            const int m = 16 * mb + row, c = ks * KPL + j;
+            if (c < kChainSlots) w = params[kOffW2 + chain_neuron(grp, c) * 64 + m];
+        }
+        M::set(f, j, w);
+    }
+    frags[idx] = f;
+}
+
+// ---------------------------------------------------------------------------
+// Fused forward, loss and activation backward: one 16-sample tile per wave.
+// GIVEN_DY: dy comes from the caller (dL/dy4 [4][n]); otherwise from the loss
+// of Eq. (9)-(11) against targets [4][n] (C_warp, C_weft, S_warp, S_weft).
+// ---------------------------------------------------------------------------
+template <int P, bool GIVEN_DY>
+__global__ __launch_bounds__(256) void fwd_bwd_kernel(
+    fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
+    const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ ffr,
+    const f32x4 *__restrict__ fbias, const typename Mfma<P>::Frag *__restrict__ bfr,
+    const float *__restrict__ tgt_or_dy, float *__restrict__ acts, int64_t cap,
+    double *__restrict__ loss_part, unsigned long long *err)
+{
+    using T = Tile<P>;
+    using M = typename T::M;
+    using Frag = typename T::Frag;
+    using B = BwdShape<T::KPL>;
+    constexpr int KPL = T::KPL;
+
+    const int lane = threadIdx.x & 63, grp = lane >> 4, col = lane & 15;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t n = g.n;
+    if (tile * 16 >= n)        // whole wave past the end (last block)
+        return;
+    const int64_t p = tile * 16 + col;
+    const bool valid = p < n;
+    const int64_t pc = valid ? p : n - 1;
+
+    int fid = g.fabric_id[pc];
+    float u = g.u[pc], v = g.v[pc], r = g.radius[pc];
+    float3 wi = make_float3(g.wi_x[pc], g.wi_y[pc], g.wi_z[pc]);
+    float3 wo = make_float3(g.wo_x[pc], g.wo_y[pc], g.wo_z[pc]);
+    const bool fault = pixel_fault(fid, n_fabrics, u, v, r, wi, wo);
+    if (fault) {
+        fid = 0;
+        u = v = 0.0f;
+        r = 1.0f;
+        wi = wo = make_float3(0.0f, 0.0f, 1.0f);
+    }
+    const bool live = valid && !fault;
+    const DevFabric &fab = fabrics[fid];
+    {
+        const unsigned long long bad = __ballot(grp == 0 && valid && fault);
+        if (lane == 0 && bad && err)
+            atomicAdd(err, (unsigned long long)__popcll(bad));
+    }
+
+    float s1[T::NS1];
+    T::spatial_slots(u, v, r, fab.fwx, fab.fwy, fab.inv_wx, fab.inv_wy, grp, s1);
+    f32x4 cf[4];
+#pragma unroll
+    for (int mb = 0; mb < 4; mb++)
+        cf[mb] = *(const f32x4 *)(cfold + fid * 64 + 16 * mb + 4 * grp);
+    float ang0, ang1;
+    angular_slots(grp, wi, wo, &ang0, &ang1);
+    auto getA = [&](int q) { return ffr[q * 64 + lane]; };
+    auto getBias = [&](int q) { return fbias[q * 64 + lane]; };
+    f32x4 a1[4], a2[4], a3[4], y;
+    T::forward(getA, getBias, cf, s1, ang0, ang1, a1, a2, a3, y);
+
+    // ---- dL/dy (lane group 0 holds y of its pixel) ----
+    float dy[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    double loss = 0.0;
+    if (grp == 0 && live) {
+        if (GIVEN_DY) {
+#pragma unroll
+            for (int c = 0; c < 4; c++)
+                dy[c] = tgt_or_dy[c * n + p];
+        } else {
+            const float inv_n = 1.0f / (float)n;
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const float t = tgt_or_dy[c * n + p];
+                const float target = c < 2 ? t : log1pf(kSpec * t);   // g(x) = ln(k x + 1)
+                const float lam = c < 2 ? 0.1f : 0.4f;                // lambda_C, lambda_S
+                const float d = y[c] - target;
+                loss += (double)(lam * d * d);
+                dy[c] = 2.0f * lam * d * inv_n;
+            }
+        }
+    }
+    if (!GIVEN_DY) {
+        // Fixed-order sum of the 16 samples' terms; lane 0 stores the tile's part.
+        for (int off = 8; off > 0; off >>= 1)
+            loss += __shfl_xor(loss, off, 64);
+        if (lane == 0)
+            loss_part[tile] = loss;
+    }
+    // Every lane fetches its pixel's dy from lane group 0.
+    float dyp[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++)
+        dyp[c] = __shfl(dy[c], col, 64);
+
+    // ---- dh3 = (W4^T dy) * [a3 > 0] ----
+    Frag Bdy[1];
+#pragma unroll
+    for (int j = 0; j < KPL; j++) {
+        const int d = dy_index(KPL, grp, j);
+        float val = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            val = d == c ? dyp[c] : val;
+        M::set(Bdy[0], j, val);
+    }
+    auto getW = [&](int q) { return bfr[q * 64 + lane]; };
+    f32x4 d3[4], d2[4], d1[4];
+#pragma unroll
+    for (int mb = 0; mb < 4; mb++)
+        d3[mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    T::template dense<4>(getW, B::FRAG_W4, Bdy, d3);
+#pragma unroll
+    for (int mb = 0; mb < 4; mb++)
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+            d3[mb][i] = a3[mb][i] > 0.0f ? d3[mb][i] : 0.0f;
+
+    // ---- dh2 = (W3[:, :64]^T dh3) * [a2 > 0] ----
+    Frag Bd3[B::KS2];
+    T::chain(d3, false, Bd3);
+#pragma unroll
+    for (int mb = 0; mb < 4; mb++)
+        d2[mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    T::template dense<4>(getW, B::FRAG_W3, Bd3, d2);
+#pragma unroll
+    for (int mb = 0; mb < 4; mb++)
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+            d2[mb][i] = a2[mb][i] > 0.0f ? d2[mb][i] : 0.0f;
+
+    // ---- dh1 = (W2^T dh2) * [a1 > 0] ----
+    Frag Bd2[B::KS2];
+    T::chain(d2, false, Bd2);
+#pragma unroll
+    for (int mb = 0; mb < 4; mb++)
+        d1[mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    T::template dense<4>(getW, B::FRAG_W2, Bd2, d1);
+#pragma unroll
+    for (int mb = 0; mb < 4; mb++)
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+            d1[mb][i] = a1[mb][i] > 0.0f ? d1[mb][i] : 0.0f;
+
+    if (!valid)
+        return;
+    // ---- per-sample rows for the weight gradients ----
+    ActPtrs ap = act_ptrs(acts, cap);
+    const float keep = live ? 1.0f : 0.0f;
+#pragma unroll
+    for (int c = 0; c < kL1Slots; c++)
+        ap.S[p * kS + l1_feature(grp, c)] = s1[c];
+#pragma unroll
+    for (int mb = 0; mb < 4; mb++) {
+        const int o = 16 * mb + 4 * grp;
+        f32x4 h1, h2, h3;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            h1[i] = fmaxf(a1[mb][i], 0.0f);
+            h2[i] = fmaxf(a2[mb][i], 0.0f);
+            h3[i] = fmaxf(a3[mb][i], 0.0f);
+        }
+        *(f32x4 *)(ap.H1 + p * kH1 + o) = h1;
+        *(f32x4 *)(ap.X3 + p * kX3 + o) = h2;
+        *(f32x4 *)(ap.H3 + p * kH3 + o) = h3;
+        *(f32x4 *)(ap.DH1 + p * kDH + o) = d1[mb] * keep;
+        *(f32x4 *)(ap.DH2 + p * kDH + o) = d2[mb] * keep;
+        *(f32x4 *)(ap.DH3 + p * kDH + o) = d3[mb] * keep;
+    }
+    if (grp == 0) {
+        float *x3 = ap.X3 + p * kX3;
+        x3[64] = wi.x;
+        x3[65] = wi.y;
+        x3[66] = wi.z;
+        x3[67] = wo.x;
+        x3[68] = wo.y;
+        x3[69] = 0.0f;
+        x3[70] = 0.0f;
+        x3[71] = 0.0f;
+        *(f32x4 *)(ap.DY + p * kDY) = f32x4{dy[0], dy[1], dy[2], dy[3]};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Split-K outer-product sums: partial[blk][m][c] = sum over the block's
+// samples of A[s][m] * Bx[s][c], m < MA, c < NC, where Bx is B's first NB
+// columns followed (if with_bias) by a column of ones, or (ids != NULL) the
+// one-hot of ids over fabrics f0 .. f0+NC-1.  FP32 MFMA 16x16x4 over
+// 64-sample LDS tiles.
+// ---------------------------------------------------------------------------
+constexpr int kOsTile = 64;
+constexpr int kOsMaxM = 64;
+constexpr int kOsMaxC = 80;
+
+__global__ __launch_bounds__(256) void outer_sum_kernel(
+    const float *__restrict__ A, int lda, int MA, const float *__restrict__ Bm, int ldb, int NB,
+    int with_bias, const uint16_t *__restrict__ ids, int f0, int NC, int64_t n, int64_t chunk,
+    float *__restrict__ partial)
+{
+    __shared__ float sA[kOsTile][kOsMaxM + 1];
+    __shared__ float sB[kOsTile][kOsMaxC + 1];
+    const int lane = threadIdx.x & 63, grp = lane >> 4, col = lane & 15;
+    const int wave = threadIdx.x >> 6;
+    const int MT = (MA + 15) / 16, CT = (NC + 15) / 16;
+    const int ntiles = MT * CT;
+    f32x4 acc[5];
+#pragma unroll
+    for (int t = 0; t < 5; t++)
+        acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int64_t s0 = (int64_t)blockIdx.x * chunk;
+    const int64_t s1 = s0 + chunk < n ? s0 + chunk : n;
+    for (int64_t base = s0; base < s1; base += kOsTile) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < kOsTile * kOsMaxM; k += blockDim.x) {
+            const int s = k / kOsMaxM, m = k % kOsMaxM;
+            const int64_t q = base + s;
+            sA[s][m] = (q < s1 && m < MA) ? A[q * lda + m] : 0.0f;
+        }
+        for (int k = threadIdx.x; k < kOsTile * kOsMaxC; k += blockDim.x) {
+            const int s = k / kOsMaxC, c = k % kOsMaxC;
+            const int64_t q = base + s;
+            float val = 0.0f;
+            if (q < s1 && c < NC) {
+                if (ids)
+                    val = (int)ids[q] == f0 + c ? 1.0f : 0.0f;
+                else if (c < NB)
+                    val = Bm[q * ldb + c];
+                else
+                    val = with_bias ? 1.0f : 0.0f;
+            }
+            sB[s][c] = val;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 5; t++) {
+            const int tt = wave + 4 * t;
+            if (tt < ntiles) {
+                const int mt = tt / CT, ct = tt % CT;
+                f32x4 a = acc[t];
+                for (int k4 = 0; k4 < kOsTile / 4; k4++) {
+                    const int s = 4 * k4 + grp;
+                    a = __builtin_amdgcn_mfma_f32_16x16x4f32(sA[s][16 * mt + col],
+                                                             sB[s][16 * ct + col], a, 0, 0, 0);
+                }
+                acc[t] = a;
+            }
+        }
+    }
+    const int stride = kOsMaxM * kOsMaxC;
+#pragma unroll
+    for (int t = 0; t < 5; t++) {
+        const int tt = wave + 4 * t;
+        if (tt < ntiles) {
+            const int mt = tt / CT, ct = tt % CT;
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int m = 16 * mt + 4 * grp + i, c = 16 * ct + col;
+                partial[(size_t)blockIdx.x * stride + m * kOsMaxC + c] = acc[t][i];
+            }
+        }
+    }
+}
+
+// Sum the partials in block order and scatter: out[m][c] goes to
+// dst[m * ldw + c] (c < NW) or to bias[m] (c == NW, with a bias), or with
+// transposed = 1 to dst[c * ldw + m].
+__global__ void reduce_partials_kernel(const float *__restrict__ partial, int nblk, int MA,
+                                       int NC, int NW, float *__restrict__ dst, int ldw,
+                                       int transposed, float *__restrict__ bias)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= MA * NC)
+        return;
+    const int m = e / NC, c = e % NC;
+    float acc = 0.0f;
+    const int stride = kOsMaxM * kOsMaxC;
+    for (int b = 0; b < nblk; b++)
+        acc += partial[(size_t)b * stride + m * kOsMaxC + c];
+    if (transposed)
+        dst[c * ldw + m] = acc;
+    else if (c < NW)
+        dst[m * ldw + c] = acc;
+    else if (bias)
+        bias[m] = acc;
+}
+
+// dz_f = W1[:, 0:32]^T dc_f and dW1[:, 0:32] = sum_f dc_f z_f^T.
+__global__ void latent_grads_kernel(const float *__restrict__ params, const float *__restrict__ dcf,
+                                    const float *__restrict__ latents, int n_fabrics,
+                                    float *__restrict__ dz, float *__restrict__ dW1)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n_fabrics * kLatent) {
+        const int f = e / kLatent, k = e % kLatent;
+        float acc = 0.0f;
+        for (int o = 0; o < 64; o++)
+            acc = fmaf(params[kOffW1 + o * 72 + k], dcf[f * 64 + o], acc);
+        dz[e] = acc;
+    }
+    if (e < 64 * kLatent) {
+        const int o = e / kLatent, k = e % kLatent;
+        float acc = 0.0f;
+        for (int f = 0; f < n_fabrics; f++)
+            acc = fmaf(dcf[f * 64 + o], latents[f * kLatent + k], acc);
+        dW1[o * 72 + k] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Encoder backward.  Per fabric: recompute the forward and backpropagate dz
+// to the pre-activation gradients; then every weight gradient is a sum over
+// fabrics in order.
+// enc scratch per fabric: x[524] a1 a2 a3 da1 da2 da3 [128 each] dz[32]
+// ---------------------------------------------------------------------------
+__device__ void dense_rows_enc(const float *__restrict__ W, const float *__restrict__ b,
+                               const float *x, int nin, int nout, float *y)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
+    for (int o = wave; o < nout; o += nwaves) {
+        float acc = 0.0f;
+        for (int i = lane; i < nin; i += 64)
+            acc = fmaf(W[(size_t)o * nin + i], x[i], acc);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            acc += __shfl_xor(acc, off, 64);
+        if (lane == 0)
+            y[o] = acc + b[o];
+    }
+    __syncthreads();
+}
+
+// y[i] = sum_o W[o][i] d[o] (transposed product), one output per thread.
+__device__ void dense_cols_enc(const float *__restrict__ W, const float *d, int nout, int nin,
+                               float *y)
+{
+    for (int i = threadIdx.x; i < nin; i += blockDim.x) {
+        float acc = 0.0f;
+        for (int o = 0; o < nout; o++)
+            acc = fmaf(W[(size_t)o * nin + i], d[o], acc);
+        y[i] = acc;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void encoder_backward_kernel(const float *__restrict__ Q,
+                                                               const float *__restrict__ inputs,
+                                                               const float *__restrict__ dz,
+                                                               float *__restrict__ scratch)
+{
+    __shared__ float x[kEncIn], a1[kEncHid], e1[kEncHid], a2[kEncHid], r2[kEncHid],
+        a3[kEncHid], e2[kEncHid], g[kEncHid], d3[kEncHid], d2[kEncHid], d1[kEncHid],
+        dzs[kLatent];
+    const int f = blockIdx.x;
+    for (int k = threadIdx.x; k < kEncIn; k += blockDim.x)
+        x[k] = inputs[(size_t)f * kEncIn + k];
+    for (int k = threadIdx.x; k < kLatent; k += blockDim.x)
+        dzs[k] = dz[f * kLatent + k];
+    __syncthreads();
+    dense_rows_enc(Q + kOffE1, Q + kOffC1, x, kEncIn, kEncHid, a1);
+    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
+        e1[k] = fmaxf(a1[k], 0.0f);
+    __syncthreads();
+    dense_rows_enc(Q + kOffE2, Q + kOffC2, e1, kEncHid, kEncHid, a2);
+    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
+        r2[k] = fmaxf(a2[k], 0.0f);
+    __syncthreads();
+    dense_rows_enc(Q + kOffE3, Q + kOffC3, r2, kEncHid, kEncHid, a3);
+    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x) {
+        a3[k] += e1[k];                     // skip connection before the activation
+        e2[k] = fmaxf(a3[k], 0.0f);
+    }
+    __syncthreads();
+    // backward
+    dense_cols_enc(Q + kOffE4, dzs, kLatent, kEncHid, g);          // dL/de2
+    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
+        d3[k] = a3[k] > 0.0f ? g[k] : 0.0f;
+    __syncthreads();
+    dense_cols_enc(Q + kOffE3, d3, kEncHid, kEncHid, g);           // dL/dr2
+    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
+        d2[k] = a2[k] > 0.0f ? g[k] : 0.0f;
+    __syncthreads();
+    dense_cols_enc(Q + kOffE2, d2, kEncHid, kEncHid, g);           // dL/de1 (through E2)
+    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
+        d1[k] = a1[k] > 0.0f ? g[k] + d3[k] : 0.0f;               // plus the skip path
+    __syncthreads();
+    float *out = scratch + (size_t)f * kEncActFloats;
+    for (int k = threadIdx.x; k < kEncIn; k += blockDim.x)
+        out[k] = x[k];
+    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x) {
+        out[kEncIn + k] = e1[k];
+        out[kEncIn + kEncHid + k] = r2[k];
+        out[kEncIn + 2 * kEncHid + k] = e2[k];
+        out[kEncIn + 3 * kEncHid + k] = d1[k];
+        out[kEncIn + 4 * kEncHid + k] = d2[k];
+        out[kEncIn + 5 * kEncHid + k] = d3[k];
+    }
+    for (int k = threadIdx.x; k < kLatent; k += blockDim.x)
+        out[kEncIn + 6 * kEncHid + k] = dzs[k];
+}
+
+// One thread per encoder parameter: the sum over fabrics, in order.
+__global__ void encoder_wgrad_kernel(const float *__restrict__ scratch, int n_fabrics,
+                                     float *__restrict__ grad)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kNEnc)
+        return;
+    // (delta offset, input offset, fan-in) of the tensor holding e
+    int dofs, xofs, nin, idx;
+    if (e < kOffC1) { dofs = kEncIn + 3 * kEncHid; xofs = 0; nin = kEncIn; idx = e - kOffE1; }
+    else if (e < kOffE2) { dofs = kEncIn + 3 * kEncHid; xofs = -1; nin = 1; idx = e - kOffC1; }
+    else if (e < kOffC2) { dofs = kEncIn + 4 * kEncHid; xofs = kEncIn; nin = kEncHid; idx = e - kOffE2; }
+    else if (e < kOffE3) { dofs = kEncIn + 4 * kEncHid; xofs = -1; nin = 1; idx = e - kOffC2; }
+    else if (e < kOffC3) { dofs = kEncIn + 5 * kEncHid; xofs = kEncIn + kEncHid; nin = kEncHid; idx = e - kOffE3; }
+    else if (e < kOffE4) { dofs = kEncIn + 5 * kEncHid; xofs = -1; nin = 1; idx = e - kOffC3; }
+    else if (e < kOffC4) { dofs = kEncIn + 6 * kEncHid; xofs = kEncIn + 2 * kEncHid; nin = kEncHid; idx = e - kOffE4; }
+    else { dofs = kEncIn + 6 * kEncHid; xofs = -1; nin = 1; idx = e - kOffC4; }
+    const int o = idx / nin, i = idx % nin;
+    float acc = 0.0f;
+    for (int f = 0; f < n_fabrics; f++) {
+        const float *s = scratch + (size_t)f * kEncActFloats;
+        const float x = xofs >= 0 ? s[xofs + i] : 1.0f;
+        acc = fmaf(s[dofs + o], x, acc);
+    }
+    grad[e] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Loss reduction and Adam
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void loss_reduce_kernel(const double *__restrict__ part,
+                                                          int64_t nparts, double inv_n,
+                                                          double *__restrict__ loss)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t k = threadIdx.x; k < nparts; k += blockDim.x)
+        acc += part[k];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        loss[0] = red[0] * inv_n;
+}
+
+__global__ void adam_kernel(float *__restrict__ params, const float *__restrict__ grad,
+                            double *__restrict__ m, double *__restrict__ v, int n, double lr,
+                            double beta1, double beta2, double eps, double c1, double c2,
+                            const double *__restrict__ loss)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n || !isfinite(loss[0]))
+        return;
+    const double gk = (double)grad[k];
+    const double mk = beta1 * m[k] + (1.0 - beta1) * gk;
+    const double vk = beta2 * v[k] + (1.0 - beta2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    const double mh = mk / c1, vh = vk / c2;
+    params[k] = (float)((double)params[k] - lr * mh / (sqrt(vh) + eps));
+}
+
+// ---------------------------------------------------------------------------
+// Host helpers
+// ---------------------------------------------------------------------------
+template <typename Tp> hipError_t grow(Tp **p, size_t count)
+{
+    (void)hipFree(*p);
+    *p = nullptr;
+    return hipMalloc((void **)p, count * sizeof(Tp));
+}
+
+hipError_t ensure_acts(TrainScratch &s, int64_t n)
+{
+    hipError_t e = hipSuccess;
+    if (!s.grad) {
+        if ((e = hipMalloc((void **)&s.grad, FABRIC_N_PARAMS * sizeof(float))) != hipSuccess) return e;
+        if ((e = hipMalloc((void **)&s.dcf, FABRIC_MAX_FABRICS * 64 * sizeof(float))) != hipSuccess) return e;
+        if ((e = hipMalloc((void **)&s.dz, FABRIC_MAX_FABRICS * kLatent * sizeof(float))) != hipSuccess) return e;
+        if ((e = hipMalloc((void **)&s.enc_acts, (size_t)FABRIC_MAX_FABRICS * kEncActFloats * sizeof(float))) != hipSuccess) return e;
+        if ((e = hipMalloc((void **)&s.latents, FABRIC_MAX_FABRICS * kLatent * sizeof(float))) != hipSuccess) return e;
+        if ((e = hipMalloc((void **)&s.cfold, FABRIC_MAX_FABRICS * 64 * sizeof(float))) != hipSuccess) return e;
+        if ((e = hipMalloc((void **)&s.loss, sizeof(double))) != hipSuccess) return e;
+        // The largest images are the FP32 ones.
+        if ((e = hipMalloc(&s.fwd_image, decoder_image_bytes(FABRIC_FP32))) != hipSuccess) return e;
+        if ((e = hipMalloc(&s.bwd_image, (size_t)BwdShape<1>::NFRAG * 64 * sizeof(float))) != hipSuccess) return e;
+    }
+    if (s.cap < n) {
+        if ((e = grow(&s.acts, (size_t)n * kActFloats)) != hipSuccess) return e;
+        if ((e = grow(&s.loss_part, (size_t)(n + 15) / 16 + 1)) != hipSuccess) return e;
+        s.cap = n;
+    }
+    return e;
+}
+
+hipError_t ensure_partials(TrainScratch &s, int nblk)
+{
+    const size_t need = (size_t)nblk * kOsMaxM * kOsMaxC;
+    if (s.partial_floats >= need)
+        return hipSuccess;
+    hipError_t e = grow(&s.partials, need);
+    if (e == hipSuccess)
+        s.partial_floats = need;
+    return e;
+}
+
+hipError_t pack_images(TrainScratch &s, int prec, const float *dec_params, hipStream_t stream)
+{
+    hipError_t e = launch_pack_decoder(prec, dec_params, s.fwd_image, stream);
+    if (e != hipSuccess)
+        return e;
+    if (prec == FABRIC_FP32) {
+        const int total = BwdShape<1>::NFRAG * 64;
+        hipLaunchKernelGGL(pack_backward_kernel<FABRIC_FP32>, dim3((total + 255) / 256), dim3(256), 0,
+                           stream, dec_params, (float *)s.bwd_image);
+    } else {
+        const int total = BwdShape<8>::NFRAG * 64;
+        hipLaunchKernelGGL(pack_backward_kernel<FABRIC_BF16>, dim3((total + 255) / 256), dim3(256), 0,
+                           stream, dec_params, (bf16x8 *)s.bwd_image);
+    }
+    return hipGetLastError();
+}
+
+template <int P, bool GIVEN>
+hipError_t launch_fwd_bwd(TrainScratch &s, const fabric_gbuffer &g, const DevFabric *fabrics,
+                          int n_fabrics, const float *cfold, const float *tgt_or_dy,
+                          unsigned long long *err, hipStream_t stream)
+{
+    using M = Mfma<P>;
+    using S = DecShape<M::KPL>;
+    const auto *ffr = (const typename M::Frag *)s.fwd_image;
+    const auto *fb = (const f32x4 *)((const char *)s.fwd_image + (size_t)S::NFRAG * 64 * sizeof(typename M::Frag));
+    const auto *bfr = (const typename M::Frag *)s.bwd_image;
+    const int64_t tiles = (g.n + 15) / 16;
+    const int64_t blocks = (tiles + 3) / 4;
+    hipLaunchKernelGGL((fwd_bwd_kernel<P, GIVEN>), dim3((unsigned)blocks), dim3(256), 0, stream, g,
+                       fabrics, n_fabrics, cfold, ffr, fb, bfr, tgt_or_dy, s.acts, s.cap,
+                       s.loss_part, err);
+    return hipGetLastError();
+}
+
+// Weight gradients of the decoder from the per-sample rows: writes every
+// decoder tensor of grad_dec except W1's latent columns, plus dcf.
+hipError_t decoder_weight_grads(TrainScratch &s, const fabric_gbuffer &g, int n_fabrics,
+                                float *grad_dec, hipStream_t stream)
+{
+    const int64_t n = g.n;
+    int64_t chunk = (n + 511) / 512;
+    chunk = ((chunk + kOsTile - 1) / kOsTile) * kOsTile;
+    if (chunk < kOsTile)
+        chunk = kOsTile;
+    const int nblk = (int)((n + chunk - 1) / chunk);
+    hipError_t e = ensure_partials(s, nblk);
+    if (e != hipSuccess)
+        return e;
+    ActPtrs ap = act_ptrs(s.acts, s.cap);
+    struct Job { const float *A; int lda, MA; const float *Bm; int ldb, NB; float *dst; int ldw; float *bias; };
+    const Job jobs[4] = {
+        {ap.DH1, kDH, 64, ap.S, kS, 40, grad_dec + kOffW1 + kLatent, 72, grad_dec + kOffB1},
+        {ap.DH2, kDH, 64, ap.H1, kH1, 64, grad_dec + kOffW2, 64, grad_dec + kOffB2},
+        {ap.DH3, kDH, 64, ap.X3, kX3, 69, grad_dec + kOffW3, 69, grad_dec + kOffB3},
+        {ap.DY, kDY, 4, ap.H3, kH3, 64, grad_dec + kOffW4, 64, grad_dec + kOffB4},
+    };
+    for (const Job &j : jobs) {
+        const int NC = j.NB + 1;
+        hipLaunchKernelGGL(outer_sum_kernel, dim3(nblk), dim3(256), 0, stream, j.A, j.lda, j.MA, j.Bm,
+                           j.ldb, j.NB, 1, (const uint16_t *)nullptr, 0, NC, n, chunk, s.partials);
+        const int tot = j.MA * NC;
+        hipLaunchKernelGGL(reduce_partials_kernel, dim3((tot + 255) / 256), dim3(256), 0, stream,
+                           (const float *)s.partials, nblk, j.MA, NC, j.NB, j.dst, j.ldw, 0, j.bias);
+    }
+    // dL/dc_f: segment sums of dh1 by fabric, 64 fabrics per pass.
+    for (int f0 = 0; f0 < n_fabrics; f0 += 64) {
+        const int NC = n_fabrics - f0 < 64 ? n_fabrics - f0 : 64;
+        hipLaunchKernelGGL(outer_sum_kernel, dim3(nblk), dim3(256), 0, stream, (const float *)ap.DH1,
+                           kDH, 64, (const float *)nullptr, 0, 0, 0, g.fabric_id, f0, NC, n, chunk,
+                           s.partials);
+        const int tot = 64 * NC;
+        hipLaunchKernelGGL(reduce_partials_kernel, dim3((tot + 255) / 256), dim3(256), 0, stream,
+                           (const float *)s.partials, nblk, 64, NC, NC, s.dcf + f0 * 64, 64, 1,
+                           (float *)nullptr);
+    }
+    return hipGetLastError();
+}
+
+hipError_t run_encoder_backward(TrainScratch &s, const float *enc_params, const float *enc_inputs,
+                                int n_fabrics, const float *dz, float *grad_enc, hipStream_t stream)
+{
+    hipLaunchKernelGGL(encoder_backward_kernel, dim3(n_fabrics), dim3(256), 0, stream, enc_params,
+                       enc_inputs, dz, s.enc_acts);
+    hipLaunchKernelGGL(encoder_wgrad_kernel, dim3((kNEnc + 255) / 256), dim3(256), 0, stream,
+                       (const float *)s.enc_acts, n_fabrics, grad_enc);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+void train_scratch_free(TrainScratch &s)
+{
+    (void)hipFree(s.acts);
+    (void)hipFree(s.loss_part);
+    (void)hipFree(s.partials);
+    (void)hipFree(s.grad);
+    (void)hipFree(s.dcf);
+    (void)hipFree(s.dz);
+    (void)hipFree(s.enc_acts);
+    (void)hipFree(s.latents);
+    (void)hipFree(s.cfold);
+    (void)hipFree(s.fwd_image);
+    (void)hipFree(s.bwd_image);
+    (void)hipFree(s.loss);
+    (void)hipFree(s.b_fid);
+    (void)hipFree(s.b_fields);
+    (void)hipFree(s.targets);
+    s = TrainScratch();
+}
+
+hipError_t launch_make_batch(uint64_t seed, int64_t n, int n_fabrics, float r_lo, float r_hi,
+                             const fabric_gbuffer_out &out, hipStream_t stream)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const double lo = std::log((double)r_lo), hi = std::log((double)r_hi);
+    hipLaunchKernelGGL(make_batch_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       seed, n, n_fabrics, (float)lo, (float)(hi - lo), out);
+    return hipGetLastError();
+}
+
+hipError_t decoder_backward(TrainScratch &s, const fabric_gbuffer &g, const DevFabric *fabrics,
+                            int n_fabrics, const float *dec_params, const float *latents,
+                            const float *grad_y4, float *grad_params, float *grad_latents,
+                            hipStream_t stream)
+{
+    hipError_t e = ensure_acts(s, g.n > 0 ? g.n : 1);
+    if (e != hipSuccess) return e;
+    if ((e = pack_images(s, FABRIC_FP32, dec_params, stream)) != hipSuccess) return e;
+    if ((e = launch_fold_latents(dec_params, latents, n_fabrics, s.cfold, stream)) != hipSuccess) return e;
+    if (g.n > 0) {
+        if ((e = launch_fwd_bwd<FABRIC_FP32, true>(s, g, fabrics, n_fabrics, s.cfold, grad_y4, nullptr,
+                                                   stream)) != hipSuccess)
+            return e;
+        if ((e = decoder_weight_grads(s, g, n_fabrics, grad_params, stream)) != hipSuccess) return e;
+    } else {
+        if ((e = hipMemsetAsync(grad_params, 0, FABRIC_N_DECODER_PARAMS * sizeof(float), stream)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(s.dcf, 0, (size_t)n_fabrics * 64 * sizeof(float), stream)) != hipSuccess) return e;
+    }
+    const int tot = (n_fabrics * kLatent > 64 * kLatent) ? n_fabrics * kLatent : 64 * kLatent;
+    hipLaunchKernelGGL(latent_grads_kernel, dim3((tot + 255) / 256), dim3(256), 0, stream, dec_params,
+                       (const float *)s.dcf, latents, n_fabrics, grad_latents, grad_params + kOffW1);
+    return hipGetLastError();
+}
+
+hipError_t encoder_backward(TrainScratch &s, const float *enc_params, const float *enc_inputs,
+                            int n_fabrics, const float *grad_latents, float *grad_enc_params,
+                            hipStream_t stream)
+{
+    hipError_t e = ensure_acts(s, 1);
+    if (e != hipSuccess)
+        return e;
+    return run_encoder_backward(s, enc_params, enc_inputs, n_fabrics, grad_latents,
+                                grad_enc_params, stream);
+}
+
+namespace {
+
+// Loss and full gradient (into s.grad) of one batch; s.loss holds the loss.
+hipError_t loss_and_grad(TrainScratch &s, const TrainArgs &a, hipStream_t stream)
+{
+    const fabric_train_cfg &cfg = a.cfg;
+    fabric_gbuffer g;
+    hipError_t e;
+    if (a.batch) {
+        g = *a.batch;
+    } else {
+        const int64_t n = cfg.batch;
+        if (s.batch_cap < n) {
+            if ((e = grow(&s.b_fid, (size_t)n)) != hipSuccess) return e;
+            if ((e = grow(&s.b_fields, (size_t)n * 9)) != hipSuccess) return e;
+            if ((e = grow(&s.targets, (size_t)n * 4)) != hipSuccess) return e;
+            s.batch_cap = n;
+        }
+        fabric_gbuffer_out o;
+        o.n = n;
+        o.fabric_id = s.b_fid;
+        float *f = s.b_fields;
+        const int64_t c = s.batch_cap;
+        o.u = f; o.v = f + c; o.radius = f + 2 * c; o.wi_x = f + 3 * c; o.wi_y = f + 4 * c;
+        o.wi_z = f + 5 * c; o.wo_x = f + 6 * c; o.wo_y = f + 7 * c; o.wo_z = f + 8 * c;
+        if ((e = launch_make_batch(cfg.seed, n, a.n_fabrics, cfg.r_lo, cfg.r_hi, o, stream)) != hipSuccess)
+            return e;
+        g.n = n; g.fabric_id = o.fabric_id; g.u = o.u; g.v = o.v; g.radius = o.radius;
+        g.wi_x = o.wi_x; g.wi_y = o.wi_y; g.wi_z = o.wi_z; g.wo_x = o.wo_x; g.wo_y = o.wo_y; g.wo_z = o.wo_z;
+    }
+    const int64_t n = g.n;
+    if ((e = ensure_acts(s, n > 0 ? n : 1)) != hipSuccess) return e;
+    const float *targets = a.targets;
+    if (!targets && n > 0) {
+        if (s.batch_cap < n) {
+            // A caller-supplied batch larger than any generated one: the
+            // batch planes are not in use, so all three buffers may grow.
+            if ((e = grow(&s.targets, (size_t)n * 4)) != hipSuccess) return e;
+            if ((e = grow(&s.b_fid, (size_t)n)) != hipSuccess) return e;
+            if ((e = grow(&s.b_fields, (size_t)n * 9)) != hipSuccess) return e;
+            s.batch_cap = n;
+        }
+        if ((e = launch_gt_filter(g, a.fabrics, a.n_fabrics, cfg.gt_samples, cfg.seed ^ 1ull, nullptr,
+                                  s.targets, a.err, stream)) != hipSuccess)
+            return e;
+        targets = s.targets;
+    }
+    const float *dec = a.params, *enc = a.params + kNDec;
+    if ((e = launch_encoder_forward(enc, a.enc_inputs, a.n_fabrics, s.latents, stream)) != hipSuccess) return e;
+    if ((e = launch_fold_latents(dec, s.latents, a.n_fabrics, s.cfold, stream)) != hipSuccess) return e;
+    if ((e = pack_images(s, cfg.prec, dec, stream)) != hipSuccess) return e;
+    if (n > 0) {
+        // Faults of a generated-target batch were counted by the filter.
+        unsigned long long *err = a.targets ? a.err : nullptr;
+        e = cfg.prec == FABRIC_FP32
+                ? launch_fwd_bwd<FABRIC_FP32, false>(s, g, a.fabrics, a.n_fabrics, s.cfold, targets, err, stream)
+                : launch_fwd_bwd<FABRIC_BF16, false>(s, g, a.fabrics, a.n_fabrics, s.cfold, targets, err, stream);
+        if (e != hipSuccess) return e;
+        const int64_t parts = (n + 15) / 16;
+        hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, stream, (const double *)s.loss_part,
+                           parts, 1.0 / (double)n, s.loss);
+        if ((e = decoder_weight_grads(s, g, a.n_fabrics, s.grad, stream)) != hipSuccess) return e;
+    } else {
+        if ((e = hipMemsetAsync(s.loss, 0, sizeof(double), stream)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(s.grad, 0, kNDec * sizeof(float), stream)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(s.dcf, 0, (size_t)a.n_fabrics * 64 * sizeof(float), stream)) != hipSuccess) return e;
+    }
+    const int tot = (a.n_fabrics * kLatent > 64 * kLatent) ? a.n_fabrics * kLatent : 64 * kLatent;
+    hipLaunchKernelGGL(latent_grads_kernel, dim3((tot + 255) / 256), dim3(256), 0, stream, dec,
+                       (const float *)s.dcf, (const float *)s.latents, a.n_fabrics, s.dz, s.grad + kOffW1);
+    if ((e = run_encoder_backward(s, enc, a.enc_inputs, a.n_fabrics, s.dz, s.grad + kNDec, stream)) != hipSuccess)
+        return e;
+    return hipGetLastError();
+}
+
+hipError_t read_loss(TrainScratch &s, float *out_loss, int *finite_loss, hipStream_t stream)
+{
+    double l = 0.0;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(&l, s.loss, sizeof(double), hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;
+    *out_loss = (float)l;
+    *finite_loss = std::isfinite(l) ? 1 : 0;
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t loss_grad(TrainScratch &s, const TrainArgs &a, float *grad_out, float *out_loss,
+                     hipStream_t stream)
+{
+    hipError_t e = loss_and_grad(s, a, stream);
+    if (e != hipSuccess)
+        return e;
+    if ((e = hipMemcpyAsync(grad_out, s.grad, FABRIC_N_PARAMS * sizeof(float), hipMemcpyDeviceToDevice,
+                            stream)) != hipSuccess)
+        return e;
+    if (out_loss) {
+        int fin = 0;
+        return read_loss(s, out_loss, &fin, stream);
+    }
+    return hipSuccess;
+}
+
+hipError_t train_step(TrainScratch &s, const TrainArgs &a, float *out_loss, int *updated,
+                      hipStream_t stream)
+{
+    *updated = 1;
+    const fabric_train_cfg &cfg = a.cfg;
+    hipError_t e = loss_and_grad(s, a, stream);
+    if (e != hipSuccess)
+        return e;
+    const double c1 = 1.0 - std::pow(cfg.beta1, (double)a.step);
+    const double c2 = 1.0 - std::pow(cfg.beta2, (double)a.step);
+    hipLaunchKernelGGL(adam_kernel, dim3((FABRIC_N_PARAMS + 255) / 256), dim3(256), 0, stream,
+                       a.params, (const float *)s.grad, a.adam_m, a.adam_v, FABRIC_N_PARAMS, cfg.lr,
+                       cfg.beta1, cfg.beta2, cfg.eps, c1, c2, (const double *)s.loss);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    if (out_loss)
+        return read_loss(s, out_loss, updated, stream);
+    return hipSuccess;
+}
+
+}  // namespace fab

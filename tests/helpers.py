@@ -1,0 +1,44 @@
+"""Shared helpers of the GPU tests: device set-up and tolerance checks."""
+import numpy as np
+import pytest
+
+
+def require_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("needs an MI355X GPU")
+    return torch
+
+
+def rel_norm_err(a, b) -> float:
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def filter_mismatch(gpu_comp, orc_comp, flagged, rel=1e-4, abs_floor=1e-9):
+    """Per-pixel error of the footprint filter, relative to the pixel's largest
+    component.  Returns (bad mask, per-pixel error)."""
+    g = np.asarray(gpu_comp, dtype=np.float64)
+    o = np.asarray(orc_comp, dtype=np.float64)
+    scale = np.abs(o).max(axis=0)
+    err = np.abs(g - o).max(axis=0) / np.maximum(scale, abs_floor)
+    bad = np.abs(g - o).max(axis=0) > rel * scale + abs_floor
+    return bad, err
+
+
+def assert_filter_parity(gpu_comp, orc_comp, flagged, rel=1e-4, max_flagged_bad=1e-3):
+    """Unflagged pixels within `rel` of their largest component; pixels whose
+    samples sit within 1e-5 cells of a classification edge (where FP32 and
+    FP64 may classify a sample differently) may deviate, but at most
+    `max_flagged_bad` of all pixels may do so."""
+    bad, err = filter_mismatch(gpu_comp, orc_comp, flagged, rel)
+    flagged = np.asarray(flagged) > 0
+    n = bad.size
+    unflagged_bad = bad & ~flagged
+    msg = (f"pixels {n}, bad {int(bad.sum())}, unflagged bad {int(unflagged_bad.sum())}, "
+           f"flagged {int(flagged.sum())}, max err unflagged "
+           f"{float(err[~flagged].max()) if (~flagged).any() else 0:.3g}")
+    assert not unflagged_bad.any(), msg
+    assert bad.sum() <= max(1, max_flagged_bad * n), msg
+    return msg
