@@ -306,9 +306,16 @@ class Fabric:
     def latents(self) -> np.ndarray:
         return fabric_get_latents(self.ctx, self.n_mats)
 
-    def train_step(self, batch=None, targets=None, **cfg) -> Optional[float]:
-        want = cfg.pop("want_loss", True)
-        return fabric_train_step(self.ctx, batch, targets, cfg, want_loss=want)
+    def train_step(self, gbuf: Optional[DeviceGBuffer] = None, targets=None, want_loss: bool = True,
+                   **cfg) -> Optional[float]:
+        """One optimiser step on `gbuf` (or on cfg["batch"] generated samples)."""
+        return fabric_train_step(self.ctx, gbuf, targets, cfg, want_loss=want_loss)
+
+    def loss_grad(self, gbuf: Optional[DeviceGBuffer] = None, targets=None, **cfg):
+        torch = _torch()
+        grad = torch.empty(FABRIC_N_PARAMS, dtype=torch.float32, device="cuda")
+        loss = fabric_loss_grad(self.ctx, gbuf, targets, cfg, grad)
+        return loss, grad
 
     def error_count(self, reset: bool = False) -> int:
         return fabric_error_count(self.ctx, reset)
