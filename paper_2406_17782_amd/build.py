@@ -14,7 +14,10 @@ SOURCES = ["fabric_api.cpp", "gt_filter.hip", "decode.hip", "encode.hip", "train
 
 # Packed FP32 VALU instructions stay disabled: ordinary float code only.
 HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",
-               "-Wno-unused-function", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+               "-Wno-unused-function", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               # MFMA results in VGPRs: the VALU reads every accumulator (bias,
+               # ReLU, conversion), so AGPR destinations would cost a copy each.
+               "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def _compile(src: str) -> str:

@@ -89,7 +89,38 @@ template <> struct Mfma<FABRIC_FP32> {
     }
     static __device__ inline void set(Frag &f, int j, float v) { (void)j; f = v; }
     static __device__ inline Frag zero() { return 0.0f; }
+    static __device__ inline Frag relu(Frag f) { return fmaxf(f, 0.0f); }
 };
+
+// ReLU of eight 16-bit floats at once: for both bf16 and fp16 a value is
+// negative exactly when its bit pattern is a negative int16, so a packed
+// signed-integer max against 0 clamps it (-0 becomes +0).
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+template <typename F> __device__ inline F relu16x8(F f)
+{
+    s16x8 s = __builtin_bit_cast(s16x8, f);
+    s = __builtin_elementwise_max(s, (s16x8)(0));
+    return __builtin_bit_cast(F, s);
+}
+
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// Eight floats rounded pairwise into one 8 x 16-bit fragment (H2 = the
+// matching 2-wide 16-bit vector): one packed conversion per pair.
+template <typename F, typename H2> __device__ inline F pack8(f32x8 v)
+{
+    u32x4 w;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        H2 h = __builtin_convertvector((f32x2){v[2 * q], v[2 * q + 1]}, H2);
+        w[q] = __builtin_bit_cast(unsigned, h);
+    }
+    return __builtin_bit_cast(F, w);
+}
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
 template <> struct Mfma<FABRIC_BF16> {
     static constexpr int KPL = 8;
@@ -99,6 +130,9 @@ template <> struct Mfma<FABRIC_BF16> {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     }
     static __device__ inline void set(Frag &f, int j, float v) { f[j] = (__bf16)v; }
+    static __device__ inline Frag relu(Frag f) { return relu16x8(f); }
+    // Round eight floats at once (pairs map onto packed conversions).
+    static __device__ inline Frag from8(f32x8 v) { return pack8<Frag, bf16x2>(v); }
     static __device__ inline Frag zero()
     {
         Frag f;
@@ -115,6 +149,8 @@ template <> struct Mfma<FABRIC_FP16> {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
     }
     static __device__ inline void set(Frag &f, int j, float v) { f[j] = (_Float16)v; }
+    static __device__ inline Frag relu(Frag f) { return relu16x8(f); }
+    static __device__ inline Frag from8(f32x8 v) { return pack8<Frag, f16x2>(v); }
     static __device__ inline Frag zero()
     {
         Frag f;

@@ -16,6 +16,7 @@
 // owns the tile evaluates them one at a time with all 64 lanes.
 #include "kernels.hpp"
 #include "mlp_tile.hpp"
+#include "mlp_tile32.hpp"
 
 namespace fab {
 
@@ -32,15 +33,21 @@ __global__ __launch_bounds__(256) void decode_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ frags,
     const f32x4 *__restrict__ bias, int fb_samples, int fb_side, float fb_inv_side,
-    uint64_t seed, float *__restrict__ out, unsigned long long *err, int64_t n_tiles)
+    uint64_t seed, float *__restrict__ out, unsigned long long *err, int n_tiles)
 {
     using T = Tile<P>;
     using Frag = typename T::Frag;
     using S = typename T::S;
+    using FM = FeatureMath<P>;
 
-    extern __shared__ float smem[];
-    float *s_cf = smem;                       // [n_fabrics][64]
-    float *s_fc = smem + n_fabrics * 64;      // [n_fabrics][kFabConsts]
+    // LDS: C-operand biases of L2..L4 [kBiasFrags][64 lanes], then per fabric
+    // c_f [64] and constants [kFabConsts].
+    extern __shared__ f32x4 smem4[];
+    f32x4 *s_bias = smem4;
+    float *s_cf = (float *)(smem4 + kBiasFrags * 64);
+    float *s_fc = s_cf + n_fabrics * 64;
+    for (int k = threadIdx.x; k < kBiasFrags * 64; k += blockDim.x)
+        s_bias[k] = bias[k];
     for (int k = threadIdx.x; k < n_fabrics * 64; k += blockDim.x)
         s_cf[k] = cfold[k];
     for (int k = threadIdx.x; k < n_fabrics * kFabConsts; k += blockDim.x) {
@@ -61,36 +68,30 @@ __global__ __launch_bounds__(256) void decode_kernel(
     const int grp = lane >> 4;
     const int col = lane & 15;
 
+    // The whole decoder stays in registers for the wave's lifetime.
     Frag A[S::NFRAG];
 #pragma unroll
     for (int q = 0; q < S::NFRAG; q++)
         A[q] = frags[q * 64 + lane];
-    f32x4 bb[kBiasFrags];
-#pragma unroll
-    for (int q = 0; q < kBiasFrags; q++)
-        bb[q] = bias[q * 64 + lane];
     auto getA = [&](int q) { return A[q]; };
-    auto getBias = [&](int q) { return bb[q]; };
+    auto getBias = [&](int q) { return s_bias[q * 64 + lane]; };
 
-    const int64_t n = g.n;
-    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int n = (int)g.n;
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    const int wave_id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
 
-    for (int64_t tile = wave_id; tile < n_tiles; tile += waves) {
-        const int64_t p = tile * 16 + col;
+    for (int tile = wave_id; tile < n_tiles; tile += waves) {
+        const int p = tile * 16 + col;
         const bool valid = p < n;
-        const int64_t pc = valid ? p : n - 1;
+        const int pc = valid ? p : n - 1;
         int fid = g.fabric_id[pc];
-        float u = g.u[pc], v = g.v[pc], r = g.radius[pc];
-        float3 wi = make_float3(g.wi_x[pc], g.wi_y[pc], g.wi_z[pc]);
-        float3 wo = make_float3(g.wo_x[pc], g.wo_y[pc], g.wo_z[pc]);
+        const float u = g.u[pc], v = g.v[pc], r = g.radius[pc];
+        const float3 wi = make_float3(g.wi_x[pc], g.wi_y[pc], g.wi_z[pc]);
+        const float3 wo = make_float3(g.wo_x[pc], g.wo_y[pc], g.wo_z[pc]);
         const bool fault = pixel_fault(fid, n_fabrics, u, v, r, wi, wo);
-        if (fault) {   // keep the arithmetic finite; the outputs are zeroed below
-            fid = 0;
-            u = v = 0.0f;
-            r = 1.0f;
-            wi = wo = make_float3(0.0f, 0.0f, 1.0f);
-        }
+        // Only the table index needs a safe value: non-finite inputs stay in
+        // their own pixel's column of every MFMA tile and are zeroed on output.
+        fid = fault ? 0 : fid;
         const float *fc = s_fc + fid * kFabConsts;
 
         float s1[T::NS1];
@@ -113,8 +114,8 @@ __global__ __launch_bounds__(256) void decode_kernel(
                     out[c * n + p] = fault ? 0.0f : y[c];
             } else {
                 float cw = fmaxf(y[0], 0.0f), cwf = fmaxf(y[1], 0.0f);
-                float sw = fmaxf(expm1f(y[2]) * (1.0f / kSpec), 0.0f);
-                float sf = fmaxf(expm1f(y[3]) * (1.0f / kSpec), 0.0f);
+                float sw = fmaxf(FM::expm1(y[2]) * (1.0f / kSpec), 0.0f);
+                float sf = fmaxf(FM::expm1(y[3]) * (1.0f / kSpec), 0.0f);
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
                     float rgb = fc[4 + c] * cw + fc[7 + c] * cwf + fc[10 + c] * sw + fc[13 + c] * sf;
@@ -132,7 +133,7 @@ __global__ __launch_bounds__(256) void decode_kernel(
             while (todo) {
                 const int c = __builtin_ctzll(todo);
                 todo &= todo - 1;
-                const int64_t pp = tile * 16 + c;
+                const int pp = tile * 16 + c;
                 const int ff = __shfl(fid, c, 64);
                 const float uu = __shfl(u, c, 64), vv = __shfl(v, c, 64), rr = __shfl(r, c, 64);
                 const float3 wwi = make_float3(__shfl(wi.x, c, 64), __shfl(wi.y, c, 64),
@@ -152,6 +153,201 @@ __global__ __launch_bounds__(256) void decode_kernel(
                 }
             }
         }
+    }
+}
+
+// Neural shading on 32x32x16 MFMA tiles (bf16 / fp16): 32 pixels per wave
+// iteration, two lane groups per pixel.  Same stages as decode_kernel.
+template <int P, bool HYBRID>
+__global__ __launch_bounds__(256) void decode32_kernel(
+    fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
+    const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ frags,
+    const f32x4 *__restrict__ bias2, const f32x4 *__restrict__ bias4, int fb_samples,
+    int fb_side, float fb_inv_side, uint64_t seed, float *__restrict__ out,
+    unsigned long long *err, int n_tiles)
+{
+    using T = Tile32<P>;
+    using Frag = typename T::Frag;
+    using S = typename T::S;
+    using FM = FeatureMath<P>;
+
+    // LDS: L2 C-operand bias [2][64 lanes][4 x f32x4], then per fabric c_f [64]
+    // and constants [kFabConsts].
+    extern __shared__ f32x4 smem4[];
+    f32x4 *s_b2 = smem4;
+    float *s_cf = (float *)(smem4 + 2 * 64 * 4);
+    float *s_fc = s_cf + n_fabrics * 64;
+    for (int k = threadIdx.x; k < 2 * 64 * 4; k += blockDim.x)
+        s_b2[k] = bias2[k];
+    for (int k = threadIdx.x; k < n_fabrics * 64; k += blockDim.x)
+        s_cf[k] = cfold[k];
+    for (int k = threadIdx.x; k < n_fabrics * kFabConsts; k += blockDim.x) {
+        const DevFabric &f = fabrics[k / kFabConsts];
+        int c = k % kFabConsts;
+        float val;
+        if (c == 0) val = f.fwx;
+        else if (c == 1) val = f.fwy;
+        else if (c == 2) val = f.inv_wx;
+        else if (c == 3) val = f.inv_wy;
+        else if (c < 10) val = f.kd[(c - 4) / 3][(c - 4) % 3];
+        else val = f.ks[(c - 10) / 3][(c - 10) % 3];
+        s_fc[k] = val;
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 5;
+    const int col = lane & 31;
+
+    Frag A[S::NFRAG];
+#pragma unroll
+    for (int q = 0; q < S::NFRAG; q++)
+        A[q] = frags[q * 64 + lane];
+    auto getA = [&](int q) { return A[q]; };
+    f32x16 b4 = f32x16{};
+    {
+        const f32x4 t = bias4[lane];
+        b4[0] = t[0];
+        b4[1] = t[1];
+        b4[2] = t[2];
+        b4[3] = t[3];
+    }
+
+    const int n = (int)g.n;
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    const int wave_id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+
+    for (int tile = wave_id; tile < n_tiles; tile += waves) {
+        const int p = tile * 32 + col;
+        const bool valid = p < n;
+        const int pc = valid ? p : n - 1;
+        int fid = g.fabric_id[pc];
+        const float u = g.u[pc], v = g.v[pc], r = g.radius[pc];
+        const float3 wi = make_float3(g.wi_x[pc], g.wi_y[pc], g.wi_z[pc]);
+        const float3 wo = make_float3(g.wo_x[pc], g.wo_y[pc], g.wo_z[pc]);
+        const bool fault = pixel_fault(fid, n_fabrics, u, v, r, wi, wo);
+        fid = fault ? 0 : fid;   // non-finite inputs stay in their own column
+        const float *fc = s_fc + fid * kFabConsts;
+
+        float s1[kL1Slots32];
+        T::spatial_slots(u, v, r, fc[0], fc[1], fc[2], fc[3], grp, s1);
+        f32x16 cf[2], b2[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; mb++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const f32x4 c4 = *(const f32x4 *)(s_cf + fid * 64 + 32 * mb + 8 * q + 4 * grp);
+                const f32x4 bq = s_b2[(mb * 64 + lane) * 4 + q];
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    cf[mb][4 * q + i] = c4[i];
+                    b2[mb][4 * q + i] = bq[i];
+                }
+            }
+        const float x0 = grp == 0 ? wi.x : wo.x;
+        const float x1 = grp == 0 ? wi.y : wo.y;
+        const float x2 = grp == 0 ? wi.z : 1.0f;
+        const f32x16 y = T::forward(getA, cf, b2, b4, s1, x0, x1, x2);
+
+        // Lanes 0..31 hold y[0..3] of pixel tile*32 + lane.
+        const bool oor = HYBRID && !fault && out_of_range(r, wo.z);
+        if (grp == 0 && valid && !oor) {
+            const float cw = fmaxf(y[0], 0.0f), cwf = fmaxf(y[1], 0.0f);
+            const float sw = fmaxf(FM::expm1(y[2]) * (1.0f / kSpec), 0.0f);
+            const float sf = fmaxf(FM::expm1(y[3]) * (1.0f / kSpec), 0.0f);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const float rgb = fc[4 + c] * cw + fc[7 + c] * cwf + fc[10 + c] * sw + fc[13 + c] * sf;
+                out[c * n + p] = fault ? 0.0f : rgb;
+            }
+        }
+        const unsigned long long bad = __ballot(grp == 0 && valid && fault);
+        if (lane == 0 && bad)
+            atomicAdd(err, (unsigned long long)__popcll(bad));
+
+        if (HYBRID) {
+            unsigned long long todo = __ballot(grp == 0 && valid && oor);
+            while (todo) {
+                const int c = __builtin_ctzll(todo);
+                todo &= todo - 1;
+                const int pp = tile * 32 + c;
+                const int ff = __shfl(fid, c, 64);
+                const float uu = __shfl(u, c, 64), vv = __shfl(v, c, 64), rr = __shfl(r, c, 64);
+                const float3 wwi = make_float3(__shfl(wi.x, c, 64), __shfl(wi.y, c, 64),
+                                               __shfl(wi.z, c, 64));
+                const float3 wwo = make_float3(__shfl(wo.x, c, 64), __shfl(wo.y, c, 64),
+                                               __shfl(wo.z, c, 64));
+                double comp[4];
+                filter_pixel_wave(fabrics[ff], seed, (uint64_t)pp, fb_samples, fb_side,
+                                  fb_inv_side, uu, vv, rr, wwi, wwo, lane, comp);
+                if (lane == 0) {
+                    const DevFabric &f = fabrics[ff];
+                    for (int ch = 0; ch < 3; ch++) {
+                        double rgb = (double)f.kd[0][ch] * comp[0] + (double)f.kd[1][ch] * comp[1] +
+                                     (double)f.ks[0][ch] * comp[2] + (double)f.ks[1][ch] * comp[3];
+                        out[ch * n + pp] = (float)rgb;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Image of the 32-pixel layout from FP32 decoder parameters.
+template <int P>
+__global__ void pack_decoder32_kernel(const float *__restrict__ params,
+                                      typename Mfma<P>::Frag *__restrict__ frags,
+                                      f32x4 *__restrict__ bias2, f32x4 *__restrict__ bias4)
+{
+    using M = Mfma<P>;
+    using S = DecShape32<8>;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < S::NFRAG * 64) {
+        const int fr = idx / 64, lane = idx % 64, row = lane & 31, grp = lane >> 5;
+        int layer, mb, ks;
+        if (fr < S::FRAG_L2) { layer = 1; mb = fr / S::KS1; ks = fr % S::KS1; }
+        else if (fr < S::FRAG_L3) { layer = 2; mb = (fr - S::FRAG_L2) / S::KS2; ks = (fr - S::FRAG_L2) % S::KS2; }
+        else if (fr < S::FRAG_L4) { layer = 3; mb = (fr - S::FRAG_L3) / S::KS3; ks = (fr - S::FRAG_L3) % S::KS3; }
+        else { layer = 4; mb = 0; ks = fr - S::FRAG_L4; }
+        const int m = 32 * mb + row;
+        typename M::Frag f = M::zero();
+        for (int j = 0; j < 8; j++) {
+            const int c = ks * 8 + j;
+            float w = 0.0f;
+            if (layer == 1) {
+                const int feat = l1_feature32(grp, c);
+                if (feat >= 0) w = params[kOffW1 + m * 72 + kLatent + feat];
+            } else if (layer == 2) {
+                if (c < kChain32) w = params[kOffW2 + m * 64 + chain32_neuron(grp, c)];
+            } else if (layer == 3) {
+                if (c < kChain32) {
+                    w = params[kOffW3 + m * 69 + chain32_neuron(grp, c)];
+                } else if (c < kL3Slots32) {
+                    const int a = l3_extra32(grp, c - kChain32);
+                    if (a == 5) w = params[kOffB3 + m];
+                    else if (a >= 0) w = params[kOffW3 + m * 69 + 64 + a];
+                }
+            } else {
+                if (m < 4 && c < kChain32) w = params[kOffW4 + m * 64 + chain32_neuron(grp, c)];
+            }
+            M::set(f, j, w);
+        }
+        frags[idx] = f;
+    }
+    if (idx < 2 * 64 * 4) {
+        // bias2[(mb*64 + lane)*4 + q][i] = b2[row of register 4q + i]
+        const int q = idx & 3, lane = (idx >> 2) & 63, mb = idx >> 8, grp = lane >> 5;
+        f32x4 b;
+        for (int i = 0; i < 4; i++)
+            b[i] = params[kOffB2 + 32 * mb + 8 * q + 4 * grp + i];
+        bias2[idx] = b;
+    }
+    if (idx < 64) {
+        const int grp = idx >> 5;
+        f32x4 b;
+        for (int i = 0; i < 4; i++)
+            b[i] = grp == 0 ? params[kOffB4 + i] : 0.0f;
+        bias4[idx] = b;
     }
 }
 
@@ -225,6 +421,62 @@ __global__ void fold_latents_kernel(const float *__restrict__ params,
     cfold[idx] = acc;
 }
 
+int device_cus()
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+size_t image32_bytes()
+{
+    return (size_t)DecShape32<8>::NFRAG * 64 * 16 + (size_t)2 * 64 * 4 * sizeof(f32x4) +
+           (size_t)64 * sizeof(f32x4);
+}
+
+template <int P> hipError_t pack32(const float *params, void *image, hipStream_t stream)
+{
+    using M = Mfma<P>;
+    auto *frags = (typename M::Frag *)image;
+    auto *b2 = (f32x4 *)((char *)image + (size_t)DecShape32<8>::NFRAG * 64 * 16);
+    auto *b4 = b2 + 2 * 64 * 4;
+    const int total = DecShape32<8>::NFRAG * 64;
+    hipLaunchKernelGGL(pack_decoder32_kernel<P>, dim3((total + 255) / 256), dim3(256), 0, stream,
+                       params, frags, b2, b4);
+    return hipGetLastError();
+}
+
+template <int P, bool HYBRID>
+hipError_t decode32(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
+                    const float *cfold, const void *image, int fb_samples, uint64_t seed,
+                    float *out, unsigned long long *err, hipStream_t stream)
+{
+    using M = Mfma<P>;
+    const auto *frags = (const typename M::Frag *)image;
+    const auto *b2 = (const f32x4 *)((const char *)image + (size_t)DecShape32<8>::NFRAG * 64 * 16);
+    const auto *b4 = b2 + 2 * 64 * 4;
+    const int n_tiles = (int)((g.n + 31) / 32);
+    int blocks = (n_tiles + 3) / 4;
+    const int cap = device_cus() * 2;
+    if (blocks > cap)
+        blocks = cap;
+    int side = 1;
+    while (side * side < fb_samples)
+        side++;
+    const size_t lds = (size_t)2 * 64 * 4 * sizeof(f32x4) +
+                       (size_t)n_fabrics * (64 + kFabConsts) * sizeof(float);
+    hipLaunchKernelGGL((decode32_kernel<P, HYBRID>), dim3(blocks), dim3(256), lds, stream, g,
+                       fabrics, n_fabrics, cfold, frags, b2, b4, fb_samples, side,
+                       1.0f / (float)side, seed, out, err, n_tiles);
+    return hipGetLastError();
+}
+
 template <int P> size_t image_bytes()
 {
     using M = Mfma<P>;
@@ -244,18 +496,6 @@ template <int P> hipError_t pack(const float *params, void *image, hipStream_t s
     return hipGetLastError();
 }
 
-int device_cus()
-{
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            cus <= 0)
-            cus = 256;
-    }
-    return cus;
-}
 
 template <int P, bool RAW, bool HYBRID>
 hipError_t decode(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
@@ -267,17 +507,17 @@ hipError_t decode(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabri
     const auto *frags = (const typename M::Frag *)image;
     const auto *bias =
         (const f32x4 *)((const char *)image + (size_t)S::NFRAG * 64 * sizeof(typename M::Frag));
-    const int64_t n_tiles = (g.n + 15) / 16;
-    const int64_t waves_wanted = n_tiles;
-    int64_t blocks = (waves_wanted + 3) / 4;
-    const int64_t cap = (int64_t)device_cus() * 2;
+    const int n_tiles = (int)((g.n + 15) / 16);
+    int blocks = (n_tiles + 3) / 4;
+    const int cap = device_cus() * 2;
     if (blocks > cap)
         blocks = cap;
     int side = 1;
     while (side * side < fb_samples)
         side++;
-    const size_t lds = (size_t)n_fabrics * (64 + kFabConsts) * sizeof(float);
-    hipLaunchKernelGGL((decode_kernel<P, RAW, HYBRID>), dim3((unsigned)blocks), dim3(256), lds,
+    const size_t lds = (size_t)kBiasFrags * 64 * sizeof(f32x4) +
+                       (size_t)n_fabrics * (64 + kFabConsts) * sizeof(float);
+    hipLaunchKernelGGL((decode_kernel<P, RAW, HYBRID>), dim3(blocks), dim3(256), lds,
                        stream, g, fabrics, n_fabrics, cfold, frags, bias, fb_samples, side,
                        1.0f / (float)side, seed, out, err, n_tiles);
     return hipGetLastError();
@@ -314,6 +554,20 @@ hipError_t launch_fold_latents(const float *dec_params, const float *latents, in
     return hipGetLastError();
 }
 
+size_t shade_image_bytes(int prec)
+{
+    return (prec == FABRIC_BF16 || prec == FABRIC_FP16) ? image32_bytes() : decoder_image_bytes(prec);
+}
+
+hipError_t launch_pack_shade(int prec, const float *dec_params, void *image, hipStream_t stream)
+{
+    switch (prec) {
+    case FABRIC_BF16: return pack32<FABRIC_BF16>(dec_params, image, stream);
+    case FABRIC_FP16: return pack32<FABRIC_FP16>(dec_params, image, stream);
+    default: return launch_pack_decoder(prec, dec_params, image, stream);
+    }
+}
+
 hipError_t launch_decode(int prec, bool raw, const fabric_gbuffer &g, const DevFabric *fabrics,
                          int n_fabrics, const float *cfold, const void *image,
                          int fallback_samples, uint64_t seed, float *out,
@@ -331,10 +585,17 @@ hipError_t launch_decode(int prec, bool raw, const fabric_gbuffer &g, const DevF
                                          seed, out, err, stream);                               \
     return decode<PREC, false, false>(g, fabrics, n_fabrics, cfold, image, 0, seed, out, err,   \
                                       stream);
+    // Shading in bf16 / fp16 runs on 32-pixel tiles (image from
+    // launch_pack_shade); the raw forward and fp32 on 16-pixel tiles.
+    if (!raw && prec == FABRIC_BF16)
+        return hybrid ? decode32<FABRIC_BF16, true>(g, fabrics, n_fabrics, cfold, image, fallback_samples, seed, out, err, stream)
+                      : decode32<FABRIC_BF16, false>(g, fabrics, n_fabrics, cfold, image, 0, seed, out, err, stream);
+    if (!raw && prec == FABRIC_FP16)
+        return hybrid ? decode32<FABRIC_FP16, true>(g, fabrics, n_fabrics, cfold, image, fallback_samples, seed, out, err, stream)
+                      : decode32<FABRIC_FP16, false>(g, fabrics, n_fabrics, cfold, image, 0, seed, out, err, stream);
     switch (prec) {
     case FABRIC_FP32: { FAB_DECODE(FABRIC_FP32) }
     case FABRIC_BF16: { FAB_DECODE(FABRIC_BF16) }
-    case FABRIC_FP16: { FAB_DECODE(FABRIC_FP16) }
     default: return hipErrorInvalidValue;
     }
 #undef FAB_DECODE

@@ -217,7 +217,8 @@ void init_params(uint64_t seed, std::vector<float> &out)
 
 bool valid_gbuffer(const fabric_gbuffer *g)
 {
-    if (!g || g->n < 0)
+    // Kernels index pixels with 32-bit integers.
+    if (!g || g->n < 0 || g->n > (int64_t)INT32_MAX / 16)
         return false;
     if (g->n == 0)
         return true;
@@ -237,7 +238,7 @@ bool perfect_square(int n)
 fabric_status ensure_image(fabric_ctx *ctx, int prec, hipStream_t stream)
 {
     if (!ctx->image[prec]) {
-        const size_t bytes = decoder_image_bytes(prec);
+        const size_t bytes = shade_image_bytes(prec);
         if (bytes == 0)
             return FABRIC_E_INVAL;
         fabric_status st = from_hip(hipMalloc(&ctx->image[prec], bytes));
@@ -245,7 +246,7 @@ fabric_status ensure_image(fabric_ctx *ctx, int prec, hipStream_t stream)
             return st;
     }
     if (ctx->image_version[prec] != ctx->weights_version) {
-        fabric_status st = from_hip(launch_pack_decoder(prec, ctx->params, ctx->image[prec], stream));
+        fabric_status st = from_hip(launch_pack_shade(prec, ctx->params, ctx->image[prec], stream));
         if (st != FABRIC_OK)
             return st;
         ctx->image_version[prec] = ctx->weights_version;

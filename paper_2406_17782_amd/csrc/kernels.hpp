@@ -19,12 +19,18 @@ size_t decoder_image_bytes(int prec);
 hipError_t launch_pack_decoder(int prec, const float *dec_params, void *image,
                                hipStream_t stream);
 
+// The image the shading kernel of precision prec reads (32-pixel tiles for
+// bf16 / fp16, 16-pixel tiles for fp32).
+size_t shade_image_bytes(int prec);
+hipError_t launch_pack_shade(int prec, const float *dec_params, void *image, hipStream_t stream);
+
 // c_f = b1 + W1[:, 0:32] z_f for every fabric: cfold[n_fabrics][64].
 hipError_t launch_fold_latents(const float *dec_params, const float *latents, int n_fabrics,
                                float *cfold, hipStream_t stream);
 
-// Neural shading.  raw = true writes the decoder's outputs y[4][n]; otherwise
-// decoded, albedo-composed rgb[3][n].  fallback_samples > 0 routes
+// Neural shading.  raw = true writes the decoder's outputs y[4][n] (image from
+// launch_pack_decoder); otherwise decoded, albedo-composed rgb[3][n] (image
+// from launch_pack_shade).  fallback_samples > 0 routes
 // out-of-range pixels to the footprint filter inside the same launch.
 hipError_t launch_decode(int prec, bool raw, const fabric_gbuffer &g, const DevFabric *fabrics,
                          int n_fabrics, const float *cfold, const void *image,
