@@ -34,6 +34,44 @@ FLOP_PER_PIXEL = 2 * (40 * 64 + 64 * 64 + 69 * 64 + 64 * 4)
 BYTES_PER_PIXEL = 2 + 9 * 4 + 3 * 4
 
 
+SHADE_SOURCES = ["common.hpp", "model.hpp", "mlp_tile.hpp", "mlp_tile32.hpp", "decode.hip"]
+PROFILE = os.path.join(ROOT, "profiles", "decode32_bf16_fabric8_1080p.md")
+
+
+def recorded_traffic():
+    """HBM bytes per shading launch from the committed rocprofv3 record, if
+    the shading kernel's sources are still the ones the counters measured."""
+    import hashlib
+    import re
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None, "no profile record"
+    m = re.search(r"traffic-record: kernel=\S+ sources_sha256=([0-9a-f]+) fetch_kib=([0-9.]+) "
+                  r"write_kib=([0-9.]+) fetch_scale=([0-9.]+) write_scale=([0-9.]+)", text)
+    if not m:
+        return None, "no traffic record"
+    h = hashlib.sha256()
+    for f in SHADE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2406_17782_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != m.group(1):
+        return None, "kernel changed since the counters were taken"
+    fetch = float(m.group(2)) * float(m.group(4)) * 1024
+    write = float(m.group(3)) * float(m.group(5)) * 1024
+    return fetch + write, "rocprofv3 FETCH_SIZE x %s + WRITE_SIZE x %s" % (m.group(4), m.group(5))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
@@ -82,6 +120,55 @@ def cpu_baseline(orc, mats, g, params, budget_s):
     return out
 
 
+def oracle_errors(args, torch, pkg, fi, fab, d, mats, g, rgb, gt_rgb):
+    """RMSE and max abs of every result against the FP64 oracle's footprint
+    filter (256 samples, same samples as the GPU) on a seeded pixel subset."""
+    import oracle
+    idx = fi.subset_indices(g.n, args.rmse_frac, 99)
+    sub = g.subset(idx)
+    t0 = time.perf_counter()
+    o_comp, o_rgb, _, _ = oracle.filter_gbuffer(mats, sub, args.gt_samples, 4242, same_sample=True,
+                                                pixel_index=idx)
+    log(f"oracle reference on {len(idx)} px in {time.perf_counter() - t0:.1f}s")
+    err = {f"neural_{k}": rmse_stats(v[:, idx], o_rgb) for k, v in rgb.items()}
+    err["analytic_gpu_same_samples"] = rmse_stats(gt_rgb[:, idx], o_rgb)
+    # The method without the network: one jittered footprint sample per pixel.
+    one = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
+    pkg.fabric_gt_filtered(fab.ctx, d, 1, 777, one, None)
+    err["analytic_1spp"] = rmse_stats(one.cpu().numpy()[:, idx], o_rgb)
+    # Monte-Carlo noise floor of the 256-sample reference (truth mode, N = 128^2).
+    nf_idx = idx[:: max(1, len(idx) // 256)]
+    _, t_rgb, _, _ = oracle.filter_gbuffer(mats, g.subset(nf_idx), 128 * 128, 4242, same_sample=False,
+                                           pixel_index=nf_idx)
+    sel = np.searchsorted(idx, nf_idx)
+    err["reference256_vs_truth16384"] = rmse_stats(o_rgb[:, sel], t_rgb)
+    err["neural_bf16_vs_truth16384"] = rmse_stats(rgb["bf16"][:, nf_idx], t_rgb)
+    ratio_bf16_fp32 = err["neural_bf16"]["rmse"] / max(err["neural_fp32"]["rmse"], 1e-30)
+    # Error by footprint radius (cells): filtering matters once the footprint
+    # covers a sizeable part of a weave cell; below that one sample already
+    # lands close to the footprint average.
+    edges = [1e-3, 0.01, 0.05, 0.15, 0.3, 0.5]
+    rad = sub.radius
+    by_r = {}
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        m = (rad >= lo) & (rad < hi)
+        key = f"[{lo},{hi})"
+        by_r[key] = {"pixels": int(m.sum())}
+        for name, pred in (("neural_bf16", rgb["bf16"][:, idx]), ("neural_fp32", rgb["fp32"][:, idx]),
+                           ("analytic_1spp", one.cpu().numpy()[:, idx])):
+            by_r[key][name] = float(np.sqrt(np.mean((pred[:, m] - o_rgb[:, m]) ** 2)))
+    big = rad >= 0.15
+    one_np = one.cpu().numpy()[:, idx]
+    gain = {"footprint": "radius >= 0.15 cells", "pixels": int(big.sum()),
+            "neural_bf16_rmse": float(np.sqrt(np.mean((rgb["bf16"][:, idx][:, big] - o_rgb[:, big]) ** 2))),
+            "analytic_1spp_rmse": float(np.sqrt(np.mean((one_np[:, big] - o_rgb[:, big]) ** 2)))}
+    gain["neural_beats_1spp"] = gain["neural_bf16_rmse"] < gain["analytic_1spp_rmse"]
+    log(f"rmse bf16 {err['neural_bf16']['rmse']:.4g}, fp32 {err['neural_fp32']['rmse']:.4g}, "
+        f"1spp {err['analytic_1spp']['rmse']:.4g}")
+
+    return {"err": err, "by_r": by_r, "gain": gain, "ratio": ratio_bf16_fp32}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +183,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=8.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-rows", action="store_true", help="skip the secondary rows")
+    ap.add_argument("--no-rmse", action="store_true", help="skip the oracle error section")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -169,6 +259,14 @@ def main():
     log(f"analytic {args.gt_samples} samples: {a_ms:.2f} ms/frame, {a_mpix:.1f} Mpix/s")
     gt_rgb = a_rgb.cpu().numpy()
 
+    if args.copy_calibration:
+        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 512 MiB read + 512 MiB written")
+        del src, dst
+
     # ---- other precisions and rows ----
     rgb = {"bf16": rgb_bf16}
     for prec in ("fp32", "fp16"):
@@ -207,57 +305,18 @@ def main():
                                     "note": "host call incl. table upload"}
 
     # ---- error against the FP64 oracle on a seeded pixel subset ----
-    import oracle
-    idx = fi.subset_indices(g.n, args.rmse_frac, 99)
-    sub = g.subset(idx)
-    t0 = time.perf_counter()
-    o_comp, o_rgb, _, _ = oracle.filter_gbuffer(mats, sub, args.gt_samples, 4242, same_sample=True,
-                                                pixel_index=idx)
-    log(f"oracle reference on {len(idx)} px in {time.perf_counter() - t0:.1f}s")
-    err = {f"neural_{k}": rmse_stats(v[:, idx], o_rgb) for k, v in rgb.items()}
-    err["analytic_gpu_same_samples"] = rmse_stats(gt_rgb[:, idx], o_rgb)
-    # The method without the network: one jittered footprint sample per pixel.
-    one = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
-    pkg.fabric_gt_filtered(fab.ctx, d, 1, 777, one, None)
-    err["analytic_1spp"] = rmse_stats(one.cpu().numpy()[:, idx], o_rgb)
-    # Monte-Carlo noise floor of the 256-sample reference (truth mode, N = 128^2).
-    nf_idx = idx[:: max(1, len(idx) // 256)]
-    _, t_rgb, _, _ = oracle.filter_gbuffer(mats, g.subset(nf_idx), 128 * 128, 4242, same_sample=False,
-                                           pixel_index=nf_idx)
-    sel = np.searchsorted(idx, nf_idx)
-    err["reference256_vs_truth16384"] = rmse_stats(o_rgb[:, sel], t_rgb)
-    err["neural_bf16_vs_truth16384"] = rmse_stats(rgb["bf16"][:, nf_idx], t_rgb)
-    ratio_bf16_fp32 = err["neural_bf16"]["rmse"] / max(err["neural_fp32"]["rmse"], 1e-30)
-    # Error by footprint radius (cells): filtering matters once the footprint
-    # covers a sizeable part of a weave cell; below that one sample already
-    # lands close to the footprint average.
-    edges = [1e-3, 0.01, 0.05, 0.15, 0.3, 0.5]
-    rad = sub.radius
-    by_r = {}
-    for lo, hi in zip(edges[:-1], edges[1:]):
-        m = (rad >= lo) & (rad < hi)
-        key = f"[{lo},{hi})"
-        by_r[key] = {"pixels": int(m.sum())}
-        for name, pred in (("neural_bf16", rgb["bf16"][:, idx]), ("neural_fp32", rgb["fp32"][:, idx]),
-                           ("analytic_1spp", one.cpu().numpy()[:, idx])):
-            by_r[key][name] = float(np.sqrt(np.mean((pred[:, m] - o_rgb[:, m]) ** 2)))
-    big = rad >= 0.15
-    one_np = one.cpu().numpy()[:, idx]
-    gain = {"footprint": "radius >= 0.15 cells", "pixels": int(big.sum()),
-            "neural_bf16_rmse": float(np.sqrt(np.mean((rgb["bf16"][:, idx][:, big] - o_rgb[:, big]) ** 2))),
-            "analytic_1spp_rmse": float(np.sqrt(np.mean((one_np[:, big] - o_rgb[:, big]) ** 2)))}
-    gain["neural_beats_1spp"] = gain["neural_bf16_rmse"] < gain["analytic_1spp_rmse"]
-    log(f"rmse bf16 {err['neural_bf16']['rmse']:.4g}, fp32 {err['neural_fp32']['rmse']:.4g}, "
-        f"1spp {err['analytic_1spp']['rmse']:.4g}")
+    errs = None if args.no_rmse else oracle_errors(args, torch, pkg, fi, fab, d, mats, g, rgb, gt_rgb)
 
     # ---- CPU baseline: the oracle on the host cores ----
     cpu = None
     if not args.no_cpu:
+        import oracle
         threads = oracle.num_threads()
         res = cpu_baseline(oracle, mats, g, params, args.cpu_budget)
         n_dec, t_dec = res["decoder"]
         n_fil, t_fil = res["filter256"]
         cpu = {"value": n_dec / t_dec / 1e6, "unit": "Mpixels/s", "cores": threads, "kind": "oracle",
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
                "sample": f"FP64 oracle decoder forward on a seeded {n_dec}-pixel subset of the frame "
                          f"({t_dec:.1f} s); footprint filter at 256 samples on {n_fil} pixels "
                          f"({t_fil:.1f} s) = {n_fil / t_fil / 1e6:.4f} Mpixels/s",
@@ -266,6 +325,7 @@ def main():
             f"Mpix/s on {threads} threads")
 
     achieved_tflops = FLOP_PER_PIXEL * g.n / (ms * 1e-3) / 1e12
+    traffic, traffic_note = recorded_traffic()
     result = {
         "metric": "Mpixels/s neural vs filtered-analytic shading at 1080p; RMSE vs FP64 oracle",
         "value": mpix,
@@ -286,12 +346,14 @@ def main():
         "analytic_mpix_per_s": a_mpix,
         "analytic_ms_per_frame": a_ms,
         "neural_over_analytic": mpix / a_mpix,
-        "rmse_vs_fp64_oracle": err,
-        "rmse_by_footprint_radius": by_r,
-        "gain_over_method_without_network": gain,
-        "bf16_over_fp32_rmse": ratio_bf16_fp32,
+        "rmse_vs_fp64_oracle": errs and errs["err"],
+        "rmse_by_footprint_radius": errs and errs["by_r"],
+        "gain_over_method_without_network": errs and errs["gain"],
+        "bf16_over_fp32_rmse": errs and errs["ratio"],
         "roofline": {"bound": "mfma", "achieved": achieved_tflops, "peak": BF16_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tflops / BF16_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved_tflops / BF16_PEAK_TFLOPS, "traffic": traffic,
+                     "traffic_note": traffic_note,
+                     "algorithmic_bytes": BYTES_PER_PIXEL * g.n,
                      "kernel": "decode32_kernel<bf16>",
                      "hbm_gbs": BYTES_PER_PIXEL * g.n / (ms * 1e-3) / 1e9},
         "cpu_baseline": cpu,

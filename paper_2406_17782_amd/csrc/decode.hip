@@ -28,6 +28,25 @@ constexpr int kFabConsts = 16;   // per fabric in LDS: fwx fwy 1/wx 1/wy kd[2][3
 // grazing view.
 __device__ inline bool out_of_range(float r, float wo_z) { return r > 1.0f || wo_z < 0.05f; }
 
+// One pixel's G-buffer fields.
+struct Pix {
+    int fid;
+    float u, v, r;
+    float3 wi, wo;
+};
+
+__device__ inline Pix load_pix(const fabric_gbuffer &g, int p)
+{
+    Pix x;
+    x.fid = g.fabric_id[p];
+    x.u = g.u[p];
+    x.v = g.v[p];
+    x.r = g.radius[p];
+    x.wi = make_float3(g.wi_x[p], g.wi_y[p], g.wi_z[p]);
+    x.wo = make_float3(g.wo_x[p], g.wo_y[p], g.wo_z[p]);
+    return x;
+}
+
 template <int P, bool RAW, bool HYBRID>
 __global__ __launch_bounds__(256) void decode_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
@@ -217,14 +236,20 @@ __global__ __launch_bounds__(256) void decode32_kernel(
     const int waves = gridDim.x * (blockDim.x >> 6);
     const int wave_id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
 
+    // The next tile's fields are loaded while this one computes, so the HBM
+    // latency overlaps the MFMA work of the (only two) waves per SIMD.
+    Pix nxt = load_pix(g, min(wave_id * 32 + col, n - 1));
     for (int tile = wave_id; tile < n_tiles; tile += waves) {
+        const Pix cur = nxt;
+        {
+            const int tn = tile + waves < n_tiles ? tile + waves : tile;
+            nxt = load_pix(g, min(tn * 32 + col, n - 1));
+        }
         const int p = tile * 32 + col;
         const bool valid = p < n;
-        const int pc = valid ? p : n - 1;
-        int fid = g.fabric_id[pc];
-        const float u = g.u[pc], v = g.v[pc], r = g.radius[pc];
-        const float3 wi = make_float3(g.wi_x[pc], g.wi_y[pc], g.wi_z[pc]);
-        const float3 wo = make_float3(g.wo_x[pc], g.wo_y[pc], g.wo_z[pc]);
+        int fid = cur.fid;
+        const float u = cur.u, v = cur.v, r = cur.r;
+        const float3 wi = cur.wi, wo = cur.wo;
         const bool fault = pixel_fault(fid, n_fabrics, u, v, r, wi, wo);
         fid = fault ? 0 : fid;   // non-finite inputs stay in their own column
         const float *fc = s_fc + fid * kFabConsts;

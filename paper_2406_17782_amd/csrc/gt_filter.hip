@@ -11,6 +11,7 @@ namespace fab {
 namespace {
 
 constexpr int kWavesPerBlock = 4;
+constexpr int kXcds = 8;
 
 __global__ __launch_bounds__(256) void gt_filter_kernel(fabric_gbuffer g,
                                                         const DevFabric *__restrict__ fabrics,
@@ -23,7 +24,12 @@ __global__ __launch_bounds__(256) void gt_filter_kernel(fabric_gbuffer g,
     const int lane = threadIdx.x & 63;
     // Wave-uniform pixel index (keeps the pixel's loads and fabric fields scalar).
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t p = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD one
+    // contiguous range of pixels so that an input cache line is fetched into
+    // one XCD's L2 only.  gridDim.x is a multiple of kXcds.
+    const int per_xcd = gridDim.x / kXcds;
+    const int block = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+    const int64_t p = (int64_t)block * kWavesPerBlock + wave;
     if (p >= g.n)
         return;
     const int fid = g.fabric_id[p];
@@ -67,6 +73,7 @@ hipError_t launch_gt_filter(const fabric_gbuffer &g, const DevFabric *fabrics, i
     while (side * side < n_samples)
         side++;
     int64_t blocks = (g.n + kWavesPerBlock - 1) / kWavesPerBlock;
+    blocks = (blocks + kXcds - 1) / kXcds * kXcds;   // padding blocks exit at once
     hipLaunchKernelGGL(gt_filter_kernel, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
                        stream, g, fabrics, n_fabrics, n_samples, side, 1.0f / (float)side, seed,
                        out_rgb, out_comp, err);

@@ -11,12 +11,18 @@ namespace fab {
 // The index-th output of the SplitMix64 generator started at `seed`
 // (Steele, Lea and Flood 2014): the state advances by the golden gamma and
 // the output is the variant-13 finaliser of the new state.
-__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t index)
+constexpr uint64_t kGoldenGamma = 0x9E3779B97F4A7C15ull;
+
+__device__ inline uint64_t splitmix64_mix(uint64_t z)
 {
-    uint64_t z = seed + (index + 1ull) * 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
+}
+
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t index)
+{
+    return splitmix64_mix(seed + (index + 1ull) * kGoldenGamma);
 }
 
 // Upper and middle 24-bit fields of a 64-bit draw as uniforms in [0, 1).
@@ -24,6 +30,19 @@ __device__ inline float u24_hi(uint64_t z) { return (float)(uint32_t)(z >> 40) *
 __device__ inline float u24_mid(uint64_t z)
 {
     return (float)(uint32_t)((z >> 16) & 0xFFFFFFull) * 0x1p-24f;
+}
+
+// Hardware transcendentals on bounded arguments.  v_sin/v_cos take the angle
+// in revolutions; every angle below stays within [-3/8, 3/8] revolutions, far
+// from where their range reduction loses accuracy.
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline float sin_rev(float t) { return __builtin_amdgcn_sinf(t); }
+__device__ inline float cos_rev(float t) { return __builtin_amdgcn_cosf(t); }
+// tan(x) for |x| <= 1.5 rad (cos x >= 0.07).
+__device__ inline float tan_small(float x)
+{
+    const float t = x * (0.5f / kPi);
+    return sin_rev(t) * rcp(cos_rev(t));
 }
 
 // Shirley-Chiu concentric mapping of [0,1)^2 onto the unit disk.
@@ -34,10 +53,10 @@ __device__ inline float2 concentric_disk(float x, float y)
         return make_float2(0.0f, 0.0f);
     bool horiz = fabsf(a) > fabsf(b);
     float rad = horiz ? a : b;
-    float phi = horiz ? (0.25f * kPi) * (b / a) : 0.5f * kPi - (0.25f * kPi) * (a / b);
-    float s, c;
-    sincosf(phi, &s, &c);
-    return make_float2(rad * c, rad * s);
+    // phi = pi/4 (b/a) or pi/2 - pi/4 (a/b), here in revolutions
+    float q = horiz ? b * rcp(a) : a * rcp(b);
+    float phi = horiz ? 0.125f * q : 0.25f - 0.125f * q;
+    return make_float2(rad * cos_rev(phi), rad * sin_rev(phi));
 }
 
 // x reduced into [0, period) (period a small positive integer as float).
@@ -96,10 +115,12 @@ __device__ inline SampleVal eval_surface_point(const DevFabric &f, float us, flo
     uint32_t len = (cell >> 5) & 31u;
     if (on_top && len != 0u) {
         float off = (float)(cell & 31u);
-        along = 2.0f * (off + (is_warp ? t : s)) / (float)len - 1.0f;
+        along = 2.0f * (off + (is_warp ? t : s)) * rcp((float)len) - 1.0f;
     }
-    float ma = f.beta[y] * tanf(f.incl[y] * along);
-    float mb = f.beta[y] * tanf(kThetaMax * across);
+    // |incl * along| <= pi/2 * 1 and |theta_max * across| <= pi/3 (inclination
+    // is validated to at most 1.5 rad, |along|, |across| <= 1).
+    float ma = f.beta[y] * tan_small(f.incl[y] * along);
+    float mb = f.beta[y] * tan_small(kThetaMax * across);
 
     // Height-field normal m = (slopes, 1); n_p = m / |m|, n_p.z = 1/|m|.
     float mx = is_warp ? mb : ma, my = is_warp ? ma : mb;
@@ -131,27 +152,27 @@ __device__ inline SampleVal eval_surface_point(const DevFabric &f, float us, flo
     float it = wi.x * tp.x + wi.y * tp.y + wi.z * tp.z;
     float ot = wo.x * tp.x + wo.y * tp.y + wo.z * tp.z;
     float q = 1.0f + f.ia2m1[y] * ht * ht;
-    float D = f.inv_pi_alpha[y] / (q * q);
+    float D = f.inv_pi_alpha[y] * rcp(q * q);
     float sig_i = sqrtf(fmaxf(1.0f - f.alpha2m1[y] * it * it, 0.0f));
     float sig_o = sqrtf(fmaxf(1.0f - f.alpha2m1[y] * ot * ot, 0.0f));
-    float L = sig_i / ci + sig_o / co;
-    float G = -expm1f(-kTRho * L) / L;
+    float L = sig_i * rcp(ci) + sig_o * rcp(co);
+    // L >= sigma_i + sigma_o >= 2 alpha, so 1 - e^{-2L} loses at most a few
+    // ulps to cancellation for the roughness range of fabrics.
+    float G = (1.0f - __expf(-kTRho * L)) * rcp(L);
     // rho_s * A = D G / (4 ci co) * ci * co * jac
     out.num_s = 0.25f * D * G * jac;
     // Blended Lambertian of Eq. (1) per unit k_d, times <wi.n_p> and A.
     float w = f.wblend[y];
-    float fd = (w * ci / wi.z + (1.0f - w)) * (1.0f / kPi);
+    float fd = (w * ci * rcp(wi.z) + (1.0f - w)) * (1.0f / kPi);
     out.num_c = fd * ci * out.area;
     return out;
 }
 
-// Footprint sample k of pixel `pixel` (n_samples = side^2): position in cells.
-__device__ inline float2 footprint_sample(uint64_t seed, uint64_t pixel, int n_samples, int side,
-                                          float inv_side, int k, float u, float v, float r)
+// Footprint sample in stratum (kx, ky) of a side x side grid, jittered by the
+// SplitMix64 draw z; position in cells.
+__device__ inline float2 footprint_sample(uint64_t z, int kx, int ky, float inv_side, float u,
+                                          float v, float r)
 {
-    int ky = k / side;
-    int kx = k - ky * side;
-    uint64_t z = splitmix64_at(seed, pixel * (uint64_t)n_samples + (uint64_t)k);
     float2 d = concentric_disk(((float)kx + u24_hi(z)) * inv_side,
                                ((float)ky + u24_mid(z)) * inv_side);
     return make_float2(fmaf(r, d.x, u), fmaf(r, d.y, v));
@@ -176,8 +197,21 @@ __device__ inline void filter_pixel_wave(const DevFabric &f, uint64_t seed, uint
                                          double comp[4])
 {
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int k = lane; k < n_samples; k += 64) {
-        float2 pos = footprint_sample(seed, pixel, n_samples, side, inv_side, k, u, v, r);
+    // Sample k = lane + 64 i draws output pixel * N + k of SplitMix64(seed):
+    // the generator state advances by 64 gammas per iteration, and the
+    // stratum (kx, ky) = (k mod side, k div side) by 64 with one carry.
+    uint64_t state = seed + ((uint64_t)pixel * (uint64_t)n_samples + (uint64_t)lane + 1ull) * kGoldenGamma;
+    const uint64_t step = 64ull * kGoldenGamma;
+    const int dky = 64 / side, dkx = 64 - dky * side;
+    int ky = lane / side, kx = lane - ky * side;
+    for (int k = lane; k < n_samples; k += 64, state += step) {
+        float2 pos = footprint_sample(splitmix64_mix(state), kx, ky, inv_side, u, v, r);
+        kx += dkx;
+        ky += dky;
+        if (kx >= side) {
+            kx -= side;
+            ky += 1;
+        }
         SampleVal sv = eval_surface_point(f, pos.x, pos.y, wi, wo);
         double nc = sv.num_c, ns = sv.num_s;
         acc[0] += sv.yarn == kWarp ? nc : 0.0;
