@@ -169,6 +169,34 @@ def oracle_errors(args, torch, pkg, fi, fab, d, mats, g, rgb, gt_rgb):
     return {"err": err, "by_r": by_r, "gain": gain, "ratio": ratio_bf16_fp32}
 
 
+def precision_row_4k(args, torch, pkg, fi, fab, params):
+    """3840x2160 G-buffer with 64 fabrics (patterns up to 16x16, radii
+    log-uniform in [1e-4, 2] cells): shading throughput per precision, and
+    each precision's error against the FP64 oracle's decoder with the same
+    (trained) parameters on a seeded 0.25 % pixel subset."""
+    import oracle
+    wl = fi.WORKLOADS["fabric64_4k"]
+    mats, g = wl.materials(), wl.gbuffer()
+    fab.encode(mats)
+    d = pkg.DeviceGBuffer.from_host(g)
+    out = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
+    idx = fi.subset_indices(g.n, 0.0025, 77)
+    z = oracle.encoder(params[fi.N_DECODER_PARAMS:].astype(np.float64), mats)
+    _, o_rgb = oracle.decoder_gbuffer(params[: fi.N_DECODER_PARAMS], z, mats, g.subset(idx))
+    row = {"pixels": g.n, "fabrics": len(mats), "subset_pixels": len(idx),
+           "reference": "FP64 oracle decoder forward, same parameters"}
+    for prec in ("bf16", "fp8", "fp32"):
+        fn = lambda: pkg.fabric_shade_gbuffer(fab.ctx, d, pkg.PREC[prec], 0, 0, out)
+        fn()
+        t = time_launches(torch, fn, 20 if prec != "fp32" else 5)
+        pred = out.cpu().numpy()[:, idx]
+        row[prec] = {"ms_per_frame": t, "mpix_per_s": g.n / (t * 1e-3) / 1e6,
+                     "hbm_gbs": BYTES_PER_PIXEL * g.n / (t * 1e-3) / 1e9, **rmse_stats(pred, o_rgb)}
+        log(f"4k 64 fabrics {prec}: {t * 1e3:.1f} us/frame, rmse {row[prec]['rmse']:.4g}")
+    del d, out
+    return row
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,7 +297,7 @@ def main():
 
     # ---- other precisions and rows ----
     rgb = {"bf16": rgb_bf16}
-    for prec in ("fp32", "fp16"):
+    for prec in ("fp32", "fp16", "fp8"):
         shade(prec)
         t = time_launches(torch, lambda: shade(prec), max(5, args.steps // 10))
         rows[f"neural_{prec}"] = {"ms_per_frame": t, "mpix_per_s": g.n / (t * 1e-3) / 1e6}
@@ -303,6 +331,8 @@ def main():
         torch.cuda.synchronize()
         rows["encode_8_fabrics"] = {"ms": (time.perf_counter() - t0) / 20 * 1e3,
                                     "note": "host call incl. table upload"}
+        rows["fabric64_4k"] = precision_row_4k(args, torch, pkg, fi, fab, params)
+        fab.encode(mats)
 
     # ---- error against the FP64 oracle on a seeded pixel subset ----
     errs = None if args.no_rmse else oracle_errors(args, torch, pkg, fi, fab, d, mats, g, rgb, gt_rgb)

@@ -151,7 +151,16 @@ fabric_status fabric_set_albedo(fabric_ctx *ctx, int32_t fabric, const float kd[
 /* Neural shading of a G-buffer (Sec. 4.3 "Rendering"): per pixel, the
  * decoder's four outputs decoded as C = max(y, 0), S = max((e^y - 1)/100, 0)
  * (inverse of the specular mapping of Eq. (9)) and composed with Eq. (8).
- *   prec              arithmetic of the dense layers
+ *   prec              arithmetic of the dense layers: FP32; BF16 or FP16
+ *                     operands with FP32 accumulation; FP8_E4M3 operands with
+ *                     FP32 accumulation and one power-of-two scale per layer
+ *                     for the weights and one for the activations.  The FP8
+ *                     activation scales are calibrated on the device (the
+ *                     largest hidden activations over a fixed synthetic batch
+ *                     drawn from the encoded fabrics) at the first FP8 call
+ *                     after fabric_encode or a parameter change, so they never
+ *                     depend on the frame being shaded; activations above the
+ *                     calibrated range saturate at the largest E4M3 value.
  *   fallback_samples  0: every pixel is shaded by the decoder.  > 0 (a perfect
  *                     square <= FABRIC_MAX_SAMPLES): pixels outside the
  *                     network's range (radius > 1 cell or wo.z < 0.05) are

@@ -14,38 +14,13 @@
 // With fallback routing, pixels outside the network's training range are
 // shaded in the same launch by the analytic footprint filter: the wave that
 // owns the tile evaluates them one at a time with all 64 lanes.
-#include "kernels.hpp"
 #include "mlp_tile.hpp"
 #include "mlp_tile32.hpp"
+#include "shade.hpp"
 
 namespace fab {
 
 namespace {
-
-constexpr int kFabConsts = 16;   // per fabric in LDS: fwx fwy 1/wx 1/wy kd[2][3] ks[2][3]
-
-// Out-of-range rule of the hybrid frame: footprint above one cell or a
-// grazing view.
-__device__ inline bool out_of_range(float r, float wo_z) { return r > 1.0f || wo_z < 0.05f; }
-
-// One pixel's G-buffer fields.
-struct Pix {
-    int fid;
-    float u, v, r;
-    float3 wi, wo;
-};
-
-__device__ inline Pix load_pix(const fabric_gbuffer &g, int p)
-{
-    Pix x;
-    x.fid = g.fabric_id[p];
-    x.u = g.u[p];
-    x.v = g.v[p];
-    x.r = g.radius[p];
-    x.wi = make_float3(g.wi_x[p], g.wi_y[p], g.wi_z[p]);
-    x.wo = make_float3(g.wo_x[p], g.wo_y[p], g.wo_z[p]);
-    return x;
-}
 
 template <int P, bool RAW, bool HYBRID>
 __global__ __launch_bounds__(256) void decode_kernel(
@@ -69,18 +44,7 @@ __global__ __launch_bounds__(256) void decode_kernel(
         s_bias[k] = bias[k];
     for (int k = threadIdx.x; k < n_fabrics * 64; k += blockDim.x)
         s_cf[k] = cfold[k];
-    for (int k = threadIdx.x; k < n_fabrics * kFabConsts; k += blockDim.x) {
-        const DevFabric &f = fabrics[k / kFabConsts];
-        int c = k % kFabConsts;
-        float val;
-        if (c == 0) val = f.fwx;
-        else if (c == 1) val = f.fwy;
-        else if (c == 2) val = f.inv_wx;
-        else if (c == 3) val = f.inv_wy;
-        else if (c < 10) val = f.kd[(c - 4) / 3][(c - 4) % 3];
-        else val = f.ks[(c - 10) / 3][(c - 10) % 3];
-        s_fc[k] = val;
-    }
+    stage_fabric_consts(fabrics, n_fabrics, s_fc);
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
@@ -146,32 +110,10 @@ __global__ __launch_bounds__(256) void decode_kernel(
         if (lane == 0 && bad)
             atomicAdd(err, (unsigned long long)__popcll(bad));
 
-        if (HYBRID) {
-            // Analytic footprint filter for this tile's out-of-range pixels.
-            unsigned long long todo = __ballot(grp == 0 && valid && oor);
-            while (todo) {
-                const int c = __builtin_ctzll(todo);
-                todo &= todo - 1;
-                const int pp = tile * 16 + c;
-                const int ff = __shfl(fid, c, 64);
-                const float uu = __shfl(u, c, 64), vv = __shfl(v, c, 64), rr = __shfl(r, c, 64);
-                const float3 wwi = make_float3(__shfl(wi.x, c, 64), __shfl(wi.y, c, 64),
-                                               __shfl(wi.z, c, 64));
-                const float3 wwo = make_float3(__shfl(wo.x, c, 64), __shfl(wo.y, c, 64),
-                                               __shfl(wo.z, c, 64));
-                double comp[4];
-                filter_pixel_wave(fabrics[ff], seed, (uint64_t)pp, fb_samples, fb_side,
-                                  fb_inv_side, uu, vv, rr, wwi, wwo, lane, comp);
-                if (lane == 0) {
-                    const DevFabric &f = fabrics[ff];
-                    for (int ch = 0; ch < 3; ch++) {
-                        double rgb = (double)f.kd[0][ch] * comp[0] + (double)f.kd[1][ch] * comp[1] +
-                                     (double)f.ks[0][ch] * comp[2] + (double)f.ks[1][ch] * comp[3];
-                        out[ch * n + pp] = (float)rgb;
-                    }
-                }
-            }
-        }
+        // Analytic footprint filter for this tile's out-of-range pixels.
+        if (HYBRID)
+            shade_fallback(__ballot(grp == 0 && valid && oor), tile * 16, n, fabrics, fid, u, v, r,
+                           wi, wo, fb_samples, fb_side, fb_inv_side, seed, lane, out);
     }
 }
 
@@ -200,18 +142,7 @@ __global__ __launch_bounds__(256) void decode32_kernel(
         s_b2[k] = bias2[k];
     for (int k = threadIdx.x; k < n_fabrics * 64; k += blockDim.x)
         s_cf[k] = cfold[k];
-    for (int k = threadIdx.x; k < n_fabrics * kFabConsts; k += blockDim.x) {
-        const DevFabric &f = fabrics[k / kFabConsts];
-        int c = k % kFabConsts;
-        float val;
-        if (c == 0) val = f.fwx;
-        else if (c == 1) val = f.fwy;
-        else if (c == 2) val = f.inv_wx;
-        else if (c == 3) val = f.inv_wy;
-        else if (c < 10) val = f.kd[(c - 4) / 3][(c - 4) % 3];
-        else val = f.ks[(c - 10) / 3][(c - 10) % 3];
-        s_fc[k] = val;
-    }
+    stage_fabric_consts(fabrics, n_fabrics, s_fc);
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
@@ -290,31 +221,9 @@ __global__ __launch_bounds__(256) void decode32_kernel(
         if (lane == 0 && bad)
             atomicAdd(err, (unsigned long long)__popcll(bad));
 
-        if (HYBRID) {
-            unsigned long long todo = __ballot(grp == 0 && valid && oor);
-            while (todo) {
-                const int c = __builtin_ctzll(todo);
-                todo &= todo - 1;
-                const int pp = tile * 32 + c;
-                const int ff = __shfl(fid, c, 64);
-                const float uu = __shfl(u, c, 64), vv = __shfl(v, c, 64), rr = __shfl(r, c, 64);
-                const float3 wwi = make_float3(__shfl(wi.x, c, 64), __shfl(wi.y, c, 64),
-                                               __shfl(wi.z, c, 64));
-                const float3 wwo = make_float3(__shfl(wo.x, c, 64), __shfl(wo.y, c, 64),
-                                               __shfl(wo.z, c, 64));
-                double comp[4];
-                filter_pixel_wave(fabrics[ff], seed, (uint64_t)pp, fb_samples, fb_side,
-                                  fb_inv_side, uu, vv, rr, wwi, wwo, lane, comp);
-                if (lane == 0) {
-                    const DevFabric &f = fabrics[ff];
-                    for (int ch = 0; ch < 3; ch++) {
-                        double rgb = (double)f.kd[0][ch] * comp[0] + (double)f.kd[1][ch] * comp[1] +
-                                     (double)f.ks[0][ch] * comp[2] + (double)f.ks[1][ch] * comp[3];
-                        out[ch * n + pp] = (float)rgb;
-                    }
-                }
-            }
-        }
+        if (HYBRID)
+            shade_fallback(__ballot(grp == 0 && valid && oor), tile * 32, n, fabrics, fid, u, v, r,
+                           wi, wo, fb_samples, fb_side, fb_inv_side, seed, lane, out);
     }
 }
 
@@ -446,19 +355,6 @@ __global__ void fold_latents_kernel(const float *__restrict__ params,
     cfold[idx] = acc;
 }
 
-int device_cus()
-{
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            cus <= 0)
-            cus = 256;
-    }
-    return cus;
-}
-
 size_t image32_bytes()
 {
     return (size_t)DecShape32<8>::NFRAG * 64 * 16 + (size_t)2 * 64 * 4 * sizeof(f32x4) +
@@ -491,9 +387,7 @@ hipError_t decode32(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fab
     const int cap = device_cus() * 2;
     if (blocks > cap)
         blocks = cap;
-    int side = 1;
-    while (side * side < fb_samples)
-        side++;
+    const int side = sample_side(fb_samples);
     const size_t lds = (size_t)2 * 64 * 4 * sizeof(f32x4) +
                        (size_t)n_fabrics * (64 + kFabConsts) * sizeof(float);
     hipLaunchKernelGGL((decode32_kernel<P, HYBRID>), dim3(blocks), dim3(256), lds, stream, g,
@@ -537,9 +431,7 @@ hipError_t decode(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabri
     const int cap = device_cus() * 2;
     if (blocks > cap)
         blocks = cap;
-    int side = 1;
-    while (side * side < fb_samples)
-        side++;
+    const int side = sample_side(fb_samples);
     const size_t lds = (size_t)kBiasFrags * 64 * sizeof(f32x4) +
                        (size_t)n_fabrics * (64 + kFabConsts) * sizeof(float);
     hipLaunchKernelGGL((decode_kernel<P, RAW, HYBRID>), dim3(blocks), dim3(256), lds,
@@ -549,6 +441,19 @@ hipError_t decode(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabri
 }
 
 }  // namespace
+
+int device_cus()
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
 
 size_t decoder_image_bytes(int prec)
 {
@@ -581,6 +486,8 @@ hipError_t launch_fold_latents(const float *dec_params, const float *latents, in
 
 size_t shade_image_bytes(int prec)
 {
+    if (prec == FABRIC_FP8_E4M3)
+        return f8_image_bytes();
     return (prec == FABRIC_BF16 || prec == FABRIC_FP16) ? image32_bytes() : decoder_image_bytes(prec);
 }
 
@@ -610,6 +517,10 @@ hipError_t launch_decode(int prec, bool raw, const fabric_gbuffer &g, const DevF
                                          seed, out, err, stream);                               \
     return decode<PREC, false, false>(g, fabrics, n_fabrics, cfold, image, 0, seed, out, err,   \
                                       stream);
+    if (prec == FABRIC_FP8_E4M3)
+        return raw ? hipErrorInvalidValue
+                   : launch_decode_f8(g, fabrics, n_fabrics, cfold, image, fallback_samples, seed,
+                                      out, err, stream);
     // Shading in bf16 / fp16 runs on 32-pixel tiles (image from
     // launch_pack_shade); the raw forward and fp32 on 16-pixel tiles.
     if (!raw && prec == FABRIC_BF16)

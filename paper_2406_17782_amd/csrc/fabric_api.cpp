@@ -28,9 +28,11 @@ struct fabric_ctx {
     float *latents = nullptr;         // [FABRIC_MAX_FABRICS][32]
     float *cfold = nullptr;           // [FABRIC_MAX_FABRICS][64]
     uint64_t encoded_version = 0;     // weights_version of the last encode
+    uint64_t encode_serial = 0;       // bumped on every encode
 
     void *image[4] = {nullptr, nullptr, nullptr, nullptr};   // packed decoders
     uint64_t image_version[4] = {0, 0, 0, 0};
+    uint64_t image_serial[4] = {0, 0, 0, 0};                 // encode_serial of an fp8 image
     void *tmp_image = nullptr;        // packing of caller-supplied parameters
     float *tmp_cfold = nullptr;
 
@@ -234,7 +236,8 @@ bool perfect_square(int n)
     return s * s == n;
 }
 
-// The packed decoder of precision prec for the context's current parameters.
+// The packed decoder of precision prec for the context's current parameters
+// (an FP8 image is calibrated on the encoded fabrics, so it also follows them).
 fabric_status ensure_image(fabric_ctx *ctx, int prec, hipStream_t stream)
 {
     if (!ctx->image[prec]) {
@@ -245,16 +248,25 @@ fabric_status ensure_image(fabric_ctx *ctx, int prec, hipStream_t stream)
         if (st != FABRIC_OK)
             return st;
     }
-    if (ctx->image_version[prec] != ctx->weights_version) {
-        fabric_status st = from_hip(launch_pack_shade(prec, ctx->params, ctx->image[prec], stream));
+    const bool fp8 = prec == FABRIC_FP8_E4M3;
+    if (ctx->image_version[prec] != ctx->weights_version ||
+        (fp8 && ctx->image_serial[prec] != ctx->encode_serial)) {
+        fabric_status st =
+            fp8 ? from_hip(launch_pack_f8(ctx->params, ctx->cfold, ctx->fabrics, ctx->n_mats,
+                                          ctx->image[prec], stream))
+                : from_hip(launch_pack_shade(prec, ctx->params, ctx->image[prec], stream));
         if (st != FABRIC_OK)
             return st;
         ctx->image_version[prec] = ctx->weights_version;
+        ctx->image_serial[prec] = ctx->encode_serial;
     }
     return FABRIC_OK;
 }
 
-bool supported_prec(int prec) { return prec == FABRIC_FP32 || prec == FABRIC_BF16 || prec == FABRIC_FP16; }
+bool supported_prec(int prec)
+{
+    return prec == FABRIC_FP32 || prec == FABRIC_BF16 || prec == FABRIC_FP16 || prec == FABRIC_FP8_E4M3;
+}
 
 }  // namespace
 
@@ -376,6 +388,7 @@ fabric_status fabric_encode(fabric_ctx *ctx, const fabric_material *mats, int32_
     ctx->mats.assign(mats, mats + n_mats);
     ctx->n_mats = n_mats;
     ctx->encoded_version = ctx->weights_version;
+    ctx->encode_serial += 1;
     return FABRIC_OK;
 }
 

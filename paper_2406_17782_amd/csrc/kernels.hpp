@@ -24,6 +24,16 @@ hipError_t launch_pack_decoder(int prec, const float *dec_params, void *image,
 size_t shade_image_bytes(int prec);
 hipError_t launch_pack_shade(int prec, const float *dec_params, void *image, hipStream_t stream);
 
+// FP8-E4M3 shading decoder: calibration over the encoded fabrics, then
+// packing with per-layer scales.  image must hold f8_image_bytes().
+size_t f8_image_bytes();
+hipError_t launch_pack_f8(const float *dec_params, const float *cfold, const DevFabric *fabrics,
+                          int n_fabrics, void *image, hipStream_t stream);
+hipError_t launch_decode_f8(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
+                            const float *cfold, const void *image, int fallback_samples,
+                            uint64_t seed, float *out, unsigned long long *err,
+                            hipStream_t stream);
+
 // c_f = b1 + W1[:, 0:32] z_f for every fabric: cfold[n_fabrics][64].
 hipError_t launch_fold_latents(const float *dec_params, const float *latents, int n_fabrics,
                                float *cfold, hipStream_t stream);

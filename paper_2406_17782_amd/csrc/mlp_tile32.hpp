@@ -150,6 +150,25 @@ template <int P> struct Tile32 {
                 acc[mb] = Mfma32<P>::mma(getA(base + mb * KS + ks), B[ks], acc[mb]);
     }
 
+    // L3 slots: chained neurons (rectified), then the three extra inputs.
+    static __device__ inline void l3_frags(const f32x16 (&a)[2], float x0, float x1, float x2,
+                                           Frag (&B3)[S::KS3])
+    {
+        float v[kL3Slots32];
+#pragma unroll
+        for (int c = 0; c < kChain32; c++)
+            v[c] = a[c >> 4][c & 15];
+        v[32] = x0;
+        v[33] = x1;
+        v[34] = x2;
+#pragma unroll
+        for (int ks = 0; ks < S::KS3; ks++) {
+            B3[ks] = frag_of(v, ks);
+            if ((ks + 1) * 8 <= kChain32)
+                B3[ks] = M::relu(B3[ks]);
+        }
+    }
+
     // Forward: cf / b2 are the L1 / L2 C operands (per lane, both M-blocks),
     // b4 the L4 one.  Returns y in accumulator registers 0..3 of lane group 0.
     template <typename GetA>
@@ -171,21 +190,7 @@ template <int P> struct Tile32 {
         dense<2>(getA, S::FRAG_L2, B2, a);
 
         Frag B3[S::KS3];
-        {
-            float v[kL3Slots32];
-#pragma unroll
-            for (int c = 0; c < kChain32; c++)
-                v[c] = a[c >> 4][c & 15];
-            v[32] = x0;
-            v[33] = x1;
-            v[34] = x2;
-#pragma unroll
-            for (int ks = 0; ks < S::KS3; ks++) {
-                B3[ks] = frag_of(v, ks);
-                if ((ks + 1) * 8 <= kChain32)
-                    B3[ks] = M::relu(B3[ks]);
-            }
-        }
+        l3_frags(a, x0, x1, x2, B3);
         a[0] = f32x16{};
         a[1] = f32x16{};
         dense<2>(getA, S::FRAG_L3, B3, a);
