@@ -34,7 +34,7 @@ FLOP_PER_PIXEL = 2 * (40 * 64 + 64 * 64 + 69 * 64 + 64 * 4)
 BYTES_PER_PIXEL = 2 + 9 * 4 + 3 * 4
 
 
-SHADE_SOURCES = ["common.hpp", "model.hpp", "mlp_tile.hpp", "mlp_tile32.hpp", "decode.hip"]
+SHADE_SOURCES = ["common.hpp", "model.hpp", "mlp_tile.hpp", "mlp_tile32.hpp", "shade.hpp", "decode.hip"]
 PROFILE = os.path.join(ROOT, "profiles", "decode32_bf16_fabric8_1080p.md")
 
 
@@ -200,8 +200,10 @@ def precision_row_4k(args, torch, pkg, fi, fab, params):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1000)
+    # The GPU's clocks settle only after several hundred back-to-back frames
+    # (about 50 ms of shading); fewer warmup frames under-report throughput.
+    ap.add_argument("--warmup", type=int, default=1500)
     ap.add_argument("--train-steps", type=int, default=6000)
     ap.add_argument("--train-batch", type=int, default=1 << 18)
     ap.add_argument("--train-lr", type=float, default=1e-2)

@@ -112,13 +112,15 @@ __global__ __launch_bounds__(256) void decode_kernel(
 
         // Analytic footprint filter for this tile's out-of-range pixels.
         if (HYBRID)
-            shade_fallback(__ballot(grp == 0 && valid && oor), tile * 16, n, fabrics, fid, u, v, r,
-                           wi, wo, fb_samples, fb_side, fb_inv_side, seed, lane, out);
+            shade_fallback(__ballot(grp == 0 && valid && oor), tile * 16, g, fabrics, fb_samples,
+                           fb_side, fb_inv_side, seed, lane, out);
     }
 }
 
 // Neural shading on 32x32x16 MFMA tiles (bf16 / fp16): 32 pixels per wave
 // iteration, two lane groups per pixel.  Same stages as decode_kernel.
+// Each lane group loads only the fields it uses (HalfPix), one tile ahead of
+// the one it shades.
 template <int P, bool HYBRID>
 __global__ __launch_bounds__(256) void decode32_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
@@ -154,39 +156,25 @@ __global__ __launch_bounds__(256) void decode32_kernel(
     for (int q = 0; q < S::NFRAG; q++)
         A[q] = frags[q * 64 + lane];
     auto getA = [&](int q) { return A[q]; };
-    f32x16 b4 = f32x16{};
-    {
-        const f32x4 t = bias4[lane];
-        b4[0] = t[0];
-        b4[1] = t[1];
-        b4[2] = t[2];
-        b4[3] = t[3];
-    }
+    const f32x4 b4 = bias4[lane];
 
     const int n = (int)g.n;
     const int waves = gridDim.x * (blockDim.x >> 6);
     const int wave_id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const HalfPlanes hp = half_planes(g, grp);
+    auto tile_px = [&](int t) { return min((t < n_tiles ? t : wave_id) * 32 + col, n - 1); };
 
-    // The next tile's fields are loaded while this one computes, so the HBM
-    // latency overlaps the MFMA work of the (only two) waves per SIMD.
-    Pix nxt = load_pix(g, min(wave_id * 32 + col, n - 1));
-    for (int tile = wave_id; tile < n_tiles; tile += waves) {
-        const Pix cur = nxt;
-        {
-            const int tn = tile + waves < n_tiles ? tile + waves : tile;
-            nxt = load_pix(g, min(tn * 32 + col, n - 1));
-        }
+    auto shade_tile = [&](const HalfPix &cur, int tile) {
         const int p = tile * 32 + col;
         const bool valid = p < n;
-        int fid = cur.fid;
-        const float u = cur.u, v = cur.v, r = cur.r;
-        const float3 wi = cur.wi, wo = cur.wo;
-        const bool fault = pixel_fault(fid, n_fabrics, u, v, r, wi, wo);
-        fid = fault ? 0 : fid;   // non-finite inputs stay in their own column
+        const bool fault = pair_any(half_fault(cur, n_fabrics), lane);
+        // Only the table index needs a safe value: non-finite inputs stay in
+        // their own pixel's column of every MFMA tile and are zeroed on output.
+        const int fid = fault ? 0 : cur.fid;
         const float *fc = s_fc + fid * kFabConsts;
 
         float s1[kL1Slots32];
-        T::spatial_slots(u, v, r, fc[0], fc[1], fc[2], fc[3], grp, s1);
+        T::spatial_slots(cur.uv, cur.uv, cur.r, fc[0], fc[1], fc[2], fc[3], grp, s1);
         f32x16 cf[2], b2[2];
 #pragma unroll
         for (int mb = 0; mb < 2; mb++)
@@ -200,30 +188,36 @@ __global__ __launch_bounds__(256) void decode32_kernel(
                     b2[mb][4 * q + i] = bq[i];
                 }
             }
-        const float x0 = grp == 0 ? wi.x : wo.x;
-        const float x1 = grp == 0 ? wi.y : wo.y;
-        const float x2 = grp == 0 ? wi.z : 1.0f;
-        const f32x16 y = T::forward(getA, cf, b2, b4, s1, x0, x1, x2);
+        // L3 extra inputs: group 0 wi, group 1 (wo.x, wo.y, 1 for the bias).
+        const float x2 = grp ? 1.0f : cur.xz;
+        f32x16 y = T::forward(getA, cf, b2, s1, cur.x0, cur.x1, x2);
 
         // Lanes 0..31 hold y[0..3] of pixel tile*32 + lane.
-        const bool oor = HYBRID && !fault && out_of_range(r, wo.z);
+        const bool oor = HYBRID && !fault &&
+                         pair_any(cur.r > 1.0f || (grp == 1 && cur.xz < 0.05f), lane);
         if (grp == 0 && valid && !oor) {
-            const float cw = fmaxf(y[0], 0.0f), cwf = fmaxf(y[1], 0.0f);
-            const float sw = fmaxf(FM::expm1(y[2]) * (1.0f / kSpec), 0.0f);
-            const float sf = fmaxf(FM::expm1(y[3]) * (1.0f / kSpec), 0.0f);
+            float rgb[3];
+            compose_rgb<FM>(y[0] + b4[0], y[1] + b4[1], y[2] + b4[2], y[3] + b4[3], fc, rgb);
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                const float rgb = fc[4 + c] * cw + fc[7 + c] * cwf + fc[10 + c] * sw + fc[13 + c] * sf;
-                out[c * n + p] = fault ? 0.0f : rgb;
-            }
+            for (int c = 0; c < 3; c++)
+                plane_store(out, c * n + p, fault ? 0.0f : rgb[c]);
         }
         const unsigned long long bad = __ballot(grp == 0 && valid && fault);
         if (lane == 0 && bad)
             atomicAdd(err, (unsigned long long)__popcll(bad));
-
         if (HYBRID)
-            shade_fallback(__ballot(grp == 0 && valid && oor), tile * 32, n, fabrics, fid, u, v, r,
-                           wi, wo, fb_samples, fb_side, fb_inv_side, seed, lane, out);
+            shade_fallback(__ballot(grp == 0 && valid && oor), tile * 32, g, fabrics, fb_samples,
+                           fb_side, fb_inv_side, seed, lane, out);
+    };
+
+    // The next tile's fields are loaded while this one is shaded.  (Deeper
+    // prefetching measured no faster: the compiler waits for the newer loads
+    // at the loop's register copies.)
+    HalfPix nxt = load_half(g, hp, tile_px(wave_id));
+    for (int tile = wave_id; tile < n_tiles; tile += waves) {
+        const HalfPix cur = nxt;
+        nxt = load_half(g, hp, tile_px(tile + waves));
+        shade_tile(cur, tile);
     }
 }
 

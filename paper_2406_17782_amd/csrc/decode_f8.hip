@@ -287,14 +287,7 @@ __global__ __launch_bounds__(256) void decode_f8_kernel(
     for (int q = 0; q < DecShapeF8::NFRAG; q++)
         A[q] = ((const i32x8 *)image)[q * 64 + lane];
     auto getA = [&](int q) { return A[q]; };
-    f32x16 b4 = f32x16{};
-    {
-        const f32x4 t = ((const f32x4 *)(image + kF8Bias4Off))[lane];
-        b4[0] = t[0];
-        b4[1] = t[1];
-        b4[2] = t[2];
-        b4[3] = t[3];
-    }
+    const f32x4 b4 = ((const f32x4 *)(image + kF8Bias4Off))[lane];
 
     // The MFMA takes its scales from VGPRs: keep them there for the whole loop.
     F8Header sc = hd;
@@ -306,17 +299,21 @@ __global__ __launch_bounds__(256) void decode_f8_kernel(
     const int n = (int)g.n;
     const int waves = gridDim.x * (blockDim.x >> 6);
     const int wave_id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const HalfPlanes hp = half_planes(g, grp);
+    auto tile_px = [&](int t) { return min((t < n_tiles ? t : wave_id) * 32 + col, n - 1); };
 
+    HalfPix nxt = load_half(g, hp, tile_px(wave_id));
     for (int tile = wave_id; tile < n_tiles; tile += waves) {
+        const HalfPix cur = nxt;
+        nxt = load_half(g, hp, tile_px(tile + waves));
         const int p = tile * 32 + col;
         const bool valid = p < n;
-        const Pix cur = load_pix(g, valid ? p : n - 1);
-        const bool fault = pixel_fault(cur.fid, n_fabrics, cur.u, cur.v, cur.r, cur.wi, cur.wo);
+        const bool fault = pair_any(half_fault(cur, n_fabrics), lane);
         const int fid = fault ? 0 : cur.fid;   // non-finite inputs stay in their own column
         const float *fc = s_fc + fid * kFabConsts;
 
         float s1[kL1Slots32];
-        Tile32<FABRIC_BF16>::spatial_slots(cur.u, cur.v, cur.r, fc[0], fc[1], fc[2], fc[3], grp, s1);
+        Tile32<FABRIC_BF16>::spatial_slots(cur.uv, cur.uv, cur.r, fc[0], fc[1], fc[2], fc[3], grp, s1);
         f32x16 cf[2], b2[2];
 #pragma unroll
         for (int mb = 0; mb < 2; mb++)
@@ -330,27 +327,25 @@ __global__ __launch_bounds__(256) void decode_f8_kernel(
                     b2[mb][4 * q + i] = bq[i];
                 }
             }
-        const float x0 = grp == 0 ? cur.wi.x : cur.wo.x;
-        const float x1 = grp == 0 ? cur.wi.y : cur.wo.y;
-        const float x2 = grp == 0 ? cur.wi.z : 1.0f;
-        const f32x16 y = TileF8::forward(getA, sc, cf, b2, b4, s1, x0, x1, x2);
+        const float x2 = grp ? 1.0f : cur.xz;
+        const f32x16 y = TileF8::forward(getA, sc, cf, b2, s1, cur.x0, cur.x1, x2);
 
         // Lanes 0..31 hold y[0..3] of pixel tile*32 + lane.
-        const bool oor = HYBRID && !fault && out_of_range(cur.r, cur.wo.z);
+        const bool oor = HYBRID && !fault &&
+                         pair_any(cur.r > 1.0f || (grp == 1 && cur.xz < 0.05f), lane);
         if (grp == 0 && valid && !oor) {
             float rgb[3];
-            compose_rgb<FM>(y[0], y[1], y[2], y[3], fc, rgb);
+            compose_rgb<FM>(y[0] + b4[0], y[1] + b4[1], y[2] + b4[2], y[3] + b4[3], fc, rgb);
 #pragma unroll
             for (int c = 0; c < 3; c++)
-                out[c * n + p] = fault ? 0.0f : rgb[c];
+                plane_store(out, c * n + p, fault ? 0.0f : rgb[c]);
         }
         const unsigned long long bad = __ballot(grp == 0 && valid && fault);
         if (lane == 0 && bad)
             atomicAdd(err, (unsigned long long)__popcll(bad));
         if (HYBRID)
-            shade_fallback(__ballot(grp == 0 && valid && oor), tile * 32, n, fabrics, fid, cur.u,
-                           cur.v, cur.r, cur.wi, cur.wo, fb_samples, fb_side, fb_inv_side, seed,
-                           lane, out);
+            shade_fallback(__ballot(grp == 0 && valid && oor), tile * 32, g, fabrics, fb_samples,
+                           fb_side, fb_inv_side, seed, lane, out);
     }
 }
 

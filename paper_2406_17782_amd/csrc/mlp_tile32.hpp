@@ -169,12 +169,14 @@ template <int P> struct Tile32 {
         }
     }
 
-    // Forward: cf / b2 are the L1 / L2 C operands (per lane, both M-blocks),
-    // b4 the L4 one.  Returns y in accumulator registers 0..3 of lane group 0.
+    // Forward: cf / b2 are the L1 / L2 C operands (per lane, both M-blocks).
+    // Returns W4 h3 (without its bias) in accumulator registers 0..3 of lane
+    // group 0; L4 starts from a zero C operand, which saves the sixteen
+    // registers a bias operand would hold for four useful rows.
     template <typename GetA>
     static __device__ inline f32x16 forward(GetA getA, const f32x16 (&cf)[2], const f32x16 (&b2)[2],
-                                            const f32x16 &b4, const float (&s1)[kL1Slots32],
-                                            float x0, float x1, float x2)
+                                            const float (&s1)[kL1Slots32], float x0, float x1,
+                                            float x2)
     {
         Frag B1[S::KS1];
 #pragma unroll
@@ -197,7 +199,7 @@ template <int P> struct Tile32 {
 
         Frag B4[S::KS4];
         chain(a, B4);
-        f32x16 y[2] = {b4, f32x16{}};
+        f32x16 y[2] = {f32x16{}, f32x16{}};
         dense<1>(getA, S::FRAG_L4, B4, y);
         return y[0];
     }

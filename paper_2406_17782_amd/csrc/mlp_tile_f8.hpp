@@ -100,14 +100,13 @@ struct TileF8 {
     }
 
     // Forward of one tile.  cf: L1 C operand (2^eh1 c_f rows of this lane),
-    // b2: L2's (pre-scaled), b4: L4's.  s1: the 20 spatial slots, x: the
-    // three L3 extra inputs of this lane group.  Returns y in accumulator
-    // registers 0..3 of lane group 0.
+    // b2: L2's (pre-scaled).  s1: the 20 spatial slots, x: the three L3 extra
+    // inputs of this lane group.  Returns W4 h3 (without its bias) in
+    // accumulator registers 0..3 of lane group 0.
     template <typename GetA>
     static __device__ inline f32x16 forward(GetA getA, const F8Header &h, const f32x16 (&cf)[2],
-                                            const f32x16 (&b2)[2], const f32x16 &b4,
-                                            const float (&s1)[kL1Slots32], float x0, float x1,
-                                            float x2)
+                                            const f32x16 (&b2)[2], const float (&s1)[kL1Slots32],
+                                            float x0, float x1, float x2)
     {
         static_assert(kFeatExp == 0, "features enter unscaled");
         float v[32];
@@ -142,7 +141,7 @@ struct TileF8 {
         }
 
         const i32x8 B4 = chain(a);
-        f32x16 y = mma(getA(DecShapeF8::FRAG_L4), B4, b4, h.sa[3], h.sb[3]);
+        f32x16 y = mma(getA(DecShapeF8::FRAG_L4), B4, f32x16{}, h.sa[3], h.sb[3]);
         // The scaled MFMA builtin is not marked convergent, so the compiler
         // would otherwise sink the whole chain into a caller's lane-divergent
         // branch (e.g. the store of lane group 0), where lanes with EXEC off

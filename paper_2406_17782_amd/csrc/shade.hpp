@@ -21,16 +21,74 @@ struct Pix {
     float3 wi, wo;
 };
 
+// Element i of a G-buffer plane through a 32-bit byte offset from the
+// plane's base, which lets the load use the scalar-base + vector-offset
+// address form (no 64-bit address arithmetic per lane).  Valid because the
+// boundary limits n to INT32_MAX / 16, so 12 n bytes stay below 2^32.
+template <typename T> __device__ inline T plane_at(const T *base, int i)
+{
+    return *(const T *)((const char *)base + (uint32_t)i * (uint32_t)sizeof(T));
+}
+__device__ inline void plane_store(float *base, int i, float v)
+{
+    *(float *)((char *)base + (uint32_t)i * 4u) = v;
+}
+
 __device__ inline Pix load_pix(const fabric_gbuffer &g, int p)
 {
     Pix x;
-    x.fid = g.fabric_id[p];
-    x.u = g.u[p];
-    x.v = g.v[p];
-    x.r = g.radius[p];
-    x.wi = make_float3(g.wi_x[p], g.wi_y[p], g.wi_z[p]);
-    x.wo = make_float3(g.wo_x[p], g.wo_y[p], g.wo_z[p]);
+    x.fid = plane_at(g.fabric_id, p);
+    x.u = plane_at(g.u, p);
+    x.v = plane_at(g.v, p);
+    x.r = plane_at(g.radius, p);
+    x.wi = make_float3(plane_at(g.wi_x, p), plane_at(g.wi_y, p), plane_at(g.wi_z, p));
+    x.wo = make_float3(plane_at(g.wo_x, p), plane_at(g.wo_y, p), plane_at(g.wo_z, p));
     return x;
+}
+
+// The half of a pixel's fields one lane group of a 32-pixel tile needs:
+// group 0 the u coordinate and wi, group 1 v and wo; both the radius and the
+// fabric id.  Six loads per lane instead of ten.
+struct HalfPix {
+    int fid;
+    float uv, r;
+    float x0, x1, xz;   // (wi or wo).x, .y, .z
+};
+struct HalfPlanes {
+    const float *uv, *x0, *x1, *xz;
+};
+__device__ inline HalfPlanes half_planes(const fabric_gbuffer &g, int grp)
+{
+    HalfPlanes h;
+    h.uv = grp ? g.v : g.u;
+    h.x0 = grp ? g.wo_x : g.wi_x;
+    h.x1 = grp ? g.wo_y : g.wi_y;
+    h.xz = grp ? g.wo_z : g.wi_z;
+    return h;
+}
+__device__ inline HalfPix load_half(const fabric_gbuffer &g, const HalfPlanes &h, int p)
+{
+    HalfPix x;
+    x.fid = plane_at(g.fabric_id, p);
+    x.r = plane_at(g.radius, p);
+    x.uv = h.uv[p];
+    x.x0 = h.x0[p];
+    x.x1 = h.x1[p];
+    x.xz = h.xz[p];
+    return x;
+}
+// This lane group's share of the fault rule of pixel_fault.
+__device__ inline bool half_fault(const HalfPix &x, int n_fabrics)
+{
+    const bool finite = isfinite(x.uv) && isfinite(x.r) && isfinite(x.x0) && isfinite(x.x1) &&
+                        isfinite(x.xz);
+    return !finite || x.fid >= n_fabrics || !(x.r > 0.0f) || !(x.xz > 0.0f);
+}
+// True in both lanes of a pixel (lanes l and l ^ 32) when either flag is set.
+__device__ inline bool pair_any(bool flag, int lane)
+{
+    const unsigned long long m = __ballot(flag);
+    return (((m | (m >> 32) | (m << 32)) >> lane) & 1ull) != 0;
 }
 
 // Block-cooperative fill of the per-fabric constants s_fc[n_fabrics][16].
@@ -66,29 +124,24 @@ __device__ inline void compose_rgb(float y0, float y1, float y2, float y3, const
 }
 
 // The analytic footprint filter for the pixels of one tile whose bits are set
-// in `todo` (bit c: pixel base + c, fields held by lane c), all 64 lanes per
-// pixel.  Writes rgb[3][n].
-__device__ inline void shade_fallback(unsigned long long todo, int base, int n,
-                                      const DevFabric *__restrict__ fabrics, int fid, float u,
-                                      float v, float r, float3 wi, float3 wo, int fb_samples,
+// in `todo` (bit c: pixel base + c), all 64 lanes per pixel; the pixel's
+// fields are read again from the G-buffer.  Writes rgb[3][n].
+__device__ inline void shade_fallback(unsigned long long todo, int base, const fabric_gbuffer &g,
+                                      const DevFabric *__restrict__ fabrics, int fb_samples,
                                       int fb_side, float fb_inv_side, uint64_t seed, int lane,
                                       float *__restrict__ out)
 {
+    const int n = (int)g.n;
     while (todo) {
         const int c = __builtin_ctzll(todo);
         todo &= todo - 1;
         const int pp = base + c;
-        const int ff = __shfl(fid, c, 64);
-        const float uu = __shfl(u, c, 64), vv = __shfl(v, c, 64), rr = __shfl(r, c, 64);
-        const float3 wwi = make_float3(__shfl(wi.x, c, 64), __shfl(wi.y, c, 64),
-                                       __shfl(wi.z, c, 64));
-        const float3 wwo = make_float3(__shfl(wo.x, c, 64), __shfl(wo.y, c, 64),
-                                       __shfl(wo.z, c, 64));
+        const Pix x = load_pix(g, pp);
         double comp[4];
-        filter_pixel_wave(fabrics[ff], seed, (uint64_t)pp, fb_samples, fb_side, fb_inv_side, uu,
-                          vv, rr, wwi, wwo, lane, comp);
+        filter_pixel_wave(fabrics[x.fid], seed, (uint64_t)pp, fb_samples, fb_side, fb_inv_side,
+                          x.u, x.v, x.r, x.wi, x.wo, lane, comp);
         if (lane == 0) {
-            const DevFabric &f = fabrics[ff];
+            const DevFabric &f = fabrics[x.fid];
             for (int ch = 0; ch < 3; ch++) {
                 const double rgb = (double)f.kd[0][ch] * comp[0] + (double)f.kd[1][ch] * comp[1] +
                                    (double)f.ks[0][ch] * comp[2] + (double)f.ks[1][ch] * comp[3];
