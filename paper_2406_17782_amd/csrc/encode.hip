@@ -2,37 +2,14 @@
 // the weave as a 16x16 one-hot grid plus 12 normalised yarn scalars ->
 // e1 = relu(E1 x + c1) -> residual block e2 = relu(e1 + E3 relu(E2 e1 + c2) + c3)
 // -> z = E4 e2 + c4.  One 256-thread block per fabric; each dense layer runs
-// one output per wavefront at a time with coalesced row reads and a fixed
+// eight outputs per wavefront at a time with coalesced row reads and a fixed
 // butterfly reduction.  It runs once per material edit, not per frame.
+#include "enc_dense.hpp"
 #include "kernels.hpp"
 
 namespace fab {
 
 namespace {
-
-// y[o] = act(b[o] + sum_i W[o][i] x[i] (+ add[o])) for o < nout; x, y, add in LDS.
-__device__ void dense_rows(const float *__restrict__ W, const float *__restrict__ b,
-                           const float *x, int nin, int nout, float *y, bool relu,
-                           const float *add)
-{
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int nwaves = blockDim.x >> 6;
-    for (int o = wave; o < nout; o += nwaves) {
-        float acc = 0.0f;
-        for (int i = lane; i < nin; i += 64)
-            acc = fmaf(W[(size_t)o * nin + i], x[i], acc);
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-            acc += __shfl_xor(acc, off, 64);
-        if (lane == 0) {
-            float val = acc + b[o];
-            if (add)
-                val += add[o];
-            y[o] = relu ? fmaxf(val, 0.0f) : val;
-        }
-    }
-    __syncthreads();
-}
 
 __global__ __launch_bounds__(256) void encoder_forward_kernel(const float *__restrict__ Q,
                                                               const float *__restrict__ inputs,
@@ -44,10 +21,10 @@ __global__ __launch_bounds__(256) void encoder_forward_kernel(const float *__res
     for (int k = threadIdx.x; k < kEncIn; k += blockDim.x)
         x[k] = inputs[(size_t)f * kEncIn + k];
     __syncthreads();
-    dense_rows(Q + kOffE1, Q + kOffC1, x, kEncIn, kEncHid, e1, true, nullptr);
-    dense_rows(Q + kOffE2, Q + kOffC2, e1, kEncHid, kEncHid, r2, true, nullptr);
-    dense_rows(Q + kOffE3, Q + kOffC3, r2, kEncHid, kEncHid, e2, true, e1);
-    dense_rows(Q + kOffE4, Q + kOffC4, e2, kEncHid, kLatent, z, false, nullptr);
+    enc_dense_rows(Q + kOffE1, Q + kOffC1, x, kEncIn, kEncHid, e1, true, nullptr);
+    enc_dense_rows(Q + kOffE2, Q + kOffC2, e1, kEncHid, kEncHid, r2, true, nullptr);
+    enc_dense_rows(Q + kOffE3, Q + kOffC3, r2, kEncHid, kEncHid, e2, true, e1);
+    enc_dense_rows(Q + kOffE4, Q + kOffC4, e2, kEncHid, kLatent, z, false, nullptr);
     for (int k = threadIdx.x; k < kLatent; k += blockDim.x)
         latents[f * kLatent + k] = z[k];
 }

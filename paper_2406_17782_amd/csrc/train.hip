@@ -7,9 +7,10 @@
 //                      MFMA tiles with transposed weight fragments, chained in
 //                      registers exactly like the forward.  Activations and
 //                      activation gradients go to per-sample buffers.
-//   outer_sum_kernel   weight gradients dW = sum_n dh_n x_n^T as split-K FP32
-//                      MFMA tiles over LDS-staged chunks of samples, with a
-//                      fixed-order reduction of the partials (deterministic).
+//   wgrad_kernel       weight gradients dW = sum_n dh_n x_n^T of every layer in
+//                      one launch: FP32 MFMA tiles with samples as K, operands
+//                      read straight from the per-sample rows, fixed-order
+//                      reductions of the partials (deterministic).
 //   encoder kernels    per-fabric backward through the encoder and its weight
 //                      gradients summed over fabrics in order.
 //   adam_kernel        Adam with FP64 moments on FP32 masters; skipped on the
@@ -17,6 +18,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "enc_dense.hpp"
 #include "kernels.hpp"
 #include "mlp_tile.hpp"
 #include "train.hpp"
@@ -319,106 +321,141 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Split-K outer-product sums: partial[blk][m][c] = sum over the block's
-// samples of A[s][m] * Bx[s][c], m < MA, c < NC, where Bx is B's first NB
-// columns followed (if with_bias) by a column of ones, or (ids != NULL) the
-// one-hot of ids over fabrics f0 .. f0+NC-1.  FP32 MFMA 16x16x4 over
-// 64-sample LDS tiles.
+// Weight gradients as sums of outer products over samples, all jobs of a
+// step in one launch: job j computes
+//   out_j[m][c] = sum_s A_j[s][m] * Bx_j[s][c],   m < MA <= 64, c < NC <= 80,
+// where Bx is B's first NB columns followed (with a bias) by a column of
+// ones, or (ids != NULL) the one-hot of ids over fabrics f0 .. f0+NC-1.
+// Samples are the K dimension of FP32 MFMA 16x16x4 tiles whose operands are
+// read straight from the sample-major rows: lane l takes sample 4k + l/16 and
+// column l%16 of a 16-wide slab, which are 16 consecutive floats of a row.
+// Every wave keeps all (up to 4 x 5) output tiles of its job in registers
+// over its share of the samples; the block's four waves are summed through
+// LDS in wave order, and the blocks' partials by wgrad_reduce_kernel in block
+// order, so the result is deterministic.
 // ---------------------------------------------------------------------------
-constexpr int kOsTile = 64;
-constexpr int kOsMaxM = 64;
-constexpr int kOsMaxC = 80;
+constexpr int kWgMaxM = 64, kWgMaxC = 80;
+constexpr int kWgMT = kWgMaxM / 16, kWgCT = kWgMaxC / 16;
+constexpr int kWgBlocks = 128;   // partial sums per job
+constexpr int kWgMaxJobs = 8;
 
-__global__ __launch_bounds__(256) void outer_sum_kernel(
-    const float *__restrict__ A, int lda, int MA, const float *__restrict__ Bm, int ldb, int NB,
-    int with_bias, const uint16_t *__restrict__ ids, int f0, int NC, int64_t n, int64_t chunk,
-    float *__restrict__ partial)
+struct WgJob {
+    const float *A;           // [n][lda], columns 0..MA-1 used
+    const float *B;           // [n][ldb], columns 0..NB-1 used (NULL with ids)
+    const uint16_t *ids;      // one-hot source, or NULL
+    int lda, MA, ldb, NB, bias, f0, NC;
+};
+struct WgJobs {
+    WgJob j[kWgMaxJobs];
+};
+
+__global__ __launch_bounds__(256) void wgrad_kernel(WgJobs jobs, int64_t n, int64_t per_block,
+                                                    float *__restrict__ partial)
 {
-    __shared__ float sA[kOsTile][kOsMaxM + 1];
-    __shared__ float sB[kOsTile][kOsMaxC + 1];
+    __shared__ float red[4][kWgMaxM * kWgMaxC / 4];   // one quarter of the tile per pass
+    const WgJob jb = jobs.j[blockIdx.y];
     const int lane = threadIdx.x & 63, grp = lane >> 4, col = lane & 15;
     const int wave = threadIdx.x >> 6;
-    const int MT = (MA + 15) / 16, CT = (NC + 15) / 16;
-    const int ntiles = MT * CT;
-    f32x4 acc[5];
+    const int MT = (jb.MA + 15) >> 4, CT = (jb.NC + 15) >> 4;
+    const int64_t b0 = (int64_t)blockIdx.x * per_block;
+    const int64_t b1 = b0 + per_block < n ? b0 + per_block : n;
+    // The block's samples are dealt to its waves in runs of 16 (four k-steps).
+    f32x4 acc[kWgMT][kWgCT];
 #pragma unroll
-    for (int t = 0; t < 5; t++)
-        acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const int64_t s0 = (int64_t)blockIdx.x * chunk;
-    const int64_t s1 = s0 + chunk < n ? s0 + chunk : n;
-    for (int64_t base = s0; base < s1; base += kOsTile) {
-        __syncthreads();
-        for (int k = threadIdx.x; k < kOsTile * kOsMaxM; k += blockDim.x) {
-            const int s = k / kOsMaxM, m = k % kOsMaxM;
-            const int64_t q = base + s;
-            sA[s][m] = (q < s1 && m < MA) ? A[q * lda + m] : 0.0f;
-        }
-        for (int k = threadIdx.x; k < kOsTile * kOsMaxC; k += blockDim.x) {
-            const int s = k / kOsMaxC, c = k % kOsMaxC;
-            const int64_t q = base + s;
-            float val = 0.0f;
-            if (q < s1 && c < NC) {
-                if (ids)
-                    val = (int)ids[q] == f0 + c ? 1.0f : 0.0f;
-                else if (c < NB)
-                    val = Bm[q * ldb + c];
-                else
-                    val = with_bias ? 1.0f : 0.0f;
+    for (int mt = 0; mt < kWgMT; mt++)
+#pragma unroll
+        for (int ct = 0; ct < kWgCT; ct++)
+            acc[mt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t base = b0 + 16 * wave; base < b1; base += 64) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int64_t smp = base + 4 * k + grp;
+            const bool in = smp < b1;
+            float av[kWgMT], bv[kWgCT];
+#pragma unroll
+            for (int mt = 0; mt < kWgMT; mt++) {
+                const int m = 16 * mt + col;
+                av[mt] = (in && mt < MT && m < jb.MA) ? jb.A[smp * jb.lda + m] : 0.0f;
             }
-            sB[s][c] = val;
-        }
-        __syncthreads();
+            const int fid = (in && jb.ids) ? (int)jb.ids[smp] : -1;
 #pragma unroll
-        for (int t = 0; t < 5; t++) {
-            const int tt = wave + 4 * t;
-            if (tt < ntiles) {
-                const int mt = tt / CT, ct = tt % CT;
-                f32x4 a = acc[t];
-                for (int k4 = 0; k4 < kOsTile / 4; k4++) {
-                    const int s = 4 * k4 + grp;
-                    a = __builtin_amdgcn_mfma_f32_16x16x4f32(sA[s][16 * mt + col],
-                                                             sB[s][16 * ct + col], a, 0, 0, 0);
+            for (int ct = 0; ct < kWgCT; ct++) {
+                const int c = 16 * ct + col;
+                float v = 0.0f;
+                if (in && ct < CT && c < jb.NC) {
+                    if (jb.ids)
+                        v = fid == jb.f0 + c ? 1.0f : 0.0f;
+                    else if (c < jb.NB)
+                        v = jb.B[smp * jb.ldb + c];
+                    else
+                        v = jb.bias ? 1.0f : 0.0f;
                 }
-                acc[t] = a;
+                bv[ct] = v;
             }
+#pragma unroll
+            for (int mt = 0; mt < kWgMT; mt++)
+#pragma unroll
+                for (int ct = 0; ct < kWgCT; ct++)
+                    if (mt < MT && ct < CT)
+                        acc[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mt], bv[ct], acc[mt][ct], 0, 0, 0);
         }
     }
-    const int stride = kOsMaxM * kOsMaxC;
+    // Sum the four waves' tiles in wave order, one M-tile row at a time, and
+    // write the block's partial [kWgMaxM][kWgMaxC].
+    float *out = partial + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (kWgMaxM * kWgMaxC);
 #pragma unroll
-    for (int t = 0; t < 5; t++) {
-        const int tt = wave + 4 * t;
-        if (tt < ntiles) {
-            const int mt = tt / CT, ct = tt % CT;
+    for (int mt = 0; mt < kWgMT; mt++) {
+        // red[w][ (m%16) * kWgMaxC + c ] for the 16 rows of M-tile mt
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const int m = 16 * mt + 4 * grp + i, c = 16 * ct + col;
-                partial[(size_t)blockIdx.x * stride + m * kOsMaxC + c] = acc[t][i];
-            }
+        for (int ct = 0; ct < kWgCT; ct++)
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+                red[wave][(4 * grp + i) * kWgMaxC + 16 * ct + col] = acc[mt][ct][i];
+        __syncthreads();
+        for (int e = threadIdx.x; e < 16 * kWgMaxC; e += blockDim.x) {
+            const float v = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+            out[(16 * mt) * kWgMaxC + e] = v;
         }
+        __syncthreads();
     }
 }
 
-// Sum the partials in block order and scatter: out[m][c] goes to
-// dst[m * ldw + c] (c < NW) or to bias[m] (c == NW, with a bias), or with
+// out_j[m][c] = sum over the blocks' partials in block order (eight
+// interleaved running sums, combined in a fixed order), scattered to
+// dst[m * ldw + c] (c < NW), bias[m] (c == NW with a bias), or with
 // transposed = 1 to dst[c * ldw + m].
-__global__ void reduce_partials_kernel(const float *__restrict__ partial, int nblk, int MA,
-                                       int NC, int NW, float *__restrict__ dst, int ldw,
-                                       int transposed, float *__restrict__ bias)
+struct WgDest {
+    float *dst, *bias;
+    int MA, NC, NW, ldw, transposed;
+};
+struct WgDests {
+    WgDest d[kWgMaxJobs];
+};
+
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float *__restrict__ partial,
+                                                           WgDests dests, int nblk)
 {
+    const WgDest d = dests.d[blockIdx.y];
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= MA * NC)
+    if (e >= d.MA * d.NC)
         return;
-    const int m = e / NC, c = e % NC;
-    float acc = 0.0f;
-    const int stride = kOsMaxM * kOsMaxC;
-    for (int b = 0; b < nblk; b++)
-        acc += partial[(size_t)b * stride + m * kOsMaxC + c];
-    if (transposed)
-        dst[c * ldw + m] = acc;
-    else if (c < NW)
-        dst[m * ldw + c] = acc;
-    else if (bias)
-        bias[m] = acc;
+    const int m = e / d.NC, c = e % d.NC;
+    const float *p = partial + (size_t)blockIdx.y * nblk * (kWgMaxM * kWgMaxC) + m * kWgMaxC + c;
+    float r[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    int b = 0;
+    for (; b + 8 <= nblk; b += 8)
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            r[k] += p[(size_t)(b + k) * (kWgMaxM * kWgMaxC)];
+    for (; b < nblk; b++)
+        r[b & 7] += p[(size_t)b * (kWgMaxM * kWgMaxC)];
+    const float acc = ((r[0] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7]));
+    if (d.transposed)
+        d.dst[c * d.ldw + m] = acc;
+    else if (c < d.NW)
+        d.dst[m * d.ldw + c] = acc;
+    else if (d.bias)
+        d.bias[m] = acc;
 }
 
 // dz_f = W1[:, 0:32]^T dc_f and dW1[:, 0:32] = sum_f dc_f z_f^T.
@@ -449,36 +486,6 @@ __global__ void latent_grads_kernel(const float *__restrict__ params, const floa
 // fabrics in order.
 // enc scratch per fabric: x[524] a1 a2 a3 da1 da2 da3 [128 each] dz[32]
 // ---------------------------------------------------------------------------
-__device__ void dense_rows_enc(const float *__restrict__ W, const float *__restrict__ b,
-                               const float *x, int nin, int nout, float *y)
-{
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
-    for (int o = wave; o < nout; o += nwaves) {
-        float acc = 0.0f;
-        for (int i = lane; i < nin; i += 64)
-            acc = fmaf(W[(size_t)o * nin + i], x[i], acc);
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-            acc += __shfl_xor(acc, off, 64);
-        if (lane == 0)
-            y[o] = acc + b[o];
-    }
-    __syncthreads();
-}
-
-// y[i] = sum_o W[o][i] d[o] (transposed product), one output per thread.
-__device__ void dense_cols_enc(const float *__restrict__ W, const float *d, int nout, int nin,
-                               float *y)
-{
-    for (int i = threadIdx.x; i < nin; i += blockDim.x) {
-        float acc = 0.0f;
-        for (int o = 0; o < nout; o++)
-            acc = fmaf(W[(size_t)o * nin + i], d[o], acc);
-        y[i] = acc;
-    }
-    __syncthreads();
-}
-
 __global__ __launch_bounds__(256) void encoder_backward_kernel(const float *__restrict__ Q,
                                                                const float *__restrict__ inputs,
                                                                const float *__restrict__ dz,
@@ -493,30 +500,30 @@ __global__ __launch_bounds__(256) void encoder_backward_kernel(const float *__re
     for (int k = threadIdx.x; k < kLatent; k += blockDim.x)
         dzs[k] = dz[f * kLatent + k];
     __syncthreads();
-    dense_rows_enc(Q + kOffE1, Q + kOffC1, x, kEncIn, kEncHid, a1);
+    enc_dense_rows(Q + kOffE1, Q + kOffC1, x, kEncIn, kEncHid, a1, false, nullptr);
     for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
         e1[k] = fmaxf(a1[k], 0.0f);
     __syncthreads();
-    dense_rows_enc(Q + kOffE2, Q + kOffC2, e1, kEncHid, kEncHid, a2);
+    enc_dense_rows(Q + kOffE2, Q + kOffC2, e1, kEncHid, kEncHid, a2, false, nullptr);
     for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
         r2[k] = fmaxf(a2[k], 0.0f);
     __syncthreads();
-    dense_rows_enc(Q + kOffE3, Q + kOffC3, r2, kEncHid, kEncHid, a3);
+    enc_dense_rows(Q + kOffE3, Q + kOffC3, r2, kEncHid, kEncHid, a3, false, nullptr);
     for (int k = threadIdx.x; k < kEncHid; k += blockDim.x) {
         a3[k] += e1[k];                     // skip connection before the activation
         e2[k] = fmaxf(a3[k], 0.0f);
     }
     __syncthreads();
     // backward
-    dense_cols_enc(Q + kOffE4, dzs, kLatent, kEncHid, g);          // dL/de2
+    enc_dense_cols(Q + kOffE4, dzs, kLatent, kEncHid, g);          // dL/de2
     for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
         d3[k] = a3[k] > 0.0f ? g[k] : 0.0f;
     __syncthreads();
-    dense_cols_enc(Q + kOffE3, d3, kEncHid, kEncHid, g);           // dL/dr2
+    enc_dense_cols(Q + kOffE3, d3, kEncHid, kEncHid, g);           // dL/dr2
     for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
         d2[k] = a2[k] > 0.0f ? g[k] : 0.0f;
     __syncthreads();
-    dense_cols_enc(Q + kOffE2, d2, kEncHid, kEncHid, g);           // dL/de1 (through E2)
+    enc_dense_cols(Q + kOffE2, d2, kEncHid, kEncHid, g);           // dL/de1 (through E2)
     for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
         d1[k] = a1[k] > 0.0f ? g[k] + d3[k] : 0.0f;               // plus the skip path
     __syncthreads();
@@ -634,9 +641,9 @@ hipError_t ensure_acts(TrainScratch &s, int64_t n)
     return e;
 }
 
-hipError_t ensure_partials(TrainScratch &s, int nblk)
+hipError_t ensure_partials(TrainScratch &s, int n_jobs)
 {
-    const size_t need = (size_t)nblk * kOsMaxM * kOsMaxC;
+    const size_t need = (size_t)n_jobs * kWgBlocks * kWgMaxM * kWgMaxC;
     if (s.partial_floats >= need)
         return hipSuccess;
     hipError_t e = grow(&s.partials, need);
@@ -686,41 +693,36 @@ hipError_t decoder_weight_grads(TrainScratch &s, const fabric_gbuffer &g, int n_
                                 float *grad_dec, hipStream_t stream)
 {
     const int64_t n = g.n;
-    int64_t chunk = (n + 511) / 512;
-    chunk = ((chunk + kOsTile - 1) / kOsTile) * kOsTile;
-    if (chunk < kOsTile)
-        chunk = kOsTile;
-    const int nblk = (int)((n + chunk - 1) / chunk);
-    hipError_t e = ensure_partials(s, nblk);
-    if (e != hipSuccess)
-        return e;
     ActPtrs ap = act_ptrs(s.acts, s.cap);
-    struct Job { const float *A; int lda, MA; const float *Bm; int ldb, NB; float *dst; int ldw; float *bias; };
-    const Job jobs[4] = {
-        {ap.DH1, kDH, 64, ap.S, kS, 40, grad_dec + kOffW1 + kLatent, 72, grad_dec + kOffB1},
-        {ap.DH2, kDH, 64, ap.H1, kH1, 64, grad_dec + kOffW2, 64, grad_dec + kOffB2},
-        {ap.DH3, kDH, 64, ap.X3, kX3, 69, grad_dec + kOffW3, 69, grad_dec + kOffB3},
-        {ap.DY, kDY, 4, ap.H3, kH3, 64, grad_dec + kOffW4, 64, grad_dec + kOffB4},
+    WgJobs jobs{};
+    WgDests dests{};
+    int nj = 0;
+    auto add = [&](const float *A, int lda, int MA, const float *B, int ldb, int NB, int bias,
+                   const uint16_t *ids, int f0, int NC, float *dst, int ldw, float *bsum,
+                   int transposed) {
+        jobs.j[nj] = WgJob{A, B, ids, lda, MA, ldb, NB, bias, f0, NC};
+        dests.d[nj] = WgDest{dst, bsum, MA, NC, ids ? NC : NB, ldw, transposed};
+        nj++;
     };
-    for (const Job &j : jobs) {
-        const int NC = j.NB + 1;
-        hipLaunchKernelGGL(outer_sum_kernel, dim3(nblk), dim3(256), 0, stream, j.A, j.lda, j.MA, j.Bm,
-                           j.ldb, j.NB, 1, (const uint16_t *)nullptr, 0, NC, n, chunk, s.partials);
-        const int tot = j.MA * NC;
-        hipLaunchKernelGGL(reduce_partials_kernel, dim3((tot + 255) / 256), dim3(256), 0, stream,
-                           (const float *)s.partials, nblk, j.MA, NC, j.NB, j.dst, j.ldw, 0, j.bias);
-    }
-    // dL/dc_f: segment sums of dh1 by fabric, 64 fabrics per pass.
+    add(ap.DH1, kDH, 64, ap.S, kS, 40, 1, nullptr, 0, 41, grad_dec + kOffW1 + kLatent, 72,
+        grad_dec + kOffB1, 0);
+    add(ap.DH2, kDH, 64, ap.H1, kH1, 64, 1, nullptr, 0, 65, grad_dec + kOffW2, 64, grad_dec + kOffB2, 0);
+    add(ap.DH3, kDH, 64, ap.X3, kX3, 69, 1, nullptr, 0, 70, grad_dec + kOffW3, 69, grad_dec + kOffB3, 0);
+    add(ap.DY, kDY, 4, ap.H3, kH3, 64, 1, nullptr, 0, 65, grad_dec + kOffW4, 64, grad_dec + kOffB4, 0);
+    // dL/dc_f: segment sums of dh1 by fabric (one-hot B), up to 64 fabrics per job.
     for (int f0 = 0; f0 < n_fabrics; f0 += 64) {
         const int NC = n_fabrics - f0 < 64 ? n_fabrics - f0 : 64;
-        hipLaunchKernelGGL(outer_sum_kernel, dim3(nblk), dim3(256), 0, stream, (const float *)ap.DH1,
-                           kDH, 64, (const float *)nullptr, 0, 0, 0, g.fabric_id, f0, NC, n, chunk,
-                           s.partials);
-        const int tot = 64 * NC;
-        hipLaunchKernelGGL(reduce_partials_kernel, dim3((tot + 255) / 256), dim3(256), 0, stream,
-                           (const float *)s.partials, nblk, 64, NC, NC, s.dcf + f0 * 64, 64, 1,
-                           (float *)nullptr);
+        add(ap.DH1, kDH, 64, nullptr, 0, 0, 0, g.fabric_id, f0, NC, s.dcf + f0 * 64, 64, nullptr, 1);
     }
+    hipError_t e = ensure_partials(s, nj);
+    if (e != hipSuccess)
+        return e;
+    int64_t per_block = (n + kWgBlocks - 1) / kWgBlocks;
+    per_block = (per_block + 63) / 64 * 64;
+    hipLaunchKernelGGL(wgrad_kernel, dim3(kWgBlocks, nj), dim3(256), 0, stream, jobs, n, per_block,
+                       s.partials);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((kWgMaxM * kWgMaxC + 255) / 256, nj), dim3(256), 0,
+                       stream, (const float *)s.partials, dests, kWgBlocks);
     return hipGetLastError();
 }
 
