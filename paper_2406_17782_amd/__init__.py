@@ -16,12 +16,13 @@ import numpy as np
 
 from . import _abi
 from ._abi import (FABRIC_BF16, FABRIC_FP8_E4M3, FABRIC_FP16, FABRIC_FP32, FABRIC_LATENT,
-                   FABRIC_MAX_FABRICS, FABRIC_N_DECODER_PARAMS, FABRIC_N_ENCODER_PARAMS,
-                   FABRIC_N_PARAMS, PREC, FabricError, check)
+                   FABRIC_MAX_FABRICS, FABRIC_MAX_SAMPLES, FABRIC_N_DECODER_PARAMS,
+                   FABRIC_N_ENCODER_PARAMS, FABRIC_N_PARAMS, PREC, FabricError, check)
 
 __all__ = [
     "Fabric", "DeviceGBuffer", "FabricError", "PREC", "FABRIC_FP32", "FABRIC_BF16", "FABRIC_FP16",
     "FABRIC_FP8_E4M3", "FABRIC_N_PARAMS", "FABRIC_N_DECODER_PARAMS", "FABRIC_N_ENCODER_PARAMS",
+    "FABRIC_MAX_FABRICS", "FABRIC_MAX_SAMPLES", "FABRIC_LATENT",
     "fabric_create", "fabric_destroy", "fabric_encode", "fabric_set_albedo",
     "fabric_shade_gbuffer", "fabric_gt_filtered", "fabric_decoder_forward",
     "fabric_decoder_backward", "fabric_encoder_forward", "fabric_encoder_backward",

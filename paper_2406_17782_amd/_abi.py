@@ -21,6 +21,7 @@ FABRIC_FP16 = 2
 FABRIC_FP8_E4M3 = 3
 
 FABRIC_MAX_FABRICS = 256
+FABRIC_MAX_SAMPLES = 16384
 FABRIC_LATENT = 32
 FABRIC_N_DECODER_PARAMS = 13572
 FABRIC_N_ENCODER_PARAMS = 104352

@@ -96,14 +96,11 @@ __global__ __launch_bounds__(256) void decode_kernel(
                 for (int c = 0; c < 4; c++)
                     out[c * n + p] = fault ? 0.0f : y[c];
             } else {
-                float cw = fmaxf(y[0], 0.0f), cwf = fmaxf(y[1], 0.0f);
-                float sw = fmaxf(FM::expm1(y[2]) * (1.0f / kSpec), 0.0f);
-                float sf = fmaxf(FM::expm1(y[3]) * (1.0f / kSpec), 0.0f);
+                float rgb[3];
+                compose_rgb<FM>(y[0], y[1], y[2], y[3], fc, rgb);
 #pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    float rgb = fc[4 + c] * cw + fc[7 + c] * cwf + fc[10 + c] * sw + fc[13 + c] * sf;
-                    out[c * n + p] = fault ? 0.0f : rgb;
-                }
+                for (int c = 0; c < 3; c++)
+                    out[c * n + p] = fault ? 0.0f : rgb[c];
             }
         }
         const unsigned long long bad = __ballot(grp == 0 && valid && fault);

@@ -118,9 +118,11 @@ template <int P> struct Tile32 {
         for (int q = 0; q < 8; q++) {
             s1[q] = sn;
             s1[8 + q] = cs;
-            const float s2 = 2.0f * sn * cs;      // angle doubling
-            cs = fmaf(-2.0f * sn, sn, 1.0f);
-            sn = s2;
+            // angle doubling: sin 2x = 2 sin x cos x, cos 2x = 1 - 2 sin^2 x
+            // (three instructions; the negation is a free source modifier)
+            const float t = sn + sn;
+            cs = fmaf(-t, sn, 1.0f);
+            sn = t * s1[8 + q];
         }
         const float tau = fminf(fmaxf((FM::log2(r) + 14.0f) * (1.0f / 16.0f), 0.0f), 1.0f);
 #pragma unroll

@@ -91,7 +91,9 @@ __device__ inline bool pair_any(bool flag, int lane)
     return (((m | (m >> 32) | (m << 32)) >> lane) & 1ull) != 0;
 }
 
-// Block-cooperative fill of the per-fabric constants s_fc[n_fabrics][16].
+// Block-cooperative fill of the per-fabric constants s_fc[n_fabrics][16]:
+// fwx, fwy, 1/wx, 1/wy, kd (warp, weft RGB), ks / 100 (warp, weft RGB).  The
+// specular albedos carry the 1/100 of the decoding S = (e^y - 1) / 100.
 __device__ inline void stage_fabric_consts(const DevFabric *__restrict__ fabrics, int n_fabrics,
                                            float *s_fc)
 {
@@ -104,20 +106,21 @@ __device__ inline void stage_fabric_consts(const DevFabric *__restrict__ fabrics
         else if (c == 2) val = f.inv_wx;
         else if (c == 3) val = f.inv_wy;
         else if (c < 10) val = f.kd[(c - 4) / 3][(c - 4) % 3];
-        else val = f.ks[(c - 10) / 3][(c - 10) % 3];
+        else val = f.ks[(c - 10) / 3][(c - 10) % 3] * (1.0f / kSpec);
         s_fc[k] = val;
     }
 }
 
 // Decoded components (Eq. (8)): C = max(y, 0), S = max((e^y - 1) / 100, 0),
-// composed with the fabric's albedos fc[4..15] into rgb.
+// composed with the fabric's albedos fc[4..15] into rgb (the 1/100 of S is
+// folded into the staged specular albedos).
 template <typename FM>
 __device__ inline void compose_rgb(float y0, float y1, float y2, float y3, const float *fc,
                                    float (&rgb)[3])
 {
     const float cw = fmaxf(y0, 0.0f), cwf = fmaxf(y1, 0.0f);
-    const float sw = fmaxf(FM::expm1(y2) * (1.0f / kSpec), 0.0f);
-    const float sf = fmaxf(FM::expm1(y3) * (1.0f / kSpec), 0.0f);
+    const float sw = fmaxf(FM::expm1(y2), 0.0f);
+    const float sf = fmaxf(FM::expm1(y3), 0.0f);
 #pragma unroll
     for (int c = 0; c < 3; c++)
         rgb[c] = fc[4 + c] * cw + fc[7 + c] * cwf + fc[10 + c] * sw + fc[13 + c] * sf;

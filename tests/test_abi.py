@@ -87,3 +87,14 @@ def test_product_path_does_not_touch_the_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.lower(), f
+
+
+def test_binding_constants_match_header():
+    """The Python binding's limits and sizes are the header's #defines."""
+    import re
+    from paper_2406_17782_amd import _abi
+    text = open(os.path.join(ROOT, "include", "fabric.h")).read()
+    defs = dict(re.findall(r"#define (FABRIC_\w+) (\d+)\s", text))
+    for name in ("FABRIC_MAX_FABRICS", "FABRIC_MAX_SAMPLES", "FABRIC_LATENT",
+                 "FABRIC_N_DECODER_PARAMS", "FABRIC_N_ENCODER_PARAMS"):
+        assert getattr(_abi, name) == int(defs[name]), name
