@@ -164,9 +164,12 @@ fabric_status fabric_set_albedo(fabric_ctx *ctx, int32_t fabric, const float kd[
  *   fallback_samples  0: every pixel is shaded by the decoder.  > 0 (a perfect
  *                     square <= FABRIC_MAX_SAMPLES): pixels outside the
  *                     network's range (radius > 1 cell or wo.z < 0.05) are
- *                     instead shaded in the same launch by the analytic
- *                     footprint filter with that many samples, keyed by `seed`
- *                     and the pixel index exactly as fabric_gt_filtered.
+ *                     instead shaded, in the same call and on the same
+ *                     stream, by the analytic footprint filter with that many
+ *                     samples, keyed by `seed` and the pixel index exactly as
+ *                     fabric_gt_filtered (bitwise the same values).  The
+ *                     shading launch marks them; a fixed-order compaction
+ *                     queues them in pixel order for the filter launch.
  *   out_rgb           device float [3][n] (R plane, G plane, B plane).
  * Requires fabric_encode after the last weight change (else E_STATE). */
 fabric_status fabric_shade_gbuffer(fabric_ctx *ctx, const fabric_gbuffer *g, fabric_prec prec,

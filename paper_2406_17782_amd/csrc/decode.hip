@@ -26,8 +26,8 @@ template <int P, bool RAW, bool HYBRID>
 __global__ __launch_bounds__(256) void decode_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ frags,
-    const f32x4 *__restrict__ bias, int fb_samples, int fb_side, float fb_inv_side,
-    uint64_t seed, float *__restrict__ out, unsigned long long *err, int n_tiles)
+    const f32x4 *__restrict__ bias, FallbackQueue q, float *__restrict__ out,
+    unsigned long long *err, int n_tiles)
 {
     using T = Tile<P>;
     using Frag = typename T::Frag;
@@ -107,10 +107,9 @@ __global__ __launch_bounds__(256) void decode_kernel(
         if (lane == 0 && bad)
             atomicAdd(err, (unsigned long long)__popcll(bad));
 
-        // Analytic footprint filter for this tile's out-of-range pixels.
+        // Out-of-range pixels are marked for the footprint filter.
         if (HYBRID)
-            shade_fallback(__ballot(grp == 0 && valid && oor), tile * 16, g, fabrics, fb_samples,
-                           fb_side, fb_inv_side, seed, lane, out);
+            queue_mark16((uint32_t)__ballot(grp == 0 && valid && oor), tile, q, lane);
     }
 }
 
@@ -122,9 +121,8 @@ template <int P, bool HYBRID>
 __global__ __launch_bounds__(256) void decode32_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ frags,
-    const f32x4 *__restrict__ bias2, const f32x4 *__restrict__ bias4, int fb_samples,
-    int fb_side, float fb_inv_side, uint64_t seed, float *__restrict__ out,
-    unsigned long long *err, int n_tiles)
+    const f32x4 *__restrict__ bias2, const f32x4 *__restrict__ bias4, FallbackQueue q,
+    float *__restrict__ out, unsigned long long *err, int n_tiles)
 {
     using T = Tile32<P>;
     using Frag = typename T::Frag;
@@ -165,6 +163,10 @@ __global__ __launch_bounds__(256) void decode32_kernel(
         const int p = tile * 32 + col;
         const bool valid = p < n;
         const bool fault = pair_any(half_fault(cur, n_fabrics), lane);
+        // Out-of-range rule (r > 1 cell or wo.z < 0.05), decided before the
+        // MFMA chain so that no pixel field stays live through it.
+        const bool oor = HYBRID && !fault &&
+                         pair_any(cur.r > 1.0f || (grp == 1 && cur.xz < 0.05f), lane);
         // Only the table index needs a safe value: non-finite inputs stay in
         // their own pixel's column of every MFMA tile and are zeroed on output.
         const int fid = fault ? 0 : cur.fid;
@@ -190,8 +192,6 @@ __global__ __launch_bounds__(256) void decode32_kernel(
         f32x16 y = T::forward(getA, cf, b2, s1, cur.x0, cur.x1, x2);
 
         // Lanes 0..31 hold y[0..3] of pixel tile*32 + lane.
-        const bool oor = HYBRID && !fault &&
-                         pair_any(cur.r > 1.0f || (grp == 1 && cur.xz < 0.05f), lane);
         if (grp == 0 && valid && !oor) {
             float rgb[3];
             compose_rgb<FM>(y[0] + b4[0], y[1] + b4[1], y[2] + b4[2], y[3] + b4[3], fc, rgb);
@@ -203,8 +203,7 @@ __global__ __launch_bounds__(256) void decode32_kernel(
         if (lane == 0 && bad)
             atomicAdd(err, (unsigned long long)__popcll(bad));
         if (HYBRID)
-            shade_fallback(__ballot(grp == 0 && valid && oor), tile * 32, g, fabrics, fb_samples,
-                           fb_side, fb_inv_side, seed, lane, out);
+            queue_mark32((uint32_t)__ballot(grp == 0 && valid && oor), tile, q, lane);
     };
 
     // The next tile's fields are loaded while this one is shaded.  (Deeper
@@ -366,8 +365,8 @@ template <int P> hipError_t pack32(const float *params, void *image, hipStream_t
 
 template <int P, bool HYBRID>
 hipError_t decode32(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
-                    const float *cfold, const void *image, int fb_samples, uint64_t seed,
-                    float *out, unsigned long long *err, hipStream_t stream)
+                    const float *cfold, const void *image, FallbackQueue q, float *out,
+                    unsigned long long *err, hipStream_t stream)
 {
     using M = Mfma<P>;
     const auto *frags = (const typename M::Frag *)image;
@@ -378,12 +377,10 @@ hipError_t decode32(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fab
     const int cap = device_cus() * 2;
     if (blocks > cap)
         blocks = cap;
-    const int side = sample_side(fb_samples);
     const size_t lds = (size_t)2 * 64 * 4 * sizeof(f32x4) +
                        (size_t)n_fabrics * (64 + kFabConsts) * sizeof(float);
     hipLaunchKernelGGL((decode32_kernel<P, HYBRID>), dim3(blocks), dim3(256), lds, stream, g,
-                       fabrics, n_fabrics, cfold, frags, b2, b4, fb_samples, side,
-                       1.0f / (float)side, seed, out, err, n_tiles);
+                       fabrics, n_fabrics, cfold, frags, b2, b4, q, out, err, n_tiles);
     return hipGetLastError();
 }
 
@@ -409,8 +406,8 @@ template <int P> hipError_t pack(const float *params, void *image, hipStream_t s
 
 template <int P, bool RAW, bool HYBRID>
 hipError_t decode(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
-                  const float *cfold, const void *image, int fb_samples, uint64_t seed,
-                  float *out, unsigned long long *err, hipStream_t stream)
+                  const float *cfold, const void *image, FallbackQueue q, float *out,
+                  unsigned long long *err, hipStream_t stream)
 {
     using M = Mfma<P>;
     using S = DecShape<M::KPL>;
@@ -422,12 +419,10 @@ hipError_t decode(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabri
     const int cap = device_cus() * 2;
     if (blocks > cap)
         blocks = cap;
-    const int side = sample_side(fb_samples);
     const size_t lds = (size_t)kBiasFrags * 64 * sizeof(f32x4) +
                        (size_t)n_fabrics * (64 + kFabConsts) * sizeof(float);
     hipLaunchKernelGGL((decode_kernel<P, RAW, HYBRID>), dim3(blocks), dim3(256), lds,
-                       stream, g, fabrics, n_fabrics, cfold, frags, bias, fb_samples, side,
-                       1.0f / (float)side, seed, out, err, n_tiles);
+                       stream, g, fabrics, n_fabrics, cfold, frags, bias, q, out, err, n_tiles);
     return hipGetLastError();
 }
 
@@ -493,39 +488,37 @@ hipError_t launch_pack_shade(int prec, const float *dec_params, void *image, hip
 
 hipError_t launch_decode(int prec, bool raw, const fabric_gbuffer &g, const DevFabric *fabrics,
                          int n_fabrics, const float *cfold, const void *image,
-                         int fallback_samples, uint64_t seed, float *out,
+                         int fallback_samples, uint64_t seed, FallbackQueue q, float *out,
                          unsigned long long *err, hipStream_t stream)
 {
     if (g.n == 0)
         return hipSuccess;
     const bool hybrid = !raw && fallback_samples > 0;
-#define FAB_DECODE(PREC)                                                                        \
-    if (raw)                                                                                    \
-        return decode<PREC, true, false>(g, fabrics, n_fabrics, cfold, image, 0, seed, out, err, \
-                                         stream);                                               \
-    if (hybrid)                                                                                 \
-        return decode<PREC, false, true>(g, fabrics, n_fabrics, cfold, image, fallback_samples, \
-                                         seed, out, err, stream);                               \
-    return decode<PREC, false, false>(g, fabrics, n_fabrics, cfold, image, 0, seed, out, err,   \
-                                      stream);
+    hipError_t e = hipSuccess;
     if (prec == FABRIC_FP8_E4M3)
-        return raw ? hipErrorInvalidValue
-                   : launch_decode_f8(g, fabrics, n_fabrics, cfold, image, fallback_samples, seed,
-                                      out, err, stream);
-    // Shading in bf16 / fp16 runs on 32-pixel tiles (image from
-    // launch_pack_shade); the raw forward and fp32 on 16-pixel tiles.
-    if (!raw && prec == FABRIC_BF16)
-        return hybrid ? decode32<FABRIC_BF16, true>(g, fabrics, n_fabrics, cfold, image, fallback_samples, seed, out, err, stream)
-                      : decode32<FABRIC_BF16, false>(g, fabrics, n_fabrics, cfold, image, 0, seed, out, err, stream);
-    if (!raw && prec == FABRIC_FP16)
-        return hybrid ? decode32<FABRIC_FP16, true>(g, fabrics, n_fabrics, cfold, image, fallback_samples, seed, out, err, stream)
-                      : decode32<FABRIC_FP16, false>(g, fabrics, n_fabrics, cfold, image, 0, seed, out, err, stream);
-    switch (prec) {
-    case FABRIC_FP32: { FAB_DECODE(FABRIC_FP32) }
-    case FABRIC_BF16: { FAB_DECODE(FABRIC_BF16) }
-    default: return hipErrorInvalidValue;
-    }
-#undef FAB_DECODE
+        e = raw ? hipErrorInvalidValue
+                : launch_decode_f8(g, fabrics, n_fabrics, cfold, image, hybrid, q, out, err, stream);
+    else if (!raw && prec == FABRIC_BF16)
+        // Shading in bf16 / fp16 runs on 32-pixel tiles (image from
+        // launch_pack_shade); the raw forward and fp32 on 16-pixel tiles.
+        e = hybrid ? decode32<FABRIC_BF16, true>(g, fabrics, n_fabrics, cfold, image, q, out, err, stream)
+                   : decode32<FABRIC_BF16, false>(g, fabrics, n_fabrics, cfold, image, q, out, err, stream);
+    else if (!raw && prec == FABRIC_FP16)
+        e = hybrid ? decode32<FABRIC_FP16, true>(g, fabrics, n_fabrics, cfold, image, q, out, err, stream)
+                   : decode32<FABRIC_FP16, false>(g, fabrics, n_fabrics, cfold, image, q, out, err, stream);
+    else if (prec == FABRIC_FP32)
+        e = raw ? decode<FABRIC_FP32, true, false>(g, fabrics, n_fabrics, cfold, image, q, out, err, stream)
+                : hybrid ? decode<FABRIC_FP32, false, true>(g, fabrics, n_fabrics, cfold, image, q, out, err, stream)
+                         : decode<FABRIC_FP32, false, false>(g, fabrics, n_fabrics, cfold, image, q, out, err, stream);
+    else if (raw && prec == FABRIC_BF16)
+        e = decode<FABRIC_BF16, true, false>(g, fabrics, n_fabrics, cfold, image, q, out, err, stream);
+    else
+        e = hipErrorInvalidValue;
+    if (e != hipSuccess || !hybrid)
+        return e;
+    if ((e = launch_queue_build(q, g.n, stream)) != hipSuccess)
+        return e;
+    return launch_gt_filter_queue(g, fabrics, fallback_samples, seed, q, out, stream);
 }
 
 }  // namespace fab

@@ -257,9 +257,8 @@ __global__ __launch_bounds__(256) void pack_decoder_f8_kernel(const float *__res
 template <bool HYBRID>
 __global__ __launch_bounds__(256) void decode_f8_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
-    const float *__restrict__ cfold, const char *__restrict__ image, int fb_samples,
-    int fb_side, float fb_inv_side, uint64_t seed, float *__restrict__ out,
-    unsigned long long *err, int n_tiles)
+    const float *__restrict__ cfold, const char *__restrict__ image, FallbackQueue q,
+    float *__restrict__ out, unsigned long long *err, int n_tiles)
 {
     using FM = FeatureMath<FABRIC_BF16>;
     const F8Header hd = *(const F8Header *)(image + kF8HeaderOff);
@@ -309,6 +308,10 @@ __global__ __launch_bounds__(256) void decode_f8_kernel(
         const int p = tile * 32 + col;
         const bool valid = p < n;
         const bool fault = pair_any(half_fault(cur, n_fabrics), lane);
+        // Out-of-range rule (r > 1 cell or wo.z < 0.05), decided before the
+        // MFMA chain so that no pixel field stays live through it.
+        const bool oor = HYBRID && !fault &&
+                         pair_any(cur.r > 1.0f || (grp == 1 && cur.xz < 0.05f), lane);
         const int fid = fault ? 0 : cur.fid;   // non-finite inputs stay in their own column
         const float *fc = s_fc + fid * kFabConsts;
 
@@ -331,8 +334,6 @@ __global__ __launch_bounds__(256) void decode_f8_kernel(
         const f32x16 y = TileF8::forward(getA, sc, cf, b2, s1, cur.x0, cur.x1, x2);
 
         // Lanes 0..31 hold y[0..3] of pixel tile*32 + lane.
-        const bool oor = HYBRID && !fault &&
-                         pair_any(cur.r > 1.0f || (grp == 1 && cur.xz < 0.05f), lane);
         if (grp == 0 && valid && !oor) {
             float rgb[3];
             compose_rgb<FM>(y[0] + b4[0], y[1] + b4[1], y[2] + b4[2], y[3] + b4[3], fc, rgb);
@@ -344,8 +345,7 @@ __global__ __launch_bounds__(256) void decode_f8_kernel(
         if (lane == 0 && bad)
             atomicAdd(err, (unsigned long long)__popcll(bad));
         if (HYBRID)
-            shade_fallback(__ballot(grp == 0 && valid && oor), tile * 32, g, fabrics, fb_samples,
-                           fb_side, fb_inv_side, seed, lane, out);
+            queue_mark32((uint32_t)__ballot(grp == 0 && valid && oor), tile, q, lane);
     }
 }
 
@@ -371,9 +371,8 @@ hipError_t launch_pack_f8(const float *dec_params, const float *cfold, const Dev
 }
 
 hipError_t launch_decode_f8(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
-                            const float *cfold, const void *image, int fallback_samples,
-                            uint64_t seed, float *out, unsigned long long *err,
-                            hipStream_t stream)
+                            const float *cfold, const void *image, bool hybrid, FallbackQueue q,
+                            float *out, unsigned long long *err, hipStream_t stream)
 {
     if (g.n == 0)
         return hipSuccess;
@@ -382,17 +381,14 @@ hipError_t launch_decode_f8(const fabric_gbuffer &g, const DevFabric *fabrics, i
     const int cap = device_cus() * 2;
     if (blocks > cap)
         blocks = cap;
-    const int side = sample_side(fallback_samples);
     const size_t lds = (size_t)2 * 64 * 4 * sizeof(f32x4) +
                        (size_t)n_fabrics * (64 + kFabConsts) * sizeof(float);
-    if (fallback_samples > 0)
+    if (hybrid)
         hipLaunchKernelGGL(decode_f8_kernel<true>, dim3(blocks), dim3(256), lds, stream, g,
-                           fabrics, n_fabrics, cfold, (const char *)image, fallback_samples, side,
-                           1.0f / (float)side, seed, out, err, n_tiles);
+                           fabrics, n_fabrics, cfold, (const char *)image, q, out, err, n_tiles);
     else
         hipLaunchKernelGGL(decode_f8_kernel<false>, dim3(blocks), dim3(256), lds, stream, g,
-                           fabrics, n_fabrics, cfold, (const char *)image, 0, 1, 1.0f, seed, out,
-                           err, n_tiles);
+                           fabrics, n_fabrics, cfold, (const char *)image, q, out, err, n_tiles);
     return hipGetLastError();
 }
 

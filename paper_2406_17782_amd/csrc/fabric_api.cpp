@@ -35,6 +35,11 @@ struct fabric_ctx {
     uint64_t image_serial[4] = {0, 0, 0, 0};                 // encode_serial of an fp8 image
     void *tmp_image = nullptr;        // packing of caller-supplied parameters
     float *tmp_cfold = nullptr;
+    uint16_t *queue_mask = nullptr;   // hybrid frames: pixels routed to the filter
+    uint32_t *queue_offsets = nullptr;
+    uint32_t *queue_count = nullptr;
+    int32_t *queue_idx = nullptr;
+    int64_t queue_cap = 0;
 
     unsigned long long *err = nullptr;
     TrainScratch train;
@@ -263,6 +268,34 @@ fabric_status ensure_image(fabric_ctx *ctx, int prec, hipStream_t stream)
     return FABRIC_OK;
 }
 
+// Room for the out-of-range masks, offsets and pixel indices of an n-pixel
+// hybrid frame.
+fabric_status ensure_queue(fabric_ctx *ctx, int64_t n)
+{
+    if (!ctx->queue_count) {
+        fabric_status st = dalloc(&ctx->queue_count, 1);
+        if (st != FABRIC_OK)
+            return st;
+    }
+    if (ctx->queue_cap >= n)
+        return FABRIC_OK;
+    (void)hipFree(ctx->queue_mask);
+    (void)hipFree(ctx->queue_offsets);
+    (void)hipFree(ctx->queue_idx);
+    ctx->queue_mask = nullptr;
+    ctx->queue_offsets = nullptr;
+    ctx->queue_idx = nullptr;
+    ctx->queue_cap = 0;
+    fabric_status st = dalloc(&ctx->queue_mask, (size_t)((n + 31) / 32) * 2);
+    if (st == FABRIC_OK)
+        st = dalloc(&ctx->queue_offsets, queue_offset_entries(n));
+    if (st == FABRIC_OK)
+        st = dalloc(&ctx->queue_idx, (size_t)n);
+    if (st == FABRIC_OK)
+        ctx->queue_cap = n;
+    return st;
+}
+
 bool supported_prec(int prec)
 {
     return prec == FABRIC_FP32 || prec == FABRIC_BF16 || prec == FABRIC_FP16 || prec == FABRIC_FP8_E4M3;
@@ -302,6 +335,10 @@ void fabric_destroy(fabric_ctx *ctx)
     for (int k = 0; k < 4; k++)
         (void)hipFree(ctx->image[k]);
     (void)hipFree(ctx->tmp_image);
+    (void)hipFree(ctx->queue_mask);
+    (void)hipFree(ctx->queue_offsets);
+    (void)hipFree(ctx->queue_count);
+    (void)hipFree(ctx->queue_idx);
     (void)hipFree(ctx->tmp_cfold);
     (void)hipFree(ctx->err);
     train_scratch_free(ctx->train);
@@ -435,10 +472,13 @@ fabric_status fabric_shade_gbuffer(fabric_ctx *ctx, const fabric_gbuffer *g, fab
     DeviceGuard guard(ctx->device);
     hipStream_t s = as_stream(stream);
     fabric_status st = ensure_image(ctx, prec, s);
+    if (st == FABRIC_OK && fallback_samples > 0)
+        st = ensure_queue(ctx, g->n);
     if (st != FABRIC_OK)
         return st;
+    const FallbackQueue q{ctx->queue_mask, ctx->queue_offsets, ctx->queue_count, ctx->queue_idx};
     return from_hip(launch_decode(prec, false, *g, ctx->fabrics, ctx->n_mats, ctx->cfold,
-                                  ctx->image[prec], fallback_samples, seed, out_rgb, ctx->err, s));
+                                  ctx->image[prec], fallback_samples, seed, q, out_rgb, ctx->err, s));
 }
 
 fabric_status fabric_gt_filtered(fabric_ctx *ctx, const fabric_gbuffer *g, int32_t n_samples,
@@ -474,7 +514,8 @@ fabric_status fabric_decoder_forward(fabric_ctx *ctx, const fabric_gbuffer *g, f
         st = from_hip(launch_fold_latents(dec_params, latents, ctx->n_mats, ctx->tmp_cfold, s));
     if (st == FABRIC_OK)
         st = from_hip(launch_decode(prec, true, *g, ctx->fabrics, ctx->n_mats, ctx->tmp_cfold,
-                                    ctx->tmp_image, 0, 0, y4, ctx->err, s));
+                                    ctx->tmp_image, 0, 0, FallbackQueue{nullptr, nullptr, nullptr, nullptr}, y4,
+                                    ctx->err, s));
     // The next shade must repack: tmp buffers are separate, so nothing else is stale.
     return st;
 }

@@ -5,6 +5,7 @@
 // fixed butterfly of wavefront shuffles.
 #include "kernels.hpp"
 #include "model.hpp"
+#include "shade.hpp"
 
 namespace fab {
 
@@ -12,6 +13,43 @@ namespace {
 
 constexpr int kWavesPerBlock = 4;
 constexpr int kXcds = 8;
+
+// Pixel p by the wave: the filter's components and Eq. (8) composition,
+// written by lane 0 (faulty inputs: zeros and one count).
+__device__ inline void filter_one_pixel(const fabric_gbuffer &g, const DevFabric *__restrict__ fabrics,
+                                        int n_fabrics, int64_t p, int n_samples, int side,
+                                        float inv_side, uint64_t seed, int lane,
+                                        float *__restrict__ out_rgb, float *__restrict__ out_comp,
+                                        unsigned long long *err)
+{
+    const int fid = g.fabric_id[p];
+    const float u = g.u[p], v = g.v[p], r = g.radius[p];
+    const float3 wi = make_float3(g.wi_x[p], g.wi_y[p], g.wi_z[p]);
+    const float3 wo = make_float3(g.wo_x[p], g.wo_y[p], g.wo_z[p]);
+    const bool fault = pixel_fault(fid, n_fabrics, u, v, r, wi, wo);
+
+    double comp[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!fault)
+        filter_pixel_wave(fabrics[fid], seed, (uint64_t)p, n_samples, side, inv_side, u, v, r,
+                          wi, wo, lane, comp);
+    if (lane == 0) {
+        const int64_t n = g.n;
+        if (fault && err)
+            atomicAdd(err, 1ull);
+        if (out_comp) {
+            for (int c = 0; c < 4; c++)
+                out_comp[c * n + p] = (float)comp[c];
+        }
+        if (out_rgb) {
+            const DevFabric &f = fabrics[fault ? 0 : fid];
+            for (int c = 0; c < 3; c++) {
+                double rgb = (double)f.kd[0][c] * comp[0] + (double)f.kd[1][c] * comp[1] +
+                             (double)f.ks[0][c] * comp[2] + (double)f.ks[1][c] * comp[3];
+                out_rgb[c * n + p] = fault ? 0.0f : (float)rgb;
+            }
+        }
+    }
+}
 
 __global__ __launch_bounds__(256) void gt_filter_kernel(fabric_gbuffer g,
                                                         const DevFabric *__restrict__ fabrics,
@@ -32,32 +70,120 @@ __global__ __launch_bounds__(256) void gt_filter_kernel(fabric_gbuffer g,
     const int64_t p = (int64_t)block * kWavesPerBlock + wave;
     if (p >= g.n)
         return;
-    const int fid = g.fabric_id[p];
-    const float u = g.u[p], v = g.v[p], r = g.radius[p];
-    const float3 wi = make_float3(g.wi_x[p], g.wi_y[p], g.wi_z[p]);
-    const float3 wo = make_float3(g.wo_x[p], g.wo_y[p], g.wo_z[p]);
-    const bool fault = pixel_fault(fid, n_fabrics, u, v, r, wi, wo);
+    filter_one_pixel(g, fabrics, n_fabrics, p, n_samples, side, inv_side, seed, lane, out_rgb,
+                     out_comp, err);
+}
 
-    double comp[4] = {0.0, 0.0, 0.0, 0.0};
-    if (!fault)
-        filter_pixel_wave(fabrics[fid], seed, (uint64_t)p, n_samples, side, inv_side, u, v, r,
-                          wi, wo, lane, comp);
-    if (lane == 0) {
-        const int64_t n = g.n;
-        if (fault)
-            atomicAdd(err, 1ull);
-        if (out_comp) {
-            for (int c = 0; c < 4; c++)
-                out_comp[c * n + p] = (float)comp[c];
-        }
-        if (out_rgb) {
-            const DevFabric &f = fabrics[fault ? 0 : fid];
-            for (int c = 0; c < 3; c++) {
-                double rgb = (double)f.kd[0][c] * comp[0] + (double)f.kd[1][c] * comp[1] +
-                             (double)f.ks[0][c] * comp[2] + (double)f.ks[1][c] * comp[3];
-                out_rgb[c * n + p] = fault ? 0.0f : (float)rgb;
-            }
-        }
+// The queued pixels of a hybrid shading launch (all valid and in range of
+// the fabric table), in increasing pixel order: one wave per queue slot,
+// like gt_filter_kernel; the grid covers every pixel of the frame and the
+// waves past the queue's length exit at once (the length is only known on
+// the device).
+__global__ __launch_bounds__(256) void gt_filter_queue_kernel(fabric_gbuffer g,
+                                                              const DevFabric *__restrict__ fabrics,
+                                                              int n_samples, int side,
+                                                              float inv_side, uint64_t seed,
+                                                              FallbackQueue q,
+                                                              float *__restrict__ out_rgb)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t k = blockIdx.x * kWavesPerBlock + wave;
+    if (k >= *q.count)
+        return;
+    const int64_t p = __builtin_amdgcn_readfirstlane(q.idx[k]);
+    filter_one_pixel(g, fabrics, FABRIC_MAX_FABRICS, p, n_samples, side, inv_side, seed, lane,
+                     out_rgb, nullptr, nullptr);
+}
+
+// Queue compaction in three fixed-order steps (no atomics).  The offsets
+// buffer holds the per-group local offsets [ngroups], then the per-block
+// totals [nblk] and the blocks' exclusive prefixes [nblk].
+constexpr int kScanGroupsPerThread = 8;
+constexpr int kScanBlock = 256;
+constexpr int kScanGroupsPerBlock = kScanBlock * kScanGroupsPerThread;   // 2048 groups
+
+// Step 1: per block, offsets of its groups relative to the block, and the
+// block's total.  Thread t takes 8 consecutive groups (one 16-byte load).
+__global__ __launch_bounds__(kScanBlock) void queue_scan_local_kernel(
+    const uint16_t *__restrict__ mask, int64_t ngroups, uint32_t *__restrict__ offsets,
+    uint32_t *__restrict__ block_sums)
+{
+    __shared__ uint32_t part[kScanBlock];
+    const int t = threadIdx.x;
+    const int64_t k0 = (int64_t)blockIdx.x * kScanGroupsPerBlock + t * kScanGroupsPerThread;
+    uint32_t c[kScanGroupsPerThread];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanGroupsPerThread; j++) {
+        c[j] = k0 + j < ngroups ? (uint32_t)__popc((uint32_t)mask[k0 + j]) : 0u;
+        sum += c[j];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < kScanBlock; d <<= 1) {   // inclusive scan of the thread sums
+        const uint32_t add = t >= d ? part[t - d] : 0u;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+#pragma unroll
+    for (int j = 0; j < kScanGroupsPerThread; j++) {
+        if (k0 + j < ngroups)
+            offsets[k0 + j] = run;
+        run += c[j];
+    }
+    if (t == kScanBlock - 1)
+        block_sums[blockIdx.x] = part[t];
+}
+
+// Step 2 (one block): exclusive prefixes of the block totals, and the count.
+__global__ __launch_bounds__(1024) void queue_scan_blocks_kernel(const uint32_t *__restrict__ block_sums,
+                                                                int nblk,
+                                                                uint32_t *__restrict__ block_prefix,
+                                                                uint32_t *__restrict__ count)
+{
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int per = (nblk + 1023) / 1024;
+    const int b0 = t * per, b1 = b0 + per < nblk ? b0 + per : nblk;
+    uint32_t sum = 0;
+    for (int b = b0; b < b1; b++)
+        sum += block_sums[b];
+    part[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const uint32_t add = t >= d ? part[t - d] : 0u;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+    for (int b = b0; b < b1; b++) {
+        block_prefix[b] = run;
+        run += block_sums[b];
+    }
+    if (t == 1023)
+        *count = part[t];
+}
+
+// Step 3: each 16-pixel group writes its marked pixels' indices, in
+// increasing order, from its offset.
+__global__ void queue_scatter_kernel(const uint16_t *__restrict__ mask,
+                                     const uint32_t *__restrict__ offsets,
+                                     const uint32_t *__restrict__ block_prefix, int64_t ngroups,
+                                     int32_t *__restrict__ idx)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ngroups)
+        return;
+    uint32_t bits = mask[k];
+    uint32_t o = offsets[k] + block_prefix[k / kScanGroupsPerBlock];
+    while (bits) {
+        const int b = __builtin_ctz(bits);
+        bits &= bits - 1u;
+        idx[o++] = (int32_t)(16 * k + b);
     }
 }
 
@@ -69,14 +195,48 @@ hipError_t launch_gt_filter(const fabric_gbuffer &g, const DevFabric *fabrics, i
 {
     if (g.n == 0)
         return hipSuccess;
-    int side = 1;
-    while (side * side < n_samples)
-        side++;
+    const int side = sample_side(n_samples);
     int64_t blocks = (g.n + kWavesPerBlock - 1) / kWavesPerBlock;
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;   // padding blocks exit at once
     hipLaunchKernelGGL(gt_filter_kernel, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
                        stream, g, fabrics, n_fabrics, n_samples, side, 1.0f / (float)side, seed,
                        out_rgb, out_comp, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_gt_filter_queue(const fabric_gbuffer &g, const DevFabric *fabrics,
+                                  int n_samples, uint64_t seed, FallbackQueue q, float *out_rgb,
+                                  hipStream_t stream)
+{
+    if (g.n == 0)
+        return hipSuccess;
+    const int side = sample_side(n_samples);
+    const int64_t blocks = (g.n + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL(gt_filter_queue_kernel, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
+                       stream, g, fabrics, n_samples, side, 1.0f / (float)side, seed, q, out_rgb);
+    return hipGetLastError();
+}
+
+size_t queue_offset_entries(int64_t n)
+{
+    const int64_t ngroups = (n + 15) / 16;
+    const int64_t nblk = (ngroups + kScanGroupsPerBlock - 1) / kScanGroupsPerBlock;
+    return (size_t)(ngroups + 2 * nblk);
+}
+
+hipError_t launch_queue_build(FallbackQueue q, int64_t n, hipStream_t stream)
+{
+    const int64_t ngroups = (n + 15) / 16;
+    const int nblk = (int)((ngroups + kScanGroupsPerBlock - 1) / kScanGroupsPerBlock);
+    uint32_t *block_sums = q.offsets + ngroups;
+    uint32_t *block_prefix = block_sums + nblk;
+    hipLaunchKernelGGL(queue_scan_local_kernel, dim3(nblk), dim3(kScanBlock), 0, stream,
+                       (const uint16_t *)q.mask, ngroups, q.offsets, block_sums);
+    hipLaunchKernelGGL(queue_scan_blocks_kernel, dim3(1), dim3(1024), 0, stream,
+                       (const uint32_t *)block_sums, nblk, block_prefix, q.count);
+    hipLaunchKernelGGL(queue_scatter_kernel, dim3((unsigned)((ngroups + 255) / 256)), dim3(256), 0,
+                       stream, (const uint16_t *)q.mask, (const uint32_t *)q.offsets,
+                       (const uint32_t *)block_prefix, ngroups, q.idx);
     return hipGetLastError();
 }
 

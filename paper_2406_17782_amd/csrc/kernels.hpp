@@ -8,10 +8,29 @@
 
 namespace fab {
 
+// Pixels a hybrid shading launch routes to the footprint filter.  The
+// shading kernel writes one out-of-range bit per pixel (mask[k] covers pixels
+// 16k .. 16k+15); launch_queue_build turns the masks into the pixel indices
+// idx[0 .. *count) in increasing order (a fixed-order scan, no atomics).
+// Sizes: mask ceil(n/32)*2, offsets queue_offset_entries(n), idx n entries.
+struct FallbackQueue {
+    uint16_t *mask;
+    uint32_t *offsets;
+    uint32_t *count;
+    int32_t *idx;
+};
+
 // Footprint filter: one wavefront per pixel.
 hipError_t launch_gt_filter(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
                             int n_samples, uint64_t seed, float *out_rgb, float *out_comp,
                             unsigned long long *err, hipStream_t stream);
+// The same filter (identical per-pixel results) over the queued pixels of
+// a hybrid shading launch, writing their rgb; and the counter reset.
+hipError_t launch_gt_filter_queue(const fabric_gbuffer &g, const DevFabric *fabrics,
+                                  int n_samples, uint64_t seed, FallbackQueue q, float *out_rgb,
+                                  hipStream_t stream);
+size_t queue_offset_entries(int64_t n);
+hipError_t launch_queue_build(FallbackQueue q, int64_t n, hipStream_t stream);
 
 // Pack FP32 decoder parameters into the MFMA fragment image of precision prec.
 // image must hold decoder_image_bytes(prec).
@@ -30,9 +49,8 @@ size_t f8_image_bytes();
 hipError_t launch_pack_f8(const float *dec_params, const float *cfold, const DevFabric *fabrics,
                           int n_fabrics, void *image, hipStream_t stream);
 hipError_t launch_decode_f8(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
-                            const float *cfold, const void *image, int fallback_samples,
-                            uint64_t seed, float *out, unsigned long long *err,
-                            hipStream_t stream);
+                            const float *cfold, const void *image, bool hybrid, FallbackQueue q,
+                            float *out, unsigned long long *err, hipStream_t stream);
 
 // c_f = b1 + W1[:, 0:32] z_f for every fabric: cfold[n_fabrics][64].
 hipError_t launch_fold_latents(const float *dec_params, const float *latents, int n_fabrics,
@@ -40,11 +58,13 @@ hipError_t launch_fold_latents(const float *dec_params, const float *latents, in
 
 // Neural shading.  raw = true writes the decoder's outputs y[4][n] (image from
 // launch_pack_decoder); otherwise decoded, albedo-composed rgb[3][n] (image
-// from launch_pack_shade).  fallback_samples > 0 routes
-// out-of-range pixels to the footprint filter inside the same launch.
+// from launch_pack_shade).  fallback_samples > 0 routes out-of-range pixels
+// to the footprint filter with that many samples (keyed by seed and the
+// pixel index as launch_gt_filter): the shading launch marks them in q, the
+// queue is compacted in pixel order, and a third launch filters it.
 hipError_t launch_decode(int prec, bool raw, const fabric_gbuffer &g, const DevFabric *fabrics,
                          int n_fabrics, const float *cfold, const void *image,
-                         int fallback_samples, uint64_t seed, float *out,
+                         int fallback_samples, uint64_t seed, FallbackQueue q, float *out,
                          unsigned long long *err, hipStream_t stream);
 
 // Encoder forward over n_fabrics fabrics: enc_inputs[n][524] -> latents[n][32].

@@ -1,6 +1,6 @@
 // Pieces shared by the neural shading kernels (Sec. 4.3): G-buffer loads,
-// per-fabric constants in LDS, and the routing of out-of-range pixels to the
-// footprint filter.
+// per-fabric constants in LDS, and the marking of out-of-range pixels for
+// the footprint filter.
 #pragma once
 
 #include "kernels.hpp"
@@ -126,32 +126,19 @@ __device__ inline void compose_rgb(float y0, float y1, float y2, float y3, const
         rgb[c] = fc[4 + c] * cw + fc[7 + c] * cwf + fc[10 + c] * sw + fc[13 + c] * sf;
 }
 
-// The analytic footprint filter for the pixels of one tile whose bits are set
-// in `todo` (bit c: pixel base + c), all 64 lanes per pixel; the pixel's
-// fields are read again from the G-buffer.  Writes rgb[3][n].
-__device__ inline void shade_fallback(unsigned long long todo, int base, const fabric_gbuffer &g,
-                                      const DevFabric *__restrict__ fabrics, int fb_samples,
-                                      int fb_side, float fb_inv_side, uint64_t seed, int lane,
-                                      float *__restrict__ out)
+// Record the out-of-range pixels of one tile (bit c of `bits`: pixel
+// 16 * group + c) in the fallback queue's mask: 16 pixels per entry, written
+// by lane 0.
+__device__ inline void queue_mark16(uint32_t bits, int group, FallbackQueue q, int lane)
 {
-    const int n = (int)g.n;
-    while (todo) {
-        const int c = __builtin_ctzll(todo);
-        todo &= todo - 1;
-        const int pp = base + c;
-        const Pix x = load_pix(g, pp);
-        double comp[4];
-        filter_pixel_wave(fabrics[x.fid], seed, (uint64_t)pp, fb_samples, fb_side, fb_inv_side,
-                          x.u, x.v, x.r, x.wi, x.wo, lane, comp);
-        if (lane == 0) {
-            const DevFabric &f = fabrics[x.fid];
-            for (int ch = 0; ch < 3; ch++) {
-                const double rgb = (double)f.kd[0][ch] * comp[0] + (double)f.kd[1][ch] * comp[1] +
-                                   (double)f.ks[0][ch] * comp[2] + (double)f.ks[1][ch] * comp[3];
-                out[ch * n + pp] = (float)rgb;
-            }
-        }
-    }
+    if (lane == 0)
+        q.mask[group] = (uint16_t)bits;
+}
+// The same for a 32-pixel tile (two mask entries in one 32-bit store).
+__device__ inline void queue_mark32(uint32_t bits, int tile, FallbackQueue q, int lane)
+{
+    if (lane == 0)
+        ((uint32_t *)q.mask)[tile] = bits;
 }
 
 // Compute units of the current device (cached).
