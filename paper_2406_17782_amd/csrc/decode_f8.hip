@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) void pack_decoder_f8_kernel(const float *__res
 }
 
 template <bool HYBRID>
-__global__ __launch_bounds__(256) void decode_f8_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void decode_f8_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ cfold, const char *__restrict__ image, FallbackQueue q,
     float *__restrict__ out, unsigned long long *err, int n_tiles)
@@ -301,51 +301,83 @@ __global__ __launch_bounds__(256) void decode_f8_kernel(
     const HalfPlanes hp = half_planes(g, grp);
     auto tile_px = [&](int t) { return min((t < n_tiles ? t : wave_id) * 32 + col, n - 1); };
 
-    HalfPix nxt = load_half(g, hp, tile_px(wave_id));
-    for (int tile = wave_id; tile < n_tiles; tile += waves) {
-        const HalfPix cur = nxt;
-        nxt = load_half(g, hp, tile_px(tile + waves));
-        const int p = tile * 32 + col;
-        const bool valid = p < n;
-        const bool fault = pair_any(half_fault(cur, n_fabrics), lane);
+    // Per tile: fault and range decisions, features and the L1 C operand.
+    struct Prep {
+        int p, fid;
+        bool valid, fault, oor;
+        i32x8 B1;   // L1's B operand
+        int x3;     // L3's angular B operand (word 0)
+    };
+    auto prepare = [&](const HalfPix &cur, int tile, Prep &r, f32x16 (&a)[2]) {
+        r.p = tile * 32 + col;
+        r.valid = tile < n_tiles && r.p < n;
+        r.fault = pair_any(half_fault(cur, n_fabrics), lane);
         // Out-of-range rule (r > 1 cell or wo.z < 0.05), decided before the
         // MFMA chain so that no pixel field stays live through it.
-        const bool oor = HYBRID && !fault &&
-                         pair_any(cur.r > 1.0f || (grp == 1 && cur.xz < 0.05f), lane);
-        const int fid = fault ? 0 : cur.fid;   // non-finite inputs stay in their own column
-        const float *fc = s_fc + fid * kFabConsts;
-
+        r.oor = HYBRID && !r.fault && pair_any(cur.r > 1.0f || (grp == 1 && cur.xz < 0.05f), lane);
+        r.fid = r.fault ? 0 : cur.fid;   // non-finite inputs stay in their own column
+        const float *fc = s_fc + r.fid * kFabConsts;
         float s1[kL1Slots32];
-        Tile32<FABRIC_BF16>::spatial_slots(cur.uv, cur.uv, cur.r, fc[0], fc[1], fc[2], fc[3], grp, s1);
-        f32x16 cf[2], b2[2];
+        Tile32<FABRIC_BF16>::spatial_slots(cur.uv, cur.uv, cur.r, fc[0], fc[1], fc[2], fc[3], grp,
+                                           s1);
+        r.B1 = TileF8::l1_operand(s1);
 #pragma unroll
         for (int mb = 0; mb < 2; mb++)
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const f32x4 c4 = *(const f32x4 *)(s_cf + fid * 64 + 32 * mb + 8 * q + 4 * grp);
-                const f32x4 bq = s_b2[(mb * 64 + lane) * 4 + q];
+            for (int q4 = 0; q4 < 4; q4++) {
+                const f32x4 c4 = *(const f32x4 *)(s_cf + r.fid * 64 + 32 * mb + 8 * q4 + 4 * grp);
 #pragma unroll
-                for (int i = 0; i < 4; i++) {
-                    cf[mb][4 * q + i] = c4[i];
-                    b2[mb][4 * q + i] = bq[i];
-                }
+                for (int i = 0; i < 4; i++)
+                    a[mb][4 * q4 + i] = c4[i];
             }
-        const float x2 = grp ? 1.0f : cur.xz;
-        const f32x16 y = TileF8::forward(getA, sc, cf, b2, s1, cur.x0, cur.x1, x2);
-
+        // group 1's third slot carries L3's bias
+        r.x3 = TileF8::l3x_word(cur.x0, cur.x1, grp ? 1.0f : cur.xz);
+    };
+    auto finish = [&](const Prep &r, const f32x16 &y, int tile) {
         // Lanes 0..31 hold y[0..3] of pixel tile*32 + lane.
-        if (grp == 0 && valid && !oor) {
+        if (grp == 0 && r.valid && !r.oor) {
             float rgb[3];
-            compose_rgb<FM>(y[0] + b4[0], y[1] + b4[1], y[2] + b4[2], y[3] + b4[3], fc, rgb);
+            compose_rgb<FM>(y[0] + b4[0], y[1] + b4[1], y[2] + b4[2], y[3] + b4[3],
+                            s_fc + r.fid * kFabConsts, rgb);
 #pragma unroll
             for (int c = 0; c < 3; c++)
-                plane_store(out, c * n + p, fault ? 0.0f : rgb[c]);
+                plane_store(out, c * n + r.p, r.fault ? 0.0f : rgb[c]);
         }
-        const unsigned long long bad = __ballot(grp == 0 && valid && fault);
+        const unsigned long long bad = __ballot(grp == 0 && r.valid && r.fault);
         if (lane == 0 && bad)
             atomicAdd(err, (unsigned long long)__popcll(bad));
-        if (HYBRID)
-            queue_mark32((uint32_t)__ballot(grp == 0 && valid && oor), tile, q, lane);
+        if (HYBRID && tile < n_tiles)
+            queue_mark32((uint32_t)__ballot(grp == 0 && r.valid && r.oor), tile, q, lane);
+    };
+    // L2's C operand, read from LDS at each use (holding it would cost 32
+    // registers for the whole loop).
+    auto getB2 = [&](int mb) {
+        f32x16 b;
+#pragma unroll
+        for (int q4 = 0; q4 < 4; q4++) {
+            const f32x4 bq = s_b2[(mb * 64 + lane) * 4 + q4];
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+                b[4 * q4 + i] = bq[i];
+        }
+        return b;
+    };
+
+    // Two tiles per iteration (tile and tile + waves), shaded in alternation;
+    // the next pair's fields are loaded while this pair is shaded.
+    HalfPix n0 = load_half(g, hp, tile_px(wave_id));
+    HalfPix n1 = load_half(g, hp, tile_px(wave_id + waves));
+    for (int tile = wave_id; tile < n_tiles; tile += 2 * waves) {
+        const HalfPix c0 = n0, c1 = n1;
+        n0 = load_half(g, hp, tile_px(tile + 2 * waves));
+        n1 = load_half(g, hp, tile_px(tile + 3 * waves));
+        Prep r0, r1;
+        f32x16 a0[2], a1[2];
+        prepare(c0, tile, r0, a0);
+        prepare(c1, tile + waves, r1, a1);
+        TileF8::forward2(getA, sc, a0, a1, getB2, r0.B1, r1.B1, r0.x3, r1.x3);
+        finish(r0, a0[0], tile);
+        finish(r1, a1[0], tile + waves);
     }
 }
 

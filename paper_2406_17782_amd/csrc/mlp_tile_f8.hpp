@@ -155,6 +155,81 @@ struct TileF8 {
         y[3] = y3;
         return y;
     }
+
+    // The B operands of L1 (the 20 spatial slots) and of L3's angular k-step
+    // (three inputs: word 0 only) of one tile.
+    static __device__ inline i32x8 l1_operand(const float (&s1)[kL1Slots32])
+    {
+        float v[32];
+#pragma unroll
+        for (int c = 0; c < 32; c++)
+            v[c] = c < kL1Slots32 ? s1[c] : 0.0f;
+        return pack_f8x32<kL1Slots32>(v);
+    }
+    static __device__ inline int l3x_word(float x0, float x1, float x2)
+    {
+        const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(x0, x1, __builtin_bit_cast(int, x0), false);
+        return __builtin_amdgcn_cvt_pk_fp8_f32(x2, 0.0f, lo, true);
+    }
+
+    // Two independent tiles, layer by layer in alternation, so that one
+    // tile's MFMAs run while the other's activations are rounded.  a0 / a1
+    // hold each tile's L1 C operand (2^eh1 c_f) on entry and W4 h3 (rows
+    // 0..3 in lane group 0) on exit; getB2(mb) is L2's (shared) C operand.
+    template <typename GetA, typename GetB2>
+    static __device__ inline void forward2(GetA getA, const F8Header &h, f32x16 (&a0)[2],
+                                           f32x16 (&a1)[2], GetB2 getB2, i32x8 B1a, i32x8 B1b,
+                                           int xa, int xb)
+    {
+#pragma unroll
+        for (int mb = 0; mb < 2; mb++)
+            a0[mb] = mma(getA(DecShapeF8::FRAG_L1 + mb), B1a, a0[mb], h.sa[0], h.sb[0]);
+#pragma unroll
+        for (int mb = 0; mb < 2; mb++)
+            a1[mb] = mma(getA(DecShapeF8::FRAG_L1 + mb), B1b, a1[mb], h.sa[0], h.sb[0]);
+
+        const i32x8 B2a = chain(a0);
+#pragma unroll
+        for (int mb = 0; mb < 2; mb++)
+            a0[mb] = mma(getA(DecShapeF8::FRAG_L2 + mb), B2a, getB2(mb), h.sa[1], h.sb[1]);
+        const i32x8 B2b = chain(a1);
+#pragma unroll
+        for (int mb = 0; mb < 2; mb++)
+            a1[mb] = mma(getA(DecShapeF8::FRAG_L2 + mb), B2b, getB2(mb), h.sa[1], h.sb[1]);
+
+        const i32x8 B3a = chain(a0);
+        const i32x8 B3xa = i32x8{xa, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int mb = 0; mb < 2; mb++) {
+            a0[mb] = mma(getA(DecShapeF8::FRAG_L3 + 2 * mb), B3a, f32x16{}, h.sa[2], h.sb[2]);
+            a0[mb] = mma(getA(DecShapeF8::FRAG_L3 + 2 * mb + 1), B3xa, a0[mb], h.sa[2], h.sb_ang);
+        }
+        const i32x8 B3b = chain(a1);
+        const i32x8 B3xb = i32x8{xb, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int mb = 0; mb < 2; mb++) {
+            a1[mb] = mma(getA(DecShapeF8::FRAG_L3 + 2 * mb), B3b, f32x16{}, h.sa[2], h.sb[2]);
+            a1[mb] = mma(getA(DecShapeF8::FRAG_L3 + 2 * mb + 1), B3xb, a1[mb], h.sa[2], h.sb_ang);
+        }
+
+        const i32x8 B4a = chain(a0);
+        a0[0] = mma(getA(DecShapeF8::FRAG_L4), B4a, f32x16{}, h.sa[3], h.sb[3]);
+        const i32x8 B4b = chain(a1);
+        a1[0] = mma(getA(DecShapeF8::FRAG_L4), B4b, f32x16{}, h.sa[3], h.sb[3]);
+        // Pin both results to uniform control flow (see forward).
+        float t0 = a0[0][0], t1 = a0[0][1], t2 = a0[0][2], t3 = a0[0][3];
+        float u0 = a1[0][0], u1 = a1[0][1], u2 = a1[0][2], u3 = a1[0][3];
+        asm volatile("" : "+v"(t0), "+v"(t1), "+v"(t2), "+v"(t3), "+v"(u0), "+v"(u1), "+v"(u2),
+                     "+v"(u3));
+        a0[0][0] = t0;
+        a0[0][1] = t1;
+        a0[0][2] = t2;
+        a0[0][3] = t3;
+        a1[0][0] = u0;
+        a1[0][1] = u1;
+        a1[0][2] = u2;
+        a1[0][3] = u3;
+    }
 };
 
 }  // namespace fab
