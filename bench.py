@@ -198,6 +198,88 @@ def precision_row_4k(args, torch, pkg, fi, fab, params):
     return row
 
 
+def interp_row(args, torch, pkg, fi, g, d):
+    """Latent interpolation study (Sec. 5 "Interpolation") on the 1080p
+    frame's geometry: a second network trained on variants of one twill whose
+    roughness and height-field scale span [0.15, 0.95]; latents encoded at
+    0.2 and 0.8, blended on the GPU at 0.3 and 0.6 and extrapolated to 0.9.
+    Every pixel of a frame shows one slot; each blended frame is compared with
+    the directly encoded one and with the analytic filter at 256 samples."""
+    import dataclasses
+    fab = pkg.Fabric(0, seed=4343)
+    try:
+        fab.encode(fi.sweep_training_set(64, 4400))
+        steps = args.interp_train_steps
+        for s in range(steps):
+            lr = args.train_lr * 0.5 * (1.0 + math.cos(math.pi * s / max(1, steps)))
+            fab.train_step(seed=2_000_000 + s, batch=1 << 16, gt_samples=args.gt_samples,
+                           prec=pkg.FABRIC_BF16, lr=lr, want_loss=(s == steps - 1))
+        pts = fi.INTERP_ENDPOINTS + fi.INTERP_POINTS
+        table = fi.parameter_sweep("alpha", pts, 4401) + fi.parameter_sweep("beta", pts, 4402)
+        fab.encode(table)
+        p0, p1 = fi.INTERP_ENDPOINTS
+        dst, a, b, t = [], [], [], []
+        for base in (0, 5):
+            for k, p in enumerate(fi.INTERP_POINTS):
+                dst.append(base + 2 + k)
+                a.append(base)
+                b.append(base + 1)
+                t.append((p - p0) / (p1 - p0))
+
+        def frame(slot):
+            fid = torch.from_numpy(np.full(g.n, slot, dtype=np.int16)).to("cuda").view(torch.uint16)
+            return dataclasses.replace(d, fabric_id=fid)
+
+        frames = [frame(k) for k in range(len(table))]
+        out = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
+
+        def shade_all(slots):
+            res = {}
+            for k in slots:
+                pkg.fabric_shade_gbuffer(fab.ctx, frames[k], pkg.PREC["bf16"], 0, 0, out)
+                res[k] = out.cpu().numpy().astype(np.float64)
+            return res
+
+        direct = shade_all(range(len(table)))
+        gt = {}
+        for k in dst:
+            pkg.fabric_gt_filtered(fab.ctx, frames[k], args.gt_samples, 4242, out, None)
+            gt[k] = out.cpu().numpy().astype(np.float64)
+        # The blend call (host arrays in, one copy, blend + refold launches).
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(100):
+            fab.lerp_latents(dst, a, b, t)
+        torch.cuda.synchronize()
+        lerp_ms = (time.perf_counter() - t0) / 100 * 1e3
+        blended = shade_all(dst)
+        shade = lambda: pkg.fabric_shade_gbuffer(fab.ctx, frames[dst[0]], pkg.PREC["bf16"], 0, 0, out)
+        for _ in range(300):
+            shade()
+        shade_ms = time_launches(torch, shade, 200)
+        rel = lambda x, y: float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-30))
+        points = {}
+        for k, field in enumerate(("alpha", "beta")):
+            for j, p in enumerate(fi.INTERP_POINTS):
+                slot = 5 * k + 2 + j
+                near = 5 * k + (0 if abs(p - p0) < abs(p - p1) else 1)
+                points[f"{field}={p}"] = {
+                    "t": t[3 * k + j],
+                    "blend_vs_direct": rel(blended[slot], direct[slot]),
+                    "nearest_endpoint_vs_direct": rel(direct[near], direct[slot]),
+                    "direct_vs_analytic": rel(direct[slot], gt[slot]),
+                    "blend_vs_analytic": rel(blended[slot], gt[slot]),
+                }
+        log("interpolation: " + ", ".join(f"{k} {v['blend_vs_direct']:.4f}" for k, v in points.items()))
+        return {"train_steps": steps, "train_batch": 1 << 16, "training_table": "64 twill variants",
+                "lerp_call_ms": lerp_ms, "blends_per_call": len(dst),
+                "bf16_ms_per_frame_after_edit": shade_ms,
+                "metric": "relative L2 over a 1080p frame showing one slot",
+                "points": points}
+    finally:
+        fab.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,6 +291,8 @@ def main():
     ap.add_argument("--train-batch", type=int, default=1 << 18)
     ap.add_argument("--train-lr", type=float, default=1e-2)
     ap.add_argument("--gt-samples", type=int, default=256)
+    ap.add_argument("--interp-train-steps", type=int, default=3000,
+                    help="training steps of the latent interpolation row's network")
     ap.add_argument("--analytic-steps", type=int, default=10)
     ap.add_argument("--rmse-frac", type=float, default=0.01)
     ap.add_argument("--cpu-budget", type=float, default=8.0)
@@ -348,6 +432,7 @@ def main():
                                     "note": "host call incl. table upload"}
         rows["fabric64_4k"] = precision_row_4k(args, torch, pkg, fi, fab, params)
         fab.encode(mats)
+        rows["latent_interpolation"] = interp_row(args, torch, pkg, fi, g, d)
 
     # ---- error against the FP64 oracle on a seeded pixel subset ----
     errs = None if args.no_rmse else oracle_errors(args, torch, pkg, fi, fab, d, mats, g, rgb, gt_rgb)

@@ -146,6 +146,40 @@ def uniform_material(pattern: np.ndarray, alpha=0.5, beta=1.0, twist=0.0,
     )
 
 
+# The parameter points of the latent interpolation study (Sec. 5
+# "Interpolation"): latents encoded at 0.2 and 0.8, blended at 0.3 and 0.6,
+# extrapolated to 0.9.
+INTERP_ENDPOINTS = (0.2, 0.8)
+INTERP_POINTS = (0.3, 0.6, 0.9)
+
+
+def parameter_sweep(field: str, values: Sequence[float], seed: int,
+                    pattern: Optional[np.ndarray] = None) -> List[Material]:
+    """One seeded material (twill 2/1 unless `pattern` is given) repeated with
+    its `field` ("alpha": roughness, or "beta": height-field scaling) set to
+    each of `values` on both yarns; every other field is shared."""
+    if field not in ("alpha", "beta"):
+        raise ValueError("field is alpha or beta")
+    rng = np.random.default_rng(seed)
+    base = random_material(rng, NAMED_PATTERNS["twill21"]() if pattern is None else pattern)
+    out = []
+    for val in values:
+        m = dataclasses.replace(base, **{field: _f32([val, val])})
+        out.append(m)
+    return out
+
+
+def sweep_training_set(n: int, seed: int, lo: float = 0.15, hi: float = 0.95,
+                       pattern: Optional[np.ndarray] = None) -> List[Material]:
+    """n variants of one seeded material whose roughness and height-field
+    scale are drawn uniformly from [lo, hi] (per yarn): a training table that
+    spans the parameter range of the interpolation study."""
+    rng = np.random.default_rng(seed)
+    base = random_material(rng, NAMED_PATTERNS["twill21"]() if pattern is None else pattern)
+    return [dataclasses.replace(base, alpha=_f32(rng.uniform(lo, hi, 2)),
+                                beta=_f32(rng.uniform(lo, hi, 2))) for _ in range(n)]
+
+
 def materials_for(n_fabrics: int, seed: int, max_random_side: int = 8) -> List[Material]:
     """The fabric set of a workload.
 

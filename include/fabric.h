@@ -148,6 +148,31 @@ fabric_status fabric_encode(fabric_ctx *ctx, const fabric_material *mats, int32_
 fabric_status fabric_set_albedo(fabric_ctx *ctx, int32_t fabric, const float kd[2][3],
                                 const float ks[2][3], void *stream);
 
+/* Latent interpolation and extrapolation (Sec. 5 "Interpolation"): the
+ * encoder's latents form a space in which a material between two encoded
+ * ones is approximated by the weighted blend of their latents, the weight
+ * being the position of the varied parameter (e.g. roughness alpha or
+ * height-field scale beta) between the two encoded values,
+ * t = (p - p_a) / (p_b - p_a); t outside [0, 1] extrapolates.  For
+ * k < count:
+ *     z[dst[k]] = (1 - t[k]) z[a[k]] + t[k] z[b[k]]
+ * computed in FP32 as fma(t, z_b, (1 - t) z_a) (exactly z_a at t = 0 and z_b
+ * at t = 1), then c_f = W1_z z_f + b1 refolded.  Every entry reads the latent
+ * table as it was before the call, so a dst may also be another entry's a
+ * or b.  dst, a, b, t: host arrays of count entries (count in
+ * 0..n_mats; 0 does nothing and the arrays may be NULL); indices are fabric
+ * slots of the last fabric_encode, the dst values pairwise distinct.  Only
+ * latents change: dst keeps its own pattern and albedos from fabric_encode
+ * (set them there to the material being approximated).  The next
+ * fabric_encode recomputes every latent from the fabric table, replacing
+ * edited ones; the FP8 activation scales are recalibrated at the next FP8
+ * shading call.  Errors: E_INVAL for a NULL array with count > 0, a
+ * repeated dst or a non-finite t; E_RANGE for a count or index out of range;
+ * E_STATE before fabric_encode or after a weight change without it.  Returns
+ * after the copies of the host arrays; the kernels run on `stream`. */
+fabric_status fabric_lerp_latents(fabric_ctx *ctx, const int32_t *dst, const int32_t *a,
+                                  const int32_t *b, const float *t, int32_t count, void *stream);
+
 /* Neural shading of a G-buffer (Sec. 4.3 "Rendering"): per pixel, the
  * decoder's four outputs decoded as C = max(y, 0), S = max((e^y - 1)/100, 0)
  * (inverse of the specular mapping of Eq. (9)) and composed with Eq. (8).

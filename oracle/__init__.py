@@ -269,6 +269,27 @@ def encoder(params_enc, mats: Sequence) -> np.ndarray:
     return z
 
 
+def parameter_weight(p: float, p_a: float, p_b: float) -> float:
+    """Blend weight of a material whose varied parameter (roughness or
+    height-field scale) is p, between latents encoded at p_a and p_b
+    (Sec. 5 "Interpolation"): the parameter's relative position, so that
+    p = p_a gives 0, p = p_b gives 1, and p beyond p_b extrapolates."""
+    return (float(p) - float(p_a)) / (float(p_b) - float(p_a))
+
+
+def interpolate_latents(latents, dst: Sequence[int], a: Sequence[int], b: Sequence[int],
+                        t: Sequence[float]) -> np.ndarray:
+    """Latent table after the blends z[dst_k] = (1 - t_k) z[a_k] + t_k z[b_k]
+    of Sec. 5 "Interpolation", in FP64.  Every blend reads the table as it
+    was before any of them, then all are written."""
+    before = np.array(latents, dtype=np.float64)
+    after = before.copy()
+    for d, i, j, w in zip(dst, a, b, t):
+        w = float(w)
+        after[d] = (1.0 - w) * before[i] + w * before[j]
+    return after
+
+
 def loss_grad(params, mats: Sequence, g, targets):
     """Loss of Eq. (11) and its gradient w.r.t. [decoder | encoder] parameters."""
     h = _GBufHolder(g)

@@ -23,7 +23,7 @@ __all__ = [
     "Fabric", "DeviceGBuffer", "FabricError", "PREC", "FABRIC_FP32", "FABRIC_BF16", "FABRIC_FP16",
     "FABRIC_FP8_E4M3", "FABRIC_N_PARAMS", "FABRIC_N_DECODER_PARAMS", "FABRIC_N_ENCODER_PARAMS",
     "FABRIC_MAX_FABRICS", "FABRIC_MAX_SAMPLES", "FABRIC_LATENT",
-    "fabric_create", "fabric_destroy", "fabric_encode", "fabric_set_albedo",
+    "fabric_create", "fabric_destroy", "fabric_encode", "fabric_set_albedo", "fabric_lerp_latents",
     "fabric_shade_gbuffer", "fabric_gt_filtered", "fabric_decoder_forward",
     "fabric_decoder_backward", "fabric_encoder_forward", "fabric_encoder_backward",
     "fabric_make_batch", "fabric_loss_grad", "fabric_train_step", "fabric_get_params", "fabric_set_params",
@@ -135,6 +135,18 @@ def fabric_set_albedo(ctx, fabric: int, kd, ks, stream=None) -> None:
     ks = np.ascontiguousarray(ks, dtype=np.float32).reshape(2, 3)
     check(_abi.lib().fabric_set_albedo(ctx, fabric, kd.ctypes.data, ks.ctypes.data, _stream(stream)),
           "fabric_set_albedo")
+
+
+def fabric_lerp_latents(ctx, dst, a, b, t, stream=None) -> None:
+    dst = np.ascontiguousarray(dst, dtype=np.int32).reshape(-1)
+    a = np.ascontiguousarray(a, dtype=np.int32).reshape(-1)
+    b = np.ascontiguousarray(b, dtype=np.int32).reshape(-1)
+    t = np.ascontiguousarray(t, dtype=np.float32).reshape(-1)
+    if not (dst.size == a.size == b.size == t.size):
+        raise ValueError("dst, a, b and t need one entry per blend")
+    check(_abi.lib().fabric_lerp_latents(ctx, dst.ctypes.data, a.ctypes.data, b.ctypes.data,
+                                         t.ctypes.data, int(dst.size), _stream(stream)),
+          "fabric_lerp_latents")
 
 
 def fabric_shade_gbuffer(ctx, g: DeviceGBuffer, prec: int, fallback_samples: int, seed: int,
@@ -306,6 +318,11 @@ class Fabric:
 
     def latents(self) -> np.ndarray:
         return fabric_get_latents(self.ctx, self.n_mats)
+
+    def lerp_latents(self, dst, a, b, t, stream=None) -> None:
+        """z[dst[k]] = (1 - t[k]) z[a[k]] + t[k] z[b[k]] on the device (latent
+        interpolation / extrapolation between encoded fabrics)."""
+        fabric_lerp_latents(self.ctx, dst, a, b, t, stream)
 
     def train_step(self, gbuf: Optional[DeviceGBuffer] = None, targets=None, want_loss: bool = True,
                    **cfg) -> Optional[float]:

@@ -29,7 +29,51 @@ __global__ __launch_bounds__(256) void encoder_forward_kernel(const float *__res
         latents[f * kLatent + k] = z[k];
 }
 
+// Latent blends of Sec. 5 "Interpolation" in one block: every thread loads
+// its blended values into registers, the block synchronises, then every
+// thread stores; so all reads of the table precede all writes and an entry
+// may target another entry's source.
+constexpr int kLerpThreads = 1024;
+constexpr int kLerpPer = FABRIC_MAX_FABRICS * kLatent / kLerpThreads;
+static_assert(FABRIC_MAX_FABRICS * kLatent % kLerpThreads == 0, "lerp work split");
+
+__global__ __launch_bounds__(kLerpThreads) void lerp_latents_kernel(
+    const LatentLerp *__restrict__ jobs, int count, float *latents)
+{
+    float val[kLerpPer];
+    const int total = count * kLatent;
+#pragma unroll
+    for (int i = 0; i < kLerpPer; i++) {
+        const int e = threadIdx.x + i * kLerpThreads;
+        if (e < total) {
+            const LatentLerp j = jobs[e / kLatent];
+            const int k = e % kLatent;
+            const float za = latents[j.a * kLatent + k], zb = latents[j.b * kLatent + k];
+            val[i] = fmaf(j.t, zb, (1.0f - j.t) * za);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kLerpPer; i++) {
+        const int e = threadIdx.x + i * kLerpThreads;
+        if (e < total)
+            latents[jobs[e / kLatent].dst * kLatent + e % kLatent] = val[i];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_lerp_latents(const LatentLerp *jobs, int count, float *latents,
+                               hipStream_t stream)
+{
+    if (count <= 0)
+        return hipSuccess;
+    if (count > FABRIC_MAX_FABRICS)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(lerp_latents_kernel, dim3(1), dim3(kLerpThreads), 0, stream, jobs, count,
+                       latents);
+    return hipGetLastError();
+}
 
 hipError_t launch_encoder_forward(const float *enc_params, const float *enc_inputs,
                                   int n_fabrics, float *latents, hipStream_t stream)

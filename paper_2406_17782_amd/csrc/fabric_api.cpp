@@ -27,8 +27,9 @@ struct fabric_ctx {
     float *enc_inputs = nullptr;      // [FABRIC_MAX_FABRICS][524]
     float *latents = nullptr;         // [FABRIC_MAX_FABRICS][32]
     float *cfold = nullptr;           // [FABRIC_MAX_FABRICS][64]
+    LatentLerp *lerp_jobs = nullptr;  // [FABRIC_MAX_FABRICS]
     uint64_t encoded_version = 0;     // weights_version of the last encode
-    uint64_t encode_serial = 0;       // bumped on every encode
+    uint64_t encode_serial = 0;       // bumped on every change of latents or fabric table
 
     void *image[4] = {nullptr, nullptr, nullptr, nullptr};   // packed decoders
     uint64_t image_version[4] = {0, 0, 0, 0};
@@ -332,6 +333,7 @@ void fabric_destroy(fabric_ctx *ctx)
     (void)hipFree(ctx->enc_inputs);
     (void)hipFree(ctx->latents);
     (void)hipFree(ctx->cfold);
+    (void)hipFree(ctx->lerp_jobs);
     for (int k = 0; k < 4; k++)
         (void)hipFree(ctx->image[k]);
     (void)hipFree(ctx->tmp_image);
@@ -370,6 +372,7 @@ fabric_status fabric_create(fabric_ctx **out, int device, uint64_t seed)
     if (st == FABRIC_OK) st = dalloc(&ctx->latents, F * kLatent);
     if (st == FABRIC_OK) st = dalloc(&ctx->cfold, F * 64);
     if (st == FABRIC_OK) st = dalloc(&ctx->tmp_cfold, F * 64);
+    if (st == FABRIC_OK) st = dalloc(&ctx->lerp_jobs, F);
     if (st == FABRIC_OK) st = dalloc(&ctx->err, 1);
     if (st == FABRIC_OK) {
         const size_t img = decoder_image_bytes(FABRIC_FP32);   // the largest image
@@ -452,6 +455,46 @@ fabric_status fabric_set_albedo(fabric_ctx *ctx, int32_t fabric, const float kd[
                                                hipMemcpyHostToDevice, s));
     if (st == FABRIC_OK)
         st = from_hip(hipStreamSynchronize(s));
+    return st;
+}
+
+fabric_status fabric_lerp_latents(fabric_ctx *ctx, const int32_t *dst, const int32_t *a,
+                                  const int32_t *b, const float *t, int32_t count, void *stream)
+{
+    if (!ctx)
+        return FABRIC_E_INVAL;
+    if (ctx->n_mats == 0 || ctx->encoded_version != ctx->weights_version)
+        return FABRIC_E_STATE;
+    if (count < 0 || count > ctx->n_mats)
+        return FABRIC_E_RANGE;
+    if (count == 0)
+        return FABRIC_OK;
+    if (!dst || !a || !b || !t)
+        return FABRIC_E_INVAL;
+    std::vector<LatentLerp> jobs(count);
+    std::vector<char> taken(ctx->n_mats, 0);
+    for (int k = 0; k < count; k++) {
+        const int32_t idx[3] = {dst[k], a[k], b[k]};
+        for (int32_t i : idx)
+            if (i < 0 || i >= ctx->n_mats)
+                return FABRIC_E_RANGE;
+        if (!finite(t[k]) || taken[dst[k]])
+            return FABRIC_E_INVAL;
+        taken[dst[k]] = 1;
+        jobs[k] = LatentLerp{dst[k], a[k], b[k], t[k]};
+    }
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = as_stream(stream);
+    fabric_status st = from_hip(hipMemcpyAsync(ctx->lerp_jobs, jobs.data(),
+                                               jobs.size() * sizeof(LatentLerp),
+                                               hipMemcpyHostToDevice, s));
+    // The host staging vector must outlive the copy.
+    if (st == FABRIC_OK) st = from_hip(hipStreamSynchronize(s));
+    if (st == FABRIC_OK) st = from_hip(launch_lerp_latents(ctx->lerp_jobs, count, ctx->latents, s));
+    if (st == FABRIC_OK)
+        st = from_hip(launch_fold_latents(ctx->params, ctx->latents, ctx->n_mats, ctx->cfold, s));
+    // Even a failed launch may have changed latents: force FP8 recalibration.
+    ctx->encode_serial += 1;
     return st;
 }
 

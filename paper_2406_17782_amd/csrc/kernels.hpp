@@ -67,6 +67,17 @@ hipError_t launch_decode(int prec, bool raw, const fabric_gbuffer &g, const DevF
                          int fallback_samples, uint64_t seed, FallbackQueue q, float *out,
                          unsigned long long *err, hipStream_t stream);
 
+// One latent blend of Sec. 5 "Interpolation": z[dst] = (1 - t) z[a] + t z[b].
+struct LatentLerp {
+    int32_t dst, a, b;
+    float t;
+};
+// Apply count (<= FABRIC_MAX_FABRICS) blends, with pairwise distinct dst and
+// indices below the table's size, to latents[.][32] in one launch; every
+// blend reads the table as it was before the launch.  jobs: device memory.
+hipError_t launch_lerp_latents(const LatentLerp *jobs, int count, float *latents,
+                               hipStream_t stream);
+
 // Encoder forward over n_fabrics fabrics: enc_inputs[n][524] -> latents[n][32].
 hipError_t launch_encoder_forward(const float *enc_params, const float *enc_inputs,
                                   int n_fabrics, float *latents, hipStream_t stream);
