@@ -198,6 +198,50 @@ def precision_row_4k(args, torch, pkg, fi, fab, params):
     return row
 
 
+def hybrid_class_errors(args, torch, pkg, fi, fab, mats, hg):
+    """Per-class error of the first hybrid frame against the FP64 oracle's
+    filter (256 samples, seeded like the frame's fallback) on a seeded 1 %
+    of its pixels: the decoder's pixels and the filter's pixels apart."""
+    import oracle
+    g0 = fi.jitter_gbuffer(hg, 50_000)
+    d0 = pkg.DeviceGBuffer.from_host(g0)
+    out = torch.empty((3, g0.n), dtype=torch.float32, device="cuda")
+    pkg.fabric_shade_gbuffer(fab.ctx, d0, pkg.FABRIC_BF16, args.gt_samples, 0, out)
+    rgb = out.cpu().numpy()
+    idx = fi.subset_indices(g0.n, 0.01, 98)
+    _, o_rgb, _, _ = oracle.filter_gbuffer(mats, g0.subset(idx), args.gt_samples, 0,
+                                           same_sample=True, pixel_index=idx)
+    oor = (g0.radius[idx] > np.float32(1.0)) | (g0.wo_z[idx] < np.float32(0.05))
+    res = {"subset_pixels": int(idx.size), "reference": "FP64 oracle filter, 256 same samples"}
+    for name, m in (("decoder_bf16", ~oor), ("filter_fallback", oor)):
+        res[name] = dict(rmse_stats(rgb[:, idx][:, m], o_rgb[:, m]), pixels=int(m.sum()))
+    log(f"hybrid rmse: decoder {res['decoder_bf16']['rmse']:.4g}, "
+        f"fallback {res['filter_fallback']['rmse']:.3g}")
+    return res
+
+
+def train_row_2p20(args, torch, pkg, fab):
+    """Training steps at the training workload's batch of 2^20 generated
+    samples (targets from the filter at 256 samples, BF16 decoder), timed by
+    events after warmup; the trained state is restored afterwards."""
+    blob = pkg.fabric_save(fab.ctx)
+    step = lambda s: fab.train_step(seed=3_000_000 + s, batch=1 << 20, gt_samples=args.gt_samples,
+                                    prec=pkg.FABRIC_BF16, lr=1e-4, want_loss=False)
+    for s in range(5):
+        step(s)
+    torch.cuda.synchronize()
+    k = [0]
+
+    def one():
+        step(5 + k[0])
+        k[0] += 1
+    ms = time_launches(torch, one, 20)
+    pkg.fabric_load(fab.ctx, blob)
+    log(f"train step 2^20: {ms:.2f} ms")
+    return {"ms_per_step": ms, "batch": 1 << 20, "gt_samples": args.gt_samples,
+            "samples_per_s": (1 << 20) / (ms * 1e-3), "prec": "bf16 decoder, FP32 masters, FP64 Adam"}
+
+
 def interp_row(args, torch, pkg, fi, g, d):
     """Latent interpolation study (Sec. 5 "Interpolation") on the 1080p
     frame's geometry: a second network trained on variants of one twill whose
@@ -393,10 +437,10 @@ def main():
         log(f"neural {prec}: {t * 1e3:.1f} us/frame")
     if not args.no_rows:
         # Hybrid frame: 20 % out-of-range pixels routed to the analytic filter.
+        # The hybrid G-buffer (20 % out of range) over the trained fabric
+        # table, so that the decoder's class is judged on fabrics it learnt.
         hw = fi.WORKLOADS["hybrid_1080p"]
         hg = hw.gbuffer()
-        hmats = hw.materials()
-        fab.encode(hmats)
         hout = torch.empty((3, hg.n), dtype=torch.float32, device="cuda")
         # 60 jittered frames, all resident first (as a renderer's G-buffers
         # would be), shaded back to back after 10 warmup frames; each frame
@@ -420,6 +464,9 @@ def main():
                                 "p99_ms": float(np.percentile(frame_ms, 99)),
                                 "fps_p50": 1e3 / float(np.percentile(frame_ms, 50)),
                                 "out_of_range_frac": hw.out_of_range_frac}
+        if not args.no_rmse:
+            rows["hybrid_frame"]["rmse_by_class"] = hybrid_class_errors(args, torch, pkg, fi, fab,
+                                                                        mats, hg)
         log(f"hybrid frame p50 {rows['hybrid_frame']['p50_ms']:.3f} ms")
         fab.encode(mats)
         # Encoder: one (re-)encode of 8 fabrics (an edit).
@@ -431,6 +478,8 @@ def main():
         rows["encode_8_fabrics"] = {"ms": (time.perf_counter() - t0) / 20 * 1e3,
                                     "note": "host call incl. table upload"}
         rows["fabric64_4k"] = precision_row_4k(args, torch, pkg, fi, fab, params)
+        fab.encode(mats)
+        rows["train_step_2p20"] = train_row_2p20(args, torch, pkg, fab)
         fab.encode(mats)
         rows["latent_interpolation"] = interp_row(args, torch, pkg, fi, g, d)
 
