@@ -23,7 +23,9 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, OpenMP, FP64; no fast-math)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall",
+        # No contraction of a*b+c: the visibility march's float32 steps must
+        # round once per operation.
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall", "-ffp-contract=off",
                "-Wno-unused-function", _SRC, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
@@ -72,10 +74,16 @@ def lib():
         L.orc_filter_pixel.restype = ctypes.c_int
         L.orc_filter_pixel.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        _P, _P, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
-                                       ctypes.c_int, _P, _P]
+                                       ctypes.c_int, ctypes.c_int, _P, _P]
         L.orc_filter_batch.restype = ctypes.c_int64
         L.orc_filter_batch.argtypes = [_P, ctypes.c_int, _P, _P, ctypes.c_int, ctypes.c_uint64,
-                                       ctypes.c_int, _P, _P, _P, _P]
+                                       ctypes.c_int, ctypes.c_int, _P, _P, _P, _P]
+        L.orc_surface_height.restype = ctypes.c_double
+        L.orc_surface_height.argtypes = [_P, ctypes.c_double, ctypes.c_double]
+        L.orc_height_table.restype = ctypes.c_float
+        L.orc_height_table.argtypes = [_P, _P]
+        L.orc_visible_at.restype = ctypes.c_int
+        L.orc_visible_at.argtypes = [_P, ctypes.c_double, ctypes.c_double, _P]
         L.orc_param_counts.restype = ctypes.c_int
         L.orc_param_counts.argtypes = [_P]
         L.orc_spatial_features.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -205,19 +213,37 @@ def point_eval_batch(mat, us, vs, wi, wo) -> dict:
 
 
 def filter_pixel(mat, u: float, v: float, r: float, wi, wo, n_samples: int, seed: int,
-                 pixel: int = 0, same_sample: bool = False):
+                 pixel: int = 0, same_sample: bool = False, visibility: bool = False):
     m = materials([mat])
     comp = np.zeros(4)
     area = np.zeros(1)
     fl = lib().orc_filter_pixel(ctypes.byref(m[0]), u, v, r, _ptr(_d(wi)), _ptr(_d(wo)),
                                 int(n_samples), ctypes.c_uint64(seed), ctypes.c_uint64(pixel),
-                                int(same_sample), _ptr(comp), _ptr(area))
+                                int(same_sample), int(visibility), _ptr(comp), _ptr(area))
     return comp, float(area[0]), int(fl)
 
 
+def surface_height(mat, us: float, vs: float) -> float:
+    """Height (cells) of the stand-in fabric surface at (us, vs)."""
+    return float(lib().orc_surface_height(ctypes.byref(materials([mat])[0]), us, vs))
+
+
+def height_table(mat):
+    """The float32 height texels [wy*16, wx*16] and their maximum."""
+    t = np.zeros((mat.wy * 16, mat.wx * 16), dtype=np.float32)
+    hmax = lib().orc_height_table(ctypes.byref(materials([mat])[0]), _ptr(t))
+    return t, float(hmax)
+
+
+def visible(mat, us: float, vs: float, w) -> int:
+    """V(x_p, w) of the sample point (us, vs) toward w."""
+    return int(lib().orc_visible_at(ctypes.byref(materials([mat])[0]), us, vs, _ptr(_d(w))))
+
+
 def filter_gbuffer(mats: Sequence, g, n_samples: int, seed: int, same_sample: bool = True,
-                   pixel_index: Optional[np.ndarray] = None):
-    """Footprint filter over a G-buffer: returns comp [4,n], rgb [3,n], flagged [n], fault [n]."""
+                   pixel_index: Optional[np.ndarray] = None, visibility: bool = False):
+    """Footprint filter over a G-buffer: returns comp [4,n], rgb [3,n], flagged [n], fault [n].
+    visibility=True includes the inter-yarn visibility V of Eq. (3)-(4)."""
     h = _GBufHolder(g)
     n = h.s.n
     comp = np.zeros((4, n))
@@ -228,7 +254,7 @@ def filter_gbuffer(mats: Sequence, g, n_samples: int, seed: int, same_sample: bo
     m = materials(mats)
     lib().orc_filter_batch(m, len(mats), h.ref, None if pidx is None else _ptr(pidx),
                            int(n_samples), ctypes.c_uint64(seed), int(same_sample),
-                           _ptr(comp), _ptr(rgb), _ptr(flagged), _ptr(fault))
+                           int(visibility), _ptr(comp), _ptr(rgb), _ptr(flagged), _ptr(fault))
     return comp, rgb, flagged, fault
 
 

@@ -20,9 +20,14 @@
  *     paper's supplementary, so this stand-in is "parity unpinned" against the
  *     paper's own geometry and pinned only by its invariants);
  *   - the footprint aggregation of Eq. (3) with A(p, wo) of Eq. (4) and the
- *     normaliser A_P of Eq. (5), with visibility V = 1, estimated by
- *     stratified, jittered Monte-Carlo samples over a disk footprint, split
- *     into the four components of Eq. (7) whose albedo-weighted sum is Eq. (8);
+ *     normaliser A_P of Eq. (5), estimated by stratified, jittered
+ *     Monte-Carlo samples over a disk footprint, split into the four
+ *     components of Eq. (7) whose albedo-weighted sum is Eq. (8); the binary
+ *     visibility V of Eq. (3)-(4) is either 1 or the inter-yarn
+ *     shadowing-masking of a stand-in height field (integrated from the same
+ *     yarn slopes, tabulated per texel, marched over a fixed two-cell patch:
+ *     the paper's own definition is in its supplementary, so this part is
+ *     "parity unpinned" against the paper and pinned by its invariants);
  *   - the network of Sec. 4.2 at the sizes of this build (encoder: one-hot
  *     weave grid + 12 yarn scalars -> residual MLP -> latent 32; decoder:
  *     spatial fusion of latent and encoded footprint, then the angular
@@ -56,6 +61,10 @@
 #define ORC_LAMBDA_C 0.1
 /* A footprint sample this close (cells) to a classification edge is flagged. */
 #define ORC_EDGE_EPS 1e-5
+/* Visibility: height-field texels per cell and axis, and march length in
+ * texel steps along the direction's major horizontal axis (two cells). */
+#define ORC_VIS_RES 16
+#define ORC_VIS_STEPS 32
 
 enum { ORC_WARP = 0, ORC_WEFT = 1, ORC_HOLE = 2 };
 
@@ -209,9 +218,14 @@ static int weft_run(const orc_material *m, int i, int j, int *offset, int *lengt
 typedef struct {
     int yarn;          /* ORC_WARP, ORC_WEFT or ORC_HOLE */
     int on_top;        /* the visible yarn is the top yarn of its cell */
+    int top;           /* the cell's top yarn type */
     double n[3];       /* ply normal n_p */
     double t[3];       /* ply orientation t_p */
     double edge;       /* distance (cells) to the nearest classification edge */
+    double across;     /* across coordinate in [-1, 1] of the visible yarn */
+    double along;      /* along coordinate in [-1, 1) (0 for a lower or flat yarn) */
+    double run;        /* length (cells) of the float of a top yarn, 0 if flat */
+    double up, vp;     /* the point reduced to the pattern period */
 } orc_point;
 
 /* Geometry at surface point (us, vs), in cells; the macro normal is +z, u
@@ -226,6 +240,11 @@ static void point_geometry(const orc_material *m, double us, double vs, orc_poin
     if (j > m->wy - 1)
         j = m->wy - 1;
     double s = up - i, t = vp - j;
+    pt->up = up;
+    pt->vp = vp;
+    pt->across = 0.0;
+    pt->along = 0.0;
+    pt->run = 0.0;
 
     /* A yarn covers the band of its cell outside the gap; both bounds inclusive. */
     double half_w = 0.5 * (1.0 - m->gap[ORC_WARP]);
@@ -233,6 +252,7 @@ static void point_geometry(const orc_material *m, double us, double vs, orc_poin
     int cov_warp = fabs(s - 0.5) <= half_w;
     int cov_weft = fabs(t - 0.5) <= half_f;
     int warp_top = pat(m, i, j);
+    pt->top = warp_top ? ORC_WARP : ORC_WEFT;
 
     double e = s;
     if (1.0 - s < e) e = 1.0 - s;
@@ -266,9 +286,13 @@ static void point_geometry(const orc_material *m, double us, double vs, orc_poin
             ok = warp_run(m, i, j, &off, &len);
         else
             ok = weft_run(m, i, j, &off, &len);
-        if (ok)
+        if (ok) {
             along = 2.0 * (off + (y == ORC_WARP ? t : s)) / len - 1.0;
+            pt->run = len;
+        }
     }
+    pt->across = across;
+    pt->along = along;
 
     /* Height-field slopes: the float arches along the yarn with the
      * inclination angle, the cross-section bulges with at most THETA_MAX;
@@ -292,6 +316,133 @@ static void point_geometry(const orc_material *m, double us, double vs, orc_poin
     for (int k = 0; k < 3; k++)
         pt->t[k] = cp * t0[k] + sp * b[k];
 }
+
+/* ------------------------------------------------------------------------ */
+/* Height field and inter-yarn visibility V of Eq. (3)-(4)                   */
+/* ------------------------------------------------------------------------ */
+
+/* Depth (cells) of a yarn's cap: the drop of its cross-section from the
+ * crown (across = 0) to its edge (across = +-1). */
+static double cap_depth(const orc_material *m, int y)
+{
+    double half = 0.5 * (1.0 - m->gap[y]);
+    return m->beta[y] * half * (-log(cos(ORC_THETA_MAX))) / ORC_THETA_MAX;
+}
+
+/* Surface height (cells above the top yarns' crowns) at (us, vs): the
+ * integral of the slopes that define n_p, so that the height field's
+ * gradient is (-n_p.x, -n_p.y) / n_p.z.  Across a yarn the slope
+ * beta tan(theta_max x') over the half-width integrates to
+ * beta half / theta_max ln cos(theta_max x'); along a top yarn's float of
+ * length L the slope beta tan(u y') integrates to
+ * beta L / (2 u) ln cos(u y').  A lower yarn lies one cap depth of the top
+ * yarn lower (its crown level with the top yarn's edges); a hole lies below
+ * both caps. */
+double orc_surface_height(const orc_material *m, double us, double vs)
+{
+    orc_point pt;
+    point_geometry(m, us, vs, &pt);
+    int top = pt.top, low = 1 - pt.top;
+    if (pt.yarn == ORC_HOLE)
+        return -cap_depth(m, top) - cap_depth(m, low);
+    int y = pt.yarn;
+    double half = 0.5 * (1.0 - m->gap[y]);
+    double h = m->beta[y] * half / ORC_THETA_MAX * log(cos(ORC_THETA_MAX * pt.across));
+    if (pt.on_top) {
+        if (pt.run > 0.0)
+            h += m->beta[y] * pt.run / (2.0 * m->incl[y]) * log(cos(m->incl[y] * pt.along));
+    } else {
+        h -= cap_depth(m, top);
+    }
+    return h;
+}
+
+/* The tabulated height field: texel (a, b) of the period, a < wx R, b < wy R,
+ * holds the surface height at its centre rounded to float32.  Returns the
+ * largest texel. */
+float orc_height_table(const orc_material *m, float *table)
+{
+    int tw = m->wx * ORC_VIS_RES, th = m->wy * ORC_VIS_RES;
+    float hmax = -INFINITY;
+    for (int b = 0; b < th; b++)
+        for (int a = 0; a < tw; a++) {
+            float h = (float)orc_surface_height(m, (a + 0.5) / ORC_VIS_RES, (b + 0.5) / ORC_VIS_RES);
+            table[b * tw + a] = h;
+            if (h > hmax)
+                hmax = h;
+        }
+    return hmax;
+}
+
+static int texel_wrap(float q, int size)
+{
+    int k = (int)floorf(q * (float)ORC_VIS_RES) % size;
+    return k < 0 ? k + size : k;
+}
+
+/* V(x_p, w): 1 if a ray from the surface point toward w (w.z > 0) clears
+ * the height field.  The point's height is its texel's; the ray advances one
+ * texel (1/R cell) per step along the major horizontal axis of w and
+ * w_minor / |w_major| / R along the other, rising w.z / |w_major| / R, for
+ * up to ORC_VIS_STEPS steps (a fixed two-cell patch); it is blocked where
+ * the texel under it is higher than the ray, and free once the ray is above
+ * the highest texel.  The positions and ray heights are float32 arithmetic,
+ * one rounding per operation in the order written, so that every texel
+ * decision is that of float32 (up, vp: the point reduced to the period, as
+ * float32). */
+int orc_visible(const float *table, int tw, int th, float hmax, float up, float vp,
+                const double w[3])
+{
+    const float inv_r = 1.0f / (float)ORC_VIS_RES;
+    float wx = (float)w[0], wy = (float)w[1], wz = (float)w[2];
+    float ax = fabsf(wx), ay = fabsf(wy);
+    float major = ax >= ay ? ax : ay;
+    if (!(major > 0.0f))
+        return 1;
+    int a0 = texel_wrap(up, tw), b0 = texel_wrap(vp, th);
+    float h0 = table[b0 * tw + a0];
+    float du, dv;
+    if (ax >= ay) {
+        du = wx > 0.0f ? inv_r : -inv_r;
+        dv = (wy / ax) * inv_r;
+    } else {
+        dv = wy > 0.0f ? inv_r : -inv_r;
+        du = (wx / ay) * inv_r;
+    }
+    float rise = (wz / major) * inv_r;
+    for (int k = 1; k <= ORC_VIS_STEPS; k++) {
+        float fk = (float)k;
+        float prod = fk * rise;
+        float h = h0 + prod;
+        if (h >= hmax)
+            return 1;
+        float pu = fk * du, pv = fk * dv;
+        float qu = up + pu, qv = vp + pv;
+        if (table[texel_wrap(qv, th) * tw + texel_wrap(qu, tw)] > h)
+            return 0;
+    }
+    return 1;
+}
+
+/* V at (us, vs) for one material, building its table (test entry point). */
+int orc_visible_at(const orc_material *m, double us, double vs, const double w[3])
+{
+    int tw = m->wx * ORC_VIS_RES, th = m->wy * ORC_VIS_RES;
+    float *table = (float *)malloc(sizeof(float) * tw * th);
+    float hmax = orc_height_table(m, table);
+    orc_point pt;
+    point_geometry(m, us, vs, &pt);
+    int v = orc_visible(table, tw, th, hmax, (float)pt.up, (float)pt.vp, w);
+    free(table);
+    return v;
+}
+
+/* The height table of a material when visibility is on (NULL when off). */
+typedef struct {
+    const float *table;
+    int tw, th;
+    float hmax;
+} orc_vis;
 
 /* ------------------------------------------------------------------------ */
 /* Point shading model, Eq. (1)-(2)                                          */
@@ -407,14 +558,21 @@ typedef struct {
     double rho_s, rho_c, area;
 } orc_sample;
 
-static void eval_point(const orc_material *m, double us, double vs,
+static void eval_point(const orc_material *m, const orc_vis *vis, double us, double vs,
                        const double wi[3], const double wo[3], orc_sample *smp)
 {
     point_geometry(m, us, vs, &smp->geo);
+    /* V(x_p, wo) enters A(p, wo) (Eq. (4)), V(x_p, wi) the integrand (Eq. (3)). */
+    double v_o = 1.0, v_i = 1.0;
+    if (vis) {
+        float up = (float)smp->geo.up, vp = (float)smp->geo.vp;
+        v_o = orc_visible(vis->table, vis->tw, vis->th, vis->hmax, up, vp, wo);
+        v_i = orc_visible(vis->table, vis->tw, vis->th, vis->hmax, up, vp, wi);
+    }
     if (smp->geo.yarn == ORC_HOLE) {
         smp->rho_s = 0.0;
         smp->rho_c = 0.0;
-        smp->area = wo[2];
+        smp->area = wo[2] * v_o;
         return;
     }
     int y = smp->geo.yarn;
@@ -422,10 +580,10 @@ static void eval_point(const orc_material *m, double us, double vs,
     orc_point_brdf(m->alpha[y], m->wblend[y], smp->geo.n, smp->geo.t, wi, wo, f);
     double ci = dot3(wi, smp->geo.n), co = dot3(wo, smp->geo.n);
     double ci_pos = ci > 0.0 ? ci : 0.0;
-    smp->rho_s = f[0] * ci_pos;
-    smp->rho_c = f[1] * ci_pos;
-    /* <wo.n_p> / <n_s.n_p> with V = 1; 1/<n_s.n_p> is the Jacobian. */
-    smp->area = (co > 0.0 ? co : 0.0) / smp->geo.n[2];
+    smp->rho_s = f[0] * ci_pos * v_i;
+    smp->rho_c = f[1] * ci_pos * v_i;
+    /* <wo.n_p> / <n_s.n_p> V(x_p, wo); 1/<n_s.n_p> is the Jacobian. */
+    smp->area = (co > 0.0 ? co : 0.0) / smp->geo.n[2] * v_o;
 }
 
 /* out[0..15]: yarn, on_top, edge, rho_s, rho_c, area, n[3], t[3], spare. */
@@ -433,7 +591,7 @@ void orc_point_eval(const orc_material *m, double us, double vs,
                     const double wi[3], const double wo[3], double out[16])
 {
     orc_sample smp;
-    eval_point(m, us, vs, wi, wo, &smp);
+    eval_point(m, NULL, us, vs, wi, wo, &smp);
     memset(out, 0, 16 * sizeof(double));
     out[0] = smp.geo.yarn;
     out[1] = smp.geo.on_top;
@@ -468,10 +626,10 @@ void orc_point_eval_batch(const orc_material *m, int64_t n, const double *us, co
  * when sum A = 0.  With same_sample the sample uv is rounded to float32
  * before classification.  Returns the number of samples within
  * ORC_EDGE_EPS of a classification edge. */
-int orc_filter_pixel(const orc_material *m, double u, double v, double r,
-                     const double wi[3], const double wo[3], int n_samples,
-                     uint64_t seed, uint64_t pixel, int same_sample,
-                     double comp[4], double *area_sum)
+static int filter_pixel(const orc_material *m, const orc_vis *vis, double u, double v,
+                        double r, const double wi[3], const double wo[3], int n_samples,
+                        uint64_t seed, uint64_t pixel, int same_sample, double comp[4],
+                        double *area_sum)
 {
     int side = (int)llround(sqrt((double)n_samples));
     double num[4] = {0.0, 0.0, 0.0, 0.0}, den = 0.0;
@@ -489,7 +647,7 @@ int orc_filter_pixel(const orc_material *m, double u, double v, double r,
                 vs = (double)(float)vs;
             }
             orc_sample smp;
-            eval_point(m, us, vs, wi, wo, &smp);
+            eval_point(m, vis, us, vs, wi, wo, &smp);
             if (smp.geo.edge < ORC_EDGE_EPS)
                 flagged++;
             if (smp.geo.yarn != ORC_HOLE) {
@@ -504,6 +662,44 @@ int orc_filter_pixel(const orc_material *m, double u, double v, double r,
     if (area_sum)
         *area_sum = den;
     return flagged;
+}
+
+/* Height tables of n materials (visibility on), or NULL arrays (off). */
+static orc_vis *vis_tables(const orc_material *mats, int nmats, int visibility)
+{
+    if (!visibility)
+        return NULL;
+    orc_vis *vis = (orc_vis *)calloc(nmats, sizeof(orc_vis));
+    for (int k = 0; k < nmats; k++) {
+        vis[k].tw = mats[k].wx * ORC_VIS_RES;
+        vis[k].th = mats[k].wy * ORC_VIS_RES;
+        float *t = (float *)malloc(sizeof(float) * vis[k].tw * vis[k].th);
+        vis[k].hmax = orc_height_table(&mats[k], t);
+        vis[k].table = t;
+    }
+    return vis;
+}
+
+static void vis_free(orc_vis *vis, int nmats)
+{
+    if (!vis)
+        return;
+    for (int k = 0; k < nmats; k++)
+        free((void *)vis[k].table);
+    free(vis);
+}
+
+/* One pixel's filter; visibility != 0 includes V of Eq. (3)-(4). */
+int orc_filter_pixel(const orc_material *m, double u, double v, double r,
+                     const double wi[3], const double wo[3], int n_samples,
+                     uint64_t seed, uint64_t pixel, int same_sample, int visibility,
+                     double comp[4], double *area_sum)
+{
+    orc_vis *vis = vis_tables(m, 1, visibility);
+    int fl = filter_pixel(m, vis, u, v, r, wi, wo, n_samples, seed, pixel, same_sample, comp,
+                          area_sum);
+    vis_free(vis, 1);
+    return fl;
 }
 
 /* f_P = kd_warp C_warp + kd_weft C_weft + ks_warp S_warp + ks_weft S_weft (Eq. (8)). */
@@ -552,10 +748,11 @@ static void load_pixel(const orc_gbuffer *g, int64_t p, int *fid, double *u, dou
  * output may be NULL.  Returns the number of faulted pixels. */
 int64_t orc_filter_batch(const orc_material *mats, int nmats, const orc_gbuffer *g,
                          const int64_t *pixel_index, int n_samples, uint64_t seed,
-                         int same_sample, double *comp, double *rgb,
+                         int same_sample, int visibility, double *comp, double *rgb,
                          int32_t *flagged, int32_t *fault)
 {
     int64_t n = g->n, faults = 0;
+    orc_vis *vis = vis_tables(mats, nmats, visibility);
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : faults)
     for (int64_t p = 0; p < n; p++) {
         int fid;
@@ -565,8 +762,8 @@ int64_t orc_filter_batch(const orc_material *mats, int nmats, const orc_gbuffer 
         int fl = 0;
         if (!bad) {
             uint64_t key = pixel_index ? (uint64_t)pixel_index[p] : (uint64_t)p;
-            fl = orc_filter_pixel(&mats[fid], u, v, r, wi, wo, n_samples, seed, key,
-                                  same_sample, c4, NULL);
+            fl = filter_pixel(&mats[fid], vis ? &vis[fid] : NULL, u, v, r, wi, wo, n_samples,
+                              seed, key, same_sample, c4, NULL);
             compose_rgb(&mats[fid], c4, c3);
         }
         faults += bad;
@@ -581,6 +778,7 @@ int64_t orc_filter_batch(const orc_material *mats, int nmats, const orc_gbuffer 
         if (fault)
             fault[p] = bad;
     }
+    vis_free(vis, nmats);
     return faults;
 }
 

@@ -1,0 +1,151 @@
+"""Pins of the oracle's inter-yarn visibility V of Eq. (3)-(4) (stand-in
+height field and march): the height field's gradient reproduces the ply
+normals (the same slopes define both), a flat fabric occludes nothing and
+filters exactly as with V = 1, the zenith and the highest texel see
+everything, visibility only grows with elevation, a hole looking along the
+surface at a grazing angle is shadowed, periodicity, V only removes
+projected area, and an axis-aligned march against a direct scan of the
+table row."""
+import math
+
+import numpy as np
+
+import fabric_inputs as fi
+import oracle as orc
+
+
+def direction(elev, azim):
+    c = math.cos(elev)
+    return np.array([c * math.cos(azim), c * math.sin(azim), math.sin(elev)])
+
+
+def some_materials(seed=3):
+    rng = np.random.default_rng(seed)
+    mats = fi.materials_for(8, seed)
+    for m in mats:
+        m.beta[:] = rng.uniform(0.5, 2.0, 2).astype(np.float32)
+    return mats
+
+
+def test_height_gradient_matches_normals():
+    """dH/du = -n.x / n.z and dH/dv = -n.y / n.z at points away from yarn
+    edges and float ends (central differences, step 1e-6 cells)."""
+    rng = np.random.default_rng(11)
+    checked = 0
+    for m in some_materials():
+        for _ in range(200):
+            u, v = rng.uniform(0, m.wx), rng.uniform(0, m.wy)
+            p = orc.point_eval(m, u, v, [0, 0, 1], [0, 0, 1])
+            if p["yarn"] == 2 or p["edge"] < 1e-3:
+                continue
+            h = 1e-6
+            du = (orc.surface_height(m, u + h, v) - orc.surface_height(m, u - h, v)) / (2 * h)
+            dv = (orc.surface_height(m, u, v + h) - orc.surface_height(m, u, v - h)) / (2 * h)
+            n = p["n"]
+            assert abs(du + n[0] / n[2]) < 1e-6 * (1 + abs(du)), (u, v, du, n)
+            assert abs(dv + n[1] / n[2]) < 1e-6 * (1 + abs(dv)), (u, v, dv, n)
+            checked += 1
+    assert checked > 500
+
+
+def test_flat_fabric_sees_everything():
+    mats = fi.materials_for(8, 12)
+    rng = np.random.default_rng(12)
+    for m in mats:
+        m.beta[:] = 0.0
+        t, hmax = orc.height_table(m)
+        assert not t.any() and hmax == 0.0
+        for _ in range(50):
+            w = direction(rng.uniform(0.01, 1.5), rng.uniform(0, 2 * math.pi))
+            assert orc.visible(m, rng.uniform(0, 8), rng.uniform(0, 8), w) == 1
+    # The filter with V is the filter with V = 1, bit for bit.
+    g = fi.make_gbuffer(16, 8, 8, seed=13)
+    a = orc.filter_gbuffer(mats, g, 64, 14, visibility=False)[0]
+    b = orc.filter_gbuffer(mats, g, 64, 14, visibility=True)[0]
+    assert np.array_equal(a, b)
+
+
+def test_zenith_and_highest_texel_see_everything():
+    rng = np.random.default_rng(15)
+    for m in some_materials(16):
+        for _ in range(30):
+            assert orc.visible(m, rng.uniform(0, 8), rng.uniform(0, 8), [0.0, 0.0, 1.0]) == 1
+        t, hmax = orc.height_table(m)
+        b, a = np.unravel_index(int(np.argmax(t)), t.shape)
+        uc, vc = (a + 0.5) / 16, (b + 0.5) / 16
+        for _ in range(100):
+            w = direction(rng.uniform(0.005, 1.5), rng.uniform(0, 2 * math.pi))
+            assert orc.visible(m, uc, vc, w) == 1
+
+
+def test_visibility_grows_with_elevation():
+    rng = np.random.default_rng(17)
+    elevs = np.radians([1, 3, 6, 10, 20, 35, 60, 85])
+    blocked_low = 0
+    for m in some_materials(18):
+        for _ in range(60):
+            u, v, az = rng.uniform(0, 8), rng.uniform(0, 8), rng.uniform(0, 2 * math.pi)
+            vis = [orc.visible(m, u, v, direction(e, az)) for e in elevs]
+            assert all(a <= b for a, b in zip(vis, vis[1:])), vis
+            blocked_low += 1 - vis[0]
+    assert blocked_low > 0      # grazing rays are blocked somewhere
+
+
+def test_hole_shadowed_at_grazing_angle():
+    """Plain weave, wide gaps, tall yarns: from the hole at a cell corner a ray
+    along +u at 2 degrees runs into the next yarn; steeply up it is free."""
+    m = fi.uniform_material(fi.pattern_plain(), beta=2.0, gap=0.3)
+    p = orc.point_eval(m, 0.02, 0.02, [0, 0, 1], [0, 0, 1])
+    assert p["yarn"] == 2
+    assert orc.visible(m, 0.02, 0.02, direction(math.radians(2), 0.0)) == 0
+    assert orc.visible(m, 0.02, 0.02, direction(math.radians(80), 0.0)) == 1
+
+
+def test_periodic():
+    rng = np.random.default_rng(19)
+    for m in some_materials(20):
+        for _ in range(40):
+            u, v = rng.uniform(0, m.wx), rng.uniform(0, m.wy)
+            w = direction(rng.uniform(0.02, 0.6), rng.uniform(0, 2 * math.pi))
+            assert orc.visible(m, u, v, w) == orc.visible(m, u + 3 * m.wx, v - 2 * m.wy, w)
+
+
+def test_visibility_only_removes_area():
+    """Same samples with and without V: the visible projected area sum never
+    grows (V <= 1 multiplies each sample's A(p, wo))."""
+    mats = some_materials(21)
+    rng = np.random.default_rng(22)
+    for k in range(40):
+        m = mats[k % len(mats)]
+        wi = direction(rng.uniform(0.05, 1.5), rng.uniform(0, 6.3))
+        wo = direction(rng.uniform(0.05, 1.5), rng.uniform(0, 6.3))
+        args = (m, rng.uniform(0, 8), rng.uniform(0, 8), rng.uniform(0.05, 1.0), wi, wo, 64, 23, k)
+        _, a0, _ = orc.filter_pixel(*args, visibility=False)
+        c1, a1, _ = orc.filter_pixel(*args, visibility=True)
+        assert a1 <= a0 + 1e-12
+        assert np.all(np.isfinite(c1)) and np.all(c1 >= 0)
+
+
+def test_axis_aligned_march_scans_the_row():
+    """For w in the x-z plane the march visits the texels of the point's row
+    one by one: compare with a scan of that row of the table."""
+    rng = np.random.default_rng(24)
+    f32 = np.float32
+    for m in some_materials(25):
+        t, hmax = orc.height_table(m)
+        th, tw = t.shape
+        for _ in range(40):
+            u, v = rng.uniform(0, m.wx), rng.uniform(0, m.wy)
+            e = rng.uniform(0.01, 0.5)
+            w = np.array([math.cos(e), 0.0, math.sin(e)])
+            a0, b0 = int(math.floor(f32(u) * 16)) % tw, int(math.floor(f32(v) * 16)) % th
+            rise = f32(f32(f32(w[2]) / f32(w[0])) * f32(1 / 16))
+            want = 1
+            for k in range(1, 33):
+                h = f32(t[b0, a0] + f32(f32(k) * rise))
+                if h >= hmax:
+                    break
+                if t[b0, (a0 + k) % tw] > h:
+                    want = 0
+                    break
+            assert orc.visible(m, u, v, w) == want
