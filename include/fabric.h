@@ -148,6 +148,23 @@ fabric_status fabric_encode(fabric_ctx *ctx, const fabric_material *mats, int32_
 fabric_status fabric_set_albedo(fabric_ctx *ctx, int32_t fabric, const float kd[2][3],
                                 const float ks[2][3], void *stream);
 
+/* Inter-yarn shadowing and masking in the analytic model: the binary
+ * visibility V(x_p, w) of Eq. (3) (toward wi, on the integrand) and Eq. (4)
+ * (toward wo, on the projected area A and so on the normaliser A_P of
+ * Eq. (5)).  enable = 0 (the default): V = 1.  enable = 1: V is the march of
+ * a ray over the fabric's height field, whose gradient is the one the ply
+ * normals n_p are built from (cross sections and floats integrated from
+ * their slopes, lower yarns one cap depth below the top yarns, holes below
+ * both), tabulated at 16 x 16 texels per cell in float32; the ray leaves the
+ * centre of the point's texel at the texel's height, steps one texel along
+ * the major horizontal axis of w per step for up to 32 steps (two cells),
+ * and is blocked by a higher texel.  Applies to fabric_gt_filtered, to the
+ * fallback pixels of fabric_shade_gbuffer and to targets that
+ * fabric_train_step / fabric_loss_grad generate; the decoder is unchanged.
+ * The texels are built on the host (FP64, rounded to float32) at the first
+ * such call after fabric_encode.  Errors: E_INVAL for enable not 0 or 1. */
+fabric_status fabric_set_visibility(fabric_ctx *ctx, int32_t enable);
+
 /* Latent interpolation and extrapolation (Sec. 5 "Interpolation"): the
  * encoder's latents form a space in which a material between two encoded
  * ones is approximated by the weighted blend of their latents, the weight

@@ -61,6 +61,10 @@
 #define ORC_LAMBDA_C 0.1
 /* A footprint sample this close (cells) to a classification edge is flagged. */
 #define ORC_EDGE_EPS 1e-5
+/* With visibility, a sample this close (cells) to a texel boundary is
+ * flagged: float32 positions computed in another order may pick the
+ * neighbouring texel as the ray's start. */
+#define ORC_TEXEL_EPS 4e-6
 /* Visibility: height-field texels per cell and axis, and march length in
  * texel steps along the direction's major horizontal axis (two cells). */
 #define ORC_VIS_RES 16
@@ -349,7 +353,8 @@ double orc_surface_height(const orc_material *m, double us, double vs)
     double half = 0.5 * (1.0 - m->gap[y]);
     double h = m->beta[y] * half / ORC_THETA_MAX * log(cos(ORC_THETA_MAX * pt.across));
     if (pt.on_top) {
-        if (pt.run > 0.0)
+        /* At zero inclination the float is flat: its term's limit is 0. */
+        if (pt.run > 0.0 && m->incl[y] != 0.0)
             h += m->beta[y] * pt.run / (2.0 * m->incl[y]) * log(cos(m->incl[y] * pt.along));
     } else {
         h -= cap_depth(m, top);
@@ -381,15 +386,15 @@ static int texel_wrap(float q, int size)
 }
 
 /* V(x_p, w): 1 if a ray from the surface point toward w (w.z > 0) clears
- * the height field.  The point's height is its texel's; the ray advances one
- * texel (1/R cell) per step along the major horizontal axis of w and
- * w_minor / |w_major| / R along the other, rising w.z / |w_major| / R, for
- * up to ORC_VIS_STEPS steps (a fixed two-cell patch); it is blocked where
- * the texel under it is higher than the ray, and free once the ray is above
- * the highest texel.  The positions and ray heights are float32 arithmetic,
- * one rounding per operation in the order written, so that every texel
- * decision is that of float32 (up, vp: the point reduced to the period, as
- * float32). */
+ * the height field.  The ray leaves the centre of the point's texel at that
+ * texel's height and advances one texel (1/R cell) per step along the major
+ * horizontal axis of w and w_minor / |w_major| / R along the other, rising
+ * w.z / |w_major| / R, for up to ORC_VIS_STEPS steps (a fixed two-cell
+ * patch); it is blocked where the texel under it is higher than the ray,
+ * and free once the ray is above the highest texel.  The positions and ray
+ * heights are float32 arithmetic, one rounding per operation in the order
+ * written, so that every texel decision is that of float32 (up, vp: the
+ * point reduced to the period, as float32). */
 int orc_visible(const float *table, int tw, int th, float hmax, float up, float vp,
                 const double w[3])
 {
@@ -401,6 +406,7 @@ int orc_visible(const float *table, int tw, int th, float hmax, float up, float 
         return 1;
     int a0 = texel_wrap(up, tw), b0 = texel_wrap(vp, th);
     float h0 = table[b0 * tw + a0];
+    float cu = ((float)a0 + 0.5f) * inv_r, cv = ((float)b0 + 0.5f) * inv_r;
     float du, dv;
     if (ax >= ay) {
         du = wx > 0.0f ? inv_r : -inv_r;
@@ -417,7 +423,7 @@ int orc_visible(const float *table, int tw, int th, float hmax, float up, float 
         if (h >= hmax)
             return 1;
         float pu = fk * du, pv = fk * dv;
-        float qu = up + pu, qv = vp + pv;
+        float qu = cu + pu, qv = cv + pv;
         if (table[texel_wrap(qv, th) * tw + texel_wrap(qu, tw)] > h)
             return 0;
     }
@@ -648,8 +654,15 @@ static int filter_pixel(const orc_material *m, const orc_vis *vis, double u, dou
             }
             orc_sample smp;
             eval_point(m, vis, us, vs, wi, wo, &smp);
-            if (smp.geo.edge < ORC_EDGE_EPS)
-                flagged++;
+            int flag = smp.geo.edge < ORC_EDGE_EPS;
+            if (vis) {
+                double fu = smp.geo.up * ORC_VIS_RES, fv = smp.geo.vp * ORC_VIS_RES;
+                double du = fu - floor(fu), dv = fv - floor(fv);
+                if (fmin(du, 1.0 - du) < ORC_TEXEL_EPS * ORC_VIS_RES ||
+                    fmin(dv, 1.0 - dv) < ORC_TEXEL_EPS * ORC_VIS_RES)
+                    flag = 1;
+            }
+            flagged += flag;
             if (smp.geo.yarn != ORC_HOLE) {
                 num[smp.geo.yarn] += smp.rho_c * smp.area;       /* C_warp, C_weft */
                 num[2 + smp.geo.yarn] += smp.rho_s * smp.area;   /* S_warp, S_weft */

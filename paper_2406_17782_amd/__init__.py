@@ -24,6 +24,7 @@ __all__ = [
     "FABRIC_FP8_E4M3", "FABRIC_N_PARAMS", "FABRIC_N_DECODER_PARAMS", "FABRIC_N_ENCODER_PARAMS",
     "FABRIC_MAX_FABRICS", "FABRIC_MAX_SAMPLES", "FABRIC_LATENT",
     "fabric_create", "fabric_destroy", "fabric_encode", "fabric_set_albedo", "fabric_lerp_latents",
+    "fabric_set_visibility",
     "fabric_shade_gbuffer", "fabric_gt_filtered", "fabric_decoder_forward",
     "fabric_decoder_backward", "fabric_encoder_forward", "fabric_encoder_backward",
     "fabric_make_batch", "fabric_loss_grad", "fabric_train_step", "fabric_get_params", "fabric_set_params",
@@ -135,6 +136,10 @@ def fabric_set_albedo(ctx, fabric: int, kd, ks, stream=None) -> None:
     ks = np.ascontiguousarray(ks, dtype=np.float32).reshape(2, 3)
     check(_abi.lib().fabric_set_albedo(ctx, fabric, kd.ctypes.data, ks.ctypes.data, _stream(stream)),
           "fabric_set_albedo")
+
+
+def fabric_set_visibility(ctx, enable: bool) -> None:
+    check(_abi.lib().fabric_set_visibility(ctx, int(bool(enable))), "fabric_set_visibility")
 
 
 def fabric_lerp_latents(ctx, dst, a, b, t, stream=None) -> None:
@@ -318,6 +323,11 @@ class Fabric:
 
     def latents(self) -> np.ndarray:
         return fabric_get_latents(self.ctx, self.n_mats)
+
+    def set_visibility(self, enable: bool) -> None:
+        """Inter-yarn visibility V in the analytic filter (targets, ground
+        truth, fallback); off by default."""
+        fabric_set_visibility(self.ctx, enable)
 
     def lerp_latents(self, dst, a, b, t, stream=None) -> None:
         """z[dst[k]] = (1 - t[k]) z[a[k]] + t[k] z[b[k]] on the device (latent

@@ -61,7 +61,7 @@ class fabric_train_cfg(ctypes.Structure):
 
 EXPORTS = [
     "fabric_create", "fabric_destroy", "fabric_status_str", "fabric_encode", "fabric_set_albedo",
-    "fabric_lerp_latents",
+    "fabric_lerp_latents", "fabric_set_visibility",
     "fabric_shade_gbuffer", "fabric_gt_filtered", "fabric_decoder_forward",
     "fabric_decoder_backward", "fabric_encoder_forward", "fabric_encoder_backward",
     "fabric_make_batch", "fabric_loss_grad", "fabric_train_step", "fabric_get_params", "fabric_set_params",
@@ -85,6 +85,8 @@ def _declare(L):
     L.fabric_set_albedo.restype = _S
     L.fabric_lerp_latents.argtypes = [_P, _P, _P, _P, _P, ctypes.c_int32, _P]
     L.fabric_lerp_latents.restype = _S
+    L.fabric_set_visibility.argtypes = [_P, ctypes.c_int32]
+    L.fabric_set_visibility.restype = _S
     L.fabric_shade_gbuffer.argtypes = [_P, ctypes.POINTER(fabric_gbuffer), ctypes.c_int,
                                        ctypes.c_int32, ctypes.c_uint64, _P, _P]
     L.fabric_shade_gbuffer.restype = _S

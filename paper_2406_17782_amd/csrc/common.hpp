@@ -68,6 +68,22 @@ struct alignas(16) DevFabric {
     uint16_t cell[256];
 };
 
+// Inter-yarn visibility (V of Eq. (3)-(4)): per fabric, the tabulated height
+// field of one pattern period, kVisRes texels per cell and axis, row-major
+// (tw = wx kVisRes columns, th = wy kVisRes rows) at texel offset `off` of
+// the shared table, and its largest texel.
+constexpr int kVisRes = 16;
+constexpr int kVisSteps = 32;   // march length in texel steps: two cells
+struct VisFabric {
+    int32_t off, tw, th;
+    float hmax;
+};
+// tex == nullptr: V = 1 everywhere.
+struct VisArgs {
+    const float *tex;
+    const VisFabric *fab;
+};
+
 // ---------------------------------------------------------------------------
 // MFMA operand traits.  All variants are 16 x 16 output tiles in the
 // "transposed" orientation: M = output neurons, N = 16 pixels, K = inputs.

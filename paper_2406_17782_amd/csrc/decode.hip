@@ -488,8 +488,8 @@ hipError_t launch_pack_shade(int prec, const float *dec_params, void *image, hip
 
 hipError_t launch_decode(int prec, bool raw, const fabric_gbuffer &g, const DevFabric *fabrics,
                          int n_fabrics, const float *cfold, const void *image,
-                         int fallback_samples, uint64_t seed, FallbackQueue q, float *out,
-                         unsigned long long *err, hipStream_t stream)
+                         int fallback_samples, uint64_t seed, VisArgs vis, FallbackQueue q,
+                         float *out, unsigned long long *err, hipStream_t stream)
 {
     if (g.n == 0)
         return hipSuccess;
@@ -518,7 +518,7 @@ hipError_t launch_decode(int prec, bool raw, const fabric_gbuffer &g, const DevF
         return e;
     if ((e = launch_queue_build(q, g.n, stream)) != hipSuccess)
         return e;
-    return launch_gt_filter_queue(g, fabrics, fallback_samples, seed, q, out, stream);
+    return launch_gt_filter_queue(g, fabrics, fallback_samples, seed, vis, q, out, stream);
 }
 
 }  // namespace fab

@@ -2,6 +2,7 @@
 // lifetime, argument validation, host-side fabric tables and the launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -28,6 +29,12 @@ struct fabric_ctx {
     float *latents = nullptr;         // [FABRIC_MAX_FABRICS][32]
     float *cfold = nullptr;           // [FABRIC_MAX_FABRICS][64]
     LatentLerp *lerp_jobs = nullptr;  // [FABRIC_MAX_FABRICS]
+    bool visibility = false;          // V of Eq. (3)-(4) in the analytic filter
+    uint64_t table_serial = 0;        // bumped when the fabric table's geometry changes
+    uint64_t vis_serial = 0;          // table_serial of the built height texels
+    float *vis_tex = nullptr;         // height texels of every fabric
+    size_t vis_cap = 0;               // texels allocated
+    VisFabric *vis_fab = nullptr;     // [FABRIC_MAX_FABRICS]
     uint64_t encoded_version = 0;     // weights_version of the last encode
     uint64_t encode_serial = 0;       // bumped on every change of latents or fabric table
 
@@ -271,6 +278,111 @@ fabric_status ensure_image(fabric_ctx *ctx, int prec, hipStream_t stream)
 
 // Room for the out-of-range masks, offsets and pixel indices of an n-pixel
 // hybrid frame.
+// Height of the fabric surface at a point of its period (cells; Eq. (3)-(4)
+// visibility).  The slopes that define n_p integrate to
+//   across a yarn:    beta half / theta_max  ln cos(theta_max x')
+//   along a top float: beta L / (2 incl)     ln cos(incl y')
+// with the float's length L in cells; a lower yarn lies one cap depth of the
+// cell's top yarn lower (cap: the drop from a yarn's crown to its edge,
+// beta half ln(1 / cos theta_max) / theta_max); a hole lies below both caps.
+// FP64, each product and quotient taken left to right as written, so that
+// the texels rounded to float32 are reproducible.
+double surface_height(const fabric_material &m, const uint16_t cell[256], double up, double vp)
+{
+    const double theta = M_PI / 3.0;
+    const int i = std::min((int)std::floor(up), m.wx - 1);
+    const int j = std::min((int)std::floor(vp), m.wy - 1);
+    const double s = up - i, t = vp - j;
+    double half[2], cap[2];
+    for (int y = 0; y < 2; y++) {
+        half[y] = 0.5 * (1.0 - (double)m.gap[y]);
+        cap[y] = (double)m.beta[y] * half[y] * (-std::log(std::cos(theta))) / theta;
+    }
+    const bool cov_warp = std::fabs(s - 0.5) <= half[0];
+    const bool cov_weft = std::fabs(t - 0.5) <= half[1];
+    const uint16_t c = cell[j * 16 + i];
+    const int top = (c >> 15) ? 0 : 1;   // 0 warp, 1 weft
+    int yarn;
+    if (top == 0)
+        yarn = cov_warp ? 0 : (cov_weft ? 1 : 2);
+    else
+        yarn = cov_weft ? 1 : (cov_warp ? 0 : 2);
+    if (yarn == 2)
+        return -cap[top] - cap[1 - top];
+    const double across = ((yarn == 0 ? s : t) - 0.5) / half[yarn];
+    double h = (double)m.beta[yarn] * half[yarn] / theta * std::log(std::cos(theta * across));
+    if (yarn == top) {
+        const int len = (c >> 5) & 31, off = c & 31;
+        const double incl = (double)m.incl[yarn];
+        // A zero inclination leaves the float flat (its limit term is 0).
+        if (len > 0 && incl != 0.0) {
+            const double along = 2.0 * (off + (yarn == 0 ? t : s)) / len - 1.0;
+            h += (double)m.beta[yarn] * (double)len / (2.0 * incl) * std::log(std::cos(incl * along));
+        }
+    } else {
+        h -= cap[top];
+    }
+    return h;
+}
+
+// Height texels of every encoded fabric (kVisRes per cell and axis, the
+// height at each texel's centre rounded to float32), uploaded when the
+// fabric table changed since the last build.  Returns the arguments of the
+// filter launches: V = 1 when visibility is off.
+fabric_status ensure_vis(fabric_ctx *ctx, hipStream_t s, VisArgs *out)
+{
+    *out = VisArgs{nullptr, nullptr};
+    if (!ctx->visibility)
+        return FABRIC_OK;
+    if (ctx->vis_serial != ctx->table_serial || !ctx->vis_tex) {
+        std::vector<VisFabric> info(ctx->n_mats);
+        size_t total = 0;
+        for (int k = 0; k < ctx->n_mats; k++) {
+            const fabric_material &m = ctx->mats[k];
+            info[k].off = (int32_t)total;
+            info[k].tw = m.wx * kVisRes;
+            info[k].th = m.wy * kVisRes;
+            total += (size_t)info[k].tw * info[k].th;
+        }
+        std::vector<float> tex(total);
+        for (int k = 0; k < ctx->n_mats; k++) {
+            const fabric_material &m = ctx->mats[k];
+            uint16_t cell[256];
+            cell_table(m, cell);
+            float hmax = -INFINITY;
+            for (int b = 0; b < info[k].th; b++)
+                for (int a = 0; a < info[k].tw; a++) {
+                    const float h = (float)surface_height(m, cell, (a + 0.5) / kVisRes,
+                                                          (b + 0.5) / kVisRes);
+                    tex[info[k].off + (size_t)b * info[k].tw + a] = h;
+                    hmax = std::max(hmax, h);
+                }
+            info[k].hmax = hmax;
+        }
+        if (ctx->vis_cap < total) {
+            (void)hipFree(ctx->vis_tex);
+            ctx->vis_tex = nullptr;
+            ctx->vis_cap = 0;
+            fabric_status st = dalloc(&ctx->vis_tex, total);
+            if (st != FABRIC_OK)
+                return st;
+            ctx->vis_cap = total;
+        }
+        fabric_status st = from_hip(hipMemcpyAsync(ctx->vis_tex, tex.data(), total * sizeof(float),
+                                                   hipMemcpyHostToDevice, s));
+        if (st == FABRIC_OK)
+            st = from_hip(hipMemcpyAsync(ctx->vis_fab, info.data(), info.size() * sizeof(VisFabric),
+                                         hipMemcpyHostToDevice, s));
+        // The host staging vectors must outlive the copies.
+        if (st == FABRIC_OK) st = from_hip(hipStreamSynchronize(s));
+        if (st != FABRIC_OK)
+            return st;
+        ctx->vis_serial = ctx->table_serial;
+    }
+    *out = VisArgs{ctx->vis_tex, ctx->vis_fab};
+    return FABRIC_OK;
+}
+
 fabric_status ensure_queue(fabric_ctx *ctx, int64_t n)
 {
     if (!ctx->queue_count) {
@@ -334,6 +446,8 @@ void fabric_destroy(fabric_ctx *ctx)
     (void)hipFree(ctx->latents);
     (void)hipFree(ctx->cfold);
     (void)hipFree(ctx->lerp_jobs);
+    (void)hipFree(ctx->vis_tex);
+    (void)hipFree(ctx->vis_fab);
     for (int k = 0; k < 4; k++)
         (void)hipFree(ctx->image[k]);
     (void)hipFree(ctx->tmp_image);
@@ -373,6 +487,7 @@ fabric_status fabric_create(fabric_ctx **out, int device, uint64_t seed)
     if (st == FABRIC_OK) st = dalloc(&ctx->cfold, F * 64);
     if (st == FABRIC_OK) st = dalloc(&ctx->tmp_cfold, F * 64);
     if (st == FABRIC_OK) st = dalloc(&ctx->lerp_jobs, F);
+    if (st == FABRIC_OK) st = dalloc(&ctx->vis_fab, F);
     if (st == FABRIC_OK) st = dalloc(&ctx->err, 1);
     if (st == FABRIC_OK) {
         const size_t img = decoder_image_bytes(FABRIC_FP32);   // the largest image
@@ -429,6 +544,7 @@ fabric_status fabric_encode(fabric_ctx *ctx, const fabric_material *mats, int32_
     ctx->n_mats = n_mats;
     ctx->encoded_version = ctx->weights_version;
     ctx->encode_serial += 1;
+    ctx->table_serial += 1;
     return FABRIC_OK;
 }
 
@@ -456,6 +572,14 @@ fabric_status fabric_set_albedo(fabric_ctx *ctx, int32_t fabric, const float kd[
     if (st == FABRIC_OK)
         st = from_hip(hipStreamSynchronize(s));
     return st;
+}
+
+fabric_status fabric_set_visibility(fabric_ctx *ctx, int32_t enable)
+{
+    if (!ctx || (enable != 0 && enable != 1))
+        return FABRIC_E_INVAL;
+    ctx->visibility = enable != 0;
+    return FABRIC_OK;
 }
 
 fabric_status fabric_lerp_latents(fabric_ctx *ctx, const int32_t *dst, const int32_t *a,
@@ -515,13 +639,17 @@ fabric_status fabric_shade_gbuffer(fabric_ctx *ctx, const fabric_gbuffer *g, fab
     DeviceGuard guard(ctx->device);
     hipStream_t s = as_stream(stream);
     fabric_status st = ensure_image(ctx, prec, s);
+    VisArgs vis{nullptr, nullptr};
     if (st == FABRIC_OK && fallback_samples > 0)
         st = ensure_queue(ctx, g->n);
+    if (st == FABRIC_OK && fallback_samples > 0)
+        st = ensure_vis(ctx, s, &vis);
     if (st != FABRIC_OK)
         return st;
     const FallbackQueue q{ctx->queue_mask, ctx->queue_offsets, ctx->queue_count, ctx->queue_idx};
     return from_hip(launch_decode(prec, false, *g, ctx->fabrics, ctx->n_mats, ctx->cfold,
-                                  ctx->image[prec], fallback_samples, seed, q, out_rgb, ctx->err, s));
+                                  ctx->image[prec], fallback_samples, seed, vis, q, out_rgb,
+                                  ctx->err, s));
 }
 
 fabric_status fabric_gt_filtered(fabric_ctx *ctx, const fabric_gbuffer *g, int32_t n_samples,
@@ -534,8 +662,13 @@ fabric_status fabric_gt_filtered(fabric_ctx *ctx, const fabric_gbuffer *g, int32
     if (g->n == 0)
         return FABRIC_OK;
     DeviceGuard guard(ctx->device);
-    return from_hip(launch_gt_filter(*g, ctx->fabrics, ctx->n_mats, n_samples, seed, out_rgb,
-                                     out_comp, ctx->err, as_stream(stream)));
+    hipStream_t s = as_stream(stream);
+    VisArgs vis;
+    fabric_status st = ensure_vis(ctx, s, &vis);
+    if (st != FABRIC_OK)
+        return st;
+    return from_hip(launch_gt_filter(*g, ctx->fabrics, ctx->n_mats, n_samples, seed, vis, out_rgb,
+                                     out_comp, ctx->err, s));
 }
 
 fabric_status fabric_decoder_forward(fabric_ctx *ctx, const fabric_gbuffer *g, fabric_prec prec,
@@ -557,7 +690,8 @@ fabric_status fabric_decoder_forward(fabric_ctx *ctx, const fabric_gbuffer *g, f
         st = from_hip(launch_fold_latents(dec_params, latents, ctx->n_mats, ctx->tmp_cfold, s));
     if (st == FABRIC_OK)
         st = from_hip(launch_decode(prec, true, *g, ctx->fabrics, ctx->n_mats, ctx->tmp_cfold,
-                                    ctx->tmp_image, 0, 0, FallbackQueue{nullptr, nullptr, nullptr, nullptr}, y4,
+                                    ctx->tmp_image, 0, 0, VisArgs{nullptr, nullptr},
+                                    FallbackQueue{nullptr, nullptr, nullptr, nullptr}, y4,
                                     ctx->err, s));
     // The next shade must repack: tmp buffers are separate, so nothing else is stale.
     return st;
@@ -660,6 +794,7 @@ TrainArgs train_args(fabric_ctx *ctx, const fabric_gbuffer *batch, const float *
     a.targets = targets;
     a.cfg = *cfg;
     a.err = ctx->err;
+    a.vis = VisArgs{nullptr, nullptr};
     return a;
 }
 }  // namespace
@@ -675,6 +810,8 @@ fabric_status fabric_loss_grad(fabric_ctx *ctx, const fabric_gbuffer *batch, con
         return FABRIC_E_INVAL;
     DeviceGuard guard(ctx->device);
     TrainArgs a = train_args(ctx, batch, targets, cfg);
+    if (!targets && (st = ensure_vis(ctx, as_stream(stream), &a.vis)) != FABRIC_OK)
+        return st;
     return from_hip(loss_grad(ctx->train, a, grad, out_loss, as_stream(stream)));
 }
 
@@ -686,6 +823,8 @@ fabric_status fabric_train_step(fabric_ctx *ctx, const fabric_gbuffer *batch, co
         return st;
     DeviceGuard guard(ctx->device);
     TrainArgs a = train_args(ctx, batch, targets, cfg);
+    if (!targets && (st = ensure_vis(ctx, as_stream(stream), &a.vis)) != FABRIC_OK)
+        return st;
     int updated = 0;
     hipError_t e = train_step(ctx->train, a, out_loss, &updated, as_stream(stream));
     if (e != hipSuccess)

@@ -1,5 +1,6 @@
-// Footprint-filtered analytic shading on VALU (Eq. (3)-(5) with V = 1,
-// components of Eq. (7), albedo composition of Eq. (8)).  One wavefront owns
+// Footprint-filtered analytic shading on VALU (Eq. (3)-(5), with V = 1 or
+// the inter-yarn visibility march of the height field, components of
+// Eq. (7), albedo composition of Eq. (8)).  One wavefront owns
 // one pixel: its 64 lanes take the pixel's footprint sub-samples (lane,
 // lane + 64, ...), accumulate the five sums in FP64 and reduce them with a
 // fixed butterfly of wavefront shuffles.
@@ -16,9 +17,10 @@ constexpr int kXcds = 8;
 
 // Pixel p by the wave: the filter's components and Eq. (8) composition,
 // written by lane 0 (faulty inputs: zeros and one count).
+template <bool VIS>
 __device__ inline void filter_one_pixel(const fabric_gbuffer &g, const DevFabric *__restrict__ fabrics,
                                         int n_fabrics, int64_t p, int n_samples, int side,
-                                        float inv_side, uint64_t seed, int lane,
+                                        float inv_side, uint64_t seed, int lane, VisArgs vis,
                                         float *__restrict__ out_rgb, float *__restrict__ out_comp,
                                         unsigned long long *err)
 {
@@ -29,9 +31,11 @@ __device__ inline void filter_one_pixel(const fabric_gbuffer &g, const DevFabric
     const bool fault = pixel_fault(fid, n_fabrics, u, v, r, wi, wo);
 
     double comp[4] = {0.0, 0.0, 0.0, 0.0};
-    if (!fault)
-        filter_pixel_wave(fabrics[fid], seed, (uint64_t)p, n_samples, side, inv_side, u, v, r,
-                          wi, wo, lane, comp);
+    if (!fault) {
+        const VisFabric vf = VIS ? vis.fab[fid] : VisFabric{0, 0, 0, 0.0f};
+        filter_pixel_wave<VIS>(fabrics[fid], seed, (uint64_t)p, n_samples, side, inv_side, u, v,
+                               r, wi, wo, lane, vis.tex, vf, comp);
+    }
     if (lane == 0) {
         const int64_t n = g.n;
         if (fault && err)
@@ -51,10 +55,11 @@ __device__ inline void filter_one_pixel(const fabric_gbuffer &g, const DevFabric
     }
 }
 
+template <bool VIS>
 __global__ __launch_bounds__(256) void gt_filter_kernel(fabric_gbuffer g,
                                                         const DevFabric *__restrict__ fabrics,
                                                         int n_fabrics, int n_samples, int side,
-                                                        float inv_side, uint64_t seed,
+                                                        float inv_side, uint64_t seed, VisArgs vis,
                                                         float *__restrict__ out_rgb,
                                                         float *__restrict__ out_comp,
                                                         unsigned long long *err)
@@ -70,8 +75,8 @@ __global__ __launch_bounds__(256) void gt_filter_kernel(fabric_gbuffer g,
     const int64_t p = (int64_t)block * kWavesPerBlock + wave;
     if (p >= g.n)
         return;
-    filter_one_pixel(g, fabrics, n_fabrics, p, n_samples, side, inv_side, seed, lane, out_rgb,
-                     out_comp, err);
+    filter_one_pixel<VIS>(g, fabrics, n_fabrics, p, n_samples, side, inv_side, seed, lane, vis,
+                          out_rgb, out_comp, err);
 }
 
 // The queued pixels of a hybrid shading launch (all valid and in range of
@@ -79,11 +84,12 @@ __global__ __launch_bounds__(256) void gt_filter_kernel(fabric_gbuffer g,
 // like gt_filter_kernel; the grid covers every pixel of the frame and the
 // waves past the queue's length exit at once (the length is only known on
 // the device).
+template <bool VIS>
 __global__ __launch_bounds__(256) void gt_filter_queue_kernel(fabric_gbuffer g,
                                                               const DevFabric *__restrict__ fabrics,
                                                               int n_samples, int side,
                                                               float inv_side, uint64_t seed,
-                                                              FallbackQueue q,
+                                                              VisArgs vis, FallbackQueue q,
                                                               float *__restrict__ out_rgb)
 {
     const int lane = threadIdx.x & 63;
@@ -92,8 +98,8 @@ __global__ __launch_bounds__(256) void gt_filter_queue_kernel(fabric_gbuffer g,
     if (k >= *q.count)
         return;
     const int64_t p = __builtin_amdgcn_readfirstlane(q.idx[k]);
-    filter_one_pixel(g, fabrics, FABRIC_MAX_FABRICS, p, n_samples, side, inv_side, seed, lane,
-                     out_rgb, nullptr, nullptr);
+    filter_one_pixel<VIS>(g, fabrics, FABRIC_MAX_FABRICS, p, n_samples, side, inv_side, seed,
+                          lane, vis, out_rgb, nullptr, nullptr);
 }
 
 // Queue compaction in three fixed-order steps (no atomics).  The offsets
@@ -190,30 +196,41 @@ __global__ void queue_scatter_kernel(const uint16_t *__restrict__ mask,
 }  // namespace
 
 hipError_t launch_gt_filter(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
-                            int n_samples, uint64_t seed, float *out_rgb, float *out_comp,
-                            unsigned long long *err, hipStream_t stream)
+                            int n_samples, uint64_t seed, VisArgs vis, float *out_rgb,
+                            float *out_comp, unsigned long long *err, hipStream_t stream)
 {
     if (g.n == 0)
         return hipSuccess;
     const int side = sample_side(n_samples);
     int64_t blocks = (g.n + kWavesPerBlock - 1) / kWavesPerBlock;
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;   // padding blocks exit at once
-    hipLaunchKernelGGL(gt_filter_kernel, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
-                       stream, g, fabrics, n_fabrics, n_samples, side, 1.0f / (float)side, seed,
-                       out_rgb, out_comp, err);
+    if (vis.tex)
+        hipLaunchKernelGGL(gt_filter_kernel<true>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
+                           0, stream, g, fabrics, n_fabrics, n_samples, side, 1.0f / (float)side,
+                           seed, vis, out_rgb, out_comp, err);
+    else
+        hipLaunchKernelGGL(gt_filter_kernel<false>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
+                           0, stream, g, fabrics, n_fabrics, n_samples, side, 1.0f / (float)side,
+                           seed, vis, out_rgb, out_comp, err);
     return hipGetLastError();
 }
 
 hipError_t launch_gt_filter_queue(const fabric_gbuffer &g, const DevFabric *fabrics,
-                                  int n_samples, uint64_t seed, FallbackQueue q, float *out_rgb,
-                                  hipStream_t stream)
+                                  int n_samples, uint64_t seed, VisArgs vis, FallbackQueue q,
+                                  float *out_rgb, hipStream_t stream)
 {
     if (g.n == 0)
         return hipSuccess;
     const int side = sample_side(n_samples);
     const int64_t blocks = (g.n + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL(gt_filter_queue_kernel, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
-                       stream, g, fabrics, n_samples, side, 1.0f / (float)side, seed, q, out_rgb);
+    if (vis.tex)
+        hipLaunchKernelGGL(gt_filter_queue_kernel<true>, dim3((unsigned)blocks),
+                           dim3(64 * kWavesPerBlock), 0, stream, g, fabrics, n_samples, side,
+                           1.0f / (float)side, seed, vis, q, out_rgb);
+    else
+        hipLaunchKernelGGL(gt_filter_queue_kernel<false>, dim3((unsigned)blocks),
+                           dim3(64 * kWavesPerBlock), 0, stream, g, fabrics, n_samples, side,
+                           1.0f / (float)side, seed, vis, q, out_rgb);
     return hipGetLastError();
 }
 

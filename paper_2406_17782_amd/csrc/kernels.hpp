@@ -20,15 +20,15 @@ struct FallbackQueue {
     int32_t *idx;
 };
 
-// Footprint filter: one wavefront per pixel.
+// Footprint filter: one wavefront per pixel; vis.tex == nullptr for V = 1.
 hipError_t launch_gt_filter(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
-                            int n_samples, uint64_t seed, float *out_rgb, float *out_comp,
-                            unsigned long long *err, hipStream_t stream);
+                            int n_samples, uint64_t seed, VisArgs vis, float *out_rgb,
+                            float *out_comp, unsigned long long *err, hipStream_t stream);
 // The same filter (identical per-pixel results) over the queued pixels of
-// a hybrid shading launch, writing their rgb; and the counter reset.
+// a hybrid shading launch, writing their rgb.
 hipError_t launch_gt_filter_queue(const fabric_gbuffer &g, const DevFabric *fabrics,
-                                  int n_samples, uint64_t seed, FallbackQueue q, float *out_rgb,
-                                  hipStream_t stream);
+                                  int n_samples, uint64_t seed, VisArgs vis, FallbackQueue q,
+                                  float *out_rgb, hipStream_t stream);
 size_t queue_offset_entries(int64_t n);
 hipError_t launch_queue_build(FallbackQueue q, int64_t n, hipStream_t stream);
 
@@ -64,8 +64,8 @@ hipError_t launch_fold_latents(const float *dec_params, const float *latents, in
 // queue is compacted in pixel order, and a third launch filters it.
 hipError_t launch_decode(int prec, bool raw, const fabric_gbuffer &g, const DevFabric *fabrics,
                          int n_fabrics, const float *cfold, const void *image,
-                         int fallback_samples, uint64_t seed, FallbackQueue q, float *out,
-                         unsigned long long *err, hipStream_t stream);
+                         int fallback_samples, uint64_t seed, VisArgs vis, FallbackQueue q,
+                         float *out, unsigned long long *err, hipStream_t stream);
 
 // One latent blend of Sec. 5 "Interpolation": z[dst] = (1 - t) z[a] + t z[b].
 struct LatentLerp {

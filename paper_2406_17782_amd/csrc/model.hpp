@@ -76,12 +76,78 @@ struct SampleVal {
 };
 
 // The integrand of Eq. (3) and weight of Eq. (4) at surface point (us, vs).
+// Texel column (or row) of reduced coordinate q, wrapped into [0, size).
+// q lies within two cells of the period (size >= kVisRes), so two
+// corrections each way suffice; the clamps keep any other value (a huge
+// coordinate whose float32 reduction is inexact) inside the table.
+__device__ inline int texel_of(float q, int size)
+{
+    int k = (int)floorf(fminf(fmaxf(q, -4.0f), 4096.0f) * (float)kVisRes);
+    k = k < 0 ? k + size : k;
+    k = k < 0 ? k + size : k;
+    k = k >= size ? k - size : k;
+    k = k >= size ? k - size : k;
+    return min(max(k, 0), size - 1);
+}
+
+// V(x_p, w) of Eq. (3)-(4) for the point in texel (a0, b0), w.z > 0: a ray
+// from the texel's centre at its height, one texel per step along the major
+// horizontal axis of w (w_minor / |w_major| per texel along the other,
+// rising w.z / |w_major| per texel), for at most kVisSteps steps; blocked
+// where the texel under the ray is higher than the ray, free once the ray
+// is above the highest texel.  Every position and ray height is float32
+// with one rounding per operation (no contraction, correctly rounded
+// division), so that each texel decision is reproducible.
+__device__ inline bool vis_march(const float *__restrict__ tex, const VisFabric &vf, int a0,
+                                 int b0, float3 w)
+{
+#pragma clang fp contract(off)
+    const float inv_r = 1.0f / (float)kVisRes;
+    const float ax = fabsf(w.x), ay = fabsf(w.y);
+    const float major = ax >= ay ? ax : ay;
+    if (!(major > 0.0f))
+        return true;
+    const float *t = tex + vf.off;
+    const float h0 = t[b0 * vf.tw + a0];
+    float du, dv;
+    if (ax >= ay) {
+        du = w.x > 0.0f ? inv_r : -inv_r;
+        dv = (w.y / ax) * inv_r;
+    } else {
+        dv = w.y > 0.0f ? inv_r : -inv_r;
+        du = (w.x / ay) * inv_r;
+    }
+    const float rise = (w.z / major) * inv_r;
+    const float cu = ((float)a0 + 0.5f) * inv_r, cv = ((float)b0 + 0.5f) * inv_r;
+    for (int k = 1; k <= kVisSteps; k++) {
+        const float fk = (float)k;
+        const float h = h0 + fk * rise;
+        if (h >= vf.hmax)
+            return true;
+        const float qu = cu + fk * du, qv = cv + fk * dv;
+        if (t[texel_of(qv, vf.th) * vf.tw + texel_of(qu, vf.tw)] > h)
+            return false;
+    }
+    return true;
+}
+
+// One footprint sample.  VIS: multiply A(p, wo) by V(x_p, wo) and the
+// integrand by V(x_p, wi) (Eq. (3)-(4)); otherwise V = 1.
+template <bool VIS>
 __device__ inline SampleVal eval_surface_point(const DevFabric &f, float us, float vs,
-                                               float3 wi, float3 wo)
+                                               float3 wi, float3 wo, const float *tex,
+                                               const VisFabric &vf)
 {
     SampleVal out;
     float up = wrap_period(us, f.fwx, f.inv_wx);
     float vp = wrap_period(vs, f.fwy, f.inv_wy);
+    int ta = 0, tb = 0;
+    bool vis_o = true;
+    if (VIS) {
+        ta = texel_of(up, vf.tw);
+        tb = texel_of(vp, vf.th);
+        vis_o = vis_march(tex, vf, ta, tb, wo);
+    }
     // Clamped so that even a huge finite uv, whose FP32 reduction is inexact,
     // indexes inside the cell table.
     int i = min(max((int)up, 0), f.wx - 1);
@@ -102,7 +168,7 @@ __device__ inline SampleVal eval_surface_point(const DevFabric &f, float us, flo
         // The gap between yarns: nothing reflects, the macro plane projects wo.z.
         out.num_c = 0.0f;
         out.num_s = 0.0f;
-        out.area = wo.z;
+        out.area = vis_o ? wo.z : 0.0f;
         return out;
     }
     const int y = yarn;
@@ -138,8 +204,8 @@ __device__ inline SampleVal eval_surface_point(const DevFabric &f, float us, flo
 
     float ci = wi.x * n.x + wi.y * n.y + wi.z * n.z;
     float co = wo.x * n.x + wo.y * n.y + wo.z * n.z;
-    out.area = fmaxf(co, 0.0f) * jac;
-    if (!(ci > 0.0f && co > 0.0f)) {
+    out.area = vis_o ? fmaxf(co, 0.0f) * jac : 0.0f;
+    if (!(ci > 0.0f && co > 0.0f && vis_o) || (VIS && !vis_march(tex, vf, ta, tb, wi))) {
         out.num_c = 0.0f;
         out.num_s = 0.0f;
         return out;
@@ -191,10 +257,11 @@ __device__ inline bool pixel_fault(int fid, int n_fabrics, float u, float v, flo
 // Wave-wide FP64 footprint estimate for one pixel: lanes take samples
 // lane, lane + 64, ...; partial sums are reduced across the wave in a fixed
 // butterfly order.  Every lane returns the four components.
+template <bool VIS>
 __device__ inline void filter_pixel_wave(const DevFabric &f, uint64_t seed, uint64_t pixel,
                                          int n_samples, int side, float inv_side, float u,
                                          float v, float r, float3 wi, float3 wo, int lane,
-                                         double comp[4])
+                                         const float *tex, const VisFabric &vf, double comp[4])
 {
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     // Sample k = lane + 64 i draws output pixel * N + k of SplitMix64(seed):
@@ -212,7 +279,7 @@ __device__ inline void filter_pixel_wave(const DevFabric &f, uint64_t seed, uint
             kx -= side;
             ky += 1;
         }
-        SampleVal sv = eval_surface_point(f, pos.x, pos.y, wi, wo);
+        SampleVal sv = eval_surface_point<VIS>(f, pos.x, pos.y, wi, wo, tex, vf);
         double nc = sv.num_c, ns = sv.num_s;
         acc[0] += sv.yarn == kWarp ? nc : 0.0;
         acc[1] += sv.yarn == kWeft ? nc : 0.0;

@@ -846,8 +846,8 @@ hipError_t loss_and_grad(TrainScratch &s, const TrainArgs &a, hipStream_t stream
             if ((e = grow(&s.b_fields, (size_t)n * 9)) != hipSuccess) return e;
             s.batch_cap = n;
         }
-        if ((e = launch_gt_filter(g, a.fabrics, a.n_fabrics, cfg.gt_samples, cfg.seed ^ 1ull, nullptr,
-                                  s.targets, a.err, stream)) != hipSuccess)
+        if ((e = launch_gt_filter(g, a.fabrics, a.n_fabrics, cfg.gt_samples, cfg.seed ^ 1ull, a.vis,
+                                  nullptr, s.targets, a.err, stream)) != hipSuccess)
             return e;
         targets = s.targets;
     }

@@ -43,6 +43,7 @@ struct TrainArgs {
     const float *targets;             // NULL: analytic filter
     fabric_train_cfg cfg;
     unsigned long long *err;
+    VisArgs vis;                      // visibility of generated targets
 };
 
 hipError_t launch_make_batch(uint64_t seed, int64_t n, int n_fabrics, float r_lo, float r_hi,

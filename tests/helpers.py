@@ -45,3 +45,23 @@ def assert_filter_parity(gpu_comp, orc_comp, flagged, rel=1e-4, max_bad=1e-3, un
     assert max_unflagged <= unflagged_cap, msg
     assert bad.sum() <= max(1, max_bad * n), msg
     return msg
+
+
+def assert_filter_parity_vis(gpu_comp, orc_comp, flagged, rel=1e-4, max_bad=1e-3,
+                             flagged_cap=5e-2):
+    """Footprint filter with visibility, same samples.  Unflagged pixels as
+    assert_filter_parity.  A flagged pixel holds a sample within 4e-6 cells
+    of a texel boundary (or 1e-5 of a classification edge): float32 sample
+    positions rounded in another order may start its ray in the neighbouring
+    texel, which changes that sample's V; such pixels stay within
+    `flagged_cap` of their largest component."""
+    bad, err = filter_mismatch(gpu_comp, orc_comp, flagged, rel)
+    flagged = np.asarray(flagged) > 0
+    n = bad.size
+    unflagged_bad = bad & ~flagged
+    max_flagged = float(err[flagged].max()) if flagged.any() else 0.0
+    msg = (f"pixels {n}, bad {int(bad.sum())}, unflagged bad {int(unflagged_bad.sum())}, "
+           f"flagged {int(flagged.sum())}, max err flagged {max_flagged:.3g}")
+    assert unflagged_bad.sum() <= max(1, max_bad * n), msg
+    assert max_flagged <= flagged_cap, msg
+    return msg

@@ -149,3 +149,21 @@ def test_axis_aligned_march_scans_the_row():
                     want = 0
                     break
             assert orc.visible(m, u, v, w) == want
+
+
+def test_zero_inclination_and_single_cell_period():
+    """Zero inclination: floats are flat, the height is the cross-section
+    profile alone (finite everywhere).  A 1 x 1 period (one yarn on top
+    everywhere): rays wrap over the period several times."""
+    m = fi.uniform_material(fi.pattern_twill(3, 2), beta=1.5, incl=0.0)
+    t, hmax = orc.height_table(m)
+    assert np.all(np.isfinite(t))
+    p = orc.point_eval(m, 1.5, 1.5, [0, 0, 1], [0, 0, 1])
+    assert p["n"][1] == 0.0 and p["n"][0] == 0.0           # centre of a flat top float
+    assert orc.surface_height(m, 1.5, 1.5) == 0.0
+    one = fi.uniform_material(np.ones((1, 1), dtype=np.uint8), beta=1.0, gap=0.3)
+    rng = np.random.default_rng(26)
+    for _ in range(50):
+        w = direction(rng.uniform(0.01, 0.3), rng.uniform(0, 2 * math.pi))
+        u, v = rng.uniform(0, 1), rng.uniform(0, 1)
+        assert orc.visible(one, u, v, w) == orc.visible(one, u + 5, v + 7, w)
