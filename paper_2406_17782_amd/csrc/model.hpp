@@ -90,6 +90,18 @@ __device__ inline int texel_of(float q, int size)
     return min(max(k, 0), size - 1);
 }
 
+// texel_of for a march position: within two cells of the period by
+// construction (texel centre plus at most kVisSteps steps of at most one
+// texel), so the clamps are not needed.
+__device__ inline int texel_near(float q, int size)
+{
+    int k = (int)floorf(q * (float)kVisRes);
+    k = k < 0 ? k + size : k;
+    k = k < 0 ? k + size : k;
+    k = k >= size ? k - size : k;
+    return k >= size ? k - size : k;
+}
+
 // V(x_p, w) of Eq. (3)-(4) for the point in texel (a0, b0), w.z > 0: a ray
 // from the texel's centre at its height, one texel per step along the major
 // horizontal axis of w (w_minor / |w_major| per texel along the other,
@@ -119,13 +131,24 @@ __device__ inline bool vis_march(const float *__restrict__ tex, const VisFabric 
     }
     const float rise = (w.z / major) * inv_r;
     const float cu = ((float)a0 + 0.5f) * inv_r, cv = ((float)b0 + 0.5f) * inv_r;
+    // Along the major axis the position is the texel centre +- k texels
+    // exactly, so its texel index steps by one (wrapped); the minor axis
+    // takes the rounded float32 position (|w_minor / w_major| <= 1, so it
+    // moves at most one texel per step).  Table reads use 32-bit offsets.
+    const bool major_u = ax >= ay;
+    const int step = major_u ? (w.x > 0.0f ? 1 : -1) : (w.y > 0.0f ? 1 : -1);
+    const int span = major_u ? vf.tw : vf.th;
+    int m = major_u ? a0 : b0;
     for (int k = 1; k <= kVisSteps; k++) {
         const float fk = (float)k;
         const float h = h0 + fk * rise;
         if (h >= vf.hmax)
             return true;
-        const float qu = cu + fk * du, qv = cv + fk * dv;
-        if (t[texel_of(qv, vf.th) * vf.tw + texel_of(qu, vf.tw)] > h)
+        m += step;
+        m = m == span ? 0 : (m < 0 ? span - 1 : m);
+        const int a = major_u ? m : texel_near(cu + fk * du, vf.tw);
+        const int b = major_u ? texel_near(cv + fk * dv, vf.th) : m;
+        if (*(const float *)((const char *)t + (uint32_t)(b * vf.tw + a) * 4u) > h)
             return false;
     }
     return true;
