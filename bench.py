@@ -242,6 +242,67 @@ def train_row_2p20(args, torch, pkg, fab):
             "samples_per_s": (1 << 20) / (ms * 1e-3), "prec": "bf16 decoder, FP32 masters, FP64 Adam"}
 
 
+def visibility_row(args, torch, pkg, fi, wl, mats, g, d, neural_ms):
+    """The analytic model with inter-yarn visibility (V of Eq. (3)-(4)): the
+    filter's cost on the 1080p frame, a network trained on visibility
+    targets (same schedule as the main one), and the errors of that network
+    and of one analytic sample against the FP64 oracle's filter with V on
+    the seeded 1 % subset."""
+    import oracle
+    fab = pkg.Fabric(0, seed=wl.seed())
+    try:
+        fab.encode(mats)
+        fab.set_visibility(True)
+        steps = args.train_steps
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        for s in range(steps):
+            lr = args.train_lr * 0.5 * (1.0 + math.cos(math.pi * s / max(1, steps)))
+            loss = fab.train_step(seed=1_000_000 + s, batch=args.train_batch,
+                                  gt_samples=args.gt_samples, prec=pkg.FABRIC_BF16, lr=lr,
+                                  want_loss=(s == steps - 1))
+        ev1.record()
+        torch.cuda.synchronize()
+        train_ms = ev0.elapsed_time(ev1) / max(1, steps)
+        fab.encode(mats)
+        out = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
+        pkg.fabric_shade_gbuffer(fab.ctx, d, pkg.PREC["bf16"], 0, 0, out)
+        rgb = out.cpu().numpy()
+        filt = lambda: pkg.fabric_gt_filtered(fab.ctx, d, args.gt_samples, 4242, out, None)
+        filt()
+        f_ms = time_launches(torch, filt, args.analytic_steps)
+        gt = out.cpu().numpy()
+        pkg.fabric_gt_filtered(fab.ctx, d, 1, 777, out, None)
+        one = out.cpu().numpy()
+        res = {"filter_ms_per_frame": f_ms, "filter_mpix_per_s": g.n / (f_ms * 1e-3) / 1e6,
+               "neural_bf16_over_filter": f_ms / neural_ms, "train_ms_per_step": train_ms,
+               "train_steps": steps, "loss_last": loss,
+               "definition": "height texels 16/cell from the yarn slopes, 32-step march (2 cells)"}
+        if not args.no_rmse:
+            idx = fi.subset_indices(g.n, args.rmse_frac, 99)
+            sub = g.subset(idx)
+            _, o_rgb, _, _ = oracle.filter_gbuffer(mats, sub, args.gt_samples, 4242,
+                                                   same_sample=True, pixel_index=idx,
+                                                   visibility=True)
+            res["rmse_vs_fp64_oracle"] = {
+                "neural_bf16": rmse_stats(rgb[:, idx], o_rgb),
+                "analytic_gpu_same_samples": rmse_stats(gt[:, idx], o_rgb),
+                "analytic_1spp": rmse_stats(one[:, idx], o_rgb)}
+            big = sub.radius >= 0.15
+            res["radius_ge_0.15"] = {
+                "pixels": int(big.sum()),
+                "neural_bf16_rmse": float(np.sqrt(np.mean((rgb[:, idx][:, big] - o_rgb[:, big]) ** 2))),
+                "analytic_1spp_rmse": float(np.sqrt(np.mean((one[:, idx][:, big] - o_rgb[:, big]) ** 2)))}
+        log(f"visibility: filter {f_ms:.2f} ms/frame, train {train_ms:.2f} ms/step" +
+            ("" if args.no_rmse else
+             f", rmse bf16 {res['rmse_vs_fp64_oracle']['neural_bf16']['rmse']:.4g}, "
+             f"1spp {res['rmse_vs_fp64_oracle']['analytic_1spp']['rmse']:.4g}"))
+        return res
+    finally:
+        fab.close()
+
+
 def interp_row(args, torch, pkg, fi, g, d):
     """Latent interpolation study (Sec. 5 "Interpolation") on the 1080p
     frame's geometry: a second network trained on variants of one twill whose
@@ -482,6 +543,7 @@ def main():
         rows["train_step_2p20"] = train_row_2p20(args, torch, pkg, fab)
         fab.encode(mats)
         rows["latent_interpolation"] = interp_row(args, torch, pkg, fi, g, d)
+        rows["visibility"] = visibility_row(args, torch, pkg, fi, wl, mats, g, d, ms)
 
     # ---- error against the FP64 oracle on a seeded pixel subset ----
     errs = None if args.no_rmse else oracle_errors(args, torch, pkg, fi, fab, d, mats, g, rgb, gt_rgb)
