@@ -99,7 +99,7 @@ def lib():
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double]
         L.orc_batch_gen.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int,
-                                    ctypes.c_double, ctypes.c_double] + [_P] * 10
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double] + [_P] * 10
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -348,12 +348,15 @@ def adam_step(theta: np.ndarray, grad, m: np.ndarray, v: np.ndarray, t: int, lr:
                         lr, beta1, beta2, eps)
 
 
-def batch_gen(seed: int, n: int, n_fabrics: int, r_lo: float = 1e-3, r_hi: float = 0.5):
+def batch_gen(seed: int, n: int, n_fabrics: int, r_lo: float = 1e-3, r_hi: float = 0.5,
+              btdf_frac: float = 0.0):
+    """Training batch recipe; btdf_frac (a float32 value) of the samples are
+    lit from below (transmission)."""
     import fabric_inputs as fi
     fid = np.zeros(n, dtype=np.uint16)
     arrs = [np.zeros(n, dtype=np.float32) for _ in range(9)]
-    lib().orc_batch_gen(ctypes.c_uint64(seed), n, n_fabrics, r_lo, r_hi, _ptr(fid),
-                        *[_ptr(a) for a in arrs])
+    lib().orc_batch_gen(ctypes.c_uint64(seed), n, n_fabrics, r_lo, r_hi,
+                        float(np.float32(btdf_frac)), _ptr(fid), *[_ptr(a) for a in arrs])
     return fi.GBuffer(fid, *arrs)
 
 

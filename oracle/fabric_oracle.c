@@ -13,7 +13,11 @@
  *   - the point shading model: Eq. (1) (specular SpongeCake layer with a
  *     fiber-like SGGX microflake plus the blended Lambertian term) with D, G
  *     and Lambda from Eq. (2), S = R^T diag(1,1,alpha^2) R and T*rho = 2
- *     (Sec. 3.1);
+ *     (Sec. 3.1); for light from below the fabric (wi.z < 0) a transmission
+ *     lobe: the single scattering of the same slab between its two faces
+ *     (Wang et al. 2021), plus the Lambertian share (1 - w)/pi (the paper's
+ *     BTDF is in its supplementary: "parity unpinned", pinned by
+ *     reciprocity and energy bounds);
  *   - a procedural yarn geometry that yields the ply normal n_p and
  *     orientation t_p from the weave pattern and the per-yarn parameters of
  *     Table 1 (the paper takes it from Jin et al.; its exact form lives in the
@@ -54,8 +58,10 @@
 #define ORC_THETA_MAX (ORC_PI / 3.0)
 /* Optical depth T*rho of the specular layer, fixed to 2 for fabrics (Sec. 3.1). */
 #define ORC_T_RHO 2.0
-/* k of the specular log mapping g(x) = ln(k x + 1) for reflection (Eq. (9)). */
+/* k of the specular log mapping g(x) = ln(k x + 1) (Eq. (9)): 100 for
+ * reflection, 1000 for transmission (Sec. 4.2). */
 #define ORC_K_SPEC 100.0
+#define ORC_K_SPEC_T 1000.0
 /* Loss weights lambda_S and lambda_C (Eq. (11)). */
 #define ORC_LAMBDA_S 0.4
 #define ORC_LAMBDA_C 0.1
@@ -523,14 +529,52 @@ double orc_sggx_sigma(double alpha, const double t[3], const double w[3])
     return sqrt(quad_form(S, w));
 }
 
+/* Transmission through the specular layer (light below the fabric,
+ * wi.z < 0, and below the ply, ci < 0; viewer above both): single
+ * scattering by the microflakes of a slab of optical depth T rho between its
+ * faces.  A flake at depth d (from the top) scatters wi into wo with phase
+ * D(h) / (4 sigma(wi)), h = (wi + wo)/|wi + wo|; the light reaching it is
+ * attenuated by e^{-Lambda_i (T - d)}, the scattered light by
+ * e^{-Lambda_o d}; integrating over d gives
+ *   f_t = D / (4 |ci| co) (e^{-T Lambda_o} - e^{-T Lambda_i}) / (Lambda_i - Lambda_o)
+ * (T e^{-T Lambda} when the two are equal), with Lambda(w) = sigma(w) / |w.n|.
+ * The diffuse share is the Lambertian (1 - w)/pi.  Straight-through light
+ * (wi = -wo, the excluded delta transmission) has no flake to scatter it. */
+static void point_btdf(double alpha, double w, const double n[3], const double t[3],
+                       const double wi[3], const double wo[3], double ci, double co, double out[2])
+{
+    double h[3] = {wi[0] + wo[0], wi[1] + wo[1], wi[2] + wo[2]};
+    double hl = sqrt(dot3(h, h));
+    out[1] = (1.0 - w) / ORC_PI;
+    if (hl < 1e-9) {
+        out[0] = 0.0;
+        return;
+    }
+    for (int k = 0; k < 3; k++)
+        h[k] /= hl;
+    double D = orc_sggx_D(alpha, t, h);
+    double lam_i = orc_sggx_sigma(alpha, t, wi) / -ci;
+    double lam_o = orc_sggx_sigma(alpha, t, wo) / co;
+    double d = lam_i - lam_o;
+    double g = d != 0.0 ? (exp(-ORC_T_RHO * lam_o) - exp(-ORC_T_RHO * lam_i)) / d
+                        : ORC_T_RHO * exp(-ORC_T_RHO * lam_o);
+    out[0] = D * g / (4.0 * -ci * co);
+}
+
 /* f_s / k_s and f_d / k_d of Eq. (1) at a ply with normal n and orientation t.
- * Cosines are taken against the ply normal; both lobes vanish unless wi and
- * wo are above the ply.  wi[2] is the cosine against the macro normal. */
+ * Cosines are taken against the ply normal.  Reflection needs wi above the
+ * macro surface and the ply, transmission wi below both; wo is always above
+ * the ply; otherwise both lobes vanish.  wi[2] is the cosine against the
+ * macro normal. */
 void orc_point_brdf(double alpha, double w, const double n[3], const double t[3],
                     const double wi[3], const double wo[3], double out[2])
 {
     double ci = dot3(wi, n), co = dot3(wo, n);
-    if (ci <= 0.0 || co <= 0.0) {
+    if (co > 0.0 && ci < 0.0 && wi[2] < 0.0) {
+        point_btdf(alpha, w, n, t, wi, wo, ci, co, out);
+        return;
+    }
+    if (ci <= 0.0 || co <= 0.0 || wi[2] <= 0.0) {
         out[0] = 0.0;
         out[1] = 0.0;
         return;
@@ -569,11 +613,13 @@ static void eval_point(const orc_material *m, const orc_vis *vis, double us, dou
 {
     point_geometry(m, us, vs, &smp->geo);
     /* V(x_p, wo) enters A(p, wo) (Eq. (4)), V(x_p, wi) the integrand (Eq. (3)). */
+    /* Light from below (transmission) is not shadowed by the height field. */
     double v_o = 1.0, v_i = 1.0;
     if (vis) {
         float up = (float)smp->geo.up, vp = (float)smp->geo.vp;
         v_o = orc_visible(vis->table, vis->tw, vis->th, vis->hmax, up, vp, wo);
-        v_i = orc_visible(vis->table, vis->tw, vis->th, vis->hmax, up, vp, wi);
+        if (wi[2] > 0.0)
+            v_i = orc_visible(vis->table, vis->tw, vis->th, vis->hmax, up, vp, wi);
     }
     if (smp->geo.yarn == ORC_HOLE) {
         smp->rho_s = 0.0;
@@ -585,9 +631,11 @@ static void eval_point(const orc_material *m, const orc_vis *vis, double us, dou
     double f[2];
     orc_point_brdf(m->alpha[y], m->wblend[y], smp->geo.n, smp->geo.t, wi, wo, f);
     double ci = dot3(wi, smp->geo.n), co = dot3(wo, smp->geo.n);
-    double ci_pos = ci > 0.0 ? ci : 0.0;
-    smp->rho_s = f[0] * ci_pos * v_i;
-    smp->rho_c = f[1] * ci_pos * v_i;
+    /* <wi.n_p> of Eq. (3): the cosine on the lit side of the ply (the lobes
+     * are zero where wi and the ply disagree on the side). */
+    double ci_lit = fabs(ci);
+    smp->rho_s = f[0] * ci_lit * v_i;
+    smp->rho_c = f[1] * ci_lit * v_i;
     /* <wo.n_p> / <n_s.n_p> V(x_p, wo); 1/<n_s.n_p> is the Jacobian. */
     smp->area = (co > 0.0 ? co : 0.0) / smp->geo.n[2] * v_o;
 }
@@ -723,9 +771,10 @@ static void compose_rgb(const orc_material *m, const double comp[4], double rgb[
                + m->ks[0][c] * comp[2] + m->ks[1][c] * comp[3];
 }
 
-/* A pixel is a fault (all outputs 0) if any field is non-finite, a direction
- * is not above the macro surface, the radius is not positive or the fabric id
- * is out of range. */
+/* A pixel is a fault (all outputs 0) if any field is non-finite, the view is
+ * not above the macro surface, the light grazes it exactly (wi.z = 0; below
+ * it is transmission), the radius is not positive or the fabric id is out of
+ * range. */
 static int pixel_fault(int nmats, int fid, double u, double v, double r,
                        const double wi[3], const double wo[3])
 {
@@ -733,7 +782,7 @@ static int pixel_fault(int nmats, int fid, double u, double v, double r,
     for (int k = 0; k < 9; k++)
         if (!isfinite(f[k]))
             return 1;
-    if (fid < 0 || fid >= nmats || r <= 0.0 || wi[2] <= 0.0 || wo[2] <= 0.0)
+    if (fid < 0 || fid >= nmats || r <= 0.0 || wi[2] == 0.0 || wo[2] <= 0.0)
         return 1;
     return 0;
 }
@@ -940,12 +989,15 @@ static void decoder_backward(const double *P, const dec_acts *A, const double dy
 
 /* Components from the decoder's outputs: diffuse terms are linear, specular
  * terms invert the log mapping g of Eq. (9); both clamp at 0. */
-static void decode_outputs(const double y[NOUT], double comp[4])
+/* k of Eq. (9) for a query: transmission when the light is below. */
+static double spec_k(double wi_z) { return wi_z < 0.0 ? ORC_K_SPEC_T : ORC_K_SPEC; }
+
+static void decode_outputs(const double y[NOUT], double k, double comp[4])
 {
     comp[0] = relu(y[0]);
     comp[1] = relu(y[1]);
-    comp[2] = relu((exp(y[2]) - 1.0) / ORC_K_SPEC);
-    comp[3] = relu((exp(y[3]) - 1.0) / ORC_K_SPEC);
+    comp[2] = relu((exp(y[2]) - 1.0) / k);
+    comp[3] = relu((exp(y[3]) - 1.0) / k);
 }
 
 /* Decoder over a G-buffer with per-fabric latents z[nmats][32].  y is [4][n]
@@ -966,7 +1018,7 @@ int64_t orc_decoder_batch(const double *P, const double *latents, const orc_mate
             orc_spatial_features(u, v, r, mats[fid].wx, mats[fid].wy, s);
             decoder_forward(P, latents + (int64_t)fid * LATENT, s, ang, &A);
             for (int c = 0; c < 4; c++) out[c] = A.y[c];
-            decode_outputs(A.y, comp);
+            decode_outputs(A.y, spec_k(wi[2]), comp);
             compose_rgb(&mats[fid], comp, c3);
         }
         faults += bad;
@@ -1056,7 +1108,8 @@ void orc_encoder_batch(const double *Q, const orc_material *mats, int nmats, dou
 /* Per-sample loss terms and dL/dy for outputs y and targets (C_warp, C_weft,
  * S_warp, S_weft).  With n samples in the batch, the loss is
  * sum_y lambda_S mean (y_S - ln(k S + 1))^2 + lambda_C mean (y_C - C)^2. */
-static double loss_terms(const double y[NOUT], const double tgt[4], int64_t n, double dy[NOUT])
+static double loss_terms(const double y[NOUT], const double tgt[4], double k, int64_t n,
+                         double dy[NOUT])
 {
     double l = 0.0;
     for (int c = 0; c < 2; c++) {
@@ -1065,7 +1118,7 @@ static double loss_terms(const double y[NOUT], const double tgt[4], int64_t n, d
         dy[c] = ORC_LAMBDA_C * 2.0 * d / (double)n;
     }
     for (int c = 2; c < 4; c++) {
-        double d = y[c] - log(ORC_K_SPEC * tgt[c] + 1.0);
+        double d = y[c] - log(k * tgt[c] + 1.0);
         l += ORC_LAMBDA_S * d * d / (double)n;
         dy[c] = ORC_LAMBDA_S * 2.0 * d / (double)n;
     }
@@ -1122,7 +1175,7 @@ double orc_loss_grad(const double *params, const orc_material *mats, int nmats,
             dec_acts A;
             orc_spatial_features(u, v, r, mats[fid].wx, mats[fid].wy, s);
             decoder_forward(P, z + fid * LATENT, s, ang, &A);
-            lt[tid] += loss_terms(A.y, tgt, n, dy);
+            lt[tid] += loss_terms(A.y, tgt, spec_k(wi[2]), n, dy);
             decoder_backward(P, &A, dy, G, dzp);
             for (int k = 0; k < LATENT; k++)
                 dzl[fid * LATENT + k] += dzp[k];
@@ -1203,8 +1256,8 @@ void orc_adam_step(float *theta, const double *grad, double *m, double *v, int64
  *   8q+4: wo likewise.
  * Values are computed in double and rounded to float32. */
 void orc_batch_gen(uint64_t seed, int64_t n, int n_fabrics, double r_lo, double r_hi,
-                   uint16_t *fid, float *u, float *v, float *r, float *wi_x, float *wi_y,
-                   float *wi_z, float *wo_x, float *wo_y, float *wo_z)
+                   double btdf_frac, uint16_t *fid, float *u, float *v, float *r, float *wi_x,
+                   float *wi_y, float *wi_z, float *wo_x, float *wo_y, float *wo_z)
 {
     for (int64_t q = 0; q < n; q++) {
         uint64_t base = 8ull * (uint64_t)q;
@@ -1223,6 +1276,10 @@ void orc_batch_gen(uint64_t seed, int64_t n, int n_fabrics, double r_lo, double 
         wo_x[q] = (float)(sqrt(a) * cos(2.0 * ORC_PI * b));
         wo_y[q] = (float)(sqrt(a) * sin(2.0 * ORC_PI * b));
         wo_z[q] = (float)sqrt(1.0 - a);
+        /* Output 8q+5 lights the sample from below with probability btdf_frac. */
+        u24_pair(orc_splitmix64(seed, base + 5), &a, &b);
+        if (a < btdf_frac)
+            wi_z[q] = -wi_z[q];
     }
 }
 
