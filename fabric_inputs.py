@@ -267,13 +267,15 @@ def tile_fabric_ids(rng: np.random.Generator, width: int, height: int,
 
 def make_gbuffer(width: int, height: int, n_fabrics: int, seed: int,
                  r_range=(1e-3, 0.5), uv_max: float = 8.0,
-                 out_of_range_frac: float = 0.0) -> GBuffer:
+                 out_of_range_frac: float = 0.0, btdf_frac: float = 0.0) -> GBuffer:
     """A seeded width x height G-buffer (row-major pixels).
 
     Per pixel, iid: uv ~ U[0, uv_max)^2, radius log-uniform over r_range,
     wi and wo cosine-weighted.  With out_of_range_frac > 0 that fraction of
     pixels (iid) is moved outside the network's training range: half get
     radius ~ log-U[1, 2] cells, half a grazing view wo.z ~ U(0, 0.05).
+    With btdf_frac > 0 that fraction (iid, from a stream of its own) is lit
+    from below the fabric (wi.z negated): transmission queries.
     """
     rng = np.random.default_rng(seed)
     n = width * height
@@ -296,6 +298,9 @@ def make_gbuffer(width: int, height: int, n_fabrics: int, seed: int,
         wox[graze] = _f32(sxy * np.cos(phi))
         woy[graze] = _f32(sxy * np.sin(phi))
         woz[graze] = _f32(z)
+    if btdf_frac > 0.0:
+        below = np.random.default_rng(seed + 7919).random(n) < btdf_frac
+        wiz[below] = -wiz[below]
     return GBuffer(fid, u, v, r, wix, wiy, wiz, wox, woy, woz)
 
 
@@ -378,6 +383,7 @@ class Workload:
     out_of_range_frac: float = 0.0
     max_random_side: int = 8
     subset_frac: float = 1.0
+    btdf_frac: float = 0.0
 
     def seed(self, run: int = 0) -> int:
         return 1000 * WORKLOAD_INDEX[self.name] + run
@@ -387,7 +393,8 @@ class Workload:
 
     def gbuffer(self, run: int = 0) -> GBuffer:
         return make_gbuffer(self.width, self.height, self.n_fabrics, self.seed(run) + 17,
-                            r_range=self.r_range, out_of_range_frac=self.out_of_range_frac)
+                            r_range=self.r_range, out_of_range_frac=self.out_of_range_frac,
+                            btdf_frac=self.btdf_frac)
 
 
 WORKLOADS = {
@@ -398,6 +405,9 @@ WORKLOADS = {
                             max_random_side=16, subset_frac=0.0025),
     "hybrid_1080p": Workload("hybrid_1080p", 1920, 1080, 8, 256, (1e-3, 0.5),
                              out_of_range_frac=0.2, subset_frac=0.01),
+    # The 1080p frame with half its pixels lit from below (transmission).
+    "btdf_1080p": Workload("btdf_1080p", 1920, 1080, 8, 256, (1e-3, 0.5), subset_frac=0.01,
+                           btdf_frac=0.5),
 }
 WORKLOAD_INDEX = {"plain128": 1, "fabric8_1080p": 2, "train_2p20": 3,
-                  "fabric64_4k": 4, "hybrid_1080p": 5}
+                  "fabric64_4k": 4, "hybrid_1080p": 5, "btdf_1080p": 6}

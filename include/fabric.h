@@ -29,7 +29,7 @@
  *     host data synchronise.
  *   - Errors.  Every call validates its arguments first and, on failure,
  *     returns a status without enqueuing work.  No C++ exception crosses
- *     the ABI.  Per-pixel input faults (a non-finite field, wi.z <= 0,
+ *     the ABI.  Per-pixel input faults (a non-finite field, wi.z == 0,
  *     wo.z <= 0, radius <= 0, fabric_id >= fabrics encoded) do not fail the
  *     call: the pixel's outputs are written as 0 and a device counter is
  *     incremented (read it with fabric_error_count).
@@ -97,7 +97,9 @@ typedef struct {
 
 /* A G-buffer of n pixels as device structure-of-arrays, one element per pixel
  * in every array.  fabric_id indexes the fabrics passed to fabric_encode.
- * The library only reads these arrays. */
+ * wi (toward the light) may point below the fabric (wi.z < 0): a
+ * transmission query; wo (toward the viewer) points above it.  The library
+ * only reads these arrays. */
 typedef struct {
     int64_t n;
     const uint16_t *fabric_id;
@@ -122,6 +124,7 @@ typedef struct {
     double lr;            /* Adam learning rate of this step */
     double beta1, beta2, eps;   /* Adam constants, e.g. 0.9, 0.999, 1e-8 */
     float r_lo, r_hi;     /* footprint radius range (cells) of generated batches */
+    float btdf_frac;      /* share of generated samples lit from below, in [0, 1] */
 } fabric_train_cfg;
 
 /* Create a context on HIP device `device`.  Network parameters are drawn
@@ -191,7 +194,8 @@ fabric_status fabric_lerp_latents(fabric_ctx *ctx, const int32_t *dst, const int
                                   const int32_t *b, const float *t, int32_t count, void *stream);
 
 /* Neural shading of a G-buffer (Sec. 4.3 "Rendering"): per pixel, the
- * decoder's four outputs decoded as C = max(y, 0), S = max((e^y - 1)/100, 0)
+ * decoder's four outputs decoded as C = max(y, 0), S = max((e^y - 1)/k, 0)
+ * with k = 100, or 1000 where wi.z < 0 (transmission, Sec. 4.2)
  * (inverse of the specular mapping of Eq. (9)) and composed with Eq. (8).
  *   prec              arithmetic of the dense layers: FP32; BF16 or FP16
  *                     operands with FP32 accumulation; FP8_E4M3 operands with
@@ -224,7 +228,12 @@ fabric_status fabric_shade_gbuffer(fabric_ctx *ctx, const fabric_gbuffer *g, fab
  * stratum k = ky*m + kx jittered by the (p*n_samples + k)-th output of
  * SplitMix64 seeded with `seed` (upper 24 bits for x, bits 39..16 for y) and
  * mapped to the disk with the Shirley-Chiu concentric map.  Per sample:
- * rho = f * <wi.n_p> and projected area <wo.n_p>/<n_s.n_p> (holes: wo.z);
+ * rho = f * <wi.n_p> and projected area <wo.n_p>/<n_s.n_p> (holes: wo.z).
+ * Light below the fabric (wi.z < 0) is transmitted by plies it reaches from
+ * below: f_s is the single scattering of the specular slab between its
+ * faces, D / (4 |ci| co) (e^{-2 Lambda_o} - e^{-2 Lambda_i}) /
+ * (Lambda_i - Lambda_o), f_d the Lambertian share (1 - w)/pi, the cosine
+ * |wi.n_p|; holes transmit nothing (no delta transmission);
  * C_y = sum[yarn = y] rho_d A / sum A, S_y likewise, summed in FP64.
  *   out_comp  device float [4][n] (C_warp, C_weft, S_warp, S_weft) or NULL
  *   out_rgb   device float [3][n] (Eq. (8)) or NULL (not both NULL). */
@@ -265,15 +274,20 @@ fabric_status fabric_encoder_backward(fabric_ctx *ctx, const float *enc_params,
                                       const float *grad_latents, float *grad_enc_params,
                                       void *stream);
 
-/* Draw a training batch: sample q takes the outputs 8q..8q+4 of SplitMix64
+/* Draw a training batch: sample q takes the outputs 8q..8q+5 of SplitMix64
  * seeded with `seed`: fabric id = (z >> 32) mod n_mats; (u, v) = 8 * two
  * 24-bit uniforms; radius log-uniform on [r_lo, r_hi]; wi and wo
- * cosine-weighted from two 24-bit uniforms each.  out arrays: device, n each. */
+ * cosine-weighted from two 24-bit uniforms each; wi is turned below the
+ * fabric (wi.z negated: a transmission query, Sec. 4.2) when the upper 24
+ * bits of output 8q+5, as a uniform in [0, 1), are below btdf_frac.  out
+ * arrays: device, n each.  E_INVAL for btdf_frac outside [0, 1]. */
 fabric_status fabric_make_batch(fabric_ctx *ctx, uint64_t seed, int64_t n, float r_lo,
-                                float r_hi, const fabric_gbuffer_out *out, void *stream);
+                                float r_hi, float btdf_frac, const fabric_gbuffer_out *out,
+                                void *stream);
 
 /* One optimisation step of encoder + decoder on the encoded fabric table:
- * loss of Eq. (9)-(11) (lambda_S = 0.4, lambda_C = 0.1, k = 100), gradients
+ * loss of Eq. (9)-(11) (lambda_S = 0.4, lambda_C = 0.1, k = 100 for samples
+ * lit from above and 1000 for samples lit from below), gradients
  * by hand-written backward kernels, Adam with FP64 moments on FP32 masters.
  *   batch        device G-buffer, or NULL to draw cfg->batch samples with
  *                fabric_make_batch(cfg->seed)

@@ -199,10 +199,10 @@ def fabric_encoder_backward(ctx, enc_params, grad_latents, grad_enc_params, stre
 
 
 def fabric_make_batch(ctx, seed: int, n: int, r_lo: float, r_hi: float, out: DeviceGBuffer,
-                      stream=None) -> None:
+                      btdf_frac: float = 0.0, stream=None) -> None:
     os_ = out.c_struct(_abi.fabric_gbuffer_out)
-    check(_abi.lib().fabric_make_batch(ctx, ctypes.c_uint64(seed), n, r_lo, r_hi, ctypes.byref(os_),
-                                       _stream(stream)), "fabric_make_batch")
+    check(_abi.lib().fabric_make_batch(ctx, ctypes.c_uint64(seed), n, r_lo, r_hi, btdf_frac,
+                                       ctypes.byref(os_), _stream(stream)), "fabric_make_batch")
 
 
 def _train_cfg(cfg: dict) -> _abi.fabric_train_cfg:
@@ -210,7 +210,7 @@ def _train_cfg(cfg: dict) -> _abi.fabric_train_cfg:
         int(cfg.get("batch", 1 << 20)), int(cfg.get("gt_samples", 256)), int(cfg.get("prec", FABRIC_BF16)),
         int(cfg.get("seed", 0)), float(cfg.get("lr", 1e-3)), float(cfg.get("beta1", 0.9)),
         float(cfg.get("beta2", 0.999)), float(cfg.get("eps", 1e-8)), float(cfg.get("r_lo", 1e-3)),
-        float(cfg.get("r_hi", 0.5)))
+        float(cfg.get("r_hi", 0.5)), float(cfg.get("btdf_frac", 0.0)))
 
 
 def fabric_loss_grad(ctx, batch: Optional[DeviceGBuffer], targets, cfg: dict, grad,

@@ -56,7 +56,7 @@ class fabric_train_cfg(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int64), ("gt_samples", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("seed", ctypes.c_uint64), ("lr", ctypes.c_double),
                 ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
-                ("r_lo", ctypes.c_float), ("r_hi", ctypes.c_float)]
+                ("r_lo", ctypes.c_float), ("r_hi", ctypes.c_float), ("btdf_frac", ctypes.c_float)]
 
 
 EXPORTS = [
@@ -103,7 +103,8 @@ def _declare(L):
     L.fabric_encoder_backward.argtypes = [_P, _P, _P, _P, _P]
     L.fabric_encoder_backward.restype = _S
     L.fabric_make_batch.argtypes = [_P, ctypes.c_uint64, ctypes.c_int64, ctypes.c_float,
-                                    ctypes.c_float, ctypes.POINTER(fabric_gbuffer_out), _P]
+                                    ctypes.c_float, ctypes.c_float,
+                                    ctypes.POINTER(fabric_gbuffer_out), _P]
     L.fabric_make_batch.restype = _S
     L.fabric_loss_grad.argtypes = [_P, ctypes.POINTER(fabric_gbuffer), _P,
                                    ctypes.POINTER(fabric_train_cfg), _P, ctypes.POINTER(ctypes.c_float), _P]

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void decode_kernel(
                     out[c * n + p] = fault ? 0.0f : y[c];
             } else {
                 float rgb[3];
-                compose_rgb<FM>(y[0], y[1], y[2], y[3], fc, rgb);
+                compose_rgb<FM>(y[0], y[1], y[2], y[3], fc, wi.z, rgb);
 #pragma unroll
                 for (int c = 0; c < 3; c++)
                     out[c * n + p] = fault ? 0.0f : rgb[c];
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(256) void decode32_kernel(
     auto shade_tile = [&](const HalfPix &cur, int tile) {
         const int p = tile * 32 + col;
         const bool valid = p < n;
-        const bool fault = pair_any(half_fault(cur, n_fabrics), lane);
+        const bool fault = pair_any(half_fault(cur, n_fabrics, grp), lane);
         // Out-of-range rule (r > 1 cell or wo.z < 0.05), decided before the
         // MFMA chain so that no pixel field stays live through it.
         const bool oor = HYBRID && !fault &&
@@ -194,7 +194,8 @@ __global__ __launch_bounds__(256) void decode32_kernel(
         // Lanes 0..31 hold y[0..3] of pixel tile*32 + lane.
         if (grp == 0 && valid && !oor) {
             float rgb[3];
-            compose_rgb<FM>(y[0] + b4[0], y[1] + b4[1], y[2] + b4[2], y[3] + b4[3], fc, rgb);
+            compose_rgb<FM>(y[0] + b4[0], y[1] + b4[1], y[2] + b4[2], y[3] + b4[3], fc, cur.xz,
+                            rgb);
 #pragma unroll
             for (int c = 0; c < 3; c++)
                 plane_store(out, c * n + p, fault ? 0.0f : rgb[c]);

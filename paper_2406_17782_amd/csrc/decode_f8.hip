@@ -42,7 +42,8 @@ __global__ __launch_bounds__(kCalibBlock) void calib_f8_kernel(
 
     // Sample: fabric uniform over the encoded ones, uv uniform over 8 cells,
     // radius log-uniform over the one-blob encoding's span [2^-14, 4],
-    // cosine-distributed directions.
+    // cosine-distributed directions, a quarter of them lit from below
+    // (transmission queries feed wi.z < 0 to the decoder).
     const uint64_t base = 8ull * (uint64_t)q;
     const uint64_t z0 = splitmix64_at(kCalibSeed, base + 0);
     const uint64_t z1 = splitmix64_at(kCalibSeed, base + 1);
@@ -55,7 +56,9 @@ __global__ __launch_bounds__(kCalibBlock) void calib_f8_kernel(
     float s, c, xi;
     xi = u24_hi(z3);
     sincospif(2.0f * u24_mid(z3), &s, &c);
-    const float3 wi = make_float3(sqrtf(xi) * c, sqrtf(xi) * s, sqrtf(1.0f - xi));
+    const float wz = sqrtf(1.0f - xi);
+    const float3 wi = make_float3(sqrtf(xi) * c, sqrtf(xi) * s,
+                                  u24_hi(splitmix64_at(kCalibSeed, base + 5)) < 0.25f ? -wz : wz);
     xi = u24_hi(z4);
     sincospif(2.0f * u24_mid(z4), &s, &c);
     const float3 wo = make_float3(sqrtf(xi) * c, sqrtf(xi) * s, sqrtf(1.0f - xi));
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
     // Per tile: fault and range decisions, features and the L1 C operand.
     struct Prep {
-        int p, fid;
+        int p, fid;     // fid: the table index, plus kTransmitBit for light from below
         bool valid, fault, oor;
         i32x8 B1;   // L1's B operand
         int x3;     // L3's angular B operand (word 0)
@@ -311,7 +314,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     auto prepare = [&](const HalfPix &cur, int tile, Prep &r, f32x16 (&a)[2]) {
         r.p = tile * 32 + col;
         r.valid = tile < n_tiles && r.p < n;
-        r.fault = pair_any(half_fault(cur, n_fabrics), lane);
+        r.fault = pair_any(half_fault(cur, n_fabrics, grp), lane);
         // Out-of-range rule (r > 1 cell or wo.z < 0.05), decided before the
         // MFMA chain so that no pixel field stays live through it.
         r.oor = HYBRID && !r.fault && pair_any(cur.r > 1.0f || (grp == 1 && cur.xz < 0.05f), lane);
@@ -332,13 +335,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             }
         // group 1's third slot carries L3's bias
         r.x3 = TileF8::l3x_word(cur.x0, cur.x1, grp ? 1.0f : cur.xz);
+        if (grp == 0 && cur.xz < 0.0f)
+            r.fid |= kTransmitBit;   // after every table read above
     };
     auto finish = [&](const Prep &r, const f32x16 &y, int tile) {
         // Lanes 0..31 hold y[0..3] of pixel tile*32 + lane.
         if (grp == 0 && r.valid && !r.oor) {
             float rgb[3];
             compose_rgb<FM>(y[0] + b4[0], y[1] + b4[1], y[2] + b4[2], y[3] + b4[3],
-                            s_fc + r.fid * kFabConsts, rgb);
+                            s_fc + (r.fid & (kTransmitBit - 1)) * kFabConsts,
+                            (r.fid & kTransmitBit) ? -1.0f : 1.0f, rgb);
 #pragma unroll
             for (int c = 0; c < 3; c++)
                 plane_store(out, c * n + r.p, r.fault ? 0.0f : rgb[c]);

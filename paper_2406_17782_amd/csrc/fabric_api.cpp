@@ -738,9 +738,11 @@ fabric_status fabric_encoder_backward(fabric_ctx *ctx, const float *enc_params,
 }
 
 fabric_status fabric_make_batch(fabric_ctx *ctx, uint64_t seed, int64_t n, float r_lo, float r_hi,
-                                const fabric_gbuffer_out *out, void *stream)
+                                float btdf_frac, const fabric_gbuffer_out *out, void *stream)
 {
     if (!ctx || !out || n < 0 || out->n < n || !(r_lo > 0.0f) || !(r_hi >= r_lo) || !finite(r_hi))
+        return FABRIC_E_INVAL;
+    if (!(btdf_frac >= 0.0f && btdf_frac <= 1.0f))
         return FABRIC_E_INVAL;
     if (n > 0 && !(out->fabric_id && out->u && out->v && out->radius && out->wi_x && out->wi_y &&
                    out->wi_z && out->wo_x && out->wo_y && out->wo_z))
@@ -750,7 +752,8 @@ fabric_status fabric_make_batch(fabric_ctx *ctx, uint64_t seed, int64_t n, float
     if (n == 0)
         return FABRIC_OK;
     DeviceGuard guard(ctx->device);
-    return from_hip(launch_make_batch(seed, n, ctx->n_mats, r_lo, r_hi, *out, as_stream(stream)));
+    return from_hip(launch_make_batch(seed, n, ctx->n_mats, r_lo, r_hi, btdf_frac, *out,
+                                      as_stream(stream)));
 }
 
 namespace {
@@ -768,6 +771,8 @@ fabric_status check_train_args(fabric_ctx *ctx, const fabric_gbuffer *batch, con
     if (!targets && !perfect_square(cfg->gt_samples))
         return FABRIC_E_INVAL;
     if (cfg->prec != FABRIC_FP32 && cfg->prec != FABRIC_BF16)
+        return FABRIC_E_INVAL;
+    if (!batch && !(cfg->btdf_frac >= 0.0f && cfg->btdf_frac <= 1.0f))
         return FABRIC_E_INVAL;
     if (!std::isfinite(cfg->lr) || cfg->lr < 0.0 || !(cfg->beta1 >= 0.0 && cfg->beta1 < 1.0) ||
         !(cfg->beta2 >= 0.0 && cfg->beta2 < 1.0) || !(cfg->eps > 0.0))

@@ -228,15 +228,22 @@ __device__ inline SampleVal eval_surface_point(const DevFabric &f, float us, flo
     float ci = wi.x * n.x + wi.y * n.y + wi.z * n.z;
     float co = wo.x * n.x + wo.y * n.y + wo.z * n.z;
     out.area = vis_o ? fmaxf(co, 0.0f) * jac : 0.0f;
-    if (!(ci > 0.0f && co > 0.0f && vis_o) || (VIS && !vis_march(tex, vf, ta, tb, wi))) {
+    // Light below the fabric is transmitted (it must reach the ply from
+    // below too); light above is reflected (from above the ply).  Light from
+    // below is not shadowed by the height field.
+    const bool transmit = wi.z < 0.0f;
+    const bool lit = transmit ? ci < 0.0f : ci > 0.0f;
+    if (!(lit && co > 0.0f && vis_o) || (VIS && !transmit && !vis_march(tex, vf, ta, tb, wi))) {
         out.num_c = 0.0f;
         out.num_s = 0.0f;
         return out;
     }
+    const float aci = fabsf(ci);
     // Specular: fiber SGGX with S = I - (1 - alpha^2) t t^T, so that
     // h^T S^-1 h = 1 + (1/alpha^2 - 1)(h.t)^2 and w^T S w = 1 - (1 - alpha^2)(w.t)^2.
     float hx = wi.x + wo.x, hy = wi.y + wo.y, hz = wi.z + wo.z;
-    float hr = rsqrtf(hx * hx + hy * hy + hz * hz);
+    const float h2 = hx * hx + hy * hy + hz * hz;
+    float hr = rsqrtf(h2);
     float ht = (hx * tp.x + hy * tp.y + hz * tp.z) * hr;
     float it = wi.x * tp.x + wi.y * tp.y + wi.z * tp.z;
     float ot = wo.x * tp.x + wo.y * tp.y + wo.z * tp.z;
@@ -244,16 +251,30 @@ __device__ inline SampleVal eval_surface_point(const DevFabric &f, float us, flo
     float D = f.inv_pi_alpha[y] * rcp(q * q);
     float sig_i = sqrtf(fmaxf(1.0f - f.alpha2m1[y] * it * it, 0.0f));
     float sig_o = sqrtf(fmaxf(1.0f - f.alpha2m1[y] * ot * ot, 0.0f));
-    float L = sig_i * rcp(ci) + sig_o * rcp(co);
-    // L >= sigma_i + sigma_o >= 2 alpha, so 1 - e^{-2L} loses at most a few
-    // ulps to cancellation for the roughness range of fabrics.
-    float G = (1.0f - __expf(-kTRho * L)) * rcp(L);
-    // rho_s * A = D G / (4 ci co) * ci * co * jac
+    const float lam_i = sig_i * rcp(aci), lam_o = sig_o * rcp(co);
+    float G;
+    if (!transmit) {
+        // L >= sigma_i + sigma_o >= 2 alpha, so 1 - e^{-2L} loses at most a
+        // few ulps to cancellation for the roughness range of fabrics.
+        const float L = lam_i + lam_o;
+        G = (1.0f - __expf(-kTRho * L)) * rcp(L);
+    } else {
+        // Single scattering between the slab's faces:
+        // (e^{-T Lo} - e^{-T Li}) / (Li - Lo) = e^{-T m} (1 - e^{-T d}) / d
+        // with m = min(Li, Lo) and d = |Li - Lo| (no overflow for either
+        // order), 1 - e^{-T d} by expm1 so that it stays accurate (and the
+        // quotient tends to T) as d -> 0.  Straight-through light has no flake.
+        const float d = fabsf(lam_i - lam_o);
+        const float frac = d > 0.0f ? -expm1f(-kTRho * d) / d : kTRho;
+        G = h2 > 1e-18f ? __expf(-kTRho * fminf(lam_i, lam_o)) * frac : 0.0f;
+    }
+    // rho_s * A = D G / (4 |ci| co) * |ci| * co * jac
     out.num_s = 0.25f * D * G * jac;
-    // Blended Lambertian of Eq. (1) per unit k_d, times <wi.n_p> and A.
+    // Blended Lambertian of Eq. (1) per unit k_d, times <wi.n_p> and A; in
+    // transmission its Lambertian share (1 - w)/pi.
     float w = f.wblend[y];
-    float fd = (w * ci * rcp(wi.z) + (1.0f - w)) * (1.0f / kPi);
-    out.num_c = fd * ci * out.area;
+    float fd = (transmit ? (1.0f - w) : (w * ci * rcp(wi.z) + (1.0f - w))) * (1.0f / kPi);
+    out.num_c = fd * aci * out.area;
     return out;
 }
 
@@ -274,7 +295,7 @@ __device__ inline bool pixel_fault(int fid, int n_fabrics, float u, float v, flo
     bool finite = isfinite(u) && isfinite(v) && isfinite(r) && isfinite(wi.x) &&
                   isfinite(wi.y) && isfinite(wi.z) && isfinite(wo.x) && isfinite(wo.y) &&
                   isfinite(wo.z);
-    return !finite || fid >= n_fabrics || !(r > 0.0f) || !(wi.z > 0.0f) || !(wo.z > 0.0f);
+    return !finite || fid >= n_fabrics || !(r > 0.0f) || wi.z == 0.0f || !(wo.z > 0.0f);
 }
 
 // Wave-wide FP64 footprint estimate for one pixel: lanes take samples

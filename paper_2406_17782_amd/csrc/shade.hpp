@@ -9,6 +9,8 @@
 namespace fab {
 
 constexpr int kFabConsts = 16;   // per fabric in LDS: fwx fwy 1/wx 1/wy kd[2][3] ks[2][3]
+// Set in a carried fabric index when the pixel's light is below the fabric.
+constexpr int kTransmitBit = 1 << 16;
 
 // Out-of-range rule of the hybrid frame: footprint above one cell or a
 // grazing view.
@@ -77,12 +79,14 @@ __device__ inline HalfPix load_half(const fabric_gbuffer &g, const HalfPlanes &h
     x.xz = h.xz[p];
     return x;
 }
-// This lane group's share of the fault rule of pixel_fault.
-__device__ inline bool half_fault(const HalfPix &x, int n_fabrics)
+// This lane group's share of the fault rule of pixel_fault (group 0 holds
+// wi, which may point below the fabric, group 1 wo).
+__device__ inline bool half_fault(const HalfPix &x, int n_fabrics, int grp)
 {
     const bool finite = isfinite(x.uv) && isfinite(x.r) && isfinite(x.x0) && isfinite(x.x1) &&
                         isfinite(x.xz);
-    return !finite || x.fid >= n_fabrics || !(x.r > 0.0f) || !(x.xz > 0.0f);
+    return !finite || x.fid >= n_fabrics || !(x.r > 0.0f) ||
+           (grp ? !(x.xz > 0.0f) : x.xz == 0.0f);
 }
 // True in both lanes of a pixel (lanes l and l ^ 32) when either flag is set.
 __device__ inline bool pair_any(bool flag, int lane)
@@ -111,16 +115,19 @@ __device__ inline void stage_fabric_consts(const DevFabric *__restrict__ fabrics
     }
 }
 
-// Decoded components (Eq. (8)): C = max(y, 0), S = max((e^y - 1) / 100, 0),
+// Decoded components (Eq. (8)): C = max(y, 0), S = max((e^y - 1) / k, 0)
+// with k = 100 for reflection and 1000 for transmission (wi_z < 0, Sec. 4.2),
 // composed with the fabric's albedos fc[4..15] into rgb (the 1/100 of S is
-// folded into the staged specular albedos).
+// folded into the staged specular albedos, the further 1/10 of transmission
+// applied here).
 template <typename FM>
 __device__ inline void compose_rgb(float y0, float y1, float y2, float y3, const float *fc,
-                                   float (&rgb)[3])
+                                   float wi_z, float (&rgb)[3])
 {
     const float cw = fmaxf(y0, 0.0f), cwf = fmaxf(y1, 0.0f);
-    const float sw = fmaxf(FM::expm1(y2), 0.0f);
-    const float sf = fmaxf(FM::expm1(y3), 0.0f);
+    const float ks = wi_z < 0.0f ? 0.1f : 1.0f;
+    const float sw = fmaxf(FM::expm1(y2), 0.0f) * ks;
+    const float sf = fmaxf(FM::expm1(y3), 0.0f) * ks;
 #pragma unroll
     for (int c = 0; c < 3; c++)
         rgb[c] = fc[4 + c] * cw + fc[7 + c] * cwf + fc[10 + c] * sw + fc[13 + c] * sf;

@@ -55,7 +55,7 @@ constexpr int kEncActFloats = kEncIn + 6 * kEncHid + kLatent;
 // ---------------------------------------------------------------------------
 
 __global__ void make_batch_kernel(uint64_t seed, int64_t n, int n_fabrics, float log_lo,
-                                  float log_span, fabric_gbuffer_out out)
+                                  float log_span, float btdf_frac, fabric_gbuffer_out out)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n)
@@ -75,7 +75,9 @@ __global__ void make_batch_kernel(uint64_t seed, int64_t n, int n_fabrics, float
     sincospif(2.0f * u24_mid(z3), &s, &c);
     out.wi_x[q] = sqrtf(xi) * c;
     out.wi_y[q] = sqrtf(xi) * s;
-    out.wi_z[q] = sqrtf(1.0f - xi);
+    // Output 8q+5 lights the sample from below with probability btdf_frac.
+    const float wz = sqrtf(1.0f - xi);
+    out.wi_z[q] = u24_hi(splitmix64_at(seed, base + 5)) < btdf_frac ? -wz : wz;
     xi = u24_hi(z4);
     sincospif(2.0f * u24_mid(z4), &s, &c);
     out.wo_x[q] = sqrtf(xi) * c;
@@ -208,10 +210,12 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(
                 dy[c] = tgt_or_dy[c * n + p];
         } else {
             const float inv_n = 1.0f / (float)n;
+            // g(x) = ln(k x + 1): k = 100 for reflection, 1000 for transmission.
+            const float k = wi.z < 0.0f ? 10.0f * kSpec : kSpec;
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 const float t = tgt_or_dy[c * n + p];
-                const float target = c < 2 ? t : log1pf(kSpec * t);   // g(x) = ln(k x + 1)
+                const float target = c < 2 ? t : log1pf(k * t);
                 const float lam = c < 2 ? 0.1f : 0.4f;                // lambda_C, lambda_S
                 const float d = y[c] - target;
                 loss += (double)(lam * d * d);
@@ -759,13 +763,13 @@ void train_scratch_free(TrainScratch &s)
 }
 
 hipError_t launch_make_batch(uint64_t seed, int64_t n, int n_fabrics, float r_lo, float r_hi,
-                             const fabric_gbuffer_out &out, hipStream_t stream)
+                             float btdf_frac, const fabric_gbuffer_out &out, hipStream_t stream)
 {
     if (n <= 0)
         return hipSuccess;
     const double lo = std::log((double)r_lo), hi = std::log((double)r_hi);
     hipLaunchKernelGGL(make_batch_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
-                       seed, n, n_fabrics, (float)lo, (float)(hi - lo), out);
+                       seed, n, n_fabrics, (float)lo, (float)(hi - lo), btdf_frac, out);
     return hipGetLastError();
 }
 
@@ -829,7 +833,8 @@ hipError_t loss_and_grad(TrainScratch &s, const TrainArgs &a, hipStream_t stream
         const int64_t c = s.batch_cap;
         o.u = f; o.v = f + c; o.radius = f + 2 * c; o.wi_x = f + 3 * c; o.wi_y = f + 4 * c;
         o.wi_z = f + 5 * c; o.wo_x = f + 6 * c; o.wo_y = f + 7 * c; o.wo_z = f + 8 * c;
-        if ((e = launch_make_batch(cfg.seed, n, a.n_fabrics, cfg.r_lo, cfg.r_hi, o, stream)) != hipSuccess)
+        if ((e = launch_make_batch(cfg.seed, n, a.n_fabrics, cfg.r_lo, cfg.r_hi, cfg.btdf_frac, o,
+                                   stream)) != hipSuccess)
             return e;
         g.n = n; g.fabric_id = o.fabric_id; g.u = o.u; g.v = o.v; g.radius = o.radius;
         g.wi_x = o.wi_x; g.wi_y = o.wi_y; g.wi_z = o.wi_z; g.wo_x = o.wo_x; g.wo_y = o.wo_y; g.wo_z = o.wo_z;

