@@ -303,6 +303,64 @@ def visibility_row(args, torch, pkg, fi, wl, mats, g, d, neural_ms):
         fab.close()
 
 
+def btdf_row(args, torch, pkg, fi):
+    """Transmission (light below the fabric, Sec. 4.2's BTDF queries): a
+    network trained like the main one on batches with half the samples lit
+    from below (targets with k = 1000), shaded on the 1080p frame whose
+    pixels are half lit from below; the decoder's and the filter's cost on
+    that frame, and RMSE against the FP64 oracle's filter on a seeded 1 %,
+    for the pixels lit from above and from below apart."""
+    import oracle
+    wl = fi.WORKLOADS["btdf_1080p"]
+    mats, g = wl.materials(), wl.gbuffer()
+    d = pkg.DeviceGBuffer.from_host(g)
+    fab = pkg.Fabric(0, seed=wl.seed())
+    try:
+        fab.encode(mats)
+        steps = args.train_steps
+        for s in range(steps):
+            lr = args.train_lr * 0.5 * (1.0 + math.cos(math.pi * s / max(1, steps)))
+            loss = fab.train_step(seed=5_000_000 + s, batch=args.train_batch,
+                                  gt_samples=args.gt_samples, prec=pkg.FABRIC_BF16, lr=lr,
+                                  btdf_frac=0.5, want_loss=(s == steps - 1))
+        fab.encode(mats)
+        out = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
+        shade = lambda: pkg.fabric_shade_gbuffer(fab.ctx, d, pkg.PREC["bf16"], 0, 0, out)
+        for _ in range(args.warmup // 2):
+            shade()
+        s_ms = time_launches(torch, shade, args.steps // 2)
+        rgb = out.cpu().numpy()
+        filt = lambda: pkg.fabric_gt_filtered(fab.ctx, d, args.gt_samples, 4242, out, None)
+        filt()
+        f_ms = time_launches(torch, filt, args.analytic_steps)
+        pkg.fabric_gt_filtered(fab.ctx, d, 1, 777, out, None)
+        one = out.cpu().numpy()
+        res = {"workload": "btdf_1080p", "below_frac": float((g.wi_z < 0).mean()),
+               "train_steps": steps, "train_btdf_frac": 0.5, "loss_last": loss,
+               "bf16_ms_per_frame": s_ms, "bf16_mpix_per_s": g.n / (s_ms * 1e-3) / 1e6,
+               "filter_ms_per_frame": f_ms, "neural_bf16_over_filter": f_ms / s_ms}
+        if not args.no_rmse:
+            idx = fi.subset_indices(g.n, args.rmse_frac, 99)
+            _, o_rgb, _, _ = oracle.filter_gbuffer(mats, g.subset(idx), args.gt_samples, 4242,
+                                                   same_sample=True, pixel_index=idx)
+            below = g.wi_z[idx] < 0
+            res["rmse_vs_fp64_oracle"] = {}
+            for name, m in (("lit_from_above", ~below), ("lit_from_below", below)):
+                res["rmse_vs_fp64_oracle"][name] = {
+                    "pixels": int(m.sum()),
+                    "neural_bf16": rmse_stats(rgb[:, idx][:, m], o_rgb[:, m]),
+                    "analytic_1spp": rmse_stats(one[:, idx][:, m], o_rgb[:, m])}
+            e = res["rmse_vs_fp64_oracle"]
+            log(f"btdf: bf16 {s_ms * 1e3:.1f} us/frame, filter {f_ms:.2f} ms; rmse above "
+                f"{e['lit_from_above']['neural_bf16']['rmse']:.4g} (1spp "
+                f"{e['lit_from_above']['analytic_1spp']['rmse']:.4g}), below "
+                f"{e['lit_from_below']['neural_bf16']['rmse']:.4g} (1spp "
+                f"{e['lit_from_below']['analytic_1spp']['rmse']:.4g})")
+        return res
+    finally:
+        fab.close()
+
+
 def interp_row(args, torch, pkg, fi, g, d):
     """Latent interpolation study (Sec. 5 "Interpolation") on the 1080p
     frame's geometry: a second network trained on variants of one twill whose
@@ -544,6 +602,7 @@ def main():
         fab.encode(mats)
         rows["latent_interpolation"] = interp_row(args, torch, pkg, fi, g, d)
         rows["visibility"] = visibility_row(args, torch, pkg, fi, wl, mats, g, d, ms)
+        rows["transmission"] = btdf_row(args, torch, pkg, fi)
 
     # ---- error against the FP64 oracle on a seeded pixel subset ----
     errs = None if args.no_rmse else oracle_errors(args, torch, pkg, fi, fab, d, mats, g, rgb, gt_rgb)
