@@ -254,6 +254,7 @@ def visibility_row(args, torch, pkg, fi, wl, mats, g, d, neural_ms):
         fab.encode(mats)
         fab.set_visibility(True)
         steps = args.train_steps
+        loss = None
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         ev0.record()
@@ -318,6 +319,7 @@ def btdf_row(args, torch, pkg, fi):
     try:
         fab.encode(mats)
         steps = args.train_steps
+        loss = None
         for s in range(steps):
             lr = args.train_lr * 0.5 * (1.0 + math.cos(math.pi * s / max(1, steps)))
             loss = fab.train_step(seed=5_000_000 + s, batch=args.train_batch,
