@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void decode_kernel(
     using FM = FeatureMath<P>;
 
     // LDS: C-operand biases of L2..L4 [kBiasFrags][64 lanes], then per fabric
-    // c_f [64] and constants [kFabConsts].
+    // c_f [64], then the staged constants [kFabCopies][n_fabrics][kFabConsts].
     extern __shared__ f32x4 smem4[];
     f32x4 *s_bias = smem4;
     float *s_cf = (float *)(smem4 + kBiasFrags * 64);
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void decode_kernel(
         // Only the table index needs a safe value: non-finite inputs stay in
         // their own pixel's column of every MFMA tile and are zeroed on output.
         fid = fault ? 0 : fid;
-        const float *fc = s_fc + fid * kFabConsts;
+        const float *fc = s_fc + fab_entry(fid, n_fabrics, wi.z) * kFabConsts;
 
         float s1[T::NS1];
         T::spatial_slots(u, v, r, fc[0], fc[1], fc[2], fc[3], grp, s1);
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void decode_kernel(
                     out[c * n + p] = fault ? 0.0f : y[c];
             } else {
                 float rgb[3];
-                compose_rgb<FM>(y[0], y[1], y[2], y[3], fc, wi.z, rgb);
+                compose_rgb<FM>(y[0], y[1], y[2], y[3], fc, rgb);
 #pragma unroll
                 for (int c = 0; c < 3; c++)
                     out[c * n + p] = fault ? 0.0f : rgb[c];
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void decode32_kernel(
     using FM = FeatureMath<P>;
 
     // LDS: L2 C-operand bias [2][64 lanes][4 x f32x4], then per fabric c_f [64]
-    // and constants [kFabConsts].
+    // then the staged constants [kFabCopies][n_fabrics][kFabConsts].
     extern __shared__ f32x4 smem4[];
     f32x4 *s_b2 = smem4;
     float *s_cf = (float *)(smem4 + 2 * 64 * 4);
@@ -170,7 +170,8 @@ __global__ __launch_bounds__(256) void decode32_kernel(
         // Only the table index needs a safe value: non-finite inputs stay in
         // their own pixel's column of every MFMA tile and are zeroed on output.
         const int fid = fault ? 0 : cur.fid;
-        const float *fc = s_fc + fid * kFabConsts;
+        // Group 0 holds wi and composes; group 1 only reads the periods.
+        const float *fc = s_fc + fab_entry(fid, n_fabrics, grp ? 1.0f : cur.xz) * kFabConsts;
 
         float s1[kL1Slots32];
         T::spatial_slots(cur.uv, cur.uv, cur.r, fc[0], fc[1], fc[2], fc[3], grp, s1);
@@ -194,8 +195,7 @@ __global__ __launch_bounds__(256) void decode32_kernel(
         // Lanes 0..31 hold y[0..3] of pixel tile*32 + lane.
         if (grp == 0 && valid && !oor) {
             float rgb[3];
-            compose_rgb<FM>(y[0] + b4[0], y[1] + b4[1], y[2] + b4[2], y[3] + b4[3], fc, cur.xz,
-                            rgb);
+            compose_rgb<FM>(y[0] + b4[0], y[1] + b4[1], y[2] + b4[2], y[3] + b4[3], fc, rgb);
 #pragma unroll
             for (int c = 0; c < 3; c++)
                 plane_store(out, c * n + p, fault ? 0.0f : rgb[c]);
@@ -379,7 +379,7 @@ hipError_t decode32(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fab
     if (blocks > cap)
         blocks = cap;
     const size_t lds = (size_t)2 * 64 * 4 * sizeof(f32x4) +
-                       (size_t)n_fabrics * (64 + kFabConsts) * sizeof(float);
+                       (size_t)n_fabrics * (64 + kFabCopies * kFabConsts) * sizeof(float);
     hipLaunchKernelGGL((decode32_kernel<P, HYBRID>), dim3(blocks), dim3(256), lds, stream, g,
                        fabrics, n_fabrics, cfold, frags, b2, b4, q, out, err, n_tiles);
     return hipGetLastError();
@@ -421,7 +421,7 @@ hipError_t decode(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabri
     if (blocks > cap)
         blocks = cap;
     const size_t lds = (size_t)kBiasFrags * 64 * sizeof(f32x4) +
-                       (size_t)n_fabrics * (64 + kFabConsts) * sizeof(float);
+                       (size_t)n_fabrics * (64 + kFabCopies * kFabConsts) * sizeof(float);
     hipLaunchKernelGGL((decode_kernel<P, RAW, HYBRID>), dim3(blocks), dim3(256), lds,
                        stream, g, fabrics, n_fabrics, cfold, frags, bias, q, out, err, n_tiles);
     return hipGetLastError();

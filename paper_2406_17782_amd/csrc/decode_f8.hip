@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const F8Header hd = *(const F8Header *)(image + kF8HeaderOff);
 
     // LDS: L2 C-operand bias [2][64 lanes][4 x f32x4], then per fabric
-    // 2^eh1 c_f [64] and constants [kFabConsts].
+    // 2^eh1 c_f [64], then the staged constants [kFabCopies][n_fabrics][kFabConsts].
     extern __shared__ f32x4 smem4[];
     f32x4 *s_b2 = smem4;
     float *s_cf = (float *)(smem4 + 2 * 64 * 4);
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
     // Per tile: fault and range decisions, features and the L1 C operand.
     struct Prep {
-        int p, fid;     // fid: the table index, plus kTransmitBit for light from below
+        int p, fid;     // fid: the staged-constant entry (transmission copy for light from below)
         bool valid, fault, oor;
         i32x8 B1;   // L1's B operand
         int x3;     // L3's angular B operand (word 0)
@@ -335,16 +335,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             }
         // group 1's third slot carries L3's bias
         r.x3 = TileF8::l3x_word(cur.x0, cur.x1, grp ? 1.0f : cur.xz);
-        if (grp == 0 && cur.xz < 0.0f)
-            r.fid |= kTransmitBit;   // after every table read above
+        r.fid = fab_entry(r.fid, n_fabrics, grp ? 1.0f : cur.xz);   // after the c_f reads above
     };
     auto finish = [&](const Prep &r, const f32x16 &y, int tile) {
         // Lanes 0..31 hold y[0..3] of pixel tile*32 + lane.
         if (grp == 0 && r.valid && !r.oor) {
             float rgb[3];
             compose_rgb<FM>(y[0] + b4[0], y[1] + b4[1], y[2] + b4[2], y[3] + b4[3],
-                            s_fc + (r.fid & (kTransmitBit - 1)) * kFabConsts,
-                            (r.fid & kTransmitBit) ? -1.0f : 1.0f, rgb);
+                            s_fc + r.fid * kFabConsts, rgb);
 #pragma unroll
             for (int c = 0; c < 3; c++)
                 plane_store(out, c * n + r.p, r.fault ? 0.0f : rgb[c]);
@@ -420,7 +418,7 @@ hipError_t launch_decode_f8(const fabric_gbuffer &g, const DevFabric *fabrics, i
     if (blocks > cap)
         blocks = cap;
     const size_t lds = (size_t)2 * 64 * 4 * sizeof(f32x4) +
-                       (size_t)n_fabrics * (64 + kFabConsts) * sizeof(float);
+                       (size_t)n_fabrics * (64 + kFabCopies * kFabConsts) * sizeof(float);
     if (hybrid)
         hipLaunchKernelGGL(decode_f8_kernel<true>, dim3(blocks), dim3(256), lds, stream, g,
                            fabrics, n_fabrics, cfold, (const char *)image, q, out, err, n_tiles);

@@ -9,8 +9,16 @@
 namespace fab {
 
 constexpr int kFabConsts = 16;   // per fabric in LDS: fwx fwy 1/wx 1/wy kd[2][3] ks[2][3]
-// Set in a carried fabric index when the pixel's light is below the fabric.
-constexpr int kTransmitBit = 1 << 16;
+// The staged constants hold two copies of the fabric table: entries
+// 0 .. n-1 with the specular albedos divided by k = 100 (reflection), entries
+// n .. 2n-1 divided by k = 1000 (transmission, wi.z < 0).
+constexpr int kFabCopies = 2;
+
+// Staged-constant entry of fabric fid for a pixel lit from below or above.
+__device__ inline int fab_entry(int fid, int n_fabrics, float wi_z)
+{
+    return wi_z < 0.0f ? fid + n_fabrics : fid;
+}
 
 // Out-of-range rule of the hybrid frame: footprint above one cell or a
 // grazing view.
@@ -95,14 +103,17 @@ __device__ inline bool pair_any(bool flag, int lane)
     return (((m | (m >> 32) | (m << 32)) >> lane) & 1ull) != 0;
 }
 
-// Block-cooperative fill of the per-fabric constants s_fc[n_fabrics][16]:
-// fwx, fwy, 1/wx, 1/wy, kd (warp, weft RGB), ks / 100 (warp, weft RGB).  The
-// specular albedos carry the 1/100 of the decoding S = (e^y - 1) / 100.
+// Block-cooperative fill of the per-fabric constants s_fc[2 n_fabrics][16]:
+// fwx, fwy, 1/wx, 1/wy, kd (warp, weft RGB), ks / k (warp, weft RGB).  The
+// specular albedos carry the 1/k of the decoding S = (e^y - 1) / k: k = 100
+// in the first copy, 1000 in the second (transmission, Sec. 4.2).
 __device__ inline void stage_fabric_consts(const DevFabric *__restrict__ fabrics, int n_fabrics,
                                            float *s_fc)
 {
-    for (int k = threadIdx.x; k < n_fabrics * kFabConsts; k += blockDim.x) {
-        const DevFabric &f = fabrics[k / kFabConsts];
+    for (int k = threadIdx.x; k < kFabCopies * n_fabrics * kFabConsts; k += blockDim.x) {
+        const int entry = k / kFabConsts;
+        const bool transmit = entry >= n_fabrics;
+        const DevFabric &f = fabrics[transmit ? entry - n_fabrics : entry];
         const int c = k % kFabConsts;
         float val;
         if (c == 0) val = f.fwx;
@@ -110,24 +121,22 @@ __device__ inline void stage_fabric_consts(const DevFabric *__restrict__ fabrics
         else if (c == 2) val = f.inv_wx;
         else if (c == 3) val = f.inv_wy;
         else if (c < 10) val = f.kd[(c - 4) / 3][(c - 4) % 3];
-        else val = f.ks[(c - 10) / 3][(c - 10) % 3] * (1.0f / kSpec);
+        else val = f.ks[(c - 10) / 3][(c - 10) % 3] * (transmit ? 0.1f / kSpec : 1.0f / kSpec);
         s_fc[k] = val;
     }
 }
 
 // Decoded components (Eq. (8)): C = max(y, 0), S = max((e^y - 1) / k, 0)
-// with k = 100 for reflection and 1000 for transmission (wi_z < 0, Sec. 4.2),
-// composed with the fabric's albedos fc[4..15] into rgb (the 1/100 of S is
-// folded into the staged specular albedos, the further 1/10 of transmission
-// applied here).
+// with k = 100 for reflection and 1000 for transmission (Sec. 4.2), composed
+// with the albedos fc[4..15] of the pixel's staged entry into rgb (the 1/k
+// of S is folded into the entry's specular albedos).
 template <typename FM>
 __device__ inline void compose_rgb(float y0, float y1, float y2, float y3, const float *fc,
-                                   float wi_z, float (&rgb)[3])
+                                   float (&rgb)[3])
 {
     const float cw = fmaxf(y0, 0.0f), cwf = fmaxf(y1, 0.0f);
-    const float ks = wi_z < 0.0f ? 0.1f : 1.0f;
-    const float sw = fmaxf(FM::expm1(y2), 0.0f) * ks;
-    const float sf = fmaxf(FM::expm1(y3), 0.0f) * ks;
+    const float sw = fmaxf(FM::expm1(y2), 0.0f);
+    const float sf = fmaxf(FM::expm1(y3), 0.0f);
 #pragma unroll
     for (int c = 0; c < 3; c++)
         rgb[c] = fc[4 + c] * cw + fc[7 + c] * cwf + fc[10 + c] * sw + fc[13 + c] * sf;
