@@ -355,9 +355,27 @@ def init_params(seed: int, bias_scale: float = 0.0) -> np.ndarray:
     return _f32(np.concatenate(out))
 
 
-def random_latents(n_fabrics: int, seed: int, scale: float = 1.0) -> np.ndarray:
+def random_latents(n_fabrics: int, seed: int, scale: float = 1.0, dim: int = 32) -> np.ndarray:
     rng = np.random.default_rng(seed)
-    return _f32(rng.normal(0.0, scale, size=(n_fabrics, 32)))
+    return _f32(rng.normal(0.0, scale, size=(n_fabrics, dim)))
+
+
+# The decoder at the paper's own form (latent 64, 24 one-blob channels, two
+# fusion and five angular layers of width 64): rows x columns per layer
+# [F1 (z, blob), F2, A1 (s, wi.xyz, wo.xy), A2, A3, A4, A5].
+PAPER_DECODER_SHAPES = [(64, 88), (64, 64), (64, 69), (64, 64), (64, 64), (64, 64), (4, 64)]
+N_PAPER_DECODER_PARAMS = _layer_sizes(PAPER_DECODER_SHAPES)   # 27,076
+
+
+def init_paper_params(seed: int, bias_scale: float = 0.0) -> np.ndarray:
+    """Paper-size decoder parameters, Kaiming-uniform like init_params."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for o, i in PAPER_DECODER_SHAPES:
+        bound = math.sqrt(6.0 / i)
+        out.append(rng.uniform(-bound, bound, size=o * i))
+        out.append(rng.uniform(-bias_scale, bias_scale, size=o) if bias_scale > 0 else np.zeros(o))
+    return _f32(np.concatenate(out))
 
 
 def random_targets(n: int, seed: int) -> np.ndarray:

@@ -91,6 +91,11 @@ def lib():
         L.orc_decoder_batch.restype = ctypes.c_int64
         L.orc_decoder_batch.argtypes = [_P, _P, _P, ctypes.c_int, _P, _P, _P]
         L.orc_encoder_input.argtypes = [_P, _P]
+        L.orc_paper_param_count.restype = ctypes.c_int
+        L.orc_paper_features.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_int, _P]
+        L.orc_paper_decoder_batch.restype = ctypes.c_int64
+        L.orc_paper_decoder_batch.argtypes = [_P, _P, _P, ctypes.c_int, _P, _P, _P]
         L.orc_encoder_batch.argtypes = [_P, _P, ctypes.c_int, _P]
         L.orc_loss_grad.restype = ctypes.c_double
         L.orc_loss_grad.argtypes = [_P, _P, ctypes.c_int, _P, _P, _P, _P]
@@ -279,6 +284,30 @@ def decoder_gbuffer(params, latents, mats: Sequence, g):
     y = np.zeros((4, n))
     rgb = np.zeros((3, n))
     lib().orc_decoder_batch(_ptr(P), _ptr(Z), materials(mats), len(mats), h.ref, _ptr(y), _ptr(rgb))
+    return y, rgb
+
+
+def paper_param_count() -> int:
+    return int(lib().orc_paper_param_count())
+
+
+def paper_features(u: float, v: float, r: float, wx: int, wy: int) -> np.ndarray:
+    """One-blob footprint encoding of the paper-size decoder (24 channels)."""
+    f = np.zeros(24)
+    lib().orc_paper_features(u, v, r, wx, wy, _ptr(f))
+    return f
+
+
+def paper_decoder_gbuffer(params, latents, mats: Sequence, g):
+    """Paper-size decoder forward: raw outputs y [4,n] and composed rgb [3,n]."""
+    h = _GBufHolder(g)
+    n = h.s.n
+    P = _d(params)
+    Z = _d(latents).reshape(-1)
+    y = np.zeros((4, n))
+    rgb = np.zeros((3, n))
+    lib().orc_paper_decoder_batch(_ptr(P), _ptr(Z), materials(mats), len(mats), h.ref, _ptr(y),
+                                  _ptr(rgb))
     return y, rgb
 
 

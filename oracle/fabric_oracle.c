@@ -36,7 +36,10 @@
  *     weave grid + 12 yarn scalars -> residual MLP -> latent 32; decoder:
  *     spatial fusion of latent and encoded footprint, then the angular
  *     decoder with wi.xyz and wo.xy), forward and backward;
- *   - the loss of Eq. (9)-(11) and an Adam step (Kingma and Ba 2015, Alg. 1).
+ *   - the loss of Eq. (9)-(11) and an Adam step (Kingma and Ba 2015, Alg. 1);
+ *   - the decoder at the paper's own form (latent 64, one-blob footprint
+ *     encoding to 24 channels, two fusion layers, a five-layer angular
+ *     decoder with one residual skip, leaky ReLU), forward only.
  *
  * Random numbers: the jitter of footprint samples and the training-batch
  * recipe draw from SplitMix64 (Steele, Lea and Flood, OOPSLA 2014), written
@@ -1019,6 +1022,115 @@ int64_t orc_decoder_batch(const double *P, const double *latents, const orc_mate
             decoder_forward(P, latents + (int64_t)fid * LATENT, s, ang, &A);
             for (int c = 0; c < 4; c++) out[c] = A.y[c];
             decode_outputs(A.y, spec_k(wi[2]), comp);
+            compose_rgb(&mats[fid], comp, c3);
+        }
+        faults += bad;
+        if (y)
+            for (int c = 0; c < 4; c++) y[(int64_t)c * n + p] = out[c];
+        if (rgb)
+            for (int c = 0; c < 3; c++) rgb[(int64_t)c * n + p] = c3[c];
+    }
+    return faults;
+}
+
+/* ---- Paper-size decoder (Sec. 4.2 "Decoder", Fig. "network_whole") ------ */
+
+/* One-blob encoding of the footprint (Sec. 4.2): 3 inputs to 24 channels,
+ * 8 Gaussian bins (exp(-d^2/2), d in bins) each.  The position in the
+ * pattern period, p = (u mod W_x)/W_x, is periodic, so its bins wrap: d is
+ * the circular distance from 8p to the bin centre b + 1/2.  The size is
+ * tau = clamp((log2 r + 14)/16, 0, 1) with ordinary bins.  Channels:
+ * [u bins 0..7, v bins 0..7, size bins 0..7]. */
+#define PBLOB 24
+#define PLATENT 64
+#define PHID 64
+#define PX1 (PLATENT + PBLOB)
+#define PXA1 (PHID + NANG)
+#define P_WF1 0
+#define P_BF1 (P_WF1 + PHID * PX1)
+#define P_WF2 (P_BF1 + PHID)
+#define P_BF2 (P_WF2 + PHID * PHID)
+#define P_WA1 (P_BF2 + PHID)
+#define P_BA1 (P_WA1 + PHID * PXA1)
+#define P_WA2 (P_BA1 + PHID)
+#define P_BA2 (P_WA2 + PHID * PHID)
+#define P_WA3 (P_BA2 + PHID)
+#define P_BA3 (P_WA3 + PHID * PHID)
+#define P_WA4 (P_BA3 + PHID)
+#define P_BA4 (P_WA4 + PHID * PHID)
+#define P_WA5 (P_BA4 + PHID)
+#define P_BA5 (P_WA5 + NOUT * PHID)
+#define N_PDEC (P_BA5 + NOUT)
+/* Leaky ReLU slope. */
+#define ORC_LEAK 0.01
+
+int orc_paper_param_count(void) { return N_PDEC; }
+
+static double lrelu(double x) { return x > 0.0 ? x : ORC_LEAK * x; }
+
+void orc_paper_features(double u, double v, double r, int wx, int wy, double f[PBLOB])
+{
+    double p[2] = {floor_mod(u, wx) / wx, floor_mod(v, wy) / wy};
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 8; b++) {
+            double d = 8.0 * p[a] - (b + 0.5);
+            d -= 8.0 * floor((d + 4.0) / 8.0);     /* circular distance in [-4, 4) */
+            f[8 * a + b] = exp(-0.5 * d * d);
+        }
+    double tau = (log2(r) + 14.0) / 16.0;
+    if (tau < 0.0) tau = 0.0;
+    if (tau > 1.0) tau = 1.0;
+    for (int b = 0; b < 8; b++) {
+        double d = 8.0 * tau - (b + 0.5);
+        f[16 + b] = exp(-0.5 * d * d);
+    }
+}
+
+/* Spatial fusion: two FC layers over [z, one-blob]; angular decoder: five
+ * FC layers over [spatial feature, wi.xyz, wo.xy], the second and third a
+ * residual block whose input is added before the block's last activation;
+ * leaky ReLU after every layer but the output. */
+static void paper_forward(const double *P, const double *z, const double f[PBLOB],
+                          const double ang[NANG], double y[NOUT])
+{
+    double x1[PX1], t[PHID], sp[PHID], xa[PXA1], x[PHID], h[PHID], rr[PHID], g[PHID];
+    for (int k = 0; k < PLATENT; k++) x1[k] = z[k];
+    for (int k = 0; k < PBLOB; k++) x1[PLATENT + k] = f[k];
+    dense(P + P_WF1, P + P_BF1, x1, PX1, PHID, t);
+    for (int k = 0; k < PHID; k++) t[k] = lrelu(t[k]);
+    dense(P + P_WF2, P + P_BF2, t, PHID, PHID, sp);
+    for (int k = 0; k < PHID; k++) sp[k] = lrelu(sp[k]);
+    for (int k = 0; k < PHID; k++) xa[k] = sp[k];
+    for (int k = 0; k < NANG; k++) xa[PHID + k] = ang[k];
+    dense(P + P_WA1, P + P_BA1, xa, PXA1, PHID, x);
+    for (int k = 0; k < PHID; k++) x[k] = lrelu(x[k]);
+    dense(P + P_WA2, P + P_BA2, x, PHID, PHID, h);
+    for (int k = 0; k < PHID; k++) h[k] = lrelu(h[k]);
+    dense(P + P_WA3, P + P_BA3, h, PHID, PHID, rr);
+    for (int k = 0; k < PHID; k++) rr[k] = lrelu(rr[k] + x[k]);
+    dense(P + P_WA4, P + P_BA4, rr, PHID, PHID, g);
+    for (int k = 0; k < PHID; k++) g[k] = lrelu(g[k]);
+    dense(P + P_WA5, P + P_BA5, g, PHID, NOUT, y);
+}
+
+/* The paper-size decoder over a G-buffer with per-fabric latents
+ * z[nmats][64]: raw outputs y [4][n] and composed rgb [3][n] (decoded and
+ * composed as the shading path does); faulted pixels give 0. */
+int64_t orc_paper_decoder_batch(const double *P, const double *latents, const orc_material *mats,
+                                int nmats, const orc_gbuffer *g, double *y, double *rgb)
+{
+    int64_t n = g->n, faults = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : faults)
+    for (int64_t p = 0; p < n; p++) {
+        int fid;
+        double u, v, r, wi[3], wo[3], out[4] = {0, 0, 0, 0}, c3[3] = {0, 0, 0};
+        load_pixel(g, p, &fid, &u, &v, &r, wi, wo);
+        int bad = pixel_fault(nmats, fid, u, v, r, wi, wo);
+        if (!bad) {
+            double f[PBLOB], ang[NANG] = {wi[0], wi[1], wi[2], wo[0], wo[1]}, comp[4];
+            orc_paper_features(u, v, r, mats[fid].wx, mats[fid].wy, f);
+            paper_forward(P, latents + (int64_t)fid * PLATENT, f, ang, out);
+            decode_outputs(out, spec_k(wi[2]), comp);
             compose_rgb(&mats[fid], comp, c3);
         }
         faults += bad;
