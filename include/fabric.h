@@ -75,6 +75,8 @@ typedef enum {
 #define FABRIC_N_ENCODER_PARAMS 104352
 #define FABRIC_N_PARAMS (FABRIC_N_DECODER_PARAMS + FABRIC_N_ENCODER_PARAMS)
 #define FABRIC_MAX_SAMPLES 16384
+#define FABRIC_PAPER_LATENT 64
+#define FABRIC_N_PAPER_DECODER_PARAMS 27076
 
 /* One fabric: the weave pattern and the Table 1 parameters per yarn type
  * ([0] = warp, [1] = weft).  Host memory, copied by fabric_encode.
@@ -192,6 +194,33 @@ fabric_status fabric_set_visibility(fabric_ctx *ctx, int32_t enable);
  * after the copies of the host arrays; the kernels run on `stream`. */
 fabric_status fabric_lerp_latents(fabric_ctx *ctx, const int32_t *dst, const int32_t *a,
                                   const int32_t *b, const float *t, int32_t count, void *stream);
+
+/* The decoder at the paper's own form (Sec. 4.2 "Decoder" and its figure):
+ * latent 64; the footprint's position in the pattern period (u, v) and its
+ * size one-blob encoded to 24 channels (8 Gaussian bins exp(-d^2/2) each,
+ * d in bins; position bins circular, size bins over
+ * tau = clamp((log2 r + 14)/16, 0, 1)); spatial fusion by two FC layers
+ * over [z, one-blob]; an angular decoder of five FC layers over
+ * [spatial feature, wi.xyz, wo.xy], the second and third forming a residual
+ * block whose input is added before its last activation; leaky ReLU (0.01)
+ * after every layer but the output; width 64.  Outputs decoded and composed
+ * as fabric_shade_gbuffer does (k = 100, or 1000 where wi.z < 0).  Inference
+ * only, BF16 operands with FP32 accumulation.
+ *   params   device float [FABRIC_N_PAPER_DECODER_PARAMS], rows = outputs:
+ *            WF1[64][88] ([z(64), u bins, v bins, size bins]) bF1[64]
+ *            WF2[64][64] bF2 WA1[64][69] ([s(64), wi.xyz, wo.xy]) bA1
+ *            WA2[64][64] bA2 WA3[64][64] bA3 WA4[64][64] bA4 WA5[4][64] bA5[4]
+ *   latents  device float [n_mats][FABRIC_PAPER_LATENT], for the fabrics of
+ *            the last fabric_encode
+ * fabric_paper_prepare packs the weights and folds each latent into the
+ * first layer (both read once, on `stream`); fabric_paper_shade then shades
+ * like fabric_shade_gbuffer (no fallback), with the fabric table's patterns
+ * and albedos.  E_STATE: prepare before any fabric_encode, shade before
+ * prepare or after a later fabric_encode. */
+fabric_status fabric_paper_prepare(fabric_ctx *ctx, const float *params, const float *latents,
+                                   void *stream);
+fabric_status fabric_paper_shade(fabric_ctx *ctx, const fabric_gbuffer *g, float *out_rgb,
+                                 void *stream);
 
 /* Neural shading of a G-buffer (Sec. 4.3 "Rendering"): per pixel, the
  * decoder's four outputs decoded as C = max(y, 0), S = max((e^y - 1)/k, 0)

@@ -17,14 +17,16 @@ import numpy as np
 from . import _abi
 from ._abi import (FABRIC_BF16, FABRIC_FP8_E4M3, FABRIC_FP16, FABRIC_FP32, FABRIC_LATENT,
                    FABRIC_MAX_FABRICS, FABRIC_MAX_SAMPLES, FABRIC_N_DECODER_PARAMS,
-                   FABRIC_N_ENCODER_PARAMS, FABRIC_N_PARAMS, PREC, FabricError, check)
+                   FABRIC_N_ENCODER_PARAMS, FABRIC_N_PAPER_DECODER_PARAMS, FABRIC_N_PARAMS,
+                   FABRIC_PAPER_LATENT, PREC, FabricError, check)
 
 __all__ = [
     "Fabric", "DeviceGBuffer", "FabricError", "PREC", "FABRIC_FP32", "FABRIC_BF16", "FABRIC_FP16",
     "FABRIC_FP8_E4M3", "FABRIC_N_PARAMS", "FABRIC_N_DECODER_PARAMS", "FABRIC_N_ENCODER_PARAMS",
     "FABRIC_MAX_FABRICS", "FABRIC_MAX_SAMPLES", "FABRIC_LATENT",
     "fabric_create", "fabric_destroy", "fabric_encode", "fabric_set_albedo", "fabric_lerp_latents",
-    "fabric_set_visibility",
+    "fabric_set_visibility", "fabric_paper_prepare", "fabric_paper_shade",
+    "FABRIC_PAPER_LATENT", "FABRIC_N_PAPER_DECODER_PARAMS",
     "fabric_shade_gbuffer", "fabric_gt_filtered", "fabric_decoder_forward",
     "fabric_decoder_backward", "fabric_encoder_forward", "fabric_encoder_backward",
     "fabric_make_batch", "fabric_loss_grad", "fabric_train_step", "fabric_get_params", "fabric_set_params",
@@ -136,6 +138,17 @@ def fabric_set_albedo(ctx, fabric: int, kd, ks, stream=None) -> None:
     ks = np.ascontiguousarray(ks, dtype=np.float32).reshape(2, 3)
     check(_abi.lib().fabric_set_albedo(ctx, fabric, kd.ctypes.data, ks.ctypes.data, _stream(stream)),
           "fabric_set_albedo")
+
+
+def fabric_paper_prepare(ctx, params, latents, stream=None) -> None:
+    check(_abi.lib().fabric_paper_prepare(ctx, _dptr(params), _dptr(latents), _stream(stream)),
+          "fabric_paper_prepare")
+
+
+def fabric_paper_shade(ctx, g: DeviceGBuffer, out_rgb, stream=None) -> None:
+    gs = g.c_struct()
+    check(_abi.lib().fabric_paper_shade(ctx, ctypes.byref(gs), _dptr(out_rgb), _stream(stream)),
+          "fabric_paper_shade")
 
 
 def fabric_set_visibility(ctx, enable: bool) -> None:

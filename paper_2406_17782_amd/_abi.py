@@ -24,6 +24,8 @@ FABRIC_MAX_FABRICS = 256
 FABRIC_MAX_SAMPLES = 16384
 FABRIC_LATENT = 32
 FABRIC_N_DECODER_PARAMS = 13572
+FABRIC_PAPER_LATENT = 64
+FABRIC_N_PAPER_DECODER_PARAMS = 27076
 FABRIC_N_ENCODER_PARAMS = 104352
 FABRIC_N_PARAMS = FABRIC_N_DECODER_PARAMS + FABRIC_N_ENCODER_PARAMS
 
@@ -61,7 +63,7 @@ class fabric_train_cfg(ctypes.Structure):
 
 EXPORTS = [
     "fabric_create", "fabric_destroy", "fabric_status_str", "fabric_encode", "fabric_set_albedo",
-    "fabric_lerp_latents", "fabric_set_visibility",
+    "fabric_lerp_latents", "fabric_set_visibility", "fabric_paper_prepare", "fabric_paper_shade",
     "fabric_shade_gbuffer", "fabric_gt_filtered", "fabric_decoder_forward",
     "fabric_decoder_backward", "fabric_encoder_forward", "fabric_encoder_backward",
     "fabric_make_batch", "fabric_loss_grad", "fabric_train_step", "fabric_get_params", "fabric_set_params",
@@ -87,6 +89,10 @@ def _declare(L):
     L.fabric_lerp_latents.restype = _S
     L.fabric_set_visibility.argtypes = [_P, ctypes.c_int32]
     L.fabric_set_visibility.restype = _S
+    L.fabric_paper_prepare.argtypes = [_P, _P, _P, _P]
+    L.fabric_paper_prepare.restype = _S
+    L.fabric_paper_shade.argtypes = [_P, ctypes.POINTER(fabric_gbuffer), _P, _P]
+    L.fabric_paper_shade.restype = _S
     L.fabric_shade_gbuffer.argtypes = [_P, ctypes.POINTER(fabric_gbuffer), ctypes.c_int,
                                        ctypes.c_int32, ctypes.c_uint64, _P, _P]
     L.fabric_shade_gbuffer.restype = _S

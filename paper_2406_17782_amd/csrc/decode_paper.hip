@@ -1,0 +1,403 @@
+// The decoder at the paper's own form (Sec. 4.2 "Decoder"): latent 64; the
+// footprint's position and size one-blob encoded to 24 channels; spatial
+// fusion by two FC layers; an angular decoder of five FC layers over
+// [spatial feature, wi.xyz, wo.xy] whose second and third layers form a
+// residual block (the block's input added before its last activation);
+// leaky ReLU (slope 0.01) after every layer but the output.  Width 64.
+//
+// BF16 operands on 32x32x16 MFMA with FP32 accumulation, 32-pixel tiles in
+// the layout of the config decoder's shading kernel (lane group g = l/32
+// owns chained neurons 32 mb + 8 (r/4) + 4 g + r%4; one layer's output is
+// the next layer's B operand without data movement).  The 58 weight
+// fragments (58 KB) stay in LDS and are read before each MFMA, which leaves
+// the registers to four waves per SIMD; each layer's bias rides in a K slot
+// that holds 1 (the first extra slot of lane group 0): layer F1's bias is
+// folded with the latent into the per-fabric C operand c_f, A1's extra slots
+// carry wi.xyz / wo.xy / 1 as in the config decoder, A3's C operand is the
+// residual x, A5's bias is added after the MFMA.
+#include "kernels.hpp"
+#include "mlp_tile32.hpp"
+#include "model.hpp"
+#include "shade.hpp"
+
+namespace fab {
+
+namespace {
+
+constexpr int kPLat = 64;                      // latent size
+constexpr int kPBlob = 24;                     // one-blob channels
+constexpr int kPX1 = kPLat + kPBlob;           // F1 inputs
+constexpr int kPXA1 = 64 + 5;                  // A1 inputs
+// Parameter offsets (rows = outputs, row-major), layers F1 F2 A1 A2 A3 A4 A5.
+constexpr int kPOffWF1 = 0;
+constexpr int kPOffBF1 = kPOffWF1 + 64 * kPX1;
+constexpr int kPOffWF2 = kPOffBF1 + 64;
+constexpr int kPOffBF2 = kPOffWF2 + 64 * 64;
+constexpr int kPOffWA1 = kPOffBF2 + 64;
+constexpr int kPOffBA1 = kPOffWA1 + 64 * kPXA1;
+constexpr int kPOffWA2 = kPOffBA1 + 64;
+constexpr int kPOffBA2 = kPOffWA2 + 64 * 64;
+constexpr int kPOffWA3 = kPOffBA2 + 64;
+constexpr int kPOffBA3 = kPOffWA3 + 64 * 64;
+constexpr int kPOffWA4 = kPOffBA3 + 64;
+constexpr int kPOffBA4 = kPOffWA4 + 64 * 64;
+constexpr int kPOffWA5 = kPOffBA4 + 64;
+constexpr int kPOffBA5 = kPOffWA5 + 4 * 64;
+constexpr int kPNDec = kPOffBA5 + 4;
+static_assert(kPNDec == FABRIC_N_PAPER_DECODER_PARAMS, "paper decoder layout");
+static_assert(kPLat == FABRIC_PAPER_LATENT, "paper latent size");
+
+constexpr float kLeak = 0.01f;
+
+// Fragment image: [layer][M-block][k-step] A fragments of 64 lanes x 8 bf16.
+// K steps: F1 2 (12 slots: 8 position bins, 4 size bins), chain layers 5
+// (32 chained neurons + the bias slot), A1 5 (32 + wi.xyz | wo.xy, 1), A5 4.
+enum PLayer { kF1 = 0, kF2, kA1, kA2, kA3, kA4, kA5, kPLayers };
+__host__ __device__ constexpr int p_ks(int l) { return l == kF1 ? 2 : (l == kA5 ? 4 : 5); }
+__host__ __device__ constexpr int p_mb(int l) { return l == kA5 ? 1 : 2; }
+__host__ __device__ constexpr int p_first(int l)
+{
+    return l == 0 ? 0 : p_first(l - 1) + p_mb(l - 1) * p_ks(l - 1);
+}
+constexpr int kPFrags = p_first(kPLayers);     // 58
+static_assert(kPFrags == 58, "fragment count");
+constexpr int kPSlots1 = 12;                   // F1 slots per lane group
+
+using M = Mfma<FABRIC_BF16>;
+using Frag = M::Frag;
+using FM = FeatureMath<FABRIC_BF16>;
+
+// F1 slot c of lane group g: position bin c of axis g (c < 8), size bin
+// 4 g + c - 8 (c < 12); blob channel index [u 0..7, v 8..15, size 16..23].
+__host__ __device__ inline int p_blob_channel(int g, int c)
+{
+    if (c < 8)
+        return 8 * g + c;
+    if (c < kPSlots1)
+        return 16 + 4 * g + (c - 8);
+    return -1;
+}
+
+__global__ void pack_paper_kernel(const float *__restrict__ params, Frag *__restrict__ frags,
+                                  f32x4 *__restrict__ b5)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < kPFrags * 64) {
+        const int fr = idx / 64, lane = idx % 64, row = lane & 31, grp = lane >> 5;
+        int layer = 0;
+        while (layer + 1 < kPLayers && fr >= p_first(layer + 1))
+            layer++;
+        const int local = fr - p_first(layer);
+        const int mb = local / p_ks(layer), ks = local % p_ks(layer);
+        const int m = 32 * mb + row;
+        Frag f = M::zero();
+        for (int j = 0; j < 8; j++) {
+            const int c = ks * 8 + j;
+            float w = 0.0f;
+            if (layer == kF1) {
+                const int ch = p_blob_channel(grp, c);
+                if (ch >= 0) w = params[kPOffWF1 + m * kPX1 + kPLat + ch];
+            } else if (layer == kA1) {
+                if (c < kChain32) {
+                    w = params[kPOffWA1 + m * kPXA1 + chain32_neuron(grp, c)];
+                } else if (c < kL3Slots32) {
+                    const int a = l3_extra32(grp, c - kChain32);
+                    if (a == 5) w = params[kPOffBA1 + m];
+                    else if (a >= 0) w = params[kPOffWA1 + m * kPXA1 + 64 + a];
+                }
+            } else if (layer == kA5) {
+                if (m < 4 && c < kChain32) w = params[kPOffWA5 + m * 64 + chain32_neuron(grp, c)];
+            } else {
+                const int offw = layer == kF2 ? kPOffWF2 : layer == kA2 ? kPOffWA2
+                                 : layer == kA3 ? kPOffWA3 : kPOffWA4;
+                const int offb = layer == kF2 ? kPOffBF2 : layer == kA2 ? kPOffBA2
+                                 : layer == kA3 ? kPOffBA3 : kPOffBA4;
+                if (c < kChain32) w = params[offw + m * 64 + chain32_neuron(grp, c)];
+                else if (c == kChain32 && grp == 0) w = params[offb + m];
+            }
+            M::set(f, j, w);
+        }
+        frags[idx] = f;
+    }
+    if (idx < 64) {
+        f32x4 b;
+        for (int i = 0; i < 4; i++)
+            b[i] = (idx >> 5) == 0 ? params[kPOffBA5 + i] : 0.0f;
+        b5[idx] = b;
+    }
+}
+
+// c_f = WF1[:, 0:64] z_f + bF1 for every fabric: cfold[n_fabrics][64].
+__global__ void fold_paper_kernel(const float *__restrict__ params,
+                                  const float *__restrict__ latents, int n_fabrics,
+                                  float *__restrict__ cfold)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_fabrics * 64)
+        return;
+    const int f = idx / 64, o = idx % 64;
+    float acc = params[kPOffBF1 + o];
+    for (int k = 0; k < kPLat; k++)
+        acc = fmaf(params[kPOffWF1 + o * kPX1 + k], latents[f * kPLat + k], acc);
+    cfold[idx] = acc;
+}
+
+// One-blob slots of lane group g: 8 circular position bins along its axis,
+// then 4 of the 8 size bins (exp(-d^2/2), d in bins).
+__device__ inline void paper_slots(float coord, float iper, float r, int g,
+                                   float (&s1)[kPSlots1])
+{
+    const float t0 = 8.0f * (coord * iper) - 0.5f;
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+        float d = t0 - (float)b;                       // in [-7.5, 7.5)
+        d -= 8.0f * floorf((d + 4.0f) * 0.125f);       // circular, in [-4, 4)
+        s1[b] = FM::gauss(d);
+    }
+    const float tau = fminf(fmaxf((FM::log2(r) + 14.0f) * (1.0f / 16.0f), 0.0f), 1.0f);
+#pragma unroll
+    for (int b = 0; b < 4; b++)
+        s1[8 + b] = FM::gauss(8.0f * tau - (float)(4 * g + b) - 0.5f);
+}
+
+template <int NSL> __device__ inline Frag frag_of(const float (&v)[NSL], int ks)
+{
+    f32x8 x;
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        const int c = ks * 8 + j;
+        x[j] = c < NSL ? v[c] : 0.0f;
+    }
+    return M::from8(x);
+}
+
+__device__ inline float lrelu(float x) { return fmaxf(x, kLeak * x); }
+
+// Leaky ReLU of a 64-neuron accumulator pair, in place.
+__device__ inline void lrelu_acc(f32x16 (&a)[2])
+{
+#pragma unroll
+    for (int mb = 0; mb < 2; mb++)
+#pragma unroll
+        for (int r = 0; r < 16; r++)
+            a[mb][r] = lrelu(a[mb][r]);
+}
+
+// The chained B operand of a 64-neuron layer output (already activated).
+__device__ inline void chain_b(const f32x16 (&a)[2], Frag (&B)[4])
+{
+    float v[kChain32];
+#pragma unroll
+    for (int c = 0; c < kChain32; c++)
+        v[c] = a[c >> 4][c & 15];
+#pragma unroll
+    for (int ks = 0; ks < 4; ks++)
+        B[ks] = frag_of(v, ks);
+}
+
+// acc[mb] += A(layer, mb, ks) B[ks] over the layer's K steps; A fragments
+// are read from LDS right before use.
+template <int NMB, int KS>
+__device__ inline void dense_lds(const Frag *__restrict__ s_w, int first, const Frag (&B)[KS],
+                                 f32x16 (&acc)[2], int lane)
+{
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++)
+#pragma unroll
+        for (int mb = 0; mb < NMB; mb++)
+            acc[mb] = Mfma32<FABRIC_BF16>::mma(s_w[(first + mb * KS + ks) * 64 + lane], B[ks], acc[mb]);
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void decode_paper_kernel(
+    fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
+    const float *__restrict__ cfold, const Frag *__restrict__ frags,
+    const f32x4 *__restrict__ bias5, float *__restrict__ out, unsigned long long *err, int n_tiles)
+{
+    // LDS: the 58 weight fragments, then per fabric c_f [64], then the staged
+    // constants [kFabCopies][n_fabrics][kFabConsts].
+    extern __shared__ f32x4 smem4[];
+    Frag *s_w = (Frag *)smem4;
+    float *s_cf = (float *)(smem4 + kPFrags * 64);
+    float *s_fc = s_cf + n_fabrics * 64;
+    for (int k = threadIdx.x; k < kPFrags * 64; k += blockDim.x)
+        s_w[k] = frags[k];
+    for (int k = threadIdx.x; k < n_fabrics * 64; k += blockDim.x)
+        s_cf[k] = cfold[k];
+    stage_fabric_consts(fabrics, n_fabrics, s_fc);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 5;
+    const int col = lane & 31;
+    const f32x4 b5 = bias5[lane];
+    // The bias K step of the chain layers: 1 in slot 32 of lane group 0.
+    f32x8 one8 = {grp == 0 ? 1.0f : 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    const Frag bias_b = M::from8(one8);
+
+    const int n = (int)g.n;
+    const int waves = gridDim.x * WAVES;
+    const int wave_id = blockIdx.x * WAVES + (threadIdx.x >> 6);
+    const HalfPlanes hp = half_planes(g, grp);
+    auto tile_px = [&](int t) { return min((t < n_tiles ? t : wave_id) * 32 + col, n - 1); };
+
+    auto shade_tile = [&](const HalfPix &cur, int tile) {
+        // An offset the compiler cannot see through, so that the weight
+        // reads stay inside the loop instead of being hoisted into
+        // registers for all tiles (58 fragments would not fit).
+        int wofs = 0;
+        asm volatile("" : "+s"(wofs));
+        const Frag *s_wt = s_w + wofs;
+        const int p = tile * 32 + col;
+        const bool valid = p < n;
+        const bool fault = pair_any(half_fault(cur, n_fabrics, grp), lane);
+        const int fid = fault ? 0 : cur.fid;
+        const float *fc = s_fc + fab_entry(fid, n_fabrics, grp ? 1.0f : cur.xz) * kFabConsts;
+
+        // F1: one-blob slots; C operand c_f.
+        float s1[kPSlots1];
+        const float per = grp ? fc[1] : fc[0], iper = grp ? fc[3] : fc[2];
+        paper_slots(wrap_period(cur.uv, per, iper), iper, cur.r, grp, s1);
+        Frag B1[2] = {frag_of(s1, 0), frag_of(s1, 1)};
+        f32x16 a[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; mb++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const f32x4 c4 = *(const f32x4 *)(s_cf + fid * 64 + 32 * mb + 8 * q + 4 * grp);
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+                    a[mb][4 * q + i] = c4[i];
+            }
+        dense_lds<2, 2>(s_wt, p_first(kF1), B1, a, lane);
+        lrelu_acc(a);
+
+        // A chain layer (64 -> 64) with its bias step, from C operand c0.
+        auto chain_layer = [&](int layer, f32x16 (&acc)[2]) {
+            Frag B[5];
+            Frag B4[4];
+            chain_b(acc, B4);
+#pragma unroll
+            for (int ks = 0; ks < 4; ks++)
+                B[ks] = B4[ks];
+            B[4] = bias_b;
+            f32x16 c[2] = {f32x16{}, f32x16{}};
+            dense_lds<2, 5>(s_wt, p_first(layer), B, c, lane);
+            acc[0] = c[0];
+            acc[1] = c[1];
+        };
+        chain_layer(kF2, a);                      // spatial feature
+        lrelu_acc(a);
+
+        // A1: [spatial feature, wi.xyz | wo.xy, 1].
+        {
+            float v[kL3Slots32];
+#pragma unroll
+            for (int c = 0; c < kChain32; c++)
+                v[c] = a[c >> 4][c & 15];
+            v[32] = cur.x0;
+            v[33] = cur.x1;
+            v[34] = grp ? 1.0f : cur.xz;
+            Frag B[5];
+#pragma unroll
+            for (int ks = 0; ks < 5; ks++)
+                B[ks] = frag_of(v, ks);
+            a[0] = f32x16{};
+            a[1] = f32x16{};
+            dense_lds<2, 5>(s_wt, p_first(kA1), B, a, lane);
+        }
+        lrelu_acc(a);
+        f32x16 x[2] = {a[0], a[1]};               // the residual block's input
+
+        chain_layer(kA2, a);
+        lrelu_acc(a);
+        // A3 from C operand x: the skip enters before the activation.
+        {
+            Frag B[5];
+            Frag B4[4];
+            chain_b(a, B4);
+#pragma unroll
+            for (int ks = 0; ks < 4; ks++)
+                B[ks] = B4[ks];
+            B[4] = bias_b;
+            dense_lds<2, 5>(s_wt, p_first(kA3), B, x, lane);
+            a[0] = x[0];
+            a[1] = x[1];
+        }
+        lrelu_acc(a);
+        chain_layer(kA4, a);
+        lrelu_acc(a);
+        // A5: four outputs in rows 0..3 (lane group 0), bias added after.
+        f32x16 y[2] = {f32x16{}, f32x16{}};
+        {
+            Frag B4[4];
+            chain_b(a, B4);
+            dense_lds<1, 4>(s_wt, p_first(kA5), B4, y, lane);
+        }
+        if (grp == 0 && valid) {
+            float rgb[3];
+            compose_rgb<FM>(y[0][0] + b5[0], y[0][1] + b5[1], y[0][2] + b5[2], y[0][3] + b5[3],
+                            fc, rgb);
+#pragma unroll
+            for (int c = 0; c < 3; c++)
+                plane_store(out, c * n + p, fault ? 0.0f : rgb[c]);
+        }
+        const unsigned long long bad = __ballot(grp == 0 && valid && fault);
+        if (lane == 0 && bad)
+            atomicAdd(err, (unsigned long long)__popcll(bad));
+    };
+
+    HalfPix nxt = load_half(g, hp, tile_px(wave_id));
+    for (int tile = wave_id; tile < n_tiles; tile += waves) {
+        const HalfPix cur = nxt;
+        nxt = load_half(g, hp, tile_px(tile + waves));
+        shade_tile(cur, tile);
+    }
+}
+
+// 512-thread blocks, two per CU (the LDS holds two copies of the weights):
+// four waves per SIMD at <= 128 VGPRs.  (One 768-thread block at three
+// waves per SIMD and 152 VGPRs measured 3x slower.)
+constexpr int kPaperWaves = 8;
+
+}  // namespace
+
+size_t paper_image_bytes() { return (size_t)kPFrags * 64 * sizeof(Frag) + (size_t)64 * sizeof(f32x4); }
+
+hipError_t launch_paper_prepare(const float *params, const float *latents, int n_fabrics,
+                                void *image, float *cfold, hipStream_t stream)
+{
+    auto *frags = (Frag *)image;
+    auto *b5 = (f32x4 *)((char *)image + (size_t)kPFrags * 64 * sizeof(Frag));
+    hipLaunchKernelGGL(pack_paper_kernel, dim3((kPFrags * 64 + 255) / 256), dim3(256), 0, stream,
+                       params, frags, b5);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const int total = n_fabrics * 64;
+    hipLaunchKernelGGL(fold_paper_kernel, dim3((total + 255) / 256), dim3(256), 0, stream, params,
+                       latents, n_fabrics, cfold);
+    return hipGetLastError();
+}
+
+hipError_t launch_paper_shade(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
+                              const float *cfold, const void *image, float *out,
+                              unsigned long long *err, hipStream_t stream)
+{
+    if (g.n == 0)
+        return hipSuccess;
+    const auto *frags = (const Frag *)image;
+    const auto *b5 = (const f32x4 *)((const char *)image + (size_t)kPFrags * 64 * sizeof(Frag));
+    const int n_tiles = (int)((g.n + 31) / 32);
+    int blocks = (n_tiles + kPaperWaves - 1) / kPaperWaves;
+    const int cap = 2 * device_cus();
+    if (blocks > cap)
+        blocks = cap;
+    const size_t lds = (size_t)kPFrags * 64 * sizeof(Frag) +
+                       (size_t)n_fabrics * (64 + kFabCopies * kFabConsts) * sizeof(float);
+    hipLaunchKernelGGL(decode_paper_kernel<kPaperWaves>, dim3(blocks), dim3(64 * kPaperWaves), lds,
+                       stream, g, fabrics, n_fabrics, cfold, frags, b5, out, err, n_tiles);
+    return hipGetLastError();
+}
+
+}  // namespace fab

@@ -35,6 +35,10 @@ struct fabric_ctx {
     float *vis_tex = nullptr;         // height texels of every fabric
     size_t vis_cap = 0;               // texels allocated
     VisFabric *vis_fab = nullptr;     // [FABRIC_MAX_FABRICS]
+    void *paper_image = nullptr;      // paper-size decoder: packed weights
+    float *paper_cfold = nullptr;     // [FABRIC_MAX_FABRICS][64]
+    int paper_n_mats = 0;             // fabrics folded by the last prepare
+    uint64_t paper_serial = 0;        // table_serial of the last prepare
     uint64_t encoded_version = 0;     // weights_version of the last encode
     uint64_t encode_serial = 0;       // bumped on every change of latents or fabric table
 
@@ -448,6 +452,8 @@ void fabric_destroy(fabric_ctx *ctx)
     (void)hipFree(ctx->lerp_jobs);
     (void)hipFree(ctx->vis_tex);
     (void)hipFree(ctx->vis_fab);
+    (void)hipFree(ctx->paper_image);
+    (void)hipFree(ctx->paper_cfold);
     for (int k = 0; k < 4; k++)
         (void)hipFree(ctx->image[k]);
     (void)hipFree(ctx->tmp_image);
@@ -488,6 +494,8 @@ fabric_status fabric_create(fabric_ctx **out, int device, uint64_t seed)
     if (st == FABRIC_OK) st = dalloc(&ctx->tmp_cfold, F * 64);
     if (st == FABRIC_OK) st = dalloc(&ctx->lerp_jobs, F);
     if (st == FABRIC_OK) st = dalloc(&ctx->vis_fab, F);
+    if (st == FABRIC_OK) st = dalloc((char **)&ctx->paper_image, paper_image_bytes());
+    if (st == FABRIC_OK) st = dalloc(&ctx->paper_cfold, F * 64);
     if (st == FABRIC_OK) st = dalloc(&ctx->err, 1);
     if (st == FABRIC_OK) {
         const size_t img = decoder_image_bytes(FABRIC_FP32);   // the largest image
@@ -572,6 +580,37 @@ fabric_status fabric_set_albedo(fabric_ctx *ctx, int32_t fabric, const float kd[
     if (st == FABRIC_OK)
         st = from_hip(hipStreamSynchronize(s));
     return st;
+}
+
+fabric_status fabric_paper_prepare(fabric_ctx *ctx, const float *params, const float *latents,
+                                   void *stream)
+{
+    if (!ctx || !params || !latents)
+        return FABRIC_E_INVAL;
+    if (ctx->n_mats == 0)
+        return FABRIC_E_STATE;
+    DeviceGuard guard(ctx->device);
+    fabric_status st = from_hip(launch_paper_prepare(params, latents, ctx->n_mats, ctx->paper_image,
+                                                     ctx->paper_cfold, as_stream(stream)));
+    if (st != FABRIC_OK)
+        return st;
+    ctx->paper_n_mats = ctx->n_mats;
+    ctx->paper_serial = ctx->table_serial;
+    return FABRIC_OK;
+}
+
+fabric_status fabric_paper_shade(fabric_ctx *ctx, const fabric_gbuffer *g, float *out_rgb,
+                                 void *stream)
+{
+    if (!ctx || !valid_gbuffer(g) || (g->n > 0 && !out_rgb))
+        return FABRIC_E_INVAL;
+    if (ctx->paper_n_mats == 0 || ctx->paper_serial != ctx->table_serial)
+        return FABRIC_E_STATE;
+    if (g->n == 0)
+        return FABRIC_OK;
+    DeviceGuard guard(ctx->device);
+    return from_hip(launch_paper_shade(*g, ctx->fabrics, ctx->n_mats, ctx->paper_cfold,
+                                       ctx->paper_image, out_rgb, ctx->err, as_stream(stream)));
 }
 
 fabric_status fabric_set_visibility(fabric_ctx *ctx, int32_t enable)

@@ -78,6 +78,16 @@ struct LatentLerp {
 hipError_t launch_lerp_latents(const LatentLerp *jobs, int count, float *latents,
                                hipStream_t stream);
 
+// The paper-size decoder: image of paper_image_bytes() (58 BF16 weight
+// fragments + the output bias), c_f [n_fabrics][64] folded from latents
+// [n_fabrics][64]; shading of a G-buffer into rgb [3][n].
+size_t paper_image_bytes();
+hipError_t launch_paper_prepare(const float *params, const float *latents, int n_fabrics,
+                                void *image, float *cfold, hipStream_t stream);
+hipError_t launch_paper_shade(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
+                              const float *cfold, const void *image, float *out,
+                              unsigned long long *err, hipStream_t stream);
+
 // Encoder forward over n_fabrics fabrics: enc_inputs[n][524] -> latents[n][32].
 hipError_t launch_encoder_forward(const float *enc_params, const float *enc_inputs,
                                   int n_fabrics, float *latents, hipStream_t stream);

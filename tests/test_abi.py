@@ -96,5 +96,6 @@ def test_binding_constants_match_header():
     text = open(os.path.join(ROOT, "include", "fabric.h")).read()
     defs = dict(re.findall(r"#define (FABRIC_\w+) (\d+)\s", text))
     for name in ("FABRIC_MAX_FABRICS", "FABRIC_MAX_SAMPLES", "FABRIC_LATENT",
-                 "FABRIC_N_DECODER_PARAMS", "FABRIC_N_ENCODER_PARAMS"):
+                 "FABRIC_N_DECODER_PARAMS", "FABRIC_N_ENCODER_PARAMS", "FABRIC_PAPER_LATENT",
+                 "FABRIC_N_PAPER_DECODER_PARAMS"):
         assert getattr(_abi, name) == int(defs[name]), name

@@ -1,0 +1,126 @@
+"""GPU tests of the paper-size decoder (latent 64, one-blob 24, 2 + 5 FC
+layers with a residual skip, leaky ReLU) through the C ABI against the FP64
+oracle: ragged frames with transmission pixels, the 1080p frame on a
+sampled subset, 256 fabrics, sub-tile frames, faults and call order.
+
+BF16 bound: unit roundoff 2^-9 (rms 2^-9 / sqrt(3) = 0.11 % per operand),
+sqrt(2) per layer, seven chained layers: about sqrt(7) x 0.16 % = 0.42 % on
+the raw outputs; the composed rgb passes S through e^y, so it carries the
+error of y times y's size: the test allows 6 % norm-wise, as for the config
+decoder's shading."""
+import numpy as np
+import pytest
+
+import fabric_inputs as fi
+from tests.helpers import rel_norm_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+BOUND = 6e-2
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def pkg(torch):
+    import paper_2406_17782_amd as pkg
+    return pkg
+
+
+@pytest.fixture()
+def fab(pkg):
+    f = pkg.Fabric(0, seed=61)
+    yield f
+    f.close()
+
+
+def prepare(fab, pkg, torch, mats, seed):
+    fab.encode(mats)
+    params = fi.init_paper_params(seed, bias_scale=0.05)
+    z = fi.random_latents(len(mats), seed + 1, dim=64)
+    pkg.fabric_paper_prepare(fab.ctx, torch.from_numpy(params).cuda(), torch.from_numpy(z).cuda())
+    return params, z
+
+
+def shade(pkg, torch, fab, d):
+    out = torch.empty((3, d.n), dtype=torch.float32, device="cuda")
+    pkg.fabric_paper_shade(fab.ctx, d, out)
+    return out.cpu().numpy()
+
+
+def test_paper_decoder_matches_oracle(fab, pkg, orc, torch):
+    mats = fi.materials_for(8, 210)
+    g = fi.make_gbuffer(64, 65, 8, seed=211, btdf_frac=0.3)
+    g.fabric_id[:] = np.random.default_rng(212).integers(0, 8, g.n).astype(np.uint16)
+    params, z = prepare(fab, pkg, torch, mats, 213)
+    rgb = shade(pkg, torch, fab, pkg.DeviceGBuffer.from_host(g))
+    _, orgb = orc.paper_decoder_gbuffer(params, z, mats, g)
+    err = rel_norm_err(rgb, orgb)
+    print("paper decoder rel err", err)
+    assert err < BOUND
+
+
+def test_paper_decoder_1080p_sampled(fab, pkg, orc, torch):
+    wl = fi.WORKLOADS["fabric8_1080p"]
+    mats, g = wl.materials(), wl.gbuffer()
+    params, z = prepare(fab, pkg, torch, mats, 214)
+    rgb = shade(pkg, torch, fab, pkg.DeviceGBuffer.from_host(g))
+    idx = fi.subset_indices(g.n, 0.01, 215)
+    _, orgb = orc.paper_decoder_gbuffer(params, z, mats, g.subset(idx))
+    err = rel_norm_err(rgb[:, idx], orgb)
+    print("paper decoder 1080p rel err", err)
+    assert err < BOUND
+
+
+def test_paper_decoder_256_fabrics(fab, pkg, orc, torch):
+    n_fab = pkg.FABRIC_MAX_FABRICS
+    mats = fi.materials_for(n_fab, 216, max_random_side=16)
+    g = fi.make_gbuffer(80, 51, n_fab, seed=217)
+    g.fabric_id[:] = np.random.default_rng(218).integers(0, n_fab, g.n).astype(np.uint16)
+    params, z = prepare(fab, pkg, torch, mats, 219)
+    rgb = shade(pkg, torch, fab, pkg.DeviceGBuffer.from_host(g))
+    _, orgb = orc.paper_decoder_gbuffer(params, z, mats, g)
+    assert rel_norm_err(rgb, orgb) < BOUND
+
+
+@pytest.mark.parametrize("n", [1, 2, 31, 33])
+def test_paper_decoder_tiny_frames(fab, pkg, orc, torch, n):
+    mats = fi.materials_for(3, 220)
+    g = fi.make_gbuffer(n, 1, 3, seed=221 + n)
+    params, z = prepare(fab, pkg, torch, mats, 222)
+    rgb = shade(pkg, torch, fab, pkg.DeviceGBuffer.from_host(g))
+    _, orgb = orc.paper_decoder_gbuffer(params, z, mats, g)
+    assert rgb.shape == (3, n) and rel_norm_err(rgb, orgb) < BOUND
+
+
+def test_paper_decoder_faults_and_order(fab, pkg, torch):
+    mats = fi.materials_for(4, 223)
+    g = fi.make_gbuffer(16, 8, 4, seed=224)
+    d = pkg.DeviceGBuffer.from_host(g)
+    out = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
+    params = torch.from_numpy(fi.init_paper_params(225)).cuda()
+    z = torch.from_numpy(fi.random_latents(4, 226, dim=64)).cuda()
+    with pytest.raises(pkg.FabricError) as e:
+        pkg.fabric_paper_prepare(fab.ctx, params, z)       # nothing encoded
+    assert e.value.status == 6
+    fab.encode(mats)
+    with pytest.raises(pkg.FabricError) as e:
+        pkg.fabric_paper_shade(fab.ctx, d, out)            # not prepared
+    assert e.value.status == 6
+    pkg.fabric_paper_prepare(fab.ctx, params, z)
+    g.wi_z[:3] = 0.0
+    g.radius[3] = -1.0
+    d = pkg.DeviceGBuffer.from_host(g)
+    fab.error_count(reset=True)
+    pkg.fabric_paper_shade(fab.ctx, d, out)
+    assert fab.error_count(reset=True) == 4
+    o = out.cpu().numpy()
+    assert np.all(o[:, :4] == 0.0) and np.all(np.isfinite(o))
+    pkg.fabric_paper_shade(fab.ctx, pkg.DeviceGBuffer.from_host(fi.make_gbuffer(0, 1, 4, seed=1)), out)
+    fab.encode(mats)
+    with pytest.raises(pkg.FabricError) as e:
+        pkg.fabric_paper_shade(fab.ctx, d, out)            # re-encoded since prepare
+    assert e.value.status == 6
