@@ -195,20 +195,25 @@ __device__ inline void chain_b(const f32x16 (&a)[2], Frag (&B)[4])
         B[ks] = frag_of(v, ks);
 }
 
-// acc[mb] += A(layer, mb, ks) B[ks] over the layer's K steps; A fragments
-// are read from LDS right before use.
-template <int NMB, int KS>
-__device__ inline void dense_lds(const Frag *__restrict__ s_w, int first, const Frag (&B)[KS],
-                                 f32x16 (&acc)[2], int lane)
+// acc[t][mb] += A(layer, mb, ks) B[t][ks] over the layer's K steps for the
+// T tiles in flight: each A fragment is read from LDS once and used by all T.
+template <int T, int NMB, int KS>
+__device__ inline void dense_lds(const Frag *__restrict__ s_w, int first,
+                                 const Frag (&B)[T][KS], f32x16 (&acc)[T][2], int lane)
 {
 #pragma unroll
     for (int ks = 0; ks < KS; ks++)
 #pragma unroll
-        for (int mb = 0; mb < NMB; mb++)
-            acc[mb] = Mfma32<FABRIC_BF16>::mma(s_w[(first + mb * KS + ks) * 64 + lane], B[ks], acc[mb]);
+        for (int mb = 0; mb < NMB; mb++) {
+            const Frag w = s_w[(first + mb * KS + ks) * 64 + lane];
+#pragma unroll
+            for (int t = 0; t < T; t++)
+                acc[t][mb] = Mfma32<FABRIC_BF16>::mma(w, B[t][ks], acc[t][mb]);
+        }
 }
 
-template <int WAVES>
+// Shading of T tiles per wave iteration (T x 32 pixels).
+template <int WAVES, int T>
 __global__ __launch_bounds__(64 * WAVES) void decode_paper_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ cfold, const Frag *__restrict__ frags,
@@ -239,126 +244,168 @@ __global__ __launch_bounds__(64 * WAVES) void decode_paper_kernel(
     const int waves = gridDim.x * WAVES;
     const int wave_id = blockIdx.x * WAVES + (threadIdx.x >> 6);
     const HalfPlanes hp = half_planes(g, grp);
-    auto tile_px = [&](int t) { return min((t < n_tiles ? t : wave_id) * 32 + col, n - 1); };
+    // Wave w takes tiles T w + t, T w + t + T waves, ...; indices past the
+    // end load a clamped pixel and store nothing.
+    auto tile_px = [&](int t) { return min(t * 32 + col, n - 1); };
 
-    auto shade_tile = [&](const HalfPix &cur, int tile) {
+    auto shade = [&](const HalfPix (&cur)[T], int tile0) {
         // An offset the compiler cannot see through, so that the weight
         // reads stay inside the loop instead of being hoisted into
         // registers for all tiles (58 fragments would not fit).
         int wofs = 0;
         asm volatile("" : "+s"(wofs));
         const Frag *s_wt = s_w + wofs;
-        const int p = tile * 32 + col;
-        const bool valid = p < n;
-        const bool fault = pair_any(half_fault(cur, n_fabrics, grp), lane);
-        const int fid = fault ? 0 : cur.fid;
-        const float *fc = s_fc + fab_entry(fid, n_fabrics, grp ? 1.0f : cur.xz) * kFabConsts;
 
-        // F1: one-blob slots; C operand c_f.
-        float s1[kPSlots1];
-        const float per = grp ? fc[1] : fc[0], iper = grp ? fc[3] : fc[2];
-        paper_slots(wrap_period(cur.uv, per, iper), iper, cur.r, grp, s1);
-        Frag B1[2] = {frag_of(s1, 0), frag_of(s1, 1)};
-        f32x16 a[2];
+        int p[T], fid[T], entry[T];
+        bool valid[T], fault[T];
+        f32x16 a[T][2];
+        {
+            Frag B1[T][2];
 #pragma unroll
-        for (int mb = 0; mb < 2; mb++)
+            for (int t = 0; t < T; t++) {
+                p[t] = (tile0 + t) * 32 + col;
+                valid[t] = tile0 + t < n_tiles && p[t] < n;
+                fault[t] = pair_any(half_fault(cur[t], n_fabrics, grp), lane);
+                fid[t] = fault[t] ? 0 : cur[t].fid;
+                entry[t] = fab_entry(fid[t], n_fabrics, grp ? 1.0f : cur[t].xz);
+                const float *fc = s_fc + entry[t] * kFabConsts;
+                // F1: one-blob slots; C operand c_f.
+                float s1[kPSlots1];
+                const float per = grp ? fc[1] : fc[0], iper = grp ? fc[3] : fc[2];
+                paper_slots(wrap_period(cur[t].uv, per, iper), iper, cur[t].r, grp, s1);
+                B1[t][0] = frag_of(s1, 0);
+                B1[t][1] = frag_of(s1, 1);
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const f32x4 c4 = *(const f32x4 *)(s_cf + fid * 64 + 32 * mb + 8 * q + 4 * grp);
+                for (int mb = 0; mb < 2; mb++)
 #pragma unroll
-                for (int i = 0; i < 4; i++)
-                    a[mb][4 * q + i] = c4[i];
+                    for (int q = 0; q < 4; q++) {
+                        const f32x4 c4 =
+                            *(const f32x4 *)(s_cf + fid[t] * 64 + 32 * mb + 8 * q + 4 * grp);
+#pragma unroll
+                        for (int i = 0; i < 4; i++)
+                            a[t][mb][4 * q + i] = c4[i];
+                    }
             }
-        dense_lds<2, 2>(s_wt, p_first(kF1), B1, a, lane);
-        lrelu_acc(a);
-
-        // A chain layer (64 -> 64) with its bias step, from C operand c0.
-        auto chain_layer = [&](int layer, f32x16 (&acc)[2]) {
-            Frag B[5];
-            Frag B4[4];
-            chain_b(acc, B4);
+            dense_lds<T, 2, 2>(s_wt, p_first(kF1), B1, a, lane);
+        }
+        auto lrelu_all = [&]() {
 #pragma unroll
-            for (int ks = 0; ks < 4; ks++)
-                B[ks] = B4[ks];
-            B[4] = bias_b;
-            f32x16 c[2] = {f32x16{}, f32x16{}};
-            dense_lds<2, 5>(s_wt, p_first(layer), B, c, lane);
-            acc[0] = c[0];
-            acc[1] = c[1];
+            for (int t = 0; t < T; t++)
+                lrelu_acc(a[t]);
         };
-        chain_layer(kF2, a);                      // spatial feature
-        lrelu_acc(a);
-
+        // The chained B operand with its bias step; the accumulators restart
+        // from `start` (zero, or the residual).
+        auto chain_in = [&](Frag (&B)[T][5]) {
+#pragma unroll
+            for (int t = 0; t < T; t++) {
+                Frag B4[4];
+                chain_b(a[t], B4);
+#pragma unroll
+                for (int ks = 0; ks < 4; ks++)
+                    B[t][ks] = B4[ks];
+                B[t][4] = bias_b;
+            }
+        };
+        auto chain_layer = [&](int layer) {
+            Frag B[T][5];
+            chain_in(B);
+#pragma unroll
+            for (int t = 0; t < T; t++)
+                a[t][0] = a[t][1] = f32x16{};
+            dense_lds<T, 2, 5>(s_wt, p_first(layer), B, a, lane);
+        };
+        lrelu_all();
+        chain_layer(kF2);                         // spatial feature
+        lrelu_all();
         // A1: [spatial feature, wi.xyz | wo.xy, 1].
         {
-            float v[kL3Slots32];
+            Frag B[T][5];
 #pragma unroll
-            for (int c = 0; c < kChain32; c++)
-                v[c] = a[c >> 4][c & 15];
-            v[32] = cur.x0;
-            v[33] = cur.x1;
-            v[34] = grp ? 1.0f : cur.xz;
-            Frag B[5];
+            for (int t = 0; t < T; t++) {
+                float v[kL3Slots32];
 #pragma unroll
-            for (int ks = 0; ks < 5; ks++)
-                B[ks] = frag_of(v, ks);
-            a[0] = f32x16{};
-            a[1] = f32x16{};
-            dense_lds<2, 5>(s_wt, p_first(kA1), B, a, lane);
+                for (int c = 0; c < kChain32; c++)
+                    v[c] = a[t][c >> 4][c & 15];
+                v[32] = cur[t].x0;
+                v[33] = cur[t].x1;
+                v[34] = grp ? 1.0f : cur[t].xz;
+#pragma unroll
+                for (int ks = 0; ks < 5; ks++)
+                    B[t][ks] = frag_of(v, ks);
+                a[t][0] = a[t][1] = f32x16{};
+            }
+            dense_lds<T, 2, 5>(s_wt, p_first(kA1), B, a, lane);
         }
-        lrelu_acc(a);
-        f32x16 x[2] = {a[0], a[1]};               // the residual block's input
-
-        chain_layer(kA2, a);
-        lrelu_acc(a);
+        lrelu_all();
+        f32x16 x[T][2];                           // the residual block's input
+#pragma unroll
+        for (int t = 0; t < T; t++) {
+            x[t][0] = a[t][0];
+            x[t][1] = a[t][1];
+        }
+        chain_layer(kA2);
+        lrelu_all();
         // A3 from C operand x: the skip enters before the activation.
         {
-            Frag B[5];
-            Frag B4[4];
-            chain_b(a, B4);
+            Frag B[T][5];
+            chain_in(B);
+            dense_lds<T, 2, 5>(s_wt, p_first(kA3), B, x, lane);
 #pragma unroll
-            for (int ks = 0; ks < 4; ks++)
-                B[ks] = B4[ks];
-            B[4] = bias_b;
-            dense_lds<2, 5>(s_wt, p_first(kA3), B, x, lane);
-            a[0] = x[0];
-            a[1] = x[1];
+            for (int t = 0; t < T; t++) {
+                a[t][0] = x[t][0];
+                a[t][1] = x[t][1];
+            }
         }
-        lrelu_acc(a);
-        chain_layer(kA4, a);
-        lrelu_acc(a);
+        lrelu_all();
+        chain_layer(kA4);
+        lrelu_all();
         // A5: four outputs in rows 0..3 (lane group 0), bias added after.
-        f32x16 y[2] = {f32x16{}, f32x16{}};
         {
-            Frag B4[4];
-            chain_b(a, B4);
-            dense_lds<1, 4>(s_wt, p_first(kA5), B4, y, lane);
-        }
-        if (grp == 0 && valid) {
-            float rgb[3];
-            compose_rgb<FM>(y[0][0] + b5[0], y[0][1] + b5[1], y[0][2] + b5[2], y[0][3] + b5[3],
-                            fc, rgb);
+            Frag B[T][4];
 #pragma unroll
-            for (int c = 0; c < 3; c++)
-                plane_store(out, c * n + p, fault ? 0.0f : rgb[c]);
+            for (int t = 0; t < T; t++) {
+                chain_b(a[t], B[t]);
+                a[t][0] = f32x16{};
+            }
+            dense_lds<T, 1, 4>(s_wt, p_first(kA5), B, a, lane);
         }
-        const unsigned long long bad = __ballot(grp == 0 && valid && fault);
-        if (lane == 0 && bad)
-            atomicAdd(err, (unsigned long long)__popcll(bad));
+#pragma unroll
+        for (int t = 0; t < T; t++) {
+            if (grp == 0 && valid[t]) {
+                float rgb[3];
+                compose_rgb<FM>(a[t][0][0] + b5[0], a[t][0][1] + b5[1], a[t][0][2] + b5[2],
+                                a[t][0][3] + b5[3], s_fc + entry[t] * kFabConsts, rgb);
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    plane_store(out, c * n + p[t], fault[t] ? 0.0f : rgb[c]);
+            }
+            const unsigned long long bad = __ballot(grp == 0 && valid[t] && fault[t]);
+            if (lane == 0 && bad)
+                atomicAdd(err, (unsigned long long)__popcll(bad));
+        }
     };
 
-    HalfPix nxt = load_half(g, hp, tile_px(wave_id));
-    for (int tile = wave_id; tile < n_tiles; tile += waves) {
-        const HalfPix cur = nxt;
-        nxt = load_half(g, hp, tile_px(tile + waves));
-        shade_tile(cur, tile);
+    // Loop over this wave's groups of T tiles, loading the next group's
+    // fields while the current one is shaded.
+    HalfPix nxt[T];
+#pragma unroll
+    for (int t = 0; t < T; t++)
+        nxt[t] = load_half(g, hp, tile_px(T * wave_id + t));
+    for (int tile0 = T * wave_id; tile0 < n_tiles; tile0 += T * waves) {
+        HalfPix cur[T];
+#pragma unroll
+        for (int t = 0; t < T; t++) {
+            cur[t] = nxt[t];
+            nxt[t] = load_half(g, hp, tile_px(tile0 + T * waves + t));
+        }
+        shade(cur, tile0);
     }
 }
 
-// 512-thread blocks, two per CU (the LDS holds two copies of the weights):
-// four waves per SIMD at <= 128 VGPRs.  (One 768-thread block at three
-// waves per SIMD and 152 VGPRs measured 3x slower.)
+// Two tiles per wave iteration share every weight read; 512-thread blocks,
+// one per CU, two waves per SIMD.
 constexpr int kPaperWaves = 8;
+constexpr int kPaperTiles = 2;
 
 }  // namespace
 
@@ -389,13 +436,14 @@ hipError_t launch_paper_shade(const fabric_gbuffer &g, const DevFabric *fabrics,
     const auto *frags = (const Frag *)image;
     const auto *b5 = (const f32x4 *)((const char *)image + (size_t)kPFrags * 64 * sizeof(Frag));
     const int n_tiles = (int)((g.n + 31) / 32);
-    int blocks = (n_tiles + kPaperWaves - 1) / kPaperWaves;
-    const int cap = 2 * device_cus();
+    int blocks = (n_tiles + kPaperWaves * kPaperTiles - 1) / (kPaperWaves * kPaperTiles);
+    const int cap = device_cus();
     if (blocks > cap)
         blocks = cap;
     const size_t lds = (size_t)kPFrags * 64 * sizeof(Frag) +
                        (size_t)n_fabrics * (64 + kFabCopies * kFabConsts) * sizeof(float);
-    hipLaunchKernelGGL(decode_paper_kernel<kPaperWaves>, dim3(blocks), dim3(64 * kPaperWaves), lds,
+    hipLaunchKernelGGL((decode_paper_kernel<kPaperWaves, kPaperTiles>), dim3(blocks),
+                       dim3(64 * kPaperWaves), lds,
                        stream, g, fabrics, n_fabrics, cfold, frags, b5, out, err, n_tiles);
     return hipGetLastError();
 }
