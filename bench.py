@@ -363,6 +363,54 @@ def btdf_row(args, torch, pkg, fi):
         fab.close()
 
 
+PAPER_FLOP_PER_PIXEL = 2 * (24 * 64 + 64 * 64 + 69 * 64 + 3 * 64 * 64 + 64 * 4)   # 45,184
+
+
+def paper_decoder_row(args, torch, pkg, fi, mats, g, d):
+    """The decoder at the paper's own form (latent 64, one-blob 24, 2 + 5
+    layers of width 64 with a residual skip, leaky ReLU), BF16 on the 1080p
+    frame with seeded weights and latents (inference only: this build trains
+    the config-size decoder); its error against the FP64 oracle's forward of
+    the same weights on a seeded 1 %."""
+    fab = pkg.Fabric(0, seed=7)
+    try:
+        fab.encode(mats)
+        params = fi.init_paper_params(4500, bias_scale=0.05)
+        z = fi.random_latents(len(mats), 4501, dim=64)
+        pkg.fabric_paper_prepare(fab.ctx, torch.from_numpy(params).cuda(), torch.from_numpy(z).cuda())
+        out = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
+        fp16 = lambda: pkg.fabric_paper_shade(fab.ctx, d, out, "fp16")
+        for _ in range(args.warmup // 2):
+            fp16()
+        ms16 = time_launches(torch, fp16, args.steps // 2)
+        rgb16 = out.cpu().numpy()
+        shade = lambda: pkg.fabric_paper_shade(fab.ctx, d, out, "bf16")
+        for _ in range(args.warmup // 4):
+            shade()
+        ms = time_launches(torch, shade, args.steps // 2)
+        tflops = PAPER_FLOP_PER_PIXEL * g.n / (ms * 1e-3) / 1e12
+        res = {"ms_per_frame": ms, "mpix_per_s": g.n / (ms * 1e-3) / 1e6,
+               "algorithmic_flop_per_pixel": PAPER_FLOP_PER_PIXEL, "tflops": tflops,
+               "mfma_frac": tflops / BF16_PEAK_TFLOPS, "weights": "seeded (inference only)",
+               "fp16_ms_per_frame": ms16,
+               "fp16_mfma_frac": PAPER_FLOP_PER_PIXEL * g.n / (ms16 * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
+               "paper_rtx3090_decoder_ms_per_1080p_frame": [13.6, 14.4]}
+        if not args.no_rmse:
+            import oracle
+            idx = fi.subset_indices(g.n, args.rmse_frac, 98)
+            _, o_rgb = oracle.paper_decoder_gbuffer(params, z, mats, g.subset(idx))
+            rgb = out.cpu().numpy()[:, idx]
+            res["rel_l2_vs_fp64_oracle"] = float(np.linalg.norm(rgb - o_rgb) / np.linalg.norm(o_rgb))
+            res["rmse_vs_fp64_oracle"] = rmse_stats(rgb, o_rgb)
+            r16 = rgb16[:, idx]
+            res["fp16_rel_l2_vs_fp64_oracle"] = float(np.linalg.norm(r16 - o_rgb) / np.linalg.norm(o_rgb))
+        log(f"paper-size decoder: bf16 {ms * 1e3:.1f} us/frame, {tflops:.0f} TFLOP/s "
+            f"({100 * tflops / BF16_PEAK_TFLOPS:.1f} % of bf16 peak); fp16 {ms16 * 1e3:.1f} us")
+        return res
+    finally:
+        fab.close()
+
+
 def interp_row(args, torch, pkg, fi, g, d):
     """Latent interpolation study (Sec. 5 "Interpolation") on the 1080p
     frame's geometry: a second network trained on variants of one twill whose
@@ -605,6 +653,7 @@ def main():
         rows["latent_interpolation"] = interp_row(args, torch, pkg, fi, g, d)
         rows["visibility"] = visibility_row(args, torch, pkg, fi, wl, mats, g, d, ms)
         rows["transmission"] = btdf_row(args, torch, pkg, fi)
+        rows["paper_decoder"] = paper_decoder_row(args, torch, pkg, fi, mats, g, d)
 
     # ---- error against the FP64 oracle on a seeded pixel subset ----
     errs = None if args.no_rmse else oracle_errors(args, torch, pkg, fi, fab, d, mats, g, rgb, gt_rgb)

@@ -205,7 +205,8 @@ fabric_status fabric_lerp_latents(fabric_ctx *ctx, const int32_t *dst, const int
  * block whose input is added before its last activation; leaky ReLU (0.01)
  * after every layer but the output; width 64.  Outputs decoded and composed
  * as fabric_shade_gbuffer does (k = 100, or 1000 where wi.z < 0).  Inference
- * only, BF16 operands with FP32 accumulation.
+ * only: prec FABRIC_BF16 or FABRIC_FP16 operands with FP32 accumulation (the
+ * FP16 path applies the leaky ReLU to packed halves).
  *   params   device float [FABRIC_N_PAPER_DECODER_PARAMS], rows = outputs:
  *            WF1[64][88] ([z(64), u bins, v bins, size bins]) bF1[64]
  *            WF2[64][64] bF2 WA1[64][69] ([s(64), wi.xyz, wo.xy]) bA1
@@ -219,8 +220,8 @@ fabric_status fabric_lerp_latents(fabric_ctx *ctx, const int32_t *dst, const int
  * prepare or after a later fabric_encode. */
 fabric_status fabric_paper_prepare(fabric_ctx *ctx, const float *params, const float *latents,
                                    void *stream);
-fabric_status fabric_paper_shade(fabric_ctx *ctx, const fabric_gbuffer *g, float *out_rgb,
-                                 void *stream);
+fabric_status fabric_paper_shade(fabric_ctx *ctx, const fabric_gbuffer *g, fabric_prec prec,
+                                 float *out_rgb, void *stream);
 
 /* Neural shading of a G-buffer (Sec. 4.3 "Rendering"): per pixel, the
  * decoder's four outputs decoded as C = max(y, 0), S = max((e^y - 1)/k, 0)

@@ -145,10 +145,10 @@ def fabric_paper_prepare(ctx, params, latents, stream=None) -> None:
           "fabric_paper_prepare")
 
 
-def fabric_paper_shade(ctx, g: DeviceGBuffer, out_rgb, stream=None) -> None:
+def fabric_paper_shade(ctx, g: DeviceGBuffer, out_rgb, prec: str = "bf16", stream=None) -> None:
     gs = g.c_struct()
-    check(_abi.lib().fabric_paper_shade(ctx, ctypes.byref(gs), _dptr(out_rgb), _stream(stream)),
-          "fabric_paper_shade")
+    check(_abi.lib().fabric_paper_shade(ctx, ctypes.byref(gs), PREC[prec], _dptr(out_rgb),
+                                        _stream(stream)), "fabric_paper_shade")
 
 
 def fabric_set_visibility(ctx, enable: bool) -> None:

@@ -91,7 +91,7 @@ def _declare(L):
     L.fabric_set_visibility.restype = _S
     L.fabric_paper_prepare.argtypes = [_P, _P, _P, _P]
     L.fabric_paper_prepare.restype = _S
-    L.fabric_paper_shade.argtypes = [_P, ctypes.POINTER(fabric_gbuffer), _P, _P]
+    L.fabric_paper_shade.argtypes = [_P, ctypes.POINTER(fabric_gbuffer), ctypes.c_int, _P, _P]
     L.fabric_paper_shade.restype = _S
     L.fabric_shade_gbuffer.argtypes = [_P, ctypes.POINTER(fabric_gbuffer), ctypes.c_int,
                                        ctypes.c_int32, ctypes.c_uint64, _P, _P]

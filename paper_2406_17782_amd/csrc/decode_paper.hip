@@ -63,10 +63,6 @@ constexpr int kPFrags = p_first(kPLayers);     // 58
 static_assert(kPFrags == 58, "fragment count");
 constexpr int kPSlots1 = 12;                   // F1 slots per lane group
 
-using M = Mfma<FABRIC_BF16>;
-using Frag = M::Frag;
-using FM = FeatureMath<FABRIC_BF16>;
-
 // F1 slot c of lane group g: position bin c of axis g (c < 8), size bin
 // 4 g + c - 8 (c < 12); blob channel index [u 0..7, v 8..15, size 16..23].
 __host__ __device__ inline int p_blob_channel(int g, int c)
@@ -78,9 +74,13 @@ __host__ __device__ inline int p_blob_channel(int g, int c)
     return -1;
 }
 
-__global__ void pack_paper_kernel(const float *__restrict__ params, Frag *__restrict__ frags,
+template <int P>
+__global__ void pack_paper_kernel(const float *__restrict__ params,
+                                  typename Mfma<P>::Frag *__restrict__ frags,
                                   f32x4 *__restrict__ b5)
 {
+    using M = Mfma<P>;
+    using Frag = typename M::Frag;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < kPFrags * 64) {
         const int fr = idx / 64, lane = idx % 64, row = lane & 31, grp = lane >> 5;
@@ -144,9 +144,11 @@ __global__ void fold_paper_kernel(const float *__restrict__ params,
 
 // One-blob slots of lane group g: 8 circular position bins along its axis,
 // then 4 of the 8 size bins (exp(-d^2/2), d in bins).
+template <int P>
 __device__ inline void paper_slots(float coord, float iper, float r, int g,
                                    float (&s1)[kPSlots1])
 {
+    using FM = FeatureMath<P>;
     const float t0 = 8.0f * (coord * iper) - 0.5f;
 #pragma unroll
     for (int b = 0; b < 8; b++) {
@@ -160,20 +162,9 @@ __device__ inline void paper_slots(float coord, float iper, float r, int g,
         s1[8 + b] = FM::gauss(8.0f * tau - (float)(4 * g + b) - 0.5f);
 }
 
-template <int NSL> __device__ inline Frag frag_of(const float (&v)[NSL], int ks)
-{
-    f32x8 x;
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-        const int c = ks * 8 + j;
-        x[j] = c < NSL ? v[c] : 0.0f;
-    }
-    return M::from8(x);
-}
-
 __device__ inline float lrelu(float x) { return fmaxf(x, kLeak * x); }
 
-// Leaky ReLU of a 64-neuron accumulator pair, in place.
+// Leaky ReLU of a 64-neuron accumulator pair, in place (FP32).
 __device__ inline void lrelu_acc(f32x16 (&a)[2])
 {
 #pragma unroll
@@ -183,42 +174,78 @@ __device__ inline void lrelu_acc(f32x16 (&a)[2])
             a[mb][r] = lrelu(a[mb][r]);
 }
 
-// The chained B operand of a 64-neuron layer output (already activated).
-__device__ inline void chain_b(const f32x16 (&a)[2], Frag (&B)[4])
-{
-    float v[kChain32];
-#pragma unroll
-    for (int c = 0; c < kChain32; c++)
-        v[c] = a[c >> 4][c & 15];
-#pragma unroll
-    for (int ks = 0; ks < 4; ks++)
-        B[ks] = frag_of(v, ks);
-}
+// Operand packing and the MFMA sweep per operand precision.  act(): the
+// leaky ReLU fused into the packing of eight outputs - in FP32 before the
+// BF16 rounding (CDNA has no packed BF16 arithmetic), on packed halves after
+// the FP16 rounding (packed multiply and max, two values per instruction).
+template <int P> struct PaperTile {
+    using M = Mfma<P>;
+    using Frag = typename M::Frag;
 
-// acc[t][mb] += A(layer, mb, ks) B[t][ks] over the layer's K steps for the
-// T tiles in flight: each A fragment is read from LDS once and used by all T.
-template <int T, int NMB, int KS>
-__device__ inline void dense_lds(const Frag *__restrict__ s_w, int first,
-                                 const Frag (&B)[T][KS], f32x16 (&acc)[T][2], int lane)
-{
+    template <int NSL> static __device__ inline Frag frag_of(const float (&v)[NSL], int ks, bool act)
+    {
+        f32x8 x;
 #pragma unroll
-    for (int ks = 0; ks < KS; ks++)
-#pragma unroll
-        for (int mb = 0; mb < NMB; mb++) {
-            const Frag w = s_w[(first + mb * KS + ks) * 64 + lane];
-#pragma unroll
-            for (int t = 0; t < T; t++)
-                acc[t][mb] = Mfma32<FABRIC_BF16>::mma(w, B[t][ks], acc[t][mb]);
+        for (int j = 0; j < 8; j++) {
+            const int c = ks * 8 + j;
+            x[j] = c < NSL ? v[c] : 0.0f;
         }
-}
+        if (P == FABRIC_FP16) {
+            Frag f = M::from8(x);
+            if (act)
+                f = __builtin_elementwise_max(f, f * (Frag)((_Float16)kLeak));
+            return f;
+        }
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < 8; j++)
+                x[j] = lrelu(x[j]);
+        }
+        return M::from8(x);
+    }
+
+    // The chained B operand of a 64-neuron layer output.
+    static __device__ inline void chain_b(const f32x16 (&a)[2], Frag (&B)[4], bool act)
+    {
+        float v[kChain32];
+#pragma unroll
+        for (int c = 0; c < kChain32; c++)
+            v[c] = a[c >> 4][c & 15];
+#pragma unroll
+        for (int ks = 0; ks < 4; ks++)
+            B[ks] = frag_of(v, ks, act);
+    }
+
+    // acc[t][mb] += A(layer, mb, ks) B[t][ks] over the layer's K steps for
+    // the T tiles in flight: each A fragment is read from LDS once and used
+    // by all T.
+    template <int T, int NMB, int KS>
+    static __device__ inline void dense_lds(const Frag *__restrict__ s_w, int first,
+                                            const Frag (&B)[T][KS], f32x16 (&acc)[T][2], int lane)
+    {
+#pragma unroll
+        for (int ks = 0; ks < KS; ks++)
+#pragma unroll
+            for (int mb = 0; mb < NMB; mb++) {
+                const Frag w = s_w[(first + mb * KS + ks) * 64 + lane];
+#pragma unroll
+                for (int t = 0; t < T; t++)
+                    acc[t][mb] = Mfma32<P>::mma(w, B[t][ks], acc[t][mb]);
+            }
+    }
+};
 
 // Shading of T tiles per wave iteration (T x 32 pixels).
-template <int WAVES, int T>
+template <int P, int WAVES, int T>
 __global__ __launch_bounds__(64 * WAVES) void decode_paper_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
-    const float *__restrict__ cfold, const Frag *__restrict__ frags,
+    const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ frags,
     const f32x4 *__restrict__ bias5, float *__restrict__ out, unsigned long long *err, int n_tiles)
 {
+    using PT = PaperTile<P>;
+    using M = typename PT::M;
+    using Frag = typename PT::Frag;
+    using FM = FeatureMath<P>;
     // LDS: the 58 weight fragments, then per fabric c_f [64], then the staged
     // constants [kFabCopies][n_fabrics][kFabConsts].
     extern __shared__ f32x4 smem4[];
@@ -272,9 +299,9 @@ __global__ __launch_bounds__(64 * WAVES) void decode_paper_kernel(
                 // F1: one-blob slots; C operand c_f.
                 float s1[kPSlots1];
                 const float per = grp ? fc[1] : fc[0], iper = grp ? fc[3] : fc[2];
-                paper_slots(wrap_period(cur[t].uv, per, iper), iper, cur[t].r, grp, s1);
-                B1[t][0] = frag_of(s1, 0);
-                B1[t][1] = frag_of(s1, 1);
+                paper_slots<P>(wrap_period(cur[t].uv, per, iper), iper, cur[t].r, grp, s1);
+                B1[t][0] = PT::frag_of(s1, 0, false);
+                B1[t][1] = PT::frag_of(s1, 1, false);
 #pragma unroll
                 for (int mb = 0; mb < 2; mb++)
 #pragma unroll
@@ -286,37 +313,30 @@ __global__ __launch_bounds__(64 * WAVES) void decode_paper_kernel(
                             a[t][mb][4 * q + i] = c4[i];
                     }
             }
-            dense_lds<T, 2, 2>(s_wt, p_first(kF1), B1, a, lane);
+            PT::template dense_lds<T, 2, 2>(s_wt, p_first(kF1), B1, a, lane);
         }
-        auto lrelu_all = [&]() {
-#pragma unroll
-            for (int t = 0; t < T; t++)
-                lrelu_acc(a[t]);
-        };
-        // The chained B operand with its bias step; the accumulators restart
-        // from `start` (zero, or the residual).
-        auto chain_in = [&](Frag (&B)[T][5]) {
+        // The chained B operand (with the previous layer's activation fused
+        // into the packing when `act`) and its bias step.
+        auto chain_in = [&](Frag (&B)[T][5], bool act) {
 #pragma unroll
             for (int t = 0; t < T; t++) {
                 Frag B4[4];
-                chain_b(a[t], B4);
+                PT::chain_b(a[t], B4, act);
 #pragma unroll
                 for (int ks = 0; ks < 4; ks++)
                     B[t][ks] = B4[ks];
                 B[t][4] = bias_b;
             }
         };
-        auto chain_layer = [&](int layer) {
+        auto chain_layer = [&](int layer, bool act) {
             Frag B[T][5];
-            chain_in(B);
+            chain_in(B, act);
 #pragma unroll
             for (int t = 0; t < T; t++)
                 a[t][0] = a[t][1] = f32x16{};
-            dense_lds<T, 2, 5>(s_wt, p_first(layer), B, a, lane);
+            PT::template dense_lds<T, 2, 5>(s_wt, p_first(layer), B, a, lane);
         };
-        lrelu_all();
-        chain_layer(kF2);                         // spatial feature
-        lrelu_all();
+        chain_layer(kF2, true);                   // spatial feature
         // A1: [spatial feature, wi.xyz | wo.xy, 1].
         {
             Frag B[T][5];
@@ -331,43 +351,42 @@ __global__ __launch_bounds__(64 * WAVES) void decode_paper_kernel(
                 v[34] = grp ? 1.0f : cur[t].xz;
 #pragma unroll
                 for (int ks = 0; ks < 5; ks++)
-                    B[t][ks] = frag_of(v, ks);
+                    B[t][ks] = PT::frag_of(v, ks, ks < 4);
                 a[t][0] = a[t][1] = f32x16{};
             }
-            dense_lds<T, 2, 5>(s_wt, p_first(kA1), B, a, lane);
+            PT::template dense_lds<T, 2, 5>(s_wt, p_first(kA1), B, a, lane);
         }
-        lrelu_all();
-        f32x16 x[T][2];                           // the residual block's input
+        // The residual block's input, activated in FP32 (it is also A3's C
+        // operand); A2 then packs it without a further activation.
+        f32x16 x[T][2];
 #pragma unroll
         for (int t = 0; t < T; t++) {
+            lrelu_acc(a[t]);
             x[t][0] = a[t][0];
             x[t][1] = a[t][1];
         }
-        chain_layer(kA2);
-        lrelu_all();
+        chain_layer(kA2, false);
         // A3 from C operand x: the skip enters before the activation.
         {
             Frag B[T][5];
-            chain_in(B);
-            dense_lds<T, 2, 5>(s_wt, p_first(kA3), B, x, lane);
+            chain_in(B, true);
+            PT::template dense_lds<T, 2, 5>(s_wt, p_first(kA3), B, x, lane);
 #pragma unroll
             for (int t = 0; t < T; t++) {
                 a[t][0] = x[t][0];
                 a[t][1] = x[t][1];
             }
         }
-        lrelu_all();
-        chain_layer(kA4);
-        lrelu_all();
+        chain_layer(kA4, true);
         // A5: four outputs in rows 0..3 (lane group 0), bias added after.
         {
             Frag B[T][4];
 #pragma unroll
             for (int t = 0; t < T; t++) {
-                chain_b(a[t], B[t]);
+                PT::chain_b(a[t], B[t], true);
                 a[t][0] = f32x16{};
             }
-            dense_lds<T, 1, 4>(s_wt, p_first(kA5), B, a, lane);
+            PT::template dense_lds<T, 1, 4>(s_wt, p_first(kA5), B, a, lane);
         }
 #pragma unroll
         for (int t = 0; t < T; t++) {
@@ -409,15 +428,35 @@ constexpr int kPaperTiles = 2;
 
 }  // namespace
 
-size_t paper_image_bytes() { return (size_t)kPFrags * 64 * sizeof(Frag) + (size_t)64 * sizeof(f32x4); }
+// One image per operand precision: BF16 first, then FP16.
+size_t paper_image_bytes()
+{
+    return 2 * ((size_t)kPFrags * 64 * 16 + (size_t)64 * sizeof(f32x4));
+}
+
+template <int P> static void *paper_image_of(void *image)
+{
+    return (char *)image + (P == FABRIC_FP16 ? paper_image_bytes() / 2 : 0);
+}
 
 hipError_t launch_paper_prepare(const float *params, const float *latents, int n_fabrics,
                                 void *image, float *cfold, hipStream_t stream)
 {
-    auto *frags = (Frag *)image;
-    auto *b5 = (f32x4 *)((char *)image + (size_t)kPFrags * 64 * sizeof(Frag));
-    hipLaunchKernelGGL(pack_paper_kernel, dim3((kPFrags * 64 + 255) / 256), dim3(256), 0, stream,
-                       params, frags, b5);
+    const int blocks = (kPFrags * 64 + 255) / 256;
+    {
+        using Frag = Mfma<FABRIC_BF16>::Frag;
+        auto *frags = (Frag *)paper_image_of<FABRIC_BF16>(image);
+        auto *b5 = (f32x4 *)(frags + kPFrags * 64);
+        hipLaunchKernelGGL(pack_paper_kernel<FABRIC_BF16>, dim3(blocks), dim3(256), 0, stream,
+                           params, frags, b5);
+    }
+    {
+        using Frag = Mfma<FABRIC_FP16>::Frag;
+        auto *frags = (Frag *)paper_image_of<FABRIC_FP16>(image);
+        auto *b5 = (f32x4 *)(frags + kPFrags * 64);
+        hipLaunchKernelGGL(pack_paper_kernel<FABRIC_FP16>, dim3(blocks), dim3(256), 0, stream,
+                           params, frags, b5);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
@@ -427,14 +466,14 @@ hipError_t launch_paper_prepare(const float *params, const float *latents, int n
     return hipGetLastError();
 }
 
-hipError_t launch_paper_shade(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
+template <int P>
+static hipError_t paper_shade(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
                               const float *cfold, const void *image, float *out,
                               unsigned long long *err, hipStream_t stream)
 {
-    if (g.n == 0)
-        return hipSuccess;
-    const auto *frags = (const Frag *)image;
-    const auto *b5 = (const f32x4 *)((const char *)image + (size_t)kPFrags * 64 * sizeof(Frag));
+    using Frag = typename Mfma<P>::Frag;
+    const auto *frags = (const Frag *)paper_image_of<P>((void *)image);
+    const auto *b5 = (const f32x4 *)(frags + kPFrags * 64);
     const int n_tiles = (int)((g.n + 31) / 32);
     int blocks = (n_tiles + kPaperWaves * kPaperTiles - 1) / (kPaperWaves * kPaperTiles);
     const int cap = device_cus();
@@ -442,10 +481,23 @@ hipError_t launch_paper_shade(const fabric_gbuffer &g, const DevFabric *fabrics,
         blocks = cap;
     const size_t lds = (size_t)kPFrags * 64 * sizeof(Frag) +
                        (size_t)n_fabrics * (64 + kFabCopies * kFabConsts) * sizeof(float);
-    hipLaunchKernelGGL((decode_paper_kernel<kPaperWaves, kPaperTiles>), dim3(blocks),
-                       dim3(64 * kPaperWaves), lds,
-                       stream, g, fabrics, n_fabrics, cfold, frags, b5, out, err, n_tiles);
+    hipLaunchKernelGGL((decode_paper_kernel<P, kPaperWaves, kPaperTiles>), dim3(blocks),
+                       dim3(64 * kPaperWaves), lds, stream, g, fabrics, n_fabrics, cfold, frags,
+                       b5, out, err, n_tiles);
     return hipGetLastError();
+}
+
+hipError_t launch_paper_shade(int prec, const fabric_gbuffer &g, const DevFabric *fabrics,
+                              int n_fabrics, const float *cfold, const void *image, float *out,
+                              unsigned long long *err, hipStream_t stream)
+{
+    if (g.n == 0)
+        return hipSuccess;
+    if (prec == FABRIC_BF16)
+        return paper_shade<FABRIC_BF16>(g, fabrics, n_fabrics, cfold, image, out, err, stream);
+    if (prec == FABRIC_FP16)
+        return paper_shade<FABRIC_FP16>(g, fabrics, n_fabrics, cfold, image, out, err, stream);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace fab

@@ -599,17 +599,19 @@ fabric_status fabric_paper_prepare(fabric_ctx *ctx, const float *params, const f
     return FABRIC_OK;
 }
 
-fabric_status fabric_paper_shade(fabric_ctx *ctx, const fabric_gbuffer *g, float *out_rgb,
-                                 void *stream)
+fabric_status fabric_paper_shade(fabric_ctx *ctx, const fabric_gbuffer *g, fabric_prec prec,
+                                 float *out_rgb, void *stream)
 {
     if (!ctx || !valid_gbuffer(g) || (g->n > 0 && !out_rgb))
+        return FABRIC_E_INVAL;
+    if (prec != FABRIC_BF16 && prec != FABRIC_FP16)
         return FABRIC_E_INVAL;
     if (ctx->paper_n_mats == 0 || ctx->paper_serial != ctx->table_serial)
         return FABRIC_E_STATE;
     if (g->n == 0)
         return FABRIC_OK;
     DeviceGuard guard(ctx->device);
-    return from_hip(launch_paper_shade(*g, ctx->fabrics, ctx->n_mats, ctx->paper_cfold,
+    return from_hip(launch_paper_shade(prec, *g, ctx->fabrics, ctx->n_mats, ctx->paper_cfold,
                                        ctx->paper_image, out_rgb, ctx->err, as_stream(stream)));
 }
 

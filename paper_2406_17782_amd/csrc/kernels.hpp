@@ -78,14 +78,15 @@ struct LatentLerp {
 hipError_t launch_lerp_latents(const LatentLerp *jobs, int count, float *latents,
                                hipStream_t stream);
 
-// The paper-size decoder: image of paper_image_bytes() (58 BF16 weight
-// fragments + the output bias), c_f [n_fabrics][64] folded from latents
-// [n_fabrics][64]; shading of a G-buffer into rgb [3][n].
+// The paper-size decoder: image of paper_image_bytes() (the 58 weight
+// fragments + the output bias, in BF16 and in FP16), c_f [n_fabrics][64]
+// folded from latents [n_fabrics][64]; shading of a G-buffer into rgb [3][n]
+// with prec FABRIC_BF16 or FABRIC_FP16 operands.
 size_t paper_image_bytes();
 hipError_t launch_paper_prepare(const float *params, const float *latents, int n_fabrics,
                                 void *image, float *cfold, hipStream_t stream);
-hipError_t launch_paper_shade(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
-                              const float *cfold, const void *image, float *out,
+hipError_t launch_paper_shade(int prec, const fabric_gbuffer &g, const DevFabric *fabrics,
+                              int n_fabrics, const float *cfold, const void *image, float *out,
                               unsigned long long *err, hipStream_t stream);
 
 // Encoder forward over n_fabrics fabrics: enc_inputs[n][524] -> latents[n][32].

@@ -7,7 +7,7 @@ BF16 bound: unit roundoff 2^-9 (rms 2^-9 / sqrt(3) = 0.11 % per operand),
 sqrt(2) per layer, seven chained layers: about sqrt(7) x 0.16 % = 0.42 % on
 the raw outputs; the composed rgb passes S through e^y, so it carries the
 error of y times y's size: the test allows 6 % norm-wise, as for the config
-decoder's shading."""
+decoder's shading.  FP16 (unit roundoff 2^-11, 4x finer) gets 2 %."""
 import numpy as np
 import pytest
 
@@ -16,7 +16,7 @@ from tests.helpers import rel_norm_err, require_gpu
 
 pytestmark = pytest.mark.gpu
 
-BOUND = 6e-2
+BOUND = {"bf16": 6e-2, "fp16": 2e-2}
 
 
 @pytest.fixture(scope="module")
@@ -45,9 +45,9 @@ def prepare(fab, pkg, torch, mats, seed):
     return params, z
 
 
-def shade(pkg, torch, fab, d):
+def shade(pkg, torch, fab, d, prec="bf16"):
     out = torch.empty((3, d.n), dtype=torch.float32, device="cuda")
-    pkg.fabric_paper_shade(fab.ctx, d, out)
+    pkg.fabric_paper_shade(fab.ctx, d, out, prec)
     return out.cpu().numpy()
 
 
@@ -56,23 +56,25 @@ def test_paper_decoder_matches_oracle(fab, pkg, orc, torch):
     g = fi.make_gbuffer(64, 65, 8, seed=211, btdf_frac=0.3)
     g.fabric_id[:] = np.random.default_rng(212).integers(0, 8, g.n).astype(np.uint16)
     params, z = prepare(fab, pkg, torch, mats, 213)
-    rgb = shade(pkg, torch, fab, pkg.DeviceGBuffer.from_host(g))
+    d = pkg.DeviceGBuffer.from_host(g)
     _, orgb = orc.paper_decoder_gbuffer(params, z, mats, g)
-    err = rel_norm_err(rgb, orgb)
-    print("paper decoder rel err", err)
-    assert err < BOUND
+    for prec in ("bf16", "fp16"):
+        err = rel_norm_err(shade(pkg, torch, fab, d, prec), orgb)
+        print("paper decoder rel err", prec, err)
+        assert err < BOUND[prec]
 
 
 def test_paper_decoder_1080p_sampled(fab, pkg, orc, torch):
     wl = fi.WORKLOADS["fabric8_1080p"]
     mats, g = wl.materials(), wl.gbuffer()
     params, z = prepare(fab, pkg, torch, mats, 214)
-    rgb = shade(pkg, torch, fab, pkg.DeviceGBuffer.from_host(g))
+    d = pkg.DeviceGBuffer.from_host(g)
     idx = fi.subset_indices(g.n, 0.01, 215)
     _, orgb = orc.paper_decoder_gbuffer(params, z, mats, g.subset(idx))
-    err = rel_norm_err(rgb[:, idx], orgb)
-    print("paper decoder 1080p rel err", err)
-    assert err < BOUND
+    for prec in ("bf16", "fp16"):
+        err = rel_norm_err(shade(pkg, torch, fab, d, prec)[:, idx], orgb)
+        print("paper decoder 1080p rel err", prec, err)
+        assert err < BOUND[prec]
 
 
 def test_paper_decoder_256_fabrics(fab, pkg, orc, torch):
@@ -83,7 +85,7 @@ def test_paper_decoder_256_fabrics(fab, pkg, orc, torch):
     params, z = prepare(fab, pkg, torch, mats, 219)
     rgb = shade(pkg, torch, fab, pkg.DeviceGBuffer.from_host(g))
     _, orgb = orc.paper_decoder_gbuffer(params, z, mats, g)
-    assert rel_norm_err(rgb, orgb) < BOUND
+    assert rel_norm_err(rgb, orgb) < BOUND["bf16"]
 
 
 @pytest.mark.parametrize("n", [1, 2, 31, 33])
@@ -91,9 +93,11 @@ def test_paper_decoder_tiny_frames(fab, pkg, orc, torch, n):
     mats = fi.materials_for(3, 220)
     g = fi.make_gbuffer(n, 1, 3, seed=221 + n)
     params, z = prepare(fab, pkg, torch, mats, 222)
-    rgb = shade(pkg, torch, fab, pkg.DeviceGBuffer.from_host(g))
+    d = pkg.DeviceGBuffer.from_host(g)
     _, orgb = orc.paper_decoder_gbuffer(params, z, mats, g)
-    assert rgb.shape == (3, n) and rel_norm_err(rgb, orgb) < BOUND
+    for prec in ("bf16", "fp16"):
+        rgb = shade(pkg, torch, fab, d, prec)
+        assert rgb.shape == (3, n) and rel_norm_err(rgb, orgb) < BOUND[prec]
 
 
 def test_paper_decoder_faults_and_order(fab, pkg, torch):
@@ -120,6 +124,9 @@ def test_paper_decoder_faults_and_order(fab, pkg, torch):
     o = out.cpu().numpy()
     assert np.all(o[:, :4] == 0.0) and np.all(np.isfinite(o))
     pkg.fabric_paper_shade(fab.ctx, pkg.DeviceGBuffer.from_host(fi.make_gbuffer(0, 1, 4, seed=1)), out)
+    with pytest.raises(pkg.FabricError) as e:
+        pkg.fabric_paper_shade(fab.ctx, d, out, "fp32")     # precision not offered
+    assert e.value.status == 1
     fab.encode(mats)
     with pytest.raises(pkg.FabricError) as e:
         pkg.fabric_paper_shade(fab.ctx, d, out)            # re-encoded since prepare
