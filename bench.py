@@ -117,6 +117,16 @@ def cpu_baseline(orc, mats, g, params, budget_s):
                 out[leg] = (len(idx), dt)
                 break
             n = min(g.n, int(n * max(2.0, 1.2 * budget_s / max(dt, 1e-3))))
+    # One host thread: the decoder on a fixed 4,096-pixel subset.
+    threads = orc.num_threads()
+    orc.set_num_threads(1)
+    try:
+        idx = fi.subset_indices(g.n, 4096 / g.n, 4322)
+        t0 = time.perf_counter()
+        orc.decoder_gbuffer(P, z, mats, g.subset(idx))
+        out["decoder_1thread"] = (len(idx), time.perf_counter() - t0)
+    finally:
+        orc.set_num_threads(threads)
     return out
 
 
@@ -136,6 +146,21 @@ def oracle_errors(args, torch, pkg, fi, fab, d, mats, g, rgb, gt_rgb):
     one = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
     pkg.fabric_gt_filtered(fab.ctx, d, 1, 777, one, None)
     err["analytic_1spp"] = rmse_stats(one.cpu().numpy()[:, idx], o_rgb)
+    # The method without the network at the network's frame time: the
+    # largest square sample count whose filter frame is no slower than the
+    # BF16 decoder's (informational, as the paper's equal-time comparison).
+    eqo = torch.empty_like(one)
+    eq = {}
+    for m in (1, 2, 3, 4):
+        ms_m = time_launches(torch, lambda: pkg.fabric_gt_filtered(fab.ctx, d, m * m, 778, eqo, None), 5)
+        eq[m * m] = ms_m
+    neural_ms = args.neural_ms
+    n_eq = max([k for k, t in eq.items() if t <= neural_ms] or [1])
+    pkg.fabric_gt_filtered(fab.ctx, d, n_eq, 778, eqo, None)
+    err["analytic_equal_time"] = dict(rmse_stats(eqo.cpu().numpy()[:, idx], o_rgb), samples=n_eq,
+                                      ms_per_frame=eq[n_eq], neural_bf16_ms=neural_ms,
+                                      within_neural_time=eq[n_eq] <= neural_ms,
+                                      filter_ms_by_samples=eq)
     # Monte-Carlo noise floor of the 256-sample reference (truth mode, N = 128^2).
     nf_idx = idx[:: max(1, len(idx) // 256)]
     _, t_rgb, _, _ = oracle.filter_gbuffer(mats, g.subset(nf_idx), 128 * 128, 4242, same_sample=False,
@@ -656,6 +681,7 @@ def main():
         rows["paper_decoder"] = paper_decoder_row(args, torch, pkg, fi, mats, g, d)
 
     # ---- error against the FP64 oracle on a seeded pixel subset ----
+    args.neural_ms = ms
     errs = None if args.no_rmse else oracle_errors(args, torch, pkg, fi, fab, d, mats, g, rgb, gt_rgb)
 
     # ---- CPU baseline: the oracle on the host cores ----
@@ -666,8 +692,10 @@ def main():
         res = cpu_baseline(oracle, mats, g, params, args.cpu_budget)
         n_dec, t_dec = res["decoder"]
         n_fil, t_fil = res["filter256"]
+        n_1t, t_1t = res["decoder_1thread"]
         cpu = {"value": n_dec / t_dec / 1e6, "unit": "Mpixels/s", "cores": threads, "kind": "oracle",
                "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+               "decoder_1thread_mpix_per_s": n_1t / t_1t / 1e6,
                "sample": f"FP64 oracle decoder forward on a seeded {n_dec}-pixel subset of the frame "
                          f"({t_dec:.1f} s); footprint filter at 256 samples on {n_fil} pixels "
                          f"({t_fil:.1f} s) = {n_fil / t_fil / 1e6:.4f} Mpixels/s",
