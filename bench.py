@@ -151,7 +151,7 @@ def oracle_errors(args, torch, pkg, fi, fab, d, mats, g, rgb, gt_rgb):
     # BF16 decoder's (informational, as the paper's equal-time comparison).
     eqo = torch.empty_like(one)
     eq = {}
-    for m in (1, 2, 3, 4):
+    for m in range(1, 8):
         ms_m = time_launches(torch, lambda: pkg.fabric_gt_filtered(fab.ctx, d, m * m, 778, eqo, None), 5)
         eq[m * m] = ms_m
     neural_ms = args.neural_ms

@@ -1,9 +1,10 @@
 // Footprint-filtered analytic shading on VALU (Eq. (3)-(5), with V = 1 or
 // the inter-yarn visibility march of the height field, components of
-// Eq. (7), albedo composition of Eq. (8)).  One wavefront owns
-// one pixel: its 64 lanes take the pixel's footprint sub-samples (lane,
-// lane + 64, ...), accumulate the five sums in FP64 and reduce them with a
-// fixed butterfly of wavefront shuffles.
+// Eq. (7), albedo composition of Eq. (8)).  At 64 samples and more one
+// wavefront owns one pixel: its 64 lanes take the pixel's footprint
+// sub-samples (lane, lane + 64, ...), accumulate the five sums in FP64 and
+// reduce them with a fixed butterfly of wavefront shuffles.  Below 64
+// samples each lane owns one pixel and takes its samples in order.
 #include "kernels.hpp"
 #include "model.hpp"
 #include "shade.hpp"
@@ -15,9 +16,10 @@ namespace {
 constexpr int kWavesPerBlock = 4;
 constexpr int kXcds = 8;
 
-// Pixel p by the wave: the filter's components and Eq. (8) composition,
-// written by lane 0 (faulty inputs: zeros and one count).
-template <bool VIS>
+// Pixel p by the wave (LANE = false; lane 0 writes) or by one lane (LANE =
+// true): the filter's components and Eq. (8) composition (faulty inputs:
+// zeros and one count).
+template <bool VIS, bool LANE>
 __device__ inline void filter_one_pixel(const fabric_gbuffer &g, const DevFabric *__restrict__ fabrics,
                                         int n_fabrics, int64_t p, int n_samples, int side,
                                         float inv_side, uint64_t seed, int lane, VisArgs vis,
@@ -33,10 +35,14 @@ __device__ inline void filter_one_pixel(const fabric_gbuffer &g, const DevFabric
     double comp[4] = {0.0, 0.0, 0.0, 0.0};
     if (!fault) {
         const VisFabric vf = VIS ? vis.fab[fid] : VisFabric{0, 0, 0, 0.0f};
-        filter_pixel_wave<VIS>(fabrics[fid], seed, (uint64_t)p, n_samples, side, inv_side, u, v,
-                               r, wi, wo, lane, vis.tex, vf, comp);
+        if (LANE)
+            filter_pixel_lane<VIS>(fabrics[fid], seed, (uint64_t)p, n_samples, side, inv_side, u,
+                                   v, r, wi, wo, vis.tex, vf, comp);
+        else
+            filter_pixel_wave<VIS>(fabrics[fid], seed, (uint64_t)p, n_samples, side, inv_side, u,
+                                   v, r, wi, wo, lane, vis.tex, vf, comp);
     }
-    if (lane == 0) {
+    if (LANE || lane == 0) {
         const int64_t n = g.n;
         if (fault && err)
             atomicAdd(err, 1ull);
@@ -75,8 +81,28 @@ __global__ __launch_bounds__(256) void gt_filter_kernel(fabric_gbuffer g,
     const int64_t p = (int64_t)block * kWavesPerBlock + wave;
     if (p >= g.n)
         return;
-    filter_one_pixel<VIS>(g, fabrics, n_fabrics, p, n_samples, side, inv_side, seed, lane, vis,
-                          out_rgb, out_comp, err);
+    filter_one_pixel<VIS, false>(g, fabrics, n_fabrics, p, n_samples, side, inv_side, seed, lane,
+                                 vis, out_rgb, out_comp, err);
+}
+
+// Fewer than 64 samples: one lane per pixel, 256 consecutive pixels per
+// workgroup, with the same XCD-contiguous block order as above.
+template <bool VIS>
+__global__ __launch_bounds__(256) void gt_filter_lane_kernel(fabric_gbuffer g,
+                                                             const DevFabric *__restrict__ fabrics,
+                                                             int n_fabrics, int n_samples, int side,
+                                                             float inv_side, uint64_t seed,
+                                                             VisArgs vis, float *__restrict__ out_rgb,
+                                                             float *__restrict__ out_comp,
+                                                             unsigned long long *err)
+{
+    const int per_xcd = gridDim.x / kXcds;
+    const int block = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+    const int64_t p = (int64_t)block * blockDim.x + threadIdx.x;
+    if (p >= g.n)
+        return;
+    filter_one_pixel<VIS, true>(g, fabrics, n_fabrics, p, n_samples, side, inv_side, seed, 0, vis,
+                                out_rgb, out_comp, err);
 }
 
 // The queued pixels of a hybrid shading launch (all valid and in range of
@@ -98,9 +124,28 @@ __global__ __launch_bounds__(256) void gt_filter_queue_kernel(fabric_gbuffer g,
     if (k >= *q.count)
         return;
     const int64_t p = __builtin_amdgcn_readfirstlane(q.idx[k]);
-    filter_one_pixel<VIS>(g, fabrics, FABRIC_MAX_FABRICS, p, n_samples, side, inv_side, seed,
-                          lane, vis, out_rgb, nullptr, nullptr);
+    filter_one_pixel<VIS, false>(g, fabrics, FABRIC_MAX_FABRICS, p, n_samples, side, inv_side,
+                                 seed, lane, vis, out_rgb, nullptr, nullptr);
 }
+
+// The queue below 64 samples: one lane per queue slot, each pixel computed
+// exactly as gt_filter_lane_kernel computes it.
+template <bool VIS>
+__global__ __launch_bounds__(256) void gt_filter_queue_lane_kernel(fabric_gbuffer g,
+                                                                   const DevFabric *__restrict__ fabrics,
+                                                                   int n_samples, int side,
+                                                                   float inv_side, uint64_t seed,
+                                                                   VisArgs vis, FallbackQueue q,
+                                                                   float *__restrict__ out_rgb)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)*q.count)
+        return;
+    filter_one_pixel<VIS, true>(g, fabrics, FABRIC_MAX_FABRICS, (int64_t)q.idx[k], n_samples, side,
+                                inv_side, seed, 0, vis, out_rgb, nullptr, nullptr);
+}
+
+constexpr int kLaneBelow = 64;   // sample counts below this take one lane per pixel
 
 // Queue compaction in three fixed-order steps (no atomics).  The offsets
 // buffer holds the per-group local offsets [ngroups], then the per-block
@@ -202,6 +247,19 @@ hipError_t launch_gt_filter(const fabric_gbuffer &g, const DevFabric *fabrics, i
     if (g.n == 0)
         return hipSuccess;
     const int side = sample_side(n_samples);
+    if (n_samples < kLaneBelow) {
+        int64_t blocks = (g.n + 255) / 256;
+        blocks = (blocks + kXcds - 1) / kXcds * kXcds;   // padding blocks exit at once
+        if (vis.tex)
+            hipLaunchKernelGGL(gt_filter_lane_kernel<true>, dim3((unsigned)blocks), dim3(256), 0,
+                               stream, g, fabrics, n_fabrics, n_samples, side, 1.0f / (float)side,
+                               seed, vis, out_rgb, out_comp, err);
+        else
+            hipLaunchKernelGGL(gt_filter_lane_kernel<false>, dim3((unsigned)blocks), dim3(256), 0,
+                               stream, g, fabrics, n_fabrics, n_samples, side, 1.0f / (float)side,
+                               seed, vis, out_rgb, out_comp, err);
+        return hipGetLastError();
+    }
     int64_t blocks = (g.n + kWavesPerBlock - 1) / kWavesPerBlock;
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;   // padding blocks exit at once
     if (vis.tex)
@@ -222,6 +280,18 @@ hipError_t launch_gt_filter_queue(const fabric_gbuffer &g, const DevFabric *fabr
     if (g.n == 0)
         return hipSuccess;
     const int side = sample_side(n_samples);
+    if (n_samples < kLaneBelow) {
+        const int64_t blocks = (g.n + 255) / 256;
+        if (vis.tex)
+            hipLaunchKernelGGL(gt_filter_queue_lane_kernel<true>, dim3((unsigned)blocks), dim3(256),
+                               0, stream, g, fabrics, n_samples, side, 1.0f / (float)side, seed,
+                               vis, q, out_rgb);
+        else
+            hipLaunchKernelGGL(gt_filter_queue_lane_kernel<false>, dim3((unsigned)blocks), dim3(256),
+                               0, stream, g, fabrics, n_samples, side, 1.0f / (float)side, seed,
+                               vis, q, out_rgb);
+        return hipGetLastError();
+    }
     const int64_t blocks = (g.n + kWavesPerBlock - 1) / kWavesPerBlock;
     if (vis.tex)
         hipLaunchKernelGGL(gt_filter_queue_kernel<true>, dim3((unsigned)blocks),

@@ -20,7 +20,8 @@ struct FallbackQueue {
     int32_t *idx;
 };
 
-// Footprint filter: one wavefront per pixel; vis.tex == nullptr for V = 1.
+// Footprint filter: one wavefront per pixel at 64 samples and more, one lane
+// per pixel below; vis.tex == nullptr for V = 1.
 hipError_t launch_gt_filter(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
                             int n_samples, uint64_t seed, VisArgs vis, float *out_rgb,
                             float *out_comp, unsigned long long *err, hipStream_t stream);

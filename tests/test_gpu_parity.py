@@ -106,6 +106,37 @@ def test_gt_filter_deterministic_and_seeded(fab, pkg, torch):
     assert not np.array_equal(a, c)
 
 
+@pytest.mark.parametrize("n_samples", [1, 4, 16, 49])
+def test_gt_filter_below_64_samples(fab, pkg, orc, torch, n_samples):
+    """Below 64 samples a lane owns a pixel and takes its samples in order:
+    8 weaves, per-pixel fabric ids, n not a multiple of the 256-pixel
+    workgroup; every pixel against the oracle with the same samples."""
+    mats = fi.materials_for(8, 2100)
+    g = fi.make_gbuffer(61, 37, 8, seed=2101)
+    g.fabric_id[:] = np.random.default_rng(2102).integers(0, 8, g.n).astype(np.uint16)
+    fab.encode(mats)
+    rgb, comp = fab.gt_filtered(dev(pkg, g), n_samples, 321)
+    torch.cuda.synchronize()
+    o_comp, o_rgb, flagged, _ = orc.filter_gbuffer(mats, g, n_samples, 321, same_sample=True)
+    print(assert_filter_parity(comp.cpu().numpy(), o_comp, flagged))
+    assert_filter_parity(rgb.cpu().numpy(), o_rgb, flagged)
+    assert fab.error_count() == 0
+
+
+def test_gt_filter_1080p_16_samples_sampled(fab, pkg, orc, torch):
+    """The 1080p frame at 16 samples (one lane per pixel, as the equal-time
+    comparison launches it); a seeded 0.2 % of the pixels against the oracle."""
+    wl = fi.WORKLOADS["fabric8_1080p"]
+    mats, g = wl.materials(), wl.gbuffer()
+    fab.encode(mats)
+    _, comp = fab.gt_filtered(dev(pkg, g), 16, 778)
+    torch.cuda.synchronize()
+    idx = fi.subset_indices(g.n, 0.002, 78)
+    o_comp, _, flagged, _ = orc.filter_gbuffer(mats, g.subset(idx), 16, 778, same_sample=True,
+                                               pixel_index=idx)
+    print(assert_filter_parity(comp.cpu().numpy()[:, idx], o_comp, flagged))
+
+
 # ---------------------------------------------------------------------------
 # Decoder forward
 # ---------------------------------------------------------------------------
@@ -214,6 +245,11 @@ def test_hybrid_routing_matches_both_paths(fab, pkg, torch):
     assert 0.1 < oor.mean() < 0.3
     assert np.array_equal(hybrid[:, ~oor], neural[:, ~oor])
     assert np.array_equal(hybrid[:, oor], analytic[:, oor])
+    # Below 64 samples both the queue and the plain filter take a lane per pixel.
+    hybrid9 = fab.shade(d, "bf16", fallback_samples=9, seed=9).cpu().numpy()
+    analytic9 = fab.gt_filtered(d, 9, 9)[0].cpu().numpy()
+    assert np.array_equal(hybrid9[:, ~oor], neural[:, ~oor])
+    assert np.array_equal(hybrid9[:, oor], analytic9[:, oor])
 
 
 # ---------------------------------------------------------------------------

@@ -58,6 +58,18 @@ def test_filter_visibility_matches_oracle(fab, pkg, orc, torch):
     assert np.array_equal(c2.cpu().numpy(), c0)
 
 
+def test_filter_visibility_below_64_samples(fab, pkg, orc, torch):
+    """The lane-per-pixel filter with V, 16 samples, against the oracle."""
+    mats = fi.materials_for(8, 180)
+    g = fi.make_gbuffer(45, 29, 8, seed=181)
+    g.fabric_id[:] = np.random.default_rng(182).integers(0, 8, g.n).astype(np.uint16)
+    fab.encode(mats)
+    fab.set_visibility(True)
+    _, comp = fab.gt_filtered(pkg.DeviceGBuffer.from_host(g), 16, 183)
+    o_comp, _, flagged, _ = orc.filter_gbuffer(mats, g, 16, 183, same_sample=True, visibility=True)
+    print(assert_filter_parity_vis(comp.cpu().numpy(), o_comp, flagged))
+
+
 def test_flat_fabrics_unchanged(fab, pkg, torch):
     mats = fi.materials_for(8, 175)
     for m in mats:
