@@ -341,35 +341,4 @@ __device__ inline void filter_pixel_wave(const DevFabric &f, uint64_t seed, uint
         comp[c] = acc[4] > 0.0 ? acc[c] / acc[4] : 0.0;
 }
 
-// One lane's FP64 footprint estimate for its own pixel: samples k = 0 ..
-// N - 1 in order (the same sample positions as the wave-wide estimate, the
-// five sums added in sample order).  For footprints of fewer than 64
-// samples, where a wave per pixel would leave lanes idle.
-template <bool VIS>
-__device__ inline void filter_pixel_lane(const DevFabric &f, uint64_t seed, uint64_t pixel,
-                                         int n_samples, int side, float inv_side, float u,
-                                         float v, float r, float3 wi, float3 wo,
-                                         const float *tex, const VisFabric &vf, double comp[4])
-{
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    uint64_t state = seed + ((uint64_t)pixel * (uint64_t)n_samples + 1ull) * kGoldenGamma;
-    int kx = 0, ky = 0;
-    for (int k = 0; k < n_samples; k++, state += kGoldenGamma) {
-        float2 pos = footprint_sample(splitmix64_mix(state), kx, ky, inv_side, u, v, r);
-        if (++kx == side) {
-            kx = 0;
-            ky += 1;
-        }
-        SampleVal sv = eval_surface_point<VIS>(f, pos.x, pos.y, wi, wo, tex, vf);
-        double nc = sv.num_c, ns = sv.num_s;
-        acc[0] += sv.yarn == kWarp ? nc : 0.0;
-        acc[1] += sv.yarn == kWeft ? nc : 0.0;
-        acc[2] += sv.yarn == kWarp ? ns : 0.0;
-        acc[3] += sv.yarn == kWeft ? ns : 0.0;
-        acc[4] += (double)sv.area;
-    }
-    for (int c = 0; c < 4; c++)
-        comp[c] = acc[4] > 0.0 ? acc[c] / acc[4] : 0.0;
-}
-
 }  // namespace fab
