@@ -4,8 +4,8 @@ preservation, the SGGX projected-area identity behind Eq. (2), reciprocity and
 albedo bounds of Eq. (1), the Lambertian closed forms, the geometry's
 invariants (unit, orthogonal, flat for beta = 0, periodic, pattern
 symmetries, warp/weft transposition), coverage fractions, the flat-fabric
-closed form of the footprint filter Eq. (3)-(5), its r -> 0 limit and its
-Monte-Carlo convergence."""
+closed form of the footprint filter Eq. (3)-(5), its r -> 0 and r -> infinity
+limits and its Monte-Carlo convergence."""
 import math
 
 import numpy as np
@@ -403,6 +403,23 @@ def test_radius_to_zero_limit(orc):
     slope = np.polyfit(np.log(radii), np.log(errs), 1)[0]
     assert 1.6 < slope < 2.4
     assert errs[-1] < 1e-3 * np.abs(point).max()
+
+
+def test_radius_to_infinity_limit(orc):
+    """A footprint covering many pattern periods averages over the period, so
+    the components stop depending on where it is centred (edge effects fall
+    off at least like W / r)."""
+    m = fi.uniform_material(fi.pattern_twill(3, 2), alpha=0.4, beta=1.0, twist=0.3)
+    wi, wo = sph(0.5, 0.3), sph(0.4, 2.5)
+    centres = [(0.3, 0.7), (1.1, 0.2), (2.45, 1.6), (0.9, 2.2)]
+
+    def spread(r):
+        cs = np.array([orc.filter_pixel(m, u, v, r, wi, wo, 512 * 512, 5)[0] for u, v in centres])
+        return (cs.max(axis=0) - cs.min(axis=0)).max() / np.abs(cs).max()
+
+    near, far = spread(3.0), spread(12.0)
+    assert near > 1e-2            # a 2-period footprint still sees where it sits
+    assert far < 0.25 * near and far < 1e-2
 
 
 def test_monte_carlo_convergence(orc):
