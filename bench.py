@@ -450,10 +450,13 @@ def interp_row(args, torch, pkg, fi, g, d):
         steps = args.interp_train_steps
         for s in range(steps):
             lr = args.train_lr * 0.5 * (1.0 + math.cos(math.pi * s / max(1, steps)))
-            fab.train_step(seed=2_000_000 + s, batch=1 << 16, gt_samples=args.gt_samples,
+            fab.train_step(seed=2_000_000 + s, batch=1 << 17, gt_samples=args.gt_samples,
                            prec=pkg.FABRIC_BF16, lr=lr, want_loss=(s == steps - 1))
         pts = fi.INTERP_ENDPOINTS + fi.INTERP_POINTS
-        table = fi.parameter_sweep("alpha", pts, 4401) + fi.parameter_sweep("beta", pts, 4402)
+        # The trained twill itself, the other parameter held at 0.5 (inside
+        # the training range).
+        table = (fi.parameter_sweep("alpha", pts, 4400, other=0.5) +
+                 fi.parameter_sweep("beta", pts, 4400, other=0.5))
         fab.encode(table)
         p0, p1 = fi.INTERP_ENDPOINTS
         dst, a, b, t = [], [], [], []
@@ -509,7 +512,25 @@ def interp_row(args, torch, pkg, fi, g, d):
                     "blend_vs_analytic": rel(blended[slot], gt[slot]),
                 }
         log("interpolation: " + ", ".join(f"{k} {v['blend_vs_direct']:.4f}" for k, v in points.items()))
-        return {"train_steps": steps, "train_batch": 1 << 16, "training_table": "64 twill variants",
+        # Unseen parameters: 8 variants from the training table and 8 new
+        # draws of the same family, each shaded over the frame and compared
+        # with the analytic filter.
+        seen = fi.sweep_training_set(64, 4400)[:8]
+        unseen = fi.sweep_training_set(8, 4400, variant_seed=4499)
+        fab.encode(seen + unseen)
+        frames = [frame(k) for k in range(16)]
+        errs = []
+        for k in range(16):
+            pkg.fabric_shade_gbuffer(fab.ctx, frames[k], pkg.PREC["bf16"], 0, 0, out)
+            nn = out.cpu().numpy().astype(np.float64)
+            pkg.fabric_gt_filtered(fab.ctx, frames[k], args.gt_samples, 4242, out, None)
+            errs.append(rel(nn, out.cpu().numpy().astype(np.float64)))
+        general = {"seen_mean": float(np.mean(errs[:8])), "seen_max": float(np.max(errs[:8])),
+                   "unseen_mean": float(np.mean(errs[8:])), "unseen_max": float(np.max(errs[8:])),
+                   "metric": "relative L2 of the BF16 frame against the 256-sample filter"}
+        log(f"generalisation: seen {general['seen_mean']:.4f}, unseen {general['unseen_mean']:.4f}")
+        return {"train_steps": steps, "train_batch": 1 << 17, "training_table": "64 twill variants",
+                "generalisation": general,
                 "lerp_call_ms": lerp_ms, "blends_per_call": len(dst),
                 "bf16_ms_per_frame_after_edit": shade_ms,
                 "metric": "relative L2 over a 1080p frame showing one slot",
@@ -529,7 +550,7 @@ def main():
     ap.add_argument("--train-batch", type=int, default=1 << 18)
     ap.add_argument("--train-lr", type=float, default=1e-2)
     ap.add_argument("--gt-samples", type=int, default=256)
-    ap.add_argument("--interp-train-steps", type=int, default=3000,
+    ap.add_argument("--interp-train-steps", type=int, default=12000,
                     help="training steps of the latent interpolation row's network")
     ap.add_argument("--analytic-steps", type=int, default=10)
     ap.add_argument("--rmse-frac", type=float, default=0.01)

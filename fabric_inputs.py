@@ -154,14 +154,19 @@ INTERP_POINTS = (0.3, 0.6, 0.9)
 
 
 def parameter_sweep(field: str, values: Sequence[float], seed: int,
-                    pattern: Optional[np.ndarray] = None) -> List[Material]:
+                    pattern: Optional[np.ndarray] = None,
+                    other: Optional[float] = None) -> List[Material]:
     """One seeded material (twill 2/1 unless `pattern` is given) repeated with
     its `field` ("alpha": roughness, or "beta": height-field scaling) set to
-    each of `values` on both yarns; every other field is shared."""
+    each of `values` on both yarns; every other field is shared, the other
+    of the two set to `other` on both yarns when given.  The same seed gives
+    the same material as `sweep_training_set`'s variants start from."""
     if field not in ("alpha", "beta"):
         raise ValueError("field is alpha or beta")
     rng = np.random.default_rng(seed)
     base = random_material(rng, NAMED_PATTERNS["twill21"]() if pattern is None else pattern)
+    if other is not None:
+        base = dataclasses.replace(base, **{("beta" if field == "alpha" else "alpha"): _f32([other, other])})
     out = []
     for val in values:
         m = dataclasses.replace(base, **{field: _f32([val, val])})
@@ -170,12 +175,17 @@ def parameter_sweep(field: str, values: Sequence[float], seed: int,
 
 
 def sweep_training_set(n: int, seed: int, lo: float = 0.15, hi: float = 0.95,
-                       pattern: Optional[np.ndarray] = None) -> List[Material]:
+                       pattern: Optional[np.ndarray] = None,
+                       variant_seed: Optional[int] = None) -> List[Material]:
     """n variants of one seeded material whose roughness and height-field
     scale are drawn uniformly from [lo, hi] (per yarn): a training table that
-    spans the parameter range of the interpolation study."""
+    spans the parameter range of the interpolation study.  With
+    `variant_seed` the draws come from a generator of their own: variants of
+    the same material that a table made without it does not hold."""
     rng = np.random.default_rng(seed)
     base = random_material(rng, NAMED_PATTERNS["twill21"]() if pattern is None else pattern)
+    if variant_seed is not None:
+        rng = np.random.default_rng(variant_seed)
     return [dataclasses.replace(base, alpha=_f32(rng.uniform(lo, hi, 2)),
                                 beta=_f32(rng.uniform(lo, hi, 2))) for _ in range(n)]
 
