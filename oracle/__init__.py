@@ -97,6 +97,8 @@ def lib():
         L.orc_paper_decoder_batch.restype = ctypes.c_int64
         L.orc_paper_decoder_batch.argtypes = [_P, _P, _P, ctypes.c_int, _P, _P, _P]
         L.orc_encoder_batch.argtypes = [_P, _P, ctypes.c_int, _P]
+        L.orc_paper_loss_grad.restype = ctypes.c_double
+        L.orc_paper_loss_grad.argtypes = [_P, _P, _P, ctypes.c_int, _P, _P, _P, _P]
         L.orc_loss_grad.restype = ctypes.c_double
         L.orc_loss_grad.argtypes = [_P, _P, ctypes.c_int, _P, _P, _P, _P]
         L.orc_decoder_backward_batch.argtypes = [_P, _P, _P, ctypes.c_int, _P, _P, _P, _P]
@@ -309,6 +311,20 @@ def paper_decoder_gbuffer(params, latents, mats: Sequence, g):
     lib().orc_paper_decoder_batch(_ptr(P), _ptr(Z), materials(mats), len(mats), h.ref, _ptr(y),
                                   _ptr(rgb))
     return y, rgb
+
+
+def paper_loss_grad(params, latents, mats: Sequence, g, targets):
+    """Loss of Eq. (11) of the paper-size decoder with per-fabric latents
+    [F, 64] and its gradient: (loss, grad [27076], dlatent [F, 64])."""
+    h = _GBufHolder(g)
+    P = _d(params)
+    Z = _d(latents).reshape(-1)
+    T = np.ascontiguousarray(targets, dtype=np.float32)
+    grad = np.zeros_like(P)
+    dlat = np.zeros((len(mats), 64))
+    loss = lib().orc_paper_loss_grad(_ptr(P), _ptr(Z), materials(mats), len(mats), h.ref, _ptr(T),
+                                     _ptr(grad), _ptr(dlat))
+    return float(loss), grad, dlat
 
 
 def encoder_input(mat) -> np.ndarray:

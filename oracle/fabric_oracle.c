@@ -1090,27 +1090,67 @@ void orc_paper_features(double u, double v, double r, int wx, int wy, double f[P
  * FC layers over [spatial feature, wi.xyz, wo.xy], the second and third a
  * residual block whose input is added before the block's last activation;
  * leaky ReLU after every layer but the output. */
+/* Activations (after each leaky ReLU) kept for the backward pass. */
+typedef struct {
+    double x1[PX1], t[PHID], sp[PHID], xa[PXA1], x[PHID], h[PHID], rr[PHID], g[PHID], y[NOUT];
+} paper_acts;
+
+static void paper_forward_acts(const double *P, const double *z, const double f[PBLOB],
+                               const double ang[NANG], paper_acts *A)
+{
+    for (int k = 0; k < PLATENT; k++) A->x1[k] = z[k];
+    for (int k = 0; k < PBLOB; k++) A->x1[PLATENT + k] = f[k];
+    dense(P + P_WF1, P + P_BF1, A->x1, PX1, PHID, A->t);
+    for (int k = 0; k < PHID; k++) A->t[k] = lrelu(A->t[k]);
+    dense(P + P_WF2, P + P_BF2, A->t, PHID, PHID, A->sp);
+    for (int k = 0; k < PHID; k++) A->sp[k] = lrelu(A->sp[k]);
+    for (int k = 0; k < PHID; k++) A->xa[k] = A->sp[k];
+    for (int k = 0; k < NANG; k++) A->xa[PHID + k] = ang[k];
+    dense(P + P_WA1, P + P_BA1, A->xa, PXA1, PHID, A->x);
+    for (int k = 0; k < PHID; k++) A->x[k] = lrelu(A->x[k]);
+    dense(P + P_WA2, P + P_BA2, A->x, PHID, PHID, A->h);
+    for (int k = 0; k < PHID; k++) A->h[k] = lrelu(A->h[k]);
+    dense(P + P_WA3, P + P_BA3, A->h, PHID, PHID, A->rr);
+    for (int k = 0; k < PHID; k++) A->rr[k] = lrelu(A->rr[k] + A->x[k]);
+    dense(P + P_WA4, P + P_BA4, A->rr, PHID, PHID, A->g);
+    for (int k = 0; k < PHID; k++) A->g[k] = lrelu(A->g[k]);
+    dense(P + P_WA5, P + P_BA5, A->g, PHID, NOUT, A->y);
+}
+
 static void paper_forward(const double *P, const double *z, const double f[PBLOB],
                           const double ang[NANG], double y[NOUT])
 {
-    double x1[PX1], t[PHID], sp[PHID], xa[PXA1], x[PHID], h[PHID], rr[PHID], g[PHID];
-    for (int k = 0; k < PLATENT; k++) x1[k] = z[k];
-    for (int k = 0; k < PBLOB; k++) x1[PLATENT + k] = f[k];
-    dense(P + P_WF1, P + P_BF1, x1, PX1, PHID, t);
-    for (int k = 0; k < PHID; k++) t[k] = lrelu(t[k]);
-    dense(P + P_WF2, P + P_BF2, t, PHID, PHID, sp);
-    for (int k = 0; k < PHID; k++) sp[k] = lrelu(sp[k]);
-    for (int k = 0; k < PHID; k++) xa[k] = sp[k];
-    for (int k = 0; k < NANG; k++) xa[PHID + k] = ang[k];
-    dense(P + P_WA1, P + P_BA1, xa, PXA1, PHID, x);
-    for (int k = 0; k < PHID; k++) x[k] = lrelu(x[k]);
-    dense(P + P_WA2, P + P_BA2, x, PHID, PHID, h);
-    for (int k = 0; k < PHID; k++) h[k] = lrelu(h[k]);
-    dense(P + P_WA3, P + P_BA3, h, PHID, PHID, rr);
-    for (int k = 0; k < PHID; k++) rr[k] = lrelu(rr[k] + x[k]);
-    dense(P + P_WA4, P + P_BA4, rr, PHID, PHID, g);
-    for (int k = 0; k < PHID; k++) g[k] = lrelu(g[k]);
-    dense(P + P_WA5, P + P_BA5, g, PHID, NOUT, y);
+    paper_acts A;
+    paper_forward_acts(P, z, f, ang, &A);
+    for (int k = 0; k < NOUT; k++) y[k] = A.y[k];
+}
+
+/* Slope of the leaky ReLU at an activation a (its sign is the input's sign;
+ * the slope at 0 is the leak). */
+static double dlrelu(double a) { return a > 0.0 ? 1.0 : ORC_LEAK; }
+
+/* Backward through the paper-size decoder: adds parameter gradients into G
+ * and writes dL/dz into dz.  The residual block passes the gradient at A3's
+ * activation input both through A3 and A2 and straight to A1's output. */
+static void paper_backward(const double *P, const paper_acts *A, const double dy[NOUT],
+                           double *G, double dz[PLATENT])
+{
+    double dg[PHID], drr[PHID], dh[PHID], dxb[PHID], dx[PHID], dxa[PXA1], dsp[PHID], dt[PHID];
+    double dx1[PX1];
+    dense_backward(P + P_WA5, A->g, dy, PHID, NOUT, G + P_WA5, G + P_BA5, dg);
+    for (int k = 0; k < PHID; k++) dg[k] *= dlrelu(A->g[k]);
+    dense_backward(P + P_WA4, A->rr, dg, PHID, PHID, G + P_WA4, G + P_BA4, drr);
+    for (int k = 0; k < PHID; k++) drr[k] *= dlrelu(A->rr[k]);
+    dense_backward(P + P_WA3, A->h, drr, PHID, PHID, G + P_WA3, G + P_BA3, dh);
+    for (int k = 0; k < PHID; k++) dh[k] *= dlrelu(A->h[k]);
+    dense_backward(P + P_WA2, A->x, dh, PHID, PHID, G + P_WA2, G + P_BA2, dxb);
+    for (int k = 0; k < PHID; k++) dx[k] = (dxb[k] + drr[k]) * dlrelu(A->x[k]);
+    dense_backward(P + P_WA1, A->xa, dx, PXA1, PHID, G + P_WA1, G + P_BA1, dxa);
+    for (int k = 0; k < PHID; k++) dsp[k] = dxa[k] * dlrelu(A->sp[k]);
+    dense_backward(P + P_WF2, A->t, dsp, PHID, PHID, G + P_WF2, G + P_BF2, dt);
+    for (int k = 0; k < PHID; k++) dt[k] *= dlrelu(A->t[k]);
+    dense_backward(P + P_WF1, A->x1, dt, PX1, PHID, G + P_WF1, G + P_BF1, dx1);
+    for (int k = 0; k < PLATENT; k++) dz[k] = dx1[k];
 }
 
 /* The paper-size decoder over a G-buffer with per-fabric latents
@@ -1339,6 +1379,69 @@ void orc_decoder_backward_batch(const double *P, const double *latents, const or
         for (int k = 0; k < LATENT; k++)
             grad_latent[fid * LATENT + k] += dzp[k];
     }
+}
+
+/* Loss of Eq. (9)-(11) of the paper-size decoder on a batch with per-fabric
+ * latents z[nmats][64] (trained directly as parameters), and its gradient:
+ * grad [N_PDEC] and dlatent [nmats][64].  Faulted samples contribute
+ * nothing but count in n.  Returns the loss. */
+double orc_paper_loss_grad(const double *P, const double *latents, const orc_material *mats,
+                           int nmats, const orc_gbuffer *g, const float *targets, double *grad,
+                           double *dlatent)
+{
+    int64_t n = g->n;
+#ifdef _OPENMP
+    int nth = omp_get_max_threads();
+#else
+    int nth = 1;
+#endif
+    double *Gt = (double *)calloc((size_t)nth * N_PDEC, sizeof(double));
+    double *dzt = (double *)calloc((size_t)nth * nmats * PLATENT + 1, sizeof(double));
+    double *lt = (double *)calloc((size_t)nth, sizeof(double));
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+        int tid = omp_get_thread_num();
+#else
+        int tid = 0;
+#endif
+        double *G = Gt + (size_t)tid * N_PDEC;
+        double *dzl = dzt + (size_t)tid * nmats * PLATENT;
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < n; p++) {
+            int fid;
+            double u, v, r, wi[3], wo[3];
+            load_pixel(g, p, &fid, &u, &v, &r, wi, wo);
+            if (pixel_fault(nmats, fid, u, v, r, wi, wo))
+                continue;
+            double f[PBLOB], ang[NANG] = {wi[0], wi[1], wi[2], wo[0], wo[1]};
+            double tgt[4], dy[NOUT], dzp[PLATENT];
+            for (int c = 0; c < 4; c++)
+                tgt[c] = targets[(int64_t)c * n + p];
+            paper_acts A;
+            orc_paper_features(u, v, r, mats[fid].wx, mats[fid].wy, f);
+            paper_forward_acts(P, latents + (int64_t)fid * PLATENT, f, ang, &A);
+            lt[tid] += loss_terms(A.y, tgt, spec_k(wi[2]), n, dy);
+            paper_backward(P, &A, dy, G, dzp);
+            for (int k = 0; k < PLATENT; k++)
+                dzl[fid * PLATENT + k] += dzp[k];
+        }
+    }
+    /* Fixed-order reduction of the per-thread partials. */
+    double loss = 0.0;
+    memset(grad, 0, sizeof(double) * N_PDEC);
+    memset(dlatent, 0, sizeof(double) * nmats * PLATENT);
+    for (int t = 0; t < nth; t++) {
+        loss += lt[t];
+        for (int k = 0; k < N_PDEC; k++)
+            grad[k] += Gt[(size_t)t * N_PDEC + k];
+        for (int k = 0; k < nmats * PLATENT; k++)
+            dlatent[k] += dzt[(size_t)t * nmats * PLATENT + k];
+    }
+    free(Gt);
+    free(dzt);
+    free(lt);
+    return loss;
 }
 
 /* ---- Adam (Kingma and Ba 2015, Algorithm 1) ------------------------------ */

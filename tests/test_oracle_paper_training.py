@@ -1,0 +1,83 @@
+"""Pins of the oracle's loss gradient for the paper-size decoder (Sec. 4.2
+"Decoder", loss of Eq. (9)-(11)) with per-fabric latents as parameters:
+central differences of the oracle's own loss in FP64 for entries of every
+layer, bias and latent; the loss against the forward outputs; faulted
+samples contribute nothing; latents of fabrics absent from the batch get no
+gradient."""
+import dataclasses
+
+import numpy as np
+
+import fabric_inputs as fi
+import oracle as orc
+
+SH = fi.PAPER_DECODER_SHAPES
+
+
+def case(n=24, n_fab=3, seed=5, btdf_frac=0.3):
+    mats = fi.materials_for(n_fab, seed)
+    g = fi.make_gbuffer(n, 1, n_fab, seed=seed + 1, btdf_frac=btdf_frac)
+    g.fabric_id[:] = np.random.default_rng(seed).integers(0, n_fab, g.n).astype(np.uint16)
+    # FP64 copies, so that a perturbation of 1e-6 is not rounded away.
+    P = fi.init_paper_params(seed + 2, bias_scale=0.1).astype(np.float64)
+    Z = fi.random_latents(n_fab, seed + 3, dim=64).astype(np.float64)
+    rng = np.random.default_rng(seed + 4)
+    T = np.abs(rng.normal(0.0, 0.3, (4, g.n))).astype(np.float32)
+    return mats, g, P, Z, T
+
+
+def layer_offsets():
+    out, off = [], 0
+    for o, i in SH:
+        out.append((off, o, i))
+        off += o * i + o
+    return out
+
+
+def test_gradient_matches_central_differences():
+    mats, g, P, Z, T = case()
+    loss, grad, dlat = orc.paper_loss_grad(P, Z, mats, g, T)
+    assert np.isfinite(loss) and loss > 0
+    rng = np.random.default_rng(11)
+    idx = []
+    for off, o, i in layer_offsets():
+        idx += list(off + rng.integers(0, o * i, 6))           # weights
+        idx += list(off + o * i + rng.integers(0, o, 2))        # biases
+    h = 1e-6
+    for k in idx:
+        Pp, Pm = P.copy(), P.copy()
+        Pp[k] += h
+        Pm[k] -= h
+        fd = (orc.paper_loss_grad(Pp, Z, mats, g, T)[0] - orc.paper_loss_grad(Pm, Z, mats, g, T)[0]) / (2 * h)
+        assert abs(fd - grad[k]) <= 1e-6 * max(1.0, abs(grad).max()), (k, fd, grad[k])
+    for f, j in [(0, 0), (1, 17), (2, 63), (1, 40)]:
+        Zp, Zm = Z.copy(), Z.copy()
+        Zp[f, j] += h
+        Zm[f, j] -= h
+        fd = (orc.paper_loss_grad(P, Zp, mats, g, T)[0] - orc.paper_loss_grad(P, Zm, mats, g, T)[0]) / (2 * h)
+        assert abs(fd - dlat[f, j]) <= 1e-6 * max(1.0, abs(dlat).max()), (f, j, fd, dlat[f, j])
+
+
+def test_loss_against_forward_outputs():
+    mats, g, P, Z, T = case(n=40, btdf_frac=0.5)
+    loss, _, _ = orc.paper_loss_grad(P, Z, mats, g, T)
+    y, _ = orc.paper_decoder_gbuffer(P, Z, mats, g)
+    k = np.where(g.wi_z < 0, 1000.0, 100.0)
+    T = T.astype(np.float64)
+    ref = (0.1 * ((y[:2] - T[:2]) ** 2).sum() + 0.4 * ((y[2:] - np.log(k * T[2:] + 1.0)) ** 2).sum()) / g.n
+    assert abs(loss - ref) <= 1e-12 * ref
+
+
+def test_faulted_samples_and_absent_fabrics():
+    mats, g, P, Z, T = case(n=30, n_fab=4)
+    g.fabric_id[:] = np.where(g.fabric_id == 3, 0, g.fabric_id).astype(np.uint16)   # fabric 3 absent
+    loss, grad, dlat = orc.paper_loss_grad(P, Z, mats, g, T)
+    assert np.all(dlat[3] == 0.0) and np.abs(dlat[:3]).max() > 0
+    # A faulted sample (wo below the surface) changes nothing but the 1/n.
+    g2 = fi.GBuffer(**{f.name: np.concatenate([getattr(g, f.name), getattr(g, f.name)[:1]])
+                       for f in dataclasses.fields(fi.GBuffer)})
+    g2.wo_z[-1] = -0.5
+    T2 = np.concatenate([T, T[:, :1]], axis=1)
+    loss2, grad2, _ = orc.paper_loss_grad(P, Z, mats, g2, T2)
+    assert abs(loss2 * (g.n + 1) - loss * g.n) <= 1e-12 * loss * g.n
+    np.testing.assert_allclose(grad2 * (g.n + 1), grad * g.n, rtol=1e-10, atol=1e-14)
