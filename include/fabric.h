@@ -214,7 +214,9 @@ fabric_status fabric_lerp_latents(fabric_ctx *ctx, const int32_t *dst, const int
  *   latents  device float [n_mats][FABRIC_PAPER_LATENT], for the fabrics of
  *            the last fabric_encode
  * fabric_paper_prepare packs the weights and folds each latent into the
- * first layer (both read once, on `stream`); fabric_paper_shade then shades
+ * first layer (both read on `stream`) and keeps its own copy of both: the
+ * masters that fabric_paper_train_step updates (their Adam state is reset
+ * here).  fabric_paper_shade then shades
  * like fabric_shade_gbuffer (no fallback), with the fabric table's patterns
  * and albedos.  E_STATE: prepare before any fabric_encode, shade before
  * prepare or after a later fabric_encode. */
@@ -339,6 +341,34 @@ fabric_status fabric_train_step(fabric_ctx *ctx, const fabric_gbuffer *batch,
 fabric_status fabric_loss_grad(fabric_ctx *ctx, const fabric_gbuffer *batch, const float *targets,
                                const fabric_train_cfg *cfg, float *grad, float *out_loss,
                                void *stream);
+
+/* Training of the paper-size decoder (Sec. 4.2 "Decoder", loss of
+ * Eq. (9)-(11)) on the context's masters from fabric_paper_prepare, with
+ * one latent of FABRIC_PAPER_LATENT per fabric trained as a parameter (the
+ * paper's ResNet encoder of normal and orientation maps is not part of this
+ * library).  The batch, targets and cfg behave as for fabric_train_step
+ * (generated batch and 256-sample targets by default, visibility as set by
+ * fabric_set_visibility); cfg->prec must be FABRIC_FP32: the forward and
+ * backward run in FP32 on the vector units, one sample per lane, with
+ * fixed-order split-K weight gradients, and Adam keeps FP64 moments.
+ * fabric_paper_train_step takes one Adam step over [params | latents] and
+ * re-packs the shading image from the updated masters; a non-finite loss
+ * (known only when out_loss != NULL) skips the update and returns
+ * E_NONFINITE.  fabric_paper_loss_grad writes the gradient to device
+ * `grad` [FABRIC_N_PAPER_DECODER_PARAMS + n_mats * FABRIC_PAPER_LATENT]
+ * (parameter layout of fabric_paper_prepare, then the latents).
+ * Errors: as fabric_train_step; E_STATE before fabric_paper_prepare or
+ * after a later fabric_encode; E_RANGE for more than 64 fabrics. */
+fabric_status fabric_paper_train_step(fabric_ctx *ctx, const fabric_gbuffer *batch,
+                                      const float *targets, const fabric_train_cfg *cfg,
+                                      float *out_loss, void *stream);
+fabric_status fabric_paper_loss_grad(fabric_ctx *ctx, const fabric_gbuffer *batch,
+                                     const float *targets, const fabric_train_cfg *cfg, float *grad,
+                                     float *out_loss, void *stream);
+/* The paper-size masters to host: params [FABRIC_N_PAPER_DECODER_PARAMS],
+ * latents [n_mats][FABRIC_PAPER_LATENT].  Synchronises the device.  E_STATE
+ * before fabric_paper_prepare. */
+fabric_status fabric_paper_get_params(fabric_ctx *ctx, float *params_host, float *latents_host);
 
 /* Parameters as one FP32 vector [FABRIC_N_PARAMS] = [decoder | encoder]
  * (layouts as in fabric_decoder_forward and fabric_encoder_forward; encoder:

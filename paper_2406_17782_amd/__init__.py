@@ -26,6 +26,7 @@ __all__ = [
     "FABRIC_MAX_FABRICS", "FABRIC_MAX_SAMPLES", "FABRIC_LATENT",
     "fabric_create", "fabric_destroy", "fabric_encode", "fabric_set_albedo", "fabric_lerp_latents",
     "fabric_set_visibility", "fabric_paper_prepare", "fabric_paper_shade",
+    "fabric_paper_train_step", "fabric_paper_loss_grad", "fabric_paper_get_params",
     "FABRIC_PAPER_LATENT", "FABRIC_N_PAPER_DECODER_PARAMS",
     "fabric_shade_gbuffer", "fabric_gt_filtered", "fabric_decoder_forward",
     "fabric_decoder_backward", "fabric_encoder_forward", "fabric_encoder_backward",
@@ -248,6 +249,38 @@ def fabric_train_step(ctx, batch: Optional[DeviceGBuffer], targets, cfg: dict, w
                                       _stream(stream))
     check(st, "fabric_train_step")
     return float(loss.value) if want_loss else None
+
+
+def fabric_paper_loss_grad(ctx, batch: Optional[DeviceGBuffer], targets, cfg: dict, grad,
+                           want_loss: bool = True, stream=None) -> Optional[float]:
+    c = _train_cfg(dict(cfg, prec=FABRIC_FP32))
+    loss = ctypes.c_float(0.0)
+    gs = batch.c_struct() if batch is not None else None
+    st = _abi.lib().fabric_paper_loss_grad(ctx, ctypes.byref(gs) if gs is not None else None,
+                                           _dptr(targets), ctypes.byref(c), _dptr(grad),
+                                           ctypes.byref(loss) if want_loss else None, _stream(stream))
+    check(st, "fabric_paper_loss_grad")
+    return float(loss.value) if want_loss else None
+
+
+def fabric_paper_train_step(ctx, batch: Optional[DeviceGBuffer], targets, cfg: dict,
+                            want_loss: bool = True, stream=None) -> Optional[float]:
+    c = _train_cfg(dict(cfg, prec=FABRIC_FP32))
+    loss = ctypes.c_float(0.0)
+    gs = batch.c_struct() if batch is not None else None
+    st = _abi.lib().fabric_paper_train_step(ctx, ctypes.byref(gs) if gs is not None else None,
+                                            _dptr(targets), ctypes.byref(c),
+                                            ctypes.byref(loss) if want_loss else None, _stream(stream))
+    check(st, "fabric_paper_train_step")
+    return float(loss.value) if want_loss else None
+
+
+def fabric_paper_get_params(ctx, n_mats: int):
+    params = np.zeros(FABRIC_N_PAPER_DECODER_PARAMS, dtype=np.float32)
+    latents = np.zeros((n_mats, FABRIC_PAPER_LATENT), dtype=np.float32)
+    check(_abi.lib().fabric_paper_get_params(ctx, params.ctypes.data, latents.ctypes.data),
+          "fabric_paper_get_params")
+    return params, latents
 
 
 def fabric_get_params(ctx) -> np.ndarray:

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfabric.so")
 SOURCES = ["fabric_api.cpp", "gt_filter.hip", "decode.hip", "decode_f8.hip", "decode_paper.hip",
-           "encode.hip", "train.hip"]
+           "encode.hip", "train.hip", "paper_train.hip"]
 
 # Packed FP32 VALU instructions stay disabled: ordinary float code only.
 HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",

@@ -18,36 +18,13 @@
 #include "kernels.hpp"
 #include "mlp_tile32.hpp"
 #include "model.hpp"
+#include "paper_net.hpp"
 #include "shade.hpp"
 
 namespace fab {
 
 namespace {
 
-constexpr int kPLat = 64;                      // latent size
-constexpr int kPBlob = 24;                     // one-blob channels
-constexpr int kPX1 = kPLat + kPBlob;           // F1 inputs
-constexpr int kPXA1 = 64 + 5;                  // A1 inputs
-// Parameter offsets (rows = outputs, row-major), layers F1 F2 A1 A2 A3 A4 A5.
-constexpr int kPOffWF1 = 0;
-constexpr int kPOffBF1 = kPOffWF1 + 64 * kPX1;
-constexpr int kPOffWF2 = kPOffBF1 + 64;
-constexpr int kPOffBF2 = kPOffWF2 + 64 * 64;
-constexpr int kPOffWA1 = kPOffBF2 + 64;
-constexpr int kPOffBA1 = kPOffWA1 + 64 * kPXA1;
-constexpr int kPOffWA2 = kPOffBA1 + 64;
-constexpr int kPOffBA2 = kPOffWA2 + 64 * 64;
-constexpr int kPOffWA3 = kPOffBA2 + 64;
-constexpr int kPOffBA3 = kPOffWA3 + 64 * 64;
-constexpr int kPOffWA4 = kPOffBA3 + 64;
-constexpr int kPOffBA4 = kPOffWA4 + 64 * 64;
-constexpr int kPOffWA5 = kPOffBA4 + 64;
-constexpr int kPOffBA5 = kPOffWA5 + 4 * 64;
-constexpr int kPNDec = kPOffBA5 + 4;
-static_assert(kPNDec == FABRIC_N_PAPER_DECODER_PARAMS, "paper decoder layout");
-static_assert(kPLat == FABRIC_PAPER_LATENT, "paper latent size");
-
-constexpr float kLeak = 0.01f;
 
 // Fragment image: [layer][M-block][k-step] A fragments of 64 lanes x 8 bf16.
 // K steps: F1 2 (12 slots: 8 position bins, 4 size bins), chain layers 5
@@ -161,8 +138,6 @@ __device__ inline void paper_slots(float coord, float iper, float r, int g,
     for (int b = 0; b < 4; b++)
         s1[8 + b] = FM::gauss(8.0f * tau - (float)(4 * g + b) - 0.5f);
 }
-
-__device__ inline float lrelu(float x) { return fmaxf(x, kLeak * x); }
 
 // Leaky ReLU of a 64-neuron accumulator pair, in place (FP32).
 __device__ inline void lrelu_acc(f32x16 (&a)[2])

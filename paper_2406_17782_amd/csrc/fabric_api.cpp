@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "paper_train.hpp"
 #include "train.hpp"
 
 using namespace fab;
@@ -39,6 +40,11 @@ struct fabric_ctx {
     float *paper_cfold = nullptr;     // [FABRIC_MAX_FABRICS][64]
     int paper_n_mats = 0;             // fabrics folded by the last prepare
     uint64_t paper_serial = 0;        // table_serial of the last prepare
+    float *paper_master = nullptr;    // FP32 masters [params | latents [F][64]] (first prepare)
+    double *paper_m = nullptr;        // their FP64 Adam moments
+    double *paper_v = nullptr;
+    int64_t paper_step = 0;
+    PaperTrainScratch paper_train;
     uint64_t encoded_version = 0;     // weights_version of the last encode
     uint64_t encode_serial = 0;       // bumped on every change of latents or fabric table
 
@@ -454,6 +460,10 @@ void fabric_destroy(fabric_ctx *ctx)
     (void)hipFree(ctx->vis_fab);
     (void)hipFree(ctx->paper_image);
     (void)hipFree(ctx->paper_cfold);
+    (void)hipFree(ctx->paper_master);
+    (void)hipFree(ctx->paper_m);
+    (void)hipFree(ctx->paper_v);
+    paper_train_scratch_free(ctx->paper_train);
     for (int k = 0; k < 4; k++)
         (void)hipFree(ctx->image[k]);
     (void)hipFree(ctx->tmp_image);
@@ -590,10 +600,38 @@ fabric_status fabric_paper_prepare(fabric_ctx *ctx, const float *params, const f
     if (ctx->n_mats == 0)
         return FABRIC_E_STATE;
     DeviceGuard guard(ctx->device);
-    fabric_status st = from_hip(launch_paper_prepare(params, latents, ctx->n_mats, ctx->paper_image,
-                                                     ctx->paper_cfold, as_stream(stream)));
-    if (st != FABRIC_OK)
+    const size_t total = (size_t)FABRIC_N_PAPER_DECODER_PARAMS + (size_t)FABRIC_MAX_FABRICS * FABRIC_PAPER_LATENT;
+    fabric_status st = FABRIC_OK;
+    if (!ctx->paper_master) {
+        st = dalloc(&ctx->paper_master, total);
+        if (st == FABRIC_OK) st = dalloc(&ctx->paper_m, total);
+        if (st == FABRIC_OK) st = dalloc(&ctx->paper_v, total);
+        if (st != FABRIC_OK) {
+            (void)hipFree(ctx->paper_master);
+            (void)hipFree(ctx->paper_m);
+            (void)hipFree(ctx->paper_v);
+            ctx->paper_master = nullptr;
+            ctx->paper_m = ctx->paper_v = nullptr;
+            return st;
+        }
+    }
+    // The context keeps its own copy (the masters training updates).
+    hipStream_t s = as_stream(stream);
+    float *pm = ctx->paper_master, *lm = ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS;
+    st = from_hip(hipMemcpyAsync(pm, params, FABRIC_N_PAPER_DECODER_PARAMS * sizeof(float),
+                                 hipMemcpyDeviceToDevice, s));
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpyAsync(lm, latents, (size_t)ctx->n_mats * FABRIC_PAPER_LATENT * sizeof(float),
+                                     hipMemcpyDeviceToDevice, s));
+    if (st == FABRIC_OK) st = from_hip(hipMemsetAsync(ctx->paper_m, 0, total * sizeof(double), s));
+    if (st == FABRIC_OK) st = from_hip(hipMemsetAsync(ctx->paper_v, 0, total * sizeof(double), s));
+    if (st == FABRIC_OK)
+        st = from_hip(launch_paper_prepare(pm, lm, ctx->n_mats, ctx->paper_image, ctx->paper_cfold, s));
+    if (st != FABRIC_OK) {
+        ctx->paper_n_mats = 0;
         return st;
+    }
+    ctx->paper_step = 0;
     ctx->paper_n_mats = ctx->n_mats;
     ctx->paper_serial = ctx->table_serial;
     return FABRIC_OK;
@@ -880,6 +918,102 @@ fabric_status fabric_train_step(fabric_ctx *ctx, const fabric_gbuffer *batch, co
     ctx->step += 1;
     ctx->weights_version += 1;
     return FABRIC_OK;
+}
+
+namespace {
+fabric_status check_paper_train_args(fabric_ctx *ctx, const fabric_gbuffer *batch,
+                                     const float *targets, const fabric_train_cfg *cfg)
+{
+    fabric_status st = check_train_args(ctx, batch, targets, cfg);
+    if (st != FABRIC_OK)
+        return st;
+    if (cfg->prec != FABRIC_FP32)
+        return FABRIC_E_INVAL;
+    if (ctx->paper_n_mats == 0 || ctx->paper_serial != ctx->table_serial ||
+        ctx->paper_n_mats != ctx->n_mats)
+        return FABRIC_E_STATE;
+    if (ctx->n_mats > kPaperTrainMaxFabrics)
+        return FABRIC_E_RANGE;
+    return FABRIC_OK;
+}
+
+PaperTrainArgs paper_train_args(fabric_ctx *ctx, const fabric_gbuffer *batch, const float *targets,
+                                const fabric_train_cfg *cfg)
+{
+    PaperTrainArgs a;
+    a.master = ctx->paper_master;
+    a.adam_m = ctx->paper_m;
+    a.adam_v = ctx->paper_v;
+    a.step = ctx->paper_step + 1;
+    a.fabrics = ctx->fabrics;
+    a.n_fabrics = ctx->n_mats;
+    a.batch = batch;
+    a.targets = targets;
+    a.cfg = *cfg;
+    a.err = ctx->err;
+    a.vis = VisArgs{nullptr, nullptr};
+    return a;
+}
+}  // namespace
+
+fabric_status fabric_paper_loss_grad(fabric_ctx *ctx, const fabric_gbuffer *batch,
+                                     const float *targets, const fabric_train_cfg *cfg, float *grad,
+                                     float *out_loss, void *stream)
+{
+    fabric_status st = check_paper_train_args(ctx, batch, targets, cfg);
+    if (st != FABRIC_OK)
+        return st;
+    if (!grad)
+        return FABRIC_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    PaperTrainArgs a = paper_train_args(ctx, batch, targets, cfg);
+    if (!targets && (st = ensure_vis(ctx, as_stream(stream), &a.vis)) != FABRIC_OK)
+        return st;
+    return from_hip(paper_loss_grad(ctx->paper_train, a, grad, out_loss, as_stream(stream)));
+}
+
+fabric_status fabric_paper_train_step(fabric_ctx *ctx, const fabric_gbuffer *batch,
+                                      const float *targets, const fabric_train_cfg *cfg,
+                                      float *out_loss, void *stream)
+{
+    fabric_status st = check_paper_train_args(ctx, batch, targets, cfg);
+    if (st != FABRIC_OK)
+        return st;
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = as_stream(stream);
+    PaperTrainArgs a = paper_train_args(ctx, batch, targets, cfg);
+    if (!targets && (st = ensure_vis(ctx, s, &a.vis)) != FABRIC_OK)
+        return st;
+    int updated = 0;
+    hipError_t e = paper_train_step(ctx->paper_train, a, out_loss, &updated, s);
+    // The shading image follows the masters (unchanged when the step was skipped).
+    if (e == hipSuccess)
+        e = launch_paper_prepare(ctx->paper_master, ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS,
+                                 ctx->n_mats, ctx->paper_image, ctx->paper_cfold, s);
+    if (e != hipSuccess)
+        return from_hip(e);
+    if (!updated)
+        return FABRIC_E_NONFINITE;
+    ctx->paper_step += 1;
+    return FABRIC_OK;
+}
+
+fabric_status fabric_paper_get_params(fabric_ctx *ctx, float *params_host, float *latents_host)
+{
+    if (!ctx || !params_host || !latents_host)
+        return FABRIC_E_INVAL;
+    if (ctx->paper_n_mats == 0 || !ctx->paper_master)
+        return FABRIC_E_STATE;
+    DeviceGuard guard(ctx->device);
+    fabric_status st = from_hip(hipDeviceSynchronize());
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpy(params_host, ctx->paper_master,
+                                FABRIC_N_PAPER_DECODER_PARAMS * sizeof(float), hipMemcpyDeviceToHost));
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpy(latents_host, ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS,
+                                (size_t)ctx->paper_n_mats * FABRIC_PAPER_LATENT * sizeof(float),
+                                hipMemcpyDeviceToHost));
+    return st;
 }
 
 fabric_status fabric_get_params(fabric_ctx *ctx, float *host, size_t count)

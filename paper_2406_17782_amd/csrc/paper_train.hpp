@@ -1,0 +1,56 @@
+// Training of the paper-size decoder (Sec. 4.2 "Decoder", loss of Eq. (9)-(11))
+// with one latent of 64 per fabric as a free parameter.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace fab {
+
+// Fabrics a paper-size training batch may draw from (the per-fabric latent
+// gradient is one split-K job of 64 x n_fabrics entries).
+constexpr int kPaperTrainMaxFabrics = 64;
+
+// Device scratch owned by a context, grown on demand.
+struct PaperTrainScratch {
+    int64_t cap = 0;              // samples the per-sample planes hold
+    float *planes = nullptr;      // per-sample planes [801][cap] (see paper_train.hip)
+    double *loss_part = nullptr;  // per 256-sample block
+    double *loss = nullptr;       // [1]
+    float *wt = nullptr;          // transposed weights of F2, A1 (first 64 inputs), A2, A3, A4
+    float *partial = nullptr;     // split-K partial weight gradients
+    size_t partial_floats = 0;
+    float *grad = nullptr;        // [params | latents]
+    float *dsum = nullptr;        // [fabric][64]: per-fabric sums of F1's input gradient
+    int64_t batch_cap = 0;        // generated batch and targets
+    uint16_t *b_fid = nullptr;
+    float *b_fields = nullptr;    // 9 planes of batch_cap floats
+    float *targets = nullptr;     // [4][batch_cap]
+};
+
+void paper_train_scratch_free(PaperTrainScratch &s);
+
+struct PaperTrainArgs {
+    float *master;                // [params (FABRIC_N_PAPER_DECODER_PARAMS) | latents [F][64]]
+    double *adam_m, *adam_v;      // same length
+    int64_t step;                 // 1-based Adam step of this update
+    const DevFabric *fabrics;
+    int n_fabrics;
+    const fabric_gbuffer *batch;  // NULL: generate
+    const float *targets;         // NULL: analytic filter
+    fabric_train_cfg cfg;
+    unsigned long long *err;
+    VisArgs vis;
+};
+
+// Loss and gradient [params | latents] of one batch into grad_out (device).
+hipError_t paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, float *grad_out,
+                           float *out_loss, hipStream_t stream);
+
+// One Adam step of the paper-size decoder and its latents; *updated = 0 when
+// the loss was non-finite (known only when out_loss != NULL).
+hipError_t paper_train_step(PaperTrainScratch &s, const PaperTrainArgs &a, float *out_loss,
+                            int *updated, hipStream_t stream);
+
+}  // namespace fab

@@ -762,6 +762,17 @@ void train_scratch_free(TrainScratch &s)
     s = TrainScratch();
 }
 
+hipError_t launch_adam(float *params, const float *grad, double *m, double *v, int n,
+                       const fabric_train_cfg &cfg, int64_t step, const double *loss,
+                       hipStream_t stream)
+{
+    const double c1 = 1.0 - std::pow(cfg.beta1, (double)step);
+    const double c2 = 1.0 - std::pow(cfg.beta2, (double)step);
+    hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, params, grad, m, v,
+                       n, cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, c1, c2, loss);
+    return hipGetLastError();
+}
+
 hipError_t launch_make_batch(uint64_t seed, int64_t n, int n_fabrics, float r_lo, float r_hi,
                              float btdf_frac, const fabric_gbuffer_out &out, hipStream_t stream)
 {

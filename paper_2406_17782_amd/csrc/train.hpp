@@ -50,6 +50,12 @@ hipError_t launch_make_batch(uint64_t seed, int64_t n, int n_fabrics, float r_lo
                              float btdf_frac,
                              const fabric_gbuffer_out &out, hipStream_t stream);
 
+// Adam (FP64 moments, FP32 masters) on n parameters at 1-based step `step`;
+// the kernel skips the update when *loss is not finite.
+hipError_t launch_adam(float *params, const float *grad, double *m, double *v, int n,
+                       const fabric_train_cfg &cfg, int64_t step, const double *loss,
+                       hipStream_t stream);
+
 // Decoder backward for explicit parameters and upstream gradients dy[4][n]
 // (FP32): grad_params [FABRIC_N_DECODER_PARAMS], grad_latents [F][32].
 hipError_t decoder_backward(TrainScratch &s, const fabric_gbuffer &g, const DevFabric *fabrics,

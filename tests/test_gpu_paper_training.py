@@ -1,0 +1,141 @@
+"""GPU parity of the paper-size decoder's training (Sec. 4.2 "Decoder", loss
+of Eq. (9)-(11), per-fabric latents trained as parameters) through the C
+ABI: the FP32 loss and gradient against the oracle's FP64 backward on a
+ragged batch with transmission and faulted samples (norm-wise per tensor
+1e-4, as for the config decoder); two Adam steps against the oracle's;
+training on generated batches lowers the loss and the shading image follows
+the trained masters; call errors."""
+import numpy as np
+import pytest
+
+import fabric_inputs as fi
+from tests.helpers import rel_norm_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+N = fi.N_PAPER_DECODER_PARAMS
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def pkg(torch):
+    import paper_2406_17782_amd as pkg
+    return pkg
+
+
+@pytest.fixture()
+def fab(pkg):
+    f = pkg.Fabric(0, seed=71)
+    yield f
+    f.close()
+
+
+def prepare(fab, pkg, torch, mats, seed):
+    fab.encode(mats)
+    params = fi.init_paper_params(seed, bias_scale=0.05)
+    z = fi.random_latents(len(mats), seed + 1, dim=64)
+    pkg.fabric_paper_prepare(fab.ctx, torch.from_numpy(params).cuda(), torch.from_numpy(z).cuda())
+    return params, z
+
+
+def batch(n_fab, w, h, seed):
+    g = fi.make_gbuffer(w, h, n_fab, seed=seed, btdf_frac=0.3)
+    g.fabric_id[:] = np.random.default_rng(seed + 1).integers(0, n_fab, g.n).astype(np.uint16)
+    return g
+
+
+def per_tensor_errors(got, ref, n_fab):
+    errs, off = [], 0
+    for o, i in fi.PAPER_DECODER_SHAPES:
+        for size in (o * i, o):
+            errs.append(rel_norm_err(got[off:off + size], ref[off:off + size]))
+            off += size
+    errs.append(rel_norm_err(got[off:off + n_fab * 64], ref[off:off + n_fab * 64]))
+    return errs
+
+
+def test_paper_loss_grad_matches_oracle(fab, pkg, orc, torch):
+    mats = fi.materials_for(5, 300)
+    g = batch(5, 61, 53, 301)            # 3,233 samples: ragged in every split
+    g.wo_z[5] = -0.3                     # faulted samples contribute nothing
+    g.radius[9] = 0.0
+    tg = fi.random_targets(g.n, 302)
+    params, z = prepare(fab, pkg, torch, mats, 303)
+    grad = torch.empty(N + 5 * 64, device="cuda")
+    loss = pkg.fabric_paper_loss_grad(fab.ctx, pkg.DeviceGBuffer.from_host(g),
+                                      torch.from_numpy(tg).cuda(), {}, grad)
+    oloss, ograd, odlat = orc.paper_loss_grad(params, z, mats, g, tg)
+    assert loss == pytest.approx(oloss, rel=1e-5)
+    errs = per_tensor_errors(grad.cpu().numpy(), np.concatenate([ograd, odlat.ravel()]), 5)
+    print("paper gradient errors", ["%.2e" % e for e in errs])
+    assert max(errs) < 1e-4
+
+
+def test_paper_adam_steps_match_oracle(fab, pkg, orc, torch):
+    mats = fi.materials_for(3, 310)
+    g = batch(3, 40, 31, 311)
+    tg = fi.random_targets(g.n, 312)
+    params, z = prepare(fab, pkg, torch, mats, 313)
+    theta = np.concatenate([params, z.ravel()]).astype(np.float32)
+    m = np.zeros(theta.size)
+    v = np.zeros(theta.size)
+    dg, dt = pkg.DeviceGBuffer.from_host(g), torch.from_numpy(tg).cuda()
+    for t in (1, 2):
+        _, og, odl = orc.paper_loss_grad(theta[:N].astype(np.float64),
+                                         theta[N:].reshape(3, 64).astype(np.float64), mats, g, tg)
+        full = np.concatenate([og, odl.ravel()])
+        orc.adam_step(theta, full, m, v, t, 1e-3)
+        pkg.fabric_paper_train_step(fab.ctx, dg, dt, {"lr": 1e-3})
+        gp, gz = pkg.fabric_paper_get_params(fab.ctx, 3)
+        got = np.concatenate([gp, gz.ravel()])
+        solid = np.abs(full) > 1e-5
+        assert np.abs(got[solid] - theta[solid]).max() < 2e-6 * t
+        assert np.abs(got - theta).max() <= 2.1e-3 * t
+
+
+def test_paper_training_lowers_loss_and_shades(fab, pkg, orc, torch):
+    mats = fi.materials_for(8, 320)
+    prepare(fab, pkg, torch, mats, 321)
+    cfg = dict(batch=1 << 13, gt_samples=16, lr=3e-3)
+    first = pkg.fabric_paper_train_step(fab.ctx, None, None, dict(cfg, seed=1))
+    for s in range(2, 80):
+        pkg.fabric_paper_train_step(fab.ctx, None, None, dict(cfg, seed=s), want_loss=False)
+    last = np.mean([pkg.fabric_paper_train_step(fab.ctx, None, None, dict(cfg, seed=100 + s))
+                    for s in range(5)])
+    print("paper training loss", first, last)
+    assert last < 0.5 * first
+    # The shading image is re-packed from the trained masters.
+    gp, gz = pkg.fabric_paper_get_params(fab.ctx, 8)
+    g = batch(8, 48, 40, 322)
+    out = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
+    pkg.fabric_paper_shade(fab.ctx, pkg.DeviceGBuffer.from_host(g), out, "fp16")
+    _, orgb = orc.paper_decoder_gbuffer(gp, gz, mats, g)
+    err = rel_norm_err(out.cpu().numpy(), orgb)
+    print("trained paper decoder fp16 vs oracle", err)
+    assert err < 2e-2
+
+
+def test_paper_training_errors(fab, pkg, torch):
+    mats = fi.materials_for(2, 330)
+    fab.encode(mats)
+    with pytest.raises(pkg.FabricError) as e:
+        pkg.fabric_paper_train_step(fab.ctx, None, None, dict(batch=256, gt_samples=4))
+    assert e.value.status == 6                        # E_STATE: no prepare yet
+    prepare(fab, pkg, torch, mats, 331)
+    c = pkg._train_cfg(dict(batch=256, gt_samples=4, prec=pkg.FABRIC_BF16))
+    st = pkg._abi.lib().fabric_paper_train_step(fab.ctx, None, None, pkg.ctypes.byref(c), None, None)
+    assert st == 1                                    # E_INVAL: FP32 only
+    pkg.fabric_paper_train_step(fab.ctx, None, None, dict(batch=256, gt_samples=4))
+    fab.encode(mats)
+    with pytest.raises(pkg.FabricError) as e:
+        pkg.fabric_paper_train_step(fab.ctx, None, None, dict(batch=256, gt_samples=4))
+    assert e.value.status == 6                        # E_STATE: table re-encoded
+    many = fi.materials_for(65, 332)
+    prepare(fab, pkg, torch, many, 333)
+    with pytest.raises(pkg.FabricError) as e:
+        pkg.fabric_paper_train_step(fab.ctx, None, None, dict(batch=256, gt_samples=4))
+    assert e.value.status == 2                        # E_RANGE: more than 64 fabrics
