@@ -394,9 +394,9 @@ PAPER_FLOP_PER_PIXEL = 2 * (24 * 64 + 64 * 64 + 69 * 64 + 3 * 64 * 64 + 64 * 4) 
 def paper_decoder_row(args, torch, pkg, fi, mats, g, d):
     """The decoder at the paper's own form (latent 64, one-blob 24, 2 + 5
     layers of width 64 with a residual skip, leaky ReLU), BF16 on the 1080p
-    frame with seeded weights and latents (inference only: this build trains
-    the config-size decoder); its error against the FP64 oracle's forward of
-    the same weights on a seeded 1 %."""
+    frame with seeded weights and latents (the training row trains its own);
+    its error against the FP64 oracle's forward of the same weights on a
+    seeded 1 %."""
     fab = pkg.Fabric(0, seed=7)
     try:
         fab.encode(mats)
@@ -416,7 +416,7 @@ def paper_decoder_row(args, torch, pkg, fi, mats, g, d):
         tflops = PAPER_FLOP_PER_PIXEL * g.n / (ms * 1e-3) / 1e12
         res = {"ms_per_frame": ms, "mpix_per_s": g.n / (ms * 1e-3) / 1e6,
                "algorithmic_flop_per_pixel": PAPER_FLOP_PER_PIXEL, "tflops": tflops,
-               "mfma_frac": tflops / BF16_PEAK_TFLOPS, "weights": "seeded (inference only)",
+               "mfma_frac": tflops / BF16_PEAK_TFLOPS, "weights": "seeded",
                "fp16_ms_per_frame": ms16,
                "fp16_mfma_frac": PAPER_FLOP_PER_PIXEL * g.n / (ms16 * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
                "paper_rtx3090_decoder_ms_per_1080p_frame": [13.6, 14.4]}
@@ -431,6 +431,78 @@ def paper_decoder_row(args, torch, pkg, fi, mats, g, d):
             res["fp16_rel_l2_vs_fp64_oracle"] = float(np.linalg.norm(r16 - o_rgb) / np.linalg.norm(o_rgb))
         log(f"paper-size decoder: bf16 {ms * 1e3:.1f} us/frame, {tflops:.0f} TFLOP/s "
             f"({100 * tflops / BF16_PEAK_TFLOPS:.1f} % of bf16 peak); fp16 {ms16 * 1e3:.1f} us")
+        return res
+    finally:
+        fab.close()
+
+
+def paper_training_row(args, torch, pkg, fi, mats, g, d, config_rgb):
+    """The paper-size decoder trained on the 1080p workload's fabrics (one
+    latent of 64 per fabric trained as a parameter; FP32 training kernels;
+    generated batches of 2^16 samples with 256-sample targets, Adam with a
+    cosine-decayed rate); its FP16 and BF16 frames against the oracle's
+    filter on the main section's seeded 1 %, by footprint radius, beside the
+    config-size network and one analytic sample."""
+    fab = pkg.Fabric(0, seed=4600)
+    try:
+        fab.encode(mats)
+        params = fi.init_paper_params(5, bias_scale=0.0)
+        z = fi.random_latents(len(mats), 6, scale=0.1, dim=64)
+        pkg.fabric_paper_prepare(fab.ctx, torch.from_numpy(params).cuda(), torch.from_numpy(z).cuda())
+        steps, batch = args.paper_train_steps, 1 << 16
+        losses = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            lr = args.train_lr * 0.5 * (1.0 + math.cos(math.pi * s / max(1, steps)))
+            want = s == 0 or s == steps - 1
+            l = pkg.fabric_paper_train_step(fab.ctx, None, None,
+                                            dict(batch=batch, gt_samples=args.gt_samples,
+                                                 seed=3_000_000 + s, lr=lr), want_loss=want)
+            if want:
+                losses.append(l)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        out = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
+        fp16 = lambda: pkg.fabric_paper_shade(fab.ctx, d, out, "fp16")
+        for _ in range(100):
+            fp16()
+        ms16 = time_launches(torch, fp16, 100)
+        rgb16 = out.cpu().numpy()
+        pkg.fabric_paper_shade(fab.ctx, d, out, "bf16")
+        rgb_bf = out.cpu().numpy()
+        res = {"train_steps": steps, "train_batch": batch,
+               "train_ms_per_step": train_s / max(1, steps) * 1e3,
+               "train_s": train_s, "loss_first": losses[0] if losses else None,
+               "loss_last": losses[-1] if losses else None,
+               "latents": "one per fabric, trained as parameters",
+               "fp16_ms_per_frame": ms16}
+        log(f"paper-size training: {steps} steps in {train_s:.1f}s, loss "
+            f"{res['loss_first']} -> {res['loss_last']}")
+        if not args.no_rmse and steps > 0:
+            import oracle
+            idx = fi.subset_indices(g.n, args.rmse_frac, 99)
+            sub = g.subset(idx)
+            _, o_rgb, _, _ = oracle.filter_gbuffer(mats, sub, args.gt_samples, 4242,
+                                                   same_sample=True, pixel_index=idx)
+            one = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
+            pkg.fabric_gt_filtered(fab.ctx, d, 1, 777, one, None)
+            preds = {"paper_fp16": rgb16[:, idx], "paper_bf16": rgb_bf[:, idx],
+                     "config_bf16": config_rgb[:, idx], "analytic_1spp": one.cpu().numpy()[:, idx]}
+            res["rmse_vs_fp64_oracle"] = {k: rmse_stats(v, o_rgb) for k, v in preds.items()}
+            edges = [1e-3, 0.01, 0.05, 0.15, 0.3, 0.5]
+            by_r = {}
+            for lo, hi in zip(edges[:-1], edges[1:]):
+                m = (sub.radius >= lo) & (sub.radius < hi)
+                by_r[f"[{lo},{hi})"] = dict(
+                    pixels=int(m.sum()),
+                    **{k: float(np.sqrt(np.mean((v[:, m] - o_rgb[:, m]) ** 2))) for k, v in preds.items()})
+            res["rmse_by_footprint_radius"] = by_r
+            e = res["rmse_vs_fp64_oracle"]
+            res["paper_fp16_beats_1spp"] = e["paper_fp16"]["rmse"] < e["analytic_1spp"]["rmse"]
+            log(f"paper-size network rmse fp16 {e['paper_fp16']['rmse']:.4g}, bf16 "
+                f"{e['paper_bf16']['rmse']:.4g}; config bf16 {e['config_bf16']['rmse']:.4g}, "
+                f"1spp {e['analytic_1spp']['rmse']:.4g}")
         return res
     finally:
         fab.close()
@@ -552,6 +624,8 @@ def main():
     ap.add_argument("--gt-samples", type=int, default=256)
     ap.add_argument("--interp-train-steps", type=int, default=12000,
                     help="training steps of the latent interpolation row's network")
+    ap.add_argument("--paper-train-steps", type=int, default=48000,
+                    help="training steps (2^16 samples each) of the paper-size decoder's row")
     ap.add_argument("--analytic-steps", type=int, default=10)
     ap.add_argument("--rmse-frac", type=float, default=0.01)
     ap.add_argument("--cpu-budget", type=float, default=8.0)
@@ -700,6 +774,7 @@ def main():
         rows["visibility"] = visibility_row(args, torch, pkg, fi, wl, mats, g, d, ms)
         rows["transmission"] = btdf_row(args, torch, pkg, fi)
         rows["paper_decoder"] = paper_decoder_row(args, torch, pkg, fi, mats, g, d)
+        rows["paper_training"] = paper_training_row(args, torch, pkg, fi, mats, g, d, rgb["bf16"])
 
     # ---- error against the FP64 oracle on a seeded pixel subset ----
     args.neural_ms = ms

@@ -204,9 +204,10 @@ fabric_status fabric_lerp_latents(fabric_ctx *ctx, const int32_t *dst, const int
  * [spatial feature, wi.xyz, wo.xy], the second and third forming a residual
  * block whose input is added before its last activation; leaky ReLU (0.01)
  * after every layer but the output; width 64.  Outputs decoded and composed
- * as fabric_shade_gbuffer does (k = 100, or 1000 where wi.z < 0).  Inference
- * only: prec FABRIC_BF16 or FABRIC_FP16 operands with FP32 accumulation (the
- * FP16 path applies the leaky ReLU to packed halves).
+ * as fabric_shade_gbuffer does (k = 100, or 1000 where wi.z < 0).  Shading
+ * takes prec FABRIC_BF16 or FABRIC_FP16 operands with FP32 accumulation (the
+ * FP16 path applies the leaky ReLU to packed halves); training is
+ * fabric_paper_train_step.
  *   params   device float [FABRIC_N_PAPER_DECODER_PARAMS], rows = outputs:
  *            WF1[64][88] ([z(64), u bins, v bins, size bins]) bF1[64]
  *            WF2[64][64] bF2 WA1[64][69] ([s(64), wi.xyz, wo.xy]) bA1
