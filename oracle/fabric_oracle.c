@@ -1068,6 +1068,21 @@ int orc_paper_param_count(void) { return N_PDEC; }
 
 static double lrelu(double x) { return x > 0.0 ? x : ORC_LEAK * x; }
 
+/* Footprint inputs without the encoding (the ablation of Sec. 5 "Encoding
+ * of footprint"): the position fractions p_u, p_v and the size tau as plain
+ * inputs, in the channels of their first one-blob bin (0, 8, 16); the other
+ * channels are 0. */
+void orc_paper_features_raw(double u, double v, double r, int wx, int wy, double f[PBLOB])
+{
+    for (int k = 0; k < PBLOB; k++) f[k] = 0.0;
+    f[0] = floor_mod(u, wx) / wx;
+    f[8] = floor_mod(v, wy) / wy;
+    double tau = (log2(r) + 14.0) / 16.0;
+    if (tau < 0.0) tau = 0.0;
+    if (tau > 1.0) tau = 1.0;
+    f[16] = tau;
+}
+
 void orc_paper_features(double u, double v, double r, int wx, int wy, double f[PBLOB])
 {
     double p[2] = {floor_mod(u, wx) / wx, floor_mod(v, wy) / wy};
@@ -1155,9 +1170,10 @@ static void paper_backward(const double *P, const paper_acts *A, const double dy
 
 /* The paper-size decoder over a G-buffer with per-fabric latents
  * z[nmats][64]: raw outputs y [4][n] and composed rgb [3][n] (decoded and
- * composed as the shading path does); faulted pixels give 0. */
+ * composed as the shading path does); faulted pixels give 0.  raw != 0:
+ * footprint inputs without the one-blob encoding. */
 int64_t orc_paper_decoder_batch(const double *P, const double *latents, const orc_material *mats,
-                                int nmats, const orc_gbuffer *g, double *y, double *rgb)
+                                int nmats, const orc_gbuffer *g, int raw, double *y, double *rgb)
 {
     int64_t n = g->n, faults = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : faults)
@@ -1168,7 +1184,7 @@ int64_t orc_paper_decoder_batch(const double *P, const double *latents, const or
         int bad = pixel_fault(nmats, fid, u, v, r, wi, wo);
         if (!bad) {
             double f[PBLOB], ang[NANG] = {wi[0], wi[1], wi[2], wo[0], wo[1]}, comp[4];
-            orc_paper_features(u, v, r, mats[fid].wx, mats[fid].wy, f);
+            (raw ? orc_paper_features_raw : orc_paper_features)(u, v, r, mats[fid].wx, mats[fid].wy, f);
             paper_forward(P, latents + (int64_t)fid * PLATENT, f, ang, out);
             decode_outputs(out, spec_k(wi[2]), comp);
             compose_rgb(&mats[fid], comp, c3);
@@ -1386,8 +1402,8 @@ void orc_decoder_backward_batch(const double *P, const double *latents, const or
  * grad [N_PDEC] and dlatent [nmats][64].  Faulted samples contribute
  * nothing but count in n.  Returns the loss. */
 double orc_paper_loss_grad(const double *P, const double *latents, const orc_material *mats,
-                           int nmats, const orc_gbuffer *g, const float *targets, double *grad,
-                           double *dlatent)
+                           int nmats, const orc_gbuffer *g, int raw, const float *targets,
+                           double *grad, double *dlatent)
 {
     int64_t n = g->n;
 #ifdef _OPENMP
@@ -1419,7 +1435,7 @@ double orc_paper_loss_grad(const double *P, const double *latents, const orc_mat
             for (int c = 0; c < 4; c++)
                 tgt[c] = targets[(int64_t)c * n + p];
             paper_acts A;
-            orc_paper_features(u, v, r, mats[fid].wx, mats[fid].wy, f);
+            (raw ? orc_paper_features_raw : orc_paper_features)(u, v, r, mats[fid].wx, mats[fid].wy, f);
             paper_forward_acts(P, latents + (int64_t)fid * PLATENT, f, ang, &A);
             lt[tid] += loss_terms(A.y, tgt, spec_k(wi[2]), n, dy);
             paper_backward(P, &A, dy, G, dzp);

@@ -7,6 +7,7 @@ gradient."""
 import dataclasses
 
 import numpy as np
+import pytest
 
 import fabric_inputs as fi
 import oracle as orc
@@ -34,9 +35,10 @@ def layer_offsets():
     return out
 
 
-def test_gradient_matches_central_differences():
+@pytest.mark.parametrize("raw", [False, True])
+def test_gradient_matches_central_differences(raw):
     mats, g, P, Z, T = case()
-    loss, grad, dlat = orc.paper_loss_grad(P, Z, mats, g, T)
+    loss, grad, dlat = orc.paper_loss_grad(P, Z, mats, g, T, raw=raw)
     assert np.isfinite(loss) and loss > 0
     rng = np.random.default_rng(11)
     idx = []
@@ -48,13 +50,15 @@ def test_gradient_matches_central_differences():
         Pp, Pm = P.copy(), P.copy()
         Pp[k] += h
         Pm[k] -= h
-        fd = (orc.paper_loss_grad(Pp, Z, mats, g, T)[0] - orc.paper_loss_grad(Pm, Z, mats, g, T)[0]) / (2 * h)
+        fd = (orc.paper_loss_grad(Pp, Z, mats, g, T, raw=raw)[0] -
+              orc.paper_loss_grad(Pm, Z, mats, g, T, raw=raw)[0]) / (2 * h)
         assert abs(fd - grad[k]) <= 1e-6 * max(1.0, abs(grad).max()), (k, fd, grad[k])
     for f, j in [(0, 0), (1, 17), (2, 63), (1, 40)]:
         Zp, Zm = Z.copy(), Z.copy()
         Zp[f, j] += h
         Zm[f, j] -= h
-        fd = (orc.paper_loss_grad(P, Zp, mats, g, T)[0] - orc.paper_loss_grad(P, Zm, mats, g, T)[0]) / (2 * h)
+        fd = (orc.paper_loss_grad(P, Zp, mats, g, T, raw=raw)[0] -
+              orc.paper_loss_grad(P, Zm, mats, g, T, raw=raw)[0]) / (2 * h)
         assert abs(fd - dlat[f, j]) <= 1e-6 * max(1.0, abs(dlat).max()), (f, j, fd, dlat[f, j])
 
 
@@ -81,3 +85,28 @@ def test_faulted_samples_and_absent_fabrics():
     loss2, grad2, _ = orc.paper_loss_grad(P, Z, mats, g2, T2)
     assert abs(loss2 * (g.n + 1) - loss * g.n) <= 1e-12 * loss * g.n
     np.testing.assert_allclose(grad2 * (g.n + 1), grad * g.n, rtol=1e-10, atol=1e-14)
+
+
+def test_raw_footprint_inputs():
+    """Without the encoding (the ablation of Sec. 5 "Encoding of
+    footprint") the inputs are p_u = (u mod W_x) / W_x, p_v likewise and
+    tau = clamp((log2 r + 14) / 16, 0, 1), in the channels of their first
+    one-blob bin; every other channel is 0."""
+    for (u, v, r, wx, wy), (pu, pv, tau) in [((2.5, -1.25, 0.25, 4, 3), (0.625, 1.75 / 3, 0.75)),
+                                             ((7.0, 3.0, 2.0 ** -20, 2, 3), (0.5, 0.0, 0.0)),
+                                             ((0.0, 0.5, 8.0, 5, 1), (0.0, 0.5, 1.0))]:
+        f = orc.paper_features(u, v, r, wx, wy, raw=True)
+        assert f[0] == pytest.approx(pu, abs=1e-15) and f[8] == pytest.approx(pv, abs=1e-15)
+        assert f[16] == pytest.approx(tau, abs=1e-15)
+        assert np.count_nonzero(np.delete(f, [0, 8, 16])) == 0
+    # The network sees exactly these inputs: with weights that pass F1's
+    # neuron 0 (reading channel 16) through F2, A1, the residual skip, A4
+    # and A5 unchanged, the first output is tau.
+    mats, g, P, Z, _ = case(n=6, n_fab=1)
+    P = np.zeros_like(P)
+    (f1, _, i1), (f2, _, i2), (a1, _, ia1), _, _, (a4, _, i4), (a5, _, _) = layer_offsets()
+    P[f1 + 64 + 16] = 1.0                 # WF1[0][z(64) + channel 16]
+    P[f2] = P[a1] = P[a4] = P[a5] = 1.0   # WF2[0][0], WA1[0][0], WA4[0][0], WA5[0][0]
+    y, _ = orc.paper_decoder_gbuffer(P, Z, mats, g, raw=True)
+    tau = np.clip((np.log2(g.radius.astype(np.float64)) + 14.0) / 16.0, 0.0, 1.0)
+    np.testing.assert_allclose(y[0], tau, rtol=0, atol=1e-15)
