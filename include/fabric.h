@@ -366,6 +366,14 @@ fabric_status fabric_paper_train_step(fabric_ctx *ctx, const fabric_gbuffer *bat
 fabric_status fabric_paper_loss_grad(fabric_ctx *ctx, const fabric_gbuffer *batch,
                                      const float *targets, const fabric_train_cfg *cfg, float *grad,
                                      float *out_loss, void *stream);
+/* Footprint encoding of the paper-size decoder's shading and training:
+ * one_blob = 1 (the default) is the one-blob encoding of Sec. 4.2; 0 feeds
+ * the unencoded inputs instead (the ablation of Sec. 5 "Encoding of
+ * footprint"): the position fractions (u mod W_x)/W_x, (v mod W_y)/W_y and
+ * tau = clamp((log2 r + 14)/16, 0, 1) in the first channel of their bins,
+ * the other channels 0; the parameter layout is unchanged.  A network is
+ * shaded with the encoding it was trained with.  E_INVAL unless 0 or 1. */
+fabric_status fabric_paper_set_footprint_encoding(fabric_ctx *ctx, int32_t one_blob);
 /* The paper-size masters to host: params [FABRIC_N_PAPER_DECODER_PARAMS],
  * latents [n_mats][FABRIC_PAPER_LATENT].  Synchronises the device.  E_STATE
  * before fabric_paper_prepare. */

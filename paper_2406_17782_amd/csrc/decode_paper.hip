@@ -120,12 +120,23 @@ __global__ void fold_paper_kernel(const float *__restrict__ params,
 }
 
 // One-blob slots of lane group g: 8 circular position bins along its axis,
-// then 4 of the 8 size bins (exp(-d^2/2), d in bins).
-template <int P>
+// then 4 of the 8 size bins (exp(-d^2/2), d in bins).  RAW (the footprint
+// encoding's ablation): the position fraction of the group's axis in its
+// first bin's slot and, in group 0, tau in the first size bin's slot.
+template <int P, bool RAW>
 __device__ inline void paper_slots(float coord, float iper, float r, int g,
                                    float (&s1)[kPSlots1])
 {
     using FM = FeatureMath<P>;
+    if (RAW) {
+#pragma unroll
+        for (int c = 0; c < kPSlots1; c++)
+            s1[c] = 0.0f;
+        s1[0] = coord * iper;
+        if (g == 0)
+            s1[8] = fminf(fmaxf((FM::log2(r) + 14.0f) * (1.0f / 16.0f), 0.0f), 1.0f);
+        return;
+    }
     const float t0 = 8.0f * (coord * iper) - 0.5f;
 #pragma unroll
     for (int b = 0; b < 8; b++) {
@@ -211,7 +222,7 @@ template <int P> struct PaperTile {
 };
 
 // Shading of T tiles per wave iteration (T x 32 pixels).
-template <int P, int WAVES, int T>
+template <int P, int WAVES, int T, bool RAW>
 __global__ __launch_bounds__(64 * WAVES) void decode_paper_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ frags,
@@ -274,7 +285,7 @@ __global__ __launch_bounds__(64 * WAVES) void decode_paper_kernel(
                 // F1: one-blob slots; C operand c_f.
                 float s1[kPSlots1];
                 const float per = grp ? fc[1] : fc[0], iper = grp ? fc[3] : fc[2];
-                paper_slots<P>(wrap_period(cur[t].uv, per, iper), iper, cur[t].r, grp, s1);
+                paper_slots<P, RAW>(wrap_period(cur[t].uv, per, iper), iper, cur[t].r, grp, s1);
                 B1[t][0] = PT::frag_of(s1, 0, false);
                 B1[t][1] = PT::frag_of(s1, 1, false);
 #pragma unroll
@@ -441,7 +452,7 @@ hipError_t launch_paper_prepare(const float *params, const float *latents, int n
     return hipGetLastError();
 }
 
-template <int P>
+template <int P, bool RAW>
 static hipError_t paper_shade(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
                               const float *cfold, const void *image, float *out,
                               unsigned long long *err, hipStream_t stream)
@@ -456,22 +467,24 @@ static hipError_t paper_shade(const fabric_gbuffer &g, const DevFabric *fabrics,
         blocks = cap;
     const size_t lds = (size_t)kPFrags * 64 * sizeof(Frag) +
                        (size_t)n_fabrics * (64 + kFabCopies * kFabConsts) * sizeof(float);
-    hipLaunchKernelGGL((decode_paper_kernel<P, kPaperWaves, kPaperTiles>), dim3(blocks),
+    hipLaunchKernelGGL((decode_paper_kernel<P, kPaperWaves, kPaperTiles, RAW>), dim3(blocks),
                        dim3(64 * kPaperWaves), lds, stream, g, fabrics, n_fabrics, cfold, frags,
                        b5, out, err, n_tiles);
     return hipGetLastError();
 }
 
-hipError_t launch_paper_shade(int prec, const fabric_gbuffer &g, const DevFabric *fabrics,
+hipError_t launch_paper_shade(int prec, bool raw, const fabric_gbuffer &g, const DevFabric *fabrics,
                               int n_fabrics, const float *cfold, const void *image, float *out,
                               unsigned long long *err, hipStream_t stream)
 {
     if (g.n == 0)
         return hipSuccess;
     if (prec == FABRIC_BF16)
-        return paper_shade<FABRIC_BF16>(g, fabrics, n_fabrics, cfold, image, out, err, stream);
+        return raw ? paper_shade<FABRIC_BF16, true>(g, fabrics, n_fabrics, cfold, image, out, err, stream)
+                   : paper_shade<FABRIC_BF16, false>(g, fabrics, n_fabrics, cfold, image, out, err, stream);
     if (prec == FABRIC_FP16)
-        return paper_shade<FABRIC_FP16>(g, fabrics, n_fabrics, cfold, image, out, err, stream);
+        return raw ? paper_shade<FABRIC_FP16, true>(g, fabrics, n_fabrics, cfold, image, out, err, stream)
+                   : paper_shade<FABRIC_FP16, false>(g, fabrics, n_fabrics, cfold, image, out, err, stream);
     return hipErrorInvalidValue;
 }
 

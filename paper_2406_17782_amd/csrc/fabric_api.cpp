@@ -44,6 +44,7 @@ struct fabric_ctx {
     double *paper_m = nullptr;        // their FP64 Adam moments
     double *paper_v = nullptr;
     int64_t paper_step = 0;
+    bool paper_raw = false;           // footprint inputs without the one-blob encoding
     PaperTrainScratch paper_train;
     uint64_t encoded_version = 0;     // weights_version of the last encode
     uint64_t encode_serial = 0;       // bumped on every change of latents or fabric table
@@ -649,7 +650,7 @@ fabric_status fabric_paper_shade(fabric_ctx *ctx, const fabric_gbuffer *g, fabri
     if (g->n == 0)
         return FABRIC_OK;
     DeviceGuard guard(ctx->device);
-    return from_hip(launch_paper_shade(prec, *g, ctx->fabrics, ctx->n_mats, ctx->paper_cfold,
+    return from_hip(launch_paper_shade(prec, ctx->paper_raw, *g, ctx->fabrics, ctx->n_mats, ctx->paper_cfold,
                                        ctx->paper_image, out_rgb, ctx->err, as_stream(stream)));
 }
 
@@ -952,9 +953,18 @@ PaperTrainArgs paper_train_args(fabric_ctx *ctx, const fabric_gbuffer *batch, co
     a.cfg = *cfg;
     a.err = ctx->err;
     a.vis = VisArgs{nullptr, nullptr};
+    a.raw = ctx->paper_raw;
     return a;
 }
 }  // namespace
+
+fabric_status fabric_paper_set_footprint_encoding(fabric_ctx *ctx, int32_t one_blob)
+{
+    if (!ctx || (one_blob != 0 && one_blob != 1))
+        return FABRIC_E_INVAL;
+    ctx->paper_raw = one_blob == 0;
+    return FABRIC_OK;
+}
 
 fabric_status fabric_paper_loss_grad(fabric_ctx *ctx, const fabric_gbuffer *batch,
                                      const float *targets, const fabric_train_cfg *cfg, float *grad,

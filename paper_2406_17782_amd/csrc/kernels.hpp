@@ -86,7 +86,8 @@ hipError_t launch_lerp_latents(const LatentLerp *jobs, int count, float *latents
 size_t paper_image_bytes();
 hipError_t launch_paper_prepare(const float *params, const float *latents, int n_fabrics,
                                 void *image, float *cfold, hipStream_t stream);
-hipError_t launch_paper_shade(int prec, const fabric_gbuffer &g, const DevFabric *fabrics,
+// raw: footprint inputs without the one-blob encoding (the encoding's ablation).
+hipError_t launch_paper_shade(int prec, bool raw, const fabric_gbuffer &g, const DevFabric *fabrics,
                               int n_fabrics, const float *cfold, const void *image, float *out,
                               unsigned long long *err, hipStream_t stream);
 

@@ -64,11 +64,22 @@ __global__ void transpose_kernel(const float *__restrict__ P, float *__restrict_
 }
 
 // One-blob channels of the footprint (FP32, library functions): circular
-// position bins along u and v, then size bins.
-__device__ inline void blob24(const DevFabric &f, float u, float v, float r, float (&x)[24])
+// position bins along u and v, then size bins.  raw (the encoding's
+// ablation): p_u, p_v and tau in channels 0, 8 and 16, zeros elsewhere.
+__device__ inline void blob24(const DevFabric &f, float u, float v, float r, bool raw,
+                              float (&x)[24])
 {
     const float p[2] = {wrap_period(u, f.fwx, f.inv_wx) * f.inv_wx,
                         wrap_period(v, f.fwy, f.inv_wy) * f.inv_wy};
+    if (raw) {
+#pragma unroll
+        for (int k = 0; k < 24; k++)
+            x[k] = 0.0f;
+        x[0] = p[0];
+        x[8] = p[1];
+        x[16] = fminf(fmaxf((log2f(r) + 14.0f) * (1.0f / 16.0f), 0.0f), 1.0f);
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
@@ -136,7 +147,7 @@ __device__ inline void layer_bwd(const float *__restrict__ W, const float (&gin)
 __global__ __launch_bounds__(256) void paper_fwd_bwd_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ P, const float *__restrict__ lat, const float *__restrict__ wt,
-    const float *__restrict__ targets, float *__restrict__ pl, int64_t cap,
+    const float *__restrict__ targets, float *__restrict__ pl, int64_t cap, int raw,
     double *__restrict__ loss_part)
 {
     __shared__ double red[256];
@@ -160,7 +171,7 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_kernel(
                 for (int k = 0; k < kPLat; k++)
                     x1[k] = lat[fid * kPLat + k];
                 float f[24];
-                blob24(fabrics[fid], u, v, r, f);
+                blob24(fabrics[fid], u, v, r, raw != 0, f);
 #pragma unroll
                 for (int k = 0; k < 24; k++) {
                     x1[kPLat + k] = f[k];
@@ -538,7 +549,7 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
     (void)a.err;
     hipLaunchKernelGGL(paper_fwd_bwd_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, g,
                        a.fabrics, a.n_fabrics, P, lat, (const float *)s.wt, targets, s.planes,
-                       s.cap, s.loss_part);
+                       s.cap, a.raw ? 1 : 0, s.loss_part);
     hipLaunchKernelGGL(paper_loss_reduce_kernel, dim3(1), dim3(256), 0, stream,
                        (const double *)s.loss_part, blocks, 1.0 / (double)n, s.loss);
     hipLaunchKernelGGL(paper_wgrad_kernel, dim3(n_chunks, jobs.n_jobs), dim3(256), 0, stream, jobs,

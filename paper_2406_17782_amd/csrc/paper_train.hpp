@@ -42,6 +42,7 @@ struct PaperTrainArgs {
     fabric_train_cfg cfg;
     unsigned long long *err;
     VisArgs vis;
+    bool raw;                     // footprint inputs without the one-blob encoding
 };
 
 // Loss and gradient [params | latents] of one batch into grad_out (device).

@@ -4,7 +4,8 @@ ABI: the FP32 loss and gradient against the oracle's FP64 backward on a
 ragged batch with transmission and faulted samples (norm-wise per tensor
 1e-4, as for the config decoder); two Adam steps against the oracle's;
 training on generated batches lowers the loss and the shading image follows
-the trained masters; call errors."""
+the trained masters; the same without the one-blob footprint encoding
+(the encoding's ablation); call errors."""
 import numpy as np
 import pytest
 
@@ -117,6 +118,35 @@ def test_paper_training_lowers_loss_and_shades(fab, pkg, orc, torch):
     err = rel_norm_err(out.cpu().numpy(), orgb)
     print("trained paper decoder fp16 vs oracle", err)
     assert err < 2e-2
+
+
+def test_unencoded_footprint_shading_and_gradient(fab, pkg, orc, torch):
+    """The footprint encoding's ablation: shading (FP16) and the loss
+    gradient without the one-blob encoding against the oracle's, and the
+    switch back to the encoding."""
+    mats = fi.materials_for(4, 340)
+    g = batch(4, 45, 37, 341)
+    tg = fi.random_targets(g.n, 342)
+    params, z = prepare(fab, pkg, torch, mats, 343)
+    d = pkg.DeviceGBuffer.from_host(g)
+    out = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
+    pkg.fabric_paper_set_footprint_encoding(fab.ctx, False)
+    pkg.fabric_paper_shade(fab.ctx, d, out, "fp16")
+    _, o_raw = orc.paper_decoder_gbuffer(params, z, mats, g, raw=True)
+    _, o_blob = orc.paper_decoder_gbuffer(params, z, mats, g)
+    err_raw = rel_norm_err(out.cpu().numpy(), o_raw)
+    print("unencoded fp16 vs oracle", err_raw, "encodings differ by", rel_norm_err(o_raw, o_blob))
+    assert err_raw < 2e-2 and rel_norm_err(o_raw, o_blob) > 0.1
+    grad = torch.empty(N + 4 * 64, device="cuda")
+    loss = pkg.fabric_paper_loss_grad(fab.ctx, d, torch.from_numpy(tg).cuda(), {}, grad)
+    oloss, ograd, odlat = orc.paper_loss_grad(params, z, mats, g, tg, raw=True)
+    assert loss == pytest.approx(oloss, rel=1e-5)
+    assert max(per_tensor_errors(grad.cpu().numpy(), np.concatenate([ograd, odlat.ravel()]), 4)) < 1e-4
+    pkg.fabric_paper_set_footprint_encoding(fab.ctx, True)
+    pkg.fabric_paper_shade(fab.ctx, d, out, "fp16")
+    assert rel_norm_err(out.cpu().numpy(), o_blob) < 2e-2
+    c = pkg._abi.lib().fabric_paper_set_footprint_encoding(fab.ctx, 2)
+    assert c == 1                                     # E_INVAL
 
 
 def test_paper_training_errors(fab, pkg, torch):
