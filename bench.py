@@ -436,68 +436,85 @@ def paper_decoder_row(args, torch, pkg, fi, mats, g, d):
         fab.close()
 
 
-def paper_training_row(args, torch, pkg, fi, mats, g, d, config_rgb):
-    """The paper-size decoder trained on the 1080p workload's fabrics (one
-    latent of 64 per fabric trained as a parameter; FP32 training kernels;
-    generated batches of 2^16 samples with 256-sample targets, Adam with a
-    cosine-decayed rate); its FP16 and BF16 frames against the oracle's
-    filter on the main section's seeded 1 %, by footprint radius, beside the
-    config-size network and one analytic sample."""
+def train_paper_network(args, torch, pkg, fi, mats, steps, one_blob=True):
+    """A paper-size decoder trained on `mats` (one latent of 64 per fabric
+    trained as a parameter; FP32 training kernels; generated batches of 2^16
+    samples with 256-sample targets; Adam with the main network's
+    cosine-decayed rate).  Returns the open context and the training record."""
     fab = pkg.Fabric(0, seed=4600)
+    fab.encode(mats)
+    params = fi.init_paper_params(5, bias_scale=0.0)
+    z = fi.random_latents(len(mats), 6, scale=0.1, dim=64)
+    pkg.fabric_paper_prepare(fab.ctx, torch.from_numpy(params).cuda(), torch.from_numpy(z).cuda())
+    pkg.fabric_paper_set_footprint_encoding(fab.ctx, one_blob)
+    batch = 1 << 16
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        lr = args.train_lr * 0.5 * (1.0 + math.cos(math.pi * s / max(1, steps)))
+        want = s == 0 or s == steps - 1
+        l = pkg.fabric_paper_train_step(fab.ctx, None, None,
+                                        dict(batch=batch, gt_samples=args.gt_samples,
+                                             seed=3_000_000 + s, lr=lr), want_loss=want)
+        if want:
+            losses.append(l)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    rec = {"train_steps": steps, "train_batch": batch,
+           "train_ms_per_step": train_s / max(1, steps) * 1e3, "train_s": train_s,
+           "loss_first": losses[0] if losses else None, "loss_last": losses[-1] if losses else None,
+           "footprint_encoding": "one-blob" if one_blob else "none"}
+    return fab, rec
+
+
+def subset_reference(args, fi, mats, g):
+    """The main section's seeded 1 % and the oracle's filter on it."""
+    import oracle
+    idx = fi.subset_indices(g.n, args.rmse_frac, 99)
+    sub = g.subset(idx)
+    _, o_rgb, _, _ = oracle.filter_gbuffer(mats, sub, args.gt_samples, 4242, same_sample=True,
+                                           pixel_index=idx)
+    return idx, sub, o_rgb
+
+
+def errors_by_radius(preds, o_rgb, radius):
+    edges = [1e-3, 0.01, 0.05, 0.15, 0.3, 0.5]
+    by_r = {}
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        m = (radius >= lo) & (radius < hi)
+        by_r[f"[{lo},{hi})"] = dict(
+            pixels=int(m.sum()),
+            **{k: float(np.sqrt(np.mean((v[:, m] - o_rgb[:, m]) ** 2))) for k, v in preds.items()})
+    return by_r
+
+
+def paper_training_row(args, torch, pkg, fi, mats, g, d, config_rgb):
+    """The paper-size decoder trained on the 1080p workload's fabrics; its
+    FP16 and BF16 frames against the oracle's filter on the main section's
+    seeded 1 %, by footprint radius, beside the config-size network and one
+    analytic sample."""
+    fab, res = train_paper_network(args, torch, pkg, fi, mats, args.paper_train_steps)
     try:
-        fab.encode(mats)
-        params = fi.init_paper_params(5, bias_scale=0.0)
-        z = fi.random_latents(len(mats), 6, scale=0.1, dim=64)
-        pkg.fabric_paper_prepare(fab.ctx, torch.from_numpy(params).cuda(), torch.from_numpy(z).cuda())
-        steps, batch = args.paper_train_steps, 1 << 16
-        losses = []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for s in range(steps):
-            lr = args.train_lr * 0.5 * (1.0 + math.cos(math.pi * s / max(1, steps)))
-            want = s == 0 or s == steps - 1
-            l = pkg.fabric_paper_train_step(fab.ctx, None, None,
-                                            dict(batch=batch, gt_samples=args.gt_samples,
-                                                 seed=3_000_000 + s, lr=lr), want_loss=want)
-            if want:
-                losses.append(l)
-        torch.cuda.synchronize()
-        train_s = time.perf_counter() - t0
+        res["latents"] = "one per fabric, trained as parameters"
         out = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
         fp16 = lambda: pkg.fabric_paper_shade(fab.ctx, d, out, "fp16")
         for _ in range(100):
             fp16()
-        ms16 = time_launches(torch, fp16, 100)
+        res["fp16_ms_per_frame"] = time_launches(torch, fp16, 100)
         rgb16 = out.cpu().numpy()
         pkg.fabric_paper_shade(fab.ctx, d, out, "bf16")
         rgb_bf = out.cpu().numpy()
-        res = {"train_steps": steps, "train_batch": batch,
-               "train_ms_per_step": train_s / max(1, steps) * 1e3,
-               "train_s": train_s, "loss_first": losses[0] if losses else None,
-               "loss_last": losses[-1] if losses else None,
-               "latents": "one per fabric, trained as parameters",
-               "fp16_ms_per_frame": ms16}
-        log(f"paper-size training: {steps} steps in {train_s:.1f}s, loss "
+        log(f"paper-size training: {res['train_steps']} steps in {res['train_s']:.1f}s, loss "
             f"{res['loss_first']} -> {res['loss_last']}")
-        if not args.no_rmse and steps > 0:
-            import oracle
-            idx = fi.subset_indices(g.n, args.rmse_frac, 99)
-            sub = g.subset(idx)
-            _, o_rgb, _, _ = oracle.filter_gbuffer(mats, sub, args.gt_samples, 4242,
-                                                   same_sample=True, pixel_index=idx)
+        if not args.no_rmse and res["train_steps"] > 0:
+            idx, sub, o_rgb = subset_reference(args, fi, mats, g)
             one = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
             pkg.fabric_gt_filtered(fab.ctx, d, 1, 777, one, None)
             preds = {"paper_fp16": rgb16[:, idx], "paper_bf16": rgb_bf[:, idx],
                      "config_bf16": config_rgb[:, idx], "analytic_1spp": one.cpu().numpy()[:, idx]}
             res["rmse_vs_fp64_oracle"] = {k: rmse_stats(v, o_rgb) for k, v in preds.items()}
-            edges = [1e-3, 0.01, 0.05, 0.15, 0.3, 0.5]
-            by_r = {}
-            for lo, hi in zip(edges[:-1], edges[1:]):
-                m = (sub.radius >= lo) & (sub.radius < hi)
-                by_r[f"[{lo},{hi})"] = dict(
-                    pixels=int(m.sum()),
-                    **{k: float(np.sqrt(np.mean((v[:, m] - o_rgb[:, m]) ** 2))) for k, v in preds.items()})
-            res["rmse_by_footprint_radius"] = by_r
+            res["rmse_by_footprint_radius"] = errors_by_radius(preds, o_rgb, sub.radius)
             e = res["rmse_vs_fp64_oracle"]
             res["paper_fp16_beats_1spp"] = e["paper_fp16"]["rmse"] < e["analytic_1spp"]["rmse"]
             log(f"paper-size network rmse fp16 {e['paper_fp16']['rmse']:.4g}, bf16 "
@@ -506,6 +523,34 @@ def paper_training_row(args, torch, pkg, fi, mats, g, d, config_rgb):
         return res
     finally:
         fab.close()
+
+
+def encoding_ablation_row(args, torch, pkg, fi, mats, g, d):
+    """Sec. 5 "Encoding of footprint": two paper-size networks trained alike,
+    with and without the one-blob footprint encoding; their FP16 frames
+    against the oracle's filter on the main section's seeded 1 %, overall
+    and by footprint radius."""
+    steps = args.ablation_train_steps
+    res = {"train_steps": steps, "train_batch": 1 << 16}
+    ref = None if args.no_rmse or steps == 0 else subset_reference(args, fi, mats, g)
+    preds = {}
+    for name, one_blob in (("one_blob", True), ("unencoded", False)):
+        fab, rec = train_paper_network(args, torch, pkg, fi, mats, steps, one_blob)
+        try:
+            out = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
+            pkg.fabric_paper_shade(fab.ctx, d, out, "fp16")
+            res[name] = {"loss_last": rec["loss_last"], "train_s": rec["train_s"]}
+            if ref is not None:
+                preds[name] = out.cpu().numpy()[:, ref[0]]
+                res[name]["rmse"] = rmse_stats(preds[name], ref[2])
+        finally:
+            fab.close()
+    if ref is not None:
+        res["rmse_by_footprint_radius"] = errors_by_radius(preds, ref[2], ref[1].radius)
+        res["encoding_lowers_rmse"] = res["one_blob"]["rmse"]["rmse"] < res["unencoded"]["rmse"]["rmse"]
+        log(f"footprint encoding ablation: one-blob {res['one_blob']['rmse']['rmse']:.4g}, "
+            f"unencoded {res['unencoded']['rmse']['rmse']:.4g}")
+    return res
 
 
 def interp_row(args, torch, pkg, fi, g, d):
@@ -626,6 +671,8 @@ def main():
                     help="training steps of the latent interpolation row's network")
     ap.add_argument("--paper-train-steps", type=int, default=48000,
                     help="training steps (2^16 samples each) of the paper-size decoder's row")
+    ap.add_argument("--ablation-train-steps", type=int, default=12000,
+                    help="training steps of each network of the footprint-encoding ablation")
     ap.add_argument("--analytic-steps", type=int, default=10)
     ap.add_argument("--rmse-frac", type=float, default=0.01)
     ap.add_argument("--cpu-budget", type=float, default=8.0)
@@ -775,6 +822,7 @@ def main():
         rows["transmission"] = btdf_row(args, torch, pkg, fi)
         rows["paper_decoder"] = paper_decoder_row(args, torch, pkg, fi, mats, g, d)
         rows["paper_training"] = paper_training_row(args, torch, pkg, fi, mats, g, d, rgb["bf16"])
+        rows["footprint_encoding_ablation"] = encoding_ablation_row(args, torch, pkg, fi, mats, g, d)
 
     # ---- error against the FP64 oracle on a seeded pixel subset ----
     args.neural_ms = ms
