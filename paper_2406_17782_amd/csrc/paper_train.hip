@@ -8,15 +8,17 @@
 //                          layers backward (transposed weights), storing
 //                          every layer's gradient at its pre-activation
 //   paper_wgrad_kernel     split-K weight gradients: per (job, chunk of
-//                          1,024 samples) block, dL/dW and dL/db of one
-//                          layer as sums of outer products over the chunk,
-//                          staged through LDS 32 samples at a time; one job
-//                          sums F1's input gradient per fabric instead
+//                          256 samples) block, dL/dW and dL/db of one layer
+//                          as sums of outer products over the chunk, staged
+//                          through LDS 32 samples at a time, 4 x 4 entries
+//                          per thread; one job sums F1's input gradient per
+//                          fabric instead
 //   paper_wgrad_reduce_kernel  fixed-order sum over the chunks
 //   paper_latent_grads_kernel  F1's latent columns and the latents'
 //                          gradients from the per-fabric sums
 // Every reduction has a fixed order: results do not depend on scheduling.
 #include <cmath>
+#include <type_traits>
 
 #include "kernels.hpp"
 #include "model.hpp"
@@ -48,19 +50,32 @@ constexpr int kPlDG = kPlDRR + 64;
 constexpr int kPlanes = kPlDG + 64;
 static_assert(kPlanes == 801, "plane count");
 
-// Transposed 64 x 64 blocks: WT[l][i][o] = W_l[o][i].
-enum { kTF2 = 0, kTA1, kTA2, kTA3, kTA4, kTLayers };
+// Transposed weights of every layer for the forward pass, WT[i][o] =
+// W[o][i] (the 16 outputs of a wave are then 16 consecutive floats).
+enum { kTF1 = 0, kTF2, kTA1, kTA2, kTA3, kTA4, kTA5, kTLayers };
+__host__ __device__ constexpr int t_in(int l) { return l == kTF1 ? kPX1 : l == kTA1 ? kPXA1 : 64; }
+__host__ __device__ constexpr int t_out(int l) { return l == kTA5 ? 4 : 64; }
+__host__ __device__ constexpr int t_first(int l)
+{
+    return l == 0 ? 0 : t_first(l - 1) + t_in(l - 1) * t_out(l - 1);
+}
+constexpr int kTFloats = t_first(kTLayers);          // 26,688
+__host__ __device__ constexpr int w_off(int l)
+{
+    return l == kTF1 ? kPOffWF1 : l == kTF2 ? kPOffWF2 : l == kTA1 ? kPOffWA1 : l == kTA2 ? kPOffWA2
+           : l == kTA3 ? kPOffWA3 : l == kTA4 ? kPOffWA4 : kPOffWA5;
+}
 
 __global__ void transpose_kernel(const float *__restrict__ P, float *__restrict__ wt)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= kTLayers * 64 * 64)
+    if (idx >= kTFloats)
         return;
-    const int l = idx / 4096, i = (idx / 64) % 64, o = idx % 64;
-    const int off = l == kTF2 ? kPOffWF2 : l == kTA1 ? kPOffWA1 : l == kTA2 ? kPOffWA2
-                    : l == kTA3 ? kPOffWA3 : kPOffWA4;
-    const int row = l == kTA1 ? kPXA1 : 64;
-    wt[idx] = P[off + o * row + i];
+    int l = 0;
+    while (l + 1 < kTLayers && idx >= t_first(l + 1))
+        l++;
+    const int k = idx - t_first(l), i = k / t_out(l), o = k % t_out(l);
+    wt[idx] = P[w_off(l) + o * t_in(l) + i];
 }
 
 // One-blob channels of the footprint (FP32, library functions): circular
@@ -96,51 +111,46 @@ __device__ inline void blob24(const DevFabric &f, float u, float v, float r, boo
     }
 }
 
-template <int N>
-__device__ inline void load_vec(const float *__restrict__ pl, int plane, int64_t cap, int64_t s,
-                                float (&x)[N])
-{
-#pragma unroll
-    for (int k = 0; k < N; k++)
-        x[k] = pl[(int64_t)(plane + k) * cap + s];
-}
+// The forward and backward pass of 64 samples per block: lane l of every
+// wave owns sample 64 b + l, and wave w owns neurons 16 w .. 16 w + 15 of each
+// 64-wide layer (weights read as wave-uniform scalars).  A layer's input
+// vector of each sample is shared through LDS; every value a wave needs from
+// its own earlier work (activations for the slopes, the residual input) is
+// its own.  Activations and gradients also go to the per-sample planes.
+constexpr int kFbSamples = 64;
+constexpr int kFbStride = kPX1 + 1;                  // LDS row of one sample (odd: no conflicts)
 
-// out = lrelu(W x + b [+ skip]) for a 64-output layer whose rows hold NIN
-// inputs; outputs go to the sample's planes.
-template <int NIN>
-__device__ inline void layer_fwd(const float *__restrict__ W, const float *__restrict__ b,
-                                 const float (&x)[NIN], float *__restrict__ pl, int skip_plane,
-                                 int out_plane, int64_t cap, int64_t s)
+// acc[k] = b[o] + sum_i WT[i][o] x[i] for o = o0 + k (WT: [NIN][NOUT]).
+template <int NIN, int NOUT>
+__device__ inline void fwd16(const float *__restrict__ WT, const float *__restrict__ b,
+                             const float *xrow, int o0, float (&acc)[16])
 {
-#pragma unroll 2
-    for (int o = 0; o < 64; o++) {
-        float acc = b[o];
 #pragma unroll
-        for (int i = 0; i < NIN; i++)
-            acc = fmaf(W[o * NIN + i], x[i], acc);
-        if (skip_plane >= 0)
-            acc += pl[(int64_t)(skip_plane + o) * cap + s];
-        pl[(int64_t)(out_plane + o) * cap + s] = lrelu(acc);
+    for (int k = 0; k < 16; k++)
+        acc[k] = b[o0 + k];
+#pragma unroll 4
+    for (int i = 0; i < NIN; i++) {
+        const float xi = xrow[i];
+#pragma unroll
+        for (int k = 0; k < 16; k++)
+            acc[k] = fmaf(WT[i * NOUT + o0 + k], xi, acc[k]);
     }
 }
 
-// d_i = slope(act_i) (sum_o W[o][i] g_o [+ extra_i]) for i < 64, with the
-// weight of (o, i) at W[o * SO + i * SI]; stored to the gradient plane.
-template <int NG, int SO, int SI>
-__device__ inline void layer_bwd(const float *__restrict__ W, const float (&gin)[NG],
-                                 float *__restrict__ pl, int act_plane, int extra_plane,
-                                 int out_plane, int64_t cap, int64_t s)
+// acc[k] = sum_o W[o][i] g[o] for i = i0 + k (W row-major [NG][ROW]).
+template <int NG, int ROW>
+__device__ inline void bwd16(const float *__restrict__ W, const float *grow, int i0,
+                             float (&acc)[16])
 {
-#pragma unroll 2
-    for (int i = 0; i < 64; i++) {
-        float acc = 0.0f;
 #pragma unroll
-        for (int o = 0; o < NG; o++)
-            acc = fmaf(W[o * SO + i * SI], gin[o], acc);
-        if (extra_plane >= 0)
-            acc += pl[(int64_t)(extra_plane + i) * cap + s];
-        const float a = pl[(int64_t)(act_plane + i) * cap + s];
-        pl[(int64_t)(out_plane + i) * cap + s] = a > 0.0f ? acc : kLeak * acc;
+    for (int k = 0; k < 16; k++)
+        acc[k] = 0.0f;
+#pragma unroll 4
+    for (int o = 0; o < NG; o++) {
+        const float go = grow[o];
+#pragma unroll
+        for (int k = 0; k < 16; k++)
+            acc[k] = fmaf(W[o * ROW + i0 + k], go, acc[k]);
     }
 }
 
@@ -150,139 +160,163 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_kernel(
     const float *__restrict__ targets, float *__restrict__ pl, int64_t cap, int raw,
     double *__restrict__ loss_part)
 {
-    __shared__ double red[256];
+    __shared__ float bufA[kFbSamples * kFbStride];
+    __shared__ float bufB[kFbSamples * kFbStride];
+    __shared__ double red[kFbSamples];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int o0 = 16 * w;
     const int64_t n = g.n;
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = (int64_t)blockIdx.x * kFbSamples + lane;
+    const bool live = s < n;
+    int fid = 0;
+    float u = 0.0f, v = 0.0f, r = 1.0f;
+    float3 wi = make_float3(0.0f, 0.0f, 1.0f), wo = make_float3(0.0f, 0.0f, 1.0f);
+    if (live) {
+        fid = g.fabric_id[s];
+        u = g.u[s]; v = g.v[s]; r = g.radius[s];
+        wi = make_float3(g.wi_x[s], g.wi_y[s], g.wi_z[s]);
+        wo = make_float3(g.wo_x[s], g.wo_y[s], g.wo_z[s]);
+    }
+    // A faulted sample contributes nothing: it runs on harmless inputs and
+    // stores zeros to every plane.
+    const bool fault = !live || pixel_fault(fid, n_fabrics, u, v, r, wi, wo);
+    if (fault) {
+        fid = 0; u = 0.0f; v = 0.0f; r = 1.0f;
+        wi = make_float3(0.0f, 0.0f, 1.0f);
+        wo = make_float3(0.0f, 0.0f, 1.0f);
+    }
+    auto store = [&](int plane, float val) {
+        if (live)
+            pl[(int64_t)plane * cap + s] = fault ? 0.0f : val;
+    };
+    // This thread's own earlier stores (absent past the end of the batch).
+    auto own = [&](int plane) { return live ? pl[(int64_t)plane * cap + s] : 0.0f; };
+    float *rowA = bufA + lane * kFbStride, *rowB = bufB + lane * kFbStride;
+    const float ang[5] = {wi.x, wi.y, wi.z, wo.x, wo.y};
+
+    // ---- F1 input [z, one-blob] (each wave fills a quarter of the row) ----
+#pragma unroll
+    for (int k = 0; k < 16; k++)
+        rowA[o0 + k] = lat[fid * kPLat + o0 + k];
+    if (w == 0) {
+        float f[24];
+        blob24(fabrics[fid], u, v, r, raw != 0, f);
+#pragma unroll
+        for (int k = 0; k < 24; k++) {
+            rowA[kPLat + k] = f[k];
+            store(kPlFeat + k, f[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 5; k++)
+            store(kPlAng + k, ang[k]);
+    }
+    __syncthreads();
+    float acc[16], xres[16];
+    // A forward layer: outputs of this wave's neurons, activated (+ skip),
+    // to the other buffer and the plane.
+    auto layer = [&](auto nin_tag, int tl, const float *bias, const float *in, float *out, int plane,
+                     bool skip) {
+        constexpr int NIN = decltype(nin_tag)::value;
+        fwd16<NIN, 64>(wt + t_first(tl), bias, in, o0, acc);
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            const float a = lrelu(skip ? acc[k] + xres[k] : acc[k]);
+            out[o0 + k] = a;
+            store(plane + o0 + k, a);
+            acc[k] = a;
+        }
+        __syncthreads();
+    };
+    using I88 = std::integral_constant<int, kPX1>;
+    using I69 = std::integral_constant<int, kPXA1>;
+    using I64 = std::integral_constant<int, 64>;
+    layer(I88{}, kTF1, P + kPOffBF1, rowA, rowB, kPlT, false);
+    layer(I64{}, kTF2, P + kPOffBF2, rowB, rowA, kPlSP, false);
+    if (w == 0) {
+#pragma unroll
+        for (int k = 0; k < 5; k++)
+            rowA[64 + k] = ang[k];
+    }
+    __syncthreads();
+    layer(I69{}, kTA1, P + kPOffBA1, rowA, rowB, kPlX, false);
+#pragma unroll
+    for (int k = 0; k < 16; k++)
+        xres[k] = acc[k];                               // the residual block's input
+    layer(I64{}, kTA2, P + kPOffBA2, rowB, rowA, kPlH, false);
+    layer(I64{}, kTA3, P + kPOffBA3, rowA, rowB, kPlRR, true);
+    layer(I64{}, kTA4, P + kPOffBA4, rowB, rowA, kPlG, false);
+    // ---- A5: wave w computes output w; the four meet in LDS ----
+    {
+        float y = P[kPOffBA5 + w];
+        const float *WT5 = wt + t_first(kTA5);
+#pragma unroll 8
+        for (int i = 0; i < 64; i++)
+            y = fmaf(WT5[i * 4 + w], rowA[i], y);
+        rowB[w] = y;
+    }
+    __syncthreads();
+    // ---- loss terms of Eq. (9)-(11) and dL/dy (every wave, for its own use) ----
+    float dy[4];
     double loss = 0.0;
-    if (s < n) {
-        const int fid = g.fabric_id[s];
-        const float u = g.u[s], v = g.v[s], r = g.radius[s];
-        const float3 wi = make_float3(g.wi_x[s], g.wi_y[s], g.wi_z[s]);
-        const float3 wo = make_float3(g.wo_x[s], g.wo_y[s], g.wo_z[s]);
-        if (pixel_fault(fid, n_fabrics, u, v, r, wi, wo)) {
-            // Contributes nothing: zero activations and gradients alike.
-            for (int k = 0; k < kPlanes; k++)
-                pl[(int64_t)k * cap + s] = 0.0f;
-        } else {
-            // ---- forward ----
-            {
-                float x1[kPX1];
+    {
+        const float inv_n = 1.0f / (float)n;
+        // g(x) = ln(k x + 1): k = 100 for reflection, 1000 for transmission.
+        const float k = wi.z < 0.0f ? 10.0f * kSpec : kSpec;
 #pragma unroll
-                for (int k = 0; k < kPLat; k++)
-                    x1[k] = lat[fid * kPLat + k];
-                float f[24];
-                blob24(fabrics[fid], u, v, r, raw != 0, f);
+        for (int c = 0; c < 4; c++) {
+            const float t = fault ? 0.0f : targets[c * n + s];
+            const float target = c < 2 ? t : log1pf(k * t);
+            const float lam = c < 2 ? 0.1f : 0.4f;        // lambda_C, lambda_S
+            const float d = rowB[c] - target;
+            loss += fault ? 0.0 : (double)(lam * d * d);
+            dy[c] = fault ? 0.0f : 2.0f * lam * d * inv_n;
+        }
+        if (w == 0) {
 #pragma unroll
-                for (int k = 0; k < 24; k++) {
-                    x1[kPLat + k] = f[k];
-                    pl[(int64_t)(kPlFeat + k) * cap + s] = f[k];
-                }
-                layer_fwd<kPX1>(P + kPOffWF1, P + kPOffBF1, x1, pl, -1, kPlT, cap, s);
-            }
-            {
-                float x[64];
-                load_vec(pl, kPlT, cap, s, x);
-                layer_fwd<64>(P + kPOffWF2, P + kPOffBF2, x, pl, -1, kPlSP, cap, s);
-            }
-            {
-                float x[kPXA1];
-                float sp[64];
-                load_vec(pl, kPlSP, cap, s, sp);
-#pragma unroll
-                for (int k = 0; k < 64; k++)
-                    x[k] = sp[k];
-                const float ang[5] = {wi.x, wi.y, wi.z, wo.x, wo.y};
-#pragma unroll
-                for (int k = 0; k < 5; k++) {
-                    x[64 + k] = ang[k];
-                    pl[(int64_t)(kPlAng + k) * cap + s] = ang[k];
-                }
-                layer_fwd<kPXA1>(P + kPOffWA1, P + kPOffBA1, x, pl, -1, kPlX, cap, s);
-            }
-            {
-                float x[64];
-                load_vec(pl, kPlX, cap, s, x);
-                layer_fwd<64>(P + kPOffWA2, P + kPOffBA2, x, pl, -1, kPlH, cap, s);
-            }
-            {
-                float x[64];
-                load_vec(pl, kPlH, cap, s, x);
-                layer_fwd<64>(P + kPOffWA3, P + kPOffBA3, x, pl, kPlX, kPlRR, cap, s);
-            }
-            {
-                float x[64];
-                load_vec(pl, kPlRR, cap, s, x);
-                layer_fwd<64>(P + kPOffWA4, P + kPOffBA4, x, pl, -1, kPlG, cap, s);
-            }
-            float y[4];
-            {
-                float x[64];
-                load_vec(pl, kPlG, cap, s, x);
-#pragma unroll
-                for (int o = 0; o < 4; o++) {
-                    float acc = P[kPOffBA5 + o];
-#pragma unroll
-                    for (int i = 0; i < 64; i++)
-                        acc = fmaf(P[kPOffWA5 + o * 64 + i], x[i], acc);
-                    y[o] = acc;
-                }
-            }
-            // ---- loss terms of Eq. (9)-(11) and dL/dy ----
-            float dy[4];
-            {
-                const float inv_n = 1.0f / (float)n;
-                // g(x) = ln(k x + 1): k = 100 for reflection, 1000 for transmission.
-                const float k = wi.z < 0.0f ? 10.0f * kSpec : kSpec;
-#pragma unroll
-                for (int c = 0; c < 4; c++) {
-                    const float t = targets[c * n + s];
-                    const float target = c < 2 ? t : log1pf(k * t);
-                    const float lam = c < 2 ? 0.1f : 0.4f;        // lambda_C, lambda_S
-                    const float d = y[c] - target;
-                    loss += (double)(lam * d * d);
-                    dy[c] = 2.0f * lam * d * inv_n;
-                    pl[(int64_t)(kPlDY + c) * cap + s] = dy[c];
-                }
-            }
-            // ---- backward ----
-            layer_bwd<4, 64, 1>(P + kPOffWA5, dy, pl, kPlG, -1, kPlDG, cap, s);
-            {
-                float gv[64];
-                load_vec(pl, kPlDG, cap, s, gv);
-                layer_bwd<64, 1, 64>(wt + kTA4 * 4096, gv, pl, kPlRR, -1, kPlDRR, cap, s);
-            }
-            {
-                float gv[64];
-                load_vec(pl, kPlDRR, cap, s, gv);
-                layer_bwd<64, 1, 64>(wt + kTA3 * 4096, gv, pl, kPlH, -1, kPlDH, cap, s);
-            }
-            {
-                // The skip carries A3's pre-activation gradient to A1's output.
-                float gv[64];
-                load_vec(pl, kPlDH, cap, s, gv);
-                layer_bwd<64, 1, 64>(wt + kTA2 * 4096, gv, pl, kPlX, kPlDRR, kPlDX, cap, s);
-            }
-            {
-                float gv[64];
-                load_vec(pl, kPlDX, cap, s, gv);
-                layer_bwd<64, 1, 64>(wt + kTA1 * 4096, gv, pl, kPlSP, -1, kPlDSP, cap, s);
-            }
-            {
-                float gv[64];
-                load_vec(pl, kPlDSP, cap, s, gv);
-                layer_bwd<64, 1, 64>(wt + kTF2 * 4096, gv, pl, kPlT, -1, kPlDT, cap, s);
-            }
+            for (int c = 0; c < 4; c++)
+                store(kPlDY + c, dy[c]);
         }
     }
-    red[threadIdx.x] = loss;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();                                    // rowB's outputs read by all
+    // ---- backward: this wave's 16 input gradients of each layer ----
+    auto back = [&](auto ng_tag, auto row_tag, int woff, const float *gin, float *gout,
+                    int act_plane, int out_plane, const float *extra) {
+        constexpr int NG = decltype(ng_tag)::value;
+        constexpr int ROW = decltype(row_tag)::value;
+        bwd16<NG, ROW>(P + woff, gin, o0, acc);
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            const float t = extra ? acc[k] + extra[k] : acc[k];
+            const float d = own(act_plane + o0 + k) > 0.0f ? t : kLeak * t;
+            acc[k] = fault ? 0.0f : d;
+            gout[o0 + k] = acc[k];
+            store(out_plane + o0 + k, acc[k]);
+        }
         __syncthreads();
+    };
+    using I4 = std::integral_constant<int, 4>;
+    back(I4{}, I64{}, kPOffWA5, dy, rowA, kPlG, kPlDG, nullptr);
+    back(I64{}, I64{}, kPOffWA4, rowA, rowB, kPlRR, kPlDRR, nullptr);
+    float drr[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++)
+        drr[k] = acc[k];                                // the skip's gradient to A1's output
+    back(I64{}, I64{}, kPOffWA3, rowB, rowA, kPlH, kPlDH, nullptr);
+    back(I64{}, I64{}, kPOffWA2, rowA, rowB, kPlX, kPlDX, drr);
+    back(I64{}, I69{}, kPOffWA1, rowB, rowA, kPlSP, kPlDSP, nullptr);
+    back(I64{}, I64{}, kPOffWF2, rowA, rowB, kPlT, kPlDT, nullptr);
+
+    // Fixed-order sum of the block's loss terms (wave 0 holds them).
+    if (w == 0)
+        red[lane] = loss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kFbSamples; k++)
+            t += red[k];
+        loss_part[blockIdx.x] = t;
     }
-    if (threadIdx.x == 0)
-        loss_part[blockIdx.x] = red[0];
 }
 
 __global__ __launch_bounds__(256) void paper_loss_reduce_kernel(const double *__restrict__ part,
@@ -322,41 +356,52 @@ struct PWJobs {
 };
 
 constexpr int kPwSub = 32;          // samples per LDS sub-tile
-constexpr int kPwChunk = 1024;      // samples per block
+constexpr int kPwChunk = 256;       // samples per block
 constexpr int kPwMaxIn = 70;        // columns (inputs + bias) of any job
-constexpr int kPwMaxE = 18;         // entries per thread: 64 x 70 <= 256 x 18
+// LDS rows (one per sample of the sub-tile) hold 4-wide groups of rows and
+// of columns, padded by 4 floats against bank conflicts of the fills.
+constexpr int kPwDStride = 64 + 4;
+constexpr int kPwIStride = 72 + 4;
 
 __host__ __device__ inline int pw_cols(const PWJob &jb)
 {
     return jb.nA + jb.nB + (jb.b_off >= 0 ? 1 : 0);
 }
 
+// Each thread accumulates up to two 4 x 4 blocks of (row, column) entries:
+// per sample, two 16-byte LDS reads feed 16 FMAs.
 __global__ __launch_bounds__(256) void paper_wgrad_kernel(PWJobs jobs, const float *__restrict__ pl,
                                                           int64_t cap, const uint16_t *__restrict__ fid,
                                                           int64_t n, float *__restrict__ partial)
 {
-    __shared__ float dt[64][kPwSub + 1];
-    __shared__ float it[kPwMaxIn][kPwSub + 1];
+    __shared__ __align__(16) float dt[kPwSub * kPwDStride];
+    __shared__ __align__(16) float it[kPwSub * kPwIStride];
     const PWJob jb = jobs.j[blockIdx.y];
     const int cols = pw_cols(jb);
-    const int E = jb.n_out * cols;
-    float acc[kPwMaxE];
+    const int rg = (jb.n_out + 3) / 4, cg = (cols + 3) / 4;
+    const int tiles = rg * cg;                  // <= 16 x 18
+    float acc[2][4][4];
 #pragma unroll
-    for (int m = 0; m < kPwMaxE; m++)
-        acc[m] = 0.0f;
+    for (int m = 0; m < 2; m++)
+#pragma unroll
+        for (int x = 0; x < 4; x++)
+#pragma unroll
+            for (int y = 0; y < 4; y++)
+                acc[m][x][y] = 0.0f;
     const int64_t s0 = (int64_t)blockIdx.x * kPwChunk;
     const int64_t s1 = s0 + kPwChunk < n ? s0 + kPwChunk : n;
     for (int64_t sb = s0; sb < s1; sb += kPwSub) {
-        for (int k = threadIdx.x; k < jb.n_out * kPwSub; k += blockDim.x) {
+        // Fills: consecutive threads take consecutive samples of one plane.
+        for (int k = threadIdx.x; k < 4 * rg * kPwSub; k += blockDim.x) {
             const int i = k / kPwSub, q = k % kPwSub;
             const int64_t s = sb + q;
-            dt[i][q] = s < s1 ? pl[(int64_t)(jb.delta + i) * cap + s] : 0.0f;
+            dt[q * kPwDStride + i] = (s < s1 && i < jb.n_out) ? pl[(int64_t)(jb.delta + i) * cap + s] : 0.0f;
         }
-        for (int k = threadIdx.x; k < cols * kPwSub; k += blockDim.x) {
+        for (int k = threadIdx.x; k < 4 * cg * kPwSub; k += blockDim.x) {
             const int j = k / kPwSub, q = k % kPwSub;
             const int64_t s = sb + q;
             float val = 0.0f;
-            if (s < s1) {
+            if (s < s1 && j < cols) {
                 if (jb.onehot)
                     val = (int)fid[s] == j ? 1.0f : 0.0f;
                 else if (j < jb.nA)
@@ -366,29 +411,45 @@ __global__ __launch_bounds__(256) void paper_wgrad_kernel(PWJobs jobs, const flo
                 else
                     val = 1.0f;
             }
-            it[j][q] = val;
+            it[q * kPwIStride + j] = val;
         }
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < kPwMaxE; m++) {
-            const int e = threadIdx.x + 256 * m;
-            if (e < E) {
-                const int i = e / cols, j = e % cols;
-                float a = acc[m];
-#pragma unroll 8
-                for (int q = 0; q < kPwSub; q++)
-                    a = fmaf(dt[i][q], it[j][q], a);
-                acc[m] = a;
+        for (int m = 0; m < 2; m++) {
+            const int t = threadIdx.x + 256 * m;
+            if (t < tiles) {
+                const int r = t / cg, c = t % cg;
+#pragma unroll 4
+                for (int q = 0; q < kPwSub; q++) {
+                    const float4 a = *(const float4 *)&dt[q * kPwDStride + 4 * r];
+                    const float4 b = *(const float4 *)&it[q * kPwIStride + 4 * c];
+                    const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+                    for (int x = 0; x < 4; x++)
+#pragma unroll
+                        for (int y = 0; y < 4; y++)
+                            acc[m][x][y] = fmaf(av[x], bv[y], acc[m][x][y]);
+                }
             }
         }
         __syncthreads();
     }
+    const int E = jb.n_out * cols;
     float *dst = partial + jobs.poff[blockIdx.y] + (int64_t)blockIdx.x * E;
 #pragma unroll
-    for (int m = 0; m < kPwMaxE; m++) {
-        const int e = threadIdx.x + 256 * m;
-        if (e < E)
-            dst[e] = acc[m];
+    for (int m = 0; m < 2; m++) {
+        const int t = threadIdx.x + 256 * m;
+        if (t < tiles) {
+            const int r = t / cg, c = t % cg;
+#pragma unroll
+            for (int x = 0; x < 4; x++)
+#pragma unroll
+                for (int y = 0; y < 4; y++) {
+                    const int i = 4 * r + x, j = 4 * c + y;
+                    if (i < jb.n_out && j < cols)
+                        dst[i * cols + j] = acc[m][x][y];
+                }
+        }
     }
 }
 
@@ -404,9 +465,21 @@ __global__ __launch_bounds__(256) void paper_wgrad_reduce_kernel(PWJobs jobs, in
     if (e >= E)
         return;
     const float *src = partial + jobs.poff[blockIdx.y] + e;
+    // Eight interleaved partial sums (independent loads in flight), combined
+    // in a fixed order.
+    double part[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int c = 0;
+    for (; c + 8 <= n_chunks; c += 8) {
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            part[k] += (double)src[(int64_t)(c + k) * E];
+    }
+    for (; c < n_chunks; c++)
+        part[0] += (double)src[(int64_t)c * E];
     double acc = 0.0;
-    for (int c = 0; c < n_chunks; c++)
-        acc += (double)src[(int64_t)c * E];
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+        acc += part[k];
     const int i = e / cols, j = e % cols;
     if (jb.onehot)
         dsum[j * 64 + i] = (float)acc;
@@ -479,7 +552,7 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
     if (!s.grad) {
         if ((e = hipMalloc((void **)&s.grad, (size_t)(kPNDec + kPaperTrainMaxFabrics * kPLat) * sizeof(float))) != hipSuccess) return e;
         if ((e = hipMalloc((void **)&s.dsum, (size_t)kPaperTrainMaxFabrics * 64 * sizeof(float))) != hipSuccess) return e;
-        if ((e = hipMalloc((void **)&s.wt, (size_t)kTLayers * 4096 * sizeof(float))) != hipSuccess) return e;
+        if ((e = hipMalloc((void **)&s.wt, (size_t)kTFloats * sizeof(float))) != hipSuccess) return e;
         if ((e = hipMalloc((void **)&s.loss, sizeof(double))) != hipSuccess) return e;
     }
     fabric_gbuffer g;
@@ -528,7 +601,7 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
             return e;
         targets = s.targets;
     }
-    const int64_t blocks = (n + 255) / 256;
+    const int64_t blocks = (n + kFbSamples - 1) / kFbSamples;
     if (s.cap < n) {
         if ((e = regrow(&s.planes, (size_t)n * kPlanes)) != hipSuccess) return e;
         if ((e = regrow(&s.loss_part, (size_t)blocks)) != hipSuccess) return e;
@@ -543,7 +616,7 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
         if ((e = regrow(&s.partial, need)) != hipSuccess) return e;
         s.partial_floats = need;
     }
-    hipLaunchKernelGGL(transpose_kernel, dim3((kTLayers * 4096 + 255) / 256), dim3(256), 0, stream,
+    hipLaunchKernelGGL(transpose_kernel, dim3((kTFloats + 255) / 256), dim3(256), 0, stream,
                        P, s.wt);
     // Faults of a generated-target batch were counted by the filter.
     (void)a.err;
