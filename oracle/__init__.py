@@ -95,11 +95,13 @@ def lib():
         L.orc_paper_features.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_int, ctypes.c_int, _P]
         L.orc_paper_decoder_batch.restype = ctypes.c_int64
-        L.orc_paper_decoder_batch.argtypes = [_P, _P, _P, ctypes.c_int, _P, ctypes.c_int, _P, _P]
+        L.orc_paper_decoder_batch.argtypes = [_P, _P, _P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int,
+                                              _P, _P]
         L.orc_paper_features_raw.argtypes = L.orc_paper_features.argtypes
         L.orc_encoder_batch.argtypes = [_P, _P, ctypes.c_int, _P]
         L.orc_paper_loss_grad.restype = ctypes.c_double
-        L.orc_paper_loss_grad.argtypes = [_P, _P, _P, ctypes.c_int, _P, ctypes.c_int, _P, _P, _P]
+        L.orc_paper_loss_grad.argtypes = [_P, _P, _P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int,
+                                          _P, _P, _P]
         L.orc_loss_grad.restype = ctypes.c_double
         L.orc_loss_grad.argtypes = [_P, _P, ctypes.c_int, _P, _P, _P, _P]
         L.orc_decoder_backward_batch.argtypes = [_P, _P, _P, ctypes.c_int, _P, _P, _P, _P]
@@ -302,21 +304,25 @@ def paper_features(u: float, v: float, r: float, wx: int, wy: int, raw: bool = F
     return f
 
 
-def paper_decoder_gbuffer(params, latents, mats: Sequence, g, raw: bool = False):
+def paper_decoder_gbuffer(params, latents, mats: Sequence, g, raw: bool = False,
+                          fused: bool = True):
     """Paper-size decoder forward: raw outputs y [4,n] and composed rgb [3,n]
-    (raw: footprint inputs without the one-blob encoding)."""
+    (raw: footprint inputs without the one-blob encoding; fused = False: the
+    angular inputs enter the first layer, no spatial fusion stage)."""
     h = _GBufHolder(g)
     n = h.s.n
     P = _d(params)
     Z = _d(latents).reshape(-1)
     y = np.zeros((4, n))
     rgb = np.zeros((3, n))
-    lib().orc_paper_decoder_batch(_ptr(P), _ptr(Z), materials(mats), len(mats), h.ref, int(raw), _ptr(y),
+    lib().orc_paper_decoder_batch(_ptr(P), _ptr(Z), materials(mats), len(mats), h.ref, int(raw),
+                                  int(fused), _ptr(y),
                                   _ptr(rgb))
     return y, rgb
 
 
-def paper_loss_grad(params, latents, mats: Sequence, g, targets, raw: bool = False):
+def paper_loss_grad(params, latents, mats: Sequence, g, targets, raw: bool = False,
+                    fused: bool = True):
     """Loss of Eq. (11) of the paper-size decoder with per-fabric latents
     [F, 64] and its gradient: (loss, grad [27076], dlatent [F, 64])."""
     h = _GBufHolder(g)
@@ -325,7 +331,8 @@ def paper_loss_grad(params, latents, mats: Sequence, g, targets, raw: bool = Fal
     T = np.ascontiguousarray(targets, dtype=np.float32)
     grad = np.zeros_like(P)
     dlat = np.zeros((len(mats), 64))
-    loss = lib().orc_paper_loss_grad(_ptr(P), _ptr(Z), materials(mats), len(mats), h.ref, int(raw), _ptr(T),
+    loss = lib().orc_paper_loss_grad(_ptr(P), _ptr(Z), materials(mats), len(mats), h.ref, int(raw),
+                                     int(fused), _ptr(T),
                                      _ptr(grad), _ptr(dlat))
     return float(loss), grad, dlat
 

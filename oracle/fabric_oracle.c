@@ -1108,19 +1108,31 @@ void orc_paper_features(double u, double v, double r, int wx, int wy, double f[P
 /* Activations (after each leaky ReLU) kept for the backward pass. */
 typedef struct {
     double x1[PX1], t[PHID], sp[PHID], xa[PXA1], x[PHID], h[PHID], rr[PHID], g[PHID], y[NOUT];
+    double ang[NANG];
+    int fused;
 } paper_acts;
 
+/* fused = 0: the network without the spatial fusion stage (the ablation of
+ * Sec. 5 "Spatial fusion"): the angular inputs enter the first layer, through
+ * A1's angular columns, and A1 sees zeros in their place; the parameter
+ * layout and count are those of the paper's network. */
 static void paper_forward_acts(const double *P, const double *z, const double f[PBLOB],
-                               const double ang[NANG], paper_acts *A)
+                               const double ang[NANG], int fused, paper_acts *A)
 {
     for (int k = 0; k < PLATENT; k++) A->x1[k] = z[k];
     for (int k = 0; k < PBLOB; k++) A->x1[PLATENT + k] = f[k];
+    for (int k = 0; k < NANG; k++) A->ang[k] = ang[k];
+    A->fused = fused;
     dense(P + P_WF1, P + P_BF1, A->x1, PX1, PHID, A->t);
+    if (!fused)
+        for (int o = 0; o < PHID; o++)
+            for (int a = 0; a < NANG; a++)
+                A->t[o] += P[P_WA1 + o * PXA1 + PHID + a] * ang[a];
     for (int k = 0; k < PHID; k++) A->t[k] = lrelu(A->t[k]);
     dense(P + P_WF2, P + P_BF2, A->t, PHID, PHID, A->sp);
     for (int k = 0; k < PHID; k++) A->sp[k] = lrelu(A->sp[k]);
     for (int k = 0; k < PHID; k++) A->xa[k] = A->sp[k];
-    for (int k = 0; k < NANG; k++) A->xa[PHID + k] = ang[k];
+    for (int k = 0; k < NANG; k++) A->xa[PHID + k] = fused ? ang[k] : 0.0;
     dense(P + P_WA1, P + P_BA1, A->xa, PXA1, PHID, A->x);
     for (int k = 0; k < PHID; k++) A->x[k] = lrelu(A->x[k]);
     dense(P + P_WA2, P + P_BA2, A->x, PHID, PHID, A->h);
@@ -1133,10 +1145,10 @@ static void paper_forward_acts(const double *P, const double *z, const double f[
 }
 
 static void paper_forward(const double *P, const double *z, const double f[PBLOB],
-                          const double ang[NANG], double y[NOUT])
+                          const double ang[NANG], int fused, double y[NOUT])
 {
     paper_acts A;
-    paper_forward_acts(P, z, f, ang, &A);
+    paper_forward_acts(P, z, f, ang, fused, &A);
     for (int k = 0; k < NOUT; k++) y[k] = A.y[k];
 }
 
@@ -1164,6 +1176,10 @@ static void paper_backward(const double *P, const paper_acts *A, const double dy
     for (int k = 0; k < PHID; k++) dsp[k] = dxa[k] * dlrelu(A->sp[k]);
     dense_backward(P + P_WF2, A->t, dsp, PHID, PHID, G + P_WF2, G + P_BF2, dt);
     for (int k = 0; k < PHID; k++) dt[k] *= dlrelu(A->t[k]);
+    if (!A->fused)     /* A1's angular columns act in the first layer */
+        for (int o = 0; o < PHID; o++)
+            for (int a = 0; a < NANG; a++)
+                G[P_WA1 + o * PXA1 + PHID + a] += dt[o] * A->ang[a];
     dense_backward(P + P_WF1, A->x1, dt, PX1, PHID, G + P_WF1, G + P_BF1, dx1);
     for (int k = 0; k < PLATENT; k++) dz[k] = dx1[k];
 }
@@ -1173,7 +1189,8 @@ static void paper_backward(const double *P, const paper_acts *A, const double dy
  * composed as the shading path does); faulted pixels give 0.  raw != 0:
  * footprint inputs without the one-blob encoding. */
 int64_t orc_paper_decoder_batch(const double *P, const double *latents, const orc_material *mats,
-                                int nmats, const orc_gbuffer *g, int raw, double *y, double *rgb)
+                                int nmats, const orc_gbuffer *g, int raw, int fused, double *y,
+                                double *rgb)
 {
     int64_t n = g->n, faults = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : faults)
@@ -1185,7 +1202,7 @@ int64_t orc_paper_decoder_batch(const double *P, const double *latents, const or
         if (!bad) {
             double f[PBLOB], ang[NANG] = {wi[0], wi[1], wi[2], wo[0], wo[1]}, comp[4];
             (raw ? orc_paper_features_raw : orc_paper_features)(u, v, r, mats[fid].wx, mats[fid].wy, f);
-            paper_forward(P, latents + (int64_t)fid * PLATENT, f, ang, out);
+            paper_forward(P, latents + (int64_t)fid * PLATENT, f, ang, fused, out);
             decode_outputs(out, spec_k(wi[2]), comp);
             compose_rgb(&mats[fid], comp, c3);
         }
@@ -1402,8 +1419,8 @@ void orc_decoder_backward_batch(const double *P, const double *latents, const or
  * grad [N_PDEC] and dlatent [nmats][64].  Faulted samples contribute
  * nothing but count in n.  Returns the loss. */
 double orc_paper_loss_grad(const double *P, const double *latents, const orc_material *mats,
-                           int nmats, const orc_gbuffer *g, int raw, const float *targets,
-                           double *grad, double *dlatent)
+                           int nmats, const orc_gbuffer *g, int raw, int fused,
+                           const float *targets, double *grad, double *dlatent)
 {
     int64_t n = g->n;
 #ifdef _OPENMP
@@ -1436,7 +1453,7 @@ double orc_paper_loss_grad(const double *P, const double *latents, const orc_mat
                 tgt[c] = targets[(int64_t)c * n + p];
             paper_acts A;
             (raw ? orc_paper_features_raw : orc_paper_features)(u, v, r, mats[fid].wx, mats[fid].wy, f);
-            paper_forward_acts(P, latents + (int64_t)fid * PLATENT, f, ang, &A);
+            paper_forward_acts(P, latents + (int64_t)fid * PLATENT, f, ang, fused, &A);
             lt[tid] += loss_terms(A.y, tgt, spec_k(wi[2]), n, dy);
             paper_backward(P, &A, dy, G, dzp);
             for (int k = 0; k < PLATENT; k++)

@@ -35,30 +35,33 @@ def layer_offsets():
     return out
 
 
-@pytest.mark.parametrize("raw", [False, True])
-def test_gradient_matches_central_differences(raw):
+@pytest.mark.parametrize("raw,fused", [(False, True), (True, True), (False, False)])
+def test_gradient_matches_central_differences(raw, fused):
     mats, g, P, Z, T = case()
-    loss, grad, dlat = orc.paper_loss_grad(P, Z, mats, g, T, raw=raw)
+    kw = dict(raw=raw, fused=fused)
+    loss, grad, dlat = orc.paper_loss_grad(P, Z, mats, g, T, **kw)
     assert np.isfinite(loss) and loss > 0
     rng = np.random.default_rng(11)
     idx = []
     for off, o, i in layer_offsets():
         idx += list(off + rng.integers(0, o * i, 6))           # weights
         idx += list(off + o * i + rng.integers(0, o, 2))        # biases
+    a1 = layer_offsets()[2][0]
+    idx += [a1 + 5 * 69 + 64, a1 + 17 * 69 + 66, a1 + 40 * 69 + 68]   # A1's angular columns
     h = 1e-6
     for k in idx:
         Pp, Pm = P.copy(), P.copy()
         Pp[k] += h
         Pm[k] -= h
-        fd = (orc.paper_loss_grad(Pp, Z, mats, g, T, raw=raw)[0] -
-              orc.paper_loss_grad(Pm, Z, mats, g, T, raw=raw)[0]) / (2 * h)
+        fd = (orc.paper_loss_grad(Pp, Z, mats, g, T, **kw)[0] -
+              orc.paper_loss_grad(Pm, Z, mats, g, T, **kw)[0]) / (2 * h)
         assert abs(fd - grad[k]) <= 1e-6 * max(1.0, abs(grad).max()), (k, fd, grad[k])
     for f, j in [(0, 0), (1, 17), (2, 63), (1, 40)]:
         Zp, Zm = Z.copy(), Z.copy()
         Zp[f, j] += h
         Zm[f, j] -= h
-        fd = (orc.paper_loss_grad(P, Zp, mats, g, T, raw=raw)[0] -
-              orc.paper_loss_grad(P, Zm, mats, g, T, raw=raw)[0]) / (2 * h)
+        fd = (orc.paper_loss_grad(P, Zp, mats, g, T, **kw)[0] -
+              orc.paper_loss_grad(P, Zm, mats, g, T, **kw)[0]) / (2 * h)
         assert abs(fd - dlat[f, j]) <= 1e-6 * max(1.0, abs(dlat).max()), (f, j, fd, dlat[f, j])
 
 
@@ -110,3 +113,24 @@ def test_raw_footprint_inputs():
     y, _ = orc.paper_decoder_gbuffer(P, Z, mats, g, raw=True)
     tau = np.clip((np.log2(g.radius.astype(np.float64)) + 14.0) / 16.0, 0.0, 1.0)
     np.testing.assert_allclose(y[0], tau, rtol=0, atol=1e-15)
+
+
+def test_angular_inputs_enter_first_layer_without_fusion():
+    """Without the spatial fusion stage (the ablation of Sec. 5 "Spatial
+    fusion") wi and wo enter the first layer through A1's angular columns
+    and A1 sees zeros in their place.  With WA1[0][wi.z] = 1, F2[0][0] = -1
+    and pass-through weights elsewhere, the paper's network outputs wi.z
+    (A1 adds it after the spatial feature, which is 0), the unfused one
+    outputs -1e-8 wi.z (wi.z passes the first layer, is negated by F2 and
+    then takes four leaky slopes)."""
+    mats, g, P, Z, _ = case(n=8, n_fab=1, btdf_frac=0.0)
+    P = np.zeros_like(P)
+    (f1, _, _), (f2, _, _), (a1, _, _), _, _, (a4, _, _), (a5, _, _) = layer_offsets()
+    P[a1 + 64 + 2] = 1.0                  # WA1[0][wi.z]
+    P[f2] = -1.0                          # WF2[0][0]
+    P[a1] = P[a4] = P[a5] = 1.0           # WA1[0][0], WA4[0][0], WA5[0][0]
+    wz = g.wi_z.astype(np.float64)
+    y_f, _ = orc.paper_decoder_gbuffer(P, Z, mats, g)
+    y_n, _ = orc.paper_decoder_gbuffer(P, Z, mats, g, fused=False)
+    np.testing.assert_allclose(y_f[0], wz, rtol=1e-15, atol=0)
+    np.testing.assert_allclose(y_n[0], -1e-8 * wz, rtol=1e-12, atol=0)
