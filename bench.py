@@ -436,7 +436,7 @@ def paper_decoder_row(args, torch, pkg, fi, mats, g, d):
         fab.close()
 
 
-def train_paper_network(args, torch, pkg, fi, mats, steps, one_blob=True):
+def train_paper_network(args, torch, pkg, fi, mats, steps, one_blob=True, fused=True):
     """A paper-size decoder trained on `mats` (one latent of 64 per fabric
     trained as a parameter; FP32 training kernels; generated batches of 2^16
     samples with 256-sample targets; Adam with the main network's
@@ -447,6 +447,7 @@ def train_paper_network(args, torch, pkg, fi, mats, steps, one_blob=True):
     z = fi.random_latents(len(mats), 6, scale=0.1, dim=64)
     pkg.fabric_paper_prepare(fab.ctx, torch.from_numpy(params).cuda(), torch.from_numpy(z).cuda())
     pkg.fabric_paper_set_footprint_encoding(fab.ctx, one_blob)
+    pkg.fabric_paper_set_spatial_fusion(fab.ctx, fused)
     batch = 1 << 16
     losses = []
     torch.cuda.synchronize()
@@ -464,7 +465,7 @@ def train_paper_network(args, torch, pkg, fi, mats, steps, one_blob=True):
     rec = {"train_steps": steps, "train_batch": batch,
            "train_ms_per_step": train_s / max(1, steps) * 1e3, "train_s": train_s,
            "loss_first": losses[0] if losses else None, "loss_last": losses[-1] if losses else None,
-           "footprint_encoding": "one-blob" if one_blob else "none"}
+           "footprint_encoding": "one-blob" if one_blob else "none", "spatial_fusion": fused}
     return fab, rec
 
 
@@ -525,17 +526,19 @@ def paper_training_row(args, torch, pkg, fi, mats, g, d, config_rgb):
         fab.close()
 
 
-def encoding_ablation_row(args, torch, pkg, fi, mats, g, d):
-    """Sec. 5 "Encoding of footprint": two paper-size networks trained alike,
-    with and without the one-blob footprint encoding; their FP16 frames
-    against the oracle's filter on the main section's seeded 1 %, overall
-    and by footprint radius."""
+def ablation_row(args, torch, pkg, fi, mats, g, d):
+    """Sec. 5 "Ablation study": three paper-size networks trained alike -
+    the paper's, one without the one-blob footprint encoding ("Encoding of
+    footprint") and one without the spatial fusion stage ("Spatial
+    fusion"); their FP16 frames against the oracle's filter on the main
+    section's seeded 1 %, overall and by footprint radius."""
     steps = args.ablation_train_steps
     res = {"train_steps": steps, "train_batch": 1 << 16}
     ref = None if args.no_rmse or steps == 0 else subset_reference(args, fi, mats, g)
     preds = {}
-    for name, one_blob in (("one_blob", True), ("unencoded", False)):
-        fab, rec = train_paper_network(args, torch, pkg, fi, mats, steps, one_blob)
+    for name, one_blob, fused in (("paper", True, True), ("unencoded", False, True),
+                                  ("unfused", True, False)):
+        fab, rec = train_paper_network(args, torch, pkg, fi, mats, steps, one_blob, fused)
         try:
             out = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
             pkg.fabric_paper_shade(fab.ctx, d, out, "fp16")
@@ -547,9 +550,11 @@ def encoding_ablation_row(args, torch, pkg, fi, mats, g, d):
             fab.close()
     if ref is not None:
         res["rmse_by_footprint_radius"] = errors_by_radius(preds, ref[2], ref[1].radius)
-        res["encoding_lowers_rmse"] = res["one_blob"]["rmse"]["rmse"] < res["unencoded"]["rmse"]["rmse"]
-        log(f"footprint encoding ablation: one-blob {res['one_blob']['rmse']['rmse']:.4g}, "
-            f"unencoded {res['unencoded']['rmse']['rmse']:.4g}")
+        e = {k: res[k]["rmse"]["rmse"] for k in preds}
+        res["encoding_lowers_rmse"] = e["paper"] < e["unencoded"]
+        res["fusion_lowers_rmse"] = e["paper"] < e["unfused"]
+        log(f"ablations: paper {e['paper']:.4g}, without one-blob {e['unencoded']:.4g}, "
+            f"without spatial fusion {e['unfused']:.4g}")
     return res
 
 
@@ -672,7 +677,7 @@ def main():
     ap.add_argument("--paper-train-steps", type=int, default=48000,
                     help="training steps (2^16 samples each) of the paper-size decoder's row")
     ap.add_argument("--ablation-train-steps", type=int, default=12000,
-                    help="training steps of each network of the footprint-encoding ablation")
+                    help="training steps of each network of the ablation row")
     ap.add_argument("--analytic-steps", type=int, default=10)
     ap.add_argument("--rmse-frac", type=float, default=0.01)
     ap.add_argument("--cpu-budget", type=float, default=8.0)
@@ -822,7 +827,7 @@ def main():
         rows["transmission"] = btdf_row(args, torch, pkg, fi)
         rows["paper_decoder"] = paper_decoder_row(args, torch, pkg, fi, mats, g, d)
         rows["paper_training"] = paper_training_row(args, torch, pkg, fi, mats, g, d, rgb["bf16"])
-        rows["footprint_encoding_ablation"] = encoding_ablation_row(args, torch, pkg, fi, mats, g, d)
+        rows["ablations"] = ablation_row(args, torch, pkg, fi, mats, g, d)
 
     # ---- error against the FP64 oracle on a seeded pixel subset ----
     args.neural_ms = ms

@@ -374,6 +374,16 @@ fabric_status fabric_paper_loss_grad(fabric_ctx *ctx, const fabric_gbuffer *batc
  * the other channels 0; the parameter layout is unchanged.  A network is
  * shaded with the encoding it was trained with.  E_INVAL unless 0 or 1. */
 fabric_status fabric_paper_set_footprint_encoding(fabric_ctx *ctx, int32_t one_blob);
+/* Wiring of the paper-size decoder's shading and training: fused = 1 (the
+ * default) is the paper's network, the angular inputs entering A1 after the
+ * spatial fusion F1, F2; fused = 0 removes the fusion stage (the ablation of
+ * Sec. 5 "Spatial fusion"): wi.xyz and wo.xy enter F1 beside the latent and
+ * the footprint, weighted by A1's angular columns, and A1 sees zeros in
+ * their place, so all seven layers follow the concatenated input and the
+ * parameter layout is unchanged.  Re-packs the shading image of the prepared
+ * masters on `stream`.  A network is shaded with the wiring it was trained
+ * with.  E_INVAL unless 0 or 1. */
+fabric_status fabric_paper_set_spatial_fusion(fabric_ctx *ctx, int32_t fused, void *stream);
 /* The paper-size masters to host: params [FABRIC_N_PAPER_DECODER_PARAMS],
  * latents [n_mats][FABRIC_PAPER_LATENT].  Synchronises the device.  E_STATE
  * before fabric_paper_prepare. */

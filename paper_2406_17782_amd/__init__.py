@@ -27,7 +27,7 @@ __all__ = [
     "fabric_create", "fabric_destroy", "fabric_encode", "fabric_set_albedo", "fabric_lerp_latents",
     "fabric_set_visibility", "fabric_paper_prepare", "fabric_paper_shade",
     "fabric_paper_train_step", "fabric_paper_loss_grad", "fabric_paper_get_params",
-    "fabric_paper_set_footprint_encoding", "FABRIC_PAPER_LATENT", "FABRIC_N_PAPER_DECODER_PARAMS",
+    "fabric_paper_set_footprint_encoding", "fabric_paper_set_spatial_fusion", "FABRIC_PAPER_LATENT", "FABRIC_N_PAPER_DECODER_PARAMS",
     "fabric_shade_gbuffer", "fabric_gt_filtered", "fabric_decoder_forward",
     "fabric_decoder_backward", "fabric_encoder_forward", "fabric_encoder_backward",
     "fabric_make_batch", "fabric_loss_grad", "fabric_train_step", "fabric_get_params", "fabric_set_params",
@@ -278,6 +278,11 @@ def fabric_paper_train_step(ctx, batch: Optional[DeviceGBuffer], targets, cfg: d
 def fabric_paper_set_footprint_encoding(ctx, one_blob: bool) -> None:
     check(_abi.lib().fabric_paper_set_footprint_encoding(ctx, 1 if one_blob else 0),
           "fabric_paper_set_footprint_encoding")
+
+
+def fabric_paper_set_spatial_fusion(ctx, fused: bool, stream=None) -> None:
+    check(_abi.lib().fabric_paper_set_spatial_fusion(ctx, 1 if fused else 0, _stream(stream)),
+          "fabric_paper_set_spatial_fusion")
 
 
 def fabric_paper_get_params(ctx, n_mats: int):

@@ -65,7 +65,7 @@ EXPORTS = [
     "fabric_create", "fabric_destroy", "fabric_status_str", "fabric_encode", "fabric_set_albedo",
     "fabric_lerp_latents", "fabric_set_visibility", "fabric_paper_prepare", "fabric_paper_shade",
     "fabric_paper_train_step", "fabric_paper_loss_grad", "fabric_paper_get_params",
-    "fabric_paper_set_footprint_encoding",
+    "fabric_paper_set_footprint_encoding", "fabric_paper_set_spatial_fusion",
     "fabric_shade_gbuffer", "fabric_gt_filtered", "fabric_decoder_forward",
     "fabric_decoder_backward", "fabric_encoder_forward", "fabric_encoder_backward",
     "fabric_make_batch", "fabric_loss_grad", "fabric_train_step", "fabric_get_params", "fabric_set_params",
@@ -103,6 +103,8 @@ def _declare(L):
     L.fabric_paper_loss_grad.restype = _S
     L.fabric_paper_set_footprint_encoding.argtypes = [_P, ctypes.c_int32]
     L.fabric_paper_set_footprint_encoding.restype = _S
+    L.fabric_paper_set_spatial_fusion.argtypes = [_P, ctypes.c_int32, _P]
+    L.fabric_paper_set_spatial_fusion.restype = _S
     L.fabric_paper_get_params.argtypes = [_P, _P, _P]
     L.fabric_paper_get_params.restype = _S
     L.fabric_shade_gbuffer.argtypes = [_P, ctypes.POINTER(fabric_gbuffer), ctypes.c_int,

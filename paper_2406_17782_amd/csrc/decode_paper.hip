@@ -51,10 +51,21 @@ __host__ __device__ inline int p_blob_channel(int g, int c)
     return -1;
 }
 
+// Without the spatial fusion stage (the ablation of Sec. 5 "Spatial
+// fusion"), F1 slots 12 .. 14 of lane group 0 carry wi.xyz and slots 12 .. 13
+// of group 1 wo.xy, weighted by A1's angular columns; returns the angular
+// input 0 .. 4 of F1 slot c, or -1.
+__host__ __device__ inline int p_f1_angular(int g, int c)
+{
+    if (c < kPSlots1 || c >= kPSlots1 + (g == 0 ? 3 : 2))
+        return -1;
+    return 3 * g + (c - kPSlots1);
+}
+
 template <int P>
 __global__ void pack_paper_kernel(const float *__restrict__ params,
                                   typename Mfma<P>::Frag *__restrict__ frags,
-                                  f32x4 *__restrict__ b5)
+                                  f32x4 *__restrict__ b5, int fused)
 {
     using M = Mfma<P>;
     using Frag = typename M::Frag;
@@ -73,14 +84,16 @@ __global__ void pack_paper_kernel(const float *__restrict__ params,
             float w = 0.0f;
             if (layer == kF1) {
                 const int ch = p_blob_channel(grp, c);
+                const int a = fused ? -1 : p_f1_angular(grp, c);
                 if (ch >= 0) w = params[kPOffWF1 + m * kPX1 + kPLat + ch];
+                else if (a >= 0) w = params[kPOffWA1 + m * kPXA1 + 64 + a];
             } else if (layer == kA1) {
                 if (c < kChain32) {
                     w = params[kPOffWA1 + m * kPXA1 + chain32_neuron(grp, c)];
                 } else if (c < kL3Slots32) {
                     const int a = l3_extra32(grp, c - kChain32);
                     if (a == 5) w = params[kPOffBA1 + m];
-                    else if (a >= 0) w = params[kPOffWA1 + m * kPXA1 + 64 + a];
+                    else if (a >= 0 && fused) w = params[kPOffWA1 + m * kPXA1 + 64 + a];
                 }
             } else if (layer == kA5) {
                 if (m < 4 && c < kChain32) w = params[kPOffWA5 + m * 64 + chain32_neuron(grp, c)];
@@ -123,11 +136,13 @@ __global__ void fold_paper_kernel(const float *__restrict__ params,
 // then 4 of the 8 size bins (exp(-d^2/2), d in bins).  RAW (the footprint
 // encoding's ablation): the position fraction of the group's axis in its
 // first bin's slot and, in group 0, tau in the first size bin's slot.
-template <int P, bool RAW>
-__device__ inline void paper_slots(float coord, float iper, float r, int g,
-                                   float (&s1)[kPSlots1])
+template <int P, bool RAW, int NS>
+__device__ inline void paper_slots(float coord, float iper, float r, int g, float (&s1)[NS])
 {
     using FM = FeatureMath<P>;
+#pragma unroll
+    for (int c = kPSlots1; c < NS; c++)
+        s1[c] = 0.0f;
     if (RAW) {
 #pragma unroll
         for (int c = 0; c < kPSlots1; c++)
@@ -222,7 +237,7 @@ template <int P> struct PaperTile {
 };
 
 // Shading of T tiles per wave iteration (T x 32 pixels).
-template <int P, int WAVES, int T, bool RAW>
+template <int P, int WAVES, int T, bool RAW, bool FUSED>
 __global__ __launch_bounds__(64 * WAVES) void decode_paper_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ frags,
@@ -283,9 +298,15 @@ __global__ __launch_bounds__(64 * WAVES) void decode_paper_kernel(
                 entry[t] = fab_entry(fid[t], n_fabrics, grp ? 1.0f : cur[t].xz);
                 const float *fc = s_fc + entry[t] * kFabConsts;
                 // F1: one-blob slots; C operand c_f.
-                float s1[kPSlots1];
+                // Without fusion, four more slots carry the angular inputs.
+                float s1[FUSED ? kPSlots1 : kPSlots1 + 4];
                 const float per = grp ? fc[1] : fc[0], iper = grp ? fc[3] : fc[2];
                 paper_slots<P, RAW>(wrap_period(cur[t].uv, per, iper), iper, cur[t].r, grp, s1);
+                if (!FUSED) {
+                    s1[kPSlots1] = cur[t].x0;
+                    s1[kPSlots1 + 1] = cur[t].x1;
+                    s1[kPSlots1 + 2] = grp ? 0.0f : cur[t].xz;
+                }
                 B1[t][0] = PT::frag_of(s1, 0, false);
                 B1[t][1] = PT::frag_of(s1, 1, false);
 #pragma unroll
@@ -426,7 +447,7 @@ template <int P> static void *paper_image_of(void *image)
 }
 
 hipError_t launch_paper_prepare(const float *params, const float *latents, int n_fabrics,
-                                void *image, float *cfold, hipStream_t stream)
+                                bool fused, void *image, float *cfold, hipStream_t stream)
 {
     const int blocks = (kPFrags * 64 + 255) / 256;
     {
@@ -434,14 +455,14 @@ hipError_t launch_paper_prepare(const float *params, const float *latents, int n
         auto *frags = (Frag *)paper_image_of<FABRIC_BF16>(image);
         auto *b5 = (f32x4 *)(frags + kPFrags * 64);
         hipLaunchKernelGGL(pack_paper_kernel<FABRIC_BF16>, dim3(blocks), dim3(256), 0, stream,
-                           params, frags, b5);
+                           params, frags, b5, fused ? 1 : 0);
     }
     {
         using Frag = Mfma<FABRIC_FP16>::Frag;
         auto *frags = (Frag *)paper_image_of<FABRIC_FP16>(image);
         auto *b5 = (f32x4 *)(frags + kPFrags * 64);
         hipLaunchKernelGGL(pack_paper_kernel<FABRIC_FP16>, dim3(blocks), dim3(256), 0, stream,
-                           params, frags, b5);
+                           params, frags, b5, fused ? 1 : 0);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -452,7 +473,7 @@ hipError_t launch_paper_prepare(const float *params, const float *latents, int n
     return hipGetLastError();
 }
 
-template <int P, bool RAW>
+template <int P, bool RAW, bool FUSED>
 static hipError_t paper_shade(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
                               const float *cfold, const void *image, float *out,
                               unsigned long long *err, hipStream_t stream)
@@ -467,24 +488,38 @@ static hipError_t paper_shade(const fabric_gbuffer &g, const DevFabric *fabrics,
         blocks = cap;
     const size_t lds = (size_t)kPFrags * 64 * sizeof(Frag) +
                        (size_t)n_fabrics * (64 + kFabCopies * kFabConsts) * sizeof(float);
-    hipLaunchKernelGGL((decode_paper_kernel<P, kPaperWaves, kPaperTiles, RAW>), dim3(blocks),
+    hipLaunchKernelGGL((decode_paper_kernel<P, kPaperWaves, kPaperTiles, RAW, FUSED>), dim3(blocks),
                        dim3(64 * kPaperWaves), lds, stream, g, fabrics, n_fabrics, cfold, frags,
                        b5, out, err, n_tiles);
     return hipGetLastError();
 }
 
-hipError_t launch_paper_shade(int prec, bool raw, const fabric_gbuffer &g, const DevFabric *fabrics,
-                              int n_fabrics, const float *cfold, const void *image, float *out,
-                              unsigned long long *err, hipStream_t stream)
+template <int P>
+static hipError_t paper_shade_variant(bool raw, bool fused, const fabric_gbuffer &g,
+                                      const DevFabric *fabrics, int n_fabrics, const float *cfold,
+                                      const void *image, float *out, unsigned long long *err,
+                                      hipStream_t stream)
+{
+    if (raw)
+        return fused ? paper_shade<P, true, true>(g, fabrics, n_fabrics, cfold, image, out, err, stream)
+                     : paper_shade<P, true, false>(g, fabrics, n_fabrics, cfold, image, out, err, stream);
+    return fused ? paper_shade<P, false, true>(g, fabrics, n_fabrics, cfold, image, out, err, stream)
+                 : paper_shade<P, false, false>(g, fabrics, n_fabrics, cfold, image, out, err, stream);
+}
+
+hipError_t launch_paper_shade(int prec, bool raw, bool fused, const fabric_gbuffer &g,
+                              const DevFabric *fabrics, int n_fabrics, const float *cfold,
+                              const void *image, float *out, unsigned long long *err,
+                              hipStream_t stream)
 {
     if (g.n == 0)
         return hipSuccess;
     if (prec == FABRIC_BF16)
-        return raw ? paper_shade<FABRIC_BF16, true>(g, fabrics, n_fabrics, cfold, image, out, err, stream)
-                   : paper_shade<FABRIC_BF16, false>(g, fabrics, n_fabrics, cfold, image, out, err, stream);
+        return paper_shade_variant<FABRIC_BF16>(raw, fused, g, fabrics, n_fabrics, cfold, image,
+                                                out, err, stream);
     if (prec == FABRIC_FP16)
-        return raw ? paper_shade<FABRIC_FP16, true>(g, fabrics, n_fabrics, cfold, image, out, err, stream)
-                   : paper_shade<FABRIC_FP16, false>(g, fabrics, n_fabrics, cfold, image, out, err, stream);
+        return paper_shade_variant<FABRIC_FP16>(raw, fused, g, fabrics, n_fabrics, cfold, image,
+                                                out, err, stream);
     return hipErrorInvalidValue;
 }
 

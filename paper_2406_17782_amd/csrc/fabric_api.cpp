@@ -45,6 +45,7 @@ struct fabric_ctx {
     double *paper_v = nullptr;
     int64_t paper_step = 0;
     bool paper_raw = false;           // footprint inputs without the one-blob encoding
+    bool paper_fused = true;          // false: no spatial fusion stage
     PaperTrainScratch paper_train;
     uint64_t encoded_version = 0;     // weights_version of the last encode
     uint64_t encode_serial = 0;       // bumped on every change of latents or fabric table
@@ -627,7 +628,8 @@ fabric_status fabric_paper_prepare(fabric_ctx *ctx, const float *params, const f
     if (st == FABRIC_OK) st = from_hip(hipMemsetAsync(ctx->paper_m, 0, total * sizeof(double), s));
     if (st == FABRIC_OK) st = from_hip(hipMemsetAsync(ctx->paper_v, 0, total * sizeof(double), s));
     if (st == FABRIC_OK)
-        st = from_hip(launch_paper_prepare(pm, lm, ctx->n_mats, ctx->paper_image, ctx->paper_cfold, s));
+        st = from_hip(launch_paper_prepare(pm, lm, ctx->n_mats, ctx->paper_fused, ctx->paper_image,
+                                           ctx->paper_cfold, s));
     if (st != FABRIC_OK) {
         ctx->paper_n_mats = 0;
         return st;
@@ -650,7 +652,7 @@ fabric_status fabric_paper_shade(fabric_ctx *ctx, const fabric_gbuffer *g, fabri
     if (g->n == 0)
         return FABRIC_OK;
     DeviceGuard guard(ctx->device);
-    return from_hip(launch_paper_shade(prec, ctx->paper_raw, *g, ctx->fabrics, ctx->n_mats, ctx->paper_cfold,
+    return from_hip(launch_paper_shade(prec, ctx->paper_raw, ctx->paper_fused, *g, ctx->fabrics, ctx->n_mats, ctx->paper_cfold,
                                        ctx->paper_image, out_rgb, ctx->err, as_stream(stream)));
 }
 
@@ -954,6 +956,7 @@ PaperTrainArgs paper_train_args(fabric_ctx *ctx, const fabric_gbuffer *batch, co
     a.err = ctx->err;
     a.vis = VisArgs{nullptr, nullptr};
     a.raw = ctx->paper_raw;
+    a.fused = ctx->paper_fused;
     return a;
 }
 }  // namespace
@@ -964,6 +967,21 @@ fabric_status fabric_paper_set_footprint_encoding(fabric_ctx *ctx, int32_t one_b
         return FABRIC_E_INVAL;
     ctx->paper_raw = one_blob == 0;
     return FABRIC_OK;
+}
+
+fabric_status fabric_paper_set_spatial_fusion(fabric_ctx *ctx, int32_t fused, void *stream)
+{
+    if (!ctx || (fused != 0 && fused != 1))
+        return FABRIC_E_INVAL;
+    ctx->paper_fused = fused != 0;
+    if (ctx->paper_n_mats == 0 || !ctx->paper_master)
+        return FABRIC_OK;
+    // The shading image of the prepared masters follows the wiring.
+    DeviceGuard guard(ctx->device);
+    return from_hip(launch_paper_prepare(ctx->paper_master,
+                                         ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS,
+                                         ctx->paper_n_mats, ctx->paper_fused, ctx->paper_image,
+                                         ctx->paper_cfold, as_stream(stream)));
 }
 
 fabric_status fabric_paper_loss_grad(fabric_ctx *ctx, const fabric_gbuffer *batch,
@@ -999,7 +1017,7 @@ fabric_status fabric_paper_train_step(fabric_ctx *ctx, const fabric_gbuffer *bat
     // The shading image follows the masters (unchanged when the step was skipped).
     if (e == hipSuccess)
         e = launch_paper_prepare(ctx->paper_master, ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS,
-                                 ctx->n_mats, ctx->paper_image, ctx->paper_cfold, s);
+                                 ctx->n_mats, ctx->paper_fused, ctx->paper_image, ctx->paper_cfold, s);
     if (e != hipSuccess)
         return from_hip(e);
     if (!updated)

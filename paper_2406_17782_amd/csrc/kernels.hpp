@@ -84,12 +84,15 @@ hipError_t launch_lerp_latents(const LatentLerp *jobs, int count, float *latents
 // folded from latents [n_fabrics][64]; shading of a G-buffer into rgb [3][n]
 // with prec FABRIC_BF16 or FABRIC_FP16 operands.
 size_t paper_image_bytes();
+// fused = false: the network without the spatial fusion stage (the angular
+// inputs enter F1 through A1's angular columns).
 hipError_t launch_paper_prepare(const float *params, const float *latents, int n_fabrics,
-                                void *image, float *cfold, hipStream_t stream);
+                                bool fused, void *image, float *cfold, hipStream_t stream);
 // raw: footprint inputs without the one-blob encoding (the encoding's ablation).
-hipError_t launch_paper_shade(int prec, bool raw, const fabric_gbuffer &g, const DevFabric *fabrics,
-                              int n_fabrics, const float *cfold, const void *image, float *out,
-                              unsigned long long *err, hipStream_t stream);
+hipError_t launch_paper_shade(int prec, bool raw, bool fused, const fabric_gbuffer &g,
+                              const DevFabric *fabrics, int n_fabrics, const float *cfold,
+                              const void *image, float *out, unsigned long long *err,
+                              hipStream_t stream);
 
 // Encoder forward over n_fabrics fabrics: enc_inputs[n][524] -> latents[n][32].
 hipError_t launch_encoder_forward(const float *enc_params, const float *enc_inputs,

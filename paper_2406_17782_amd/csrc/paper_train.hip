@@ -157,7 +157,7 @@ __device__ inline void bwd16(const float *__restrict__ W, const float *grow, int
 __global__ __launch_bounds__(256) void paper_fwd_bwd_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ P, const float *__restrict__ lat, const float *__restrict__ wt,
-    const float *__restrict__ targets, float *__restrict__ pl, int64_t cap, int raw,
+    const float *__restrict__ targets, float *__restrict__ pl, int64_t cap, int raw, int fused,
     double *__restrict__ loss_part)
 {
     __shared__ float bufA[kFbSamples * kFbStride];
@@ -215,10 +215,19 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_kernel(
     float acc[16], xres[16];
     // A forward layer: outputs of this wave's neurons, activated (+ skip),
     // to the other buffer and the plane.
+    // Without the spatial fusion stage the angular inputs enter F1 through
+    // A1's angular columns (add_ang).
     auto layer = [&](auto nin_tag, int tl, const float *bias, const float *in, float *out, int plane,
-                     bool skip) {
+                     bool skip, bool add_ang) {
         constexpr int NIN = decltype(nin_tag)::value;
         fwd16<NIN, 64>(wt + t_first(tl), bias, in, o0, acc);
+        if (add_ang) {
+#pragma unroll
+            for (int k = 0; k < 16; k++)
+#pragma unroll
+                for (int a = 0; a < 5; a++)
+                    acc[k] = fmaf(P[kPOffWA1 + (o0 + k) * kPXA1 + 64 + a], ang[a], acc[k]);
+        }
 #pragma unroll
         for (int k = 0; k < 16; k++) {
             const float a = lrelu(skip ? acc[k] + xres[k] : acc[k]);
@@ -231,21 +240,21 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_kernel(
     using I88 = std::integral_constant<int, kPX1>;
     using I69 = std::integral_constant<int, kPXA1>;
     using I64 = std::integral_constant<int, 64>;
-    layer(I88{}, kTF1, P + kPOffBF1, rowA, rowB, kPlT, false);
-    layer(I64{}, kTF2, P + kPOffBF2, rowB, rowA, kPlSP, false);
+    layer(I88{}, kTF1, P + kPOffBF1, rowA, rowB, kPlT, false, fused == 0);
+    layer(I64{}, kTF2, P + kPOffBF2, rowB, rowA, kPlSP, false, false);
     if (w == 0) {
 #pragma unroll
         for (int k = 0; k < 5; k++)
-            rowA[64 + k] = ang[k];
+            rowA[64 + k] = fused ? ang[k] : 0.0f;
     }
     __syncthreads();
-    layer(I69{}, kTA1, P + kPOffBA1, rowA, rowB, kPlX, false);
+    layer(I69{}, kTA1, P + kPOffBA1, rowA, rowB, kPlX, false, false);
 #pragma unroll
     for (int k = 0; k < 16; k++)
         xres[k] = acc[k];                               // the residual block's input
-    layer(I64{}, kTA2, P + kPOffBA2, rowB, rowA, kPlH, false);
-    layer(I64{}, kTA3, P + kPOffBA3, rowA, rowB, kPlRR, true);
-    layer(I64{}, kTA4, P + kPOffBA4, rowB, rowA, kPlG, false);
+    layer(I64{}, kTA2, P + kPOffBA2, rowB, rowA, kPlH, false, false);
+    layer(I64{}, kTA3, P + kPOffBA3, rowA, rowB, kPlRR, true, false);
+    layer(I64{}, kTA4, P + kPOffBA4, rowB, rowA, kPlG, false, false);
     // ---- A5: wave w computes output w; the four meet in LDS ----
     {
         float y = P[kPOffBA5 + w];
@@ -348,7 +357,7 @@ struct PWJob {
     int w_off, row, col, b_off;     // destination in the parameter gradient
     int onehot;                     // 1: per-fabric sums into dsum[j][i]
 };
-constexpr int kPWMaxJobs = 8;
+constexpr int kPWMaxJobs = 9;
 struct PWJobs {
     PWJob j[kPWMaxJobs];
     int64_t poff[kPWMaxJobs];       // job offsets in the partial buffer
@@ -519,7 +528,7 @@ template <typename Tp> hipError_t regrow(Tp **p, size_t count)
     return hipMalloc((void **)p, count * sizeof(Tp));
 }
 
-PWJobs make_jobs(int n_fabrics, int n_chunks)
+PWJobs make_jobs(int n_fabrics, int n_chunks, bool fused)
 {
     PWJobs J;
     auto job = [](int delta, int n_out, int inA, int nA, int inB, int nB, int w_off, int row,
@@ -531,7 +540,13 @@ PWJobs make_jobs(int n_fabrics, int n_chunks)
     J.j[k++] = job(kPlDG, 64, kPlRR, 64, 0, 0, kPOffWA4, 64, 0, kPOffBA4);
     J.j[k++] = job(kPlDRR, 64, kPlH, 64, 0, 0, kPOffWA3, 64, 0, kPOffBA3);
     J.j[k++] = job(kPlDH, 64, kPlX, 64, 0, 0, kPOffWA2, 64, 0, kPOffBA2);
-    J.j[k++] = job(kPlDX, 64, kPlSP, 64, kPlAng, 5, kPOffWA1, kPXA1, 0, kPOffBA1);
+    if (fused) {
+        J.j[k++] = job(kPlDX, 64, kPlSP, 64, kPlAng, 5, kPOffWA1, kPXA1, 0, kPOffBA1);
+    } else {
+        // A1 sees zeros for the angular inputs; its angular columns act in F1.
+        J.j[k++] = job(kPlDX, 64, kPlSP, 64, 0, 0, kPOffWA1, kPXA1, 0, kPOffBA1);
+        J.j[k++] = job(kPlDT, 64, kPlAng, 5, 0, 0, kPOffWA1, kPXA1, 64, -1);
+    }
     J.j[k++] = job(kPlDSP, 64, kPlT, 64, 0, 0, kPOffWF2, 64, 0, kPOffBF2);
     J.j[k++] = job(kPlDT, 64, kPlFeat, 24, 0, 0, kPOffWF1, kPX1, kPLat, kPOffBF1);
     J.j[k++] = PWJob{kPlDT, 64, 0, n_fabrics, 0, 0, 0, 0, 0, -1, 1};
@@ -608,7 +623,7 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
         s.cap = n;
     }
     const int n_chunks = (int)((n + kPwChunk - 1) / kPwChunk);
-    const PWJobs jobs = make_jobs(a.n_fabrics, n_chunks);
+    const PWJobs jobs = make_jobs(a.n_fabrics, n_chunks, a.fused);
     const size_t need = (size_t)(jobs.poff[jobs.n_jobs - 1] +
                                  (int64_t)n_chunks * jobs.j[jobs.n_jobs - 1].n_out *
                                      pw_cols(jobs.j[jobs.n_jobs - 1]));
@@ -622,7 +637,7 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
     (void)a.err;
     hipLaunchKernelGGL(paper_fwd_bwd_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, g,
                        a.fabrics, a.n_fabrics, P, lat, (const float *)s.wt, targets, s.planes,
-                       s.cap, a.raw ? 1 : 0, s.loss_part);
+                       s.cap, a.raw ? 1 : 0, a.fused ? 1 : 0, s.loss_part);
     hipLaunchKernelGGL(paper_loss_reduce_kernel, dim3(1), dim3(256), 0, stream,
                        (const double *)s.loss_part, blocks, 1.0 / (double)n, s.loss);
     hipLaunchKernelGGL(paper_wgrad_kernel, dim3(n_chunks, jobs.n_jobs), dim3(256), 0, stream, jobs,

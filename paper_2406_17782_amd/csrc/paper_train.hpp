@@ -43,6 +43,7 @@ struct PaperTrainArgs {
     unsigned long long *err;
     VisArgs vis;
     bool raw;                     // footprint inputs without the one-blob encoding
+    bool fused;                   // false: the angular inputs enter F1 (no spatial fusion)
 };
 
 // Loss and gradient [params | latents] of one batch into grad_out (device).

@@ -5,7 +5,8 @@ ragged batch with transmission and faulted samples (norm-wise per tensor
 1e-4, as for the config decoder); two Adam steps against the oracle's;
 training on generated batches lowers the loss and the shading image follows
 the trained masters; the same without the one-blob footprint encoding
-(the encoding's ablation); call errors."""
+(the encoding's ablation) and without the spatial fusion stage (the
+fusion's ablation); call errors."""
 import numpy as np
 import pytest
 
@@ -147,6 +148,36 @@ def test_unencoded_footprint_shading_and_gradient(fab, pkg, orc, torch):
     assert rel_norm_err(out.cpu().numpy(), o_blob) < 2e-2
     c = pkg._abi.lib().fabric_paper_set_footprint_encoding(fab.ctx, 2)
     assert c == 1                                     # E_INVAL
+
+
+def test_unfused_shading_and_gradient(fab, pkg, orc, torch):
+    """The spatial-fusion ablation: shading (FP16) and the loss gradient of
+    the network whose angular inputs enter the first layer, against the
+    oracle's, and the switch back to the paper's wiring."""
+    mats = fi.materials_for(4, 350)
+    g = batch(4, 45, 37, 351)
+    tg = fi.random_targets(g.n, 352)
+    params, z = prepare(fab, pkg, torch, mats, 353)
+    d = pkg.DeviceGBuffer.from_host(g)
+    out = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
+    pkg.fabric_paper_set_spatial_fusion(fab.ctx, False)
+    pkg.fabric_paper_shade(fab.ctx, d, out, "fp16")
+    _, o_nf = orc.paper_decoder_gbuffer(params, z, mats, g, fused=False)
+    _, o_f = orc.paper_decoder_gbuffer(params, z, mats, g)
+    err = rel_norm_err(out.cpu().numpy(), o_nf)
+    print("unfused fp16 vs oracle", err, "wirings differ by", rel_norm_err(o_nf, o_f))
+    assert err < 2e-2 and rel_norm_err(o_nf, o_f) > 0.1
+    grad = torch.empty(N + 4 * 64, device="cuda")
+    loss = pkg.fabric_paper_loss_grad(fab.ctx, d, torch.from_numpy(tg).cuda(), {}, grad)
+    oloss, ograd, odlat = orc.paper_loss_grad(params, z, mats, g, tg, fused=False)
+    assert loss == pytest.approx(oloss, rel=1e-5)
+    errs = per_tensor_errors(grad.cpu().numpy(), np.concatenate([ograd, odlat.ravel()]), 4)
+    print("unfused gradient errors", ["%.2e" % e for e in errs])
+    assert max(errs) < 1e-4
+    pkg.fabric_paper_set_spatial_fusion(fab.ctx, True)
+    pkg.fabric_paper_shade(fab.ctx, d, out, "fp16")
+    assert rel_norm_err(out.cpu().numpy(), o_f) < 2e-2
+    assert pkg._abi.lib().fabric_paper_set_spatial_fusion(fab.ctx, 2, None) == 1     # E_INVAL
 
 
 def test_paper_training_errors(fab, pkg, torch):
