@@ -1,12 +1,14 @@
 // Training of the paper-size decoder (Sec. 4.2 "Decoder"; loss of Eq. (9)-(11))
 // with one latent of 64 per fabric trained as a parameter.
 //
-//   paper_fwd_bwd_kernel   one thread per sample: one-blob features, the
-//                          seven layers forward in FP32 (inputs in registers,
-//                          each layer's outputs stored to the sample's
-//                          planes), the loss terms and dL/dy, then the
-//                          layers backward (transposed weights), storing
-//                          every layer's gradient at its pre-activation
+//   paper_fwd_bwd_kernel   64 samples per block, wave w owning neurons
+//                          16 w .. 16 w + 15 of every layer: one-blob
+//                          features, the seven layers forward in FP32 (each
+//                          layer's input vectors shared through LDS, its
+//                          outputs also stored to the samples' planes), the
+//                          loss terms and dL/dy, then the layers backward,
+//                          storing every layer's gradient at its
+//                          pre-activation
 //   paper_wgrad_kernel     split-K weight gradients: per (job, chunk of
 //                          256 samples) block, dL/dW and dL/db of one layer
 //                          as sums of outer products over the chunk, staged
