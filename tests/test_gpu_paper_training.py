@@ -77,6 +77,27 @@ def test_paper_loss_grad_matches_oracle(fab, pkg, orc, torch):
     assert max(errs) < 1e-4
 
 
+def test_paper_loss_grad_full_batch_2p16(fab, pkg, orc, torch):
+    """The batch the benchmark trains the paper-size network on: 2^16
+    samples of the 1080p workload's 8 fabrics (the training workload's
+    recipe, cut to 2^16), at the launch size of a training step, against the
+    oracle over every sample."""
+    wl = fi.WORKLOADS["train_2p20"]
+    mats = wl.materials()
+    g = wl.gbuffer().subset(np.arange(1 << 16))
+    g.fabric_id[:] = np.random.default_rng(74).integers(0, 8, g.n).astype(np.uint16)
+    tg = fi.random_targets(g.n, 75)
+    params, z = prepare(fab, pkg, torch, mats, 76)
+    grad = torch.empty(N + 8 * 64, device="cuda")
+    loss = pkg.fabric_paper_loss_grad(fab.ctx, pkg.DeviceGBuffer.from_host(g),
+                                      torch.from_numpy(tg).cuda(), {}, grad)
+    oloss, ograd, odlat = orc.paper_loss_grad(params, z, mats, g, tg)
+    assert loss == pytest.approx(oloss, rel=1e-5)
+    errs = per_tensor_errors(grad.cpu().numpy(), np.concatenate([ograd, odlat.ravel()]), 8)
+    print("paper gradient errors at 2^16", ["%.2e" % e for e in errs])
+    assert max(errs) < 1e-4
+
+
 def test_paper_adam_steps_match_oracle(fab, pkg, orc, torch):
     mats = fi.materials_for(3, 310)
     g = batch(3, 40, 31, 311)
