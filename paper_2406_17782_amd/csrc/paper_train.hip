@@ -219,8 +219,10 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_kernel(
     // to the other buffer and the plane.
     // Without the spatial fusion stage the angular inputs enter F1 through
     // A1's angular columns (add_ang).
+    // The signs of this wave's activations (bit k: neuron o0 + k > 0), kept
+    // for the backward pass's slopes.
     auto layer = [&](auto nin_tag, int tl, const float *bias, const float *in, float *out, int plane,
-                     bool skip, bool add_ang) {
+                     bool skip, bool add_ang, uint32_t &pos) {
         constexpr int NIN = decltype(nin_tag)::value;
         fwd16<NIN, 64>(wt + t_first(tl), bias, in, o0, acc);
         if (add_ang) {
@@ -230,33 +232,36 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_kernel(
                 for (int a = 0; a < 5; a++)
                     acc[k] = fmaf(P[kPOffWA1 + (o0 + k) * kPXA1 + 64 + a], ang[a], acc[k]);
         }
+        pos = 0u;
 #pragma unroll
         for (int k = 0; k < 16; k++) {
             const float a = lrelu(skip ? acc[k] + xres[k] : acc[k]);
             out[o0 + k] = a;
             store(plane + o0 + k, a);
             acc[k] = a;
+            pos |= (a > 0.0f ? 1u : 0u) << k;
         }
         __syncthreads();
     };
     using I88 = std::integral_constant<int, kPX1>;
     using I69 = std::integral_constant<int, kPXA1>;
     using I64 = std::integral_constant<int, 64>;
-    layer(I88{}, kTF1, P + kPOffBF1, rowA, rowB, kPlT, false, fused == 0);
-    layer(I64{}, kTF2, P + kPOffBF2, rowB, rowA, kPlSP, false, false);
+    uint32_t pT, pSP, pX, pH, pRR, pG;
+    layer(I88{}, kTF1, P + kPOffBF1, rowA, rowB, kPlT, false, fused == 0, pT);
+    layer(I64{}, kTF2, P + kPOffBF2, rowB, rowA, kPlSP, false, false, pSP);
     if (w == 0) {
 #pragma unroll
         for (int k = 0; k < 5; k++)
             rowA[64 + k] = fused ? ang[k] : 0.0f;
     }
     __syncthreads();
-    layer(I69{}, kTA1, P + kPOffBA1, rowA, rowB, kPlX, false, false);
+    layer(I69{}, kTA1, P + kPOffBA1, rowA, rowB, kPlX, false, false, pX);
 #pragma unroll
     for (int k = 0; k < 16; k++)
         xres[k] = acc[k];                               // the residual block's input
-    layer(I64{}, kTA2, P + kPOffBA2, rowB, rowA, kPlH, false, false);
-    layer(I64{}, kTA3, P + kPOffBA3, rowA, rowB, kPlRR, true, false);
-    layer(I64{}, kTA4, P + kPOffBA4, rowB, rowA, kPlG, false, false);
+    layer(I64{}, kTA2, P + kPOffBA2, rowB, rowA, kPlH, false, false, pH);
+    layer(I64{}, kTA3, P + kPOffBA3, rowA, rowB, kPlRR, true, false, pRR);
+    layer(I64{}, kTA4, P + kPOffBA4, rowB, rowA, kPlG, false, false, pG);
     // ---- A5: wave w computes output w; the four meet in LDS ----
     {
         float y = P[kPOffBA5 + w];
@@ -292,14 +297,14 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_kernel(
     __syncthreads();                                    // rowB's outputs read by all
     // ---- backward: this wave's 16 input gradients of each layer ----
     auto back = [&](auto ng_tag, auto row_tag, int woff, const float *gin, float *gout,
-                    int act_plane, int out_plane, const float *extra) {
+                    uint32_t pos, int out_plane, const float *extra) {
         constexpr int NG = decltype(ng_tag)::value;
         constexpr int ROW = decltype(row_tag)::value;
         bwd16<NG, ROW>(P + woff, gin, o0, acc);
 #pragma unroll
         for (int k = 0; k < 16; k++) {
             const float t = extra ? acc[k] + extra[k] : acc[k];
-            const float d = own(act_plane + o0 + k) > 0.0f ? t : kLeak * t;
+            const float d = (pos >> k) & 1u ? t : kLeak * t;
             acc[k] = fault ? 0.0f : d;
             gout[o0 + k] = acc[k];
             store(out_plane + o0 + k, acc[k]);
@@ -307,16 +312,16 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_kernel(
         __syncthreads();
     };
     using I4 = std::integral_constant<int, 4>;
-    back(I4{}, I64{}, kPOffWA5, dy, rowA, kPlG, kPlDG, nullptr);
-    back(I64{}, I64{}, kPOffWA4, rowA, rowB, kPlRR, kPlDRR, nullptr);
+    back(I4{}, I64{}, kPOffWA5, dy, rowA, pG, kPlDG, nullptr);
+    back(I64{}, I64{}, kPOffWA4, rowA, rowB, pRR, kPlDRR, nullptr);
     float drr[16];
 #pragma unroll
     for (int k = 0; k < 16; k++)
         drr[k] = acc[k];                                // the skip's gradient to A1's output
-    back(I64{}, I64{}, kPOffWA3, rowB, rowA, kPlH, kPlDH, nullptr);
-    back(I64{}, I64{}, kPOffWA2, rowA, rowB, kPlX, kPlDX, drr);
-    back(I64{}, I69{}, kPOffWA1, rowB, rowA, kPlSP, kPlDSP, nullptr);
-    back(I64{}, I64{}, kPOffWF2, rowA, rowB, kPlT, kPlDT, nullptr);
+    back(I64{}, I64{}, kPOffWA3, rowB, rowA, pH, kPlDH, nullptr);
+    back(I64{}, I64{}, kPOffWA2, rowA, rowB, pX, kPlDX, drr);
+    back(I64{}, I69{}, kPOffWA1, rowB, rowA, pSP, kPlDSP, nullptr);
+    back(I64{}, I64{}, kPOffWF2, rowA, rowB, pT, kPlDT, nullptr);
 
     // Fixed-order sum of the block's loss terms (wave 0 holds them).
     if (w == 0)
