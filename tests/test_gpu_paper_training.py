@@ -201,6 +201,29 @@ def test_unfused_shading_and_gradient(fab, pkg, orc, torch):
     assert pkg._abi.lib().fabric_paper_set_spatial_fusion(fab.ctx, 2, None) == 1     # E_INVAL
 
 
+def test_paper_training_deterministic_and_follows_visibility(fab, pkg, torch):
+    """Fixed-order reductions: the same steps from the same masters give
+    bitwise the same parameters; generated targets follow the context's
+    visibility setting (a different loss with V, the same again without)."""
+    mats = fi.materials_for(4, 360)
+    cfg = dict(batch=4096, gt_samples=16, lr=1e-3)
+    runs = []
+    for _ in range(2):
+        prepare(fab, pkg, torch, mats, 361)
+        for s in range(3):
+            pkg.fabric_paper_train_step(fab.ctx, None, None, dict(cfg, seed=10 + s), want_loss=False)
+        runs.append(pkg.fabric_paper_get_params(fab.ctx, 4))
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    grad = torch.empty(N + 4 * 64, device="cuda")
+    l0 = pkg.fabric_paper_loss_grad(fab.ctx, None, None, dict(cfg, seed=20), grad)
+    fab.set_visibility(True)
+    l1 = pkg.fabric_paper_loss_grad(fab.ctx, None, None, dict(cfg, seed=20), grad)
+    fab.set_visibility(False)
+    l2 = pkg.fabric_paper_loss_grad(fab.ctx, None, None, dict(cfg, seed=20), grad)
+    print("paper loss without / with visibility", l0, l1)
+    assert l1 != l0 and l2 == l0
+
+
 def test_paper_training_errors(fab, pkg, torch):
     mats = fi.materials_for(2, 330)
     fab.encode(mats)
