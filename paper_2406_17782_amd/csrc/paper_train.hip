@@ -130,7 +130,7 @@ __device__ inline void fwd16(const float *__restrict__ WT, const float *__restri
 #pragma unroll
     for (int k = 0; k < 16; k++)
         acc[k] = b[o0 + k];
-#pragma unroll 4
+#pragma unroll 8
     for (int i = 0; i < NIN; i++) {
         const float xi = xrow[i];
 #pragma unroll
@@ -147,7 +147,7 @@ __device__ inline void bwd16(const float *__restrict__ W, const float *grow, int
 #pragma unroll
     for (int k = 0; k < 16; k++)
         acc[k] = 0.0f;
-#pragma unroll 4
+#pragma unroll 8
     for (int o = 0; o < NG; o++) {
         const float go = grow[o];
 #pragma unroll
