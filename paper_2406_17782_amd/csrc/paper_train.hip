@@ -384,9 +384,11 @@ __host__ __device__ inline int pw_cols(const PWJob &jb)
     return jb.nA + jb.nB + (jb.b_off >= 0 ? 1 : 0);
 }
 
-// Each thread accumulates up to two 4 x 4 blocks of (row, column) entries:
+// 512 threads; each accumulates one 4 x 4 block of (row, column) entries
+// (at most 16 x 18 blocks, so every block of a job is in flight at once):
 // per sample, two 16-byte LDS reads feed 16 FMAs.
-__global__ __launch_bounds__(256) void paper_wgrad_kernel(PWJobs jobs, const float *__restrict__ pl,
+constexpr int kPwThreads = 512;
+__global__ __launch_bounds__(kPwThreads) void paper_wgrad_kernel(PWJobs jobs, const float *__restrict__ pl,
                                                           int64_t cap, const uint16_t *__restrict__ fid,
                                                           int64_t n, float *__restrict__ partial)
 {
@@ -396,9 +398,10 @@ __global__ __launch_bounds__(256) void paper_wgrad_kernel(PWJobs jobs, const flo
     const int cols = pw_cols(jb);
     const int rg = (jb.n_out + 3) / 4, cg = (cols + 3) / 4;
     const int tiles = rg * cg;                  // <= 16 x 18
-    float acc[2][4][4];
+    static_assert(16 * 18 <= kPwThreads, "one 4 x 4 block per thread");
+    float acc[1][4][4];
 #pragma unroll
-    for (int m = 0; m < 2; m++)
+    for (int m = 0; m < 1; m++)
 #pragma unroll
         for (int x = 0; x < 4; x++)
 #pragma unroll
@@ -431,8 +434,8 @@ __global__ __launch_bounds__(256) void paper_wgrad_kernel(PWJobs jobs, const flo
         }
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < 2; m++) {
-            const int t = threadIdx.x + 256 * m;
+        for (int m = 0; m < 1; m++) {
+            const int t = threadIdx.x;
             if (t < tiles) {
                 const int r = t / cg, c = t % cg;
 #pragma unroll 4
@@ -453,8 +456,8 @@ __global__ __launch_bounds__(256) void paper_wgrad_kernel(PWJobs jobs, const flo
     const int E = jb.n_out * cols;
     float *dst = partial + jobs.poff[blockIdx.y] + (int64_t)blockIdx.x * E;
 #pragma unroll
-    for (int m = 0; m < 2; m++) {
-        const int t = threadIdx.x + 256 * m;
+    for (int m = 0; m < 1; m++) {
+        const int t = threadIdx.x;
         if (t < tiles) {
             const int r = t / cg, c = t % cg;
 #pragma unroll
@@ -647,7 +650,7 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
                        s.cap, a.raw ? 1 : 0, a.fused ? 1 : 0, s.loss_part);
     hipLaunchKernelGGL(paper_loss_reduce_kernel, dim3(1), dim3(256), 0, stream,
                        (const double *)s.loss_part, blocks, 1.0 / (double)n, s.loss);
-    hipLaunchKernelGGL(paper_wgrad_kernel, dim3(n_chunks, jobs.n_jobs), dim3(256), 0, stream, jobs,
+    hipLaunchKernelGGL(paper_wgrad_kernel, dim3(n_chunks, jobs.n_jobs), dim3(kPwThreads), 0, stream, jobs,
                        (const float *)s.planes, s.cap, g.fabric_id, n, s.partial);
     hipLaunchKernelGGL(paper_wgrad_reduce_kernel, dim3((64 * kPwMaxIn + 255) / 256, jobs.n_jobs),
                        dim3(256), 0, stream, jobs, n_chunks, (const float *)s.partial, grad, s.dsum);
