@@ -389,6 +389,10 @@ def btdf_row(args, torch, pkg, fi):
 
 
 PAPER_FLOP_PER_PIXEL = 2 * (24 * 64 + 64 * 64 + 69 * 64 + 3 * 64 * 64 + 64 * 4)   # 45,184
+# Training of the paper-size decoder per sample: forward 26,688 MAC (latent
+# columns included), input gradients 20,736 MAC, weight gradients 22,592 MAC.
+PAPER_TRAIN_FLOP_PER_SAMPLE = 2 * (26688 + 20736 + 22592)
+FP32_UNPACKED_PEAK_TFLOPS = 78.6   # half of 157.3, which counts packed FP32 FMAs
 
 
 def paper_decoder_row(args, torch, pkg, fi, mats, g, d):
@@ -462,8 +466,17 @@ def train_paper_network(args, torch, pkg, fi, mats, steps, one_blob=True, fused=
             losses.append(l)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
+    ms = train_s / max(1, steps) * 1e3
+    tflops = PAPER_TRAIN_FLOP_PER_SAMPLE * batch / (ms * 1e-3) / 1e12 if steps else None
     rec = {"train_steps": steps, "train_batch": batch,
-           "train_ms_per_step": train_s / max(1, steps) * 1e3, "train_s": train_s,
+           "train_ms_per_step": ms, "train_s": train_s,
+           # The whole step (batch, 256-sample targets, forward, backward,
+           # weight gradients, Adam) against the training's algorithmic FLOPs;
+           # the peak is that of unpacked FP32 FMAs (the library uses no
+           # packed FP32 instructions).
+           "algorithmic_flop_per_sample": PAPER_TRAIN_FLOP_PER_SAMPLE,
+           "step_tflops": tflops,
+           "step_frac_of_unpacked_fp32": tflops / FP32_UNPACKED_PEAK_TFLOPS if steps else None,
            "loss_first": losses[0] if losses else None, "loss_last": losses[-1] if losses else None,
            "footprint_encoding": "one-blob" if one_blob else "none", "spatial_fusion": fused}
     return fab, rec
