@@ -687,7 +687,7 @@ def main():
     ap.add_argument("--gt-samples", type=int, default=256)
     ap.add_argument("--interp-train-steps", type=int, default=12000,
                     help="training steps of the latent interpolation row's network")
-    ap.add_argument("--paper-train-steps", type=int, default=48000,
+    ap.add_argument("--paper-train-steps", type=int, default=96000,
                     help="training steps (2^16 samples each) of the paper-size decoder's row")
     ap.add_argument("--ablation-train-steps", type=int, default=12000,
                     help="training steps of each network of the ablation row")
