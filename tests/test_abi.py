@@ -50,6 +50,16 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     assert lib.fabric_gt_filtered(None, None, 64, 0, None, None, None) == 1
     assert lib.fabric_train_step(None, None, None, None, None, None) == 1
     assert lib.fabric_error_count(None, 0) == -1
+    # The later entry points validate the same way.
+    assert lib.fabric_set_visibility(None, 1) == 1
+    assert lib.fabric_lerp_latents(None, None, None, None, None, 0, None) == 1
+    assert lib.fabric_paper_prepare(None, None, None, None) == 1
+    assert lib.fabric_paper_shade(None, None, 1, None, None) == 1
+    assert lib.fabric_paper_train_step(None, None, None, None, None, None) == 1
+    assert lib.fabric_paper_loss_grad(None, None, None, None, None, None, None) == 1
+    assert lib.fabric_paper_set_footprint_encoding(None, 1) == 1
+    assert lib.fabric_paper_set_spatial_fusion(None, 1, None) == 1
+    assert lib.fabric_paper_get_params(None, None, None) == 1
     lib.fabric_destroy(None)
 
 
