@@ -121,6 +121,7 @@ __device__ inline void blob24(const DevFabric &f, float u, float v, float r, boo
 // its own.  Activations and gradients also go to the per-sample planes.
 constexpr int kFbSamples = 64;
 constexpr int kFbStride = kPX1 + 1;                  // LDS row of one sample (odd: no conflicts)
+constexpr int kFbStrideB = 64 + 1;                   // the second buffer holds at most 64 per sample
 
 // acc[k] = b[o] + sum_i WT[i][o] x[i] for o = o0 + k (WT: [NIN][NOUT]).
 template <int NIN, int NOUT>
@@ -156,14 +157,16 @@ __device__ inline void bwd16(const float *__restrict__ W, const float *grow, int
     }
 }
 
-__global__ __launch_bounds__(256) void paper_fwd_bwd_kernel(
+// Four blocks per CU (at most 128 VGPRs, under 40 KB of LDS per block): a
+// 2^16-sample batch is then one round of 1,024 blocks.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void paper_fwd_bwd_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ P, const float *__restrict__ lat, const float *__restrict__ wt,
     const float *__restrict__ targets, float *__restrict__ pl, int64_t cap, int raw, int fused,
     double *__restrict__ loss_part)
 {
     __shared__ float bufA[kFbSamples * kFbStride];
-    __shared__ float bufB[kFbSamples * kFbStride];
+    __shared__ float bufB[kFbSamples * kFbStrideB];
     __shared__ double red[kFbSamples];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -194,7 +197,7 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_kernel(
     };
     // This thread's own earlier stores (absent past the end of the batch).
     auto own = [&](int plane) { return live ? pl[(int64_t)plane * cap + s] : 0.0f; };
-    float *rowA = bufA + lane * kFbStride, *rowB = bufB + lane * kFbStride;
+    float *rowA = bufA + lane * kFbStride, *rowB = bufB + lane * kFbStrideB;
     const float ang[5] = {wi.x, wi.y, wi.z, wo.x, wo.y};
 
     // ---- F1 input [z, one-blob] (each wave fills a quarter of the row) ----
