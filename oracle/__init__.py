@@ -82,6 +82,9 @@ def lib():
         L.orc_surface_height.argtypes = [_P, ctypes.c_double, ctypes.c_double]
         L.orc_height_table.restype = ctypes.c_float
         L.orc_height_table.argtypes = [_P, _P]
+        L.orc_visible.restype = ctypes.c_int
+        L.orc_visible.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_float, _P]
         L.orc_visible_at.restype = ctypes.c_int
         L.orc_visible_at.argtypes = [_P, ctypes.c_double, ctypes.c_double, _P]
         L.orc_param_counts.restype = ctypes.c_int
@@ -248,6 +251,14 @@ def height_table(mat):
 def visible(mat, us: float, vs: float, w) -> int:
     """V(x_p, w) of the sample point (us, vs) toward w."""
     return int(lib().orc_visible_at(ctypes.byref(materials([mat])[0]), us, vs, _ptr(_d(w))))
+
+
+def visible_in_table(table, hmax: float, up: float, vp: float, w) -> int:
+    """V of the march over a caller-given float32 height table [th, tw]
+    (16 texels per cell) from the point (up, vp) of the period toward w."""
+    t = np.ascontiguousarray(table, dtype=np.float32)
+    th, tw = t.shape
+    return int(lib().orc_visible(_ptr(t), tw, th, float(hmax), float(up), float(vp), _ptr(_d(w))))
 
 
 def filter_gbuffer(mats: Sequence, g, n_samples: int, seed: int, same_sample: bool = True,

@@ -19,7 +19,7 @@ namespace {
 // samples, where a wave per pixel would leave lanes idle.
 template <bool VIS>
 __device__ inline void filter_pixel_lane(const DevFabric &f, uint64_t seed, uint64_t pixel,
-                                         int n_samples, int side, float inv_side, float u,
+                                         int n_samples, int side, float u,
                                          float v, float r, float3 wi, float3 wo,
                                          const float *tex, const VisFabric &vf, double comp[4])
 {
@@ -27,7 +27,7 @@ __device__ inline void filter_pixel_lane(const DevFabric &f, uint64_t seed, uint
     uint64_t state = seed + ((uint64_t)pixel * (uint64_t)n_samples + 1ull) * kGoldenGamma;
     int kx = 0, ky = 0;
     for (int k = 0; k < n_samples; k++, state += kGoldenGamma) {
-        float2 pos = footprint_sample(splitmix64_mix(state), kx, ky, inv_side, u, v, r);
+        float2 pos = footprint_sample(splitmix64_mix(state), kx, ky, (float)side, u, v, r);
         if (++kx == side) {
             kx = 0;
             ky += 1;
@@ -53,7 +53,7 @@ constexpr int kXcds = 8;
 template <bool VIS, bool LANE>
 __device__ inline void filter_one_pixel(const fabric_gbuffer &g, const DevFabric *__restrict__ fabrics,
                                         int n_fabrics, int64_t p, int n_samples, int side,
-                                        float inv_side, uint64_t seed, int lane, VisArgs vis,
+                                        uint64_t seed, int lane, VisArgs vis,
                                         float *__restrict__ out_rgb, float *__restrict__ out_comp,
                                         unsigned long long *err)
 {
@@ -67,10 +67,10 @@ __device__ inline void filter_one_pixel(const fabric_gbuffer &g, const DevFabric
     if (!fault) {
         const VisFabric vf = VIS ? vis.fab[fid] : VisFabric{0, 0, 0, 0.0f};
         if (LANE)
-            filter_pixel_lane<VIS>(fabrics[fid], seed, (uint64_t)p, n_samples, side, inv_side, u,
+            filter_pixel_lane<VIS>(fabrics[fid], seed, (uint64_t)p, n_samples, side, u,
                                    v, r, wi, wo, vis.tex, vf, comp);
         else
-            filter_pixel_wave<VIS>(fabrics[fid], seed, (uint64_t)p, n_samples, side, inv_side, u,
+            filter_pixel_wave<VIS>(fabrics[fid], seed, (uint64_t)p, n_samples, side, u,
                                    v, r, wi, wo, lane, vis.tex, vf, comp);
     }
     if (LANE || lane == 0) {
@@ -83,10 +83,12 @@ __device__ inline void filter_one_pixel(const fabric_gbuffer &g, const DevFabric
         }
         if (out_rgb) {
             const DevFabric &f = fabrics[fault ? 0 : fid];
+            const float c0 = (float)comp[0], c1 = (float)comp[1], c2 = (float)comp[2],
+                        c3 = (float)comp[3];
             for (int c = 0; c < 3; c++) {
-                double rgb = (double)f.kd[0][c] * comp[0] + (double)f.kd[1][c] * comp[1] +
-                             (double)f.ks[0][c] * comp[2] + (double)f.ks[1][c] * comp[3];
-                out_rgb[c * n + p] = fault ? 0.0f : (float)rgb;
+                const float rgb = f.kd[0][c] * c0 + f.kd[1][c] * c1 + f.ks[0][c] * c2 +
+                                  f.ks[1][c] * c3;
+                out_rgb[c * n + p] = fault ? 0.0f : rgb;
             }
         }
     }
@@ -96,7 +98,7 @@ template <bool VIS>
 __global__ __launch_bounds__(256) void gt_filter_kernel(fabric_gbuffer g,
                                                         const DevFabric *__restrict__ fabrics,
                                                         int n_fabrics, int n_samples, int side,
-                                                        float inv_side, uint64_t seed, VisArgs vis,
+                                                        uint64_t seed, VisArgs vis,
                                                         float *__restrict__ out_rgb,
                                                         float *__restrict__ out_comp,
                                                         unsigned long long *err)
@@ -112,7 +114,7 @@ __global__ __launch_bounds__(256) void gt_filter_kernel(fabric_gbuffer g,
     const int64_t p = (int64_t)block * kWavesPerBlock + wave;
     if (p >= g.n)
         return;
-    filter_one_pixel<VIS, false>(g, fabrics, n_fabrics, p, n_samples, side, inv_side, seed, lane,
+    filter_one_pixel<VIS, false>(g, fabrics, n_fabrics, p, n_samples, side, seed, lane,
                                  vis, out_rgb, out_comp, err);
 }
 
@@ -122,7 +124,7 @@ template <bool VIS>
 __global__ __launch_bounds__(256) void gt_filter_lane_kernel(fabric_gbuffer g,
                                                              const DevFabric *__restrict__ fabrics,
                                                              int n_fabrics, int n_samples, int side,
-                                                             float inv_side, uint64_t seed,
+                                                             uint64_t seed,
                                                              VisArgs vis, float *__restrict__ out_rgb,
                                                              float *__restrict__ out_comp,
                                                              unsigned long long *err)
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(256) void gt_filter_lane_kernel(fabric_gbuffer g,
     const int64_t p = (int64_t)block * blockDim.x + threadIdx.x;
     if (p >= g.n)
         return;
-    filter_one_pixel<VIS, true>(g, fabrics, n_fabrics, p, n_samples, side, inv_side, seed, 0, vis,
+    filter_one_pixel<VIS, true>(g, fabrics, n_fabrics, p, n_samples, side, seed, 0, vis,
                                 out_rgb, out_comp, err);
 }
 
@@ -145,7 +147,7 @@ template <bool VIS>
 __global__ __launch_bounds__(256) void gt_filter_queue_kernel(fabric_gbuffer g,
                                                               const DevFabric *__restrict__ fabrics,
                                                               int n_samples, int side,
-                                                              float inv_side, uint64_t seed,
+                                                              uint64_t seed,
                                                               VisArgs vis, FallbackQueue q,
                                                               float *__restrict__ out_rgb)
 {
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(256) void gt_filter_queue_kernel(fabric_gbuffer g,
     if (k >= *q.count)
         return;
     const int64_t p = __builtin_amdgcn_readfirstlane(q.idx[k]);
-    filter_one_pixel<VIS, false>(g, fabrics, FABRIC_MAX_FABRICS, p, n_samples, side, inv_side,
+    filter_one_pixel<VIS, false>(g, fabrics, FABRIC_MAX_FABRICS, p, n_samples, side,
                                  seed, lane, vis, out_rgb, nullptr, nullptr);
 }
 
@@ -165,7 +167,7 @@ template <bool VIS>
 __global__ __launch_bounds__(256) void gt_filter_queue_lane_kernel(fabric_gbuffer g,
                                                                    const DevFabric *__restrict__ fabrics,
                                                                    int n_samples, int side,
-                                                                   float inv_side, uint64_t seed,
+                                                                   uint64_t seed,
                                                                    VisArgs vis, FallbackQueue q,
                                                                    float *__restrict__ out_rgb)
 {
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(256) void gt_filter_queue_lane_kernel(fabric_gbuffe
     if (k >= (int64_t)*q.count)
         return;
     filter_one_pixel<VIS, true>(g, fabrics, FABRIC_MAX_FABRICS, (int64_t)q.idx[k], n_samples, side,
-                                inv_side, seed, 0, vis, out_rgb, nullptr, nullptr);
+                                seed, 0, vis, out_rgb, nullptr, nullptr);
 }
 
 constexpr int kLaneBelow = 64;   // sample counts below this take one lane per pixel
@@ -283,11 +285,11 @@ hipError_t launch_gt_filter(const fabric_gbuffer &g, const DevFabric *fabrics, i
         blocks = (blocks + kXcds - 1) / kXcds * kXcds;   // padding blocks exit at once
         if (vis.tex)
             hipLaunchKernelGGL(gt_filter_lane_kernel<true>, dim3((unsigned)blocks), dim3(256), 0,
-                               stream, g, fabrics, n_fabrics, n_samples, side, 1.0f / (float)side,
+                               stream, g, fabrics, n_fabrics, n_samples, side,
                                seed, vis, out_rgb, out_comp, err);
         else
             hipLaunchKernelGGL(gt_filter_lane_kernel<false>, dim3((unsigned)blocks), dim3(256), 0,
-                               stream, g, fabrics, n_fabrics, n_samples, side, 1.0f / (float)side,
+                               stream, g, fabrics, n_fabrics, n_samples, side,
                                seed, vis, out_rgb, out_comp, err);
         return hipGetLastError();
     }
@@ -295,11 +297,11 @@ hipError_t launch_gt_filter(const fabric_gbuffer &g, const DevFabric *fabrics, i
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;   // padding blocks exit at once
     if (vis.tex)
         hipLaunchKernelGGL(gt_filter_kernel<true>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
-                           0, stream, g, fabrics, n_fabrics, n_samples, side, 1.0f / (float)side,
+                           0, stream, g, fabrics, n_fabrics, n_samples, side,
                            seed, vis, out_rgb, out_comp, err);
     else
         hipLaunchKernelGGL(gt_filter_kernel<false>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
-                           0, stream, g, fabrics, n_fabrics, n_samples, side, 1.0f / (float)side,
+                           0, stream, g, fabrics, n_fabrics, n_samples, side,
                            seed, vis, out_rgb, out_comp, err);
     return hipGetLastError();
 }
@@ -315,11 +317,11 @@ hipError_t launch_gt_filter_queue(const fabric_gbuffer &g, const DevFabric *fabr
         const int64_t blocks = (g.n + 255) / 256;
         if (vis.tex)
             hipLaunchKernelGGL(gt_filter_queue_lane_kernel<true>, dim3((unsigned)blocks), dim3(256),
-                               0, stream, g, fabrics, n_samples, side, 1.0f / (float)side, seed,
+                               0, stream, g, fabrics, n_samples, side, seed,
                                vis, q, out_rgb);
         else
             hipLaunchKernelGGL(gt_filter_queue_lane_kernel<false>, dim3((unsigned)blocks), dim3(256),
-                               0, stream, g, fabrics, n_samples, side, 1.0f / (float)side, seed,
+                               0, stream, g, fabrics, n_samples, side, seed,
                                vis, q, out_rgb);
         return hipGetLastError();
     }
@@ -327,11 +329,11 @@ hipError_t launch_gt_filter_queue(const fabric_gbuffer &g, const DevFabric *fabr
     if (vis.tex)
         hipLaunchKernelGGL(gt_filter_queue_kernel<true>, dim3((unsigned)blocks),
                            dim3(64 * kWavesPerBlock), 0, stream, g, fabrics, n_samples, side,
-                           1.0f / (float)side, seed, vis, q, out_rgb);
+                           seed, vis, q, out_rgb);
     else
         hipLaunchKernelGGL(gt_filter_queue_kernel<false>, dim3((unsigned)blocks),
                            dim3(64 * kWavesPerBlock), 0, stream, g, fabrics, n_samples, side,
-                           1.0f / (float)side, seed, vis, q, out_rgb);
+                           seed, vis, q, out_rgb);
     return hipGetLastError();
 }
 

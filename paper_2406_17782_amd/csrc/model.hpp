@@ -32,20 +32,19 @@ __device__ inline float u24_mid(uint64_t z)
     return (float)(uint32_t)((z >> 16) & 0xFFFFFFull) * 0x1p-24f;
 }
 
-// Hardware transcendentals on bounded arguments.  v_sin/v_cos take the angle
-// in revolutions; every angle below stays within [-3/8, 3/8] revolutions, far
-// from where their range reduction loses accuracy.
+// Accurate float32 transcendentals (a few ulp) for everything that sets a
+// sample's position or its ply frame: an error there moves the sample by more
+// than the float32 rounding of its position, and at steep yarn slopes and
+// sharp specular lobes one ulp of position already changes a sample's
+// integrand by up to 1e-3 relative.  The hardware approximations (v_sin,
+// v_cos with their absolute error) are therefore not used on this path.
 __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ inline float sin_rev(float t) { return __builtin_amdgcn_sinf(t); }
-__device__ inline float cos_rev(float t) { return __builtin_amdgcn_cosf(t); }
 // tan(x) for |x| <= 1.5 rad (cos x >= 0.07).
-__device__ inline float tan_small(float x)
-{
-    const float t = x * (0.5f / kPi);
-    return sin_rev(t) * rcp(cos_rev(t));
-}
+__device__ inline float tan_small(float x) { return tanf(x); }
 
-// Shirley-Chiu concentric mapping of [0,1)^2 onto the unit disk.
+// Shirley-Chiu concentric mapping of [0,1)^2 onto the unit disk; the angle
+// is pi/4 (b/a) or pi/2 - pi/4 (a/b), evaluated as sin/cos of pi times
+// (b/a)/4 or 1/2 - (a/b)/4 with correctly rounded quotients.
 __device__ inline float2 concentric_disk(float x, float y)
 {
     float a = 2.0f * x - 1.0f, b = 2.0f * y - 1.0f;
@@ -53,10 +52,11 @@ __device__ inline float2 concentric_disk(float x, float y)
         return make_float2(0.0f, 0.0f);
     bool horiz = fabsf(a) > fabsf(b);
     float rad = horiz ? a : b;
-    // phi = pi/4 (b/a) or pi/2 - pi/4 (a/b), here in revolutions
-    float q = horiz ? b * rcp(a) : a * rcp(b);
-    float phi = horiz ? 0.125f * q : 0.25f - 0.125f * q;
-    return make_float2(rad * cos_rev(phi), rad * sin_rev(phi));
+    float q = horiz ? b / a : a / b;
+    float phi = horiz ? 0.25f * q : 0.5f - 0.25f * q;
+    float sn, cs;
+    sincospif(phi, &sn, &cs);
+    return make_float2(rad * cs, rad * sn);
 }
 
 // x reduced into [0, period) (period a small positive integer as float).
@@ -280,11 +280,10 @@ __device__ inline SampleVal eval_surface_point(const DevFabric &f, float us, flo
 
 // Footprint sample in stratum (kx, ky) of a side x side grid, jittered by the
 // SplitMix64 draw z; position in cells.
-__device__ inline float2 footprint_sample(uint64_t z, int kx, int ky, float inv_side, float u,
+__device__ inline float2 footprint_sample(uint64_t z, int kx, int ky, float side, float u,
                                           float v, float r)
 {
-    float2 d = concentric_disk(((float)kx + u24_hi(z)) * inv_side,
-                               ((float)ky + u24_mid(z)) * inv_side);
+    float2 d = concentric_disk(((float)kx + u24_hi(z)) / side, ((float)ky + u24_mid(z)) / side);
     return make_float2(fmaf(r, d.x, u), fmaf(r, d.y, v));
 }
 
@@ -303,7 +302,7 @@ __device__ inline bool pixel_fault(int fid, int n_fabrics, float u, float v, flo
 // butterfly order.  Every lane returns the four components.
 template <bool VIS>
 __device__ inline void filter_pixel_wave(const DevFabric &f, uint64_t seed, uint64_t pixel,
-                                         int n_samples, int side, float inv_side, float u,
+                                         int n_samples, int side, float u,
                                          float v, float r, float3 wi, float3 wo, int lane,
                                          const float *tex, const VisFabric &vf, double comp[4])
 {
@@ -316,7 +315,7 @@ __device__ inline void filter_pixel_wave(const DevFabric &f, uint64_t seed, uint
     const int dky = 64 / side, dkx = 64 - dky * side;
     int ky = lane / side, kx = lane - ky * side;
     for (int k = lane; k < n_samples; k += 64, state += step) {
-        float2 pos = footprint_sample(splitmix64_mix(state), kx, ky, inv_side, u, v, r);
+        float2 pos = footprint_sample(splitmix64_mix(state), kx, ky, (float)side, u, v, r);
         kx += dkx;
         ky += dky;
         if (kx >= side) {

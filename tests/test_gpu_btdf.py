@@ -49,7 +49,7 @@ def test_filter_transmission_matches_oracle(fab, pkg, orc, torch):
     comp = comp.cpu().numpy()
     o_comp, _, flagged, fault = orc.filter_gbuffer(mats, g, 256, 191, same_sample=True)
     assert not fault.any()
-    print(assert_filter_parity(comp, o_comp, flagged))
+    print(assert_filter_parity(comp, o_comp, flagged, 256))
     # Most pixels lit from below transmit something (not all: a footprint
     # may lie in a hole, or on plies tilted away from the light).
     below = g.wi_z < 0
@@ -65,7 +65,7 @@ def test_filter_transmission_with_visibility(fab, pkg, orc, torch):
     d = pkg.DeviceGBuffer.from_host(g)
     _, comp = fab.gt_filtered(d, 64, 193)
     o_comp, _, flagged, _ = orc.filter_gbuffer(mats, g, 64, 193, same_sample=True, visibility=True)
-    print(assert_filter_parity_vis(comp.cpu().numpy(), o_comp, flagged))
+    print(assert_filter_parity_vis(comp.cpu().numpy(), o_comp, flagged, 64))
 
 
 def test_shading_transmission_matches_oracle(fab, pkg, orc, torch):

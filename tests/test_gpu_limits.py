@@ -49,7 +49,7 @@ def test_max_fabrics_shading(fab, pkg, orc, torch):
     _, comp = fab.gt_filtered(d, 64, 125)
     o_comp, _, flagged, _ = orc.filter_gbuffer(mats, g.subset(idx), 64, 125, same_sample=True,
                                                pixel_index=idx)
-    print(assert_filter_parity(comp.cpu().numpy()[:, idx], o_comp, flagged))
+    print(assert_filter_parity(comp.cpu().numpy()[:, idx], o_comp, flagged, 64))
 
 
 def test_max_samples_filter(fab, pkg, orc, torch):
@@ -64,7 +64,7 @@ def test_max_samples_filter(fab, pkg, orc, torch):
     n_s = pkg.FABRIC_MAX_SAMPLES
     _, comp = fab.gt_filtered(d, n_s, 132)
     o_comp, _, flagged, _ = orc.filter_gbuffer(mats, g, n_s, 132, same_sample=True)
-    print(assert_filter_parity(comp.cpu().numpy(), o_comp, flagged))
+    print(assert_filter_parity(comp.cpu().numpy(), o_comp, flagged, n_s))
     with pytest.raises(pkg.FabricError):
         fab.gt_filtered(d, 129 * 129, 132)
 
@@ -87,4 +87,4 @@ def test_tiny_frames(fab, pkg, orc, torch, n):
         assert rel_norm_err(rgb, orgb) < bound, prec
     _, comp = fab.gt_filtered(d, 16, 143)
     o_comp, _, flagged, _ = orc.filter_gbuffer(mats, g, 16, 143, same_sample=True)
-    assert_filter_parity(comp.cpu().numpy(), o_comp, flagged)
+    assert_filter_parity(comp.cpu().numpy(), o_comp, flagged, 16)

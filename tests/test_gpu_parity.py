@@ -2,9 +2,9 @@
 
 Footprint filter: same samples (SplitMix64 jitter, concentric map) on both
 sides, the oracle rounding the sample position to float32 before
-classification; at least 99.9 % of the pixels agree to 1e-4 of their largest
-component, and no pixel away from a classification edge deviates by more
-than 2e-3.
+classification; every pixel with no sample near a classification edge agrees
+to 1e-4 of its largest component, and a pixel with k of its N samples near
+an edge to 1e-4 + k / N.
 Decoder FP32: norm-wise 1e-5 (elementwise 1e-4); BF16 / FP16: bounds derived
 from the operand unit roundoff (see the tests).  Gradients: 1e-4 norm-wise per
 tensor against the oracle's FP64 backprop.
@@ -60,8 +60,8 @@ def test_gt_filter_plain128_all_pixels(fab, pkg, orc, torch):
     torch.cuda.synchronize()
     o_comp, o_rgb, flagged, fault = orc.filter_gbuffer(mats, g, 64, seed, same_sample=True)
     assert fault.sum() == 0
-    print(assert_filter_parity(comp.cpu().numpy(), o_comp, flagged))
-    assert_filter_parity(rgb.cpu().numpy(), o_rgb, flagged)
+    print(assert_filter_parity(comp.cpu().numpy(), o_comp, flagged, 64))
+    assert_filter_parity(rgb.cpu().numpy(), o_rgb, flagged, 64)
     assert fab.error_count() == 0
 
 
@@ -74,8 +74,8 @@ def test_gt_filter_eight_fabrics_ragged(fab, pkg, orc, torch):
     rgb, comp = fab.gt_filtered(dev(pkg, g), 256, 99)
     torch.cuda.synchronize()
     o_comp, o_rgb, flagged, _ = orc.filter_gbuffer(mats, g, 256, 99, same_sample=True)
-    print(assert_filter_parity(comp.cpu().numpy(), o_comp, flagged))
-    assert_filter_parity(rgb.cpu().numpy(), o_rgb, flagged)
+    print(assert_filter_parity(comp.cpu().numpy(), o_comp, flagged, 256))
+    assert_filter_parity(rgb.cpu().numpy(), o_rgb, flagged, 256)
 
 
 def test_gt_filter_1080p_sampled(fab, pkg, orc, torch):
@@ -91,7 +91,7 @@ def test_gt_filter_1080p_sampled(fab, pkg, orc, torch):
     o_comp, o_rgb, flagged, _ = orc.filter_gbuffer(mats, sub, 256, 4242, same_sample=True,
                                                    pixel_index=idx)
     gc = comp.cpu().numpy()[:, idx]
-    print(assert_filter_parity(gc, o_comp, flagged))
+    print(assert_filter_parity(gc, o_comp, flagged, 256))
 
 
 def test_gt_filter_deterministic_and_seeded(fab, pkg, torch):
@@ -118,8 +118,8 @@ def test_gt_filter_below_64_samples(fab, pkg, orc, torch, n_samples):
     rgb, comp = fab.gt_filtered(dev(pkg, g), n_samples, 321)
     torch.cuda.synchronize()
     o_comp, o_rgb, flagged, _ = orc.filter_gbuffer(mats, g, n_samples, 321, same_sample=True)
-    print(assert_filter_parity(comp.cpu().numpy(), o_comp, flagged))
-    assert_filter_parity(rgb.cpu().numpy(), o_rgb, flagged)
+    print(assert_filter_parity(comp.cpu().numpy(), o_comp, flagged, n_samples))
+    assert_filter_parity(rgb.cpu().numpy(), o_rgb, flagged, n_samples)
     assert fab.error_count() == 0
 
 
@@ -134,7 +134,7 @@ def test_gt_filter_1080p_16_samples_sampled(fab, pkg, orc, torch):
     idx = fi.subset_indices(g.n, 0.002, 78)
     o_comp, _, flagged, _ = orc.filter_gbuffer(mats, g.subset(idx), 16, 778, same_sample=True,
                                                pixel_index=idx)
-    print(assert_filter_parity(comp.cpu().numpy()[:, idx], o_comp, flagged))
+    print(assert_filter_parity(comp.cpu().numpy()[:, idx], o_comp, flagged, 16))
 
 
 # ---------------------------------------------------------------------------

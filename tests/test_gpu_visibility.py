@@ -49,7 +49,7 @@ def test_filter_visibility_matches_oracle(fab, pkg, orc, torch):
     _, c1 = fab.gt_filtered(d, 256, 174)
     c0, c1 = c0.cpu().numpy(), c1.cpu().numpy()
     o_comp, _, flagged, _ = orc.filter_gbuffer(mats, g, 256, 174, same_sample=True, visibility=True)
-    print(assert_filter_parity_vis(c1, o_comp, flagged))
+    print(assert_filter_parity_vis(c1, o_comp, flagged, 256))
     changed = np.abs(c1 - c0).max(axis=0) > 1e-3 * np.abs(c0).max(axis=0)
     print("pixels changed by visibility", changed.mean())
     assert changed.mean() > 0.05
@@ -67,7 +67,7 @@ def test_filter_visibility_below_64_samples(fab, pkg, orc, torch):
     fab.set_visibility(True)
     _, comp = fab.gt_filtered(pkg.DeviceGBuffer.from_host(g), 16, 183)
     o_comp, _, flagged, _ = orc.filter_gbuffer(mats, g, 16, 183, same_sample=True, visibility=True)
-    print(assert_filter_parity_vis(comp.cpu().numpy(), o_comp, flagged))
+    print(assert_filter_parity_vis(comp.cpu().numpy(), o_comp, flagged, 16))
 
 
 def test_flat_fabrics_unchanged(fab, pkg, torch):
@@ -94,7 +94,7 @@ def test_visibility_1080p_sampled(fab, pkg, orc, torch):
     idx = fi.subset_indices(g.n, 0.002, 179)
     o_comp, _, flagged, _ = orc.filter_gbuffer(mats, g.subset(idx), 256, 178, same_sample=True,
                                                pixel_index=idx, visibility=True)
-    print(assert_filter_parity_vis(comp.cpu().numpy()[:, idx], o_comp, flagged))
+    print(assert_filter_parity_vis(comp.cpu().numpy()[:, idx], o_comp, flagged, 256))
 
 
 def test_hybrid_fallback_uses_visibility(fab, pkg, torch):

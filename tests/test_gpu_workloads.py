@@ -47,7 +47,7 @@ def test_4k_64_fabrics_sampled(fab, pkg, orc, torch):
     idx = fi.subset_indices(g.n, 0.0025, 5)
     sub = g.subset(idx)
     o_comp, _, flagged, _ = orc.filter_gbuffer(mats, sub, 256, 31, same_sample=True, pixel_index=idx)
-    print(assert_filter_parity(comp.cpu().numpy()[:, idx], o_comp, flagged))
+    print(assert_filter_parity(comp.cpu().numpy()[:, idx], o_comp, flagged, 256))
     z = orc.encoder(params[fi.N_DECODER_PARAMS:].astype(np.float64), mats)
     _, orgb = orc.decoder_gbuffer(params[: fi.N_DECODER_PARAMS], z, mats, sub)
     e32 = rel_norm_err(rgb32.cpu().numpy()[:, idx], orgb)

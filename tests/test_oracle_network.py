@@ -152,6 +152,41 @@ def test_encoder_input_layout(orc):
     assert np.all(xb[0:512:2] + xb[1:512:2] == 1)
 
 
+def test_encoder_wiring_with_hand_built_weights(orc):
+    """The encoder's wiring traced through hand-built weights: e1 picks a
+    one-hot cell and a scaled yarn scalar; the residual block adds its
+    branch to e1 before the last ReLU (a negative c3 lowers a positive skip,
+    which a skip added after the ReLU would not); the branch's inner ReLU
+    shuts a negative pre-activation; z is linear."""
+    sl = enc_slices()
+    Q = np.zeros(fi.N_PARAMS)
+    E1 = np.zeros((128, 524)); c1 = np.zeros(128)
+    E1[0, 0] = 1.0             # cell (0, 0) of the plain weave has the warp on top
+    E1[1, 512] = 1.0           # warp roughness, min-max scaled
+    E1[2, 512] = -1.0          # shut by e1's ReLU
+    c1[3] = 0.75
+    E2 = np.zeros((128, 128)); c2 = np.zeros(128)
+    E3 = np.zeros((128, 128)); c3 = np.zeros(128)
+    c3[3] = -0.5               # skip before the last ReLU: relu(0.75 - 0.5)
+    E2[4, 0] = -1.0; E3[4, 4] = 1.0                 # relu(-1) = 0 in the branch
+    E2[5, 0] = 2.0; E3[5, 5] = 3.0                  # 3 relu(2 e1[0]) = 6
+    E2[6, 0] = 0.5; c2[6] = -1.0; E3[6, 6] = 1.0; c3[6] = 1.0   # relu(1 + relu(-0.5))
+    E4 = np.zeros((32, 128)); c4 = np.zeros(32)
+    for k in range(7):
+        E4[k, k] = 1.0
+    E4[7, 1] = -2.0            # z is linear: a negative output passes
+    c4[31] = 0.125
+    for name, arr in (("E1", E1), ("c1", c1), ("E2", E2), ("c2", c2), ("E3", E3), ("c3", c3),
+                      ("E4", E4), ("c4", c4)):
+        Q[sl[name]] = arr.ravel()
+    m = fi.uniform_material(fi.pattern_plain(), alpha=0.55)
+    z = orc.encoder(Q[NDEC:], [m])[0]
+    expect = np.zeros(32)
+    expect[:8] = [1.0, 0.5, 0.0, 0.25, 0.0, 6.0, 1.0, -1.0]
+    expect[31] = 0.125
+    assert z == pytest.approx(expect, abs=1e-7)
+
+
 def test_encoder_matches_numpy_chain(orc):
     params = fi.init_params(31, bias_scale=0.1).astype(np.float64)
     Q = params[NDEC:]
