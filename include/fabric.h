@@ -75,6 +75,8 @@ typedef enum {
 #define FABRIC_N_ENCODER_PARAMS 104352
 #define FABRIC_N_PARAMS (FABRIC_N_DECODER_PARAMS + FABRIC_N_ENCODER_PARAMS)
 #define FABRIC_MAX_SAMPLES 16384
+/* Largest frame of fabric_shade_gbuffer_noalloc (2^22 pixels). */
+#define FABRIC_NOALLOC_MAX_PIXELS 4194304
 #define FABRIC_PAPER_LATENT 64
 #define FABRIC_N_PAPER_DECODER_PARAMS 27076
 
@@ -254,6 +256,25 @@ fabric_status fabric_paper_shade(fabric_ctx *ctx, const fabric_gbuffer *g, fabri
 fabric_status fabric_shade_gbuffer(fabric_ctx *ctx, const fabric_gbuffer *g, fabric_prec prec,
                                    int32_t fallback_samples, uint64_t seed, float *out_rgb,
                                    void *stream);
+
+/* fabric_shade_gbuffer for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, same kernels and bitwise the same results as
+ * fabric_shade_gbuffer, but the hybrid fallback queue (out-of-range mask,
+ * scan offsets, count, pixel indices) lives in a fixed device array of the
+ * library (20 MiB per GPU, held until the process ends) instead of context
+ * memory, and the call allocates nothing.  Nothing in the array needs to
+ * start at zero: each call rewrites the parts it reads.  Every call on one
+ * GPU shares that GPU's array, so calls that overlap on one GPU (any
+ * contexts, any streams) race and must be serialised by the caller.
+ * Errors: as fabric_shade_gbuffer; E_RANGE when n exceeds
+ * FABRIC_NOALLOC_MAX_PIXELS; E_STATE when visibility is on with fallback
+ * and the height texels of the current fabric table have not been built yet
+ * (any call of fabric_gt_filtered or fabric_shade_gbuffer with fallback
+ * builds them). */
+fabric_status fabric_shade_gbuffer_noalloc(fabric_ctx *ctx, const fabric_gbuffer *g,
+                                           fabric_prec prec, int32_t fallback_samples,
+                                           uint64_t seed, float *out_rgb, void *stream);
 
 /* Footprint-filtered analytic shading (Eq. (3)-(5), V = 1; components of
  * Eq. (7)).  Pixel p's footprint is the disk of radius radius[p] about

@@ -28,8 +28,8 @@ __all__ = [
     "fabric_set_visibility", "fabric_paper_prepare", "fabric_paper_shade",
     "fabric_paper_train_step", "fabric_paper_loss_grad", "fabric_paper_get_params",
     "fabric_paper_set_footprint_encoding", "fabric_paper_set_spatial_fusion", "FABRIC_PAPER_LATENT", "FABRIC_N_PAPER_DECODER_PARAMS",
-    "fabric_shade_gbuffer", "fabric_gt_filtered", "fabric_decoder_forward",
-    "fabric_decoder_backward", "fabric_encoder_forward", "fabric_encoder_backward",
+    "fabric_shade_gbuffer", "fabric_shade_gbuffer_noalloc", "fabric_gt_filtered",
+    "fabric_decoder_forward", "fabric_decoder_backward", "fabric_encoder_forward", "fabric_encoder_backward",
     "fabric_make_batch", "fabric_loss_grad", "fabric_train_step", "fabric_get_params", "fabric_set_params",
     "fabric_get_latents", "fabric_save", "fabric_load", "fabric_error_count",
 ]
@@ -174,6 +174,15 @@ def fabric_shade_gbuffer(ctx, g: DeviceGBuffer, prec: int, fallback_samples: int
     check(_abi.lib().fabric_shade_gbuffer(ctx, ctypes.byref(gs), prec, fallback_samples,
                                           ctypes.c_uint64(seed), _dptr(out_rgb), _stream(stream)),
           "fabric_shade_gbuffer")
+
+
+def fabric_shade_gbuffer_noalloc(ctx, g: DeviceGBuffer, prec: int, fallback_samples: int,
+                                 seed: int, out_rgb, stream=None) -> None:
+    gs = g.c_struct()
+    check(_abi.lib().fabric_shade_gbuffer_noalloc(ctx, ctypes.byref(gs), prec, fallback_samples,
+                                                  ctypes.c_uint64(seed), _dptr(out_rgb),
+                                                  _stream(stream)),
+          "fabric_shade_gbuffer_noalloc")
 
 
 def fabric_gt_filtered(ctx, g: DeviceGBuffer, n_samples: int, seed: int, out_rgb=None,

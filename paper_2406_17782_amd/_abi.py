@@ -22,6 +22,7 @@ FABRIC_FP8_E4M3 = 3
 
 FABRIC_MAX_FABRICS = 256
 FABRIC_MAX_SAMPLES = 16384
+FABRIC_NOALLOC_MAX_PIXELS = 4194304
 FABRIC_LATENT = 32
 FABRIC_N_DECODER_PARAMS = 13572
 FABRIC_PAPER_LATENT = 64
@@ -66,8 +67,8 @@ EXPORTS = [
     "fabric_lerp_latents", "fabric_set_visibility", "fabric_paper_prepare", "fabric_paper_shade",
     "fabric_paper_train_step", "fabric_paper_loss_grad", "fabric_paper_get_params",
     "fabric_paper_set_footprint_encoding", "fabric_paper_set_spatial_fusion",
-    "fabric_shade_gbuffer", "fabric_gt_filtered", "fabric_decoder_forward",
-    "fabric_decoder_backward", "fabric_encoder_forward", "fabric_encoder_backward",
+    "fabric_shade_gbuffer", "fabric_shade_gbuffer_noalloc", "fabric_gt_filtered",
+    "fabric_decoder_forward", "fabric_decoder_backward", "fabric_encoder_forward", "fabric_encoder_backward",
     "fabric_make_batch", "fabric_loss_grad", "fabric_train_step", "fabric_get_params", "fabric_set_params",
     "fabric_get_latents", "fabric_save", "fabric_load", "fabric_error_count",
 ]
@@ -110,6 +111,8 @@ def _declare(L):
     L.fabric_shade_gbuffer.argtypes = [_P, ctypes.POINTER(fabric_gbuffer), ctypes.c_int,
                                        ctypes.c_int32, ctypes.c_uint64, _P, _P]
     L.fabric_shade_gbuffer.restype = _S
+    L.fabric_shade_gbuffer_noalloc.argtypes = L.fabric_shade_gbuffer.argtypes
+    L.fabric_shade_gbuffer_noalloc.restype = _S
     L.fabric_gt_filtered.argtypes = [_P, ctypes.POINTER(fabric_gbuffer), ctypes.c_int32,
                                      ctypes.c_uint64, _P, _P, _P]
     L.fabric_gt_filtered.restype = _S

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -65,7 +66,60 @@ struct fabric_ctx {
     TrainScratch train;
 };
 
+// Fixed device memory of fabric_shade_gbuffer_noalloc: the fallback queue
+// (out-of-range mask, scan offsets and block sums, count, pixel indices) of
+// frames up to FABRIC_NOALLOC_MAX_PIXELS pixels, 256-byte aligned parts.
+// Each GPU the library runs on holds its own copy until the process ends;
+// every call on that GPU shares it.
+constexpr size_t kNoAllocScratchBytes = (size_t)20 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
+
+// Device address of `scratch` per device (the array's host-side name is not
+// a device address), resolved by fabric_create with the device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t resolve_scratch(int device)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (device < 0 || device >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    if (g_scratch_ptr[device])
+        return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess)
+        return e;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+void *scratch_of(int device)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// The fallback queue of an n-pixel frame laid out from `base`; returns the
+// bytes it spans.
+size_t carve_queue(unsigned char *base, int64_t n, FallbackQueue *q)
+{
+    size_t off = 0;
+    q->mask = (uint16_t *)(base + off);
+    off = align256(off + (size_t)((n + 31) / 32) * 2 * sizeof(uint16_t));
+    q->offsets = (uint32_t *)(base + off);
+    off = align256(off + queue_offset_entries(n) * sizeof(uint32_t));
+    q->count = (uint32_t *)(base + off);
+    off = align256(off + sizeof(uint32_t));
+    q->idx = (int32_t *)(base + off);
+    off = align256(off + (size_t)n * sizeof(int32_t));
+    return off;
+}
 
 struct DeviceGuard {
     int prev = -1;
@@ -263,16 +317,12 @@ bool perfect_square(int n)
 
 // The packed decoder of precision prec for the context's current parameters
 // (an FP8 image is calibrated on the encoded fabrics, so it also follows them).
+// The images of every precision are allocated by fabric_create; this only
+// repacks (a kernel launch, no allocation).
 fabric_status ensure_image(fabric_ctx *ctx, int prec, hipStream_t stream)
 {
-    if (!ctx->image[prec]) {
-        const size_t bytes = shade_image_bytes(prec);
-        if (bytes == 0)
-            return FABRIC_E_INVAL;
-        fabric_status st = from_hip(hipMalloc(&ctx->image[prec], bytes));
-        if (st != FABRIC_OK)
-            return st;
-    }
+    if (!ctx->image[prec])
+        return FABRIC_E_STATE;
     const bool fp8 = prec == FABRIC_FP8_E4M3;
     if (ctx->image_version[prec] != ctx->weights_version ||
         (fp8 && ctx->image_serial[prec] != ctx->encode_serial)) {
@@ -513,6 +563,9 @@ fabric_status fabric_create(fabric_ctx **out, int device, uint64_t seed)
         const size_t img = decoder_image_bytes(FABRIC_FP32);   // the largest image
         st = from_hip(hipMalloc(&ctx->tmp_image, img));
     }
+    for (int prec = 0; prec < 4 && st == FABRIC_OK; prec++)
+        st = from_hip(hipMalloc(&ctx->image[prec], shade_image_bytes(prec)));
+    if (st == FABRIC_OK) st = from_hip(resolve_scratch(device));
     if (st == FABRIC_OK) {
         std::vector<float> p;
         init_params(seed, p);
@@ -729,6 +782,45 @@ fabric_status fabric_shade_gbuffer(fabric_ctx *ctx, const fabric_gbuffer *g, fab
     if (st != FABRIC_OK)
         return st;
     const FallbackQueue q{ctx->queue_mask, ctx->queue_offsets, ctx->queue_count, ctx->queue_idx};
+    return from_hip(launch_decode(prec, false, *g, ctx->fabrics, ctx->n_mats, ctx->cfold,
+                                  ctx->image[prec], fallback_samples, seed, vis, q, out_rgb,
+                                  ctx->err, s));
+}
+
+fabric_status fabric_shade_gbuffer_noalloc(fabric_ctx *ctx, const fabric_gbuffer *g,
+                                           fabric_prec prec, int32_t fallback_samples,
+                                           uint64_t seed, float *out_rgb, void *stream)
+{
+    if (!ctx || !valid_gbuffer(g) || (g->n > 0 && !out_rgb))
+        return FABRIC_E_INVAL;
+    if (!supported_prec(prec))
+        return FABRIC_E_INVAL;
+    if (fallback_samples < 0 || (fallback_samples > 0 && !perfect_square(fallback_samples)))
+        return FABRIC_E_INVAL;
+    if (g->n > FABRIC_NOALLOC_MAX_PIXELS)
+        return FABRIC_E_RANGE;
+    if (ctx->n_mats == 0 || ctx->encoded_version != ctx->weights_version)
+        return FABRIC_E_STATE;
+    // The height texels are built (and allocated) by the other entry points.
+    if (fallback_samples > 0 && ctx->visibility &&
+        (!ctx->vis_tex || ctx->vis_serial != ctx->table_serial))
+        return FABRIC_E_STATE;
+    if (g->n == 0)
+        return FABRIC_OK;
+    unsigned char *base = (unsigned char *)scratch_of(ctx->device);
+    if (!base)
+        return FABRIC_E_STATE;
+    FallbackQueue q{nullptr, nullptr, nullptr, nullptr};
+    if (carve_queue(base, g->n, &q) > kNoAllocScratchBytes)
+        return FABRIC_E_RANGE;
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = as_stream(stream);
+    fabric_status st = ensure_image(ctx, prec, s);
+    if (st != FABRIC_OK)
+        return st;
+    VisArgs vis{nullptr, nullptr};
+    if (fallback_samples > 0 && ctx->visibility)
+        vis = VisArgs{ctx->vis_tex, ctx->vis_fab};
     return from_hip(launch_decode(prec, false, *g, ctx->fabrics, ctx->n_mats, ctx->cfold,
                                   ctx->image[prec], fallback_samples, seed, vis, q, out_rgb,
                                   ctx->err, s));

@@ -47,6 +47,7 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     assert lib.fabric_create(None, 0, 0) == 1
     assert lib.fabric_encode(None, None, 1, None) == 1
     assert lib.fabric_shade_gbuffer(None, None, 0, 0, 0, None, None) == 1
+    assert lib.fabric_shade_gbuffer_noalloc(None, None, 0, 0, 0, None, None) == 1
     assert lib.fabric_gt_filtered(None, None, 64, 0, None, None, None) == 1
     assert lib.fabric_train_step(None, None, None, None, None, None) == 1
     assert lib.fabric_error_count(None, 0) == -1
@@ -107,5 +108,5 @@ def test_binding_constants_match_header():
     defs = dict(re.findall(r"#define (FABRIC_\w+) (\d+)\s", text))
     for name in ("FABRIC_MAX_FABRICS", "FABRIC_MAX_SAMPLES", "FABRIC_LATENT",
                  "FABRIC_N_DECODER_PARAMS", "FABRIC_N_ENCODER_PARAMS", "FABRIC_PAPER_LATENT",
-                 "FABRIC_N_PAPER_DECODER_PARAMS"):
+                 "FABRIC_N_PAPER_DECODER_PARAMS", "FABRIC_NOALLOC_MAX_PIXELS"):
         assert getattr(_abi, name) == int(defs[name]), name
