@@ -12,8 +12,9 @@
 // between layers.
 //
 // With fallback routing, pixels outside the network's training range are
-// shaded in the same launch by the analytic footprint filter: the wave that
-// owns the tile evaluates them one at a time with all 64 lanes.
+// shaded in the same call by the analytic footprint filter: the shading
+// launch marks them (one bit per pixel), a fixed-order compaction queues
+// them in pixel order, and a filter launch shades the queue.
 #include "mlp_tile.hpp"
 #include "mlp_tile32.hpp"
 #include "shade.hpp"
@@ -121,8 +122,9 @@ template <int P, bool HYBRID>
 __global__ __launch_bounds__(256) void decode32_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ frags,
-    const f32x4 *__restrict__ bias2, const f32x4 *__restrict__ bias4, FallbackQueue q,
-    float *__restrict__ out, unsigned long long *err, int n_tiles)
+    const f32x4 *__restrict__ bias2, const f32x4 *__restrict__ bias4,
+    const float *__restrict__ cf_scale, FallbackQueue q, float *__restrict__ out,
+    unsigned long long *err, int n_tiles)
 {
     using T = Tile32<P>;
     using Frag = typename T::Frag;
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(256) void decode32_kernel(
     for (int k = threadIdx.x; k < 2 * 64 * 4; k += blockDim.x)
         s_b2[k] = bias2[k];
     for (int k = threadIdx.x; k < n_fabrics * 64; k += blockDim.x)
-        s_cf[k] = cfold[k];
+        s_cf[k] = cfold[k] * cf_scale[k & 63];
     stage_fabric_consts(fabrics, n_fabrics, s_fc);
     __syncthreads();
 
@@ -190,12 +192,12 @@ __global__ __launch_bounds__(256) void decode32_kernel(
             }
         // L3 extra inputs: group 0 wi, group 1 (wo.x, wo.y, 1 for the bias).
         const float x2 = grp ? 1.0f : cur.xz;
-        f32x16 y = T::forward(getA, cf, b2, s1, cur.x0, cur.x1, x2);
+        const f32x4 y = T::forward(getA, cf, b2, b4, s1, cur.x0, cur.x1, x2);
 
         // Lanes 0..31 hold y[0..3] of pixel tile*32 + lane.
         if (grp == 0 && valid && !oor) {
             float rgb[3];
-            compose_rgb<FM>(y[0] + b4[0], y[1] + b4[1], y[2] + b4[2], y[3] + b4[3], fc, rgb);
+            compose_rgb<FM>(y[0], y[1], y[2], y[3], fc, rgb);
 #pragma unroll
             for (int c = 0; c < 3; c++)
                 plane_store(out, c * n + p, fault ? 0.0f : rgb[c]);
@@ -218,14 +220,67 @@ __global__ __launch_bounds__(256) void decode32_kernel(
     }
 }
 
-// Image of the 32-pixel layout from FP32 decoder parameters.
+// Scale exponents of the 32-pixel layout's hidden neurons (BF16; zero for
+// FP16): e such that 2^e exceeds an upper bound U of the neuron's
+// pre-activation over every input, U from the weights as the image uses
+// them and the encoded fabrics' first-layer biases:
+//   U1_i = max_f c_f,i + sum_j |W1s_ij|          (spatial features in [-1, 1])
+//   U2_i = b2_i + sum_j max(W2_ij, 0) max(U1_j, 0)            (h1 >= 0)
+//   U3_i = b3_i + sum_j max(W3_ij, 0) max(U2_j, 0) + sum_a |W3a_ia|
+// (the angular inputs are unit-vector components), with a margin of 1 %
+// for the rounding of weights and sums.  A neuron whose bound is not
+// positive is never active (e = 0).  One block of 64 threads.
 template <int P>
-__global__ void pack_decoder32_kernel(const float *__restrict__ params,
+__global__ __launch_bounds__(64) void scale32_kernel(const float *__restrict__ params,
+                                                     const float *__restrict__ cfold, int n_fabrics,
+                                                     int *__restrict__ exps, float *__restrict__ cf_scale)
+{
+    __shared__ float U[64];
+    const int i = threadIdx.x;
+    auto expo = [](float u) {
+        if (!(u > 0.0f) || P != FABRIC_BF16)
+            return 0;
+        int e = (int)floorf(log2f(1.01f * u)) + 1;
+        return min(max(e, -60), 60);
+    };
+    float c = -INFINITY;
+    for (int f = 0; f < n_fabrics; f++)
+        c = fmaxf(c, cfold[f * 64 + i]);
+    float u = c;
+    for (int j = 0; j < kFeat; j++)
+        u += fabsf(params[kOffW1 + i * 72 + kLatent + j]);
+    int e = expo(u);
+    exps[i] = e;
+    cf_scale[i] = ldexpf(1.0f, -e);
+    U[i] = fmaxf(u, 0.0f);
+    __syncthreads();
+    u = params[kOffB2 + i];
+    for (int j = 0; j < 64; j++)
+        u += fmaxf(params[kOffW2 + i * 64 + j], 0.0f) * U[j];
+    __syncthreads();
+    U[i] = fmaxf(u, 0.0f);
+    exps[64 + i] = expo(u);
+    __syncthreads();
+    u = params[kOffB3 + i];
+    for (int j = 0; j < 64; j++)
+        u += fmaxf(params[kOffW3 + i * 69 + j], 0.0f) * U[j];
+    for (int a = 0; a < 5; a++)
+        u += fabsf(params[kOffW3 + i * 69 + 64 + a]);
+    exps[128 + i] = expo(u);
+}
+
+// Image of the 32-pixel layout from FP32 decoder parameters and the scale
+// exponents of scale32_kernel: hidden neuron i of layer l is scaled by
+// 2^-e_l,i (its weights, bias and, for L1, c_f) and the next layer's
+// weights of that input by 2^e_l,i.
+template <int P>
+__global__ void pack_decoder32_kernel(const float *__restrict__ params, const int *__restrict__ exps,
                                       typename Mfma<P>::Frag *__restrict__ frags,
                                       f32x4 *__restrict__ bias2, f32x4 *__restrict__ bias4)
 {
     using M = Mfma<P>;
     using S = DecShape32<8>;
+    const int *e1 = exps, *e2 = exps + 64, *e3 = exps + 128;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < S::NFRAG * 64) {
         const int fr = idx / 64, lane = idx % 64, row = lane & 31, grp = lane >> 5;
@@ -241,19 +296,32 @@ __global__ void pack_decoder32_kernel(const float *__restrict__ params,
             float w = 0.0f;
             if (layer == 1) {
                 const int feat = l1_feature32(grp, c);
-                if (feat >= 0) w = params[kOffW1 + m * 72 + kLatent + feat];
+                if (feat >= 0) w = ldexpf(params[kOffW1 + m * 72 + kLatent + feat], -e1[m]);
             } else if (layer == 2) {
-                if (c < kChain32) w = params[kOffW2 + m * 64 + chain32_neuron(grp, c)];
+                if (c < kChain32) {
+                    const int nj = chain32_neuron(grp, c);
+                    w = ldexpf(params[kOffW2 + m * 64 + nj], e1[nj] - e2[m]);
+                }
             } else if (layer == 3) {
                 if (c < kChain32) {
-                    w = params[kOffW3 + m * 69 + chain32_neuron(grp, c)];
+                    const int nj = chain32_neuron(grp, c);
+                    w = ldexpf(params[kOffW3 + m * 69 + nj], e2[nj] - e3[m]);
                 } else if (c < kL3Slots32) {
                     const int a = l3_extra32(grp, c - kChain32);
-                    if (a == 5) w = params[kOffB3 + m];
-                    else if (a >= 0) w = params[kOffW3 + m * 69 + 64 + a];
+                    if (a == 5) w = ldexpf(params[kOffB3 + m], -e3[m]);
+                    else if (a >= 0) w = ldexpf(params[kOffW3 + m * 69 + 64 + a], -e3[m]);
                 }
             } else {
-                if (m < 4 && c < kChain32) w = params[kOffW4 + m * 64 + chain32_neuron(grp, c)];
+                // 16x16x32 operand: lane l holds A[row l%16][K block l/16];
+                // rows 0..3 read K blocks 0 and 2 (pixels 0..15), rows 4..7
+                // K blocks 1 and 3 (pixels 16..31), of lane group kb/2.
+                const int r16 = lane & 15, kb = lane >> 4;
+                const int out = r16 < 4 && (kb & 1) == 0 ? r16
+                              : (r16 >= 4 && r16 < 8 && (kb & 1) == 1 ? r16 - 4 : -1);
+                if (out >= 0) {
+                    const int nj = chain32_neuron(kb >> 1, c);
+                    w = ldexpf(params[kOffW4 + out * 64 + nj], e3[nj]);
+                }
             }
             M::set(f, j, w);
         }
@@ -263,15 +331,18 @@ __global__ void pack_decoder32_kernel(const float *__restrict__ params,
         // bias2[(mb*64 + lane)*4 + q][i] = b2[row of register 4q + i]
         const int q = idx & 3, lane = (idx >> 2) & 63, mb = idx >> 8, grp = lane >> 5;
         f32x4 b;
-        for (int i = 0; i < 4; i++)
-            b[i] = params[kOffB2 + 32 * mb + 8 * q + 4 * grp + i];
+        for (int i = 0; i < 4; i++) {
+            const int m = 32 * mb + 8 * q + 4 * grp + i;
+            b[i] = ldexpf(params[kOffB2 + m], -e2[m]);
+        }
         bias2[idx] = b;
     }
     if (idx < 64) {
-        const int grp = idx >> 5;
+        // 16x16 C operand: lanes 0..31 hold rows 0..3 / 4..7, the four outputs
+        // of their own pixel.
         f32x4 b;
         for (int i = 0; i < 4; i++)
-            b[i] = grp == 0 ? params[kOffB4 + i] : 0.0f;
+            b[i] = idx < 32 ? params[kOffB4 + i] : 0.0f;
         bias4[idx] = b;
     }
 }
@@ -346,21 +417,42 @@ __global__ void fold_latents_kernel(const float *__restrict__ params,
     cfold[idx] = acc;
 }
 
+// Parts of the 32-pixel layout's image (see Tile32).
+struct Image32 {
+    void *frags;
+    f32x4 *b2, *b4;
+    int *exps;
+    float *cf_scale;
+};
+inline Image32 image32_parts(const void *image)
+{
+    Image32 im;
+    char *base = (char *)image;
+    im.frags = base;
+    im.b2 = (f32x4 *)(base + (size_t)DecShape32<8>::NFRAG * 64 * 16);
+    im.b4 = im.b2 + 2 * 64 * 4;
+    im.exps = (int *)(im.b4 + 64);
+    im.cf_scale = (float *)(im.exps + 3 * 64);
+    return im;
+}
+
 size_t image32_bytes()
 {
     return (size_t)DecShape32<8>::NFRAG * 64 * 16 + (size_t)2 * 64 * 4 * sizeof(f32x4) +
-           (size_t)64 * sizeof(f32x4);
+           (size_t)64 * sizeof(f32x4) + (size_t)3 * 64 * sizeof(int) + (size_t)64 * sizeof(float);
 }
 
-template <int P> hipError_t pack32(const float *params, void *image, hipStream_t stream)
+template <int P>
+hipError_t pack32(const float *params, const float *cfold, int n_fabrics, void *image,
+                  hipStream_t stream)
 {
     using M = Mfma<P>;
-    auto *frags = (typename M::Frag *)image;
-    auto *b2 = (f32x4 *)((char *)image + (size_t)DecShape32<8>::NFRAG * 64 * 16);
-    auto *b4 = b2 + 2 * 64 * 4;
+    const Image32 im = image32_parts(image);
+    hipLaunchKernelGGL(scale32_kernel<P>, dim3(1), dim3(64), 0, stream, params, cfold, n_fabrics,
+                       im.exps, im.cf_scale);
     const int total = DecShape32<8>::NFRAG * 64;
     hipLaunchKernelGGL(pack_decoder32_kernel<P>, dim3((total + 255) / 256), dim3(256), 0, stream,
-                       params, frags, b2, b4);
+                       params, (const int *)im.exps, (typename M::Frag *)im.frags, im.b2, im.b4);
     return hipGetLastError();
 }
 
@@ -370,9 +462,7 @@ hipError_t decode32(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fab
                     unsigned long long *err, hipStream_t stream)
 {
     using M = Mfma<P>;
-    const auto *frags = (const typename M::Frag *)image;
-    const auto *b2 = (const f32x4 *)((const char *)image + (size_t)DecShape32<8>::NFRAG * 64 * 16);
-    const auto *b4 = b2 + 2 * 64 * 4;
+    const Image32 im = image32_parts(image);
     const int n_tiles = (int)((g.n + 31) / 32);
     int blocks = (n_tiles + 3) / 4;
     const int cap = device_cus() * 2;
@@ -381,7 +471,8 @@ hipError_t decode32(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fab
     const size_t lds = (size_t)2 * 64 * 4 * sizeof(f32x4) +
                        (size_t)n_fabrics * (64 + kFabCopies * kFabConsts) * sizeof(float);
     hipLaunchKernelGGL((decode32_kernel<P, HYBRID>), dim3(blocks), dim3(256), lds, stream, g,
-                       fabrics, n_fabrics, cfold, frags, b2, b4, q, out, err, n_tiles);
+                       fabrics, n_fabrics, cfold, (const typename M::Frag *)im.frags, im.b2,
+                       im.b4, im.cf_scale, q, out, err, n_tiles);
     return hipGetLastError();
 }
 
@@ -478,11 +569,12 @@ size_t shade_image_bytes(int prec)
     return (prec == FABRIC_BF16 || prec == FABRIC_FP16) ? image32_bytes() : decoder_image_bytes(prec);
 }
 
-hipError_t launch_pack_shade(int prec, const float *dec_params, void *image, hipStream_t stream)
+hipError_t launch_pack_shade(int prec, const float *dec_params, const float *cfold, int n_fabrics,
+                             void *image, hipStream_t stream)
 {
     switch (prec) {
-    case FABRIC_BF16: return pack32<FABRIC_BF16>(dec_params, image, stream);
-    case FABRIC_FP16: return pack32<FABRIC_FP16>(dec_params, image, stream);
+    case FABRIC_BF16: return pack32<FABRIC_BF16>(dec_params, cfold, n_fabrics, image, stream);
+    case FABRIC_FP16: return pack32<FABRIC_FP16>(dec_params, cfold, n_fabrics, image, stream);
     default: return launch_pack_decoder(prec, dec_params, image, stream);
     }
 }

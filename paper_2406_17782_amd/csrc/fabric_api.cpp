@@ -53,7 +53,7 @@ struct fabric_ctx {
 
     void *image[4] = {nullptr, nullptr, nullptr, nullptr};   // packed decoders
     uint64_t image_version[4] = {0, 0, 0, 0};
-    uint64_t image_serial[4] = {0, 0, 0, 0};                 // encode_serial of an fp8 image
+    uint64_t image_serial[4] = {0, 0, 0, 0};                 // encode_serial an image was packed for
     void *tmp_image = nullptr;        // packing of caller-supplied parameters
     float *tmp_cfold = nullptr;
     uint16_t *queue_mask = nullptr;   // hybrid frames: pixels routed to the filter
@@ -323,13 +323,17 @@ fabric_status ensure_image(fabric_ctx *ctx, int prec, hipStream_t stream)
 {
     if (!ctx->image[prec])
         return FABRIC_E_STATE;
+    // FP8 scales are calibrated on the encoded fabrics and the BF16 neuron
+    // scales bound the activations over their c_f: both follow the encodes.
     const bool fp8 = prec == FABRIC_FP8_E4M3;
+    const bool per_encode = fp8 || prec == FABRIC_BF16 || prec == FABRIC_FP16;
     if (ctx->image_version[prec] != ctx->weights_version ||
-        (fp8 && ctx->image_serial[prec] != ctx->encode_serial)) {
+        (per_encode && ctx->image_serial[prec] != ctx->encode_serial)) {
         fabric_status st =
             fp8 ? from_hip(launch_pack_f8(ctx->params, ctx->cfold, ctx->fabrics, ctx->n_mats,
                                           ctx->image[prec], stream))
-                : from_hip(launch_pack_shade(prec, ctx->params, ctx->image[prec], stream));
+                : from_hip(launch_pack_shade(prec, ctx->params, ctx->cfold, ctx->n_mats,
+                                             ctx->image[prec], stream));
         if (st != FABRIC_OK)
             return st;
         ctx->image_version[prec] = ctx->weights_version;

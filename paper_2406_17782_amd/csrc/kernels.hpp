@@ -40,9 +40,12 @@ hipError_t launch_pack_decoder(int prec, const float *dec_params, void *image,
                                hipStream_t stream);
 
 // The image the shading kernel of precision prec reads (32-pixel tiles for
-// bf16 / fp16, 16-pixel tiles for fp32).
+// bf16 / fp16, 16-pixel tiles for fp32).  The bf16 image's neuron scales
+// bound the activations over the encoded fabrics' c_f [n_fabrics][64], so it
+// is repacked whenever those change.
 size_t shade_image_bytes(int prec);
-hipError_t launch_pack_shade(int prec, const float *dec_params, void *image, hipStream_t stream);
+hipError_t launch_pack_shade(int prec, const float *dec_params, const float *cfold, int n_fabrics,
+                             void *image, hipStream_t stream);
 
 // FP8-E4M3 shading decoder: calibration over the encoded fabrics, then
 // packing with per-layer scales.  image must hold f8_image_bytes().

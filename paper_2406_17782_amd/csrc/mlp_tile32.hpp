@@ -18,6 +18,22 @@
 //   L2, L4: c = 0..31 chained neurons
 //   L3: c = 0..31 chained neurons; c = 32..34: g = 0 (wi.x, wi.y, wi.z),
 //       g = 1 (wo.x, wo.y, 1), the constant 1 carrying the layer's bias
+//
+// L4 (4 outputs) runs on 16x16x32 MFMA with the same B fragments: read as a
+// 16x16x32 operand, lane l supplies K block l/16, so blocks 0 and 2 carry
+// pixels 0..15 (lane groups 0 and 1) and blocks 1 and 3 pixels 16..31.  The
+// packed A operand puts the four output rows of pixels 0..15 in rows 0..3
+// (weights in K blocks 0 and 2) and those of pixels 16..31 in rows 4..7
+// (K blocks 1 and 3); the 16x16 result layout then leaves output i of pixel
+// l in register i of lane l for l < 32, and the layer's bias rides in the C
+// operand.  Half the matrix work of a 32x32x16 L4 with 4 of 32 rows used.
+//
+// BF16 hidden layers are scaled per neuron by powers of two (chosen from
+// bounds on their activations when the image is packed, undone by the next
+// layer's weights) so that every activation lies below 1; the ReLU is then
+// the [0, 1] clamp of the packed conversion to bf16, one instruction per two
+// values.  Power-of-two scaling commutes with bf16 rounding and FP32
+// accumulation, so the results are those of the unscaled network.
 #pragma once
 
 #include "mlp_tile.hpp"
@@ -65,9 +81,34 @@ template <int KPL> struct DecShape32 {
     static constexpr int FRAG_L1 = 0;                    // 2 M-blocks each
     static constexpr int FRAG_L2 = FRAG_L1 + 2 * KS1;
     static constexpr int FRAG_L3 = FRAG_L2 + 2 * KS2;
-    static constexpr int FRAG_L4 = FRAG_L3 + 2 * KS3;    // 1 M-block (rows 0..3)
+    static constexpr int FRAG_L4 = FRAG_L3 + 2 * KS3;    // 16x16x32 operands, one per k-step
     static constexpr int NFRAG = FRAG_L4 + KS4;          // 28
 };
+
+// Pack eight floats into a bf16 fragment, each pair with the [0, 1] clamp of
+// v_cvt_pk_bf16_f32 (NaN -> 0): the ReLU of activations scaled below 1.
+// The compiler does not emit this form, and its hazard checks do not look
+// inside inline assembly, so the asm is kept safe by construction:
+//  - its inputs are MFMA results, read only after `guard`, a compiler-visible
+//    VALU read of the same MFMA result (the compiler makes that read wait
+//    for the MFMA, which writes all its result registers at once), passed
+//    as an input so that the asm cannot be scheduled before it;
+//  - its outputs are early-clobber (no output overwrites a later input);
+//  - it ends with two wait states, the gap a VALU write needs before an
+//    MFMA reads the register as an operand.
+__device__ inline bf16x8 cvt_clamp8(f32x8 v, float guard)
+{
+    unsigned w0, w1, w2, w3;
+    asm("v_cvt_pk_bf16_f32 %0, %4, %5 clamp\n\t"
+        "v_cvt_pk_bf16_f32 %1, %6, %7 clamp\n\t"
+        "v_cvt_pk_bf16_f32 %2, %8, %9 clamp\n\t"
+        "v_cvt_pk_bf16_f32 %3, %10, %11 clamp\n\t"
+        "s_nop 1"
+        : "=&v"(w0), "=&v"(w1), "=&v"(w2), "=&v"(w3)
+        : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]),
+          "v"(v[7]), "v"(guard));
+    return __builtin_bit_cast(bf16x8, (u32x4){w0, w1, w2, w3});
+}
 
 template <int P> struct Mfma32;
 template <> struct Mfma32<FABRIC_BF16> {
@@ -84,13 +125,47 @@ template <> struct Mfma32<FABRIC_FP16> {
 };
 
 // Packed decoder image of the 32-pixel layout: A fragments [NFRAG][64][8],
-// then the L2 C-operand bias [2 M-blocks][64 lanes][16] and the L4 one
-// [64 lanes][4] (rows 0..3 in lane group 0).
+// then the L2 C-operand bias [2 M-blocks][64 lanes][16], the L4 one
+// [64 lanes][4] (16x16 layout: the four biases in lanes 0..31), the hidden
+// neurons' scale exponents [3 layers][64] (int32) and the scales of the
+// per-fabric first-layer biases c_f [64] (float, 2^-e).
 template <int P> struct Tile32 {
     using M = Mfma<P>;
     using Frag = typename M::Frag;
     using S = DecShape32<8>;
     using FM = FeatureMath<P>;
+    // The ReLU by the clamp of the conversion (activations scaled below 1).
+    static constexpr bool kClampRelu = P == FABRIC_BF16;
+
+    // Rectified fragments ks = 0 .. 2 * NMB - 1 of the 16 x NMB chained
+    // values in acc (fragments 2 mb and 2 mb + 1 come from acc[mb]).
+    template <int NMB, int KS>
+    static __device__ inline void relu_frags(const f32x16 (&acc)[2], Frag (&B)[KS])
+    {
+#pragma unroll
+        for (int mb = 0; mb < NMB; mb++) {
+            if constexpr (kClampRelu) {
+                // Element 0 clamped by the compiler: the guard of this MFMA result.
+                const float g = __builtin_amdgcn_fmed3f(acc[mb][0], 0.0f, 1.0f);
+                f32x8 lo, hi;
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    lo[j] = acc[mb][j];
+                    hi[j] = acc[mb][8 + j];
+                }
+                lo[0] = g;
+                B[2 * mb] = cvt_clamp8(lo, g);
+                B[2 * mb + 1] = cvt_clamp8(hi, g);
+            } else {
+                float v[16];
+#pragma unroll
+                for (int j = 0; j < 16; j++)
+                    v[j] = acc[mb][j];
+                B[2 * mb] = M::relu(frag_of(v, 0));
+                B[2 * mb + 1] = M::relu(frag_of(v, 1));
+            }
+        }
+    }
 
     template <int NSL>
     static __device__ inline Frag frag_of(const float (&vals)[NSL], int ks)
@@ -133,13 +208,7 @@ template <int P> struct Tile32 {
     template <int KS>
     static __device__ inline void chain(const f32x16 (&acc)[2], Frag (&B)[KS])
     {
-        float v[kChain32];
-#pragma unroll
-        for (int c = 0; c < kChain32; c++)
-            v[c] = acc[c >> 4][c & 15];
-#pragma unroll
-        for (int ks = 0; ks < KS; ks++)
-            B[ks] = M::relu(frag_of(v, ks));
+        relu_frags<2>(acc, B);
     }
 
     template <int NMB, int KS, typename GetA>
@@ -156,29 +225,19 @@ template <int P> struct Tile32 {
     static __device__ inline void l3_frags(const f32x16 (&a)[2], float x0, float x1, float x2,
                                            Frag (&B3)[S::KS3])
     {
-        float v[kL3Slots32];
-#pragma unroll
-        for (int c = 0; c < kChain32; c++)
-            v[c] = a[c >> 4][c & 15];
-        v[32] = x0;
-        v[33] = x1;
-        v[34] = x2;
-#pragma unroll
-        for (int ks = 0; ks < S::KS3; ks++) {
-            B3[ks] = frag_of(v, ks);
-            if ((ks + 1) * 8 <= kChain32)
-                B3[ks] = M::relu(B3[ks]);
-        }
+        relu_frags<2>(a, B3);
+        const float v[3] = {x0, x1, x2};
+        B3[4] = frag_of(v, 0);
     }
 
-    // Forward: cf / b2 are the L1 / L2 C operands (per lane, both M-blocks).
-    // Returns W4 h3 (without its bias) in accumulator registers 0..3 of lane
-    // group 0; L4 starts from a zero C operand, which saves the sixteen
-    // registers a bias operand would hold for four useful rows.
+    // Forward: cf / b2 / b4 are the C operands of L1, L2 (per lane, both
+    // M-blocks) and L4 (16x16 layout).  Returns the four outputs, bias
+    // included, in registers 0..3 of lanes 0..31 (output i of pixel l in
+    // lane l).
     template <typename GetA>
-    static __device__ inline f32x16 forward(GetA getA, const f32x16 (&cf)[2], const f32x16 (&b2)[2],
-                                            const float (&s1)[kL1Slots32], float x0, float x1,
-                                            float x2)
+    static __device__ inline f32x4 forward(GetA getA, const f32x16 (&cf)[2], const f32x16 (&b2)[2],
+                                           f32x4 b4, const float (&s1)[kL1Slots32], float x0,
+                                           float x1, float x2)
     {
         Frag B1[S::KS1];
 #pragma unroll
@@ -201,9 +260,11 @@ template <int P> struct Tile32 {
 
         Frag B4[S::KS4];
         chain(a, B4);
-        f32x16 y[2] = {f32x16{}, f32x16{}};
-        dense<1>(getA, S::FRAG_L4, B4, y);
-        return y[0];
+        f32x4 y = b4;
+#pragma unroll
+        for (int ks = 0; ks < S::KS4; ks++)
+            y = M::mma(getA(S::FRAG_L4 + ks), B4[ks], y);
+        return y;
     }
 };
 

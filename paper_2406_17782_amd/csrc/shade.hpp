@@ -89,12 +89,13 @@ __device__ inline HalfPix load_half(const fabric_gbuffer &g, const HalfPlanes &h
 }
 // This lane group's share of the fault rule of pixel_fault (group 0 holds
 // wi, which may point below the fabric, group 1 wo).
+// Evaluated without short-circuits (no branches per tile).
 __device__ inline bool half_fault(const HalfPix &x, int n_fabrics, int grp)
 {
-    const bool finite = isfinite(x.uv) && isfinite(x.r) && isfinite(x.x0) && isfinite(x.x1) &&
+    const bool finite = isfinite(x.uv) & isfinite(x.r) & isfinite(x.x0) & isfinite(x.x1) &
                         isfinite(x.xz);
-    return !finite || x.fid >= n_fabrics || !(x.r > 0.0f) ||
-           (grp ? !(x.xz > 0.0f) : x.xz == 0.0f);
+    const bool dir_bad = grp ? !(x.xz > 0.0f) : x.xz == 0.0f;
+    return !finite | (x.fid >= n_fabrics) | !(x.r > 0.0f) | dir_bad;
 }
 // True in both lanes of a pixel (lanes l and l ^ 32) when either flag is set.
 __device__ inline bool pair_any(bool flag, int lane)
@@ -126,6 +127,13 @@ __device__ inline void stage_fabric_consts(const DevFabric *__restrict__ fabrics
     }
 }
 
+// max(x, 0) as one signed-integer max of the bits (a negative float is a
+// negative int32; -0 gives +0).
+__device__ inline float relu_bits(float x)
+{
+    return __int_as_float(max(__float_as_int(x), 0));
+}
+
 // Decoded components (Eq. (8)): C = max(y, 0), S = max((e^y - 1) / k, 0)
 // with k = 100 for reflection and 1000 for transmission (Sec. 4.2), composed
 // with the albedos fc[4..15] of the pixel's staged entry into rgb (the 1/k
@@ -134,9 +142,9 @@ template <typename FM>
 __device__ inline void compose_rgb(float y0, float y1, float y2, float y3, const float *fc,
                                    float (&rgb)[3])
 {
-    const float cw = fmaxf(y0, 0.0f), cwf = fmaxf(y1, 0.0f);
-    const float sw = fmaxf(FM::expm1(y2), 0.0f);
-    const float sf = fmaxf(FM::expm1(y3), 0.0f);
+    const float cw = relu_bits(y0), cwf = relu_bits(y1);
+    const float sw = relu_bits(FM::expm1(y2));
+    const float sf = relu_bits(FM::expm1(y3));
 #pragma unroll
     for (int c = 0; c < 3; c++)
         rgb[c] = fc[4 + c] * cw + fc[7 + c] * cwf + fc[10 + c] * sw + fc[13 + c] * sf;
