@@ -122,7 +122,7 @@ template <int P, bool HYBRID>
 __global__ __launch_bounds__(256) void decode32_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ frags,
-    const f32x4 *__restrict__ bias2, const f32x4 *__restrict__ bias4,
+    const float *__restrict__ bias2, const f32x4 *__restrict__ bias4,
     const float *__restrict__ cf_scale, FallbackQueue q, float *__restrict__ out,
     unsigned long long *err, int n_tiles)
 {
@@ -131,13 +131,14 @@ __global__ __launch_bounds__(256) void decode32_kernel(
     using S = typename T::S;
     using FM = FeatureMath<P>;
 
-    // LDS: L2 C-operand bias [2][64 lanes][4 x f32x4], then per fabric c_f [64]
-    // then the staged constants [kFabCopies][n_fabrics][kFabConsts].
+    // LDS: L2's bias [64], then per fabric c_f [64], then the staged
+    // constants [kFabCopies][n_fabrics][kFabConsts].  Both biases are read as
+    // the C operands' rows of the lane's group: broadcast reads.
     extern __shared__ f32x4 smem4[];
-    f32x4 *s_b2 = smem4;
-    float *s_cf = (float *)(smem4 + 2 * 64 * 4);
+    float *s_b2 = (float *)smem4;
+    float *s_cf = s_b2 + 64;
     float *s_fc = s_cf + n_fabrics * 64;
-    for (int k = threadIdx.x; k < 2 * 64 * 4; k += blockDim.x)
+    for (int k = threadIdx.x; k < 64; k += blockDim.x)
         s_b2[k] = bias2[k];
     for (int k = threadIdx.x; k < n_fabrics * 64; k += blockDim.x)
         s_cf[k] = cfold[k] * cf_scale[k & 63];
@@ -182,8 +183,9 @@ __global__ __launch_bounds__(256) void decode32_kernel(
         for (int mb = 0; mb < 2; mb++)
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                const f32x4 c4 = *(const f32x4 *)(s_cf + fid * 64 + 32 * mb + 8 * q + 4 * grp);
-                const f32x4 bq = s_b2[(mb * 64 + lane) * 4 + q];
+                const int row = 32 * mb + 8 * q + 4 * grp;
+                const f32x4 c4 = *(const f32x4 *)(s_cf + fid * 64 + row);
+                const f32x4 bq = *(const f32x4 *)(s_b2 + row);
 #pragma unroll
                 for (int i = 0; i < 4; i++) {
                     cf[mb][4 * q + i] = c4[i];
@@ -209,9 +211,8 @@ __global__ __launch_bounds__(256) void decode32_kernel(
             queue_mark32((uint32_t)__ballot(grp == 0 && valid && oor), tile, q, lane);
     };
 
-    // The next tile's fields are loaded while this one is shaded.  (Deeper
-    // prefetching measured no faster: the compiler waits for the newer loads
-    // at the loop's register copies.)
+    // The next tile's fields are loaded while this one is shaded (loading
+    // two tiles ahead measured no faster).
     HalfPix nxt = load_half(g, hp, tile_px(wave_id));
     for (int tile = wave_id; tile < n_tiles; tile += waves) {
         const HalfPix cur = nxt;
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(64) void scale32_kernel(const float *__restrict__ p
 template <int P>
 __global__ void pack_decoder32_kernel(const float *__restrict__ params, const int *__restrict__ exps,
                                       typename Mfma<P>::Frag *__restrict__ frags,
-                                      f32x4 *__restrict__ bias2, f32x4 *__restrict__ bias4)
+                                      float *__restrict__ bias2, f32x4 *__restrict__ bias4)
 {
     using M = Mfma<P>;
     using S = DecShape32<8>;
@@ -327,16 +328,8 @@ __global__ void pack_decoder32_kernel(const float *__restrict__ params, const in
         }
         frags[idx] = f;
     }
-    if (idx < 2 * 64 * 4) {
-        // bias2[(mb*64 + lane)*4 + q][i] = b2[row of register 4q + i]
-        const int q = idx & 3, lane = (idx >> 2) & 63, mb = idx >> 8, grp = lane >> 5;
-        f32x4 b;
-        for (int i = 0; i < 4; i++) {
-            const int m = 32 * mb + 8 * q + 4 * grp + i;
-            b[i] = ldexpf(params[kOffB2 + m], -e2[m]);
-        }
-        bias2[idx] = b;
-    }
+    if (idx < 64)
+        bias2[idx] = ldexpf(params[kOffB2 + idx], -e2[idx]);
     if (idx < 64) {
         // 16x16 C operand: lanes 0..31 hold rows 0..3 / 4..7, the four outputs
         // of their own pixel.
@@ -420,7 +413,8 @@ __global__ void fold_latents_kernel(const float *__restrict__ params,
 // Parts of the 32-pixel layout's image (see Tile32).
 struct Image32 {
     void *frags;
-    f32x4 *b2, *b4;
+    float *b2;
+    f32x4 *b4;
     int *exps;
     float *cf_scale;
 };
@@ -429,8 +423,8 @@ inline Image32 image32_parts(const void *image)
     Image32 im;
     char *base = (char *)image;
     im.frags = base;
-    im.b2 = (f32x4 *)(base + (size_t)DecShape32<8>::NFRAG * 64 * 16);
-    im.b4 = im.b2 + 2 * 64 * 4;
+    im.b2 = (float *)(base + (size_t)DecShape32<8>::NFRAG * 64 * 16);
+    im.b4 = (f32x4 *)(im.b2 + 64);
     im.exps = (int *)(im.b4 + 64);
     im.cf_scale = (float *)(im.exps + 3 * 64);
     return im;
@@ -438,7 +432,7 @@ inline Image32 image32_parts(const void *image)
 
 size_t image32_bytes()
 {
-    return (size_t)DecShape32<8>::NFRAG * 64 * 16 + (size_t)2 * 64 * 4 * sizeof(f32x4) +
+    return (size_t)DecShape32<8>::NFRAG * 64 * 16 + (size_t)64 * sizeof(float) +
            (size_t)64 * sizeof(f32x4) + (size_t)3 * 64 * sizeof(int) + (size_t)64 * sizeof(float);
 }
 
@@ -468,7 +462,7 @@ hipError_t decode32(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fab
     const int cap = device_cus() * 2;
     if (blocks > cap)
         blocks = cap;
-    const size_t lds = (size_t)2 * 64 * 4 * sizeof(f32x4) +
+    const size_t lds = (size_t)64 * sizeof(float) +
                        (size_t)n_fabrics * (64 + kFabCopies * kFabConsts) * sizeof(float);
     hipLaunchKernelGGL((decode32_kernel<P, HYBRID>), dim3(blocks), dim3(256), lds, stream, g,
                        fabrics, n_fabrics, cfold, (const typename M::Frag *)im.frags, im.b2,

@@ -125,7 +125,7 @@ template <> struct Mfma32<FABRIC_FP16> {
 };
 
 // Packed decoder image of the 32-pixel layout: A fragments [NFRAG][64][8],
-// then the L2 C-operand bias [2 M-blocks][64 lanes][16], the L4 one
+// then L2's bias [64] (scaled; the C operand's rows), the L4 C operand
 // [64 lanes][4] (16x16 layout: the four biases in lanes 0..31), the hidden
 // neurons' scale exponents [3 layers][64] (int32) and the scales of the
 // per-fabric first-layer biases c_f [64] (float, 2^-e).
