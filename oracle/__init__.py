@@ -93,6 +93,10 @@ def lib():
                                            ctypes.c_int, ctypes.c_int, _P]
         L.orc_decoder_batch.restype = ctypes.c_int64
         L.orc_decoder_batch.argtypes = [_P, _P, _P, ctypes.c_int, _P, _P, _P]
+        L.orc_decoder_batch_q.restype = ctypes.c_int64
+        L.orc_decoder_batch_q.argtypes = [_P, _P, _P, ctypes.c_int, _P, ctypes.c_int, _P, _P]
+        L.orc_round_operand.restype = ctypes.c_double
+        L.orc_round_operand.argtypes = [ctypes.c_double, ctypes.c_int]
         L.orc_encoder_input.argtypes = [_P, _P]
         L.orc_paper_param_count.restype = ctypes.c_int
         L.orc_paper_features.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -100,6 +104,9 @@ def lib():
         L.orc_paper_decoder_batch.restype = ctypes.c_int64
         L.orc_paper_decoder_batch.argtypes = [_P, _P, _P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int,
                                               _P, _P]
+        L.orc_paper_decoder_batch_q.restype = ctypes.c_int64
+        L.orc_paper_decoder_batch_q.argtypes = [_P, _P, _P, ctypes.c_int, _P, ctypes.c_int,
+                                                ctypes.c_int, ctypes.c_int, _P, _P]
         L.orc_paper_features_raw.argtypes = L.orc_paper_features.argtypes
         L.orc_encoder_batch.argtypes = [_P, _P, ctypes.c_int, _P]
         L.orc_paper_loss_grad.restype = ctypes.c_double
@@ -291,15 +298,28 @@ def spatial_features(u: float, v: float, r: float, wx: int, wy: int) -> np.ndarr
     return s
 
 
-def decoder_gbuffer(params, latents, mats: Sequence, g):
-    """Decoder forward: raw outputs y [4,n] and composed rgb [3,n]."""
+# Significant bits of the reduced operand precisions (operand_bits below).
+BF16_BITS = 8
+FP16_BITS = 11
+
+
+def round_operand(x: float, bits: int) -> float:
+    """x rounded to a reduced operand precision (8: bfloat16, 11: binary16)."""
+    return float(lib().orc_round_operand(float(x), int(bits)))
+
+
+def decoder_gbuffer(params, latents, mats: Sequence, g, operand_bits: int = 0):
+    """Decoder forward: raw outputs y [4,n] and composed rgb [3,n].
+    operand_bits > 0: every matrix product's operands (weights and per-pixel
+    inputs, not the latent term) rounded to that precision, sums exact."""
     h = _GBufHolder(g)
     n = h.s.n
     P = _d(params)
     Z = _d(latents).reshape(-1)
     y = np.zeros((4, n))
     rgb = np.zeros((3, n))
-    lib().orc_decoder_batch(_ptr(P), _ptr(Z), materials(mats), len(mats), h.ref, _ptr(y), _ptr(rgb))
+    lib().orc_decoder_batch_q(_ptr(P), _ptr(Z), materials(mats), len(mats), h.ref,
+                              int(operand_bits), _ptr(y), _ptr(rgb))
     return y, rgb
 
 
@@ -316,19 +336,19 @@ def paper_features(u: float, v: float, r: float, wx: int, wy: int, raw: bool = F
 
 
 def paper_decoder_gbuffer(params, latents, mats: Sequence, g, raw: bool = False,
-                          fused: bool = True):
+                          fused: bool = True, operand_bits: int = 0):
     """Paper-size decoder forward: raw outputs y [4,n] and composed rgb [3,n]
     (raw: footprint inputs without the one-blob encoding; fused = False: the
-    angular inputs enter the first layer, no spatial fusion stage)."""
+    angular inputs enter the first layer, no spatial fusion stage;
+    operand_bits as in decoder_gbuffer)."""
     h = _GBufHolder(g)
     n = h.s.n
     P = _d(params)
     Z = _d(latents).reshape(-1)
     y = np.zeros((4, n))
     rgb = np.zeros((3, n))
-    lib().orc_paper_decoder_batch(_ptr(P), _ptr(Z), materials(mats), len(mats), h.ref, int(raw),
-                                  int(fused), _ptr(y),
-                                  _ptr(rgb))
+    lib().orc_paper_decoder_batch_q(_ptr(P), _ptr(Z), materials(mats), len(mats), h.ref,
+                                    int(raw), int(fused), int(operand_bits), _ptr(y), _ptr(rgb))
     return y, rgb
 
 

@@ -936,27 +936,71 @@ static void dense(const double *W, const double *b, const double *x, int nin, in
     }
 }
 
+/* Operand precision of the reduced-precision decoders (the rounding rule of
+ * the reduced-precision paths: round to nearest, ties to even): x rounded to
+ * `bits` significant bits within the format's exponent range; bits = 8 is
+ * bfloat16 (binary32's exponent range), bits = 11 IEEE binary16 (spacing
+ * 2^-24 below its smallest normal 2^-14, infinity beyond 65504 after
+ * rounding).  bits <= 0 leaves x unchanged. */
+double orc_round_operand(double x, int bits)
+{
+    if (bits <= 0 || x == 0.0 || !isfinite(x))
+        return x;
+    const int emin = bits == 11 ? -14 : -126;
+    const double maxv = bits == 11 ? 65504.0 : 3.3895313892515355e38;
+    int ex;
+    frexp(x, &ex);                      /* |x| in [2^(ex-1), 2^ex) */
+    int e = ex - 1;
+    if (e < emin)
+        e = emin;
+    const double q = ldexp(1.0, e - (bits - 1));   /* the format's spacing at x */
+    const double r = nearbyint(x / q) * q;         /* x / q is exact: q is 2^k */
+    return fabs(r) > maxv ? copysign(INFINITY, x) : r;
+}
+
+/* dense() evaluated as a reduced-precision decoder evaluates it: each
+ * product's two operands rounded to `bits` (orc_round_operand), except the
+ * first `nfull` inputs and their weights (the latent, whose product the
+ * decoders fold into the first layer's bias in full precision); bias and
+ * sums exact. */
+static void dense_q(const double *W, const double *b, const double *x, int nin, int nout,
+                    int nfull, int bits, double *y)
+{
+    if (bits <= 0) {
+        dense(W, b, x, nin, nout, y);
+        return;
+    }
+    for (int o = 0; o < nout; o++) {
+        double acc = b[o];
+        for (int i = 0; i < nin; i++)
+            acc += i < nfull ? W[o * nin + i] * x[i]
+                             : orc_round_operand(W[o * nin + i], bits) * orc_round_operand(x[i], bits);
+        y[o] = acc;
+    }
+}
+
 /* Activations kept for the backward pass. */
 typedef struct {
     double x1[X1], a1[HID], h1[HID], a2[HID], h2[HID], x3[X3], a3[HID], h3[HID], y[NOUT];
 } dec_acts;
 
 /* Decoder: spatial fusion h1 = relu(W1 [z, s] + b1), h2 = relu(W2 h1 + b2);
- * angular decoder h3 = relu(W3 [h2, wi.xyz, wo.xy] + b3), y = W4 h3 + b4. */
+ * angular decoder h3 = relu(W3 [h2, wi.xyz, wo.xy] + b3), y = W4 h3 + b4.
+ * bits > 0: products' operands rounded as in dense_q. */
 static void decoder_forward(const double *P, const double *z, const double *s,
-                            const double ang[NANG], dec_acts *A)
+                            const double ang[NANG], int bits, dec_acts *A)
 {
     for (int k = 0; k < LATENT; k++) A->x1[k] = z[k];
     for (int k = 0; k < NFEAT; k++) A->x1[LATENT + k] = s[k];
-    dense(P + OFF_W1, P + OFF_B1, A->x1, X1, HID, A->a1);
+    dense_q(P + OFF_W1, P + OFF_B1, A->x1, X1, HID, LATENT, bits, A->a1);
     for (int k = 0; k < HID; k++) A->h1[k] = relu(A->a1[k]);
-    dense(P + OFF_W2, P + OFF_B2, A->h1, HID, HID, A->a2);
+    dense_q(P + OFF_W2, P + OFF_B2, A->h1, HID, HID, 0, bits, A->a2);
     for (int k = 0; k < HID; k++) A->h2[k] = relu(A->a2[k]);
     for (int k = 0; k < HID; k++) A->x3[k] = A->h2[k];
     for (int k = 0; k < NANG; k++) A->x3[HID + k] = ang[k];
-    dense(P + OFF_W3, P + OFF_B3, A->x3, X3, HID, A->a3);
+    dense_q(P + OFF_W3, P + OFF_B3, A->x3, X3, HID, 0, bits, A->a3);
     for (int k = 0; k < HID; k++) A->h3[k] = relu(A->a3[k]);
-    dense(P + OFF_W4, P + OFF_B4, A->h3, HID, NOUT, A->y);
+    dense_q(P + OFF_W4, P + OFF_B4, A->h3, HID, NOUT, 0, bits, A->y);
 }
 
 /* Accumulate dL/dW, dL/db for y = W x + b into G and return dL/dx in dx. */
@@ -1004,9 +1048,10 @@ static void decode_outputs(const double y[NOUT], double k, double comp[4])
 }
 
 /* Decoder over a G-buffer with per-fabric latents z[nmats][32].  y is [4][n]
- * raw outputs, rgb [3][n] composed reflectance; faulted pixels give 0. */
-int64_t orc_decoder_batch(const double *P, const double *latents, const orc_material *mats,
-                          int nmats, const orc_gbuffer *g, double *y, double *rgb)
+ * raw outputs, rgb [3][n] composed reflectance; faulted pixels give 0.
+ * bits > 0: the decoder in that operand precision (dense_q). */
+int64_t orc_decoder_batch_q(const double *P, const double *latents, const orc_material *mats,
+                            int nmats, const orc_gbuffer *g, int bits, double *y, double *rgb)
 {
     int64_t n = g->n, faults = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : faults)
@@ -1019,7 +1064,7 @@ int64_t orc_decoder_batch(const double *P, const double *latents, const orc_mate
             double s[NFEAT], ang[NANG] = {wi[0], wi[1], wi[2], wo[0], wo[1]}, comp[4];
             dec_acts A;
             orc_spatial_features(u, v, r, mats[fid].wx, mats[fid].wy, s);
-            decoder_forward(P, latents + (int64_t)fid * LATENT, s, ang, &A);
+            decoder_forward(P, latents + (int64_t)fid * LATENT, s, ang, bits, &A);
             for (int c = 0; c < 4; c++) out[c] = A.y[c];
             decode_outputs(A.y, spec_k(wi[2]), comp);
             compose_rgb(&mats[fid], comp, c3);
@@ -1031,6 +1076,12 @@ int64_t orc_decoder_batch(const double *P, const double *latents, const orc_mate
             for (int c = 0; c < 3; c++) rgb[(int64_t)c * n + p] = c3[c];
     }
     return faults;
+}
+
+int64_t orc_decoder_batch(const double *P, const double *latents, const orc_material *mats,
+                          int nmats, const orc_gbuffer *g, double *y, double *rgb)
+{
+    return orc_decoder_batch_q(P, latents, mats, nmats, g, 0, y, rgb);
 }
 
 /* ---- Paper-size decoder (Sec. 4.2 "Decoder", Fig. "network_whole") ------ */
@@ -1116,39 +1167,42 @@ typedef struct {
  * Sec. 5 "Spatial fusion"): the angular inputs enter the first layer, through
  * A1's angular columns, and A1 sees zeros in their place; the parameter
  * layout and count are those of the paper's network. */
+/* bits > 0: products' operands rounded as in dense_q (the residual add and
+ * the activations exact). */
 static void paper_forward_acts(const double *P, const double *z, const double f[PBLOB],
-                               const double ang[NANG], int fused, paper_acts *A)
+                               const double ang[NANG], int fused, int bits, paper_acts *A)
 {
     for (int k = 0; k < PLATENT; k++) A->x1[k] = z[k];
     for (int k = 0; k < PBLOB; k++) A->x1[PLATENT + k] = f[k];
     for (int k = 0; k < NANG; k++) A->ang[k] = ang[k];
     A->fused = fused;
-    dense(P + P_WF1, P + P_BF1, A->x1, PX1, PHID, A->t);
+    dense_q(P + P_WF1, P + P_BF1, A->x1, PX1, PHID, PLATENT, bits, A->t);
     if (!fused)
         for (int o = 0; o < PHID; o++)
             for (int a = 0; a < NANG; a++)
-                A->t[o] += P[P_WA1 + o * PXA1 + PHID + a] * ang[a];
+                A->t[o] += orc_round_operand(P[P_WA1 + o * PXA1 + PHID + a], bits) *
+                           orc_round_operand(ang[a], bits);
     for (int k = 0; k < PHID; k++) A->t[k] = lrelu(A->t[k]);
-    dense(P + P_WF2, P + P_BF2, A->t, PHID, PHID, A->sp);
+    dense_q(P + P_WF2, P + P_BF2, A->t, PHID, PHID, 0, bits, A->sp);
     for (int k = 0; k < PHID; k++) A->sp[k] = lrelu(A->sp[k]);
     for (int k = 0; k < PHID; k++) A->xa[k] = A->sp[k];
     for (int k = 0; k < NANG; k++) A->xa[PHID + k] = fused ? ang[k] : 0.0;
-    dense(P + P_WA1, P + P_BA1, A->xa, PXA1, PHID, A->x);
+    dense_q(P + P_WA1, P + P_BA1, A->xa, PXA1, PHID, 0, bits, A->x);
     for (int k = 0; k < PHID; k++) A->x[k] = lrelu(A->x[k]);
-    dense(P + P_WA2, P + P_BA2, A->x, PHID, PHID, A->h);
+    dense_q(P + P_WA2, P + P_BA2, A->x, PHID, PHID, 0, bits, A->h);
     for (int k = 0; k < PHID; k++) A->h[k] = lrelu(A->h[k]);
-    dense(P + P_WA3, P + P_BA3, A->h, PHID, PHID, A->rr);
+    dense_q(P + P_WA3, P + P_BA3, A->h, PHID, PHID, 0, bits, A->rr);
     for (int k = 0; k < PHID; k++) A->rr[k] = lrelu(A->rr[k] + A->x[k]);
-    dense(P + P_WA4, P + P_BA4, A->rr, PHID, PHID, A->g);
+    dense_q(P + P_WA4, P + P_BA4, A->rr, PHID, PHID, 0, bits, A->g);
     for (int k = 0; k < PHID; k++) A->g[k] = lrelu(A->g[k]);
-    dense(P + P_WA5, P + P_BA5, A->g, PHID, NOUT, A->y);
+    dense_q(P + P_WA5, P + P_BA5, A->g, PHID, NOUT, 0, bits, A->y);
 }
 
 static void paper_forward(const double *P, const double *z, const double f[PBLOB],
-                          const double ang[NANG], int fused, double y[NOUT])
+                          const double ang[NANG], int fused, int bits, double y[NOUT])
 {
     paper_acts A;
-    paper_forward_acts(P, z, f, ang, fused, &A);
+    paper_forward_acts(P, z, f, ang, fused, bits, &A);
     for (int k = 0; k < NOUT; k++) y[k] = A.y[k];
 }
 
@@ -1188,9 +1242,9 @@ static void paper_backward(const double *P, const paper_acts *A, const double dy
  * z[nmats][64]: raw outputs y [4][n] and composed rgb [3][n] (decoded and
  * composed as the shading path does); faulted pixels give 0.  raw != 0:
  * footprint inputs without the one-blob encoding. */
-int64_t orc_paper_decoder_batch(const double *P, const double *latents, const orc_material *mats,
-                                int nmats, const orc_gbuffer *g, int raw, int fused, double *y,
-                                double *rgb)
+int64_t orc_paper_decoder_batch_q(const double *P, const double *latents, const orc_material *mats,
+                                  int nmats, const orc_gbuffer *g, int raw, int fused, int bits,
+                                  double *y, double *rgb)
 {
     int64_t n = g->n, faults = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : faults)
@@ -1202,7 +1256,7 @@ int64_t orc_paper_decoder_batch(const double *P, const double *latents, const or
         if (!bad) {
             double f[PBLOB], ang[NANG] = {wi[0], wi[1], wi[2], wo[0], wo[1]}, comp[4];
             (raw ? orc_paper_features_raw : orc_paper_features)(u, v, r, mats[fid].wx, mats[fid].wy, f);
-            paper_forward(P, latents + (int64_t)fid * PLATENT, f, ang, fused, out);
+            paper_forward(P, latents + (int64_t)fid * PLATENT, f, ang, fused, bits, out);
             decode_outputs(out, spec_k(wi[2]), comp);
             compose_rgb(&mats[fid], comp, c3);
         }
@@ -1213,6 +1267,13 @@ int64_t orc_paper_decoder_batch(const double *P, const double *latents, const or
             for (int c = 0; c < 3; c++) rgb[(int64_t)c * n + p] = c3[c];
     }
     return faults;
+}
+
+int64_t orc_paper_decoder_batch(const double *P, const double *latents, const orc_material *mats,
+                                int nmats, const orc_gbuffer *g, int raw, int fused, double *y,
+                                double *rgb)
+{
+    return orc_paper_decoder_batch_q(P, latents, mats, nmats, g, raw, fused, 0, y, rgb);
 }
 
 /* ---- Encoder ------------------------------------------------------------ */
@@ -1359,7 +1420,7 @@ double orc_loss_grad(const double *params, const orc_material *mats, int nmats,
                 tgt[c] = targets[(int64_t)c * n + p];
             dec_acts A;
             orc_spatial_features(u, v, r, mats[fid].wx, mats[fid].wy, s);
-            decoder_forward(P, z + fid * LATENT, s, ang, &A);
+            decoder_forward(P, z + fid * LATENT, s, ang, 0, &A);
             lt[tid] += loss_terms(A.y, tgt, spec_k(wi[2]), n, dy);
             decoder_backward(P, &A, dy, G, dzp);
             for (int k = 0; k < LATENT; k++)
@@ -1407,7 +1468,7 @@ void orc_decoder_backward_batch(const double *P, const double *latents, const or
             dy[c] = dy_all[(int64_t)c * n + p];
         dec_acts A;
         orc_spatial_features(u, v, r, mats[fid].wx, mats[fid].wy, s);
-        decoder_forward(P, latents + fid * LATENT, s, ang, &A);
+        decoder_forward(P, latents + fid * LATENT, s, ang, 0, &A);
         decoder_backward(P, &A, dy, grad_dec, dzp);
         for (int k = 0; k < LATENT; k++)
             grad_latent[fid * LATENT + k] += dzp[k];
@@ -1453,7 +1514,7 @@ double orc_paper_loss_grad(const double *P, const double *latents, const orc_mat
                 tgt[c] = targets[(int64_t)c * n + p];
             paper_acts A;
             (raw ? orc_paper_features_raw : orc_paper_features)(u, v, r, mats[fid].wx, mats[fid].wy, f);
-            paper_forward_acts(P, latents + (int64_t)fid * PLATENT, f, ang, fused, &A);
+            paper_forward_acts(P, latents + (int64_t)fid * PLATENT, f, ang, fused, 0, &A);
             lt[tid] += loss_terms(A.y, tgt, spec_k(wi[2]), n, dy);
             paper_backward(P, &A, dy, G, dzp);
             for (int k = 0; k < PLATENT; k++)
