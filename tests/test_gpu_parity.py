@@ -169,9 +169,10 @@ def test_decoder_forward_fp32_matches_oracle(fab, pkg, orc, torch):
 
 @pytest.mark.parametrize("prec,bound", [("bf16", 3e-2), ("fp16", 4e-3)])
 def test_decoder_forward_low_precision_error(fab, pkg, orc, torch, prec, bound):
-    """Operand rounding to bf16 (unit roundoff 2^-9) or fp16 (2^-12) in four
-    chained layers: the norm-wise error stays within ~8 roundoffs of FP64 per
-    layer chain on these inputs; the bound leaves a 2x margin."""
+    """Operand rounding to bf16 (unit roundoff 2^-8) or fp16 (2^-11) in four
+    chained layers: the norm-wise error stays within ~4 roundoffs of FP64 per
+    layer chain on these inputs; the bound leaves a 2x margin (per-pixel
+    bounds: tests/test_gpu_precision.py)."""
     mats, g, params, lat = _decoder_case(seed=20)
     fab.encode(mats)
     dp = torch.from_numpy(params[: fi.N_DECODER_PARAMS]).cuda()

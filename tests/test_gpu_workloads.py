@@ -117,9 +117,9 @@ def test_autograd_functions_match_oracle(fab, pkg, orc, torch):
 
 
 # BF16 training: the decoder's forward and activation-gradient products take
-# BF16 operands (unit roundoff 2^-9, rms relative error 2^-9 / sqrt(3) =
-# 0.11 % per operand, sqrt(2) x that per product); four forward and four
-# backward layers chain to about sqrt(8) x 0.16 % = 0.45 % on a gradient
+# BF16 operands (unit roundoff 2^-8, rms relative error 2^-8 / sqrt(3) =
+# 0.23 % per operand, sqrt(2) x that per product); four forward and four
+# backward layers chain to about sqrt(8) x 0.32 % = 0.9 % on a gradient
 # entry.  Weight gradients and the loss sums stay in FP32.  Bound: 3 % of the
 # whole gradient's norm and 1 % of the loss.
 BF16_GRAD_BOUND = 3e-2
