@@ -208,7 +208,9 @@ fabric_status fabric_lerp_latents(fabric_ctx *ctx, const int32_t *dst, const int
  * after every layer but the output; width 64.  Outputs decoded and composed
  * as fabric_shade_gbuffer does (k = 100, or 1000 where wi.z < 0).  Shading
  * takes prec FABRIC_BF16 or FABRIC_FP16 operands with FP32 accumulation (the
- * FP16 path applies the leaky ReLU to packed halves); training is
+ * FP16 path applies the leaky ReLU to packed halves) on MFMA, or
+ * FABRIC_FP32: the reference, every layer in FP32 from the FP32 parameters
+ * and latents (one lane per pixel, not a fast path); training is
  * fabric_paper_train_step.
  *   params   device float [FABRIC_N_PAPER_DECODER_PARAMS], rows = outputs:
  *            WF1[64][88] ([z(64), u bins, v bins, size bins]) bF1[64]
@@ -227,6 +229,15 @@ fabric_status fabric_paper_prepare(fabric_ctx *ctx, const float *params, const f
                                    void *stream);
 fabric_status fabric_paper_shade(fabric_ctx *ctx, const fabric_gbuffer *g, fabric_prec prec,
                                  float *out_rgb, void *stream);
+
+/* The paper-size decoder's raw outputs (y of Sec. 4.2 before the decoding of
+ * Eq. (9): C_warp, C_weft, S_warp, S_weft in the log-mapped domain), in FP32
+ * from the parameters and latents of the last fabric_paper_prepare or
+ * fabric_paper_train_step, as fabric_paper_shade's FP32 reference computes
+ * them.  y4: device float [4][n]; faulted pixels give 0 and are counted.
+ * Errors as fabric_paper_shade. */
+fabric_status fabric_paper_forward(fabric_ctx *ctx, const fabric_gbuffer *g, float *y4,
+                                   void *stream);
 
 /* Neural shading of a G-buffer (Sec. 4.3 "Rendering"): per pixel, the
  * decoder's four outputs decoded as C = max(y, 0), S = max((e^y - 1)/k, 0)

@@ -25,7 +25,7 @@ __all__ = [
     "FABRIC_FP8_E4M3", "FABRIC_N_PARAMS", "FABRIC_N_DECODER_PARAMS", "FABRIC_N_ENCODER_PARAMS",
     "FABRIC_MAX_FABRICS", "FABRIC_MAX_SAMPLES", "FABRIC_LATENT",
     "fabric_create", "fabric_destroy", "fabric_encode", "fabric_set_albedo", "fabric_lerp_latents",
-    "fabric_set_visibility", "fabric_paper_prepare", "fabric_paper_shade",
+    "fabric_set_visibility", "fabric_paper_prepare", "fabric_paper_shade", "fabric_paper_forward",
     "fabric_paper_train_step", "fabric_paper_loss_grad", "fabric_paper_get_params",
     "fabric_paper_set_footprint_encoding", "fabric_paper_set_spatial_fusion", "FABRIC_PAPER_LATENT", "FABRIC_N_PAPER_DECODER_PARAMS",
     "fabric_shade_gbuffer", "fabric_shade_gbuffer_noalloc", "fabric_gt_filtered",
@@ -150,6 +150,12 @@ def fabric_paper_shade(ctx, g: DeviceGBuffer, out_rgb, prec: str = "bf16", strea
     gs = g.c_struct()
     check(_abi.lib().fabric_paper_shade(ctx, ctypes.byref(gs), PREC[prec], _dptr(out_rgb),
                                         _stream(stream)), "fabric_paper_shade")
+
+
+def fabric_paper_forward(ctx, g: DeviceGBuffer, y4, stream=None) -> None:
+    gs = g.c_struct()
+    check(_abi.lib().fabric_paper_forward(ctx, ctypes.byref(gs), _dptr(y4), _stream(stream)),
+          "fabric_paper_forward")
 
 
 def fabric_set_visibility(ctx, enable: bool) -> None:

@@ -65,6 +65,7 @@ class fabric_train_cfg(ctypes.Structure):
 EXPORTS = [
     "fabric_create", "fabric_destroy", "fabric_status_str", "fabric_encode", "fabric_set_albedo",
     "fabric_lerp_latents", "fabric_set_visibility", "fabric_paper_prepare", "fabric_paper_shade",
+    "fabric_paper_forward",
     "fabric_paper_train_step", "fabric_paper_loss_grad", "fabric_paper_get_params",
     "fabric_paper_set_footprint_encoding", "fabric_paper_set_spatial_fusion",
     "fabric_shade_gbuffer", "fabric_shade_gbuffer_noalloc", "fabric_gt_filtered",
@@ -96,6 +97,8 @@ def _declare(L):
     L.fabric_paper_prepare.restype = _S
     L.fabric_paper_shade.argtypes = [_P, ctypes.POINTER(fabric_gbuffer), ctypes.c_int, _P, _P]
     L.fabric_paper_shade.restype = _S
+    L.fabric_paper_forward.argtypes = [_P, ctypes.POINTER(fabric_gbuffer), _P, _P]
+    L.fabric_paper_forward.restype = _S
     L.fabric_paper_train_step.argtypes = [_P, ctypes.POINTER(fabric_gbuffer), _P,
                                           ctypes.POINTER(fabric_train_cfg), ctypes.POINTER(ctypes.c_float), _P]
     L.fabric_paper_train_step.restype = _S

@@ -473,6 +473,96 @@ hipError_t launch_paper_prepare(const float *params, const float *latents, int n
     return hipGetLastError();
 }
 
+// FP32 reference shading of the paper-size decoder: one lane per pixel,
+// every layer in FP32 from the FP32 masters (latent product included, no
+// folding), activation rows in LDS (the weights are the same for every lane:
+// scalar loads).  Writes the composed rgb [3][n] and/or the raw outputs
+// [4][n]; faulted pixels give zeros and are counted.
+constexpr int kRefThreads = 64;
+constexpr int kRefStrideA = kPX1 + 1;      // odd strides: one bank per lane
+constexpr int kRefStrideB = 64 + 1;
+
+__global__ __launch_bounds__(kRefThreads) void decode_paper_f32_kernel(
+    fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
+    const float *__restrict__ P, const float *__restrict__ lat, int raw, int fused,
+    float *__restrict__ out_rgb, float *__restrict__ out_y4, unsigned long long *err)
+{
+    __shared__ float bufA[kRefThreads * kRefStrideA];
+    __shared__ float bufB[kRefThreads * kRefStrideB];
+    const int64_t n = g.n;
+    const int64_t p = (int64_t)blockIdx.x * kRefThreads + threadIdx.x;
+    if (p >= n)
+        return;
+    const int fid = g.fabric_id[p];
+    const float u = g.u[p], v = g.v[p], r = g.radius[p];
+    const float3 wi = make_float3(g.wi_x[p], g.wi_y[p], g.wi_z[p]);
+    const float3 wo = make_float3(g.wo_x[p], g.wo_y[p], g.wo_z[p]);
+    if (pixel_fault(fid, n_fabrics, u, v, r, wi, wo)) {
+        for (int c = 0; c < 3 && out_rgb; c++)
+            out_rgb[c * n + p] = 0.0f;
+        for (int c = 0; c < 4 && out_y4; c++)
+            out_y4[c * n + p] = 0.0f;
+        atomicAdd(err, 1ull);
+        return;
+    }
+    float *a = bufA + threadIdx.x * kRefStrideA, *b = bufB + threadIdx.x * kRefStrideB;
+    const float ang[5] = {wi.x, wi.y, wi.z, wo.x, wo.y};
+    // One layer: out[o] = act(W in + bias)[o], act the leaky ReLU (of the
+    // sum with the residual `res`, when given) or none (the output layer).
+    auto layer = [&](int w_off, int b_off, const float *in, int nin, float *out, int nout,
+                     bool act, const float *res) {
+        for (int o = 0; o < nout; o++) {
+            float acc = P[b_off + o];
+            const float *W = P + w_off + o * nin;
+#pragma unroll 8
+            for (int i = 0; i < nin; i++)
+                acc = fmaf(W[i], in[i], acc);
+            if (res)
+                acc += res[o];
+            out[o] = act ? lrelu(acc) : acc;
+        }
+    };
+    for (int k = 0; k < kPLat; k++)
+        a[k] = lat[fid * kPLat + k];
+    float f[kPBlob];
+    blob24(fabrics[fid], u, v, r, raw != 0, f);
+    for (int k = 0; k < kPBlob; k++)
+        a[kPLat + k] = f[k];
+    // F1 (without the fusion stage, A1's angular columns act here instead).
+    for (int o = 0; o < 64; o++) {
+        float acc = P[kPOffBF1 + o];
+        for (int i = 0; i < kPX1; i++)
+            acc = fmaf(P[kPOffWF1 + o * kPX1 + i], a[i], acc);
+        if (!fused)
+            for (int k = 0; k < 5; k++)
+                acc = fmaf(P[kPOffWA1 + o * kPXA1 + 64 + k], ang[k], acc);
+        b[o] = lrelu(acc);
+    }
+    layer(kPOffWF2, kPOffBF2, b, 64, a, 64, true, nullptr);                 // spatial feature
+    for (int k = 0; k < 5; k++)
+        a[64 + k] = fused ? ang[k] : 0.0f;
+    layer(kPOffWA1, kPOffBA1, a, kPXA1, b, 64, true, nullptr);             // x (block input)
+    layer(kPOffWA2, kPOffBA2, b, 64, a, 64, true, nullptr);
+    layer(kPOffWA3, kPOffBA3, a, 64, b, 64, true, b);                      // in place over x
+    layer(kPOffWA4, kPOffBA4, b, 64, a, 64, true, nullptr);
+    float y[4];
+    layer(kPOffWA5, kPOffBA5, a, 64, y, 4, false, nullptr);
+    if (out_y4)
+        for (int c = 0; c < 4; c++)
+            out_y4[c * n + p] = y[c];
+    if (out_rgb) {
+        // Eq. (8): C = max(y, 0), S = max((e^y - 1) / k, 0), k = 1000 for
+        // light from below (transmission), else 100.
+        const float k = wi.z < 0.0f ? 10.0f * kSpec : kSpec;
+        const DevFabric &fb = fabrics[fid];
+        const float C0 = fmaxf(y[0], 0.0f), C1 = fmaxf(y[1], 0.0f);
+        const float S0 = fmaxf(expm1f(y[2]) / k, 0.0f), S1 = fmaxf(expm1f(y[3]) / k, 0.0f);
+        for (int c = 0; c < 3; c++)
+            out_rgb[c * n + p] = fb.kd[0][c] * C0 + fb.kd[1][c] * C1 + fb.ks[0][c] * S0 +
+                                 fb.ks[1][c] * S1;
+    }
+}
+
 template <int P, bool RAW, bool FUSED>
 static hipError_t paper_shade(const fabric_gbuffer &g, const DevFabric *fabrics, int n_fabrics,
                               const float *cfold, const void *image, float *out,
@@ -505,6 +595,20 @@ static hipError_t paper_shade_variant(bool raw, bool fused, const fabric_gbuffer
                      : paper_shade<P, true, false>(g, fabrics, n_fabrics, cfold, image, out, err, stream);
     return fused ? paper_shade<P, false, true>(g, fabrics, n_fabrics, cfold, image, out, err, stream)
                  : paper_shade<P, false, false>(g, fabrics, n_fabrics, cfold, image, out, err, stream);
+}
+
+hipError_t launch_paper_shade_f32(bool raw, bool fused, const fabric_gbuffer &g,
+                                  const DevFabric *fabrics, int n_fabrics, const float *params,
+                                  const float *latents, float *out_rgb, float *out_y4,
+                                  unsigned long long *err, hipStream_t stream)
+{
+    if (g.n == 0)
+        return hipSuccess;
+    const int64_t blocks = (g.n + kRefThreads - 1) / kRefThreads;
+    hipLaunchKernelGGL(decode_paper_f32_kernel, dim3((unsigned)blocks), dim3(kRefThreads), 0,
+                       stream, g, fabrics, n_fabrics, params, latents, raw ? 1 : 0, fused ? 1 : 0,
+                       out_rgb, out_y4, err);
+    return hipGetLastError();
 }
 
 hipError_t launch_paper_shade(int prec, bool raw, bool fused, const fabric_gbuffer &g,

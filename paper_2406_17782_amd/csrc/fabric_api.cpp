@@ -702,15 +702,36 @@ fabric_status fabric_paper_shade(fabric_ctx *ctx, const fabric_gbuffer *g, fabri
 {
     if (!ctx || !valid_gbuffer(g) || (g->n > 0 && !out_rgb))
         return FABRIC_E_INVAL;
-    if (prec != FABRIC_BF16 && prec != FABRIC_FP16)
+    if (prec != FABRIC_BF16 && prec != FABRIC_FP16 && prec != FABRIC_FP32)
         return FABRIC_E_INVAL;
     if (ctx->paper_n_mats == 0 || ctx->paper_serial != ctx->table_serial)
         return FABRIC_E_STATE;
     if (g->n == 0)
         return FABRIC_OK;
     DeviceGuard guard(ctx->device);
+    if (prec == FABRIC_FP32)
+        return from_hip(launch_paper_shade_f32(
+            ctx->paper_raw, ctx->paper_fused, *g, ctx->fabrics, ctx->paper_n_mats,
+            ctx->paper_master, ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS, out_rgb,
+            nullptr, ctx->err, as_stream(stream)));
     return from_hip(launch_paper_shade(prec, ctx->paper_raw, ctx->paper_fused, *g, ctx->fabrics, ctx->n_mats, ctx->paper_cfold,
                                        ctx->paper_image, out_rgb, ctx->err, as_stream(stream)));
+}
+
+fabric_status fabric_paper_forward(fabric_ctx *ctx, const fabric_gbuffer *g, float *y4,
+                                   void *stream)
+{
+    if (!ctx || !valid_gbuffer(g) || (g->n > 0 && !y4))
+        return FABRIC_E_INVAL;
+    if (ctx->paper_n_mats == 0 || ctx->paper_serial != ctx->table_serial)
+        return FABRIC_E_STATE;
+    if (g->n == 0)
+        return FABRIC_OK;
+    DeviceGuard guard(ctx->device);
+    return from_hip(launch_paper_shade_f32(
+        ctx->paper_raw, ctx->paper_fused, *g, ctx->fabrics, ctx->paper_n_mats, ctx->paper_master,
+        ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS, nullptr, y4, ctx->err,
+        as_stream(stream)));
 }
 
 fabric_status fabric_set_visibility(fabric_ctx *ctx, int32_t enable)

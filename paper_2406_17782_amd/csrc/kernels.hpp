@@ -96,6 +96,12 @@ hipError_t launch_paper_shade(int prec, bool raw, bool fused, const fabric_gbuff
                               const DevFabric *fabrics, int n_fabrics, const float *cfold,
                               const void *image, float *out, unsigned long long *err,
                               hipStream_t stream);
+// FP32 reference of the same network from its FP32 parameters and latents
+// (one lane per pixel): rgb [3][n] and/or raw outputs y4 [4][n] (NULL to skip).
+hipError_t launch_paper_shade_f32(bool raw, bool fused, const fabric_gbuffer &g,
+                                  const DevFabric *fabrics, int n_fabrics, const float *params,
+                                  const float *latents, float *out_rgb, float *out_y4,
+                                  unsigned long long *err, hipStream_t stream);
 
 // Encoder forward over n_fabrics fabrics: enc_inputs[n][524] -> latents[n][32].
 hipError_t launch_encoder_forward(const float *enc_params, const float *enc_inputs,

@@ -6,7 +6,7 @@
 // layer after layer.
 #pragma once
 
-#include "common.hpp"
+#include "model.hpp"
 
 namespace fab {
 
@@ -36,5 +36,38 @@ static_assert(kPLat == FABRIC_PAPER_LATENT, "paper latent size");
 constexpr float kLeak = 0.01f;
 
 __host__ __device__ inline float lrelu(float x) { return fmaxf(x, kLeak * x); }
+
+// One-blob channels of the footprint (FP32, library functions): circular
+// position bins along u and v, then size bins.  raw (the encoding's
+// ablation): p_u, p_v and tau in channels 0, 8 and 16, zeros elsewhere.
+__device__ inline void blob24(const DevFabric &f, float u, float v, float r, bool raw,
+                              float (&x)[24])
+{
+    const float p[2] = {wrap_period(u, f.fwx, f.inv_wx) * f.inv_wx,
+                        wrap_period(v, f.fwy, f.inv_wy) * f.inv_wy};
+    if (raw) {
+#pragma unroll
+        for (int k = 0; k < 24; k++)
+            x[k] = 0.0f;
+        x[0] = p[0];
+        x[8] = p[1];
+        x[16] = fminf(fmaxf((log2f(r) + 14.0f) * (1.0f / 16.0f), 0.0f), 1.0f);
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            float d = 8.0f * p[a] - ((float)b + 0.5f);
+            d -= 8.0f * floorf((d + 4.0f) * 0.125f);
+            x[8 * a + b] = expf(-0.5f * d * d);
+        }
+    const float tau = fminf(fmaxf((log2f(r) + 14.0f) * (1.0f / 16.0f), 0.0f), 1.0f);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+        const float d = 8.0f * tau - ((float)b + 0.5f);
+        x[16 + b] = expf(-0.5f * d * d);
+    }
+}
 
 }  // namespace fab

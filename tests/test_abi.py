@@ -56,6 +56,7 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     assert lib.fabric_lerp_latents(None, None, None, None, None, 0, None) == 1
     assert lib.fabric_paper_prepare(None, None, None, None) == 1
     assert lib.fabric_paper_shade(None, None, 1, None, None) == 1
+    assert lib.fabric_paper_forward(None, None, None, None) == 1
     assert lib.fabric_paper_train_step(None, None, None, None, None, None) == 1
     assert lib.fabric_paper_loss_grad(None, None, None, None, None, None, None) == 1
     assert lib.fabric_paper_set_footprint_encoding(None, 1) == 1

@@ -125,9 +125,41 @@ def test_paper_decoder_faults_and_order(fab, pkg, torch):
     assert np.all(o[:, :4] == 0.0) and np.all(np.isfinite(o))
     pkg.fabric_paper_shade(fab.ctx, pkg.DeviceGBuffer.from_host(fi.make_gbuffer(0, 1, 4, seed=1)), out)
     with pytest.raises(pkg.FabricError) as e:
-        pkg.fabric_paper_shade(fab.ctx, d, out, "fp32")     # precision not offered
+        pkg.fabric_paper_shade(fab.ctx, d, out, "fp8")      # precision not offered
     assert e.value.status == 1
     fab.encode(mats)
     with pytest.raises(pkg.FabricError) as e:
         pkg.fabric_paper_shade(fab.ctx, d, out)            # re-encoded since prepare
     assert e.value.status == 6
+
+
+@pytest.mark.parametrize("raw,fused", [(False, True), (True, True), (False, False)])
+def test_paper_decoder_fp32_element_by_element(fab, pkg, orc, torch, raw, fused):
+    """The FP32 reference (fabric_paper_forward / fabric_paper_shade with
+    FABRIC_FP32): every raw output and every rgb value against the FP64
+    oracle within 1e-5 of the frame's largest magnitude per channel (FP32
+    through seven layers of 64-term sums: ~1e-6), for the paper's network
+    and its two ablations; a ragged frame with 8 fabrics per pixel, pixels
+    lit from below and a faulted pixel."""
+    mats = fi.materials_for(8, 360)
+    g = fi.make_gbuffer(53, 29, 8, seed=361, btdf_frac=0.3)
+    g.fabric_id[:] = np.random.default_rng(362).integers(0, 8, g.n).astype(np.uint16)
+    g.radius[7] = -1.0                                            # a fault
+    params, z = prepare(fab, pkg, torch, mats, 363)
+    pkg.fabric_paper_set_footprint_encoding(fab.ctx, not raw)
+    pkg.fabric_paper_set_spatial_fusion(fab.ctx, fused)
+    d = pkg.DeviceGBuffer.from_host(g)
+    y4 = torch.empty((4, g.n), dtype=torch.float32, device="cuda")
+    rgb = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
+    fab.error_count(reset=True)
+    pkg.fabric_paper_forward(fab.ctx, d, y4)
+    pkg.fabric_paper_shade(fab.ctx, d, rgb, "fp32")
+    oy, orgb = orc.paper_decoder_gbuffer(params, z, mats, g, raw=raw, fused=fused)
+    for name, a, b in (("y", y4.cpu().numpy(), oy), ("rgb", rgb.cpu().numpy(), orgb)):
+        scale = np.abs(b).max(axis=1, keepdims=True)
+        err = np.abs(a - b) / scale
+        print(f"raw={raw} fused={fused} {name}: max err {err.max():.3g}")
+        assert err.max() < 1e-5, (name, err.max())
+    assert np.all(y4.cpu().numpy()[:, 7] == 0) and fab.error_count() == 2
+    pkg.fabric_paper_set_footprint_encoding(fab.ctx, True)
+    pkg.fabric_paper_set_spatial_fusion(fab.ctx, True)
