@@ -388,6 +388,23 @@ def init_paper_params(seed: int, bias_scale: float = 0.0) -> np.ndarray:
     return _f32(np.concatenate(out))
 
 
+# The paper-size network's encoder: the config encoder's layers with a
+# latent of 64 (E1 [128][524] .. E4 [64][128], c4 [64]).
+PAPER_ENCODER_SHAPES = [(128, 524), (128, 128), (128, 128), (64, 128)]
+N_PAPER_ENCODER_PARAMS = _layer_sizes(PAPER_ENCODER_SHAPES)   # 108,480
+
+
+def init_paper_encoder_params(seed: int, bias_scale: float = 0.0) -> np.ndarray:
+    """Paper-size encoder parameters, Kaiming-uniform like init_params."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for o, i in PAPER_ENCODER_SHAPES:
+        bound = math.sqrt(6.0 / i)
+        out.append(rng.uniform(-bound, bound, size=o * i))
+        out.append(rng.uniform(-bias_scale, bias_scale, size=o) if bias_scale > 0 else np.zeros(o))
+    return _f32(np.concatenate(out))
+
+
 def random_targets(n: int, seed: int) -> np.ndarray:
     """Plausible component targets [4][n]: C in [0, 0.4], S log-spread."""
     rng = np.random.default_rng(seed)

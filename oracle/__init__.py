@@ -109,6 +109,10 @@ def lib():
                                                 ctypes.c_int, ctypes.c_int, _P, _P]
         L.orc_paper_features_raw.argtypes = L.orc_paper_features.argtypes
         L.orc_encoder_batch.argtypes = [_P, _P, ctypes.c_int, _P]
+        L.orc_encoder_batch_n.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int, _P]
+        L.orc_encoder_param_count.restype = ctypes.c_int
+        L.orc_encoder_param_count.argtypes = [ctypes.c_int]
+        L.orc_encoder_backward_batch.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int, _P, _P]
         L.orc_paper_loss_grad.restype = ctypes.c_double
         L.orc_paper_loss_grad.argtypes = [_P, _P, _P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int,
                                           _P, _P, _P]
@@ -374,11 +378,27 @@ def encoder_input(mat) -> np.ndarray:
     return x
 
 
-def encoder(params_enc, mats: Sequence) -> np.ndarray:
+def encoder_param_count(lat: int = 32) -> int:
+    return int(lib().orc_encoder_param_count(int(lat)))
+
+
+def encoder(params_enc, mats: Sequence, lat: int = 32) -> np.ndarray:
+    """Latents [n_mats][lat] of the encoder (lat 32: the config-size network,
+    64: the paper-size network's encoder)."""
     Q = _d(params_enc)
-    z = np.zeros((len(mats), 32))
-    lib().orc_encoder_batch(_ptr(Q), materials(mats), len(mats), _ptr(z))
+    assert Q.size == encoder_param_count(lat)
+    z = np.zeros((len(mats), lat))
+    lib().orc_encoder_batch_n(_ptr(Q), materials(mats), len(mats), int(lat), _ptr(z))
     return z
+
+
+def encoder_backward(params_enc, mats: Sequence, dz, lat: int = 32) -> np.ndarray:
+    """Gradient of the encoder parameters from the latents' gradients dz [n_mats][lat]."""
+    Q = _d(params_enc)
+    D = _d(dz).reshape(-1)
+    grad = np.zeros(encoder_param_count(lat))
+    lib().orc_encoder_backward_batch(_ptr(Q), materials(mats), len(mats), int(lat), _ptr(D), _ptr(grad))
+    return grad
 
 
 def parameter_weight(p: float, p_a: float, p_b: float) -> float:

@@ -1305,13 +1305,21 @@ void orc_encoder_input(const orc_material *m, double x[ENC_IN])
 
 typedef struct {
     double x[ENC_IN], a1[ENC_HID], e1[ENC_HID], a2[ENC_HID], r2[ENC_HID], a3[ENC_HID],
-        e2[ENC_HID], z[LATENT];
+        e2[ENC_HID], z[PLATENT];
 } enc_acts;
+
+/* The encoder's last layer for a latent of `lat` values: E4 [lat][128] at
+ * OFF_E4, then c4 [lat]; the layers before it do not depend on lat. */
+static int enc_off_c4(int lat) { return OFF_E4 + lat * ENC_HID; }
+
+/* Encoder parameters for a latent of `lat` values (32: the config-size
+ * network, 64: the paper-size network's encoder). */
+int orc_encoder_param_count(int lat) { return enc_off_c4(lat) + lat; }
 
 /* e1 = relu(E1 x + c1); residual block e2 = relu(e1 + E3 relu(E2 e1 + c2) + c3)
  * (two fully connected layers, skip added before the last activation, Sec. 4.2);
- * z = E4 e2 + c4. */
-static void encoder_forward(const double *Q, const orc_material *m, enc_acts *A)
+ * z = E4 e2 + c4 with `lat` outputs. */
+static void encoder_forward_n(const double *Q, const orc_material *m, int lat, enc_acts *A)
 {
     orc_encoder_input(m, A->x);
     dense(Q + OFF_E1, Q + OFF_C1, A->x, ENC_IN, ENC_HID, A->a1);
@@ -1321,14 +1329,20 @@ static void encoder_forward(const double *Q, const orc_material *m, enc_acts *A)
     dense(Q + OFF_E3, Q + OFF_C3, A->r2, ENC_HID, ENC_HID, A->a3);
     for (int k = 0; k < ENC_HID; k++) A->a3[k] += A->e1[k];
     for (int k = 0; k < ENC_HID; k++) A->e2[k] = relu(A->a3[k]);
-    dense(Q + OFF_E4, Q + OFF_C4, A->e2, ENC_HID, LATENT, A->z);
+    dense(Q + OFF_E4, Q + enc_off_c4(lat), A->e2, ENC_HID, lat, A->z);
 }
 
-static void encoder_backward(const double *Q, const enc_acts *A, const double dz[LATENT], double *G)
+static void encoder_forward(const double *Q, const orc_material *m, enc_acts *A)
+{
+    encoder_forward_n(Q, m, LATENT, A);
+}
+
+static void encoder_backward_n(const double *Q, const enc_acts *A, const double *dz, int lat,
+                               double *G)
 {
     double de2[ENC_HID], da3[ENC_HID], dr2[ENC_HID], da2[ENC_HID], de1[ENC_HID], da1[ENC_HID],
         dx[ENC_IN];
-    dense_backward(Q + OFF_E4, A->e2, dz, ENC_HID, LATENT, G + OFF_E4, G + OFF_C4, de2);
+    dense_backward(Q + OFF_E4, A->e2, dz, ENC_HID, lat, G + OFF_E4, G + enc_off_c4(lat), de2);
     for (int k = 0; k < ENC_HID; k++) da3[k] = A->a3[k] > 0.0 ? de2[k] : 0.0;
     dense_backward(Q + OFF_E3, A->r2, da3, ENC_HID, ENC_HID, G + OFF_E3, G + OFF_C3, dr2);
     for (int k = 0; k < ENC_HID; k++) da2[k] = A->a2[k] > 0.0 ? dr2[k] : 0.0;
@@ -1338,14 +1352,38 @@ static void encoder_backward(const double *Q, const enc_acts *A, const double dz
     dense_backward(Q + OFF_E1, A->x, da1, ENC_IN, ENC_HID, G + OFF_E1, G + OFF_C1, dx);
 }
 
-/* z[nmats][32] from the encoder parameters Q. */
-void orc_encoder_batch(const double *Q, const orc_material *mats, int nmats, double *z)
+static void encoder_backward(const double *Q, const enc_acts *A, const double dz[LATENT], double *G)
+{
+    encoder_backward_n(Q, A, dz, LATENT, G);
+}
+
+/* z[nmats][lat] from the encoder parameters Q of a latent of lat values. */
+void orc_encoder_batch_n(const double *Q, const orc_material *mats, int nmats, int lat, double *z)
 {
     for (int f = 0; f < nmats; f++) {
         enc_acts A;
-        encoder_forward(Q, &mats[f], &A);
-        for (int k = 0; k < LATENT; k++)
-            z[f * LATENT + k] = A.z[k];
+        encoder_forward_n(Q, &mats[f], lat, &A);
+        for (int k = 0; k < lat; k++)
+            z[f * lat + k] = A.z[k];
+    }
+}
+
+/* z[nmats][32] from the encoder parameters Q. */
+void orc_encoder_batch(const double *Q, const orc_material *mats, int nmats, double *z)
+{
+    orc_encoder_batch_n(Q, mats, nmats, LATENT, z);
+}
+
+/* Gradient of the encoder parameters (grad, overwritten) from the latents'
+ * gradients dz[nmats][lat], summed over the fabrics in order. */
+void orc_encoder_backward_batch(const double *Q, const orc_material *mats, int nmats, int lat,
+                                const double *dz, double *grad)
+{
+    memset(grad, 0, sizeof(double) * orc_encoder_param_count(lat));
+    for (int f = 0; f < nmats; f++) {
+        enc_acts A;
+        encoder_forward_n(Q, &mats[f], lat, &A);
+        encoder_backward_n(Q, &A, dz + (size_t)f * lat, lat, grad);
     }
 }
 
