@@ -441,16 +441,24 @@ def paper_decoder_row(args, torch, pkg, fi, mats, g, d):
         fab.close()
 
 
-def train_paper_network(args, torch, pkg, fi, mats, steps, one_blob=True, fused=True):
+def train_paper_network(args, torch, pkg, fi, mats, steps, one_blob=True, fused=True,
+                        encoder=False):
     """A paper-size decoder trained on `mats` (one latent of 64 per fabric
-    trained as a parameter; FP32 training kernels; generated batches of 2^16
+    trained as a parameter, or with encoder=True the paper-size encoder
+    trained beside it; FP32 training kernels; generated batches of 2^16
     samples with 256-sample targets; Adam with the main network's
     cosine-decayed rate).  Returns the open context and the training record."""
     fab = pkg.Fabric(0, seed=4600)
     fab.encode(mats)
     params = fi.init_paper_params(5, bias_scale=0.0)
-    z = fi.random_latents(len(mats), 6, scale=0.1, dim=64)
-    pkg.fabric_paper_prepare(fab.ctx, torch.from_numpy(params).cuda(), torch.from_numpy(z).cuda())
+    if encoder:
+        enc = fi.init_paper_encoder_params(6, bias_scale=0.0)
+        pkg.fabric_paper_prepare_encoder(fab.ctx, torch.from_numpy(params).cuda(),
+                                         torch.from_numpy(enc).cuda())
+    else:
+        z = fi.random_latents(len(mats), 6, scale=0.1, dim=64)
+        pkg.fabric_paper_prepare(fab.ctx, torch.from_numpy(params).cuda(),
+                                 torch.from_numpy(z).cuda())
     pkg.fabric_paper_set_footprint_encoding(fab.ctx, one_blob)
     pkg.fabric_paper_set_spatial_fusion(fab.ctx, fused)
     batch = 1 << 16
@@ -479,7 +487,8 @@ def train_paper_network(args, torch, pkg, fi, mats, steps, one_blob=True, fused=
            "step_tflops": tflops,
            "step_frac_of_unpacked_fp32": tflops / FP32_UNPACKED_PEAK_TFLOPS if steps else None,
            "loss_first": losses[0] if losses else None, "loss_last": losses[-1] if losses else None,
-           "footprint_encoding": "one-blob" if one_blob else "none", "spatial_fusion": fused}
+           "footprint_encoding": "one-blob" if one_blob else "none", "spatial_fusion": fused,
+           "latents": "paper-size encoder" if encoder else "one per fabric, trained as parameters"}
     return fab, rec
 
 
@@ -511,7 +520,6 @@ def paper_training_row(args, torch, pkg, fi, mats, g, d, config_rgb):
     analytic sample."""
     fab, res = train_paper_network(args, torch, pkg, fi, mats, args.paper_train_steps)
     try:
-        res["latents"] = "one per fabric, trained as parameters"
         out = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
         fp16 = lambda: pkg.fabric_paper_shade(fab.ctx, d, out, "fp16")
         for _ in range(100):
@@ -572,6 +580,56 @@ def ablation_row(args, torch, pkg, fi, mats, g, d):
     return res
 
 
+def slot_frame(torch, d, slot):
+    """The G-buffer `d` with every pixel showing fabric `slot`."""
+    import dataclasses
+    fid = torch.from_numpy(np.full(d.n, slot, dtype=np.int16)).to("cuda").view(torch.uint16)
+    return dataclasses.replace(d, fabric_id=fid)
+
+
+def paper_encoder_row(args, torch, pkg, fi, d):
+    """The paper-size network with its encoder (Sec. 4.2 "Encoder"), encoder
+    and decoder trained together on the interpolation row's 64 twill
+    variants; then 8 of those variants and 8 new draws of the same family,
+    encoded by one call and each shaded (FP16) over a 1080p frame showing it
+    alone, against the 256-sample filter: the encoder lets fabrics it never
+    saw be shaded from their parameters."""
+    train = fi.sweep_training_set(64, 4400)
+    fab, rec = train_paper_network(args, torch, pkg, fi, train, args.paper_encoder_train_steps,
+                                   encoder=True)
+    try:
+        seen = train[:8]
+        unseen = fi.sweep_training_set(8, 4400, variant_seed=4499)
+        fab.encode(seen + unseen)
+        pkg.fabric_paper_encode(fab.ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(100):
+            pkg.fabric_paper_encode(fab.ctx)
+        torch.cuda.synchronize()
+        encode_ms = (time.perf_counter() - t0) / 100 * 1e3
+        out = torch.empty((3, d.n), dtype=torch.float32, device="cuda")
+        rel = lambda x, y: float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-30))
+        errs = []
+        for k in range(16):
+            f = slot_frame(torch, d, k)
+            pkg.fabric_paper_shade(fab.ctx, f, out, "fp16")
+            nn = out.cpu().numpy().astype(np.float64)
+            pkg.fabric_gt_filtered(fab.ctx, f, args.gt_samples, 4242, out, None)
+            errs.append(rel(nn, out.cpu().numpy().astype(np.float64)))
+        rec["generalisation"] = {
+            "seen_mean": float(np.mean(errs[:8])), "seen_max": float(np.max(errs[:8])),
+            "unseen_mean": float(np.mean(errs[8:])), "unseen_max": float(np.max(errs[8:])),
+            "metric": "relative L2 of the FP16 frame against the 256-sample filter"}
+        rec["training_table"] = "64 twill variants"
+        rec["encode_16_fabrics_ms"] = encode_ms
+        log(f"paper-size encoder: loss {rec['loss_first']} -> {rec['loss_last']}; seen "
+            f"{rec['generalisation']['seen_mean']:.4f}, unseen {rec['generalisation']['unseen_mean']:.4f}")
+        return rec
+    finally:
+        fab.close()
+
+
 def interp_row(args, torch, pkg, fi, g, d):
     """Latent interpolation study (Sec. 5 "Interpolation") on the 1080p
     frame's geometry: a second network trained on variants of one twill whose
@@ -579,7 +637,6 @@ def interp_row(args, torch, pkg, fi, g, d):
     0.2 and 0.8, blended on the GPU at 0.3 and 0.6 and extrapolated to 0.9.
     Every pixel of a frame shows one slot; each blended frame is compared with
     the directly encoded one and with the analytic filter at 256 samples."""
-    import dataclasses
     fab = pkg.Fabric(0, seed=4343)
     try:
         fab.encode(fi.sweep_training_set(64, 4400))
@@ -604,8 +661,7 @@ def interp_row(args, torch, pkg, fi, g, d):
                 t.append((p - p0) / (p1 - p0))
 
         def frame(slot):
-            fid = torch.from_numpy(np.full(g.n, slot, dtype=np.int16)).to("cuda").view(torch.uint16)
-            return dataclasses.replace(d, fabric_id=fid)
+            return slot_frame(torch, d, slot)
 
         frames = [frame(k) for k in range(len(table))]
         out = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
@@ -690,6 +746,8 @@ def main():
                     help="training steps of the latent interpolation row's network")
     ap.add_argument("--paper-train-steps", type=int, default=96000,
                     help="training steps (2^16 samples each) of the paper-size decoder's row")
+    ap.add_argument("--paper-encoder-train-steps", type=int, default=24000,
+                    help="training steps (2^16 samples each) of the paper-size encoder's row")
     ap.add_argument("--ablation-train-steps", type=int, default=12000,
                     help="training steps of each network of the ablation row")
     ap.add_argument("--analytic-steps", type=int, default=10)
@@ -842,6 +900,7 @@ def main():
         rows["paper_decoder"] = paper_decoder_row(args, torch, pkg, fi, mats, g, d)
         rows["paper_training"] = paper_training_row(args, torch, pkg, fi, mats, g, d, rgb["bf16"])
         rows["ablations"] = ablation_row(args, torch, pkg, fi, mats, g, d)
+        rows["paper_encoder"] = paper_encoder_row(args, torch, pkg, fi, d)
 
     # ---- error against the FP64 oracle on a seeded pixel subset ----
     args.neural_ms = ms

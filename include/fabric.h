@@ -79,6 +79,8 @@ typedef enum {
 #define FABRIC_NOALLOC_MAX_PIXELS 4194304
 #define FABRIC_PAPER_LATENT 64
 #define FABRIC_N_PAPER_DECODER_PARAMS 27076
+/* The paper-size network's encoder (E1..E3 as the config encoder's, E4 [64][128], c4 [64]). */
+#define FABRIC_N_PAPER_ENCODER_PARAMS 108480
 
 /* One fabric: the weave pattern and the Table 1 parameters per yarn type
  * ([0] = warp, [1] = weft).  Host memory, copied by fabric_encode.
@@ -230,6 +232,30 @@ fabric_status fabric_paper_prepare(fabric_ctx *ctx, const float *params, const f
 fabric_status fabric_paper_shade(fabric_ctx *ctx, const fabric_gbuffer *g, fabric_prec prec,
                                  float *out_rgb, void *stream);
 
+/* The paper-size network with its latents from an encoder (Sec. 4.2
+ * "Encoder", in this library's reading: the residual MLP of
+ * fabric_encoder_forward over the same per-fabric inputs, widened to
+ * FABRIC_PAPER_LATENT outputs) rather than trained as parameters, so that a
+ * fabric never seen in training is shaded from its inputs alone.
+ *   params      device float [FABRIC_N_PAPER_DECODER_PARAMS], as
+ *               fabric_paper_prepare
+ *   enc_params  device float [FABRIC_N_PAPER_ENCODER_PARAMS]: E1[128][524]
+ *               c1 E2[128][128] c2 E3[128][128] c3 E4[64][128] c4[64]
+ * fabric_paper_prepare_encoder keeps its own copy of both (the masters that
+ * fabric_paper_train_step then updates together, Adam state reset), encodes
+ * the current fabric table and packs the shading image, all on `stream`.
+ * fabric_paper_encode re-encodes the table of the last fabric_encode with
+ * the current masters (a new table of unseen fabrics, for instance) and
+ * re-packs; fabric_paper_prepare leaves encoder mode.  In encoder mode
+ * fabric_paper_get_params returns the encoder's latents, and
+ * fabric_paper_get_encoder copies enc_params to host (synchronises).
+ * Errors: E_INVAL for NULL pointers; E_STATE before any fabric_encode, and
+ * for encode and get_encoder outside encoder mode. */
+fabric_status fabric_paper_prepare_encoder(fabric_ctx *ctx, const float *params,
+                                           const float *enc_params, void *stream);
+fabric_status fabric_paper_encode(fabric_ctx *ctx, void *stream);
+fabric_status fabric_paper_get_encoder(fabric_ctx *ctx, float *enc_params_host);
+
 /* The paper-size decoder's raw outputs (y of Sec. 4.2 before the decoding of
  * Eq. (9): C_warp, C_weft, S_warp, S_weft in the log-mapped domain), in FP32
  * from the parameters and latents of the last fabric_paper_prepare or
@@ -377,21 +403,25 @@ fabric_status fabric_loss_grad(fabric_ctx *ctx, const fabric_gbuffer *batch, con
 
 /* Training of the paper-size decoder (Sec. 4.2 "Decoder", loss of
  * Eq. (9)-(11)) on the context's masters from fabric_paper_prepare, with
- * one latent of FABRIC_PAPER_LATENT per fabric trained as a parameter (the
- * paper's ResNet encoder of normal and orientation maps is not part of this
- * library).  The batch, targets and cfg behave as for fabric_train_step
+ * one latent of FABRIC_PAPER_LATENT per fabric trained as a parameter, or
+ * from fabric_paper_prepare_encoder, with the encoder trained beside the
+ * decoder (the paper's convolutional encoder of normal and orientation maps
+ * is not part of this library).  The batch, targets and cfg behave as for fabric_train_step
  * (generated batch and 256-sample targets by default, visibility as set by
  * fabric_set_visibility); cfg->prec must be FABRIC_FP32: the forward and
  * backward run in FP32 on the vector units, one sample per lane, with
  * fixed-order split-K weight gradients, and Adam keeps FP64 moments.
- * fabric_paper_train_step takes one Adam step over [params | latents] and
- * re-packs the shading image from the updated masters; a non-finite loss
- * (known only when out_loss != NULL) skips the update and returns
- * E_NONFINITE.  fabric_paper_loss_grad writes the gradient to device
- * `grad` [FABRIC_N_PAPER_DECODER_PARAMS + n_mats * FABRIC_PAPER_LATENT]
- * (parameter layout of fabric_paper_prepare, then the latents).
+ * fabric_paper_train_step takes one Adam step over [params | latents]
+ * ([params | enc_params] in encoder mode) and re-packs the shading image
+ * from the updated masters; a non-finite loss (known only when
+ * out_loss != NULL) skips the update and returns E_NONFINITE.
+ * fabric_paper_loss_grad writes the gradient to device `grad`
+ * [FABRIC_N_PAPER_DECODER_PARAMS + n_mats * FABRIC_PAPER_LATENT]
+ * (parameter layout of fabric_paper_prepare, then the latents), in encoder
+ * mode [FABRIC_N_PAPER_DECODER_PARAMS + FABRIC_N_PAPER_ENCODER_PARAMS].
  * Errors: as fabric_train_step; E_STATE before fabric_paper_prepare or
- * after a later fabric_encode; E_RANGE for more than 64 fabrics. */
+ * after a later fabric_encode (until fabric_paper_encode in encoder mode);
+ * E_RANGE for more than 64 fabrics. */
 fabric_status fabric_paper_train_step(fabric_ctx *ctx, const fabric_gbuffer *batch,
                                       const float *targets, const fabric_train_cfg *cfg,
                                       float *out_loss, void *stream);

@@ -17,7 +17,8 @@ import numpy as np
 from . import _abi
 from ._abi import (FABRIC_BF16, FABRIC_FP8_E4M3, FABRIC_FP16, FABRIC_FP32, FABRIC_LATENT,
                    FABRIC_MAX_FABRICS, FABRIC_MAX_SAMPLES, FABRIC_N_DECODER_PARAMS,
-                   FABRIC_N_ENCODER_PARAMS, FABRIC_N_PAPER_DECODER_PARAMS, FABRIC_N_PARAMS,
+                   FABRIC_N_ENCODER_PARAMS, FABRIC_N_PAPER_DECODER_PARAMS,
+                   FABRIC_N_PAPER_ENCODER_PARAMS, FABRIC_N_PARAMS,
                    FABRIC_PAPER_LATENT, PREC, FabricError, check)
 
 __all__ = [
@@ -26,6 +27,8 @@ __all__ = [
     "FABRIC_MAX_FABRICS", "FABRIC_MAX_SAMPLES", "FABRIC_LATENT",
     "fabric_create", "fabric_destroy", "fabric_encode", "fabric_set_albedo", "fabric_lerp_latents",
     "fabric_set_visibility", "fabric_paper_prepare", "fabric_paper_shade", "fabric_paper_forward",
+    "fabric_paper_prepare_encoder", "fabric_paper_encode", "fabric_paper_get_encoder",
+    "FABRIC_N_PAPER_ENCODER_PARAMS",
     "fabric_paper_train_step", "fabric_paper_loss_grad", "fabric_paper_get_params",
     "fabric_paper_set_footprint_encoding", "fabric_paper_set_spatial_fusion", "FABRIC_PAPER_LATENT", "FABRIC_N_PAPER_DECODER_PARAMS",
     "fabric_shade_gbuffer", "fabric_shade_gbuffer_noalloc", "fabric_gt_filtered",
@@ -144,6 +147,21 @@ def fabric_set_albedo(ctx, fabric: int, kd, ks, stream=None) -> None:
 def fabric_paper_prepare(ctx, params, latents, stream=None) -> None:
     check(_abi.lib().fabric_paper_prepare(ctx, _dptr(params), _dptr(latents), _stream(stream)),
           "fabric_paper_prepare")
+
+
+def fabric_paper_prepare_encoder(ctx, params, enc_params, stream=None) -> None:
+    check(_abi.lib().fabric_paper_prepare_encoder(ctx, _dptr(params), _dptr(enc_params),
+                                                  _stream(stream)), "fabric_paper_prepare_encoder")
+
+
+def fabric_paper_encode(ctx, stream=None) -> None:
+    check(_abi.lib().fabric_paper_encode(ctx, _stream(stream)), "fabric_paper_encode")
+
+
+def fabric_paper_get_encoder(ctx) -> np.ndarray:
+    out = np.zeros(FABRIC_N_PAPER_ENCODER_PARAMS, dtype=np.float32)
+    check(_abi.lib().fabric_paper_get_encoder(ctx, out.ctypes.data), "fabric_paper_get_encoder")
+    return out
 
 
 def fabric_paper_shade(ctx, g: DeviceGBuffer, out_rgb, prec: str = "bf16", stream=None) -> None:

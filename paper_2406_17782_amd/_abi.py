@@ -27,6 +27,7 @@ FABRIC_LATENT = 32
 FABRIC_N_DECODER_PARAMS = 13572
 FABRIC_PAPER_LATENT = 64
 FABRIC_N_PAPER_DECODER_PARAMS = 27076
+FABRIC_N_PAPER_ENCODER_PARAMS = 108480
 FABRIC_N_ENCODER_PARAMS = 104352
 FABRIC_N_PARAMS = FABRIC_N_DECODER_PARAMS + FABRIC_N_ENCODER_PARAMS
 
@@ -65,7 +66,8 @@ class fabric_train_cfg(ctypes.Structure):
 EXPORTS = [
     "fabric_create", "fabric_destroy", "fabric_status_str", "fabric_encode", "fabric_set_albedo",
     "fabric_lerp_latents", "fabric_set_visibility", "fabric_paper_prepare", "fabric_paper_shade",
-    "fabric_paper_forward",
+    "fabric_paper_forward", "fabric_paper_prepare_encoder", "fabric_paper_encode",
+    "fabric_paper_get_encoder",
     "fabric_paper_train_step", "fabric_paper_loss_grad", "fabric_paper_get_params",
     "fabric_paper_set_footprint_encoding", "fabric_paper_set_spatial_fusion",
     "fabric_shade_gbuffer", "fabric_shade_gbuffer_noalloc", "fabric_gt_filtered",
@@ -95,6 +97,12 @@ def _declare(L):
     L.fabric_set_visibility.restype = _S
     L.fabric_paper_prepare.argtypes = [_P, _P, _P, _P]
     L.fabric_paper_prepare.restype = _S
+    L.fabric_paper_prepare_encoder.argtypes = [_P, _P, _P, _P]
+    L.fabric_paper_prepare_encoder.restype = _S
+    L.fabric_paper_encode.argtypes = [_P, _P]
+    L.fabric_paper_encode.restype = _S
+    L.fabric_paper_get_encoder.argtypes = [_P, _P]
+    L.fabric_paper_get_encoder.restype = _S
     L.fabric_paper_shade.argtypes = [_P, ctypes.POINTER(fabric_gbuffer), ctypes.c_int, _P, _P]
     L.fabric_paper_shade.restype = _S
     L.fabric_paper_forward.argtypes = [_P, ctypes.POINTER(fabric_gbuffer), _P, _P]

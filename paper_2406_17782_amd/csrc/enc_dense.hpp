@@ -66,4 +66,113 @@ __device__ inline void enc_dense_cols(const float *__restrict__ W, const float *
     __syncthreads();
 }
 
+// The encoder for a latent of LAT values (32: the config-size network, 64:
+// the paper-size network's encoder): layers E1 .. E3 as above, then E4
+// [LAT][128] and c4 [LAT].
+template <int LAT> constexpr int enc_off_c4() { return kOffE4 + LAT * kEncHid; }
+template <int LAT> constexpr int enc_param_count() { return enc_off_c4<LAT>() + LAT; }
+// Per-fabric backward scratch: x[524] e1 r2 e2 d1 d2 d3 [128 each] dz[LAT].
+template <int LAT> constexpr int enc_act_floats() { return kEncIn + 6 * kEncHid + LAT; }
+
+// Forward of one fabric by one 256-thread block:
+// e1 = relu(E1 x + c1), e2 = relu(e1 + E3 relu(E2 e1 + c2) + c3), z = E4 e2 + c4.
+template <int LAT>
+__device__ inline void encoder_forward_block(const float *__restrict__ Q, const float *__restrict__ in,
+                                             float *__restrict__ z_out)
+{
+    __shared__ float x[kEncIn];
+    __shared__ float e1[kEncHid], r2[kEncHid], e2[kEncHid], z[LAT];
+    for (int k = threadIdx.x; k < kEncIn; k += blockDim.x)
+        x[k] = in[k];
+    __syncthreads();
+    enc_dense_rows(Q + kOffE1, Q + kOffC1, x, kEncIn, kEncHid, e1, true, nullptr);
+    enc_dense_rows(Q + kOffE2, Q + kOffC2, e1, kEncHid, kEncHid, r2, true, nullptr);
+    enc_dense_rows(Q + kOffE3, Q + kOffC3, r2, kEncHid, kEncHid, e2, true, e1);
+    enc_dense_rows(Q + kOffE4, Q + enc_off_c4<LAT>(), e2, kEncHid, LAT, z, false, nullptr);
+    for (int k = threadIdx.x; k < LAT; k += blockDim.x)
+        z_out[k] = z[k];
+}
+
+// Backward of one fabric by one 256-thread block: recompute the forward,
+// backpropagate dz to the layers' pre-activation gradients and store the
+// inputs and gradients the weight gradients need (layout of enc_act_floats).
+template <int LAT>
+__device__ inline void encoder_backward_block(const float *__restrict__ Q, const float *__restrict__ in,
+                                              const float *__restrict__ dz, float *__restrict__ out)
+{
+    __shared__ float x[kEncIn], a1[kEncHid], e1[kEncHid], a2[kEncHid], r2[kEncHid],
+        a3[kEncHid], e2[kEncHid], g[kEncHid], d3[kEncHid], d2[kEncHid], d1[kEncHid], dzs[LAT];
+    for (int k = threadIdx.x; k < kEncIn; k += blockDim.x)
+        x[k] = in[k];
+    for (int k = threadIdx.x; k < LAT; k += blockDim.x)
+        dzs[k] = dz[k];
+    __syncthreads();
+    enc_dense_rows(Q + kOffE1, Q + kOffC1, x, kEncIn, kEncHid, a1, false, nullptr);
+    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
+        e1[k] = fmaxf(a1[k], 0.0f);
+    __syncthreads();
+    enc_dense_rows(Q + kOffE2, Q + kOffC2, e1, kEncHid, kEncHid, a2, false, nullptr);
+    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
+        r2[k] = fmaxf(a2[k], 0.0f);
+    __syncthreads();
+    enc_dense_rows(Q + kOffE3, Q + kOffC3, r2, kEncHid, kEncHid, a3, false, nullptr);
+    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x) {
+        a3[k] += e1[k];                     // skip connection before the activation
+        e2[k] = fmaxf(a3[k], 0.0f);
+    }
+    __syncthreads();
+    enc_dense_cols(Q + kOffE4, dzs, LAT, kEncHid, g);              // dL/de2
+    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
+        d3[k] = a3[k] > 0.0f ? g[k] : 0.0f;
+    __syncthreads();
+    enc_dense_cols(Q + kOffE3, d3, kEncHid, kEncHid, g);           // dL/dr2
+    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
+        d2[k] = a2[k] > 0.0f ? g[k] : 0.0f;
+    __syncthreads();
+    enc_dense_cols(Q + kOffE2, d2, kEncHid, kEncHid, g);           // dL/de1 (through E2)
+    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
+        d1[k] = a1[k] > 0.0f ? g[k] + d3[k] : 0.0f;               // plus the skip path
+    __syncthreads();
+    for (int k = threadIdx.x; k < kEncIn; k += blockDim.x)
+        out[k] = x[k];
+    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x) {
+        out[kEncIn + k] = e1[k];
+        out[kEncIn + kEncHid + k] = r2[k];
+        out[kEncIn + 2 * kEncHid + k] = e2[k];
+        out[kEncIn + 3 * kEncHid + k] = d1[k];
+        out[kEncIn + 4 * kEncHid + k] = d2[k];
+        out[kEncIn + 5 * kEncHid + k] = d3[k];
+    }
+    for (int k = threadIdx.x; k < LAT; k += blockDim.x)
+        out[kEncIn + 6 * kEncHid + k] = dzs[k];
+}
+
+// Encoder parameter e's gradient: the sum over fabrics, in order, of the
+// products of its layer's output gradient and input in the scratch of
+// encoder_backward_block.
+template <int LAT>
+__device__ inline float encoder_wgrad_entry(const float *__restrict__ scratch, int n_fabrics, int e)
+{
+    constexpr int kAct = enc_act_floats<LAT>();
+    constexpr int kC4 = enc_off_c4<LAT>();
+    // (delta offset, input offset, fan-in) of the tensor holding e
+    int dofs, xofs, nin, idx;
+    if (e < kOffC1) { dofs = kEncIn + 3 * kEncHid; xofs = 0; nin = kEncIn; idx = e - kOffE1; }
+    else if (e < kOffE2) { dofs = kEncIn + 3 * kEncHid; xofs = -1; nin = 1; idx = e - kOffC1; }
+    else if (e < kOffC2) { dofs = kEncIn + 4 * kEncHid; xofs = kEncIn; nin = kEncHid; idx = e - kOffE2; }
+    else if (e < kOffE3) { dofs = kEncIn + 4 * kEncHid; xofs = -1; nin = 1; idx = e - kOffC2; }
+    else if (e < kOffC3) { dofs = kEncIn + 5 * kEncHid; xofs = kEncIn + kEncHid; nin = kEncHid; idx = e - kOffE3; }
+    else if (e < kOffE4) { dofs = kEncIn + 5 * kEncHid; xofs = -1; nin = 1; idx = e - kOffC3; }
+    else if (e < kC4) { dofs = kEncIn + 6 * kEncHid; xofs = kEncIn + 2 * kEncHid; nin = kEncHid; idx = e - kOffE4; }
+    else { dofs = kEncIn + 6 * kEncHid; xofs = -1; nin = 1; idx = e - kC4; }
+    const int o = idx / nin, i = idx % nin;
+    float acc = 0.0f;
+    for (int f = 0; f < n_fabrics; f++) {
+        const float *s = scratch + (size_t)f * kAct;
+        const float x = xofs >= 0 ? s[xofs + i] : 1.0f;
+        acc = fmaf(s[dofs + o], x, acc);
+    }
+    return acc;
+}
+
 }  // namespace fab

@@ -1,7 +1,8 @@
-// Material encoder forward (Sec. 4.2 "Encoder", in this library's size):
+// Material encoder forward (Sec. 4.2 "Encoder", in this library's sizes):
 // the weave as a 16x16 one-hot grid plus 12 normalised yarn scalars ->
 // e1 = relu(E1 x + c1) -> residual block e2 = relu(e1 + E3 relu(E2 e1 + c2) + c3)
-// -> z = E4 e2 + c4.  One 256-thread block per fabric; each dense layer runs
+// -> z = E4 e2 + c4 (a latent of 32 for the config-size network, 64 for the
+// paper-size one).  One 256-thread block per fabric; each dense layer runs
 // eight outputs per wavefront at a time with coalesced row reads and a fixed
 // butterfly reduction.  It runs once per material edit, not per frame.
 #include "enc_dense.hpp"
@@ -11,22 +12,13 @@ namespace fab {
 
 namespace {
 
+template <int LAT>
 __global__ __launch_bounds__(256) void encoder_forward_kernel(const float *__restrict__ Q,
                                                               const float *__restrict__ inputs,
                                                               float *__restrict__ latents)
 {
-    __shared__ float x[kEncIn];
-    __shared__ float e1[kEncHid], r2[kEncHid], e2[kEncHid], z[kLatent];
     const int f = blockIdx.x;
-    for (int k = threadIdx.x; k < kEncIn; k += blockDim.x)
-        x[k] = inputs[(size_t)f * kEncIn + k];
-    __syncthreads();
-    enc_dense_rows(Q + kOffE1, Q + kOffC1, x, kEncIn, kEncHid, e1, true, nullptr);
-    enc_dense_rows(Q + kOffE2, Q + kOffC2, e1, kEncHid, kEncHid, r2, true, nullptr);
-    enc_dense_rows(Q + kOffE3, Q + kOffC3, r2, kEncHid, kEncHid, e2, true, e1);
-    enc_dense_rows(Q + kOffE4, Q + kOffC4, e2, kEncHid, kLatent, z, false, nullptr);
-    for (int k = threadIdx.x; k < kLatent; k += blockDim.x)
-        latents[f * kLatent + k] = z[k];
+    encoder_forward_block<LAT>(Q, inputs + (size_t)f * kEncIn, latents + (size_t)f * LAT);
 }
 
 // Latent blends of Sec. 5 "Interpolation" in one block: every thread loads
@@ -78,10 +70,22 @@ hipError_t launch_lerp_latents(const LatentLerp *jobs, int count, float *latents
 hipError_t launch_encoder_forward(const float *enc_params, const float *enc_inputs,
                                   int n_fabrics, float *latents, hipStream_t stream)
 {
+    return launch_encoder_forward_n(enc_params, enc_inputs, n_fabrics, kLatent, latents, stream);
+}
+
+hipError_t launch_encoder_forward_n(const float *enc_params, const float *enc_inputs,
+                                    int n_fabrics, int lat, float *latents, hipStream_t stream)
+{
     if (n_fabrics <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(encoder_forward_kernel, dim3(n_fabrics), dim3(256), 0, stream, enc_params,
-                       enc_inputs, latents);
+    if (lat == kLatent)
+        hipLaunchKernelGGL(encoder_forward_kernel<kLatent>, dim3(n_fabrics), dim3(256), 0, stream,
+                           enc_params, enc_inputs, latents);
+    else if (lat == FABRIC_PAPER_LATENT)
+        hipLaunchKernelGGL(encoder_forward_kernel<FABRIC_PAPER_LATENT>, dim3(n_fabrics), dim3(256),
+                           0, stream, enc_params, enc_inputs, latents);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

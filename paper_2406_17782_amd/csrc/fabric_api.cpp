@@ -41,7 +41,10 @@ struct fabric_ctx {
     float *paper_cfold = nullptr;     // [FABRIC_MAX_FABRICS][64]
     int paper_n_mats = 0;             // fabrics folded by the last prepare
     uint64_t paper_serial = 0;        // table_serial of the last prepare
-    float *paper_master = nullptr;    // FP32 masters [params | latents [F][64]] (first prepare)
+    float *paper_master = nullptr;    // FP32 masters [params | latents [F][64]] or
+                                      // [params | encoder] (first prepare)
+    bool paper_encoder = false;       // the latents come from the paper-size encoder
+    float *paper_latents = nullptr;   // [FABRIC_MAX_FABRICS][64]: the encoder's latents
     double *paper_m = nullptr;        // their FP64 Adam moments
     double *paper_v = nullptr;
     int64_t paper_step = 0;
@@ -475,6 +478,40 @@ fabric_status ensure_queue(fabric_ctx *ctx, int64_t n)
     return st;
 }
 
+// The paper-size network's latents: the masters' own (latents trained as
+// parameters) or those the encoder last produced.
+const float *paper_latents_of(const fabric_ctx *ctx)
+{
+    return ctx->paper_encoder ? ctx->paper_latents
+                              : ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS;
+}
+
+// Masters and Adam moments of the paper-size network, sized for either layout.
+constexpr size_t kPaperMasterFloats =
+    (size_t)FABRIC_N_PAPER_DECODER_PARAMS +
+    ((size_t)FABRIC_MAX_FABRICS * FABRIC_PAPER_LATENT > (size_t)FABRIC_N_PAPER_ENCODER_PARAMS
+         ? (size_t)FABRIC_MAX_FABRICS * FABRIC_PAPER_LATENT
+         : (size_t)FABRIC_N_PAPER_ENCODER_PARAMS);
+
+fabric_status ensure_paper_master(fabric_ctx *ctx)
+{
+    if (ctx->paper_master)
+        return FABRIC_OK;
+    fabric_status st = dalloc(&ctx->paper_master, kPaperMasterFloats);
+    if (st == FABRIC_OK) st = dalloc(&ctx->paper_m, kPaperMasterFloats);
+    if (st == FABRIC_OK) st = dalloc(&ctx->paper_v, kPaperMasterFloats);
+    if (st == FABRIC_OK) st = dalloc(&ctx->paper_latents, (size_t)FABRIC_MAX_FABRICS * FABRIC_PAPER_LATENT);
+    if (st != FABRIC_OK) {
+        (void)hipFree(ctx->paper_master);
+        (void)hipFree(ctx->paper_m);
+        (void)hipFree(ctx->paper_v);
+        (void)hipFree(ctx->paper_latents);
+        ctx->paper_master = ctx->paper_latents = nullptr;
+        ctx->paper_m = ctx->paper_v = nullptr;
+    }
+    return st;
+}
+
 bool supported_prec(int prec)
 {
     return prec == FABRIC_FP32 || prec == FABRIC_BF16 || prec == FABRIC_FP16 || prec == FABRIC_FP8_E4M3;
@@ -519,6 +556,7 @@ void fabric_destroy(fabric_ctx *ctx)
     (void)hipFree(ctx->paper_master);
     (void)hipFree(ctx->paper_m);
     (void)hipFree(ctx->paper_v);
+    (void)hipFree(ctx->paper_latents);
     paper_train_scratch_free(ctx->paper_train);
     for (int k = 0; k < 4; k++)
         (void)hipFree(ctx->image[k]);
@@ -659,21 +697,11 @@ fabric_status fabric_paper_prepare(fabric_ctx *ctx, const float *params, const f
     if (ctx->n_mats == 0)
         return FABRIC_E_STATE;
     DeviceGuard guard(ctx->device);
-    const size_t total = (size_t)FABRIC_N_PAPER_DECODER_PARAMS + (size_t)FABRIC_MAX_FABRICS * FABRIC_PAPER_LATENT;
-    fabric_status st = FABRIC_OK;
-    if (!ctx->paper_master) {
-        st = dalloc(&ctx->paper_master, total);
-        if (st == FABRIC_OK) st = dalloc(&ctx->paper_m, total);
-        if (st == FABRIC_OK) st = dalloc(&ctx->paper_v, total);
-        if (st != FABRIC_OK) {
-            (void)hipFree(ctx->paper_master);
-            (void)hipFree(ctx->paper_m);
-            (void)hipFree(ctx->paper_v);
-            ctx->paper_master = nullptr;
-            ctx->paper_m = ctx->paper_v = nullptr;
-            return st;
-        }
-    }
+    const size_t total = kPaperMasterFloats;
+    fabric_status st = ensure_paper_master(ctx);
+    if (st != FABRIC_OK)
+        return st;
+    ctx->paper_encoder = false;
     // The context keeps its own copy (the masters training updates).
     hipStream_t s = as_stream(stream);
     float *pm = ctx->paper_master, *lm = ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS;
@@ -697,6 +725,72 @@ fabric_status fabric_paper_prepare(fabric_ctx *ctx, const float *params, const f
     return FABRIC_OK;
 }
 
+fabric_status fabric_paper_prepare_encoder(fabric_ctx *ctx, const float *params,
+                                           const float *enc_params, void *stream)
+{
+    if (!ctx || !params || !enc_params)
+        return FABRIC_E_INVAL;
+    if (ctx->n_mats == 0)
+        return FABRIC_E_STATE;
+    DeviceGuard guard(ctx->device);
+    fabric_status st = ensure_paper_master(ctx);
+    if (st != FABRIC_OK)
+        return st;
+    hipStream_t s = as_stream(stream);
+    float *pm = ctx->paper_master, *em = ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS;
+    st = from_hip(hipMemcpyAsync(pm, params, FABRIC_N_PAPER_DECODER_PARAMS * sizeof(float),
+                                 hipMemcpyDeviceToDevice, s));
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpyAsync(em, enc_params, FABRIC_N_PAPER_ENCODER_PARAMS * sizeof(float),
+                                     hipMemcpyDeviceToDevice, s));
+    if (st == FABRIC_OK) st = from_hip(hipMemsetAsync(ctx->paper_m, 0, kPaperMasterFloats * sizeof(double), s));
+    if (st == FABRIC_OK) st = from_hip(hipMemsetAsync(ctx->paper_v, 0, kPaperMasterFloats * sizeof(double), s));
+    ctx->paper_encoder = true;
+    ctx->paper_n_mats = 0;
+    if (st != FABRIC_OK)
+        return st;
+    ctx->paper_step = 0;
+    return fabric_paper_encode(ctx, stream);
+}
+
+fabric_status fabric_paper_encode(fabric_ctx *ctx, void *stream)
+{
+    if (!ctx)
+        return FABRIC_E_INVAL;
+    if (ctx->n_mats == 0 || !ctx->paper_master || !ctx->paper_encoder)
+        return FABRIC_E_STATE;
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = as_stream(stream);
+    hipError_t e = launch_encoder_forward_n(ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS,
+                                            ctx->enc_inputs, ctx->n_mats, FABRIC_PAPER_LATENT,
+                                            ctx->paper_latents, s);
+    if (e == hipSuccess)
+        e = launch_paper_prepare(ctx->paper_master, ctx->paper_latents, ctx->n_mats,
+                                 ctx->paper_fused, ctx->paper_image, ctx->paper_cfold, s);
+    if (e != hipSuccess) {
+        ctx->paper_n_mats = 0;
+        return from_hip(e);
+    }
+    ctx->paper_n_mats = ctx->n_mats;
+    ctx->paper_serial = ctx->table_serial;
+    return FABRIC_OK;
+}
+
+fabric_status fabric_paper_get_encoder(fabric_ctx *ctx, float *enc_params_host)
+{
+    if (!ctx || !enc_params_host)
+        return FABRIC_E_INVAL;
+    if (!ctx->paper_master || !ctx->paper_encoder)
+        return FABRIC_E_STATE;
+    DeviceGuard guard(ctx->device);
+    fabric_status st = from_hip(hipDeviceSynchronize());
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpy(enc_params_host, ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS,
+                                FABRIC_N_PAPER_ENCODER_PARAMS * sizeof(float),
+                                hipMemcpyDeviceToHost));
+    return st;
+}
+
 fabric_status fabric_paper_shade(fabric_ctx *ctx, const fabric_gbuffer *g, fabric_prec prec,
                                  float *out_rgb, void *stream)
 {
@@ -712,8 +806,8 @@ fabric_status fabric_paper_shade(fabric_ctx *ctx, const fabric_gbuffer *g, fabri
     if (prec == FABRIC_FP32)
         return from_hip(launch_paper_shade_f32(
             ctx->paper_raw, ctx->paper_fused, *g, ctx->fabrics, ctx->paper_n_mats,
-            ctx->paper_master, ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS, out_rgb,
-            nullptr, ctx->err, as_stream(stream)));
+            ctx->paper_master, paper_latents_of(ctx), out_rgb, nullptr, ctx->err,
+            as_stream(stream)));
     return from_hip(launch_paper_shade(prec, ctx->paper_raw, ctx->paper_fused, *g, ctx->fabrics, ctx->n_mats, ctx->paper_cfold,
                                        ctx->paper_image, out_rgb, ctx->err, as_stream(stream)));
 }
@@ -730,8 +824,7 @@ fabric_status fabric_paper_forward(fabric_ctx *ctx, const fabric_gbuffer *g, flo
     DeviceGuard guard(ctx->device);
     return from_hip(launch_paper_shade_f32(
         ctx->paper_raw, ctx->paper_fused, *g, ctx->fabrics, ctx->paper_n_mats, ctx->paper_master,
-        ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS, nullptr, y4, ctx->err,
-        as_stream(stream)));
+        paper_latents_of(ctx), nullptr, y4, ctx->err, as_stream(stream)));
 }
 
 fabric_status fabric_set_visibility(fabric_ctx *ctx, int32_t enable)
@@ -1074,6 +1167,7 @@ PaperTrainArgs paper_train_args(fabric_ctx *ctx, const fabric_gbuffer *batch, co
     a.vis = VisArgs{nullptr, nullptr};
     a.raw = ctx->paper_raw;
     a.fused = ctx->paper_fused;
+    a.enc_inputs = ctx->paper_encoder ? ctx->enc_inputs : nullptr;
     return a;
 }
 }  // namespace
@@ -1095,8 +1189,7 @@ fabric_status fabric_paper_set_spatial_fusion(fabric_ctx *ctx, int32_t fused, vo
         return FABRIC_OK;
     // The shading image of the prepared masters follows the wiring.
     DeviceGuard guard(ctx->device);
-    return from_hip(launch_paper_prepare(ctx->paper_master,
-                                         ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS,
+    return from_hip(launch_paper_prepare(ctx->paper_master, paper_latents_of(ctx),
                                          ctx->paper_n_mats, ctx->paper_fused, ctx->paper_image,
                                          ctx->paper_cfold, as_stream(stream)));
 }
@@ -1132,9 +1225,15 @@ fabric_status fabric_paper_train_step(fabric_ctx *ctx, const fabric_gbuffer *bat
     int updated = 0;
     hipError_t e = paper_train_step(ctx->paper_train, a, out_loss, &updated, s);
     // The shading image follows the masters (unchanged when the step was skipped).
+    // With the encoder, its latents after the step (left in the training
+    // scratch) become the context's.
+    if (e == hipSuccess && ctx->paper_encoder)
+        e = hipMemcpyAsync(ctx->paper_latents, ctx->paper_train.lat,
+                           (size_t)ctx->n_mats * FABRIC_PAPER_LATENT * sizeof(float),
+                           hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess)
-        e = launch_paper_prepare(ctx->paper_master, ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS,
-                                 ctx->n_mats, ctx->paper_fused, ctx->paper_image, ctx->paper_cfold, s);
+        e = launch_paper_prepare(ctx->paper_master, paper_latents_of(ctx), ctx->n_mats,
+                                 ctx->paper_fused, ctx->paper_image, ctx->paper_cfold, s);
     if (e != hipSuccess)
         return from_hip(e);
     if (!updated)
@@ -1155,7 +1254,7 @@ fabric_status fabric_paper_get_params(fabric_ctx *ctx, float *params_host, float
         st = from_hip(hipMemcpy(params_host, ctx->paper_master,
                                 FABRIC_N_PAPER_DECODER_PARAMS * sizeof(float), hipMemcpyDeviceToHost));
     if (st == FABRIC_OK)
-        st = from_hip(hipMemcpy(latents_host, ctx->paper_master + FABRIC_N_PAPER_DECODER_PARAMS,
+        st = from_hip(hipMemcpy(latents_host, paper_latents_of(ctx),
                                 (size_t)ctx->paper_n_mats * FABRIC_PAPER_LATENT * sizeof(float),
                                 hipMemcpyDeviceToHost));
     return st;

@@ -106,5 +106,9 @@ hipError_t launch_paper_shade_f32(bool raw, bool fused, const fabric_gbuffer &g,
 // Encoder forward over n_fabrics fabrics: enc_inputs[n][524] -> latents[n][32].
 hipError_t launch_encoder_forward(const float *enc_params, const float *enc_inputs,
                                   int n_fabrics, float *latents, hipStream_t stream);
+// The same for a latent of `lat` values (32 or FABRIC_PAPER_LATENT; the
+// parameters laid out as the config encoder's with E4 [lat][128], c4 [lat]).
+hipError_t launch_encoder_forward_n(const float *enc_params, const float *enc_inputs,
+                                    int n_fabrics, int lat, float *latents, hipStream_t stream);
 
 }  // namespace fab

@@ -19,9 +19,11 @@
 //   paper_latent_grads_kernel  F1's latent columns and the latents'
 //                          gradients from the per-fabric sums
 // Every reduction has a fixed order: results do not depend on scheduling.
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
+#include "enc_dense.hpp"
 #include "kernels.hpp"
 #include "model.hpp"
 #include "paper_net.hpp"
@@ -540,13 +542,40 @@ PWJobs make_jobs(int n_fabrics, int n_chunks, bool fused)
     return J;
 }
 
+// The paper-size network's encoder backward (latent 64): per fabric, the
+// latent's gradient back through the encoder into the scratch; then every
+// encoder parameter's gradient summed over the fabrics in order.
+constexpr int kPEncAct = enc_act_floats<kPLat>();
+static_assert(enc_param_count<kPLat>() == kPaperEncParams, "paper encoder layout");
+
+__global__ __launch_bounds__(256) void paper_encoder_backward_kernel(const float *__restrict__ Q,
+                                                                     const float *__restrict__ inputs,
+                                                                     const float *__restrict__ dz,
+                                                                     float *__restrict__ scratch)
+{
+    const int f = blockIdx.x;
+    encoder_backward_block<kPLat>(Q, inputs + (size_t)f * kEncIn, dz + (size_t)f * kPLat,
+                                  scratch + (size_t)f * kPEncAct);
+}
+
+__global__ void paper_encoder_wgrad_kernel(const float *__restrict__ scratch, int n_fabrics,
+                                           float *__restrict__ grad)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < kPaperEncParams)
+        grad[e] = encoder_wgrad_entry<kPLat>(scratch, n_fabrics, e);
+}
+
 // Loss and gradient ([params | latents], into s.grad) of one batch.
 hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hipStream_t stream)
 {
     const fabric_train_cfg &cfg = a.cfg;
     hipError_t e;
     if (!s.grad) {
-        if ((e = hipMalloc((void **)&s.grad, (size_t)(kPNDec + kPaperTrainMaxFabrics * kPLat) * sizeof(float))) != hipSuccess) return e;
+        const size_t tail = std::max((size_t)kPaperTrainMaxFabrics * kPLat, (size_t)kPaperEncParams);
+        if ((e = hipMalloc((void **)&s.grad, (kPNDec + tail) * sizeof(float))) != hipSuccess) return e;
+        if ((e = hipMalloc((void **)&s.lat, (size_t)kPaperTrainMaxFabrics * kPLat * sizeof(float))) != hipSuccess) return e;
+        if ((e = hipMalloc((void **)&s.enc_acts, (size_t)kPaperTrainMaxFabrics * kPEncAct * sizeof(float))) != hipSuccess) return e;
         if ((e = hipMalloc((void **)&s.dsum, (size_t)kPaperTrainMaxFabrics * 64 * sizeof(float))) != hipSuccess) return e;
         if ((e = hipMalloc((void **)&s.wt, (size_t)kTFloats * sizeof(float))) != hipSuccess) return e;
         if ((e = hipMalloc((void **)&s.loss, sizeof(double))) != hipSuccess) return e;
@@ -578,9 +607,16 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
     const int64_t n = g.n;
     const float *P = a.master, *lat = a.master + kPNDec;
     float *grad = s.grad, *glat = s.grad + kPNDec;
+    if (a.enc_inputs) {
+        // The latents of this step from the encoder (its parameters follow the decoder's).
+        if ((e = launch_encoder_forward_n(a.master + kPNDec, a.enc_inputs, a.n_fabrics, kPLat,
+                                          s.lat, stream)) != hipSuccess)
+            return e;
+        lat = s.lat;
+    }
     if (n == 0) {
         if ((e = hipMemsetAsync(s.loss, 0, sizeof(double), stream)) != hipSuccess) return e;
-        return hipMemsetAsync(s.grad, 0, (size_t)(kPNDec + a.n_fabrics * kPLat) * sizeof(float), stream);
+        return hipMemsetAsync(s.grad, 0, (size_t)paper_trained_count(a) * sizeof(float), stream);
     }
     const float *targets = a.targets;
     if (!targets) {
@@ -628,6 +664,14 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
     const int tot = 64 * kPLat + a.n_fabrics * kPLat;
     hipLaunchKernelGGL(paper_latent_grads_kernel, dim3((tot + 255) / 256), dim3(256), 0, stream, P,
                        lat, (const float *)s.dsum, a.n_fabrics, grad, glat);
+    if (a.enc_inputs) {
+        // The latents' gradient through the encoder; its parameters' gradient
+        // takes the latents' place after the decoder's.
+        hipLaunchKernelGGL(paper_encoder_backward_kernel, dim3(a.n_fabrics), dim3(256), 0, stream,
+                           a.master + kPNDec, a.enc_inputs, (const float *)glat, s.enc_acts);
+        hipLaunchKernelGGL(paper_encoder_wgrad_kernel, dim3((kPaperEncParams + 255) / 256),
+                           dim3(256), 0, stream, (const float *)s.enc_acts, a.n_fabrics, glat);
+    }
     return hipGetLastError();
 }
 
@@ -653,6 +697,8 @@ void paper_train_scratch_free(PaperTrainScratch &s)
     (void)hipFree(s.wt);
     (void)hipFree(s.partial);
     (void)hipFree(s.grad);
+    (void)hipFree(s.lat);
+    (void)hipFree(s.enc_acts);
     (void)hipFree(s.dsum);
     (void)hipFree(s.b_fid);
     (void)hipFree(s.b_fields);
@@ -666,7 +712,7 @@ hipError_t paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, float 
     hipError_t e = run_paper_loss_grad(s, a, stream);
     if (e != hipSuccess)
         return e;
-    if ((e = hipMemcpyAsync(grad_out, s.grad, (size_t)(kPNDec + a.n_fabrics * kPLat) * sizeof(float),
+    if ((e = hipMemcpyAsync(grad_out, s.grad, (size_t)paper_trained_count(a) * sizeof(float),
                             hipMemcpyDeviceToDevice, stream)) != hipSuccess)
         return e;
     if (out_loss) {
@@ -683,8 +729,13 @@ hipError_t paper_train_step(PaperTrainScratch &s, const PaperTrainArgs &a, float
     hipError_t e = run_paper_loss_grad(s, a, stream);
     if (e != hipSuccess)
         return e;
-    if ((e = launch_adam(a.master, s.grad, a.adam_m, a.adam_v, kPNDec + a.n_fabrics * kPLat, a.cfg,
+    if ((e = launch_adam(a.master, s.grad, a.adam_m, a.adam_v, paper_trained_count(a), a.cfg,
                          a.step, s.loss, stream)) != hipSuccess)
+        return e;
+    // The latents of the updated encoder, for the shading image.
+    if (a.enc_inputs &&
+        (e = launch_encoder_forward_n(a.master + kPNDec, a.enc_inputs, a.n_fabrics, kPLat, s.lat,
+                                      stream)) != hipSuccess)
         return e;
     if (out_loss)
         return read_paper_loss(s, out_loss, updated, stream);

@@ -21,7 +21,9 @@ struct PaperTrainScratch {
     float *wt = nullptr;          // transposed weights of F2, A1 (first 64 inputs), A2, A3, A4
     float *partial = nullptr;     // split-K partial weight gradients
     size_t partial_floats = 0;
-    float *grad = nullptr;        // [params | latents]
+    float *grad = nullptr;        // [params | latents], or [params | encoder] with the encoder
+    float *lat = nullptr;         // [kPaperTrainMaxFabrics][64]: the encoder's latents
+    float *enc_acts = nullptr;    // per-fabric encoder backward scratch
     float *dsum = nullptr;        // [fabric][64]: per-fabric sums of F1's input gradient
     int64_t batch_cap = 0;        // generated batch and targets
     uint16_t *b_fid = nullptr;
@@ -31,8 +33,13 @@ struct PaperTrainScratch {
 
 void paper_train_scratch_free(PaperTrainScratch &s);
 
+// Parameters of the paper-size network's encoder (latent 64).
+constexpr int kPaperEncParams = FABRIC_N_PAPER_ENCODER_PARAMS;
+
 struct PaperTrainArgs {
-    float *master;                // [params (FABRIC_N_PAPER_DECODER_PARAMS) | latents [F][64]]
+    // [params (FABRIC_N_PAPER_DECODER_PARAMS) | latents [F][64]], or with
+    // enc_inputs: [params | encoder parameters (kPaperEncParams)]
+    float *master;
     double *adam_m, *adam_v;      // same length
     int64_t step;                 // 1-based Adam step of this update
     const DevFabric *fabrics;
@@ -44,13 +51,24 @@ struct PaperTrainArgs {
     VisArgs vis;
     bool raw;                     // footprint inputs without the one-blob encoding
     bool fused;                   // false: the angular inputs enter F1 (no spatial fusion)
+    const float *enc_inputs;      // NULL: latents are parameters; else the encoder's
+                                  // inputs [F][524] and the latents come from the encoder
 };
 
-// Loss and gradient [params | latents] of one batch into grad_out (device).
+// Parameters Adam updates: the decoder and the latents or the encoder.
+inline int64_t paper_trained_count(const PaperTrainArgs &a)
+{
+    return (int64_t)FABRIC_N_PAPER_DECODER_PARAMS +
+           (a.enc_inputs ? (int64_t)kPaperEncParams : (int64_t)a.n_fabrics * FABRIC_PAPER_LATENT);
+}
+
+// Loss and gradient [params | latents] (or [params | encoder]) of one batch
+// into grad_out (device, paper_trained_count floats).
 hipError_t paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, float *grad_out,
                            float *out_loss, hipStream_t stream);
 
-// One Adam step of the paper-size decoder and its latents; *updated = 0 when
+// One Adam step of the paper-size decoder and its latents (or encoder);
+// the latents of the encoder after the step are left in s.lat.  *updated = 0 when
 // the loss was non-finite (known only when out_loss != NULL).
 hipError_t paper_train_step(PaperTrainScratch &s, const PaperTrainArgs &a, float *out_loss,
                             int *updated, hipStream_t stream);

@@ -92,10 +92,10 @@ __device__ inline HalfPix load_half(const fabric_gbuffer &g, const HalfPlanes &h
 // Evaluated without short-circuits (no branches per tile).
 __device__ inline bool half_fault(const HalfPix &x, int n_fabrics, int grp)
 {
-    const bool finite = isfinite(x.uv) & isfinite(x.r) & isfinite(x.x0) & isfinite(x.x1) &
-                        isfinite(x.xz);
-    const bool dir_bad = grp ? !(x.xz > 0.0f) : x.xz == 0.0f;
-    return !finite | (x.fid >= n_fabrics) | !(x.r > 0.0f) | dir_bad;
+    const int finite = (int)isfinite(x.uv) & (int)isfinite(x.r) & (int)isfinite(x.x0) &
+                       (int)isfinite(x.x1) & (int)isfinite(x.xz);
+    const int dir_bad = grp ? (int)!(x.xz > 0.0f) : (int)(x.xz == 0.0f);
+    return (!finite | (int)(x.fid >= n_fabrics) | (int)!(x.r > 0.0f) | dir_bad) != 0;
 }
 // True in both lanes of a pixel (lanes l and l ^ 32) when either flag is set.
 __device__ inline bool pair_any(bool flag, int lane)

@@ -48,7 +48,8 @@ __host__ __device__ inline ActPtrs act_ptrs(float *base, int64_t cap)
 }
 
 // Per-fabric encoder scratch (floats).
-constexpr int kEncActFloats = kEncIn + 6 * kEncHid + kLatent;
+constexpr int kEncActFloats = enc_act_floats<kLatent>();
+static_assert(enc_param_count<kLatent>() == kNEnc, "encoder layout");
 
 // ---------------------------------------------------------------------------
 // Training batches
@@ -495,55 +496,9 @@ __global__ __launch_bounds__(256) void encoder_backward_kernel(const float *__re
                                                                const float *__restrict__ dz,
                                                                float *__restrict__ scratch)
 {
-    __shared__ float x[kEncIn], a1[kEncHid], e1[kEncHid], a2[kEncHid], r2[kEncHid],
-        a3[kEncHid], e2[kEncHid], g[kEncHid], d3[kEncHid], d2[kEncHid], d1[kEncHid],
-        dzs[kLatent];
     const int f = blockIdx.x;
-    for (int k = threadIdx.x; k < kEncIn; k += blockDim.x)
-        x[k] = inputs[(size_t)f * kEncIn + k];
-    for (int k = threadIdx.x; k < kLatent; k += blockDim.x)
-        dzs[k] = dz[f * kLatent + k];
-    __syncthreads();
-    enc_dense_rows(Q + kOffE1, Q + kOffC1, x, kEncIn, kEncHid, a1, false, nullptr);
-    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
-        e1[k] = fmaxf(a1[k], 0.0f);
-    __syncthreads();
-    enc_dense_rows(Q + kOffE2, Q + kOffC2, e1, kEncHid, kEncHid, a2, false, nullptr);
-    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
-        r2[k] = fmaxf(a2[k], 0.0f);
-    __syncthreads();
-    enc_dense_rows(Q + kOffE3, Q + kOffC3, r2, kEncHid, kEncHid, a3, false, nullptr);
-    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x) {
-        a3[k] += e1[k];                     // skip connection before the activation
-        e2[k] = fmaxf(a3[k], 0.0f);
-    }
-    __syncthreads();
-    // backward
-    enc_dense_cols(Q + kOffE4, dzs, kLatent, kEncHid, g);          // dL/de2
-    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
-        d3[k] = a3[k] > 0.0f ? g[k] : 0.0f;
-    __syncthreads();
-    enc_dense_cols(Q + kOffE3, d3, kEncHid, kEncHid, g);           // dL/dr2
-    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
-        d2[k] = a2[k] > 0.0f ? g[k] : 0.0f;
-    __syncthreads();
-    enc_dense_cols(Q + kOffE2, d2, kEncHid, kEncHid, g);           // dL/de1 (through E2)
-    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x)
-        d1[k] = a1[k] > 0.0f ? g[k] + d3[k] : 0.0f;               // plus the skip path
-    __syncthreads();
-    float *out = scratch + (size_t)f * kEncActFloats;
-    for (int k = threadIdx.x; k < kEncIn; k += blockDim.x)
-        out[k] = x[k];
-    for (int k = threadIdx.x; k < kEncHid; k += blockDim.x) {
-        out[kEncIn + k] = e1[k];
-        out[kEncIn + kEncHid + k] = r2[k];
-        out[kEncIn + 2 * kEncHid + k] = e2[k];
-        out[kEncIn + 3 * kEncHid + k] = d1[k];
-        out[kEncIn + 4 * kEncHid + k] = d2[k];
-        out[kEncIn + 5 * kEncHid + k] = d3[k];
-    }
-    for (int k = threadIdx.x; k < kLatent; k += blockDim.x)
-        out[kEncIn + 6 * kEncHid + k] = dzs[k];
+    encoder_backward_block<kLatent>(Q, inputs + (size_t)f * kEncIn, dz + (size_t)f * kLatent,
+                                    scratch + (size_t)f * kEncActFloats);
 }
 
 // One thread per encoder parameter: the sum over fabrics, in order.
@@ -551,26 +506,8 @@ __global__ void encoder_wgrad_kernel(const float *__restrict__ scratch, int n_fa
                                      float *__restrict__ grad)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= kNEnc)
-        return;
-    // (delta offset, input offset, fan-in) of the tensor holding e
-    int dofs, xofs, nin, idx;
-    if (e < kOffC1) { dofs = kEncIn + 3 * kEncHid; xofs = 0; nin = kEncIn; idx = e - kOffE1; }
-    else if (e < kOffE2) { dofs = kEncIn + 3 * kEncHid; xofs = -1; nin = 1; idx = e - kOffC1; }
-    else if (e < kOffC2) { dofs = kEncIn + 4 * kEncHid; xofs = kEncIn; nin = kEncHid; idx = e - kOffE2; }
-    else if (e < kOffE3) { dofs = kEncIn + 4 * kEncHid; xofs = -1; nin = 1; idx = e - kOffC2; }
-    else if (e < kOffC3) { dofs = kEncIn + 5 * kEncHid; xofs = kEncIn + kEncHid; nin = kEncHid; idx = e - kOffE3; }
-    else if (e < kOffE4) { dofs = kEncIn + 5 * kEncHid; xofs = -1; nin = 1; idx = e - kOffC3; }
-    else if (e < kOffC4) { dofs = kEncIn + 6 * kEncHid; xofs = kEncIn + 2 * kEncHid; nin = kEncHid; idx = e - kOffE4; }
-    else { dofs = kEncIn + 6 * kEncHid; xofs = -1; nin = 1; idx = e - kOffC4; }
-    const int o = idx / nin, i = idx % nin;
-    float acc = 0.0f;
-    for (int f = 0; f < n_fabrics; f++) {
-        const float *s = scratch + (size_t)f * kEncActFloats;
-        const float x = xofs >= 0 ? s[xofs + i] : 1.0f;
-        acc = fmaf(s[dofs + o], x, acc);
-    }
-    grad[e] = acc;
+    if (e < kNEnc)
+        grad[e] = encoder_wgrad_entry<kLatent>(scratch, n_fabrics, e);
 }
 
 // ---------------------------------------------------------------------------

@@ -62,6 +62,9 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     assert lib.fabric_paper_set_footprint_encoding(None, 1) == 1
     assert lib.fabric_paper_set_spatial_fusion(None, 1, None) == 1
     assert lib.fabric_paper_get_params(None, None, None) == 1
+    assert lib.fabric_paper_prepare_encoder(None, None, None, None) == 1
+    assert lib.fabric_paper_encode(None, None) == 1
+    assert lib.fabric_paper_get_encoder(None, None) == 1
     lib.fabric_destroy(None)
 
 
@@ -109,5 +112,6 @@ def test_binding_constants_match_header():
     defs = dict(re.findall(r"#define (FABRIC_\w+) (\d+)\s", text))
     for name in ("FABRIC_MAX_FABRICS", "FABRIC_MAX_SAMPLES", "FABRIC_LATENT",
                  "FABRIC_N_DECODER_PARAMS", "FABRIC_N_ENCODER_PARAMS", "FABRIC_PAPER_LATENT",
-                 "FABRIC_N_PAPER_DECODER_PARAMS", "FABRIC_NOALLOC_MAX_PIXELS"):
+                 "FABRIC_N_PAPER_DECODER_PARAMS", "FABRIC_N_PAPER_ENCODER_PARAMS",
+                 "FABRIC_NOALLOC_MAX_PIXELS"):
         assert getattr(_abi, name) == int(defs[name]), name
