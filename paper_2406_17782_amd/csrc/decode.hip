@@ -147,6 +147,7 @@ __global__ __launch_bounds__(256) void decode32_kernel(
 
     const int lane = threadIdx.x & 63;
     const int grp = lane >> 5;
+    const uint32_t dmask = half_dir_mask(grp);
     const int col = lane & 31;
 
     Frag A[S::NFRAG];
@@ -165,11 +166,12 @@ __global__ __launch_bounds__(256) void decode32_kernel(
     auto shade_tile = [&](const HalfPix &cur, int tile) {
         const int p = tile * 32 + col;
         const bool valid = p < n;
-        const bool fault = pair_any(half_fault(cur, n_fabrics, grp), lane);
+        const unsigned long long fmask = pair_mask(half_fault(cur, n_fabrics, dmask));
+        const bool fault = __builtin_amdgcn_inverse_ballot_w64(fmask);
         // Out-of-range rule (r > 1 cell or wo.z < 0.05), decided before the
         // MFMA chain so that no pixel field stays live through it.
         const bool oor = HYBRID && !fault &&
-                         pair_any(cur.r > 1.0f || (grp == 1 && cur.xz < 0.05f), lane);
+                         pair_any(cur.r > 1.0f || (grp == 1 && cur.xz < 0.05f));
         // Only the table index needs a safe value: non-finite inputs stay in
         // their own pixel's column of every MFMA tile and are zeroed on output.
         const int fid = fault ? 0 : cur.fid;
@@ -204,7 +206,8 @@ __global__ __launch_bounds__(256) void decode32_kernel(
             for (int c = 0; c < 3; c++)
                 plane_store(out, c * n + p, fault ? 0.0f : rgb[c]);
         }
-        const unsigned long long bad = __ballot(grp == 0 && valid && fault);
+        // Faulted pixels of the tile, counted once (lane group 0's bits).
+        const unsigned long long bad = fmask & __ballot(valid) & 0xffffffffull;
         if (lane == 0 && bad)
             atomicAdd(err, (unsigned long long)__popcll(bad));
         if (HYBRID)

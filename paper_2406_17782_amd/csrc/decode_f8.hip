@@ -282,6 +282,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
     const int lane = threadIdx.x & 63;
     const int grp = lane >> 5;
+    const uint32_t dmask = half_dir_mask(grp);
     const int col = lane & 31;
 
     i32x8 A[DecShapeF8::NFRAG];
@@ -314,10 +315,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     auto prepare = [&](const HalfPix &cur, int tile, Prep &r, f32x16 (&a)[2]) {
         r.p = tile * 32 + col;
         r.valid = tile < n_tiles && r.p < n;
-        r.fault = pair_any(half_fault(cur, n_fabrics, grp), lane);
+        r.fault = pair_any(half_fault(cur, n_fabrics, dmask));
         // Out-of-range rule (r > 1 cell or wo.z < 0.05), decided before the
         // MFMA chain so that no pixel field stays live through it.
-        r.oor = HYBRID && !r.fault && pair_any(cur.r > 1.0f || (grp == 1 && cur.xz < 0.05f), lane);
+        r.oor = HYBRID && !r.fault && pair_any(cur.r > 1.0f || (grp == 1 && cur.xz < 0.05f));
         r.fid = r.fault ? 0 : cur.fid;   // non-finite inputs stay in their own column
         const float *fc = s_fc + r.fid * kFabConsts;
         float s1[kL1Slots32];

@@ -262,6 +262,7 @@ __global__ __launch_bounds__(64 * WAVES) void decode_paper_kernel(
 
     const int lane = threadIdx.x & 63;
     const int grp = lane >> 5;
+    const uint32_t dmask = half_dir_mask(grp);
     const int col = lane & 31;
     const f32x4 b5 = bias5[lane];
     // The bias K step of the chain layers: 1 in slot 32 of lane group 0.
@@ -293,7 +294,7 @@ __global__ __launch_bounds__(64 * WAVES) void decode_paper_kernel(
             for (int t = 0; t < T; t++) {
                 p[t] = (tile0 + t) * 32 + col;
                 valid[t] = tile0 + t < n_tiles && p[t] < n;
-                fault[t] = pair_any(half_fault(cur[t], n_fabrics, grp), lane);
+                fault[t] = pair_any(half_fault(cur[t], n_fabrics, dmask));
                 fid[t] = fault[t] ? 0 : cur[t].fid;
                 entry[t] = fab_entry(fid[t], n_fabrics, grp ? 1.0f : cur[t].xz);
                 const float *fc = s_fc + entry[t] * kFabConsts;

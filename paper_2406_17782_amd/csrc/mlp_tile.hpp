@@ -26,6 +26,9 @@ template <int P> struct FeatureMath {
     {
         return __builtin_amdgcn_exp2f(-0.72134752044448170368f * d * d);
     }
+    // exp(-d^2 / 2) from qd = kGaussQ d: exp2(-(qd)^2), kGaussQ^2 = log2(e) / 2
+    static constexpr float kGaussQ = 0.84932180028801904f;
+    static __device__ inline float gauss_q(float qd) { return __builtin_amdgcn_exp2f(-(qd * qd)); }
     // e^y - 1
     static __device__ inline float expm1(float y)
     {
@@ -41,6 +44,8 @@ template <> struct FeatureMath<FABRIC_FP32> {
     }
     static __device__ inline float log2(float x) { return log2f(x); }
     static __device__ inline float gauss(float d) { return expf(-0.5f * d * d); }
+    static constexpr float kGaussQ = 0.84932180028801904f;
+    static __device__ inline float gauss_q(float qd) { return exp2f(-(qd * qd)); }
     static __device__ inline float expm1(float y) { return expm1f(y); }
 };
 

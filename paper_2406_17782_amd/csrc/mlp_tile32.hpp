@@ -186,7 +186,11 @@ template <int P> struct Tile32 {
     {
         const float per = g ? fwy : fwx;
         const float iper = g ? iwy : iwx;
-        const float ph = wrap_period(g ? v : u, per, iper) * iper;
+        // The phase in revolutions: the coordinate less whole periods, over the
+        // period.  sin and cos are periodic, so the reduction only keeps the
+        // argument small; it need not land exactly in [0, period).
+        const float c = g ? v : u;
+        const float ph = fmaf(-per, floorf(c * iper), c) * iper;
         float sn, cs;
         FM::sincos2pi(ph, &sn, &cs);
 #pragma unroll
@@ -200,9 +204,12 @@ template <int P> struct Tile32 {
             sn = t * s1[8 + q];
         }
         const float tau = fminf(fmaxf((FM::log2(r) + 14.0f) * (1.0f / 16.0f), 0.0f), 1.0f);
+        // Bin b: exp(-d^2 / 2) with d = 8 tau - (4 g + b) - 1/2, the scale of
+        // gauss_q folded into one FMA from tau.
+        constexpr float q = FM::kGaussQ;
 #pragma unroll
         for (int b = 0; b < 4; b++)
-            s1[16 + b] = FM::gauss(8.0f * tau - (float)(4 * g + b) - 0.5f);
+            s1[16 + b] = FM::gauss_q(fmaf(tau, 8.0f * q, -q * ((float)(4 * g + b) + 0.5f)));
     }
 
     template <int KS>

@@ -88,21 +88,30 @@ __device__ inline HalfPix load_half(const fabric_gbuffer &g, const HalfPlanes &h
     return x;
 }
 // This lane group's share of the fault rule of pixel_fault (group 0 holds
-// wi, which may point below the fabric, group 1 wo).
-// Evaluated without short-circuits (no branches per tile).
-__device__ inline bool half_fault(const HalfPix &x, int n_fabrics, int grp)
+// wi, which may point below the fabric, group 1 wo), as a lane mask: one
+// comparison per condition, combined on the scalar unit.  The direction rule
+// is !(z' > 0) with z' = wo.z in group 1 and |wi.z| in group 0 (dir_mask of
+// half_dir_mask clears the sign there).
+__device__ inline uint32_t half_dir_mask(int grp) { return grp ? 0xffffffffu : 0x7fffffffu; }
+__device__ inline unsigned long long half_fault(const HalfPix &x, int n_fabrics, uint32_t dir_mask)
 {
-    const int finite = (int)isfinite(x.uv) & (int)isfinite(x.r) & (int)isfinite(x.x0) &
-                       (int)isfinite(x.x1) & (int)isfinite(x.xz);
-    const int dir_bad = grp ? (int)!(x.xz > 0.0f) : (int)(x.xz == 0.0f);
-    return (!finite | (int)(x.fid >= n_fabrics) | (int)!(x.r > 0.0f) | dir_bad) != 0;
+    const float zsel = __uint_as_float(__float_as_uint(x.xz) & dir_mask);
+    return __ballot(!isfinite(x.uv)) | __ballot(!isfinite(x.r)) | __ballot(!isfinite(x.x0)) |
+           __ballot(!isfinite(x.x1)) | __ballot(!isfinite(x.xz)) | __ballot(x.fid >= n_fabrics) |
+           __ballot(!(x.r > 0.0f)) | __ballot(!(zsel > 0.0f));
 }
-// True in both lanes of a pixel (lanes l and l ^ 32) when either flag is set.
-__device__ inline bool pair_any(bool flag, int lane)
+// Lane mask with both lanes of a pixel (lanes l and l ^ 32) set when either
+// lane's bit of m is set.
+__device__ inline unsigned long long pair_mask(unsigned long long m)
 {
-    const unsigned long long m = __ballot(flag);
-    return (((m | (m >> 32) | (m << 32)) >> lane) & 1ull) != 0;
+    return m | (m >> 32) | (m << 32);
 }
+// This lane's bit of pair_mask(m).
+__device__ inline bool pair_any(unsigned long long m)
+{
+    return __builtin_amdgcn_inverse_ballot_w64(pair_mask(m));
+}
+__device__ inline bool pair_any(bool flag) { return pair_any(__ballot(flag)); }
 
 // Block-cooperative fill of the per-fabric constants s_fc[2 n_fabrics][16]:
 // fwx, fwy, 1/wx, 1/wy, kd (warp, weft RGB), ks / k (warp, weft RGB).  The
