@@ -224,6 +224,46 @@ def precision_row_4k(args, torch, pkg, fi, fab, params):
     return row
 
 
+def c1_row(args, torch, pkg, fi):
+    """The small plain-method case: a 128x128 G-buffer of the plain weave
+    (seeded yarn parameters), the decoder with seeded weights in FP32 and
+    BF16, and the analytic filter at 64 stratified samples; the decoders'
+    largest error against the FP64 oracle's forward of the same weights over
+    every pixel."""
+    import oracle
+    wl = fi.WORKLOADS["plain128"]
+    mats, g = wl.materials(), wl.gbuffer()
+    params = fi.init_params(5, bias_scale=0.05)
+    fab = pkg.Fabric(0, seed=wl.seed())
+    try:
+        fab.set_params(params)
+        fab.encode(mats)
+        d = pkg.DeviceGBuffer.from_host(g)
+        out = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
+        z = oracle.encoder(params[fi.N_DECODER_PARAMS:].astype(np.float64), mats)
+        _, o_rgb = oracle.decoder_gbuffer(params[: fi.N_DECODER_PARAMS], z, mats, g)
+        row = {"pixels": g.n, "fabrics": 1, "weights": "seeded"}
+        for prec in ("fp32", "bf16"):
+            fn = lambda: pkg.fabric_shade_gbuffer(fab.ctx, d, pkg.PREC[prec], 0, 0, out)
+            for _ in range(200):
+                fn()
+            t = time_launches(torch, fn, 200)
+            rgb = out.cpu().numpy()
+            row[prec] = {"us_per_frame": t * 1e3, "mpix_per_s": g.n / (t * 1e-3) / 1e6,
+                         "max_abs_vs_fp64_oracle": float(np.abs(rgb - o_rgb).max())}
+        a = torch.empty((3, g.n), dtype=torch.float32, device="cuda")
+        filt = lambda: pkg.fabric_gt_filtered(fab.ctx, d, 64, 4242, a, None)
+        for _ in range(20):
+            filt()
+        t = time_launches(torch, filt, 50)
+        row["analytic_64"] = {"us_per_frame": t * 1e3, "mpix_per_s": g.n / (t * 1e-3) / 1e6}
+        log(f"c1 128x128: fp32 {row['fp32']['us_per_frame']:.1f} us, bf16 "
+            f"{row['bf16']['us_per_frame']:.1f} us, filter 64 {row['analytic_64']['us_per_frame']:.1f} us")
+        return row
+    finally:
+        fab.close()
+
+
 def hybrid_class_errors(args, torch, pkg, fi, fab, mats, hg):
     """Per-class error of the first hybrid frame against the FP64 oracle's
     filter (256 samples, seeded like the frame's fallback) on a seeded 1 %
@@ -755,6 +795,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=8.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-rows", action="store_true", help="skip the secondary rows")
+    ap.add_argument("--rows", default="all",
+                    help="comma-separated secondary rows to run (default: all)")
     ap.add_argument("--no-rmse", action="store_true", help="skip the oracle error section")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 512 MiB device copy (reference for HBM byte counters)")
@@ -848,7 +890,12 @@ def main():
         rows[f"neural_{prec}"] = {"ms_per_frame": t, "mpix_per_s": g.n / (t * 1e-3) / 1e6}
         rgb[prec] = out.cpu().numpy()
         log(f"neural {prec}: {t * 1e3:.1f} us/frame")
-    if not args.no_rows:
+    def want(name):
+        return not args.no_rows and (args.rows == "all" or name in args.rows.split(","))
+
+    if want("c1_plain128"):
+        rows["c1_plain128"] = c1_row(args, torch, pkg, fi)
+    if want("hybrid_frame"):
         # Hybrid frame: 20 % out-of-range pixels routed to the analytic filter.
         # The hybrid G-buffer (20 % out of range) over the trained fabric
         # table, so that the decoder's class is judged on fabrics it learnt.
@@ -882,6 +929,7 @@ def main():
                                                                         mats, hg)
         log(f"hybrid frame p50 {rows['hybrid_frame']['p50_ms']:.3f} ms")
         fab.encode(mats)
+    if want("encode_8_fabrics"):
         # Encoder: one (re-)encode of 8 fabrics (an edit).
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -890,16 +938,25 @@ def main():
         torch.cuda.synchronize()
         rows["encode_8_fabrics"] = {"ms": (time.perf_counter() - t0) / 20 * 1e3,
                                     "note": "host call incl. table upload"}
+    if want("fabric64_4k"):
         rows["fabric64_4k"] = precision_row_4k(args, torch, pkg, fi, fab, params)
         fab.encode(mats)
+    if want("train_step_2p20"):
         rows["train_step_2p20"] = train_row_2p20(args, torch, pkg, fab)
         fab.encode(mats)
+    if want("latent_interpolation"):
         rows["latent_interpolation"] = interp_row(args, torch, pkg, fi, g, d)
+    if want("visibility"):
         rows["visibility"] = visibility_row(args, torch, pkg, fi, wl, mats, g, d, ms)
+    if want("transmission"):
         rows["transmission"] = btdf_row(args, torch, pkg, fi)
+    if want("paper_decoder"):
         rows["paper_decoder"] = paper_decoder_row(args, torch, pkg, fi, mats, g, d)
+    if want("paper_training"):
         rows["paper_training"] = paper_training_row(args, torch, pkg, fi, mats, g, d, rgb["bf16"])
+    if want("ablations"):
         rows["ablations"] = ablation_row(args, torch, pkg, fi, mats, g, d)
+    if want("paper_encoder"):
         rows["paper_encoder"] = paper_encoder_row(args, torch, pkg, fi, d)
 
     # ---- error against the FP64 oracle on a seeded pixel subset ----

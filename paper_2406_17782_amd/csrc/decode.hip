@@ -161,7 +161,10 @@ __global__ __launch_bounds__(256) void decode32_kernel(
     const int waves = gridDim.x * (blockDim.x >> 6);
     const int wave_id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const HalfPlanes hp = half_planes(g, grp);
-    auto tile_px = [&](int t) { return min((t < n_tiles ? t : wave_id) * 32 + col, n - 1); };
+    // Pixel of this lane in tile t, clamped for the prefetch past the last
+    // tile (t * 32 stays below 2^31: n is at most INT32_MAX / 16 and t less
+    // than n_tiles + waves).
+    auto tile_px = [&](int t) { return min(t * 32 + col, n - 1); };
 
     auto shade_tile = [&](const HalfPix &cur, int tile) {
         const int p = tile * 32 + col;

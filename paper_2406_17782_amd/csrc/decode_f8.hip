@@ -21,10 +21,12 @@ constexpr int kCalibBlock = 64;
 constexpr int kCalibBlocks = kCalibSamples / kCalibBlock;
 constexpr uint64_t kCalibSeed = 0x5ca1ab1e0f8ull;
 
-// Image layout: A fragments [NFRAG][64] i32x8, L2 bias [2][64][4] f32x4,
-// L4 bias [64] f32x4, header, calibration partial maxima [3][kCalibBlocks].
+// Image layout: A fragments [NFRAG][64] i32x8, L3's angular BF16 fragments
+// [NANG][64] bf16x8, L2 bias [2][64][4] f32x4, L4 bias [64] f32x4, header,
+// calibration partial maxima [3][kCalibBlocks].
 constexpr size_t kF8FragBytes = (size_t)DecShapeF8::NFRAG * 64 * sizeof(i32x8);
-constexpr size_t kF8Bias2Off = kF8FragBytes;
+constexpr size_t kF8AngOff = kF8FragBytes;
+constexpr size_t kF8Bias2Off = kF8AngOff + (size_t)DecShapeF8::NANG * 64 * sizeof(bf16x8);
 constexpr size_t kF8Bias4Off = kF8Bias2Off + (size_t)2 * 64 * 4 * sizeof(f32x4);
 constexpr size_t kF8HeaderOff = kF8Bias4Off + (size_t)64 * sizeof(f32x4);
 constexpr size_t kF8PartOff = kF8HeaderOff + sizeof(F8Header);
@@ -138,8 +140,9 @@ __device__ inline float layer_absmax(const float *__restrict__ params, int layer
         for (int k = threadIdx.x; k < 64 * 64; k += blockDim.x)
             m = fmaxf(m, fabsf(params[kOffW2 + k]));
     } else if (layer == 3) {
-        for (int k = threadIdx.x; k < 64 * 69 + 64; k += blockDim.x)
-            m = fmaxf(m, fabsf(params[kOffW3 + k]));   // W3 then b3, contiguous
+        // the chained columns only: the angular ones and the bias are BF16
+        for (int k = threadIdx.x; k < 64 * 64; k += blockDim.x)
+            m = fmaxf(m, fabsf(params[kOffW3 + (k >> 6) * 69 + (k & 63)]));
     } else {
         for (int k = threadIdx.x; k < 4 * 64; k += blockDim.x)
             m = fmaxf(m, fabsf(params[kOffW4 + k]));
@@ -193,7 +196,7 @@ __global__ __launch_bounds__(256) void pack_decoder_f8_kernel(const float *__res
             hd.wmax[l] = wm[l];
             hd.ew[l] = ew[l];
         }
-        hd.sb_ang = 127 - kFeatExp;
+        hd.unused = 0;
         hd.cf_mult = ldexpf(1.0f, eh[0]);
         for (int l = 0; l < 3; l++) {
             hd.hmax[l] = hm[l];
@@ -207,10 +210,10 @@ __global__ __launch_bounds__(256) void pack_decoder_f8_kernel(const float *__res
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < DecShapeF8::NFRAG * 64) {
         const int fr = idx / 64, lane = idx % 64, row = lane & 31, grp = lane >> 5;
-        int layer, mb, ks = 0;
+        int layer, mb;
         if (fr < DecShapeF8::FRAG_L2) { layer = 1; mb = fr; }
         else if (fr < DecShapeF8::FRAG_L3) { layer = 2; mb = fr - DecShapeF8::FRAG_L2; }
-        else if (fr < DecShapeF8::FRAG_L4) { layer = 3; mb = (fr - DecShapeF8::FRAG_L3) / 2; ks = (fr - DecShapeF8::FRAG_L3) % 2; }
+        else if (fr < DecShapeF8::FRAG_L4) { layer = 3; mb = fr - DecShapeF8::FRAG_L3; }
         else { layer = 4; mb = 0; }
         const int m = 32 * mb + row;
         const float sc = ldexpf(1.0f, hd.ew[layer - 1]);
@@ -223,19 +226,34 @@ __global__ __launch_bounds__(256) void pack_decoder_f8_kernel(const float *__res
             } else if (layer == 2) {
                 val = params[kOffW2 + m * 64 + chain32_neuron(grp, j)];
             } else if (layer == 3) {
-                if (ks == 0) {
-                    val = params[kOffW3 + m * 69 + chain32_neuron(grp, j)];
-                } else if (j < 3) {
-                    const int a = l3_extra32(grp, j);
-                    if (a == 5) val = params[kOffB3 + m];
-                    else if (a >= 0) val = params[kOffW3 + m * 69 + 64 + a];
-                }
-            } else if (m < 4) {
-                val = params[kOffW4 + m * 64 + chain32_neuron(grp, j)];
+                val = params[kOffW3 + m * 69 + chain32_neuron(grp, j)];
+            } else {
+                // 16x16x128 operand: row lane % 16, K block lane / 16
+                const int r16 = lane & 15, kb = lane >> 4;
+                if (r16 < 4 && (kb & 1) == 0)
+                    val = params[kOffW4 + r16 * 64 + chain32_neuron(kb >> 1, j)];
+                else if (r16 >= 4 && r16 < 8 && (kb & 1) == 1)
+                    val = params[kOffW4 + (r16 - 4) * 64 + chain32_neuron(kb >> 1, j)];
             }
             w[j] = val * sc;
         }
         ((i32x8 *)image)[idx] = pack_f8x32(w);
+    }
+    if (idx < DecShapeF8::NANG * 64) {
+        // L3's angular inputs and bias: BF16 32x32x16 A fragment of M-block
+        // mb, lane group g's slots 0..2, weights 2^eh3 W (the FP8 steps'
+        // output scale).
+        const int mb = idx >> 6, lane = idx & 63, grp = lane >> 5, m = 32 * mb + (lane & 31);
+        const float sc = ldexpf(1.0f, hd.eh[2]);
+        f32x8 w;
+        for (int j = 0; j < 8; j++) {
+            const int a = j < 3 ? l3_extra32(grp, j) : -1;
+            float val = 0.0f;
+            if (a == 5) val = params[kOffB3 + m];
+            else if (a >= 0) val = params[kOffW3 + m * 69 + 64 + a];
+            w[j] = val * sc;
+        }
+        ((bf16x8 *)(image + kF8AngOff))[idx] = Mfma<FABRIC_BF16>::from8(w);
     }
     if (idx < 2 * 64 * 4) {
         // bias2[(mb*64 + lane)*4 + q][i] = 2^eh2 b2[row of register 4q + i]
@@ -266,15 +284,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     using FM = FeatureMath<FABRIC_BF16>;
     const F8Header hd = *(const F8Header *)(image + kF8HeaderOff);
 
-    // LDS: L2 C-operand bias [2][64 lanes][4 x f32x4], then per fabric
+    // LDS: L2's C-operand bias by row [64] (register r of lane group g of
+    // M-block mb holds row 32 mb + 8 (r / 4) + 4 g + r % 4, so the lanes of a
+    // group read the same four rows: broadcast reads), then per fabric
     // 2^eh1 c_f [64], then the staged constants [kFabCopies][n_fabrics][kFabConsts].
     extern __shared__ f32x4 smem4[];
-    f32x4 *s_b2 = smem4;
-    float *s_cf = (float *)(smem4 + 2 * 64 * 4);
+    float *s_b2 = (float *)smem4;
+    float *s_cf = s_b2 + 64;
     float *s_fc = s_cf + n_fabrics * 64;
-    const f32x4 *bias2 = (const f32x4 *)(image + kF8Bias2Off);
-    for (int k = threadIdx.x; k < 2 * 64 * 4; k += blockDim.x)
-        s_b2[k] = bias2[k];
+    const f32x4 *bias2 = (const f32x4 *)(image + kF8Bias2Off);   // [2][64 lanes][4]
+    for (int k = threadIdx.x; k < 64; k += blockDim.x) {
+        const int mb = k >> 5, q4 = (k & 31) >> 3, g = (k & 7) >> 2, i = k & 3;
+        s_b2[k] = bias2[(mb * 64 + 32 * g) * 4 + q4][i];
+    }
     for (int k = threadIdx.x; k < n_fabrics * 64; k += blockDim.x)
         s_cf[k] = cfold[k] * hd.cf_mult;
     stage_fabric_consts(fabrics, n_fabrics, s_fc);
@@ -291,13 +313,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         A[q] = ((const i32x8 *)image)[q * 64 + lane];
     auto getA = [&](int q) { return A[q]; };
     const f32x4 b4 = ((const f32x4 *)(image + kF8Bias4Off))[lane];
+    bf16x8 A3x[DecShapeF8::NANG];
+#pragma unroll
+    for (int mb = 0; mb < DecShapeF8::NANG; mb++)
+        A3x[mb] = ((const bf16x8 *)(image + kF8AngOff))[mb * 64 + lane];
 
     // The MFMA takes its scales from VGPRs: keep them there for the whole loop.
     F8Header sc = hd;
 #pragma unroll
     for (int l = 0; l < 4; l++)
         asm volatile("" : "+v"(sc.sa[l]), "+v"(sc.sb[l]));
-    asm volatile("" : "+v"(sc.sb_ang));
 
     const int n = (int)g.n;
     const int waves = gridDim.x * (blockDim.x >> 6);
@@ -310,7 +335,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         int p, fid;     // fid: the staged-constant entry (transmission copy for light from below)
         bool valid, fault, oor;
         i32x8 B1;   // L1's B operand
-        int x3;     // L3's angular B operand (word 0)
+        bf16x8 x3;  // L3's angular B operand
     };
     auto prepare = [&](const HalfPix &cur, int tile, Prep &r, f32x16 (&a)[2]) {
         r.p = tile * 32 + col;
@@ -335,7 +360,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                     a[mb][4 * q4 + i] = c4[i];
             }
         // group 1's third slot carries L3's bias
-        r.x3 = TileF8::l3x_word(cur.x0, cur.x1, grp ? 1.0f : cur.xz);
+        r.x3 = TileF8::l3x_frag(cur.x0, cur.x1, grp ? 1.0f : cur.xz);
         r.fid = fab_entry(r.fid, n_fabrics, grp ? 1.0f : cur.xz);   // after the c_f reads above
     };
     auto finish = [&](const Prep &r, const f32x16 &y, int tile) {
@@ -360,7 +385,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         f32x16 b;
 #pragma unroll
         for (int q4 = 0; q4 < 4; q4++) {
-            const f32x4 bq = s_b2[(mb * 64 + lane) * 4 + q4];
+            const f32x4 bq = *(const f32x4 *)(s_b2 + 32 * mb + 8 * q4 + 4 * grp);
 #pragma unroll
             for (int i = 0; i < 4; i++)
                 b[4 * q4 + i] = bq[i];
@@ -380,7 +405,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         f32x16 a0[2], a1[2];
         prepare(c0, tile, r0, a0);
         prepare(c1, tile + waves, r1, a1);
-        TileF8::forward2(getA, sc, a0, a1, getB2, r0.B1, r1.B1, r0.x3, r1.x3);
+        TileF8::forward2(getA, sc, a0, a1, getB2, A3x, r0.B1, r1.B1, r0.x3, r1.x3);
         finish(r0, a0[0], tile);
         finish(r1, a1[0], tile + waves);
     }
@@ -418,7 +443,7 @@ hipError_t launch_decode_f8(const fabric_gbuffer &g, const DevFabric *fabrics, i
     const int cap = device_cus() * 2;
     if (blocks > cap)
         blocks = cap;
-    const size_t lds = (size_t)2 * 64 * 4 * sizeof(f32x4) +
+    const size_t lds = (size_t)64 * sizeof(float) +
                        (size_t)n_fabrics * (64 + kFabCopies * kFabConsts) * sizeof(float);
     if (hybrid)
         hipLaunchKernelGGL(decode_f8_kernel<true>, dim3(blocks), dim3(256), lds, stream, g,
