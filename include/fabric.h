@@ -11,8 +11,9 @@
  *     Rendering" (SIGGRAPH 2024), Sec. 4.1 Eq. (7); the reflectance is their
  *     albedo-weighted sum, Eq. (8);
  *   - analytically: the point shading model of Eq. (1)-(2) integrated over the
- *     pixel footprint with the aggregation of Eq. (3)-(5) (visibility V = 1) by
- *     stratified Monte-Carlo samples.  This produces the decoder's training
+ *     pixel footprint with the aggregation of Eq. (3)-(5) by stratified
+ *     Monte-Carlo samples (visibility V = 1 by default, or the inter-yarn
+ *     march of fabric_set_visibility).  This produces the decoder's training
  *     targets (Sec. 4.2, "Loss functions") and serves as its ground truth and
  *     fallback.
  *
@@ -20,7 +21,9 @@
  *   - Frames and units.  The macro surface normal is +z.  u runs along +x
  *     (the weft direction), v along +y (the warp direction).  uv and the
  *     footprint radius are in weave cells (one warp x weft crossing = 1).
- *     Directions are unit vectors with z > 0 (reflection only).
+ *     Directions are unit vectors; wo.z > 0 (the viewer is above the
+ *     fabric) and wi.z != 0: wi.z > 0 is reflection, wi.z < 0 light
+ *     transmitted from below (Sec. 4.2, the BTDF queries).
  *   - Memory.  Pointers named "device" point to GPU memory of the context's
  *     device; the caller owns them.  "host" pointers are CPU memory.  The
  *     context owns its weights, latents, optimiser state and scratch.
@@ -313,8 +316,8 @@ fabric_status fabric_shade_gbuffer_noalloc(fabric_ctx *ctx, const fabric_gbuffer
                                            fabric_prec prec, int32_t fallback_samples,
                                            uint64_t seed, float *out_rgb, void *stream);
 
-/* Footprint-filtered analytic shading (Eq. (3)-(5), V = 1; components of
- * Eq. (7)).  Pixel p's footprint is the disk of radius radius[p] about
+/* Footprint-filtered analytic shading (Eq. (3)-(5), with V as set by
+ * fabric_set_visibility; components of Eq. (7)).  Pixel p's footprint is the disk of radius radius[p] about
  * (u[p], v[p]) with a uniform kernel; n_samples = m*m stratified samples,
  * stratum k = ky*m + kx jittered by the (p*n_samples + k)-th output of
  * SplitMix64 seeded with `seed` (upper 24 bits for x, bits 39..16 for y) and
@@ -380,14 +383,17 @@ fabric_status fabric_make_batch(fabric_ctx *ctx, uint64_t seed, int64_t n, float
  * loss of Eq. (9)-(11) (lambda_S = 0.4, lambda_C = 0.1, k = 100 for samples
  * lit from above and 1000 for samples lit from below), gradients
  * by hand-written backward kernels, Adam with FP64 moments on FP32 masters.
+ * The loss is summed in FP32 in a fixed order with compensated (Kahan)
+ * sums; Adam's step count lives on the device with its moments, so a step
+ * skipped for a non-finite loss is not counted, out_loss given or not.
  *   batch        device G-buffer, or NULL to draw cfg->batch samples with
  *                fabric_make_batch(cfg->seed)
  *   targets      device float [4][n] components (only with a batch), or NULL
  *                to compute them with the analytic filter (cfg->gt_samples
  *                samples, seed cfg->seed ^ 1)
  *   out_loss     host float, or NULL for no synchronisation
- * A non-finite loss leaves weights and moments unchanged and returns
- * E_NONFINITE (only detectable when out_loss is given).  After a step,
+ * A non-finite loss leaves weights, moments and step count unchanged and
+ * returns E_NONFINITE (reported only when out_loss is given).  After a step,
  * shading needs fabric_encode again (E_STATE otherwise). */
 fabric_status fabric_train_step(fabric_ctx *ctx, const fabric_gbuffer *batch,
                                 const float *targets, const fabric_train_cfg *cfg,

@@ -94,6 +94,21 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
+// Compensated (Kahan) FP32 sum, for the fixed-order reductions of the
+// training kernels: the error stays at a few units of the last place of the
+// sum of magnitudes, independent of the number of terms.
+struct KahanSum {
+    float s = 0.0f, c = 0.0f;
+    __device__ inline void add(float x)
+    {
+        const float y = x - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ inline float value() const { return s - c; }
+};
+
 template <int P> struct Mfma;
 
 template <> struct Mfma<FABRIC_FP32> {

@@ -21,7 +21,10 @@ struct fabric_ctx {
     float *params = nullptr;          // FP32 masters [decoder | encoder]
     double *adam_m = nullptr;         // FP64 first moments
     double *adam_v = nullptr;         // FP64 second moments
-    int64_t step = 0;
+    // Adam step counts on the device, [0] the config network's, [1] the
+    // paper-size network's, and their last bias corrections [2][2].
+    int64_t *adam_t = nullptr;
+    double *adam_corr = nullptr;
     uint64_t weights_version = 1;     // bumped on every parameter change
 
     int n_mats = 0;
@@ -47,7 +50,6 @@ struct fabric_ctx {
     float *paper_latents = nullptr;   // [FABRIC_MAX_FABRICS][64]: the encoder's latents
     double *paper_m = nullptr;        // their FP64 Adam moments
     double *paper_v = nullptr;
-    int64_t paper_step = 0;
     bool paper_raw = false;           // footprint inputs without the one-blob encoding
     bool paper_fused = true;          // false: no spatial fusion stage
     PaperTrainScratch paper_train;
@@ -544,6 +546,8 @@ void fabric_destroy(fabric_ctx *ctx)
     (void)hipFree(ctx->params);
     (void)hipFree(ctx->adam_m);
     (void)hipFree(ctx->adam_v);
+    (void)hipFree(ctx->adam_t);
+    (void)hipFree(ctx->adam_corr);
     (void)hipFree(ctx->fabrics);
     (void)hipFree(ctx->enc_inputs);
     (void)hipFree(ctx->latents);
@@ -591,6 +595,8 @@ fabric_status fabric_create(fabric_ctx **out, int device, uint64_t seed)
     if (st == FABRIC_OK) st = dalloc(&ctx->params, FABRIC_N_PARAMS);
     if (st == FABRIC_OK) st = dalloc(&ctx->adam_m, FABRIC_N_PARAMS);
     if (st == FABRIC_OK) st = dalloc(&ctx->adam_v, FABRIC_N_PARAMS);
+    if (st == FABRIC_OK) st = dalloc(&ctx->adam_t, 2);
+    if (st == FABRIC_OK) st = dalloc(&ctx->adam_corr, 4);
     if (st == FABRIC_OK) st = dalloc(&ctx->fabrics, F);
     if (st == FABRIC_OK) st = dalloc(&ctx->enc_inputs, F * kEncIn);
     if (st == FABRIC_OK) st = dalloc(&ctx->latents, F * kLatent);
@@ -615,6 +621,8 @@ fabric_status fabric_create(fabric_ctx **out, int device, uint64_t seed)
     }
     if (st == FABRIC_OK) st = from_hip(hipMemset(ctx->adam_m, 0, FABRIC_N_PARAMS * sizeof(double)));
     if (st == FABRIC_OK) st = from_hip(hipMemset(ctx->adam_v, 0, FABRIC_N_PARAMS * sizeof(double)));
+    if (st == FABRIC_OK) st = from_hip(hipMemset(ctx->adam_t, 0, 2 * sizeof(int64_t)));
+    if (st == FABRIC_OK) st = from_hip(hipMemset(ctx->adam_corr, 0, 4 * sizeof(double)));
     if (st == FABRIC_OK) st = from_hip(hipMemset(ctx->err, 0, sizeof(unsigned long long)));
     if (st == FABRIC_OK) st = from_hip(hipDeviceSynchronize());
     if (st != FABRIC_OK) {
@@ -712,6 +720,7 @@ fabric_status fabric_paper_prepare(fabric_ctx *ctx, const float *params, const f
                                      hipMemcpyDeviceToDevice, s));
     if (st == FABRIC_OK) st = from_hip(hipMemsetAsync(ctx->paper_m, 0, total * sizeof(double), s));
     if (st == FABRIC_OK) st = from_hip(hipMemsetAsync(ctx->paper_v, 0, total * sizeof(double), s));
+    if (st == FABRIC_OK) st = from_hip(hipMemsetAsync(ctx->adam_t + 1, 0, sizeof(int64_t), s));
     if (st == FABRIC_OK)
         st = from_hip(launch_paper_prepare(pm, lm, ctx->n_mats, ctx->paper_fused, ctx->paper_image,
                                            ctx->paper_cfold, s));
@@ -719,7 +728,6 @@ fabric_status fabric_paper_prepare(fabric_ctx *ctx, const float *params, const f
         ctx->paper_n_mats = 0;
         return st;
     }
-    ctx->paper_step = 0;
     ctx->paper_n_mats = ctx->n_mats;
     ctx->paper_serial = ctx->table_serial;
     return FABRIC_OK;
@@ -745,11 +753,11 @@ fabric_status fabric_paper_prepare_encoder(fabric_ctx *ctx, const float *params,
                                      hipMemcpyDeviceToDevice, s));
     if (st == FABRIC_OK) st = from_hip(hipMemsetAsync(ctx->paper_m, 0, kPaperMasterFloats * sizeof(double), s));
     if (st == FABRIC_OK) st = from_hip(hipMemsetAsync(ctx->paper_v, 0, kPaperMasterFloats * sizeof(double), s));
+    if (st == FABRIC_OK) st = from_hip(hipMemsetAsync(ctx->adam_t + 1, 0, sizeof(int64_t), s));
     ctx->paper_encoder = true;
     ctx->paper_n_mats = 0;
     if (st != FABRIC_OK)
         return st;
-    ctx->paper_step = 0;
     return fabric_paper_encode(ctx, stream);
 }
 
@@ -1083,7 +1091,7 @@ TrainArgs train_args(fabric_ctx *ctx, const fabric_gbuffer *batch, const float *
     a.params = ctx->params;
     a.adam_m = ctx->adam_m;
     a.adam_v = ctx->adam_v;
-    a.step = ctx->step + 1;
+    a.clock = AdamClock{ctx->adam_t, ctx->adam_corr};
     a.fabrics = ctx->fabrics;
     a.enc_inputs = ctx->enc_inputs;
     a.n_fabrics = ctx->n_mats;
@@ -1126,10 +1134,9 @@ fabric_status fabric_train_step(fabric_ctx *ctx, const fabric_gbuffer *batch, co
     hipError_t e = train_step(ctx->train, a, out_loss, &updated, as_stream(stream));
     if (e != hipSuccess)
         return from_hip(e);
+    ctx->weights_version += 1;
     if (!updated)
         return FABRIC_E_NONFINITE;
-    ctx->step += 1;
-    ctx->weights_version += 1;
     return FABRIC_OK;
 }
 
@@ -1157,7 +1164,7 @@ PaperTrainArgs paper_train_args(fabric_ctx *ctx, const fabric_gbuffer *batch, co
     a.master = ctx->paper_master;
     a.adam_m = ctx->paper_m;
     a.adam_v = ctx->paper_v;
-    a.step = ctx->paper_step + 1;
+    a.clock = AdamClock{ctx->adam_t + 1, ctx->adam_corr + 2};
     a.fabrics = ctx->fabrics;
     a.n_fabrics = ctx->n_mats;
     a.batch = batch;
@@ -1238,7 +1245,6 @@ fabric_status fabric_paper_train_step(fabric_ctx *ctx, const fabric_gbuffer *bat
         return from_hip(e);
     if (!updated)
         return FABRIC_E_NONFINITE;
-    ctx->paper_step += 1;
     return FABRIC_OK;
 }
 
@@ -1333,11 +1339,12 @@ fabric_status fabric_save(fabric_ctx *ctx, void *host, size_t *bytes)
     std::memcpy(h.magic, kMagic, 8);
     h.version = 1;
     h.n_params = FABRIC_N_PARAMS;
-    h.step = ctx->step;
+    fabric_status st = from_hip(hipDeviceSynchronize());
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpy(&h.step, ctx->adam_t, sizeof(int64_t), hipMemcpyDeviceToHost));
     char *p = (char *)host;
     std::memcpy(p, &h, sizeof(h));
     p += sizeof(h);
-    fabric_status st = from_hip(hipDeviceSynchronize());
     if (st == FABRIC_OK)
         st = from_hip(hipMemcpy(p, ctx->params, FABRIC_N_PARAMS * sizeof(float), hipMemcpyDeviceToHost));
     p += FABRIC_N_PARAMS * sizeof(float);
@@ -1370,10 +1377,10 @@ fabric_status fabric_load(fabric_ctx *ctx, const void *host, size_t bytes)
     p += FABRIC_N_PARAMS * sizeof(double);
     if (st == FABRIC_OK)
         st = from_hip(hipMemcpy(ctx->adam_v, p, FABRIC_N_PARAMS * sizeof(double), hipMemcpyHostToDevice));
-    if (st == FABRIC_OK) {
-        ctx->step = h.step;
+    if (st == FABRIC_OK)
+        st = from_hip(hipMemcpy(ctx->adam_t, &h.step, sizeof(int64_t), hipMemcpyHostToDevice));
+    if (st == FABRIC_OK)
         ctx->weights_version += 1;
-    }
     return st;
 }
 

@@ -133,11 +133,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ P, const float *__restrict__ lat, const float *__restrict__ wt,
     const float *__restrict__ targets, float *__restrict__ pl, int64_t cap, int raw, int fused,
-    double *__restrict__ loss_part)
+    float *__restrict__ loss_part)
 {
     __shared__ float bufA[kFbSamples * kFbStride];
     __shared__ float bufB[kFbSamples * kFbStrideB];
-    __shared__ double red[kFbSamples];
+    __shared__ float red[kFbSamples];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int o0 = 16 * w;
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
     __syncthreads();
     // ---- loss terms of Eq. (9)-(11) and dL/dy (every wave, for its own use) ----
     float dy[4];
-    double loss = 0.0;
+    float loss = 0.0f;
     {
         const float inv_n = 1.0f / (float)n;
         // g(x) = ln(k x + 1): k = 100 for reflection, 1000 for transmission.
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
             const float target = c < 2 ? t : log1pf(k * t);
             const float lam = c < 2 ? 0.1f : 0.4f;        // lambda_C, lambda_S
             const float d = rowB[c] - target;
-            loss += fault ? 0.0 : (double)(lam * d * d);
+            loss = fault ? loss : fmaf(lam * d, d, loss);
             dy[c] = fault ? 0.0f : 2.0f * lam * d * inv_n;
         }
         if (w == 0) {
@@ -301,22 +301,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
         red[lane] = loss;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double t = 0.0;
+        KahanSum t;
         for (int k = 0; k < kFbSamples; k++)
-            t += red[k];
-        loss_part[blockIdx.x] = t;
+            t.add(red[k]);
+        loss_part[blockIdx.x] = t.value();
     }
 }
 
-__global__ __launch_bounds__(256) void paper_loss_reduce_kernel(const double *__restrict__ part,
-                                                                int64_t nparts, double inv_n,
-                                                                double *__restrict__ loss)
+__global__ __launch_bounds__(256) void paper_loss_reduce_kernel(const float *__restrict__ part,
+                                                                int64_t nparts, float inv_n,
+                                                                float *__restrict__ loss)
 {
-    __shared__ double red[256];
-    double acc = 0.0;
+    __shared__ float red[256];
+    KahanSum acc;
     for (int64_t k = threadIdx.x; k < nparts; k += blockDim.x)
-        acc += part[k];
-    red[threadIdx.x] = acc;
+        acc.add(part[k]);
+    red[threadIdx.x] = acc.value();
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
@@ -457,28 +457,29 @@ __global__ __launch_bounds__(256) void paper_wgrad_reduce_kernel(PWJobs jobs, in
     if (e >= E)
         return;
     const float *src = partial + jobs.poff[blockIdx.y] + e;
-    // Eight interleaved partial sums (independent loads in flight), combined
-    // in a fixed order.
-    double part[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // Eight interleaved compensated sums (independent loads in flight),
+    // combined in a fixed order.
+    KahanSum part[8];
     int c = 0;
     for (; c + 8 <= n_chunks; c += 8) {
 #pragma unroll
         for (int k = 0; k < 8; k++)
-            part[k] += (double)src[(int64_t)(c + k) * E];
+            part[k].add(src[(int64_t)(c + k) * E]);
     }
     for (; c < n_chunks; c++)
-        part[0] += (double)src[(int64_t)c * E];
-    double acc = 0.0;
+        part[0].add(src[(int64_t)c * E]);
+    KahanSum tot;
 #pragma unroll
     for (int k = 0; k < 8; k++)
-        acc += part[k];
+        tot.add(part[k].value());
+    const float acc = tot.value();
     const int i = e / cols, j = e % cols;
     if (jb.onehot)
-        dsum[j * 64 + i] = (float)acc;
+        dsum[j * 64 + i] = acc;
     else if (j < jb.nA + jb.nB)
-        grad[jb.w_off + i * jb.row + jb.col + j] = (float)acc;
+        grad[jb.w_off + i * jb.row + jb.col + j] = acc;
     else
-        grad[jb.b_off + i] = (float)acc;
+        grad[jb.b_off + i] = acc;
 }
 
 // F1's latent columns: dWF1[o][j] = sum_f D[f][o] z_f[j]; the latents:
@@ -578,7 +579,7 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
         if ((e = hipMalloc((void **)&s.enc_acts, (size_t)kPaperTrainMaxFabrics * kPEncAct * sizeof(float))) != hipSuccess) return e;
         if ((e = hipMalloc((void **)&s.dsum, (size_t)kPaperTrainMaxFabrics * 64 * sizeof(float))) != hipSuccess) return e;
         if ((e = hipMalloc((void **)&s.wt, (size_t)kTFloats * sizeof(float))) != hipSuccess) return e;
-        if ((e = hipMalloc((void **)&s.loss, sizeof(double))) != hipSuccess) return e;
+        if ((e = hipMalloc((void **)&s.loss, sizeof(float))) != hipSuccess) return e;
     }
     fabric_gbuffer g;
     if (a.batch) {
@@ -615,7 +616,7 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
         lat = s.lat;
     }
     if (n == 0) {
-        if ((e = hipMemsetAsync(s.loss, 0, sizeof(double), stream)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(s.loss, 0, sizeof(float), stream)) != hipSuccess) return e;
         return hipMemsetAsync(s.grad, 0, (size_t)paper_trained_count(a) * sizeof(float), stream);
     }
     const float *targets = a.targets;
@@ -656,7 +657,7 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
                        a.fabrics, a.n_fabrics, P, lat, (const float *)s.wt, targets, s.planes,
                        s.cap, a.raw ? 1 : 0, a.fused ? 1 : 0, s.loss_part);
     hipLaunchKernelGGL(paper_loss_reduce_kernel, dim3(1), dim3(256), 0, stream,
-                       (const double *)s.loss_part, blocks, 1.0 / (double)n, s.loss);
+                       (const float *)s.loss_part, blocks, 1.0f / (float)n, s.loss);
     hipLaunchKernelGGL(paper_wgrad_kernel, dim3(n_chunks, jobs.n_jobs), dim3(kPwThreads), 0, stream, jobs,
                        (const float *)s.planes, s.cap, g.fabric_id, n, s.partial);
     hipLaunchKernelGGL(paper_wgrad_reduce_kernel, dim3((64 * kPwMaxIn + 255) / 256, jobs.n_jobs),
@@ -678,11 +679,11 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
 hipError_t read_paper_loss(PaperTrainScratch &s, float *out_loss, int *finite_loss,
                            hipStream_t stream)
 {
-    double l = 0.0;
+    float l = 0.0f;
     hipError_t e;
-    if ((e = hipMemcpyAsync(&l, s.loss, sizeof(double), hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(&l, s.loss, sizeof(float), hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;
-    *out_loss = (float)l;
+    *out_loss = l;
     *finite_loss = std::isfinite(l) ? 1 : 0;
     return hipSuccess;
 }
@@ -730,7 +731,7 @@ hipError_t paper_train_step(PaperTrainScratch &s, const PaperTrainArgs &a, float
     if (e != hipSuccess)
         return e;
     if ((e = launch_adam(a.master, s.grad, a.adam_m, a.adam_v, paper_trained_count(a), a.cfg,
-                         a.step, s.loss, stream)) != hipSuccess)
+                         a.clock, s.loss, stream)) != hipSuccess)
         return e;
     // The latents of the updated encoder, for the shading image.
     if (a.enc_inputs &&

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
+#include "train.hpp"
 
 namespace fab {
 
@@ -16,8 +17,8 @@ constexpr int kPaperTrainMaxFabrics = 64;
 struct PaperTrainScratch {
     int64_t cap = 0;              // samples the per-sample planes hold
     float *planes = nullptr;      // per-sample planes [801][cap] (see paper_train.hip)
-    double *loss_part = nullptr;  // per 256-sample block
-    double *loss = nullptr;       // [1]
+    float *loss_part = nullptr;   // per 256-sample block
+    float *loss = nullptr;        // [1]
     float *wt = nullptr;          // transposed weights of F2, A1 (first 64 inputs), A2, A3, A4
     float *partial = nullptr;     // split-K partial weight gradients
     size_t partial_floats = 0;
@@ -41,7 +42,7 @@ struct PaperTrainArgs {
     // enc_inputs: [params | encoder parameters (kPaperEncParams)]
     float *master;
     double *adam_m, *adam_v;      // same length
-    int64_t step;                 // 1-based Adam step of this update
+    AdamClock clock;              // the moments' step count
     const DevFabric *fabrics;
     int n_fabrics;
     const fabric_gbuffer *batch;  // NULL: generate

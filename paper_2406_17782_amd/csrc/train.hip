@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(
     const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ ffr,
     const f32x4 *__restrict__ fbias, const typename Mfma<P>::Frag *__restrict__ bfr,
     const float *__restrict__ tgt_or_dy, float *__restrict__ acts, int64_t cap,
-    double *__restrict__ loss_part, unsigned long long *err)
+    float *__restrict__ loss_part, unsigned long long *err)
 {
     using T = Tile<P>;
     using M = typename T::M;
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(
 
     // ---- dL/dy (lane group 0 holds y of its pixel) ----
     float dy[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    double loss = 0.0;
+    float loss = 0.0f;
     if (grp == 0 && live) {
         if (GIVEN_DY) {
 #pragma unroll
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(
                 const float target = c < 2 ? t : log1pf(k * t);
                 const float lam = c < 2 ? 0.1f : 0.4f;                // lambda_C, lambda_S
                 const float d = y[c] - target;
-                loss += (double)(lam * d * d);
+                loss = fmaf(lam * d, d, loss);
                 dy[c] = 2.0f * lam * d * inv_n;
             }
         }
@@ -513,15 +513,17 @@ __global__ void encoder_wgrad_kernel(const float *__restrict__ scratch, int n_fa
 // ---------------------------------------------------------------------------
 // Loss reduction and Adam
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void loss_reduce_kernel(const double *__restrict__ part,
-                                                          int64_t nparts, double inv_n,
-                                                          double *__restrict__ loss)
+// The batch loss: per thread a compensated sum of every 256th part, then a
+// fixed tree over the threads.
+__global__ __launch_bounds__(256) void loss_reduce_kernel(const float *__restrict__ part,
+                                                          int64_t nparts, float inv_n,
+                                                          float *__restrict__ loss)
 {
-    __shared__ double red[256];
-    double acc = 0.0;
+    __shared__ float red[256];
+    KahanSum acc;
     for (int64_t k = threadIdx.x; k < nparts; k += blockDim.x)
-        acc += part[k];
-    red[threadIdx.x] = acc;
+        acc.add(part[k]);
+    red[threadIdx.x] = acc.value();
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
@@ -532,14 +534,30 @@ __global__ __launch_bounds__(256) void loss_reduce_kernel(const double *__restri
         loss[0] = red[0] * inv_n;
 }
 
+// The step count of an Adam state lives on the device with its moments: a
+// step is counted, and its bias corrections 1 - beta^t computed, only when
+// the batch loss is finite, so that an update skipped for a non-finite loss
+// leaves the count where the moments are.  One thread.
+__global__ void adam_count_kernel(AdamClock clk, double beta1, double beta2,
+                                  const float *__restrict__ loss)
+{
+    if (!isfinite(loss[0]))
+        return;
+    const int64_t t = clk.t[0] + 1;
+    clk.t[0] = t;
+    clk.corr[0] = 1.0 - pow(beta1, (double)t);
+    clk.corr[1] = 1.0 - pow(beta2, (double)t);
+}
+
 __global__ void adam_kernel(float *__restrict__ params, const float *__restrict__ grad,
                             double *__restrict__ m, double *__restrict__ v, int n, double lr,
-                            double beta1, double beta2, double eps, double c1, double c2,
-                            const double *__restrict__ loss)
+                            double beta1, double beta2, double eps,
+                            const double *__restrict__ corr, const float *__restrict__ loss)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n || !isfinite(loss[0]))
         return;
+    const double c1 = corr[0], c2 = corr[1];
     const double gk = (double)grad[k];
     const double mk = beta1 * m[k] + (1.0 - beta1) * gk;
     const double vk = beta2 * v[k] + (1.0 - beta2) * gk * gk;
@@ -569,7 +587,7 @@ hipError_t ensure_acts(TrainScratch &s, int64_t n)
         if ((e = hipMalloc((void **)&s.enc_acts, (size_t)FABRIC_MAX_FABRICS * kEncActFloats * sizeof(float))) != hipSuccess) return e;
         if ((e = hipMalloc((void **)&s.latents, FABRIC_MAX_FABRICS * kLatent * sizeof(float))) != hipSuccess) return e;
         if ((e = hipMalloc((void **)&s.cfold, FABRIC_MAX_FABRICS * 64 * sizeof(float))) != hipSuccess) return e;
-        if ((e = hipMalloc((void **)&s.loss, sizeof(double))) != hipSuccess) return e;
+        if ((e = hipMalloc((void **)&s.loss, sizeof(float))) != hipSuccess) return e;
         // The largest images are the FP32 ones.
         if ((e = hipMalloc(&s.fwd_image, decoder_image_bytes(FABRIC_FP32))) != hipSuccess) return e;
         if ((e = hipMalloc(&s.bwd_image, (size_t)BwdShape<1>::NFRAG * 64 * sizeof(float))) != hipSuccess) return e;
@@ -700,13 +718,13 @@ void train_scratch_free(TrainScratch &s)
 }
 
 hipError_t launch_adam(float *params, const float *grad, double *m, double *v, int n,
-                       const fabric_train_cfg &cfg, int64_t step, const double *loss,
+                       const fabric_train_cfg &cfg, AdamClock clk, const float *loss,
                        hipStream_t stream)
 {
-    const double c1 = 1.0 - std::pow(cfg.beta1, (double)step);
-    const double c2 = 1.0 - std::pow(cfg.beta2, (double)step);
+    hipLaunchKernelGGL(adam_count_kernel, dim3(1), dim3(1), 0, stream, clk, cfg.beta1, cfg.beta2,
+                       loss);
     hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, params, grad, m, v,
-                       n, cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, c1, c2, loss);
+                       n, cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, (const double *)clk.corr, loss);
     return hipGetLastError();
 }
 
@@ -816,11 +834,11 @@ hipError_t loss_and_grad(TrainScratch &s, const TrainArgs &a, hipStream_t stream
                 : launch_fwd_bwd<FABRIC_BF16, false>(s, g, a.fabrics, a.n_fabrics, s.cfold, targets, err, stream);
         if (e != hipSuccess) return e;
         const int64_t parts = (n + 15) / 16;
-        hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, stream, (const double *)s.loss_part,
-                           parts, 1.0 / (double)n, s.loss);
+        hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, stream, (const float *)s.loss_part,
+                           parts, 1.0f / (float)n, s.loss);
         if ((e = decoder_weight_grads(s, g, a.n_fabrics, s.grad, stream)) != hipSuccess) return e;
     } else {
-        if ((e = hipMemsetAsync(s.loss, 0, sizeof(double), stream)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(s.loss, 0, sizeof(float), stream)) != hipSuccess) return e;
         if ((e = hipMemsetAsync(s.grad, 0, kNDec * sizeof(float), stream)) != hipSuccess) return e;
         if ((e = hipMemsetAsync(s.dcf, 0, (size_t)a.n_fabrics * 64 * sizeof(float), stream)) != hipSuccess) return e;
     }
@@ -834,11 +852,11 @@ hipError_t loss_and_grad(TrainScratch &s, const TrainArgs &a, hipStream_t stream
 
 hipError_t read_loss(TrainScratch &s, float *out_loss, int *finite_loss, hipStream_t stream)
 {
-    double l = 0.0;
+    float l = 0.0f;
     hipError_t e;
-    if ((e = hipMemcpyAsync(&l, s.loss, sizeof(double), hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(&l, s.loss, sizeof(float), hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;
-    *out_loss = (float)l;
+    *out_loss = l;
     *finite_loss = std::isfinite(l) ? 1 : 0;
     return hipSuccess;
 }
@@ -869,12 +887,8 @@ hipError_t train_step(TrainScratch &s, const TrainArgs &a, float *out_loss, int 
     hipError_t e = loss_and_grad(s, a, stream);
     if (e != hipSuccess)
         return e;
-    const double c1 = 1.0 - std::pow(cfg.beta1, (double)a.step);
-    const double c2 = 1.0 - std::pow(cfg.beta2, (double)a.step);
-    hipLaunchKernelGGL(adam_kernel, dim3((FABRIC_N_PARAMS + 255) / 256), dim3(256), 0, stream,
-                       a.params, (const float *)s.grad, a.adam_m, a.adam_v, FABRIC_N_PARAMS, cfg.lr,
-                       cfg.beta1, cfg.beta2, cfg.eps, c1, c2, (const double *)s.loss);
-    if ((e = hipGetLastError()) != hipSuccess)
+    if ((e = launch_adam(a.params, (const float *)s.grad, a.adam_m, a.adam_v, FABRIC_N_PARAMS, cfg,
+                         a.clock, (const float *)s.loss, stream)) != hipSuccess)
         return e;
     if (out_loss)
         return read_loss(s, out_loss, updated, stream);

@@ -11,7 +11,7 @@ namespace fab {
 struct TrainScratch {
     int64_t cap = 0;            // samples the per-sample buffers hold
     float *acts = nullptr;      // per-sample activations and gradients (see train.hip)
-    double *loss_part = nullptr;
+    float *loss_part = nullptr;
     float *partials = nullptr;  // split-K partial weight gradients
     size_t partial_floats = 0;
     float *grad = nullptr;      // [FABRIC_N_PARAMS] full gradient
@@ -22,7 +22,7 @@ struct TrainScratch {
     float *cfold = nullptr;     // [FABRIC_MAX_FABRICS][64]
     void *fwd_image = nullptr;  // packed forward decoder
     void *bwd_image = nullptr;  // packed transposed decoder
-    double *loss = nullptr;     // [1] loss of the last step
+    float *loss = nullptr;      // [1] loss of the last step
     // generated batch and targets
     int64_t batch_cap = 0;
     uint16_t *b_fid = nullptr;
@@ -32,10 +32,18 @@ struct TrainScratch {
 
 void train_scratch_free(TrainScratch &s);
 
+// Step count of an Adam state on the device: t [1] (completed updates) and
+// the bias corrections of the last counted step, corr [2] = 1 - beta1^t,
+// 1 - beta2^t.
+struct AdamClock {
+    int64_t *t;
+    double *corr;
+};
+
 struct TrainArgs {
     float *params;
     double *adam_m, *adam_v;
-    int64_t step;                     // 1-based Adam step of this update
+    AdamClock clock;                  // the moments' step count
     const DevFabric *fabrics;
     const float *enc_inputs;
     int n_fabrics;
@@ -50,10 +58,10 @@ hipError_t launch_make_batch(uint64_t seed, int64_t n, int n_fabrics, float r_lo
                              float btdf_frac,
                              const fabric_gbuffer_out &out, hipStream_t stream);
 
-// Adam (FP64 moments, FP32 masters) on n parameters at 1-based step `step`;
-// the kernel skips the update when *loss is not finite.
+// Adam (FP64 moments, FP32 masters) on n parameters; the step is counted
+// on the device in clk and skipped, count included, when *loss is not finite.
 hipError_t launch_adam(float *params, const float *grad, double *m, double *v, int n,
-                       const fabric_train_cfg &cfg, int64_t step, const double *loss,
+                       const fabric_train_cfg &cfg, AdamClock clk, const float *loss,
                        hipStream_t stream);
 
 // Decoder backward for explicit parameters and upstream gradients dy[4][n]
