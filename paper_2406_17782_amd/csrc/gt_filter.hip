@@ -17,7 +17,7 @@ namespace {
 // N - 1 in order (the same sample positions as the wave-wide estimate, the
 // five sums added in sample order).  For footprints of fewer than 64
 // samples, where a wave per pixel would leave lanes idle.
-template <bool VIS>
+template <bool VIS, bool POW2>
 __device__ inline void filter_pixel_lane(const DevFabric &f, uint64_t seed, uint64_t pixel,
                                          int n_samples, int side, float u,
                                          float v, float r, float3 wi, float3 wo,
@@ -27,7 +27,7 @@ __device__ inline void filter_pixel_lane(const DevFabric &f, uint64_t seed, uint
     uint64_t state = seed + ((uint64_t)pixel * (uint64_t)n_samples + 1ull) * kGoldenGamma;
     int kx = 0, ky = 0;
     for (int k = 0; k < n_samples; k++, state += kGoldenGamma) {
-        float2 pos = footprint_sample(splitmix64_mix(state), kx, ky, (float)side, u, v, r);
+        float2 pos = footprint_sample<POW2>(splitmix64_mix(state), kx, ky, (float)side, u, v, r);
         if (++kx == side) {
             kx = 0;
             ky += 1;
@@ -66,12 +66,20 @@ __device__ inline void filter_one_pixel(const fabric_gbuffer &g, const DevFabric
     double comp[4] = {0.0, 0.0, 0.0, 0.0};
     if (!fault) {
         const VisFabric vf = VIS ? vis.fab[fid] : VisFabric{0, 0, 0, 0.0f};
-        if (LANE)
-            filter_pixel_lane<VIS>(fabrics[fid], seed, (uint64_t)p, n_samples, side, u,
-                                   v, r, wi, wo, vis.tex, vf, comp);
+        // side is the same for every pixel of the launch: a uniform branch.
+        const bool pow2 = is_pow2(side);
+        if (LANE && pow2)
+            filter_pixel_lane<VIS, true>(fabrics[fid], seed, (uint64_t)p, n_samples, side, u,
+                                         v, r, wi, wo, vis.tex, vf, comp);
+        else if (LANE)
+            filter_pixel_lane<VIS, false>(fabrics[fid], seed, (uint64_t)p, n_samples, side, u,
+                                          v, r, wi, wo, vis.tex, vf, comp);
+        else if (pow2)
+            filter_pixel_wave<VIS, true>(fabrics[fid], seed, (uint64_t)p, n_samples, side, u,
+                                         v, r, wi, wo, lane, vis.tex, vf, comp);
         else
-            filter_pixel_wave<VIS>(fabrics[fid], seed, (uint64_t)p, n_samples, side, u,
-                                   v, r, wi, wo, lane, vis.tex, vf, comp);
+            filter_pixel_wave<VIS, false>(fabrics[fid], seed, (uint64_t)p, n_samples, side, u,
+                                          v, r, wi, wo, lane, vis.tex, vf, comp);
     }
     if (LANE || lane == 0) {
         const int64_t n = g.n;

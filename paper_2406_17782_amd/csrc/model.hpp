@@ -43,20 +43,19 @@ __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline float tan_small(float x) { return tanf(x); }
 
 // Shirley-Chiu concentric mapping of [0,1)^2 onto the unit disk; the angle
-// is pi/4 (b/a) or pi/2 - pi/4 (a/b), evaluated as sin/cos of pi times
-// (b/a)/4 or 1/2 - (a/b)/4 with correctly rounded quotients.
+// is pi/4 (b/a) or pi/2 - pi/4 (a/b): sin and cos of pi (q/4), q the
+// correctly rounded quotient (one division), swapped in the second case.
 __device__ inline float2 concentric_disk(float x, float y)
 {
     float a = 2.0f * x - 1.0f, b = 2.0f * y - 1.0f;
     if (a == 0.0f && b == 0.0f)
         return make_float2(0.0f, 0.0f);
-    bool horiz = fabsf(a) > fabsf(b);
-    float rad = horiz ? a : b;
-    float q = horiz ? b / a : a / b;
-    float phi = horiz ? 0.25f * q : 0.5f - 0.25f * q;
+    const bool horiz = fabsf(a) > fabsf(b);
+    const float rad = horiz ? a : b;
+    const float q = (horiz ? b : a) / rad;
     float sn, cs;
-    sincospif(phi, &sn, &cs);
-    return make_float2(rad * cs, rad * sn);
+    sincospif(0.25f * q, &sn, &cs);
+    return horiz ? make_float2(rad * cs, rad * sn) : make_float2(rad * sn, rad * cs);
 }
 
 // x reduced into [0, period) (period a small positive integer as float).
@@ -279,13 +278,19 @@ __device__ inline SampleVal eval_surface_point(const DevFabric &f, float us, flo
 }
 
 // Footprint sample in stratum (kx, ky) of a side x side grid, jittered by the
-// SplitMix64 draw z; position in cells.
+// SplitMix64 draw z; position in cells.  The stratum coordinates are divided
+// by side correctly rounded: POW2 (side a power of two) multiplies by the
+// exact reciprocal, which gives the same quotient without a division.
+template <bool POW2>
 __device__ inline float2 footprint_sample(uint64_t z, int kx, int ky, float side, float u,
                                           float v, float r)
 {
-    float2 d = concentric_disk(((float)kx + u24_hi(z)) / side, ((float)ky + u24_mid(z)) / side);
+    const float x = (float)kx + u24_hi(z), y = (float)ky + u24_mid(z);
+    const float inv = 1.0f / side;
+    const float2 d = POW2 ? concentric_disk(x * inv, y * inv) : concentric_disk(x / side, y / side);
     return make_float2(fmaf(r, d.x, u), fmaf(r, d.y, v));
 }
+__host__ __device__ inline bool is_pow2(int side) { return side > 0 && (side & (side - 1)) == 0; }
 
 // A pixel whose inputs fall outside the model's domain (shaded as 0).
 __device__ inline bool pixel_fault(int fid, int n_fabrics, float u, float v, float r, float3 wi,
@@ -300,7 +305,7 @@ __device__ inline bool pixel_fault(int fid, int n_fabrics, float u, float v, flo
 // Wave-wide FP64 footprint estimate for one pixel: lanes take samples
 // lane, lane + 64, ...; partial sums are reduced across the wave in a fixed
 // butterfly order.  Every lane returns the four components.
-template <bool VIS>
+template <bool VIS, bool POW2>
 __device__ inline void filter_pixel_wave(const DevFabric &f, uint64_t seed, uint64_t pixel,
                                          int n_samples, int side, float u,
                                          float v, float r, float3 wi, float3 wo, int lane,
@@ -315,7 +320,7 @@ __device__ inline void filter_pixel_wave(const DevFabric &f, uint64_t seed, uint
     const int dky = 64 / side, dkx = 64 - dky * side;
     int ky = lane / side, kx = lane - ky * side;
     for (int k = lane; k < n_samples; k += 64, state += step) {
-        float2 pos = footprint_sample(splitmix64_mix(state), kx, ky, (float)side, u, v, r);
+        float2 pos = footprint_sample<POW2>(splitmix64_mix(state), kx, ky, (float)side, u, v, r);
         kx += dkx;
         ky += dky;
         if (kx >= side) {
