@@ -485,8 +485,10 @@ def train_paper_network(args, torch, pkg, fi, mats, steps, one_blob=True, fused=
                         encoder=False):
     """A paper-size decoder trained on `mats` (one latent of 64 per fabric
     trained as a parameter, or with encoder=True the paper-size encoder
-    trained beside it; FP32 training kernels; generated batches of 2^16
-    samples with 256-sample targets; Adam with the main network's
+    trained beside it; forward and backward in the precision
+    --paper-train-prec names (BF16 operands on the matrix cores, or FP32 on
+    the vector units), FP32 weight gradients and masters; generated batches
+    of 2^16 samples with 256-sample targets; Adam with the main network's
     cosine-decayed rate).  Returns the open context and the training record."""
     fab = pkg.Fabric(0, seed=4600)
     fab.encode(mats)
@@ -502,6 +504,7 @@ def train_paper_network(args, torch, pkg, fi, mats, steps, one_blob=True, fused=
     pkg.fabric_paper_set_footprint_encoding(fab.ctx, one_blob)
     pkg.fabric_paper_set_spatial_fusion(fab.ctx, fused)
     batch = 1 << 16
+    prec = pkg.PREC[args.paper_train_prec]
     losses = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -510,22 +513,24 @@ def train_paper_network(args, torch, pkg, fi, mats, steps, one_blob=True, fused=
         want = s == 0 or s == steps - 1
         l = pkg.fabric_paper_train_step(fab.ctx, None, None,
                                         dict(batch=batch, gt_samples=args.gt_samples,
-                                             seed=3_000_000 + s, lr=lr), want_loss=want)
+                                             seed=3_000_000 + s, lr=lr, prec=prec),
+                                        want_loss=want)
         if want:
             losses.append(l)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     ms = train_s / max(1, steps) * 1e3
     tflops = PAPER_TRAIN_FLOP_PER_SAMPLE * batch / (ms * 1e-3) / 1e12 if steps else None
-    rec = {"train_steps": steps, "train_batch": batch,
+    rec = {"train_steps": steps, "train_batch": batch, "train_prec": args.paper_train_prec,
            "train_ms_per_step": ms, "train_s": train_s,
            # The whole step (batch, 256-sample targets, forward, backward,
            # weight gradients, Adam) against the training's algorithmic FLOPs;
-           # the peak is that of unpacked FP32 FMAs (the library uses no
-           # packed FP32 instructions).
+           # for FP32 training against the peak of unpacked FP32 FMAs (the
+           # library uses no packed FP32 instructions).
            "algorithmic_flop_per_sample": PAPER_TRAIN_FLOP_PER_SAMPLE,
            "step_tflops": tflops,
-           "step_frac_of_unpacked_fp32": tflops / FP32_UNPACKED_PEAK_TFLOPS if steps else None,
+           "step_frac_of_unpacked_fp32": (tflops / FP32_UNPACKED_PEAK_TFLOPS
+                                          if steps and args.paper_train_prec == "fp32" else None),
            "loss_first": losses[0] if losses else None, "loss_last": losses[-1] if losses else None,
            "footprint_encoding": "one-blob" if one_blob else "none", "spatial_fusion": fused,
            "latents": "paper-size encoder" if encoder else "one per fabric, trained as parameters"}
@@ -788,6 +793,8 @@ def main():
                     help="training steps (2^16 samples each) of the paper-size decoder's row")
     ap.add_argument("--paper-encoder-train-steps", type=int, default=24000,
                     help="training steps (2^16 samples each) of the paper-size encoder's row")
+    ap.add_argument("--paper-train-prec", choices=("bf16", "fp32"), default="bf16",
+                    help="forward/backward precision of the paper-size network's training")
     ap.add_argument("--ablation-train-steps", type=int, default=12000,
                     help="training steps of each network of the ablation row")
     ap.add_argument("--analytic-steps", type=int, default=10)

@@ -414,9 +414,14 @@ fabric_status fabric_loss_grad(fabric_ctx *ctx, const fabric_gbuffer *batch, con
  * decoder (the paper's convolutional encoder of normal and orientation maps
  * is not part of this library).  The batch, targets and cfg behave as for fabric_train_step
  * (generated batch and 256-sample targets by default, visibility as set by
- * fabric_set_visibility); cfg->prec must be FABRIC_FP32: the forward and
- * backward run in FP32 on the vector units, one sample per lane, with
- * fixed-order split-K weight gradients, and Adam keeps FP64 moments.
+ * fabric_set_visibility).  cfg->prec is FABRIC_FP32 (forward and backward
+ * in FP32 on the vector units, one sample per lane) or FABRIC_BF16 (forward
+ * and backward on the matrix cores, 32 samples per wave: BF16 operands,
+ * the forward's from the shading image of the current masters, the
+ * backward's from the transposed masters, FP32 accumulation); either way
+ * the weight gradients are fixed-order split-K sums of FP32 per-sample
+ * planes, the masters stay FP32 and Adam keeps FP64 moments, so repeated
+ * runs are bitwise equal.  Other precisions: E_INVAL.
  * fabric_paper_train_step takes one Adam step over [params | latents]
  * ([params | enc_params] in encoder mode) and re-packs the shading image
  * from the updated masters; a non-finite loss (known only when

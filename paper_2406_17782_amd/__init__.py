@@ -286,7 +286,7 @@ def fabric_train_step(ctx, batch: Optional[DeviceGBuffer], targets, cfg: dict, w
 
 def fabric_paper_loss_grad(ctx, batch: Optional[DeviceGBuffer], targets, cfg: dict, grad,
                            want_loss: bool = True, stream=None) -> Optional[float]:
-    c = _train_cfg(dict(cfg, prec=FABRIC_FP32))
+    c = _train_cfg(dict({"prec": FABRIC_FP32}, **cfg))
     loss = ctypes.c_float(0.0)
     gs = batch.c_struct() if batch is not None else None
     st = _abi.lib().fabric_paper_loss_grad(ctx, ctypes.byref(gs) if gs is not None else None,
@@ -298,7 +298,7 @@ def fabric_paper_loss_grad(ctx, batch: Optional[DeviceGBuffer], targets, cfg: di
 
 def fabric_paper_train_step(ctx, batch: Optional[DeviceGBuffer], targets, cfg: dict,
                             want_loss: bool = True, stream=None) -> Optional[float]:
-    c = _train_cfg(dict(cfg, prec=FABRIC_FP32))
+    c = _train_cfg(dict({"prec": FABRIC_FP32}, **cfg))
     loss = ctypes.c_float(0.0)
     gs = batch.c_struct() if batch is not None else None
     st = _abi.lib().fabric_paper_train_step(ctx, ctypes.byref(gs) if gs is not None else None,

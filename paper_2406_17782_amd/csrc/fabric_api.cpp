@@ -1147,7 +1147,7 @@ fabric_status check_paper_train_args(fabric_ctx *ctx, const fabric_gbuffer *batc
     fabric_status st = check_train_args(ctx, batch, targets, cfg);
     if (st != FABRIC_OK)
         return st;
-    if (cfg->prec != FABRIC_FP32)
+    if (cfg->prec != FABRIC_FP32 && cfg->prec != FABRIC_BF16)
         return FABRIC_E_INVAL;
     if (ctx->paper_n_mats == 0 || ctx->paper_serial != ctx->table_serial ||
         ctx->paper_n_mats != ctx->n_mats)
@@ -1175,6 +1175,10 @@ PaperTrainArgs paper_train_args(fabric_ctx *ctx, const fabric_gbuffer *batch, co
     a.raw = ctx->paper_raw;
     a.fused = ctx->paper_fused;
     a.enc_inputs = ctx->paper_encoder ? ctx->enc_inputs : nullptr;
+    // The BF16 shading image (first in the paper image) and c_f were packed
+    // from the current masters and latents by the last prepare or step.
+    a.bf16_image = ctx->paper_image;
+    a.cfold = ctx->paper_cfold;
     return a;
 }
 }  // namespace

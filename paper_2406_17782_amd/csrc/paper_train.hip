@@ -27,6 +27,7 @@
 #include "kernels.hpp"
 #include "model.hpp"
 #include "paper_net.hpp"
+#include "paper_tile.hpp"
 #include "paper_train.hpp"
 #include "shade.hpp"
 #include "train.hpp"
@@ -165,8 +166,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
         if (live)
             pl[(int64_t)plane * cap + s] = fault ? 0.0f : val;
     };
-    // This thread's own earlier stores (absent past the end of the batch).
-    auto own = [&](int plane) { return live ? pl[(int64_t)plane * cap + s] : 0.0f; };
     float *rowA = bufA + lane * kFbStride, *rowB = bufB + lane * kFbStrideB;
     const float ang[5] = {wi.x, wi.y, wi.z, wo.x, wo.y};
 
@@ -325,6 +324,312 @@ __global__ __launch_bounds__(256) void paper_loss_reduce_kernel(const float *__r
     }
     if (threadIdx.x == 0)
         loss[0] = red[0] * inv_n;
+}
+
+// ---- BF16 operands on MFMA (cfg.prec == FABRIC_BF16) ----------------------
+//
+// The forward runs the shading kernel's tile (paper_tile.hpp) on the BF16
+// shading image that the masters were last packed into, 32 samples per wave;
+// the backward chains the transposed weights the same way: the gradient at
+// a layer's pre-activation, held in the accumulator layout, is the B operand
+// of the next transposed layer without data movement.  Activations and
+// gradients (FP32, before rounding) go to the same per-sample planes as the
+// FP32 path, so the weight gradients are those kernels'.
+//
+// Transposed-weight fragments, in the order the backward uses them: A5^T
+// (2 M-blocks, one K step: the four outputs in slots 0..3 of lane group 0),
+// then A4^T, A3^T, A2^T, A1^T (its 64 spatial columns) and F2^T (2 M-blocks
+// x 4 K steps of chained neurons each).
+enum { kBA5 = 0, kBA4, kBA3, kBA2, kBA1, kBF2, kBLayers };
+__host__ __device__ constexpr int bwd_first(int l) { return l == 0 ? 0 : 2 + (l - 1) * 8; }
+constexpr int kBFrags = bwd_first(kBLayers);       // 42
+static_assert(kBFrags == 42, "backward fragment count");
+
+__global__ void pack_paper_bwd_kernel(const float *__restrict__ P, bf16x8 *__restrict__ frags)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= kBFrags * 64)
+        return;
+    const int fr = idx / 64, lane = idx % 64, row = lane & 31, grp = lane >> 5;
+    int layer = 0, mb = fr, ks = 0;
+    if (fr >= 2) {
+        layer = 1 + (fr - 2) / 8;
+        mb = ((fr - 2) % 8) / 4;
+        ks = (fr - 2) % 4;
+    }
+    const int m = 32 * mb + row;                    // input neuron of the forward layer
+    const int woff = layer == kBA4 ? kPOffWA4 : layer == kBA3 ? kPOffWA3 : layer == kBA2 ? kPOffWA2
+                     : layer == kBA1 ? kPOffWA1 : kPOffWF2;
+    const int row_len = layer == kBA1 ? kPXA1 : 64;
+    f32x8 w;
+    for (int j = 0; j < 8; j++) {
+        const int c = ks * 8 + j;
+        if (layer == kBA5)
+            w[j] = grp == 0 && c < 4 ? P[kPOffWA5 + c * 64 + m] : 0.0f;
+        else
+            w[j] = P[woff + chain32_neuron(grp, c) * row_len + m];
+    }
+    frags[idx] = Mfma<FABRIC_BF16>::from8(w);
+}
+
+// Forward, loss and backward of 32 samples per wave, four waves per block
+// (128 samples per block: one loss part each).
+template <bool RAW, bool FUSED>
+__global__ __launch_bounds__(256) void paper_fwd_bwd_bf16_kernel(
+    fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
+    const float *__restrict__ cfold, const bf16x8 *__restrict__ ffr, const f32x4 *__restrict__ bias5,
+    const bf16x8 *__restrict__ bfr, const float *__restrict__ targets, float *__restrict__ pl,
+    int64_t cap, float *__restrict__ loss_part)
+{
+    using PT = PaperTile<FABRIC_BF16>;
+    using M = typename PT::M;
+    using Frag = bf16x8;
+    // LDS: per fabric c_f [64], then the staged constants.
+    extern __shared__ f32x4 smem4[];
+    float *s_cf = (float *)smem4;
+    float *s_fc = s_cf + n_fabrics * 64;
+    __shared__ float red[4];
+    for (int k = threadIdx.x; k < n_fabrics * 64; k += blockDim.x)
+        s_cf[k] = cfold[k];
+    stage_fabric_consts(fabrics, n_fabrics, s_fc);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 5;
+    const int col = lane & 31;
+    const int w = threadIdx.x >> 6;
+    const int64_t n = g.n;
+    const int64_t s = ((int64_t)blockIdx.x * 4 + w) * 32 + col;   // this lane's sample
+    const bool live = s < n;
+    const uint32_t dmask = half_dir_mask(grp);
+    HalfPix cur = load_half(g, half_planes(g, grp), (int)(live ? s : n - 1));
+    // A faulted sample contributes nothing: it runs on harmless inputs and
+    // stores zeros to every plane.
+    const bool fault = !live || pair_any(half_fault(cur, n_fabrics, dmask));
+    if (fault) {
+        cur.fid = 0;
+        cur.uv = 0.0f;
+        cur.r = 1.0f;
+        cur.x0 = 0.0f;
+        cur.x1 = 0.0f;
+        cur.xz = 1.0f;
+    }
+    auto store = [&](int plane, float val) {
+        if (live)
+            pl[(int64_t)plane * cap + s] = fault ? 0.0f : val;
+    };
+    // Accumulator register r of M-block mb holds neuron 32 mb + 8 (r/4) + 4 g + r%4.
+    auto store_acc = [&](int plane, const f32x16 (&v)[2]) {
+#pragma unroll
+        for (int mb = 0; mb < 2; mb++)
+#pragma unroll
+            for (int r = 0; r < 16; r++)
+                store(plane + 32 * mb + 8 * (r >> 2) + 4 * grp + (r & 3), v[mb][r]);
+    };
+    // Leaky ReLU in place; bit mb*16 + r of the returned mask: positive.
+    auto activate = [&](f32x16 (&v)[2]) {
+        uint32_t pos = 0u;
+#pragma unroll
+        for (int mb = 0; mb < 2; mb++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                v[mb][r] = lrelu(v[mb][r]);
+                pos |= (v[mb][r] > 0.0f ? 1u : 0u) << (16 * mb + r);
+            }
+        return pos;
+    };
+    // The leaky ReLU's slope applied to a gradient at the activation.
+    auto slope = [&](f32x16 (&d)[2], uint32_t pos) {
+#pragma unroll
+        for (int mb = 0; mb < 2; mb++)
+#pragma unroll
+            for (int r = 0; r < 16; r++)
+                d[mb][r] = (pos >> (16 * mb + r)) & 1u ? d[mb][r] : kLeak * d[mb][r];
+    };
+    f32x8 one8 = {grp == 0 ? 1.0f : 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    const Frag bias_b = M::from8(one8);
+
+    // ---- forward ----
+    const int entry = fab_entry(cur.fid, n_fabrics, grp ? 1.0f : cur.xz);
+    const float *fc = s_fc + entry * kFabConsts;
+    f32x16 a[1][2];
+    {
+        float s1[FUSED ? kPSlots1 : kPSlots1 + 4];
+        const float per = grp ? fc[1] : fc[0], iper = grp ? fc[3] : fc[2];
+        paper_slots<FABRIC_BF16, RAW>(wrap_period(cur.uv, per, iper), iper, cur.r, grp, s1);
+        if (!FUSED) {
+            s1[kPSlots1] = cur.x0;
+            s1[kPSlots1 + 1] = cur.x1;
+            s1[kPSlots1 + 2] = grp ? 0.0f : cur.xz;
+        }
+#pragma unroll
+        for (int c = 0; c < kPSlots1; c++)
+            store(kPlFeat + p_blob_channel(grp, c), s1[c]);
+        if (grp == 0) {
+            store(kPlAng + 0, cur.x0);
+            store(kPlAng + 1, cur.x1);
+            store(kPlAng + 2, cur.xz);
+        } else {
+            store(kPlAng + 3, cur.x0);
+            store(kPlAng + 4, cur.x1);
+        }
+        Frag B1[1][2];
+        B1[0][0] = PT::frag_of(s1, 0, false);
+        B1[0][1] = PT::frag_of(s1, 1, false);
+#pragma unroll
+        for (int mb = 0; mb < 2; mb++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const f32x4 c4 = *(const f32x4 *)(s_cf + cur.fid * 64 + 32 * mb + 8 * q + 4 * grp);
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+                    a[0][mb][4 * q + i] = c4[i];
+            }
+        PT::template dense_lds<1, 2, 2>(ffr, p_first(kF1), B1, a, lane);
+    }
+    // The chained B operand of an activated 64-neuron output and its bias step.
+    auto chain_in = [&](Frag (&B)[1][5]) {
+        Frag B4[4];
+        PT::chain_b(a[0], B4, false);
+#pragma unroll
+        for (int ks = 0; ks < 4; ks++)
+            B[0][ks] = B4[ks];
+        B[0][4] = bias_b;
+    };
+    auto chain_layer = [&](int layer) {
+        Frag B[1][5];
+        chain_in(B);
+        a[0][0] = a[0][1] = f32x16{};
+        PT::template dense_lds<1, 2, 5>(ffr, p_first(layer), B, a, lane);
+    };
+    const uint32_t pT = activate(a[0]);
+    store_acc(kPlT, a[0]);
+    chain_layer(kF2);
+    const uint32_t pSP = activate(a[0]);
+    store_acc(kPlSP, a[0]);
+    {
+        // A1: [spatial feature, wi.xyz | wo.xy, 1]
+        Frag B[1][5];
+        float v[kL3Slots32];
+#pragma unroll
+        for (int c = 0; c < kChain32; c++)
+            v[c] = a[0][c >> 4][c & 15];
+        v[32] = cur.x0;
+        v[33] = cur.x1;
+        v[34] = grp ? 1.0f : cur.xz;
+#pragma unroll
+        for (int ks = 0; ks < 5; ks++)
+            B[0][ks] = PT::frag_of(v, ks, false);
+        a[0][0] = a[0][1] = f32x16{};
+        PT::template dense_lds<1, 2, 5>(ffr, p_first(kA1), B, a, lane);
+    }
+    const uint32_t pX = activate(a[0]);
+    store_acc(kPlX, a[0]);
+    f32x16 x[1][2] = {{a[0][0], a[0][1]}};              // the residual block's input
+    chain_layer(kA2);
+    const uint32_t pH = activate(a[0]);
+    store_acc(kPlH, a[0]);
+    {
+        // A3 from C operand x: the skip enters before the activation.
+        Frag B[1][5];
+        chain_in(B);
+        PT::template dense_lds<1, 2, 5>(ffr, p_first(kA3), B, x, lane);
+        a[0][0] = x[0][0];
+        a[0][1] = x[0][1];
+    }
+    const uint32_t pRR = activate(a[0]);
+    store_acc(kPlRR, a[0]);
+    chain_layer(kA4);
+    const uint32_t pG = activate(a[0]);
+    store_acc(kPlG, a[0]);
+    {
+        // A5: four outputs in rows 0..3 (lane group 0), bias added after.
+        Frag B[1][4];
+        PT::chain_b(a[0], B[0], false);
+        a[0][0] = f32x16{};
+        PT::template dense_lds<1, 1, 4>(ffr, p_first(kA5), B, a, lane);
+    }
+
+    // ---- loss terms of Eq. (9)-(11) and dL/dy (lane group 0 holds y) ----
+    const f32x4 b5 = bias5[lane];
+    float dy[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float loss = 0.0f;
+    if (grp == 0 && !fault) {
+        const float inv_n = 1.0f / (float)n;
+        // g(x) = ln(k x + 1): k = 100 for reflection, 1000 for transmission.
+        const float k = cur.xz < 0.0f ? 10.0f * kSpec : kSpec;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const float t = targets[c * n + s];
+            const float target = c < 2 ? t : log1pf(k * t);
+            const float lam = c < 2 ? 0.1f : 0.4f;        // lambda_C, lambda_S
+            const float d = a[0][0][c] + b5[c] - target;
+            loss = fmaf(lam * d, d, loss);
+            dy[c] = 2.0f * lam * d * inv_n;
+        }
+    }
+    if (grp == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            store(kPlDY + c, dy[c]);
+    }
+
+    // ---- backward ----
+    f32x16 d[2];
+    {
+        const f32x8 v = {dy[0], dy[1], dy[2], dy[3], 0.0f, 0.0f, 0.0f, 0.0f};
+        const Frag B = M::from8(v);                      // zero in lane group 1
+#pragma unroll
+        for (int mb = 0; mb < 2; mb++)
+            d[mb] = Mfma32<FABRIC_BF16>::mma(bfr[(bwd_first(kBA5) + mb) * 64 + lane], B, f32x16{});
+    }
+    // d <- (W^T d) of one chained layer, C operand c.
+    auto back = [&](int layer, const f32x16 (&c)[2]) {
+        Frag B[4];
+        PT::chain_b(d, B, false);
+#pragma unroll
+        for (int mb = 0; mb < 2; mb++) {
+            f32x16 acc = c[mb];
+#pragma unroll
+            for (int ks = 0; ks < 4; ks++)
+                acc = Mfma32<FABRIC_BF16>::mma(bfr[(bwd_first(layer) + 4 * mb + ks) * 64 + lane],
+                                               B[ks], acc);
+            d[mb] = acc;
+        }
+    };
+    const f32x16 zero2[2] = {f32x16{}, f32x16{}};
+    slope(d, pG);
+    store_acc(kPlDG, d);
+    back(kBA4, zero2);
+    slope(d, pRR);
+    store_acc(kPlDRR, d);
+    const f32x16 drr[2] = {d[0], d[1]};                  // the skip's gradient to A1's output
+    back(kBA3, zero2);
+    slope(d, pH);
+    store_acc(kPlDH, d);
+    back(kBA2, drr);
+    slope(d, pX);
+    store_acc(kPlDX, d);
+    back(kBA1, zero2);
+    slope(d, pSP);
+    store_acc(kPlDSP, d);
+    back(kBF2, zero2);
+    slope(d, pT);
+    store_acc(kPlDT, d);
+
+    // ---- the block's loss: lane group 0 of each wave, then the waves in order ----
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1)
+        loss += __shfl_xor(loss, off, 64);
+    if (lane == 0)
+        red[w] = loss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        KahanSum t;
+        for (int k = 0; k < 4; k++)
+            t.add(red[k]);
+        loss_part[blockIdx.x] = t.value();
+    }
 }
 
 // ---- split-K weight gradients ----------------------------------------------
@@ -649,15 +954,39 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
         if ((e = regrow(&s.partial, need)) != hipSuccess) return e;
         s.partial_floats = need;
     }
-    hipLaunchKernelGGL(transpose_kernel, dim3((kTFloats + 255) / 256), dim3(256), 0, stream,
-                       P, s.wt);
     // Faults of a generated-target batch were counted by the filter.
     (void)a.err;
-    hipLaunchKernelGGL(paper_fwd_bwd_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, g,
-                       a.fabrics, a.n_fabrics, P, lat, (const float *)s.wt, targets, s.planes,
-                       s.cap, a.raw ? 1 : 0, a.fused ? 1 : 0, s.loss_part);
+    int64_t loss_parts = blocks;
+    if (a.cfg.prec == FABRIC_BF16) {
+        if (!s.bwd_frags &&
+            (e = hipMalloc(&s.bwd_frags, (size_t)kBFrags * 64 * sizeof(bf16x8))) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(pack_paper_bwd_kernel, dim3((kBFrags * 64 + 255) / 256), dim3(256), 0,
+                           stream, P, (bf16x8 *)s.bwd_frags);
+        const auto *ffr = (const bf16x8 *)a.bf16_image;
+        const auto *b5 = (const f32x4 *)(ffr + kPFrags * 64);
+        loss_parts = (n + 127) / 128;
+        const size_t lds = (size_t)a.n_fabrics * (64 + kFabCopies * kFabConsts) * sizeof(float);
+        auto launch = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, dim3((unsigned)loss_parts), dim3(256), lds, stream, g,
+                               a.fabrics, a.n_fabrics, a.cfold, ffr, b5,
+                               (const bf16x8 *)s.bwd_frags, targets, s.planes, s.cap, s.loss_part);
+        };
+        if (a.raw)
+            a.fused ? launch(paper_fwd_bwd_bf16_kernel<true, true>)
+                    : launch(paper_fwd_bwd_bf16_kernel<true, false>);
+        else
+            a.fused ? launch(paper_fwd_bwd_bf16_kernel<false, true>)
+                    : launch(paper_fwd_bwd_bf16_kernel<false, false>);
+    } else {
+        hipLaunchKernelGGL(transpose_kernel, dim3((kTFloats + 255) / 256), dim3(256), 0, stream,
+                           P, s.wt);
+        hipLaunchKernelGGL(paper_fwd_bwd_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, g,
+                           a.fabrics, a.n_fabrics, P, lat, (const float *)s.wt, targets, s.planes,
+                           s.cap, a.raw ? 1 : 0, a.fused ? 1 : 0, s.loss_part);
+    }
     hipLaunchKernelGGL(paper_loss_reduce_kernel, dim3(1), dim3(256), 0, stream,
-                       (const float *)s.loss_part, blocks, 1.0f / (float)n, s.loss);
+                       (const float *)s.loss_part, loss_parts, 1.0f / (float)n, s.loss);
     hipLaunchKernelGGL(paper_wgrad_kernel, dim3(n_chunks, jobs.n_jobs), dim3(kPwThreads), 0, stream, jobs,
                        (const float *)s.planes, s.cap, g.fabric_id, n, s.partial);
     hipLaunchKernelGGL(paper_wgrad_reduce_kernel, dim3((64 * kPwMaxIn + 255) / 256, jobs.n_jobs),
@@ -696,6 +1025,7 @@ void paper_train_scratch_free(PaperTrainScratch &s)
     (void)hipFree(s.loss_part);
     (void)hipFree(s.loss);
     (void)hipFree(s.wt);
+    (void)hipFree(s.bwd_frags);
     (void)hipFree(s.partial);
     (void)hipFree(s.grad);
     (void)hipFree(s.lat);

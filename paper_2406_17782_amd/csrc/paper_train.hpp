@@ -20,6 +20,7 @@ struct PaperTrainScratch {
     float *loss_part = nullptr;   // per 256-sample block
     float *loss = nullptr;        // [1]
     float *wt = nullptr;          // transposed weights of F2, A1 (first 64 inputs), A2, A3, A4
+    void *bwd_frags = nullptr;    // BF16 transposed-weight fragments of the MFMA backward
     float *partial = nullptr;     // split-K partial weight gradients
     size_t partial_floats = 0;
     float *grad = nullptr;        // [params | latents], or [params | encoder] with the encoder
@@ -54,6 +55,11 @@ struct PaperTrainArgs {
     bool fused;                   // false: the angular inputs enter F1 (no spatial fusion)
     const float *enc_inputs;      // NULL: latents are parameters; else the encoder's
                                   // inputs [F][524] and the latents come from the encoder
+    // cfg.prec == FABRIC_BF16: the BF16 shading image packed from the
+    // current masters and the per-fabric c_f folded from the current latents
+    // (the forward's operands); unused for FP32.
+    const void *bf16_image;
+    const float *cfold;
 };
 
 // Parameters Adam updates: the decoder and the latents or the encoder.

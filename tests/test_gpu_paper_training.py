@@ -231,9 +231,10 @@ def test_paper_training_errors(fab, pkg, torch):
         pkg.fabric_paper_train_step(fab.ctx, None, None, dict(batch=256, gt_samples=4))
     assert e.value.status == 6                        # E_STATE: no prepare yet
     prepare(fab, pkg, torch, mats, 331)
-    c = pkg._train_cfg(dict(batch=256, gt_samples=4, prec=pkg.FABRIC_BF16))
-    st = pkg._abi.lib().fabric_paper_train_step(fab.ctx, None, None, pkg.ctypes.byref(c), None, None)
-    assert st == 1                                    # E_INVAL: FP32 only
+    for prec in (pkg.FABRIC_FP16, pkg.FABRIC_FP8_E4M3):
+        c = pkg._train_cfg(dict(batch=256, gt_samples=4, prec=prec))
+        st = pkg._abi.lib().fabric_paper_train_step(fab.ctx, None, None, pkg.ctypes.byref(c), None, None)
+        assert st == 1                                # E_INVAL: FP32 or BF16 only
     pkg.fabric_paper_train_step(fab.ctx, None, None, dict(batch=256, gt_samples=4))
     fab.encode(mats)
     with pytest.raises(pkg.FabricError) as e:
