@@ -54,21 +54,25 @@ __global__ void pack_paper_kernel(const float *__restrict__ params,
                 else if (a >= 0) w = params[kPOffWA1 + m * kPXA1 + 64 + a];
             } else if (layer == kA1) {
                 if (c < kChain32) {
-                    w = params[kPOffWA1 + m * kPXA1 + chain32_neuron(grp, c)];
+                    w = params[kPOffWA1 + m * kPXA1 + chain32_neuron(grp, c)] *
+                        paper_weight_scale(P, kA1);
                 } else if (c < kL3Slots32) {
                     const int a = l3_extra32(grp, c - kChain32);
                     if (a == 5) w = params[kPOffBA1 + m];
                     else if (a >= 0 && fused) w = params[kPOffWA1 + m * kPXA1 + 64 + a];
                 }
             } else if (layer == kA5) {
-                if (m < 4 && c < kChain32) w = params[kPOffWA5 + m * 64 + chain32_neuron(grp, c)];
+                if (m < 4 && c < kChain32)
+                    w = params[kPOffWA5 + m * 64 + chain32_neuron(grp, c)] * paper_weight_scale(P, kA5);
             } else {
                 const int offw = layer == kF2 ? kPOffWF2 : layer == kA2 ? kPOffWA2
                                  : layer == kA3 ? kPOffWA3 : kPOffWA4;
                 const int offb = layer == kF2 ? kPOffBF2 : layer == kA2 ? kPOffBA2
                                  : layer == kA3 ? kPOffBA3 : kPOffBA4;
-                if (c < kChain32) w = params[offw + m * 64 + chain32_neuron(grp, c)];
-                else if (c == kChain32 && grp == 0) w = params[offb + m];
+                if (c < kChain32)
+                    w = params[offw + m * 64 + chain32_neuron(grp, c)] * paper_weight_scale(P, layer);
+                else if (c == kChain32 && grp == 0)
+                    w = params[offb + m] * paper_bias_scale(P, layer);
             }
             M::set(f, j, w);
         }
@@ -230,7 +234,7 @@ __global__ __launch_bounds__(64 * WAVES) void decode_paper_kernel(
         f32x16 x[T][2];
 #pragma unroll
         for (int t = 0; t < T; t++) {
-            lrelu_acc(a[t]);
+            PT::act_acc(a[t]);
             x[t][0] = a[t][0];
             x[t][1] = a[t][1];
         }

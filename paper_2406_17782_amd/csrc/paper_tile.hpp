@@ -85,23 +85,56 @@ __device__ inline void paper_slots(float coord, float iper, float r, int g, floa
         s1[8 + b] = FM::gauss(8.0f * tau - (float)(4 * g + b) - 0.5f);
 }
 
-// Leaky ReLU of a 64-neuron accumulator pair, in place (FP32).
-__device__ inline void lrelu_acc(f32x16 (&a)[2])
+// The leaky ReLU with slope k splits as lrelu(x) = s (|x| + c x) with
+// s = (1 - k)/2 and c = (1 + k)/(1 - k).  The tile computes the scaled
+// activation |x| + c x = lrelu(x)/s in FP32 as one FMA with an
+// absolute-value source (a multiply and a max would take three
+// instructions: the max also quiets a signalling NaN of the MFMA result),
+// and the packed image carries the factor s in the weights that read it
+// (see paper_weight_scale).
+constexpr float kActS = 0.5f * (1.0f - kLeak);
+constexpr float kActC = (1.0f + kLeak) / (1.0f - kLeak);
+__device__ inline float lrelu_scaled(float x) { return fmaf(x, kActC, fabsf(x)); }
+
+// Factors of the packed image for layer l's chained weight columns and for
+// its bias, so that every layer sees its inputs as the FP32 network does.
+// The residual block's input x is scaled (x/s) in both images: it is A2's B
+// operand (A2's weights times s) and A3's C operand, so A3's output and
+// bias are kept at scale 1/s.  BF16 scales every activation: F2, A1's
+// spatial columns and A5 read one scaled activation (s); A3 reads the
+// scaled A2 activation (1); A4 reads an activation scaled by 1/s^2 (s^2).
+// FP16 activates on packed halves without scaling: A3 reads a plain one
+// (1/s) and A4 one scaled by 1/s through A3's output (s).  F1, the angular
+// columns and A5's bias (added after the MFMA) are unscaled.
+__host__ __device__ inline float paper_weight_scale(int P, int l)
 {
-#pragma unroll
-    for (int mb = 0; mb < 2; mb++)
-#pragma unroll
-        for (int r = 0; r < 16; r++)
-            a[mb][r] = lrelu(a[mb][r]);
+    if (P == FABRIC_BF16)
+        return l == kF1 || l == kA3 ? 1.0f : l == kA4 ? kActS * kActS : kActS;
+    return l == kA2 || l == kA4 ? kActS : l == kA3 ? 1.0f / kActS : 1.0f;
+}
+__host__ __device__ inline float paper_bias_scale(int, int l)
+{
+    return l == kA3 ? 1.0f / kActS : 1.0f;
 }
 
 // Operand packing and the MFMA sweep per operand precision.  act(): the
 // leaky ReLU fused into the packing of eight outputs - in FP32 before the
-// BF16 rounding (CDNA has no packed BF16 arithmetic), on packed halves after
-// the FP16 rounding (packed multiply and max, two values per instruction).
+// BF16 rounding as the scaled activation above (CDNA has no packed BF16
+// arithmetic), on packed halves after the FP16 rounding (packed multiply and
+// max, two values per instruction).
 template <int P> struct PaperTile {
     using M = Mfma<P>;
     using Frag = typename M::Frag;
+
+    // The residual block's input, in place: the scaled activation, in FP32.
+    static __device__ inline void act_acc(f32x16 (&a)[2])
+    {
+#pragma unroll
+        for (int mb = 0; mb < 2; mb++)
+#pragma unroll
+            for (int r = 0; r < 16; r++)
+                a[mb][r] = lrelu_scaled(a[mb][r]);
+    }
 
     template <int NSL> static __device__ inline Frag frag_of(const float (&v)[NSL], int ks, bool act)
     {
@@ -120,7 +153,7 @@ template <int P> struct PaperTile {
         if (act) {
 #pragma unroll
             for (int j = 0; j < 8; j++)
-                x[j] = lrelu(x[j]);
+                x[j] = P == FABRIC_BF16 ? lrelu_scaled(x[j]) : lrelu(x[j]);
         }
         return M::from8(x);
     }

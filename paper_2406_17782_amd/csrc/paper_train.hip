@@ -329,7 +329,8 @@ __global__ __launch_bounds__(256) void paper_loss_reduce_kernel(const float *__r
 // ---- BF16 operands on MFMA (cfg.prec == FABRIC_BF16) ----------------------
 //
 // The forward runs the shading kernel's tile (paper_tile.hpp) on the BF16
-// shading image that the masters were last packed into, 32 samples per wave;
+// shading image that the masters were last packed into, 32 samples per wave,
+// with its scaled activations (the FP32 leaky ReLU goes to the planes);
 // the backward chains the transposed weights the same way: the gradient at
 // a layer's pre-activation, held in the accumulator layout, is the B operand
 // of the next transposed layer without data movement.  Activations and
@@ -426,15 +427,19 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_bf16_kernel(
             for (int r = 0; r < 16; r++)
                 store(plane + 32 * mb + 8 * (r >> 2) + 4 * grp + (r & 3), v[mb][r]);
     };
-    // Leaky ReLU in place; bit mb*16 + r of the returned mask: positive.
-    auto activate = [&](f32x16 (&v)[2]) {
+    // A layer's output v, held at scale 1/pre_s of the FP32 network's
+    // pre-activation: its leaky ReLU (FP32) to `plane`, the scaled
+    // activation that the image expects in v (as the shading tile computes
+    // it); bit mb*16 + r of the returned mask: positive.
+    auto activate = [&](int plane, f32x16 (&v)[2], float pre_s) {
         uint32_t pos = 0u;
 #pragma unroll
         for (int mb = 0; mb < 2; mb++)
 #pragma unroll
             for (int r = 0; r < 16; r++) {
-                v[mb][r] = lrelu(v[mb][r]);
+                store(plane + 32 * mb + 8 * (r >> 2) + 4 * grp + (r & 3), lrelu(pre_s * v[mb][r]));
                 pos |= (v[mb][r] > 0.0f ? 1u : 0u) << (16 * mb + r);
+                v[mb][r] = lrelu_scaled(v[mb][r]);
             }
         return pos;
     };
@@ -502,11 +507,9 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_bf16_kernel(
         a[0][0] = a[0][1] = f32x16{};
         PT::template dense_lds<1, 2, 5>(ffr, p_first(layer), B, a, lane);
     };
-    const uint32_t pT = activate(a[0]);
-    store_acc(kPlT, a[0]);
+    const uint32_t pT = activate(kPlT, a[0], 1.0f);
     chain_layer(kF2);
-    const uint32_t pSP = activate(a[0]);
-    store_acc(kPlSP, a[0]);
+    const uint32_t pSP = activate(kPlSP, a[0], 1.0f);
     {
         // A1: [spatial feature, wi.xyz | wo.xy, 1]
         Frag B[1][5];
@@ -523,12 +526,10 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_bf16_kernel(
         a[0][0] = a[0][1] = f32x16{};
         PT::template dense_lds<1, 2, 5>(ffr, p_first(kA1), B, a, lane);
     }
-    const uint32_t pX = activate(a[0]);
-    store_acc(kPlX, a[0]);
+    const uint32_t pX = activate(kPlX, a[0], 1.0f);
     f32x16 x[1][2] = {{a[0][0], a[0][1]}};              // the residual block's input
     chain_layer(kA2);
-    const uint32_t pH = activate(a[0]);
-    store_acc(kPlH, a[0]);
+    const uint32_t pH = activate(kPlH, a[0], 1.0f);
     {
         // A3 from C operand x: the skip enters before the activation.
         Frag B[1][5];
@@ -537,11 +538,9 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_bf16_kernel(
         a[0][0] = x[0][0];
         a[0][1] = x[0][1];
     }
-    const uint32_t pRR = activate(a[0]);
-    store_acc(kPlRR, a[0]);
+    const uint32_t pRR = activate(kPlRR, a[0], kActS);  // A3's output at scale 1/s
     chain_layer(kA4);
-    const uint32_t pG = activate(a[0]);
-    store_acc(kPlG, a[0]);
+    const uint32_t pG = activate(kPlG, a[0], 1.0f);
     {
         // A5: four outputs in rows 0..3 (lane group 0), bias added after.
         Frag B[1][4];
