@@ -330,7 +330,8 @@ __global__ __launch_bounds__(256) void paper_loss_reduce_kernel(const float *__r
 //
 // The forward runs the shading kernel's tile (paper_tile.hpp) on the BF16
 // shading image that the masters were last packed into, 32 samples per wave,
-// with its scaled activations (the FP32 leaky ReLU goes to the planes);
+// with its scaled activations (s times them, the FP32 network's
+// activations to FP32 rounding, go to the planes);
 // the backward chains the transposed weights the same way: the gradient at
 // a layer's pre-activation, held in the accumulator layout, is the B operand
 // of the next transposed layer without data movement.  Activations and
@@ -376,7 +377,7 @@ __global__ void pack_paper_bwd_kernel(const float *__restrict__ P, bf16x8 *__res
 // Forward, loss and backward of 32 samples per wave, four waves per block
 // (128 samples per block: one loss part each).
 template <bool RAW, bool FUSED>
-__global__ __launch_bounds__(256) void paper_fwd_bwd_bf16_kernel(
+__global__ __launch_bounds__(256, 2) void paper_fwd_bwd_bf16_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ cfold, const bf16x8 *__restrict__ ffr, const f32x4 *__restrict__ bias5,
     const bf16x8 *__restrict__ bfr, const float *__restrict__ targets, float *__restrict__ pl,
@@ -427,20 +428,24 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_bf16_kernel(
             for (int r = 0; r < 16; r++)
                 store(plane + 32 * mb + 8 * (r >> 2) + 4 * grp + (r & 3), v[mb][r]);
     };
-    // A layer's output v, held at scale 1/pre_s of the FP32 network's
-    // pre-activation: its leaky ReLU (FP32) to `plane`, the scaled
-    // activation that the image expects in v (as the shading tile computes
-    // it); bit mb*16 + r of the returned mask: positive.
-    auto activate = [&](int plane, f32x16 (&v)[2], float pre_s) {
+    // A layer's output v in place: the scaled activation that the image
+    // expects (as the shading tile computes it), and plane_s times it - the
+    // FP32 network's activation - to `plane`; bit mb*16 + r of the returned
+    // mask: positive.
+    auto activate = [&](int plane, f32x16 (&v)[2], float plane_s) {
         uint32_t pos = 0u;
 #pragma unroll
         for (int mb = 0; mb < 2; mb++)
 #pragma unroll
             for (int r = 0; r < 16; r++) {
-                store(plane + 32 * mb + 8 * (r >> 2) + 4 * grp + (r & 3), lrelu(pre_s * v[mb][r]));
                 pos |= (v[mb][r] > 0.0f ? 1u : 0u) << (16 * mb + r);
                 v[mb][r] = lrelu_scaled(v[mb][r]);
             }
+#pragma unroll
+        for (int mb = 0; mb < 2; mb++)
+#pragma unroll
+            for (int r = 0; r < 16; r++)
+                store(plane + 32 * mb + 8 * (r >> 2) + 4 * grp + (r & 3), plane_s * v[mb][r]);
         return pos;
     };
     // The leaky ReLU's slope applied to a gradient at the activation.
@@ -507,9 +512,9 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_bf16_kernel(
         a[0][0] = a[0][1] = f32x16{};
         PT::template dense_lds<1, 2, 5>(ffr, p_first(layer), B, a, lane);
     };
-    const uint32_t pT = activate(kPlT, a[0], 1.0f);
+    const uint32_t pT = activate(kPlT, a[0], kActS);
     chain_layer(kF2);
-    const uint32_t pSP = activate(kPlSP, a[0], 1.0f);
+    const uint32_t pSP = activate(kPlSP, a[0], kActS);
     {
         // A1: [spatial feature, wi.xyz | wo.xy, 1]
         Frag B[1][5];
@@ -526,10 +531,10 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_bf16_kernel(
         a[0][0] = a[0][1] = f32x16{};
         PT::template dense_lds<1, 2, 5>(ffr, p_first(kA1), B, a, lane);
     }
-    const uint32_t pX = activate(kPlX, a[0], 1.0f);
+    const uint32_t pX = activate(kPlX, a[0], kActS);
     f32x16 x[1][2] = {{a[0][0], a[0][1]}};              // the residual block's input
     chain_layer(kA2);
-    const uint32_t pH = activate(kPlH, a[0], 1.0f);
+    const uint32_t pH = activate(kPlH, a[0], kActS);
     {
         // A3 from C operand x: the skip enters before the activation.
         Frag B[1][5];
@@ -538,9 +543,9 @@ __global__ __launch_bounds__(256) void paper_fwd_bwd_bf16_kernel(
         a[0][0] = x[0][0];
         a[0][1] = x[0][1];
     }
-    const uint32_t pRR = activate(kPlRR, a[0], kActS);  // A3's output at scale 1/s
+    const uint32_t pRR = activate(kPlRR, a[0], kActS * kActS);  // A3's output at scale 1/s
     chain_layer(kA4);
-    const uint32_t pG = activate(kPlG, a[0], 1.0f);
+    const uint32_t pG = activate(kPlG, a[0], kActS);
     {
         // A5: four outputs in rows 0..3 (lane group 0), bias added after.
         Frag B[1][4];
@@ -648,104 +653,165 @@ struct PWJobs {
     int n_jobs;
 };
 
-constexpr int kPwSub = 32;          // samples per LDS sub-tile
-constexpr int kPwChunk = 256;       // samples per block
+constexpr int kPwChunk = 512;       // samples per block
 constexpr int kPwMaxIn = 70;        // columns (inputs + bias) of any job
-// LDS rows (one per sample of the sub-tile) hold 4-wide groups of rows and
-// of columns, padded by 4 floats against bank conflicts of the fills.
-constexpr int kPwDStride = 64 + 4;
-constexpr int kPwIStride = 72 + 4;
+constexpr int kPwColBlocks = 5;     // 16-column blocks of the widest job
+static_assert(kPwMaxIn <= 16 * kPwColBlocks, "column blocks");
+constexpr int kPwThreads = 256;     // one 16-row block of outputs per wave
 
 __host__ __device__ inline int pw_cols(const PWJob &jb)
 {
     return jb.nA + jb.nB + (jb.b_off >= 0 ? 1 : 0);
 }
 
-// 512 threads; each accumulates one 4 x 4 block of (row, column) entries
-// (at most 16 x 18 blocks, so every block of a job is in flight at once):
-// per sample, two 16-byte LDS reads feed 16 FMAs.
-constexpr int kPwThreads = 512;
-__global__ __launch_bounds__(kPwThreads) void paper_wgrad_kernel(PWJobs jobs, const float *__restrict__ pl,
-                                                          int64_t cap, const uint16_t *__restrict__ fid,
-                                                          int64_t n, float *__restrict__ partial)
+// Weight gradients on FP32 MFMA 16x16x4, samples being the K dimension: a
+// block takes one job and one chunk of kPwChunk samples, wave w the output
+// rows 16 w .. 16 w + 15 for every 16-column block of the job.  Lane
+// (q = l/16, c = l%16) reads samples s + 8 q .. s + 8 q + 7 of its row's
+// delta plane and of its columns' input planes as two float4s (the planes
+// are sample-contiguous, their stride a multiple of 64), and MFMA t of a
+// group of 32 samples takes sample s + 8 q + t in k slot q.  A job's column
+// blocks but the last hold input planes only; the last mixes planes, the
+// bias column (1) and padding (0).  Samples past the batch (stale plane
+// values) enter as zeros in both operands.
+struct PwLane {
+    const float *a;                 // the lane's delta row (nullptr: a padding row)
+    const float *b[kPwColBlocks];   // input planes of the lane's columns
+    bool b_plane;                   // the last block's column is a plane
+    float b_const;                  // else its value (1 for the bias, 0 for padding)
+    const uint16_t *fid;            // one-hot job: the fabric ids
+};
+
+template <int CB, bool ONEHOT, bool TAIL>
+__device__ inline void pw_group(const PwLane &L, int c, int64_t base, int64_t s1, f32x4 (&acc)[CB])
 {
-    __shared__ __align__(16) float dt[kPwSub * kPwDStride];
-    __shared__ __align__(16) float it[kPwSub * kPwIStride];
+    auto in = [&](int t) { return !TAIL || base + t < s1; };
+    float a[8];
+    if (L.a) {
+        const f32x4 lo = *(const f32x4 *)(L.a + base), hi = *(const f32x4 *)(L.a + base + 4);
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            a[t] = in(t) ? lo[t] : 0.0f;
+            a[4 + t] = in(4 + t) ? hi[t] : 0.0f;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 8; t++)
+            a[t] = 0.0f;
+    }
+    float b[CB][8];
+    if (ONEHOT) {
+        int id[8];
+#pragma unroll
+        for (int t = 0; t < 8; t++)
+            id[t] = in(t) ? (int)L.fid[base + t] : -1;
+#pragma unroll
+        for (int cb = 0; cb < CB; cb++)
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+                b[cb][t] = id[t] == 16 * cb + c ? 1.0f : 0.0f;
+    } else {
+#pragma unroll
+        for (int cb = 0; cb < CB; cb++) {
+            const f32x4 lo = *(const f32x4 *)(L.b[cb] + base);
+            const f32x4 hi = *(const f32x4 *)(L.b[cb] + base + 4);
+            const bool plane = cb < CB - 1 || L.b_plane;
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                b[cb][t] = plane ? (in(t) ? lo[t] : 0.0f) : L.b_const;
+                b[cb][4 + t] = plane ? (in(4 + t) ? hi[t] : 0.0f) : L.b_const;
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 8; t++)
+#pragma unroll
+        for (int cb = 0; cb < CB; cb++)
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b[cb][t], acc[cb], 0, 0, 0);
+}
+
+template <int CB, bool ONEHOT>
+__device__ inline void pw_chunk(const PwLane &L, const PWJob &jb, int cols, int w, int q, int c,
+                                int64_t s0, int64_t s1, float *__restrict__ dst)
+{
+    f32x4 acc[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; cb++)
+        acc[cb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    int64_t sb = s0;
+    for (; sb + 32 <= s1; sb += 32)
+        pw_group<CB, ONEHOT, false>(L, c, sb + 8 * q, s1, acc);
+    if (sb < s1)
+        pw_group<CB, ONEHOT, true>(L, c, sb + 8 * q, s1, acc);
+    // Register i of a tile holds row 4 q + i, column c.
+#pragma unroll
+    for (int cb = 0; cb < CB; cb++) {
+        const int j = 16 * cb + c;
+        if (j >= cols)
+            continue;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int r = 16 * w + 4 * q + i;
+            if (r < jb.n_out)
+                dst[r * cols + j] = acc[cb][i];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kPwThreads) void paper_wgrad_kernel(PWJobs jobs,
+                                                                 const float *__restrict__ pl,
+                                                                 int64_t cap,
+                                                                 const uint16_t *__restrict__ fid,
+                                                                 int64_t n,
+                                                                 float *__restrict__ partial)
+{
     const PWJob jb = jobs.j[blockIdx.y];
     const int cols = pw_cols(jb);
-    const int rg = (jb.n_out + 3) / 4, cg = (cols + 3) / 4;
-    const int tiles = rg * cg;                  // <= 16 x 18
-    static_assert(16 * 18 <= kPwThreads, "one 4 x 4 block per thread");
-    float acc[1][4][4];
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    const int w = threadIdx.x >> 6;
+    if (16 * w >= jb.n_out)
+        return;
+    const int cb_n = (cols + 15) >> 4;
+    const int row = 16 * w + c;
+    PwLane L;
+    L.a = row < jb.n_out ? pl + (int64_t)(jb.delta + row) * cap : nullptr;
+    L.fid = fid;
+    L.b_plane = false;
+    L.b_const = 0.0f;
 #pragma unroll
-    for (int m = 0; m < 1; m++)
-#pragma unroll
-        for (int x = 0; x < 4; x++)
-#pragma unroll
-            for (int y = 0; y < 4; y++)
-                acc[m][x][y] = 0.0f;
+    for (int cb = 0; cb < kPwColBlocks; cb++) {
+        const int j = 16 * cb + c;
+        // A column that is no plane reads the first input plane (in bounds)
+        // and takes its constant instead.
+        int plane = jb.inA;
+        if (j < jb.nA)
+            plane = jb.inA + j;
+        else if (j < jb.nA + jb.nB)
+            plane = jb.inB + j - jb.nA;
+        L.b[cb] = pl + (int64_t)plane * cap;
+        if (cb == cb_n - 1) {
+            L.b_plane = j < jb.nA + jb.nB;
+            L.b_const = j < cols ? 1.0f : 0.0f;     // the bias column, or padding
+        }
+    }
     const int64_t s0 = (int64_t)blockIdx.x * kPwChunk;
     const int64_t s1 = s0 + kPwChunk < n ? s0 + kPwChunk : n;
-    for (int64_t sb = s0; sb < s1; sb += kPwSub) {
-        // Fills: consecutive threads take consecutive samples of one plane.
-        for (int k = threadIdx.x; k < 4 * rg * kPwSub; k += blockDim.x) {
-            const int i = k / kPwSub, q = k % kPwSub;
-            const int64_t s = sb + q;
-            dt[q * kPwDStride + i] = (s < s1 && i < jb.n_out) ? pl[(int64_t)(jb.delta + i) * cap + s] : 0.0f;
+    float *dst = partial + jobs.poff[blockIdx.y] + (int64_t)blockIdx.x * jb.n_out * cols;
+    if (jb.onehot) {
+        switch (cb_n) {
+        case 1: pw_chunk<1, true>(L, jb, cols, w, q, c, s0, s1, dst); break;
+        case 2: pw_chunk<2, true>(L, jb, cols, w, q, c, s0, s1, dst); break;
+        case 3: pw_chunk<3, true>(L, jb, cols, w, q, c, s0, s1, dst); break;
+        default: pw_chunk<4, true>(L, jb, cols, w, q, c, s0, s1, dst); break;
         }
-        for (int k = threadIdx.x; k < 4 * cg * kPwSub; k += blockDim.x) {
-            const int j = k / kPwSub, q = k % kPwSub;
-            const int64_t s = sb + q;
-            float val = 0.0f;
-            if (s < s1 && j < cols) {
-                if (jb.onehot)
-                    val = (int)fid[s] == j ? 1.0f : 0.0f;
-                else if (j < jb.nA)
-                    val = pl[(int64_t)(jb.inA + j) * cap + s];
-                else if (j < jb.nA + jb.nB)
-                    val = pl[(int64_t)(jb.inB + j - jb.nA) * cap + s];
-                else
-                    val = 1.0f;
-            }
-            it[q * kPwIStride + j] = val;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < 1; m++) {
-            const int t = threadIdx.x;
-            if (t < tiles) {
-                const int r = t / cg, c = t % cg;
-#pragma unroll 4
-                for (int q = 0; q < kPwSub; q++) {
-                    const float4 a = *(const float4 *)&dt[q * kPwDStride + 4 * r];
-                    const float4 b = *(const float4 *)&it[q * kPwIStride + 4 * c];
-                    const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-                    for (int x = 0; x < 4; x++)
-#pragma unroll
-                        for (int y = 0; y < 4; y++)
-                            acc[m][x][y] = fmaf(av[x], bv[y], acc[m][x][y]);
-                }
-            }
-        }
-        __syncthreads();
+        return;
     }
-    const int E = jb.n_out * cols;
-    float *dst = partial + jobs.poff[blockIdx.y] + (int64_t)blockIdx.x * E;
-#pragma unroll
-    for (int m = 0; m < 1; m++) {
-        const int t = threadIdx.x;
-        if (t < tiles) {
-            const int r = t / cg, c = t % cg;
-#pragma unroll
-            for (int x = 0; x < 4; x++)
-#pragma unroll
-                for (int y = 0; y < 4; y++) {
-                    const int i = 4 * r + x, j = 4 * c + y;
-                    if (i < jb.n_out && j < cols)
-                        dst[i * cols + j] = acc[m][x][y];
-                }
-        }
+    switch (cb_n) {
+    case 1: pw_chunk<1, false>(L, jb, cols, w, q, c, s0, s1, dst); break;
+    case 2: pw_chunk<2, false>(L, jb, cols, w, q, c, s0, s1, dst); break;
+    case 3: pw_chunk<3, false>(L, jb, cols, w, q, c, s0, s1, dst); break;
+    case 4: pw_chunk<4, false>(L, jb, cols, w, q, c, s0, s1, dst); break;
+    default: pw_chunk<5, false>(L, jb, cols, w, q, c, s0, s1, dst); break;
     }
 }
 
@@ -939,10 +1005,13 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
         targets = s.targets;
     }
     const int64_t blocks = (n + kFbSamples - 1) / kFbSamples;
-    if (s.cap < n) {
-        if ((e = regrow(&s.planes, (size_t)n * kPlanes)) != hipSuccess) return e;
-        if ((e = regrow(&s.loss_part, (size_t)blocks)) != hipSuccess) return e;
-        s.cap = n;
+    // The planes' stride: a multiple of 64 samples, so that the weight
+    // gradients read whole 32-sample groups as aligned float4s in bounds.
+    const int64_t cap = (n + 63) / 64 * 64;
+    if (s.cap < cap) {
+        if ((e = regrow(&s.planes, (size_t)cap * kPlanes)) != hipSuccess) return e;
+        if ((e = regrow(&s.loss_part, (size_t)(cap / kFbSamples))) != hipSuccess) return e;
+        s.cap = cap;
     }
     const int n_chunks = (int)((n + kPwChunk - 1) / kPwChunk);
     const PWJobs jobs = make_jobs(a.n_fabrics, n_chunks, a.fused);

