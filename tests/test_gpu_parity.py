@@ -302,6 +302,43 @@ def test_loss_grad_matches_oracle(fab, pkg, orc, torch):
             off += size
 
 
+def test_loss_grad_bf16_matches_oracle(fab, pkg, orc, torch):
+    """The training step's own precision (Sec. 5.2 config: BF16 operands on
+    the matrix cores, FP32 accumulation): loss and the full encoder +
+    decoder gradient against the oracle's FP64 backward on a ragged batch.
+    Bars from BF16's unit roundoff 2^-8: a rounded product errs by at most
+    2u with zero mean, so a layer's output picks up a relative norm error
+    of about u sqrt(2/3) ~ 3.2e-3; four forward and three transposed layers
+    stacked in quadrature give ~8.5e-3 on a delta, and a weight gradient
+    carries both of its factors' errors: 4e-2 per tensor, 2e-2 on the whole
+    gradient, 1e-2 on the loss (the forward's output error, doubled by the
+    square).  The encoder's tensors inherit the latents' gradient error."""
+    mats = fi.materials_for(8, 75)
+    g = fi.make_gbuffer(67, 61, 8, seed=76)          # 4,087 samples: a ragged last tile
+    g.fabric_id[:] = np.random.default_rng(77).integers(0, 8, g.n).astype(np.uint16)
+    g.wo_z[11] = -0.2                                # a faulted sample contributes nothing
+    tg = fi.random_targets(g.n, 78)
+    params = params_for(79)
+    fab.set_params(params)
+    fab.encode(mats)
+    grad = torch.empty(fi.N_PARAMS, device="cuda")
+    loss = pkg.fabric_loss_grad(fab.ctx, dev(pkg, g), torch.from_numpy(tg).cuda(),
+                                {"prec": pkg.FABRIC_BF16}, grad)
+    oloss, ograd, _ = orc.loss_grad(params, mats, g, tg)
+    gg = grad.cpu().numpy()
+    errs, off = [], 0
+    for o, i in fi.DECODER_SHAPES + fi.ENCODER_SHAPES:
+        for size in (o * i, o):
+            errs.append(rel_norm_err(gg[off:off + size], ograd[off:off + size]))
+            off += size
+    whole = rel_norm_err(gg, ograd)
+    print("bf16 loss", loss, oloss, "whole", "%.2e" % whole, "per tensor",
+          ["%.2e" % e for e in errs])
+    assert loss == pytest.approx(oloss, rel=1e-2)
+    assert whole < 2e-2
+    assert max(errs) < 4e-2
+
+
 def test_make_batch_matches_oracle_recipe(fab, pkg, orc, torch):
     fab.encode(fi.materials_for(8, 80))
     n = 100_003
