@@ -6,11 +6,14 @@
 //                      dL/dy, then the backward through the activations as
 //                      MFMA tiles with transposed weight fragments, chained in
 //                      registers exactly like the forward.  Activations and
-//                      activation gradients go to per-sample buffers.
+//                      activation gradients go to per-sample FP32 rows, or in
+//                      BF16 training to BF16 planes blocked by 64 samples.
 //   wgrad_kernel       weight gradients dW = sum_n dh_n x_n^T of every layer in
 //                      one launch: FP32 MFMA tiles with samples as K, operands
 //                      read straight from the per-sample rows, fixed-order
 //                      reductions of the partials (deterministic).
+//   wgrad_bf16_kernel  the same from the BF16 planes on BF16 MFMA 16x16x32
+//                      (eight consecutive samples per lane and operand).
 //   encoder kernels    per-fabric backward through the encoder and its weight
 //                      gradients summed over fabrics in order.
 //   adam_kernel        Adam with FP64 moments on FP32 masters; skipped on the
@@ -45,6 +48,25 @@ __host__ __device__ inline ActPtrs act_ptrs(float *base, int64_t cap)
     a.DH2 = a.DH1 + cap * kDH;
     a.DH3 = a.DH2 + cap * kDH;
     return a;
+}
+
+// BF16 training keeps the same quantities as planes of 16-bit values in
+// the same buffer: every MFMA operand as the forward used it (features,
+// activations, the angular inputs, dy) and the activation gradients rounded
+// to BF16.  Blocked by 64 samples: the 433 planes of samples 64 b .. 64 b + 63
+// form one contiguous region, each plane's 64 samples in order, so a lane of
+// the weight gradients reads eight consecutive samples of a plane with one
+// load and a block's accesses stay within 55 KB (DRAM pages are reused when
+// the planes do not fit in the caches).
+constexpr int kQS = 0, kQH1 = kQS + kS, kQX3 = kQH1 + kH1, kQH3 = kQX3 + 69, kQDY = kQH3 + kH3;
+constexpr int kQDH1 = kQDY + kDY, kQDH2 = kQDH1 + kDH, kQDH3 = kQDH2 + kDH;
+constexpr int kQPlanes = kQDH3 + kDH;                                  // 433
+constexpr int kQBlock = 64;                                            // samples per region (a shift of 6)
+static_assert(kQPlanes * 2 <= kActFloats * 4, "the BF16 planes fit the activation buffer");
+__host__ __device__ inline int64_t q_elem(int plane, int64_t s)
+{
+    // s >= 0: the shift and the mask are the quotient and the remainder.
+    return (s >> 6) * (kQPlanes * kQBlock) + plane * kQBlock + (s & (kQBlock - 1));
 }
 
 // Per-fabric encoder scratch (floats).
@@ -159,6 +181,9 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(
     using Frag = typename T::Frag;
     using B = BwdShape<T::KPL>;
     constexpr int KPL = T::KPL;
+
+    // BF16 training writes the blocked BF16 planes (see kQPlanes).
+    constexpr bool kQ = P == FABRIC_BF16 && !GIVEN_DY;
 
     const int lane = threadIdx.x & 63, grp = lane >> 4, col = lane & 15;
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -288,9 +313,41 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(
 
     if (!valid)
         return;
+    const float keep = live ? 1.0f : 0.0f;
+    if (kQ) {
+        // ---- per-sample BF16 planes for the weight gradients ----
+        __bf16 *qp = (__bf16 *)acts;
+        auto put = [&](int plane, float x) { qp[q_elem(plane, p)] = (__bf16)x; };
+#pragma unroll
+        for (int c = 0; c < kL1Slots; c++)
+            put(kQS + l1_feature(grp, c), s1[c]);
+#pragma unroll
+        for (int mb = 0; mb < 4; mb++) {
+            const int o = 16 * mb + 4 * grp;
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                put(kQH1 + o + i, fmaxf(a1[mb][i], 0.0f));
+                put(kQX3 + o + i, fmaxf(a2[mb][i], 0.0f));
+                put(kQH3 + o + i, fmaxf(a3[mb][i], 0.0f));
+                put(kQDH1 + o + i, d1[mb][i] * keep);
+                put(kQDH2 + o + i, d2[mb][i] * keep);
+                put(kQDH3 + o + i, d3[mb][i] * keep);
+            }
+        }
+        if (grp == 0) {
+            put(kQX3 + 64, wi.x);
+            put(kQX3 + 65, wi.y);
+            put(kQX3 + 66, wi.z);
+            put(kQX3 + 67, wo.x);
+            put(kQX3 + 68, wo.y);
+#pragma unroll
+            for (int c = 0; c < 4; c++)
+                put(kQDY + c, dy[c]);
+        }
+        return;
+    }
     // ---- per-sample rows for the weight gradients ----
     ActPtrs ap = act_ptrs(acts, cap);
-    const float keep = live ? 1.0f : 0.0f;
 #pragma unroll
     for (int c = 0; c < kL1Slots; c++)
         ap.S[p * kS + l1_feature(grp, c)] = s1[c];
@@ -425,6 +482,166 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgJobs jobs, int64_t n, int6
     }
 }
 
+// BF16 training's weight gradients, from the blocked BF16 planes: the same jobs and
+// partial layout as wgrad_kernel, on BF16 MFMA 16x16x32 with samples as K.
+// Wave w of a block takes the job's output rows 16 w .. 16 w + 15 for every
+// 16-column block over the block's samples; lane (q = l/16, c = l%16) holds
+// samples s + 8 q .. s + 8 q + 7 of its row's delta plane and of its
+// column's input plane (one 16-byte load each), which fill k slots 8 q .. 8 q
+// + 7 of both operands alike.  A job's column blocks but the last hold input
+// planes only; the last mixes planes, the bias column (1) and padding (0);
+// the one-hot job compares fabric ids.  Samples past the batch enter as
+// zeros in both operands.  The waves' rows are disjoint: no block sum.
+struct WgJob16 {
+    int A;                    // first delta plane, rows 0..MA-1
+    int B;                    // first input plane, columns 0..NB-1 (-1 with ids)
+    const uint16_t *ids;
+    int MA, NB, bias, f0, NC;
+};
+struct WgJobs16 {
+    WgJob16 j[kWgMaxJobs];
+};
+constexpr int kWg16ColBlocks = kWgMaxC / 16;
+
+struct Wg16Lane {
+    const __bf16 *qp;                 // the planes
+    int a;                            // the lane's delta plane (-1: a padding row)
+    int b[kWg16ColBlocks];            // the lane's column planes
+    bool b_plane;                     // the last block's column is a plane
+    __bf16 b_const;                   // else its value
+    const uint16_t *ids;
+    int f0, NC;
+};
+
+template <int CB, bool ONEHOT, bool TAIL>
+__device__ inline void wg16_group(const Wg16Lane &L, int c, int64_t base, int64_t s1,
+                                  f32x4 (&acc)[CB])
+{
+    const __bf16 zero = (__bf16)0.0f, one = (__bf16)1.0f;
+    auto in = [&](int t) { return !TAIL || base + t < s1; };
+    // base is a multiple of 8: the eight samples lie in one region.
+    const __bf16 *reg = L.qp + q_elem(0, base);
+    bf16x8 a;
+    if (L.a >= 0) {
+        a = *(const bf16x8 *)(reg + L.a * kQBlock);
+        if (TAIL) {
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+                a[t] = in(t) ? a[t] : zero;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 8; t++)
+            a[t] = zero;
+    }
+    bf16x8 b[CB];
+    if (ONEHOT) {
+        int id[8];
+#pragma unroll
+        for (int t = 0; t < 8; t++)
+            id[t] = in(t) ? (int)L.ids[base + t] - L.f0 : -1;
+#pragma unroll
+        for (int cb = 0; cb < CB; cb++) {
+            const int j = 16 * cb + c;
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+                b[cb][t] = j < L.NC && id[t] == j ? one : zero;
+        }
+    } else {
+#pragma unroll
+        for (int cb = 0; cb < CB; cb++) {
+            const bf16x8 v = *(const bf16x8 *)(reg + L.b[cb] * kQBlock);
+            const bool plane = cb < CB - 1 || L.b_plane;
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+                b[cb][t] = plane ? (in(t) ? v[t] : zero) : L.b_const;
+        }
+    }
+#pragma unroll
+    for (int cb = 0; cb < CB; cb++)
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[cb], acc[cb], 0, 0, 0);
+}
+
+template <int CB, bool ONEHOT>
+__device__ inline void wg16_block(const Wg16Lane &L, int MA, int NC, int w, int q, int c,
+                                  int64_t s0, int64_t s1, float *__restrict__ out)
+{
+    f32x4 acc[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; cb++)
+        acc[cb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    int64_t sb = s0;
+    for (; sb + 32 <= s1; sb += 32)
+        wg16_group<CB, ONEHOT, false>(L, c, sb + 8 * q, s1, acc);
+    if (sb < s1)
+        wg16_group<CB, ONEHOT, true>(L, c, sb + 8 * q, s1, acc);
+    // Register i of a tile holds row 4 q + i, column c.
+#pragma unroll
+    for (int cb = 0; cb < CB; cb++) {
+        const int j = 16 * cb + c;
+        if (j >= NC)
+            continue;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int m = 16 * w + 4 * q + i;
+            if (m < MA)
+                out[m * kWgMaxC + j] = acc[cb][i];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgJobs16 jobs, int64_t n,
+                                                         const __bf16 *__restrict__ qp,
+                                                         int64_t per_block,
+                                                         float *__restrict__ partial)
+{
+    const WgJob16 jb = jobs.j[blockIdx.y];
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    const int w = threadIdx.x >> 6;
+    if (16 * w >= jb.MA)
+        return;
+    const int row = 16 * w + c;
+    Wg16Lane L;
+    L.qp = qp;
+    L.a = row < jb.MA ? jb.A + row : -1;
+    L.ids = jb.ids;
+    L.f0 = jb.f0;
+    L.NC = jb.NC;
+    L.b_plane = false;
+    L.b_const = (__bf16)0.0f;
+    const int cb_n = (jb.NC + 15) >> 4;
+#pragma unroll
+    for (int cb = 0; cb < kWg16ColBlocks; cb++) {
+        const int j = 16 * cb + c;
+        // A column that is no plane reads the first input plane (in bounds)
+        // and takes its constant instead.
+        L.b[cb] = jb.B >= 0 ? jb.B + (j < jb.NB ? j : 0) : 0;
+        if (cb == cb_n - 1) {
+            L.b_plane = j < jb.NB;
+            L.b_const = (__bf16)(j < jb.NC && jb.bias ? 1.0f : 0.0f);
+        }
+    }
+    const int64_t s0 = (int64_t)blockIdx.x * per_block;
+    const int64_t s1 = s0 + per_block < n ? s0 + per_block : n;
+    float *out = partial + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (kWgMaxM * kWgMaxC);
+    if (jb.ids) {
+        switch (cb_n) {
+        case 1: wg16_block<1, true>(L, jb.MA, jb.NC, w, q, c, s0, s1, out); break;
+        case 2: wg16_block<2, true>(L, jb.MA, jb.NC, w, q, c, s0, s1, out); break;
+        case 3: wg16_block<3, true>(L, jb.MA, jb.NC, w, q, c, s0, s1, out); break;
+        default: wg16_block<4, true>(L, jb.MA, jb.NC, w, q, c, s0, s1, out); break;
+        }
+        return;
+    }
+    switch (cb_n) {
+    case 1: wg16_block<1, false>(L, jb.MA, jb.NC, w, q, c, s0, s1, out); break;
+    case 2: wg16_block<2, false>(L, jb.MA, jb.NC, w, q, c, s0, s1, out); break;
+    case 3: wg16_block<3, false>(L, jb.MA, jb.NC, w, q, c, s0, s1, out); break;
+    case 4: wg16_block<4, false>(L, jb.MA, jb.NC, w, q, c, s0, s1, out); break;
+    default: wg16_block<5, false>(L, jb.MA, jb.NC, w, q, c, s0, s1, out); break;
+    }
+}
+
 // out_j[m][c] = sum over the blocks' partials in block order (eight
 // interleaved running sums, combined in a fixed order), scattered to
 // dst[m * ldw + c] (c < NW), bias[m] (c == NW with a bias), or with
@@ -534,6 +751,32 @@ __global__ __launch_bounds__(256) void loss_reduce_kernel(const float *__restric
         loss[0] = red[0] * inv_n;
 }
 
+// First stage of the loss of a large batch: block b sums the parts
+// [b seg, (b + 1) seg) the way loss_reduce_kernel sums its input (a
+// compensated sum per thread, then a fixed tree), so the whole reduction
+// keeps a fixed order.
+constexpr int kLossStage = 256;     // first-stage blocks at most
+__global__ __launch_bounds__(256) void loss_stage_kernel(const float *__restrict__ part,
+                                                         int64_t nparts, int64_t seg,
+                                                         float *__restrict__ out)
+{
+    __shared__ float red[256];
+    const int64_t b0 = (int64_t)blockIdx.x * seg;
+    const int64_t b1 = b0 + seg < nparts ? b0 + seg : nparts;
+    KahanSum acc;
+    for (int64_t k = b0 + threadIdx.x; k < b1; k += blockDim.x)
+        acc.add(part[k]);
+    red[threadIdx.x] = acc.value();
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        out[blockIdx.x] = red[0];
+}
+
 // The step count of an Adam state lives on the device with its moments: a
 // step is counted, and its bias corrections 1 - beta^t computed, only when
 // the batch loss is finite, so that an update skipped for a non-finite loss
@@ -592,10 +835,14 @@ hipError_t ensure_acts(TrainScratch &s, int64_t n)
         if ((e = hipMalloc(&s.fwd_image, decoder_image_bytes(FABRIC_FP32))) != hipSuccess) return e;
         if ((e = hipMalloc(&s.bwd_image, (size_t)BwdShape<1>::NFRAG * 64 * sizeof(float))) != hipSuccess) return e;
     }
-    if (s.cap < n) {
-        if ((e = grow(&s.acts, (size_t)n * kActFloats)) != hipSuccess) return e;
-        if ((e = grow(&s.loss_part, (size_t)(n + 15) / 16 + 1)) != hipSuccess) return e;
-        s.cap = n;
+    // A multiple of 64 samples: whole 32-sample groups of the BF16 planes
+    // are read in bounds.
+    const int64_t cap = (n + 63) / 64 * 64;
+    if (s.cap < cap) {
+        if ((e = grow(&s.acts, (size_t)cap * kActFloats)) != hipSuccess) return e;
+        // the per-tile parts, then the first stage's sums
+        if ((e = grow(&s.loss_part, (size_t)cap / 16 + 1 + kLossStage)) != hipSuccess) return e;
+        s.cap = cap;
     }
     return e;
 }
@@ -648,6 +895,42 @@ hipError_t launch_fwd_bwd(TrainScratch &s, const fabric_gbuffer &g, const DevFab
 
 // Weight gradients of the decoder from the per-sample rows: writes every
 // decoder tensor of grad_dec except W1's latent columns, plus dcf.
+// The same from the BF16 planes of a BF16 training step.
+hipError_t decoder_weight_grads_bf16(TrainScratch &s, const fabric_gbuffer &g, int n_fabrics,
+                                     float *grad_dec, hipStream_t stream)
+{
+    const int64_t n = g.n;
+    auto plane = [](int k) { return k; };
+    WgJobs16 jobs{};
+    WgDests dests{};
+    int nj = 0;
+    auto add = [&](int A, int MA, int B, int NB, int bias, const uint16_t *ids,
+                   int f0, int NC, float *dst, int ldw, float *bsum, int transposed) {
+        jobs.j[nj] = WgJob16{A, B, ids, MA, NB, bias, f0, NC};
+        dests.d[nj] = WgDest{dst, bsum, MA, NC, ids ? NC : NB, ldw, transposed};
+        nj++;
+    };
+    add(plane(kQDH1), 64, plane(kQS), 40, 1, nullptr, 0, 41, grad_dec + kOffW1 + kLatent, 72,
+        grad_dec + kOffB1, 0);
+    add(plane(kQDH2), 64, plane(kQH1), 64, 1, nullptr, 0, 65, grad_dec + kOffW2, 64, grad_dec + kOffB2, 0);
+    add(plane(kQDH3), 64, plane(kQX3), 69, 1, nullptr, 0, 70, grad_dec + kOffW3, 69, grad_dec + kOffB3, 0);
+    add(plane(kQDY), 4, plane(kQH3), 64, 1, nullptr, 0, 65, grad_dec + kOffW4, 64, grad_dec + kOffB4, 0);
+    for (int f0 = 0; f0 < n_fabrics; f0 += 64) {
+        const int NC = n_fabrics - f0 < 64 ? n_fabrics - f0 : 64;
+        add(plane(kQDH1), 64, -1, 0, 0, g.fabric_id, f0, NC, s.dcf + f0 * 64, 64, nullptr, 1);
+    }
+    hipError_t e = ensure_partials(s, nj);
+    if (e != hipSuccess)
+        return e;
+    int64_t per_block = (n + kWgBlocks - 1) / kWgBlocks;
+    per_block = (per_block + 63) / 64 * 64;
+    hipLaunchKernelGGL(wgrad_bf16_kernel, dim3(kWgBlocks, nj), dim3(256), 0, stream, jobs, n,
+                       (const __bf16 *)s.acts, per_block, s.partials);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((kWgMaxM * kWgMaxC + 255) / 256, nj), dim3(256), 0,
+                       stream, (const float *)s.partials, dests, kWgBlocks);
+    return hipGetLastError();
+}
+
 hipError_t decoder_weight_grads(TrainScratch &s, const fabric_gbuffer &g, int n_fabrics,
                                 float *grad_dec, hipStream_t stream)
 {
@@ -834,9 +1117,22 @@ hipError_t loss_and_grad(TrainScratch &s, const TrainArgs &a, hipStream_t stream
                 : launch_fwd_bwd<FABRIC_BF16, false>(s, g, a.fabrics, a.n_fabrics, s.cfold, targets, err, stream);
         if (e != hipSuccess) return e;
         const int64_t parts = (n + 15) / 16;
-        hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, stream, (const float *)s.loss_part,
-                           parts, 1.0f / (float)n, s.loss);
-        if ((e = decoder_weight_grads(s, g, a.n_fabrics, s.grad, stream)) != hipSuccess) return e;
+        if (parts <= 4096) {
+            hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, stream,
+                               (const float *)s.loss_part, parts, 1.0f / (float)n, s.loss);
+        } else {
+            // Large batches: fixed segments summed by up to kLossStage blocks first.
+            const int64_t seg = (parts + kLossStage - 1) / kLossStage;
+            const int64_t nb = (parts + seg - 1) / seg;
+            float *stage = s.loss_part + s.cap / 16 + 1;
+            hipLaunchKernelGGL(loss_stage_kernel, dim3((unsigned)nb), dim3(256), 0, stream,
+                               (const float *)s.loss_part, parts, seg, stage);
+            hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, stream,
+                               (const float *)stage, nb, 1.0f / (float)n, s.loss);
+        }
+        e = cfg.prec == FABRIC_FP32 ? decoder_weight_grads(s, g, a.n_fabrics, s.grad, stream)
+                                    : decoder_weight_grads_bf16(s, g, a.n_fabrics, s.grad, stream);
+        if (e != hipSuccess) return e;
     } else {
         if ((e = hipMemsetAsync(s.loss, 0, sizeof(float), stream)) != hipSuccess) return e;
         if ((e = hipMemsetAsync(s.grad, 0, kNDec * sizeof(float), stream)) != hipSuccess) return e;
