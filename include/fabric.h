@@ -418,10 +418,11 @@ fabric_status fabric_loss_grad(fabric_ctx *ctx, const fabric_gbuffer *batch, con
  * in FP32 on the vector units, one sample per lane) or FABRIC_BF16 (forward
  * and backward on the matrix cores, 32 samples per wave: BF16 operands,
  * the forward's from the shading image of the current masters, the
- * backward's from the transposed masters, FP32 accumulation); either way
- * the weight gradients are fixed-order split-K sums of FP32 per-sample
- * planes, the masters stay FP32 and Adam keeps FP64 moments, so repeated
- * runs are bitwise equal.  Other precisions: E_INVAL.
+ * backward's from the transposed masters, FP32 accumulation, per-sample
+ * activations and gradients kept as BF16); the weight gradients are
+ * fixed-order split-K sums over the per-sample values (FP32 or BF16
+ * operands, FP32 sums), the masters stay FP32 and Adam keeps FP64 moments,
+ * so repeated runs are bitwise equal.  Other precisions: E_INVAL.
  * fabric_paper_train_step takes one Adam step over [params | latents]
  * ([params | enc_params] in encoder mode) and re-packs the shading image
  * from the updated masters; a non-finite loss (known only when

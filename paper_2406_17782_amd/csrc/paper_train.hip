@@ -55,6 +55,18 @@ constexpr int kPlDG = kPlDRR + 64;
 constexpr int kPlanes = kPlDG + 64;
 static_assert(kPlanes == 801, "plane count");
 
+// BF16 training keeps the planes as BF16 values blocked by 64 samples: the
+// 801 planes of samples 64 b .. 64 b + 63 form one contiguous region, each
+// plane's 64 samples in order, so the weight gradients read eight
+// consecutive samples of a plane with one 16-byte load and a chunk's reads
+// stay within its regions.
+constexpr int kQBlock = 64;
+__host__ __device__ inline int64_t q_elem(int plane, int64_t s)
+{
+    // s >= 0: the shift and the mask are the quotient and the remainder.
+    return (s >> 6) * ((int64_t)kPlanes * kQBlock) + plane * kQBlock + (s & (kQBlock - 1));
+}
+
 // Transposed weights of every layer for the forward pass, WT[i][o] =
 // W[o][i] (the 16 outputs of a wave are then 16 consecutive floats).
 enum { kTF1 = 0, kTF2, kTA1, kTA2, kTA3, kTA4, kTA5, kTLayers };
@@ -416,9 +428,12 @@ __global__ __launch_bounds__(256, 2) void paper_fwd_bwd_bf16_kernel(
         cur.x1 = 0.0f;
         cur.xz = 1.0f;
     }
+    // The BF16 planes (blocked by 64 samples) in the buffer of the FP32 ones.
+    __bf16 *qp = (__bf16 *)pl;
+    (void)cap;
     auto store = [&](int plane, float val) {
         if (live)
-            pl[(int64_t)plane * cap + s] = fault ? 0.0f : val;
+            qp[q_elem(plane, s)] = (__bf16)(fault ? 0.0f : val);
     };
     // Accumulator register r of M-block mb holds neuron 32 mb + 8 (r/4) + 4 g + r%4.
     auto store_acc = [&](int plane, const f32x16 (&v)[2]) {
@@ -815,6 +830,165 @@ __global__ __launch_bounds__(kPwThreads) void paper_wgrad_kernel(PWJobs jobs,
     }
 }
 
+// The same jobs from the BF16 planes of BF16 training, on BF16 MFMA
+// 16x16x32: lane (q = l/16, c = l%16) holds samples s + 8 q .. s + 8 q + 7 of
+// its delta row and of its columns' planes (one 16-byte load each, within
+// one 64-sample region), which fill k slots 8 q .. 8 q + 7 of both operands
+// alike; one MFMA per 16-column block and group of 32 samples.
+struct PqLane {
+    const __bf16 *qp;               // the planes
+    int a;                          // the lane's delta plane (-1: a padding row)
+    int b[kPwColBlocks];            // input planes of the lane's columns
+    bool b_plane;                   // the last block's column is a plane
+    __bf16 b_const;                 // else its value (1 for the bias, 0 for padding)
+    const uint16_t *fid;            // one-hot job: the fabric ids
+};
+
+// The operands of one group of 32 samples.
+template <int CB> struct PqOps {
+    bf16x8 a;
+    bf16x8 b[CB];
+};
+
+template <int CB, bool ONEHOT, bool TAIL>
+__device__ inline void pq_load(const PqLane &L, int c, int64_t base, int64_t s1, PqOps<CB> &o)
+{
+    const __bf16 zero = (__bf16)0.0f, one = (__bf16)1.0f;
+    auto in = [&](int t) { return !TAIL || base + t < s1; };
+    const __bf16 *reg = L.qp + q_elem(0, base);
+    if (L.a >= 0) {
+        o.a = *(const bf16x8 *)(reg + L.a * kQBlock);
+        if (TAIL) {
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+                o.a[t] = in(t) ? o.a[t] : zero;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 8; t++)
+            o.a[t] = zero;
+    }
+    if (ONEHOT) {
+        int id[8];
+#pragma unroll
+        for (int t = 0; t < 8; t++)
+            id[t] = in(t) ? (int)L.fid[base + t] : -1;
+#pragma unroll
+        for (int cb = 0; cb < CB; cb++)
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+                o.b[cb][t] = id[t] == 16 * cb + c ? one : zero;
+    } else {
+#pragma unroll
+        for (int cb = 0; cb < CB; cb++) {
+            const bf16x8 v = *(const bf16x8 *)(reg + L.b[cb] * kQBlock);
+            const bool plane = cb < CB - 1 || L.b_plane;
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+                o.b[cb][t] = plane ? (in(t) ? v[t] : zero) : L.b_const;
+        }
+    }
+}
+
+template <int CB>
+__device__ inline void pq_mma(const PqOps<CB> &o, f32x4 (&acc)[CB])
+{
+#pragma unroll
+    for (int cb = 0; cb < CB; cb++)
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a, o.b[cb], acc[cb], 0, 0, 0);
+}
+
+template <int CB, bool ONEHOT>
+__device__ inline void pq_chunk(const PqLane &L, const PWJob &jb, int cols, int w, int q, int c,
+                                int64_t s0, int64_t s1, float *__restrict__ dst)
+{
+    f32x4 acc[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; cb++)
+        acc[cb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    int64_t sb = s0;
+    for (; sb + 32 <= s1; sb += 32) {
+        PqOps<CB> o;
+        pq_load<CB, ONEHOT, false>(L, c, sb + 8 * q, s1, o);
+        pq_mma<CB>(o, acc);
+    }
+    if (sb < s1) {
+        PqOps<CB> o;
+        pq_load<CB, ONEHOT, true>(L, c, sb + 8 * q, s1, o);
+        pq_mma<CB>(o, acc);
+    }
+    // Register i of a tile holds row 4 q + i, column c.
+#pragma unroll
+    for (int cb = 0; cb < CB; cb++) {
+        const int j = 16 * cb + c;
+        if (j >= cols)
+            continue;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int r = 16 * w + 4 * q + i;
+            if (r < jb.n_out)
+                dst[r * cols + j] = acc[cb][i];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kPwThreads) void paper_wgrad_bf16_kernel(PWJobs jobs,
+                                                                      const __bf16 *__restrict__ qp,
+                                                                      const uint16_t *__restrict__ fid,
+                                                                      int64_t n,
+                                                                      float *__restrict__ partial)
+{
+    const PWJob jb = jobs.j[blockIdx.y];
+    const int cols = pw_cols(jb);
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    const int w = threadIdx.x >> 6;
+    if (16 * w >= jb.n_out)
+        return;
+    const int cb_n = (cols + 15) >> 4;
+    const int row = 16 * w + c;
+    PqLane L;
+    L.qp = qp;
+    L.a = row < jb.n_out ? jb.delta + row : -1;
+    L.fid = fid;
+    L.b_plane = false;
+    L.b_const = (__bf16)0.0f;
+#pragma unroll
+    for (int cb = 0; cb < kPwColBlocks; cb++) {
+        const int j = 16 * cb + c;
+        // A column that is no plane reads the first input plane and takes its
+        // constant instead.
+        int plane = jb.inA;
+        if (j < jb.nA)
+            plane = jb.inA + j;
+        else if (j < jb.nA + jb.nB)
+            plane = jb.inB + j - jb.nA;
+        L.b[cb] = plane;
+        if (cb == cb_n - 1) {
+            L.b_plane = j < jb.nA + jb.nB;
+            L.b_const = (__bf16)(j < cols ? 1.0f : 0.0f);     // the bias column, or padding
+        }
+    }
+    const int64_t s0 = (int64_t)blockIdx.x * kPwChunk;
+    const int64_t s1 = s0 + kPwChunk < n ? s0 + kPwChunk : n;
+    float *dst = partial + jobs.poff[blockIdx.y] + (int64_t)blockIdx.x * jb.n_out * cols;
+    if (jb.onehot) {
+        switch (cb_n) {
+        case 1: pq_chunk<1, true>(L, jb, cols, w, q, c, s0, s1, dst); break;
+        case 2: pq_chunk<2, true>(L, jb, cols, w, q, c, s0, s1, dst); break;
+        case 3: pq_chunk<3, true>(L, jb, cols, w, q, c, s0, s1, dst); break;
+        default: pq_chunk<4, true>(L, jb, cols, w, q, c, s0, s1, dst); break;
+        }
+        return;
+    }
+    switch (cb_n) {
+    case 1: pq_chunk<1, false>(L, jb, cols, w, q, c, s0, s1, dst); break;
+    case 2: pq_chunk<2, false>(L, jb, cols, w, q, c, s0, s1, dst); break;
+    case 3: pq_chunk<3, false>(L, jb, cols, w, q, c, s0, s1, dst); break;
+    case 4: pq_chunk<4, false>(L, jb, cols, w, q, c, s0, s1, dst); break;
+    default: pq_chunk<5, false>(L, jb, cols, w, q, c, s0, s1, dst); break;
+    }
+}
+
 __global__ __launch_bounds__(256) void paper_wgrad_reduce_kernel(PWJobs jobs, int n_chunks,
                                                                  const float *__restrict__ partial,
                                                                  float *__restrict__ grad,
@@ -1055,8 +1229,12 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
     }
     hipLaunchKernelGGL(paper_loss_reduce_kernel, dim3(1), dim3(256), 0, stream,
                        (const float *)s.loss_part, loss_parts, 1.0f / (float)n, s.loss);
-    hipLaunchKernelGGL(paper_wgrad_kernel, dim3(n_chunks, jobs.n_jobs), dim3(kPwThreads), 0, stream, jobs,
-                       (const float *)s.planes, s.cap, g.fabric_id, n, s.partial);
+    if (a.cfg.prec == FABRIC_BF16)
+        hipLaunchKernelGGL(paper_wgrad_bf16_kernel, dim3(n_chunks, jobs.n_jobs), dim3(kPwThreads), 0,
+                           stream, jobs, (const __bf16 *)s.planes, g.fabric_id, n, s.partial);
+    else
+        hipLaunchKernelGGL(paper_wgrad_kernel, dim3(n_chunks, jobs.n_jobs), dim3(kPwThreads), 0, stream,
+                           jobs, (const float *)s.planes, s.cap, g.fabric_id, n, s.partial);
     hipLaunchKernelGGL(paper_wgrad_reduce_kernel, dim3((64 * kPwMaxIn + 255) / 256, jobs.n_jobs),
                        dim3(256), 0, stream, jobs, n_chunks, (const float *)s.partial, grad, s.dsum);
     const int tot = 64 * kPLat + a.n_fabrics * kPLat;

@@ -513,28 +513,30 @@ struct Wg16Lane {
     int f0, NC;
 };
 
+template <int CB> struct Wg16Ops {
+    bf16x8 a;
+    bf16x8 b[CB];
+};
+
 template <int CB, bool ONEHOT, bool TAIL>
-__device__ inline void wg16_group(const Wg16Lane &L, int c, int64_t base, int64_t s1,
-                                  f32x4 (&acc)[CB])
+__device__ inline void wg16_load(const Wg16Lane &L, int c, int64_t base, int64_t s1, Wg16Ops<CB> &o)
 {
     const __bf16 zero = (__bf16)0.0f, one = (__bf16)1.0f;
     auto in = [&](int t) { return !TAIL || base + t < s1; };
     // base is a multiple of 8: the eight samples lie in one region.
     const __bf16 *reg = L.qp + q_elem(0, base);
-    bf16x8 a;
     if (L.a >= 0) {
-        a = *(const bf16x8 *)(reg + L.a * kQBlock);
+        o.a = *(const bf16x8 *)(reg + L.a * kQBlock);
         if (TAIL) {
 #pragma unroll
             for (int t = 0; t < 8; t++)
-                a[t] = in(t) ? a[t] : zero;
+                o.a[t] = in(t) ? o.a[t] : zero;
         }
     } else {
 #pragma unroll
         for (int t = 0; t < 8; t++)
-            a[t] = zero;
+            o.a[t] = zero;
     }
-    bf16x8 b[CB];
     if (ONEHOT) {
         int id[8];
 #pragma unroll
@@ -545,7 +547,7 @@ __device__ inline void wg16_group(const Wg16Lane &L, int c, int64_t base, int64_
             const int j = 16 * cb + c;
 #pragma unroll
             for (int t = 0; t < 8; t++)
-                b[cb][t] = j < L.NC && id[t] == j ? one : zero;
+                o.b[cb][t] = j < L.NC && id[t] == j ? one : zero;
         }
     } else {
 #pragma unroll
@@ -554,12 +556,17 @@ __device__ inline void wg16_group(const Wg16Lane &L, int c, int64_t base, int64_
             const bool plane = cb < CB - 1 || L.b_plane;
 #pragma unroll
             for (int t = 0; t < 8; t++)
-                b[cb][t] = plane ? (in(t) ? v[t] : zero) : L.b_const;
+                o.b[cb][t] = plane ? (in(t) ? v[t] : zero) : L.b_const;
         }
     }
+}
+
+template <int CB>
+__device__ inline void wg16_mma(const Wg16Ops<CB> &o, f32x4 (&acc)[CB])
+{
 #pragma unroll
     for (int cb = 0; cb < CB; cb++)
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[cb], acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a, o.b[cb], acc[cb], 0, 0, 0);
 }
 
 template <int CB, bool ONEHOT>
@@ -571,10 +578,16 @@ __device__ inline void wg16_block(const Wg16Lane &L, int MA, int NC, int w, int 
     for (int cb = 0; cb < CB; cb++)
         acc[cb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     int64_t sb = s0;
-    for (; sb + 32 <= s1; sb += 32)
-        wg16_group<CB, ONEHOT, false>(L, c, sb + 8 * q, s1, acc);
-    if (sb < s1)
-        wg16_group<CB, ONEHOT, true>(L, c, sb + 8 * q, s1, acc);
+    for (; sb + 32 <= s1; sb += 32) {
+        Wg16Ops<CB> o;
+        wg16_load<CB, ONEHOT, false>(L, c, sb + 8 * q, s1, o);
+        wg16_mma<CB>(o, acc);
+    }
+    if (sb < s1) {
+        Wg16Ops<CB> o;
+        wg16_load<CB, ONEHOT, true>(L, c, sb + 8 * q, s1, o);
+        wg16_mma<CB>(o, acc);
+    }
     // Register i of a tile holds row 4 q + i, column c.
 #pragma unroll
     for (int cb = 0; cb < CB; cb++) {
