@@ -342,13 +342,13 @@ __global__ __launch_bounds__(256) void paper_loss_reduce_kernel(const float *__r
 //
 // The forward runs the shading kernel's tile (paper_tile.hpp) on the BF16
 // shading image that the masters were last packed into, 32 samples per wave,
-// with its scaled activations (s times them, the FP32 network's
-// activations to FP32 rounding, go to the planes);
-// the backward chains the transposed weights the same way: the gradient at
-// a layer's pre-activation, held in the accumulator layout, is the B operand
-// of the next transposed layer without data movement.  Activations and
-// gradients (FP32, before rounding) go to the same per-sample planes as the
-// FP32 path, so the weight gradients are those kernels'.
+// with its scaled activations; the backward chains the transposed weights
+// the same way: the gradient at a layer's pre-activation, held in the
+// accumulator layout, is the B operand of the next transposed layer without
+// data movement.  The quantities of the FP32 path's planes (s times the
+// scaled activations: the FP32 network's activations to FP32 rounding; the
+// gradients) go to BF16 planes blocked by 64 samples (q_elem), whose weight
+// gradients paper_wgrad_bf16_kernel sums.
 //
 // Transposed-weight fragments, in the order the backward uses them: A5^T
 // (2 M-blocks, one K step: the four outputs in slots 0..3 of lane group 0),
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(256, 2) void paper_fwd_bwd_bf16_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ cfold, const bf16x8 *__restrict__ ffr, const f32x4 *__restrict__ bias5,
     const bf16x8 *__restrict__ bfr, const float *__restrict__ targets, float *__restrict__ pl,
-    int64_t cap, float *__restrict__ loss_part)
+    float *__restrict__ loss_part)
 {
     using PT = PaperTile<FABRIC_BF16>;
     using M = typename PT::M;
@@ -430,7 +430,6 @@ __global__ __launch_bounds__(256, 2) void paper_fwd_bwd_bf16_kernel(
     }
     // The BF16 planes (blocked by 64 samples) in the buffer of the FP32 ones.
     __bf16 *qp = (__bf16 *)pl;
-    (void)cap;
     auto store = [&](int plane, float val) {
         if (live)
             qp[q_elem(plane, s)] = (__bf16)(fault ? 0.0f : val);
@@ -1212,7 +1211,7 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
         auto launch = [&](auto kernel) {
             hipLaunchKernelGGL(kernel, dim3((unsigned)loss_parts), dim3(256), lds, stream, g,
                                a.fabrics, a.n_fabrics, a.cfold, ffr, b5,
-                               (const bf16x8 *)s.bwd_frags, targets, s.planes, s.cap, s.loss_part);
+                               (const bf16x8 *)s.bwd_frags, targets, s.planes, s.loss_part);
         };
         if (a.raw)
             a.fused ? launch(paper_fwd_bwd_bf16_kernel<true, true>)

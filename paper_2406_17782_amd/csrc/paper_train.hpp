@@ -16,7 +16,8 @@ constexpr int kPaperTrainMaxFabrics = 64;
 // Device scratch owned by a context, grown on demand.
 struct PaperTrainScratch {
     int64_t cap = 0;              // samples the per-sample planes hold
-    float *planes = nullptr;      // per-sample planes [801][cap] (see paper_train.hip)
+    float *planes = nullptr;      // per-sample planes [801][cap], or in BF16 training
+                                  // BF16 planes blocked by 64 samples (see paper_train.hip)
     float *loss_part = nullptr;   // per 256-sample block
     float *loss = nullptr;        // [1]
     float *wt = nullptr;          // transposed weights of F2, A1 (first 64 inputs), A2, A3, A4

@@ -913,7 +913,6 @@ hipError_t decoder_weight_grads_bf16(TrainScratch &s, const fabric_gbuffer &g, i
                                      float *grad_dec, hipStream_t stream)
 {
     const int64_t n = g.n;
-    auto plane = [](int k) { return k; };
     WgJobs16 jobs{};
     WgDests dests{};
     int nj = 0;
@@ -923,14 +922,14 @@ hipError_t decoder_weight_grads_bf16(TrainScratch &s, const fabric_gbuffer &g, i
         dests.d[nj] = WgDest{dst, bsum, MA, NC, ids ? NC : NB, ldw, transposed};
         nj++;
     };
-    add(plane(kQDH1), 64, plane(kQS), 40, 1, nullptr, 0, 41, grad_dec + kOffW1 + kLatent, 72,
+    add(kQDH1, 64, kQS, 40, 1, nullptr, 0, 41, grad_dec + kOffW1 + kLatent, 72,
         grad_dec + kOffB1, 0);
-    add(plane(kQDH2), 64, plane(kQH1), 64, 1, nullptr, 0, 65, grad_dec + kOffW2, 64, grad_dec + kOffB2, 0);
-    add(plane(kQDH3), 64, plane(kQX3), 69, 1, nullptr, 0, 70, grad_dec + kOffW3, 69, grad_dec + kOffB3, 0);
-    add(plane(kQDY), 4, plane(kQH3), 64, 1, nullptr, 0, 65, grad_dec + kOffW4, 64, grad_dec + kOffB4, 0);
+    add(kQDH2, 64, kQH1, 64, 1, nullptr, 0, 65, grad_dec + kOffW2, 64, grad_dec + kOffB2, 0);
+    add(kQDH3, 64, kQX3, 69, 1, nullptr, 0, 70, grad_dec + kOffW3, 69, grad_dec + kOffB3, 0);
+    add(kQDY, 4, kQH3, 64, 1, nullptr, 0, 65, grad_dec + kOffW4, 64, grad_dec + kOffB4, 0);
     for (int f0 = 0; f0 < n_fabrics; f0 += 64) {
         const int NC = n_fabrics - f0 < 64 ? n_fabrics - f0 : 64;
-        add(plane(kQDH1), 64, -1, 0, 0, g.fabric_id, f0, NC, s.dcf + f0 * 64, 64, nullptr, 1);
+        add(kQDH1, 64, -1, 0, 0, g.fabric_id, f0, NC, s.dcf + f0 * 64, 64, nullptr, 1);
     }
     hipError_t e = ensure_partials(s, nj);
     if (e != hipSuccess)
