@@ -46,10 +46,12 @@ def _torch():
 
 
 def _stream(stream) -> Optional[int]:
+    """A HIP stream handle: torch's current stream for None, a torch stream's
+    handle, or an integer handle as given."""
     if stream is None:
         torch = _torch()
         return torch.cuda.current_stream().cuda_stream
-    return int(stream)
+    return int(getattr(stream, "cuda_stream", stream))
 
 
 def _dptr(t) -> int:

@@ -115,3 +115,15 @@ def test_binding_constants_match_header():
                  "FABRIC_N_PAPER_DECODER_PARAMS", "FABRIC_N_PAPER_ENCODER_PARAMS",
                  "FABRIC_NOALLOC_MAX_PIXELS"):
         assert getattr(_abi, name) == int(defs[name]), name
+
+
+def test_stream_arguments_accept_handles_and_stream_objects():
+    """The binding passes a HIP stream handle: an integer as given, or the
+    handle of a stream object (torch's `cuda_stream`)."""
+    import paper_2406_17782_amd as pkg
+
+    class FakeStream:
+        cuda_stream = 0x1234
+
+    assert pkg._stream(0x5678) == 0x5678
+    assert pkg._stream(FakeStream()) == 0x1234
