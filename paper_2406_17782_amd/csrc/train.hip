@@ -168,13 +168,17 @@ __global__ void pack_backward_kernel(const float *__restrict__ params,
 // GIVEN_DY: dy comes from the caller (dL/dy4 [4][n]); otherwise from the loss
 // of Eq. (9)-(11) against targets [4][n] (C_warp, C_weft, S_warp, S_weft).
 // ---------------------------------------------------------------------------
-template <int P, bool GIVEN_DY>
-__global__ __launch_bounds__(256) void fwd_bwd_kernel(
-    fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
+// The forward, loss and activation backward of 16-sample tile `tile`, one
+// wave: the per-sample results go to sink(p, valid, live, s1, a1, a2, a3,
+// d1, d2, d3, dy, wi, wo) (p past the batch: valid = false, the values of a
+// clamped sample with no loss and zero gradients).
+template <int P, bool GIVEN_DY, typename Sink>
+__device__ inline void fwd_bwd_tile(
+    const fabric_gbuffer &g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ ffr,
     const f32x4 *__restrict__ fbias, const typename Mfma<P>::Frag *__restrict__ bfr,
-    const float *__restrict__ tgt_or_dy, float *__restrict__ acts, int64_t cap,
-    float *__restrict__ loss_part, unsigned long long *err)
+    const float *__restrict__ tgt_or_dy, int64_t tile, float *__restrict__ loss_part,
+    unsigned long long *err, Sink &&sink)
 {
     using T = Tile<P>;
     using M = typename T::M;
@@ -182,14 +186,8 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(
     using B = BwdShape<T::KPL>;
     constexpr int KPL = T::KPL;
 
-    // BF16 training writes the blocked BF16 planes (see kQPlanes).
-    constexpr bool kQ = P == FABRIC_BF16 && !GIVEN_DY;
-
     const int lane = threadIdx.x & 63, grp = lane >> 4, col = lane & 15;
-    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t n = g.n;
-    if (tile * 16 >= n)        // whole wave past the end (last block)
-        return;
     const int64_t p = tile * 16 + col;
     const bool valid = p < n;
     const int64_t pc = valid ? p : n - 1;
@@ -311,75 +309,103 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(
         for (int i = 0; i < 4; i++)
             d1[mb][i] = a1[mb][i] > 0.0f ? d1[mb][i] : 0.0f;
 
-    if (!valid)
+    sink(p, valid, live, s1, a1, a2, a3, d1, d2, d3, dy, wi, wo);
+}
+
+// Fused forward, loss and activation backward: one 16-sample tile per wave;
+// the activations and activation gradients go to per-sample FP32 rows, or
+// in BF16 training to BF16 planes blocked by 64 samples.
+template <int P, bool GIVEN_DY>
+__global__ __launch_bounds__(256) void fwd_bwd_kernel(
+    fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
+    const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ ffr,
+    const f32x4 *__restrict__ fbias, const typename Mfma<P>::Frag *__restrict__ bfr,
+    const float *__restrict__ tgt_or_dy, float *__restrict__ acts, int64_t cap,
+    float *__restrict__ loss_part, unsigned long long *err)
+{
+    using T = Tile<P>;
+    // BF16 training writes the blocked BF16 planes (see kQPlanes).
+    constexpr bool kQ = P == FABRIC_BF16 && !GIVEN_DY;
+    const int grp = (threadIdx.x & 63) >> 4;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile * 16 >= g.n)      // whole wave past the end (last block)
         return;
-    const float keep = live ? 1.0f : 0.0f;
-    if (kQ) {
-        // ---- per-sample BF16 planes for the weight gradients ----
-        __bf16 *qp = (__bf16 *)acts;
-        auto put = [&](int plane, float x) { qp[q_elem(plane, p)] = (__bf16)x; };
+    auto sink = [&](int64_t p, bool valid, bool live, const float (&s1)[T::NS1],
+                    const f32x4 (&a1)[4], const f32x4 (&a2)[4], const f32x4 (&a3)[4],
+                    const f32x4 (&d1)[4], const f32x4 (&d2)[4], const f32x4 (&d3)[4],
+                    const float (&dy)[4], float3 wi, float3 wo) {
+        if (!valid)
+            return;
+        const float keep = live ? 1.0f : 0.0f;
+        if (kQ) {
+            // ---- per-sample BF16 planes for the weight gradients ----
+            __bf16 *qp = (__bf16 *)acts;
+            auto put = [&](int plane, float x) { qp[q_elem(plane, p)] = (__bf16)x; };
+#pragma unroll
+            for (int c = 0; c < kL1Slots; c++)
+                put(kQS + l1_feature(grp, c), s1[c]);
+#pragma unroll
+            for (int mb = 0; mb < 4; mb++) {
+                const int o = 16 * mb + 4 * grp;
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    put(kQH1 + o + i, fmaxf(a1[mb][i], 0.0f));
+                    put(kQX3 + o + i, fmaxf(a2[mb][i], 0.0f));
+                    put(kQH3 + o + i, fmaxf(a3[mb][i], 0.0f));
+                    put(kQDH1 + o + i, d1[mb][i] * keep);
+                    put(kQDH2 + o + i, d2[mb][i] * keep);
+                    put(kQDH3 + o + i, d3[mb][i] * keep);
+                }
+            }
+            if (grp == 0) {
+                put(kQX3 + 64, wi.x);
+                put(kQX3 + 65, wi.y);
+                put(kQX3 + 66, wi.z);
+                put(kQX3 + 67, wo.x);
+                put(kQX3 + 68, wo.y);
+#pragma unroll
+                for (int c = 0; c < 4; c++)
+                    put(kQDY + c, dy[c]);
+            }
+            return;
+        }
+        // ---- per-sample rows for the weight gradients ----
+        ActPtrs ap = act_ptrs(acts, cap);
 #pragma unroll
         for (int c = 0; c < kL1Slots; c++)
-            put(kQS + l1_feature(grp, c), s1[c]);
+            ap.S[p * kS + l1_feature(grp, c)] = s1[c];
 #pragma unroll
         for (int mb = 0; mb < 4; mb++) {
             const int o = 16 * mb + 4 * grp;
+            f32x4 h1, h2, h3;
 #pragma unroll
             for (int i = 0; i < 4; i++) {
-                put(kQH1 + o + i, fmaxf(a1[mb][i], 0.0f));
-                put(kQX3 + o + i, fmaxf(a2[mb][i], 0.0f));
-                put(kQH3 + o + i, fmaxf(a3[mb][i], 0.0f));
-                put(kQDH1 + o + i, d1[mb][i] * keep);
-                put(kQDH2 + o + i, d2[mb][i] * keep);
-                put(kQDH3 + o + i, d3[mb][i] * keep);
+                h1[i] = fmaxf(a1[mb][i], 0.0f);
+                h2[i] = fmaxf(a2[mb][i], 0.0f);
+                h3[i] = fmaxf(a3[mb][i], 0.0f);
             }
+            *(f32x4 *)(ap.H1 + p * kH1 + o) = h1;
+            *(f32x4 *)(ap.X3 + p * kX3 + o) = h2;
+            *(f32x4 *)(ap.H3 + p * kH3 + o) = h3;
+            *(f32x4 *)(ap.DH1 + p * kDH + o) = d1[mb] * keep;
+            *(f32x4 *)(ap.DH2 + p * kDH + o) = d2[mb] * keep;
+            *(f32x4 *)(ap.DH3 + p * kDH + o) = d3[mb] * keep;
         }
         if (grp == 0) {
-            put(kQX3 + 64, wi.x);
-            put(kQX3 + 65, wi.y);
-            put(kQX3 + 66, wi.z);
-            put(kQX3 + 67, wo.x);
-            put(kQX3 + 68, wo.y);
-#pragma unroll
-            for (int c = 0; c < 4; c++)
-                put(kQDY + c, dy[c]);
+            float *x3 = ap.X3 + p * kX3;
+            x3[64] = wi.x;
+            x3[65] = wi.y;
+            x3[66] = wi.z;
+            x3[67] = wo.x;
+            x3[68] = wo.y;
+            x3[69] = 0.0f;
+            x3[70] = 0.0f;
+            x3[71] = 0.0f;
+            *(f32x4 *)(ap.DY + p * kDY) = f32x4{dy[0], dy[1], dy[2], dy[3]};
         }
-        return;
-    }
-    // ---- per-sample rows for the weight gradients ----
-    ActPtrs ap = act_ptrs(acts, cap);
-#pragma unroll
-    for (int c = 0; c < kL1Slots; c++)
-        ap.S[p * kS + l1_feature(grp, c)] = s1[c];
-#pragma unroll
-    for (int mb = 0; mb < 4; mb++) {
-        const int o = 16 * mb + 4 * grp;
-        f32x4 h1, h2, h3;
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            h1[i] = fmaxf(a1[mb][i], 0.0f);
-            h2[i] = fmaxf(a2[mb][i], 0.0f);
-            h3[i] = fmaxf(a3[mb][i], 0.0f);
-        }
-        *(f32x4 *)(ap.H1 + p * kH1 + o) = h1;
-        *(f32x4 *)(ap.X3 + p * kX3 + o) = h2;
-        *(f32x4 *)(ap.H3 + p * kH3 + o) = h3;
-        *(f32x4 *)(ap.DH1 + p * kDH + o) = d1[mb] * keep;
-        *(f32x4 *)(ap.DH2 + p * kDH + o) = d2[mb] * keep;
-        *(f32x4 *)(ap.DH3 + p * kDH + o) = d3[mb] * keep;
-    }
-    if (grp == 0) {
-        float *x3 = ap.X3 + p * kX3;
-        x3[64] = wi.x;
-        x3[65] = wi.y;
-        x3[66] = wi.z;
-        x3[67] = wo.x;
-        x3[68] = wo.y;
-        x3[69] = 0.0f;
-        x3[70] = 0.0f;
-        x3[71] = 0.0f;
-        *(f32x4 *)(ap.DY + p * kDY) = f32x4{dy[0], dy[1], dy[2], dy[3]};
-    }
+    };
+    fwd_bwd_tile<P, GIVEN_DY>(g, fabrics, n_fabrics, cfold, ffr, fbias, bfr, tgt_or_dy, tile,
+                              loss_part, err, sink);
 }
 
 // ---------------------------------------------------------------------------
@@ -655,6 +681,171 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgJobs16 jobs, int64_t 
     }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 training in one persistent kernel, the activations kept on chip: a
+// block of kFWaves waves takes kFChunk consecutive samples at a time; each
+// wave runs the forward, loss and activation backward of its 16 samples
+// (fwd_bwd_tile) and writes the per-sample values - every MFMA operand as
+// the forward used it and the activation gradients, rounded to BF16 - as
+// rows of the block's LDS region ([plane][sample], the planes of kQPlanes);
+// after a barrier the waves accumulate the weight gradients of those
+// samples from the region on BF16 MFMA 16x16x16 (samples as K: lane
+// (q = l/16, c = l%16) reads samples 4q .. 4q + 3 of a 16-sample step from
+// row c of the tile's delta planes and of its input planes, one 8-byte read
+// each), a wave owning the tiles w, w + kFWaves, ... of the step's 16x16
+// output tiles over all its chunks; a second barrier frees the region for
+// the next chunk.  The tiles' sums go to the partial layout of
+// wgrad_kernel (one partial per block), summed by wgrad_reduce_kernel.
+// Samples past the batch run on a clamped sample with zero gradients and
+// add nothing.
+// ---------------------------------------------------------------------------
+constexpr int kFWaves = 8;
+constexpr int kFChunk = 16 * kFWaves;        // samples per chunk
+constexpr int kFStride = kFChunk + 8;        // LDS row of a plane (BF16 values)
+constexpr int kFMaxSlots = 8;                // output tiles per wave
+constexpr size_t kFLds = (size_t)kQPlanes * kFStride * 2 + (size_t)kFChunk * 2;
+static_assert(kFLds <= 160 * 1024, "the region fits in a CU's LDS");
+
+struct FusedJobs {
+    WgJob16 j[kWgMaxJobs];       // A, B: first planes of the region (B < 0: one-hot)
+    int first_tile[kWgMaxJobs + 1];
+    int n_jobs;
+};
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(64 * kFWaves) void train_bf16_fused_kernel(
+    fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
+    const float *__restrict__ cfold, const bf16x8 *__restrict__ ffr,
+    const f32x4 *__restrict__ fbias, const bf16x8 *__restrict__ bfr,
+    const float *__restrict__ targets, float *__restrict__ loss_part, unsigned long long *err,
+    FusedJobs jobs, int64_t n_chunks, float *__restrict__ partial)
+{
+    using T = Tile<FABRIC_BF16>;
+    extern __shared__ __align__(16) unsigned char f_smem[];
+    __bf16 *region = (__bf16 *)f_smem;
+    uint16_t *s_fid = (uint16_t *)(f_smem + (size_t)kQPlanes * kFStride * 2);
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    const int w = threadIdx.x >> 6;
+    const int n_tiles = jobs.first_tile[jobs.n_jobs];
+
+    f32x4 acc[kFMaxSlots];
+#pragma unroll
+    for (int k = 0; k < kFMaxSlots; k++)
+        acc[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+        // ---- the wave's 16 samples into the region ----
+        const int64_t tile = chunk * kFWaves + w;
+        auto sink = [&](int64_t p, bool valid, bool live, const float (&s1)[T::NS1],
+                        const f32x4 (&a1)[4], const f32x4 (&a2)[4], const f32x4 (&a3)[4],
+                        const f32x4 (&d1)[4], const f32x4 (&d2)[4], const f32x4 (&d3)[4],
+                        const float (&dy)[4], float3 wi, float3 wo) {
+            (void)valid;
+            const float keep = live ? 1.0f : 0.0f;
+            const int sl = 16 * w + c;
+            auto put = [&](int plane, float x) { region[plane * kFStride + sl] = (__bf16)x; };
+#pragma unroll
+            for (int k = 0; k < kL1Slots; k++)
+                put(kQS + l1_feature(q, k), s1[k]);
+#pragma unroll
+            for (int mb = 0; mb < 4; mb++) {
+                const int o = 16 * mb + 4 * q;
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    put(kQH1 + o + i, fmaxf(a1[mb][i], 0.0f));
+                    put(kQX3 + o + i, fmaxf(a2[mb][i], 0.0f));
+                    put(kQH3 + o + i, fmaxf(a3[mb][i], 0.0f));
+                    put(kQDH1 + o + i, d1[mb][i] * keep);
+                    put(kQDH2 + o + i, d2[mb][i] * keep);
+                    put(kQDH3 + o + i, d3[mb][i] * keep);
+                }
+            }
+            if (q == 0) {
+                put(kQX3 + 64, wi.x);
+                put(kQX3 + 65, wi.y);
+                put(kQX3 + 66, wi.z);
+                put(kQX3 + 67, wo.x);
+                put(kQX3 + 68, wo.y);
+#pragma unroll
+                for (int k = 0; k < 4; k++)
+                    put(kQDY + k, dy[k]);
+                s_fid[sl] = (uint16_t)g.fabric_id[p < g.n ? p : g.n - 1];
+            }
+        };
+        // An offset the compiler cannot see through, so that the decoder's
+        // weight reads stay inside the loop instead of being hoisted into
+        // registers for all chunks (they would not fit beside the tiles' sums).
+        int wofs = 0;
+        asm volatile("" : "+s"(wofs));
+        fwd_bwd_tile<FABRIC_BF16, false>(g, fabrics, n_fabrics, cfold, ffr + wofs, fbias + wofs,
+                                         bfr + wofs, targets, tile, loss_part, err, sink);
+        __syncthreads();
+
+        // ---- the chunk's weight-gradient terms ----
+#pragma unroll
+        for (int slot = 0; slot < kFMaxSlots; slot++) {
+            const int t = slot * kFWaves + w;
+            if (t >= n_tiles)
+                continue;
+            int jn = 0;
+            while (jn + 1 < jobs.n_jobs && t >= jobs.first_tile[jn + 1])
+                jn++;
+            const WgJob16 jb = jobs.j[jn];
+            const int nbk = (jb.NC + 15) >> 4;
+            const int local = t - jobs.first_tile[jn];
+            const int mb = local / nbk, nb = local % nbk;
+            const int row = 16 * mb + c, colj = 16 * nb + c;
+            const __bf16 *arow = row < jb.MA ? region + (jb.A + row) * kFStride : nullptr;
+            const bool bplane = jb.B >= 0 && colj < jb.NB;
+            const __bf16 *brow = region + (bplane ? jb.B + colj : 0) * kFStride;
+            const short bconst = jb.B >= 0 && colj == jb.NB && jb.bias ? (short)0x3F80 : (short)0;
+#pragma unroll
+            for (int ks = 0; ks < kFChunk / 16; ks++) {
+                const int k0 = 16 * ks + 4 * q;
+                s16x4 a = {0, 0, 0, 0}, b;
+                if (arow)
+                    a = *(const s16x4 *)(arow + k0);
+                if (jb.B < 0) {
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+                        b[j] = (int)s_fid[k0 + j] - jb.f0 == colj && colj < jb.NC ? (short)0x3F80
+                                                                                  : (short)0;
+                } else if (bplane) {
+                    b = *(const s16x4 *)(brow + k0);
+                } else {
+                    b = s16x4{bconst, bconst, bconst, bconst};
+                }
+                acc[slot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[slot], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- the block's partial sums: register i of a tile holds row 4 q + i, column c ----
+#pragma unroll
+    for (int slot = 0; slot < kFMaxSlots; slot++) {
+        const int t = slot * kFWaves + w;
+        if (t >= n_tiles)
+            continue;
+        int jn = 0;
+        while (jn + 1 < jobs.n_jobs && t >= jobs.first_tile[jn + 1])
+            jn++;
+        const WgJob16 jb = jobs.j[jn];
+        const int nbk = (jb.NC + 15) >> 4;
+        const int local = t - jobs.first_tile[jn];
+        const int mb = local / nbk, nb = local % nbk;
+        float *out = partial + ((size_t)jn * gridDim.x + blockIdx.x) * (kWgMaxM * kWgMaxC);
+        const int colj = 16 * nb + c;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int m = 16 * mb + 4 * q + i;
+            if (m < jb.MA && colj < jb.NC)
+                out[m * kWgMaxC + colj] = acc[slot][i];
+        }
+    }
+}
+
 // out_j[m][c] = sum over the blocks' partials in block order (eight
 // interleaved running sums, combined in a fixed order), scattered to
 // dst[m * ldw + c] (c < NW), bias[m] (c == NW with a bias), or with
@@ -860,9 +1051,9 @@ hipError_t ensure_acts(TrainScratch &s, int64_t n)
     return e;
 }
 
-hipError_t ensure_partials(TrainScratch &s, int n_jobs)
+hipError_t ensure_partials(TrainScratch &s, int n_jobs, int nblk = kWgBlocks)
 {
-    const size_t need = (size_t)n_jobs * kWgBlocks * kWgMaxM * kWgMaxC;
+    const size_t need = (size_t)n_jobs * nblk * kWgMaxM * kWgMaxC;
     if (s.partial_floats >= need)
         return hipSuccess;
     hipError_t e = grow(&s.partials, need);
@@ -940,6 +1131,77 @@ hipError_t decoder_weight_grads_bf16(TrainScratch &s, const fabric_gbuffer &g, i
                        (const __bf16 *)s.acts, per_block, s.partials);
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((kWgMaxM * kWgMaxC + 255) / 256, nj), dim3(256), 0,
                        stream, (const float *)s.partials, dests, kWgBlocks);
+    return hipGetLastError();
+}
+
+// Output tiles of the fused launch's weight gradients: W1 (4 x 3), W2 and W3
+// (4 x 5 each), W4 (1 x 5), and 4 per 16 fabrics of dL/dc_f.
+int fused_tile_count(int n_fabrics)
+{
+    int tiles = 4 * 3 + 4 * 5 + 4 * 5 + 1 * 5;
+    for (int f0 = 0; f0 < n_fabrics; f0 += 64) {
+        const int NC = n_fabrics - f0 < 64 ? n_fabrics - f0 : 64;
+        tiles += 4 * ((NC + 15) / 16);
+    }
+    return tiles;
+}
+bool fused_fits(int n_fabrics) { return fused_tile_count(n_fabrics) <= kFMaxSlots * kFWaves; }
+
+// BF16 training's forward, loss, backward and decoder weight gradients in
+// one persistent launch (train_bf16_fused_kernel), then the partials' sums:
+// writes the loss parts, every decoder tensor of grad_dec except W1's latent
+// columns, and dcf.
+hipError_t train_bf16_fused(TrainScratch &s, const fabric_gbuffer &g, const DevFabric *fabrics,
+                            int n_fabrics, const float *targets, unsigned long long *err,
+                            float *grad_dec, hipStream_t stream)
+{
+    FusedJobs jobs{};
+    WgDests dests{};
+    int nj = 0, tiles = 0;
+    auto add = [&](int A, int MA, int B, int NB, int bias, int f0, int NC, float *dst, int ldw,
+                   float *bsum, int transposed) {
+        jobs.j[nj] = WgJob16{A, B, B < 0 ? g.fabric_id : nullptr, MA, NB, bias, f0, NC};
+        dests.d[nj] = WgDest{dst, bsum, MA, NC, B < 0 ? NC : NB, ldw, transposed};
+        jobs.first_tile[nj] = tiles;
+        tiles += ((MA + 15) / 16) * ((NC + 15) / 16);
+        nj++;
+    };
+    add(kQDH1, 64, kQS, 40, 1, 0, 41, grad_dec + kOffW1 + kLatent, 72, grad_dec + kOffB1, 0);
+    add(kQDH2, 64, kQH1, 64, 1, 0, 65, grad_dec + kOffW2, 64, grad_dec + kOffB2, 0);
+    add(kQDH3, 64, kQX3, 69, 1, 0, 70, grad_dec + kOffW3, 69, grad_dec + kOffB3, 0);
+    add(kQDY, 4, kQH3, 64, 1, 0, 65, grad_dec + kOffW4, 64, grad_dec + kOffB4, 0);
+    for (int f0 = 0; f0 < n_fabrics; f0 += 64) {
+        const int NC = n_fabrics - f0 < 64 ? n_fabrics - f0 : 64;
+        add(kQDH1, 64, -1, 0, 0, f0, NC, s.dcf + f0 * 64, 64, nullptr, 1);
+    }
+    jobs.first_tile[nj] = tiles;
+    jobs.n_jobs = nj;
+    if (tiles != fused_tile_count(n_fabrics) || tiles > kFMaxSlots * kFWaves)
+        return hipErrorInvalidValue;
+    hipError_t e;
+    if (s.n_cu == 0) {
+        int dev = 0;
+        if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+        if ((e = hipDeviceGetAttribute(&s.n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+            return e;
+        if ((e = hipFuncSetAttribute((const void *)train_bf16_fused_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFLds)) != hipSuccess)
+            return e;
+    }
+    const int64_t n_chunks = (g.n + kFChunk - 1) / kFChunk;
+    const int grid = (int)(n_chunks < s.n_cu ? n_chunks : s.n_cu);   // one block per CU
+    if ((e = ensure_partials(s, nj, grid)) != hipSuccess)
+        return e;
+    using M = Mfma<FABRIC_BF16>;
+    using S = DecShape<M::KPL>;
+    const auto *ffr = (const bf16x8 *)s.fwd_image;
+    const auto *fb = (const f32x4 *)((const char *)s.fwd_image + (size_t)S::NFRAG * 64 * sizeof(bf16x8));
+    hipLaunchKernelGGL(train_bf16_fused_kernel, dim3(grid), dim3(64 * kFWaves), kFLds, stream, g,
+                       fabrics, n_fabrics, (const float *)s.cfold, ffr, fb,
+                       (const bf16x8 *)s.bwd_image, targets, s.loss_part, err, jobs, n_chunks,
+                       s.partials);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((kWgMaxM * kWgMaxC + 255) / 256, nj), dim3(256), 0,
+                       stream, (const float *)s.partials, dests, grid);
     return hipGetLastError();
 }
 
@@ -1124,9 +1386,13 @@ hipError_t loss_and_grad(TrainScratch &s, const TrainArgs &a, hipStream_t stream
     if (n > 0) {
         // Faults of a generated-target batch were counted by the filter.
         unsigned long long *err = a.targets ? a.err : nullptr;
+        // BF16 with at most 16 fabrics: one fused launch, the activations kept
+        // on chip; otherwise the blocked BF16 planes through HBM.
+        const bool fused = cfg.prec == FABRIC_BF16 && fused_fits(a.n_fabrics);
         e = cfg.prec == FABRIC_FP32
                 ? launch_fwd_bwd<FABRIC_FP32, false>(s, g, a.fabrics, a.n_fabrics, s.cfold, targets, err, stream)
-                : launch_fwd_bwd<FABRIC_BF16, false>(s, g, a.fabrics, a.n_fabrics, s.cfold, targets, err, stream);
+            : fused ? train_bf16_fused(s, g, a.fabrics, a.n_fabrics, targets, err, s.grad, stream)
+                    : launch_fwd_bwd<FABRIC_BF16, false>(s, g, a.fabrics, a.n_fabrics, s.cfold, targets, err, stream);
         if (e != hipSuccess) return e;
         const int64_t parts = (n + 15) / 16;
         if (parts <= 4096) {
@@ -1142,9 +1408,11 @@ hipError_t loss_and_grad(TrainScratch &s, const TrainArgs &a, hipStream_t stream
             hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, stream,
                                (const float *)stage, nb, 1.0f / (float)n, s.loss);
         }
-        e = cfg.prec == FABRIC_FP32 ? decoder_weight_grads(s, g, a.n_fabrics, s.grad, stream)
-                                    : decoder_weight_grads_bf16(s, g, a.n_fabrics, s.grad, stream);
-        if (e != hipSuccess) return e;
+        if (!fused) {
+            e = cfg.prec == FABRIC_FP32 ? decoder_weight_grads(s, g, a.n_fabrics, s.grad, stream)
+                                        : decoder_weight_grads_bf16(s, g, a.n_fabrics, s.grad, stream);
+            if (e != hipSuccess) return e;
+        }
     } else {
         if ((e = hipMemsetAsync(s.loss, 0, sizeof(float), stream)) != hipSuccess) return e;
         if ((e = hipMemsetAsync(s.grad, 0, kNDec * sizeof(float), stream)) != hipSuccess) return e;

@@ -23,6 +23,7 @@ struct TrainScratch {
     void *fwd_image = nullptr;  // packed forward decoder
     void *bwd_image = nullptr;  // packed transposed decoder
     float *loss = nullptr;      // [1] loss of the last step
+    int n_cu = 0;               // compute units of the device (0: not yet queried)
     // generated batch and targets
     int64_t batch_cap = 0;
     uint16_t *b_fid = nullptr;

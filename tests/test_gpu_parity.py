@@ -339,6 +339,41 @@ def test_loss_grad_bf16_matches_oracle(fab, pkg, orc, torch):
     assert max(errs) < 4e-2
 
 
+@pytest.mark.parametrize("n_fab", [16, 20, 70])
+def test_loss_grad_many_fabrics(pkg, orc, torch, n_fab):
+    """Training gradients with more fabrics: 16 (the most whose dL/dc_f tiles
+    the fused BF16 launch holds), 20 (BF16 through the blocked planes in
+    HBM) and 70 (two one-hot jobs); FP32 at 1e-4 per tensor, BF16 at the
+    bars of test_loss_grad_bf16_matches_oracle."""
+    mats = fi.materials_for(n_fab, 700 + n_fab)
+    g = fi.make_gbuffer(50, 41, n_fab, seed=701)
+    g.fabric_id[:] = np.random.default_rng(702).integers(0, n_fab, g.n).astype(np.uint16)
+    tg = fi.random_targets(g.n, 703)
+    params = params_for(704)
+    f = pkg.Fabric(0, seed=705)
+    try:
+        f.set_params(params)
+        f.encode(mats)
+        oloss, ograd, _ = orc.loss_grad(params, mats, g, tg)
+        for prec, tensor_bar, whole_bar, loss_rel in ((pkg.FABRIC_FP32, 1e-4, 1e-4, 1e-5),
+                                                      (pkg.FABRIC_BF16, 4e-2, 2e-2, 1e-2)):
+            grad = torch.empty(fi.N_PARAMS, device="cuda")
+            loss = pkg.fabric_loss_grad(f.ctx, dev(pkg, g), torch.from_numpy(tg).cuda(),
+                                        {"prec": prec}, grad)
+            gg = grad.cpu().numpy()
+            errs, off = [], 0
+            for o, i in fi.DECODER_SHAPES + fi.ENCODER_SHAPES:
+                for size in (o * i, o):
+                    errs.append(rel_norm_err(gg[off:off + size], ograd[off:off + size]))
+                    off += size
+            print(n_fab, "fabrics, prec", prec, "loss", loss, oloss, "worst tensor %.2e" % max(errs))
+            assert loss == pytest.approx(oloss, rel=loss_rel)
+            assert max(errs) < tensor_bar
+            assert rel_norm_err(gg, ograd) < whole_bar
+    finally:
+        f.close()
+
+
 def test_make_batch_matches_oracle_recipe(fab, pkg, orc, torch):
     fab.encode(fi.materials_for(8, 80))
     n = 100_003
