@@ -39,8 +39,51 @@ __device__ inline float u24_mid(uint64_t z)
 // integrand by up to 1e-3 relative.  The hardware approximations (v_sin,
 // v_cos with their absolute error) are therefore not used on this path.
 __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-// tan(x) for |x| <= 1.5 rad (cos x >= 0.07).
-__device__ inline float tan_small(float x) { return tanf(x); }
+
+// The two functions below replace the general library routines on the
+// bounded arguments this model takes: polynomials in s = x^2 fitted to the
+// functions on those intervals (least squares iteratively reweighted towards
+// the minimax fit, coefficients rounded to float32; fit_model_polys.py
+// beside this file derives them).  In float32 arithmetic they stay within 2
+// ulp (sin pi x, cos pi x on |x| <= 1/4) and 4 ulp (tan x on |x| <= 1.5) of
+// the exact functions, without the library's argument reduction and its
+// branches.
+
+// sin(pi x) = x S(s) and cos(pi x) = 1 + s C(s) for |x| <= 1/4.
+__device__ inline void sincospi_quarter(float x, float *sn, float *cs)
+{
+    const float s = x * x;
+    float p = fmaf(s, -0.5890786647796631f, 2.549767255783081f);
+    p = fmaf(p, s, -5.167707920074463f);
+    p = fmaf(p, s, 3.1415927410125732f);
+    float c = fmaf(s, 0.23212634027004242f, -1.3351378440856934f);
+    c = fmaf(c, s, 4.05871057510376f);
+    c = fmaf(c, s, -4.934802055358887f);
+    *sn = x * p;
+    *cs = fmaf(c, s, 1.0f);
+}
+
+// tan(x) for |x| <= 1.5 rad (cos x >= 0.07): tan x = x + x s Q(s) / d with
+// the pole factored out, d = (pi/2)^2 - s (one rounding of the exact x^2
+// against the constant's float32 head, then its tail), and Q fitted to
+// ((pi/2)^2 - s) (tan(x)/x - 1) / s; the quotient is the rounded product by
+// the reciprocal with one correction step.
+__device__ inline float tan_small(float x)
+{
+    constexpr float kHalfPiSqHi = 2.4674010276794434f;     // (pi/2)^2 = hi + lo
+    constexpr float kHalfPiSqLo = 7.259289702687965e-08f;
+    const float s = x * x;
+    float p = fmaf(s, -4.3158843254786916e-07f, -7.24434403309715e-06f);
+    p = fmaf(p, s, -0.0001721783191896975f);
+    p = fmaf(p, s, -0.004346469882875681f);
+    p = fmaf(p, s, 0.822467029094696f);
+    const float d = fmaf(-x, x, kHalfPiSqHi) + kHalfPiSqLo;
+    const float num = (x * s) * p;
+    const float r = rcp(d);
+    float q = num * r;
+    q = fmaf(fmaf(-d, q, num), r, q);
+    return q + x;
+}
 
 // Shirley-Chiu concentric mapping of [0,1)^2 onto the unit disk; the angle
 // is pi/4 (b/a) or pi/2 - pi/4 (a/b): sin and cos of pi (q/4), q the
@@ -54,7 +97,7 @@ __device__ inline float2 concentric_disk(float x, float y)
     const float rad = horiz ? a : b;
     const float q = (horiz ? b : a) / rad;
     float sn, cs;
-    sincospif(0.25f * q, &sn, &cs);
+    sincospi_quarter(0.25f * q, &sn, &cs);
     return horiz ? make_float2(rad * cs, rad * sn) : make_float2(rad * sn, rad * cs);
 }
 
