@@ -39,6 +39,13 @@ __device__ inline float u24_mid(uint64_t z)
 // integrand by up to 1e-3 relative.  The hardware approximations (v_sin,
 // v_cos with their absolute error) are therefore not used on this path.
 __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// The hardware reciprocal square root (1 ulp) for arguments >= 1, where the
+// library's rsqrtf adds nothing but its rescaling of denormal inputs.
+__device__ inline float rsqrt_ge1(float x) { return __builtin_amdgcn_rsqf(x); }
+// The hardware square root (1 ulp) of a shading term 1 - a b with float32
+// a, b in [0, 1] (0 or at least 2^-48, never denormal), in place of the
+// library's correctly rounded sqrtf with its rescaling and correction steps.
+__device__ inline float sqrt_term(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // The two functions below replace the general library routines on the
 // bounded arguments this model takes: polynomials in s = x^2 fitted to the
@@ -256,11 +263,11 @@ __device__ inline SampleVal eval_surface_point(const DevFabric &f, float us, flo
     // Height-field normal m = (slopes, 1); n_p = m / |m|, n_p.z = 1/|m|.
     float mx = is_warp ? mb : ma, my = is_warp ? ma : mb;
     float len2 = 1.0f + ma * ma + mb * mb;
-    float rl = rsqrtf(len2);
+    float rl = rsqrt_ge1(len2);
     float jac = len2 * rl;                       // 1 / <n_s . n_p>
     float3 n = make_float3(mx * rl, my * rl, rl);
     // Yarn axis t0 (tilted with the float) and its twist about n_p.
-    float re = rsqrtf(1.0f + ma * ma);
+    float re = rsqrt_ge1(1.0f + ma * ma);
     float3 t0 = is_warp ? make_float3(0.0f, re, -ma * re) : make_float3(re, 0.0f, -ma * re);
     float3 bx = make_float3(n.y * t0.z - n.z * t0.y, n.z * t0.x - n.x * t0.z,
                             n.x * t0.y - n.y * t0.x);
@@ -291,8 +298,8 @@ __device__ inline SampleVal eval_surface_point(const DevFabric &f, float us, flo
     float ot = wo.x * tp.x + wo.y * tp.y + wo.z * tp.z;
     float q = 1.0f + f.ia2m1[y] * ht * ht;
     float D = f.inv_pi_alpha[y] * rcp(q * q);
-    float sig_i = sqrtf(fmaxf(1.0f - f.alpha2m1[y] * it * it, 0.0f));
-    float sig_o = sqrtf(fmaxf(1.0f - f.alpha2m1[y] * ot * ot, 0.0f));
+    float sig_i = sqrt_term(fmaxf(1.0f - f.alpha2m1[y] * it * it, 0.0f));
+    float sig_o = sqrt_term(fmaxf(1.0f - f.alpha2m1[y] * ot * ot, 0.0f));
     const float lam_i = sig_i * rcp(aci), lam_o = sig_o * rcp(co);
     float G;
     if (!transmit) {
