@@ -2,7 +2,7 @@
 // the weave as a 16x16 one-hot grid plus 12 normalised yarn scalars ->
 // e1 = relu(E1 x + c1) -> residual block e2 = relu(e1 + E3 relu(E2 e1 + c2) + c3)
 // -> z = E4 e2 + c4 (a latent of 32 for the config-size network, 64 for the
-// paper-size one).  One 256-thread block per fabric; each dense layer runs
+// paper-size one).  One 16-wave block per fabric; each dense layer runs
 // eight outputs per wavefront at a time with coalesced row reads and a fixed
 // butterfly reduction.  It runs once per material edit, not per frame.
 #include "enc_dense.hpp"
@@ -13,7 +13,7 @@ namespace fab {
 namespace {
 
 template <int LAT>
-__global__ __launch_bounds__(256) void encoder_forward_kernel(const float *__restrict__ Q,
+__global__ __launch_bounds__(kEncThreads) void encoder_forward_kernel(const float *__restrict__ Q,
                                                               const float *__restrict__ inputs,
                                                               float *__restrict__ latents)
 {
@@ -79,10 +79,10 @@ hipError_t launch_encoder_forward_n(const float *enc_params, const float *enc_in
     if (n_fabrics <= 0)
         return hipSuccess;
     if (lat == kLatent)
-        hipLaunchKernelGGL(encoder_forward_kernel<kLatent>, dim3(n_fabrics), dim3(256), 0, stream,
+        hipLaunchKernelGGL(encoder_forward_kernel<kLatent>, dim3(n_fabrics), dim3(kEncThreads), 0, stream,
                            enc_params, enc_inputs, latents);
     else if (lat == FABRIC_PAPER_LATENT)
-        hipLaunchKernelGGL(encoder_forward_kernel<FABRIC_PAPER_LATENT>, dim3(n_fabrics), dim3(256),
+        hipLaunchKernelGGL(encoder_forward_kernel<FABRIC_PAPER_LATENT>, dim3(n_fabrics), dim3(kEncThreads),
                            0, stream, enc_params, enc_inputs, latents);
     else
         return hipErrorInvalidValue;

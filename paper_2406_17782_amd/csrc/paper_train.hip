@@ -1027,24 +1027,18 @@ __global__ __launch_bounds__(256) void paper_wgrad_reduce_kernel(PWJobs jobs, in
 
 // F1's latent columns: dWF1[o][j] = sum_f D[f][o] z_f[j]; the latents:
 // dz_f[j] = sum_o WF1[o][j] D[f][o] (D: per-fabric sums of F1's gradient).
-__global__ void paper_latent_grads_kernel(const float *__restrict__ P, const float *__restrict__ lat,
+__global__ __launch_bounds__(256) void paper_latent_grads_kernel(const float *__restrict__ P, const float *__restrict__ lat,
                                           const float *__restrict__ dsum, int n_fabrics,
                                           float *__restrict__ grad, float *__restrict__ glat)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < 64 * kPLat) {
         const int o = idx / kPLat, j = idx % kPLat;
-        float acc = 0.0f;
-        for (int f = 0; f < n_fabrics; f++)
-            acc = fmaf(dsum[f * 64 + o], lat[f * kPLat + j], acc);
-        grad[kPOffWF1 + o * kPX1 + j] = acc;
+        grad[kPOffWF1 + o * kPX1 + j] = ordered_dot(dsum + o, 64, lat + j, kPLat, n_fabrics);
     } else if (idx < 64 * kPLat + n_fabrics * kPLat) {
         const int k = idx - 64 * kPLat;
         const int f = k / kPLat, j = k % kPLat;
-        float acc = 0.0f;
-        for (int o = 0; o < 64; o++)
-            acc = fmaf(P[kPOffWF1 + o * kPX1 + j], dsum[f * 64 + o], acc);
-        glat[f * kPLat + j] = acc;
+        glat[f * kPLat + j] = ordered_dot(P + kPOffWF1 + j, kPX1, dsum + f * 64, 1, 64);
     }
 }
 
@@ -1092,10 +1086,9 @@ PWJobs make_jobs(int n_fabrics, int n_chunks, bool fused)
 constexpr int kPEncAct = enc_act_floats<kPLat>();
 static_assert(enc_param_count<kPLat>() == kPaperEncParams, "paper encoder layout");
 
-__global__ __launch_bounds__(256) void paper_encoder_backward_kernel(const float *__restrict__ Q,
-                                                                     const float *__restrict__ inputs,
-                                                                     const float *__restrict__ dz,
-                                                                     float *__restrict__ scratch)
+__global__ __launch_bounds__(kEncThreads) void paper_encoder_backward_kernel(
+    const float *__restrict__ Q, const float *__restrict__ inputs, const float *__restrict__ dz,
+    float *__restrict__ scratch)
 {
     const int f = blockIdx.x;
     encoder_backward_block<kPLat>(Q, inputs + (size_t)f * kEncIn, dz + (size_t)f * kPLat,
@@ -1242,7 +1235,7 @@ hipError_t run_paper_loss_grad(PaperTrainScratch &s, const PaperTrainArgs &a, hi
     if (a.enc_inputs) {
         // The latents' gradient through the encoder; its parameters' gradient
         // takes the latents' place after the decoder's.
-        hipLaunchKernelGGL(paper_encoder_backward_kernel, dim3(a.n_fabrics), dim3(256), 0, stream,
+        hipLaunchKernelGGL(paper_encoder_backward_kernel, dim3(a.n_fabrics), dim3(kEncThreads), 0, stream,
                            a.master + kPNDec, a.enc_inputs, (const float *)glat, s.enc_acts);
         hipLaunchKernelGGL(paper_encoder_wgrad_kernel, dim3((kPaperEncParams + 255) / 256),
                            dim3(256), 0, stream, (const float *)s.enc_acts, a.n_fabrics, glat);

@@ -885,24 +885,18 @@ __global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float *__restri
 }
 
 // dz_f = W1[:, 0:32]^T dc_f and dW1[:, 0:32] = sum_f dc_f z_f^T.
-__global__ void latent_grads_kernel(const float *__restrict__ params, const float *__restrict__ dcf,
+__global__ __launch_bounds__(256) void latent_grads_kernel(const float *__restrict__ params, const float *__restrict__ dcf,
                                     const float *__restrict__ latents, int n_fabrics,
                                     float *__restrict__ dz, float *__restrict__ dW1)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < n_fabrics * kLatent) {
         const int f = e / kLatent, k = e % kLatent;
-        float acc = 0.0f;
-        for (int o = 0; o < 64; o++)
-            acc = fmaf(params[kOffW1 + o * 72 + k], dcf[f * 64 + o], acc);
-        dz[e] = acc;
+        dz[e] = ordered_dot(params + kOffW1 + k, 72, dcf + f * 64, 1, 64);
     }
     if (e < 64 * kLatent) {
         const int o = e / kLatent, k = e % kLatent;
-        float acc = 0.0f;
-        for (int f = 0; f < n_fabrics; f++)
-            acc = fmaf(dcf[f * 64 + o], latents[f * kLatent + k], acc);
-        dW1[o * 72 + k] = acc;
+        dW1[o * 72 + k] = ordered_dot(dcf + o, 64, latents + k, kLatent, n_fabrics);
     }
 }
 
@@ -912,10 +906,9 @@ __global__ void latent_grads_kernel(const float *__restrict__ params, const floa
 // fabrics in order.
 // enc scratch per fabric: x[524] a1 a2 a3 da1 da2 da3 [128 each] dz[32]
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void encoder_backward_kernel(const float *__restrict__ Q,
-                                                               const float *__restrict__ inputs,
-                                                               const float *__restrict__ dz,
-                                                               float *__restrict__ scratch)
+__global__ __launch_bounds__(kEncThreads) void encoder_backward_kernel(
+    const float *__restrict__ Q, const float *__restrict__ inputs, const float *__restrict__ dz,
+    float *__restrict__ scratch)
 {
     const int f = blockIdx.x;
     encoder_backward_block<kLatent>(Q, inputs + (size_t)f * kEncIn, dz + (size_t)f * kLatent,
@@ -1245,7 +1238,7 @@ hipError_t decoder_weight_grads(TrainScratch &s, const fabric_gbuffer &g, int n_
 hipError_t run_encoder_backward(TrainScratch &s, const float *enc_params, const float *enc_inputs,
                                 int n_fabrics, const float *dz, float *grad_enc, hipStream_t stream)
 {
-    hipLaunchKernelGGL(encoder_backward_kernel, dim3(n_fabrics), dim3(256), 0, stream, enc_params,
+    hipLaunchKernelGGL(encoder_backward_kernel, dim3(n_fabrics), dim3(kEncThreads), 0, stream, enc_params,
                        enc_inputs, dz, s.enc_acts);
     hipLaunchKernelGGL(encoder_wgrad_kernel, dim3((kNEnc + 255) / 256), dim3(256), 0, stream,
                        (const float *)s.enc_acts, n_fabrics, grad_enc);
