@@ -1004,6 +1004,16 @@ __global__ __launch_bounds__(256) void paper_wgrad_reduce_kernel(PWJobs jobs, in
     // combined in a fixed order.
     KahanSum part[8];
     int c = 0;
+    // 32 loads in flight, added in the same order as the loop below
+    for (; c + 32 <= n_chunks; c += 32) {
+        float v[32];
+#pragma unroll
+        for (int k = 0; k < 32; k++)
+            v[k] = src[(int64_t)(c + k) * E];
+#pragma unroll
+        for (int k = 0; k < 32; k++)
+            part[k & 7].add(v[k]);
+    }
     for (; c + 8 <= n_chunks; c += 8) {
 #pragma unroll
         for (int k = 0; k < 8; k++)

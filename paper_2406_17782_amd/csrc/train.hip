@@ -167,18 +167,26 @@ __global__ void pack_backward_kernel(const float *__restrict__ params,
 // Fused forward, loss and activation backward: one 16-sample tile per wave.
 // GIVEN_DY: dy comes from the caller (dL/dy4 [4][n]); otherwise from the loss
 // of Eq. (9)-(11) against targets [4][n] (C_warp, C_weft, S_warp, S_weft).
+// max(x, 0) as the integer maximum of the bit pattern (a negative float is a
+// negative integer): one instruction, where fmaxf on an MFMA result also
+// quiets a signalling NaN first.
+__device__ inline float relu_bits(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 // ---------------------------------------------------------------------------
 // The forward, loss and activation backward of 16-sample tile `tile`, one
 // wave: the per-sample results go to sink(p, valid, live, s1, a1, a2, a3,
 // d1, d2, d3, dy, wi, wo) (p past the batch: valid = false, the values of a
 // clamped sample with no loss and zero gradients).
-template <int P, bool GIVEN_DY, typename Sink>
+// With LDSW, the forward's L2 and L3 fragments and all backward fragments
+// come from `lw` (a copy in LDS: the L2 and L3 fragments, then the backward
+// ones, [fragment][lane]) instead of the packed images in global memory.
+template <int P, bool GIVEN_DY, typename Sink, bool LDSW = false>
 __device__ inline void fwd_bwd_tile(
     const fabric_gbuffer &g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ ffr,
     const f32x4 *__restrict__ fbias, const typename Mfma<P>::Frag *__restrict__ bfr,
     const float *__restrict__ tgt_or_dy, int64_t tile, float *__restrict__ loss_part,
-    unsigned long long *err, Sink &&sink)
+    unsigned long long *err, Sink &&sink, const typename Mfma<P>::Frag *lw = nullptr)
 {
     using T = Tile<P>;
     using M = typename T::M;
@@ -219,7 +227,12 @@ __device__ inline void fwd_bwd_tile(
         cf[mb] = *(const f32x4 *)(cfold + fid * 64 + 16 * mb + 4 * grp);
     float ang0, ang1;
     angular_slots(grp, wi, wo, &ang0, &ang1);
-    auto getA = [&](int q) { return ffr[q * 64 + lane]; };
+    using DS = DecShape<T::KPL>;
+    auto getA = [&](int q) {
+        if (LDSW && q >= DS::FRAG_L2 && q < DS::FRAG_L4)
+            return lw[(q - DS::FRAG_L2) * 64 + lane];
+        return ffr[q * 64 + lane];
+    };
     auto getBias = [&](int q) { return fbias[q * 64 + lane]; };
     f32x4 a1[4], a2[4], a3[4], y;
     T::forward(getA, getBias, cf, s1, ang0, ang1, a1, a2, a3, y);
@@ -271,7 +284,11 @@ __device__ inline void fwd_bwd_tile(
             val = d == c ? dyp[c] : val;
         M::set(Bdy[0], j, val);
     }
-    auto getW = [&](int q) { return bfr[q * 64 + lane]; };
+    auto getW = [&](int q) {
+        if (LDSW)
+            return lw[(DS::FRAG_L4 - DS::FRAG_L2 + q) * 64 + lane];
+        return bfr[q * 64 + lane];
+    };
     f32x4 d3[4], d2[4], d1[4];
 #pragma unroll
     for (int mb = 0; mb < 4; mb++)
@@ -349,9 +366,9 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(
                 const int o = 16 * mb + 4 * grp;
 #pragma unroll
                 for (int i = 0; i < 4; i++) {
-                    put(kQH1 + o + i, fmaxf(a1[mb][i], 0.0f));
-                    put(kQX3 + o + i, fmaxf(a2[mb][i], 0.0f));
-                    put(kQH3 + o + i, fmaxf(a3[mb][i], 0.0f));
+                    put(kQH1 + o + i, relu_bits(a1[mb][i]));
+                    put(kQX3 + o + i, relu_bits(a2[mb][i]));
+                    put(kQH3 + o + i, relu_bits(a3[mb][i]));
                     put(kQDH1 + o + i, d1[mb][i] * keep);
                     put(kQDH2 + o + i, d2[mb][i] * keep);
                     put(kQDH3 + o + i, d3[mb][i] * keep);
@@ -380,9 +397,9 @@ __global__ __launch_bounds__(256) void fwd_bwd_kernel(
             f32x4 h1, h2, h3;
 #pragma unroll
             for (int i = 0; i < 4; i++) {
-                h1[i] = fmaxf(a1[mb][i], 0.0f);
-                h2[i] = fmaxf(a2[mb][i], 0.0f);
-                h3[i] = fmaxf(a3[mb][i], 0.0f);
+                h1[i] = relu_bits(a1[mb][i]);
+                h2[i] = relu_bits(a2[mb][i]);
+                h3[i] = relu_bits(a3[mb][i]);
             }
             *(f32x4 *)(ap.H1 + p * kH1 + o) = h1;
             *(f32x4 *)(ap.X3 + p * kX3 + o) = h2;
@@ -703,7 +720,13 @@ constexpr int kFWaves = 8;
 constexpr int kFChunk = 16 * kFWaves;        // samples per chunk
 constexpr int kFStride = kFChunk + 8;        // LDS row of a plane (BF16 values)
 constexpr int kFMaxSlots = 8;                // output tiles per wave
-constexpr size_t kFLds = (size_t)kQPlanes * kFStride * 2 + (size_t)kFChunk * 2;
+constexpr int kFMaxTiles = kFMaxSlots * kFWaves;
+constexpr size_t kFTileOfs = (size_t)kQPlanes * kFStride * 2 + (size_t)kFChunk * 2;
+constexpr size_t kFConstOfs = kFTileOfs + (size_t)kFMaxTiles * 16;
+constexpr size_t kFWOfs = kFConstOfs + (size_t)2 * kFStride * 2;
+// the L2, L3 and backward fragments of the decoder image, [fragment][lane]
+constexpr int kFWFrags = DecShape<8>::FRAG_L4 - DecShape<8>::FRAG_L2 + BwdShape<8>::NFRAG;
+constexpr size_t kFLds = kFWOfs + (size_t)kFWFrags * 64 * 16;
 static_assert(kFLds <= 160 * 1024, "the region fits in a CU's LDS");
 
 struct FusedJobs {
@@ -713,6 +736,34 @@ struct FusedJobs {
 };
 
 typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+// Output tile t of the weight gradients, in the terms of the lane (q, c)
+// that accumulates rows 4q.. of column c: x = first delta plane of its rows,
+// y = rows present, z = first input plane of its columns (one-hot: the fabric
+// id of column 0), w = columns present (bits 0-7), one-hot (bit 8) and the
+// column carrying the bias constant (bits 9-13; 31: none).  Built once per
+// block from the job table, so that the chunks' loops read one LDS word per
+// tile instead of searching the table.
+__device__ inline int4 fused_tile_desc(const FusedJobs &jobs, int t)
+{
+    int jn = 0;
+    while (jn + 1 < jobs.n_jobs && t >= jobs.first_tile[jn + 1])
+        jn++;
+    const WgJob16 jb = jobs.j[jn];
+    const int nbk = (jb.NC + 15) >> 4;
+    const int local = t - jobs.first_tile[jn];
+    const int mb = local / nbk, nb = local % nbk;
+    auto clamp16 = [](int v) { return v < 0 ? 0 : (v > 16 ? 16 : v); };
+    const bool onehot = jb.B < 0;
+    const int bias_col = !onehot && jb.bias ? jb.NB - 16 * nb : -1;
+    int4 d;
+    d.x = jb.A + 16 * mb;
+    d.y = clamp16(jb.MA - 16 * mb);
+    d.z = onehot ? jb.f0 + 16 * nb : jb.B + 16 * nb;
+    d.w = clamp16(onehot ? jb.NC - 16 * nb : jb.NB - 16 * nb) | (onehot ? 1 << 8 : 0) |
+          ((bias_col >= 0 && bias_col < 16 ? bias_col : 31) << 9);
+    return d;
+}
 
 __global__ __launch_bounds__(64 * kFWaves) void train_bf16_fused_kernel(
     fabric_gbuffer g, const DevFabric *__restrict__ fabrics, int n_fabrics,
@@ -725,9 +776,26 @@ __global__ __launch_bounds__(64 * kFWaves) void train_bf16_fused_kernel(
     extern __shared__ __align__(16) unsigned char f_smem[];
     __bf16 *region = (__bf16 *)f_smem;
     uint16_t *s_fid = (uint16_t *)(f_smem + (size_t)kQPlanes * kFStride * 2);
+    int4 *s_tile = (int4 *)(f_smem + kFTileOfs);
+    // a row of zeros and a row of ones (BF16 1.0): the operand rows of a
+    // tile's absent rows and columns and of its bias column
+    __bf16 *zero_row = (__bf16 *)(f_smem + kFConstOfs), *one_row = zero_row + kFStride;
     const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n_tiles = jobs.first_tile[jobs.n_jobs];
+    if ((int)threadIdx.x < n_tiles)
+        s_tile[threadIdx.x] = fused_tile_desc(jobs, threadIdx.x);
+    for (int k = threadIdx.x; k < kFStride; k += blockDim.x) {
+        zero_row[k] = (__bf16)0.0f;
+        one_row[k] = (__bf16)1.0f;
+    }
+    bf16x8 *s_w = (bf16x8 *)(f_smem + kFWOfs);
+    {
+        constexpr int kFwd = (DecShape<8>::FRAG_L4 - DecShape<8>::FRAG_L2) * 64;
+        for (int k = threadIdx.x; k < kFWFrags * 64; k += blockDim.x)
+            s_w[k] = k < kFwd ? ffr[DecShape<8>::FRAG_L2 * 64 + k] : bfr[k - kFwd];
+    }
+    __syncthreads();
 
     f32x4 acc[kFMaxSlots];
 #pragma unroll
@@ -741,8 +809,10 @@ __global__ __launch_bounds__(64 * kFWaves) void train_bf16_fused_kernel(
                         const f32x4 (&a1)[4], const f32x4 (&a2)[4], const f32x4 (&a3)[4],
                         const f32x4 (&d1)[4], const f32x4 (&d2)[4], const f32x4 (&d3)[4],
                         const float (&dy)[4], float3 wi, float3 wo) {
+            // A sample without a loss term (past the batch or faulted) has
+            // dy = 0, so its activation gradients are exact zeros already.
             (void)valid;
-            const float keep = live ? 1.0f : 0.0f;
+            (void)live;
             const int sl = 16 * w + c;
             auto put = [&](int plane, float x) { region[plane * kFStride + sl] = (__bf16)x; };
 #pragma unroll
@@ -753,12 +823,12 @@ __global__ __launch_bounds__(64 * kFWaves) void train_bf16_fused_kernel(
                 const int o = 16 * mb + 4 * q;
 #pragma unroll
                 for (int i = 0; i < 4; i++) {
-                    put(kQH1 + o + i, fmaxf(a1[mb][i], 0.0f));
-                    put(kQX3 + o + i, fmaxf(a2[mb][i], 0.0f));
-                    put(kQH3 + o + i, fmaxf(a3[mb][i], 0.0f));
-                    put(kQDH1 + o + i, d1[mb][i] * keep);
-                    put(kQDH2 + o + i, d2[mb][i] * keep);
-                    put(kQDH3 + o + i, d3[mb][i] * keep);
+                    put(kQH1 + o + i, relu_bits(a1[mb][i]));
+                    put(kQX3 + o + i, relu_bits(a2[mb][i]));
+                    put(kQH3 + o + i, relu_bits(a3[mb][i]));
+                    put(kQDH1 + o + i, d1[mb][i]);
+                    put(kQDH2 + o + i, d2[mb][i]);
+                    put(kQDH3 + o + i, d3[mb][i]);
                 }
             }
             if (q == 0) {
@@ -778,8 +848,9 @@ __global__ __launch_bounds__(64 * kFWaves) void train_bf16_fused_kernel(
         // registers for all chunks (they would not fit beside the tiles' sums).
         int wofs = 0;
         asm volatile("" : "+s"(wofs));
-        fwd_bwd_tile<FABRIC_BF16, false>(g, fabrics, n_fabrics, cfold, ffr + wofs, fbias + wofs,
-                                         bfr + wofs, targets, tile, loss_part, err, sink);
+        fwd_bwd_tile<FABRIC_BF16, false, decltype(sink) &, true>(
+            g, fabrics, n_fabrics, cfold, ffr + wofs, fbias + wofs, bfr + wofs, targets, tile,
+            loss_part, err, sink, s_w + wofs);
         __syncthreads();
 
         // ---- the chunk's weight-gradient terms ----
@@ -788,35 +859,35 @@ __global__ __launch_bounds__(64 * kFWaves) void train_bf16_fused_kernel(
             const int t = slot * kFWaves + w;
             if (t >= n_tiles)
                 continue;
-            int jn = 0;
-            while (jn + 1 < jobs.n_jobs && t >= jobs.first_tile[jn + 1])
-                jn++;
-            const WgJob16 jb = jobs.j[jn];
-            const int nbk = (jb.NC + 15) >> 4;
-            const int local = t - jobs.first_tile[jn];
-            const int mb = local / nbk, nb = local % nbk;
-            const int row = 16 * mb + c, colj = 16 * nb + c;
-            const __bf16 *arow = row < jb.MA ? region + (jb.A + row) * kFStride : nullptr;
-            const bool bplane = jb.B >= 0 && colj < jb.NB;
-            const __bf16 *brow = region + (bplane ? jb.B + colj : 0) * kFStride;
-            const short bconst = jb.B >= 0 && colj == jb.NB && jb.bias ? (short)0x3F80 : (short)0;
+            const int4 dv = s_tile[t];
+            const int a0 = __builtin_amdgcn_readfirstlane(dv.x);
+            const int na = __builtin_amdgcn_readfirstlane(dv.y);
+            const int b0 = __builtin_amdgcn_readfirstlane(dv.z);
+            const int info = __builtin_amdgcn_readfirstlane(dv.w);
+            const int nb = info & 0xff;
+            const __bf16 *arow = c < na ? region + (a0 + c) * kFStride : zero_row;
+            if (info & (1 << 8)) {
+                // one-hot columns: fabric b0 + c
 #pragma unroll
-            for (int ks = 0; ks < kFChunk / 16; ks++) {
-                const int k0 = 16 * ks + 4 * q;
-                s16x4 a = {0, 0, 0, 0}, b;
-                if (arow)
-                    a = *(const s16x4 *)(arow + k0);
-                if (jb.B < 0) {
+                for (int ks = 0; ks < kFChunk / 16; ks++) {
+                    const int k0 = 16 * ks + 4 * q;
+                    const s16x4 a = *(const s16x4 *)(arow + k0);
+                    s16x4 b;
 #pragma unroll
                     for (int j = 0; j < 4; j++)
-                        b[j] = (int)s_fid[k0 + j] - jb.f0 == colj && colj < jb.NC ? (short)0x3F80
-                                                                                  : (short)0;
-                } else if (bplane) {
-                    b = *(const s16x4 *)(brow + k0);
-                } else {
-                    b = s16x4{bconst, bconst, bconst, bconst};
+                        b[j] = (int)s_fid[k0 + j] - b0 == c && c < nb ? (short)0x3F80 : (short)0;
+                    acc[slot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[slot], 0, 0, 0);
                 }
-                acc[slot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[slot], 0, 0, 0);
+            } else {
+                const __bf16 *brow = c < nb ? region + (b0 + c) * kFStride
+                                            : (c == ((info >> 9) & 31) ? one_row : zero_row);
+#pragma unroll
+                for (int ks = 0; ks < kFChunk / 16; ks++) {
+                    const int k0 = 16 * ks + 4 * q;
+                    const s16x4 a = *(const s16x4 *)(arow + k0);
+                    const s16x4 b = *(const s16x4 *)(brow + k0);
+                    acc[slot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[slot], 0, 0, 0);
+                }
             }
         }
         __syncthreads();
@@ -869,6 +940,16 @@ __global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float *__restri
     const float *p = partial + (size_t)blockIdx.y * nblk * (kWgMaxM * kWgMaxC) + m * kWgMaxC + c;
     float r[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     int b = 0;
+    // 32 loads in flight, added in the same order as the loop below
+    for (; b + 32 <= nblk; b += 32) {
+        float v[32];
+#pragma unroll
+        for (int k = 0; k < 32; k++)
+            v[k] = p[(size_t)(b + k) * (kWgMaxM * kWgMaxC)];
+#pragma unroll
+        for (int k = 0; k < 32; k++)
+            r[k & 7] += v[k];
+    }
     for (; b + 8 <= nblk; b += 8)
 #pragma unroll
         for (int k = 0; k < 8; k++)
