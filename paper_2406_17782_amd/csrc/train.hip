@@ -173,8 +173,37 @@ __global__ void pack_backward_kernel(const float *__restrict__ params,
 __device__ inline float relu_bits(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
 
 // ---------------------------------------------------------------------------
+// The inputs of this lane's sample of 16-sample tile `tile` (p clamped into
+// the batch): its G-buffer fields and, in lane group 0, its four targets (or
+// given dL/dy).
+struct TileSample {
+    int fid;
+    float u, v, r;
+    float3 wi, wo;
+    float t[4];
+};
+__device__ inline TileSample load_tile_sample(const fabric_gbuffer &g,
+                                              const float *__restrict__ tgt_or_dy, int64_t tile)
+{
+    const int lane = threadIdx.x & 63, grp = lane >> 4, col = lane & 15;
+    const int64_t n = g.n;
+    const int64_t p = tile * 16 + col;
+    const int64_t pc = p < n ? p : n - 1;
+    TileSample sm;
+    sm.fid = g.fabric_id[pc];
+    sm.u = g.u[pc];
+    sm.v = g.v[pc];
+    sm.r = g.radius[pc];
+    sm.wi = make_float3(g.wi_x[pc], g.wi_y[pc], g.wi_z[pc]);
+    sm.wo = make_float3(g.wo_x[pc], g.wo_y[pc], g.wo_z[pc]);
+#pragma unroll
+    for (int c = 0; c < 4; c++)
+        sm.t[c] = grp == 0 ? tgt_or_dy[c * n + pc] : 0.0f;
+    return sm;
+}
+
 // The forward, loss and activation backward of 16-sample tile `tile`, one
-// wave: the per-sample results go to sink(p, valid, live, s1, a1, a2, a3,
+// wave (`pre`: its inputs loaded ahead by the caller, else loaded here): the per-sample results go to sink(p, valid, live, s1, a1, a2, a3,
 // d1, d2, d3, dy, wi, wo) (p past the batch: valid = false, the values of a
 // clamped sample with no loss and zero gradients).
 // With LDSW, the forward's L2 and L3 fragments and all backward fragments
@@ -186,7 +215,8 @@ __device__ inline void fwd_bwd_tile(
     const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ ffr,
     const f32x4 *__restrict__ fbias, const typename Mfma<P>::Frag *__restrict__ bfr,
     const float *__restrict__ tgt_or_dy, int64_t tile, float *__restrict__ loss_part,
-    unsigned long long *err, Sink &&sink, const typename Mfma<P>::Frag *lw = nullptr)
+    unsigned long long *err, Sink &&sink, const typename Mfma<P>::Frag *lw = nullptr,
+    const TileSample *pre = nullptr)
 {
     using T = Tile<P>;
     using M = typename T::M;
@@ -198,12 +228,10 @@ __device__ inline void fwd_bwd_tile(
     const int64_t n = g.n;
     const int64_t p = tile * 16 + col;
     const bool valid = p < n;
-    const int64_t pc = valid ? p : n - 1;
-
-    int fid = g.fabric_id[pc];
-    float u = g.u[pc], v = g.v[pc], r = g.radius[pc];
-    float3 wi = make_float3(g.wi_x[pc], g.wi_y[pc], g.wi_z[pc]);
-    float3 wo = make_float3(g.wo_x[pc], g.wo_y[pc], g.wo_z[pc]);
+    const TileSample sm = pre ? *pre : load_tile_sample(g, tgt_or_dy, tile);
+    int fid = sm.fid;
+    float u = sm.u, v = sm.v, r = sm.r;
+    float3 wi = sm.wi, wo = sm.wo;
     const bool fault = pixel_fault(fid, n_fabrics, u, v, r, wi, wo);
     if (fault) {
         fid = 0;
@@ -244,14 +272,14 @@ __device__ inline void fwd_bwd_tile(
         if (GIVEN_DY) {
 #pragma unroll
             for (int c = 0; c < 4; c++)
-                dy[c] = tgt_or_dy[c * n + p];
+                dy[c] = sm.t[c];
         } else {
             const float inv_n = 1.0f / (float)n;
             // g(x) = ln(k x + 1): k = 100 for reflection, 1000 for transmission.
             const float k = wi.z < 0.0f ? 10.0f * kSpec : kSpec;
 #pragma unroll
             for (int c = 0; c < 4; c++) {
-                const float t = tgt_or_dy[c * n + p];
+                const float t = sm.t[c];
                 const float target = c < 2 ? t : log1pf(k * t);
                 const float lam = c < 2 ? 0.1f : 0.4f;                // lambda_C, lambda_S
                 const float d = y[c] - target;
@@ -802,9 +830,15 @@ __global__ __launch_bounds__(64 * kFWaves) void train_bf16_fused_kernel(
     for (int k = 0; k < kFMaxSlots; k++)
         acc[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
+    // The samples of the wave's next tile, loaded one chunk ahead (during the
+    // previous chunk's weight-gradient phase).
+    TileSample next;
+    if ((int64_t)blockIdx.x < n_chunks)
+        next = load_tile_sample(g, targets, (int64_t)blockIdx.x * kFWaves + w);
     for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
         // ---- the wave's 16 samples into the region ----
         const int64_t tile = chunk * kFWaves + w;
+        const TileSample cur = next;
         auto sink = [&](int64_t p, bool valid, bool live, const float (&s1)[T::NS1],
                         const f32x4 (&a1)[4], const f32x4 (&a2)[4], const f32x4 (&a3)[4],
                         const f32x4 (&d1)[4], const f32x4 (&d2)[4], const f32x4 (&d3)[4],
@@ -850,8 +884,10 @@ __global__ __launch_bounds__(64 * kFWaves) void train_bf16_fused_kernel(
         asm volatile("" : "+s"(wofs));
         fwd_bwd_tile<FABRIC_BF16, false, decltype(sink) &, true>(
             g, fabrics, n_fabrics, cfold, ffr + wofs, fbias + wofs, bfr + wofs, targets, tile,
-            loss_part, err, sink, s_w + wofs);
+            loss_part, err, sink, s_w + wofs, &cur);
         __syncthreads();
+        if (chunk + gridDim.x < n_chunks)
+            next = load_tile_sample(g, targets, (chunk + gridDim.x) * kFWaves + w);
 
         // ---- the chunk's weight-gradient terms ----
 #pragma unroll
