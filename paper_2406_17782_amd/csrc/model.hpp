@@ -93,16 +93,21 @@ __device__ inline float tan_small(float x)
 }
 
 // Shirley-Chiu concentric mapping of [0,1)^2 onto the unit disk; the angle
-// is pi/4 (b/a) or pi/2 - pi/4 (a/b): sin and cos of pi (q/4), q the
-// correctly rounded quotient (one division), swapped in the second case.
+// is pi/4 (b/a) or pi/2 - pi/4 (a/b): sin and cos of pi (q/4), swapped in the
+// second case.  q is the product by the hardware reciprocal of the larger
+// coordinate with one correction step from the exact residual (within an ulp
+// of the quotient, |q| <= 1; the larger coordinate is at least 2^-25 in
+// magnitude, never denormal).
 __device__ inline float2 concentric_disk(float x, float y)
 {
     float a = 2.0f * x - 1.0f, b = 2.0f * y - 1.0f;
     if (a == 0.0f && b == 0.0f)
         return make_float2(0.0f, 0.0f);
     const bool horiz = fabsf(a) > fabsf(b);
-    const float rad = horiz ? a : b;
-    const float q = (horiz ? b : a) / rad;
+    const float rad = horiz ? a : b, num = horiz ? b : a;
+    const float rr = rcp(rad);
+    float q = num * rr;
+    q = fmaf(fmaf(-rad, q, num), rr, q);
     float sn, cs;
     sincospi_quarter(0.25f * q, &sn, &cs);
     return horiz ? make_float2(rad * cs, rad * sn) : make_float2(rad * sn, rad * cs);
