@@ -734,9 +734,9 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgJobs16 jobs, int64_t 
 // the forward used it and the activation gradients, rounded to BF16 - as
 // rows of the block's LDS region ([plane][sample], the planes of kQPlanes);
 // after a barrier the waves accumulate the weight gradients of those
-// samples from the region on BF16 MFMA 16x16x16 (samples as K: lane
-// (q = l/16, c = l%16) reads samples 4q .. 4q + 3 of a 16-sample step from
-// row c of the tile's delta planes and of its input planes, one 8-byte read
+// samples from the region on BF16 MFMA 16x16x32 (samples as K: lane
+// (q = l/16, c = l%16) reads samples 8q .. 8q + 7 of a 32-sample step from
+// row c of the tile's delta planes and of its input planes, one 16-byte read
 // each), a wave owning the tiles w, w + kFWaves, ... of the step's 16x16
 // output tiles over all its chunks; a second barrier frees the region for
 // the next chunk.  The tiles' sums go to the partial layout of
@@ -763,7 +763,7 @@ struct FusedJobs {
     int n_jobs;
 };
 
-typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
 
 // Output tile t of the weight gradients, in the terms of the lane (q, c)
 // that accumulates rows 4q.. of column c: x = first delta plane of its rows,
@@ -905,24 +905,25 @@ __global__ __launch_bounds__(64 * kFWaves) void train_bf16_fused_kernel(
             if (info & (1 << 8)) {
                 // one-hot columns: fabric b0 + c
 #pragma unroll
-                for (int ks = 0; ks < kFChunk / 16; ks++) {
-                    const int k0 = 16 * ks + 4 * q;
-                    const s16x4 a = *(const s16x4 *)(arow + k0);
-                    s16x4 b;
+                for (int ks = 0; ks < kFChunk / 32; ks++) {
+                    const int k0 = 32 * ks + 8 * q;
+                    const bf16x8 a = *(const bf16x8 *)(arow + k0);
+                    s16x8 b;
 #pragma unroll
-                    for (int j = 0; j < 4; j++)
+                    for (int j = 0; j < 8; j++)
                         b[j] = (int)s_fid[k0 + j] - b0 == c && c < nb ? (short)0x3F80 : (short)0;
-                    acc[slot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[slot], 0, 0, 0);
+                    acc[slot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        a, __builtin_bit_cast(bf16x8, b), acc[slot], 0, 0, 0);
                 }
             } else {
                 const __bf16 *brow = c < nb ? region + (b0 + c) * kFStride
                                             : (c == ((info >> 9) & 31) ? one_row : zero_row);
 #pragma unroll
-                for (int ks = 0; ks < kFChunk / 16; ks++) {
-                    const int k0 = 16 * ks + 4 * q;
-                    const s16x4 a = *(const s16x4 *)(arow + k0);
-                    const s16x4 b = *(const s16x4 *)(brow + k0);
-                    acc[slot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[slot], 0, 0, 0);
+                for (int ks = 0; ks < kFChunk / 32; ks++) {
+                    const int k0 = 32 * ks + 8 * q;
+                    const bf16x8 a = *(const bf16x8 *)(arow + k0);
+                    const bf16x8 b = *(const bf16x8 *)(brow + k0);
+                    acc[slot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[slot], 0, 0, 0);
                 }
             }
         }
