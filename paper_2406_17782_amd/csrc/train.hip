@@ -954,8 +954,9 @@ __global__ __launch_bounds__(64 * kFWaves) void train_bf16_fused_kernel(
     }
 }
 
-// out_j[m][c] = sum over the blocks' partials in block order (eight
-// interleaved running sums, combined in a fixed order), scattered to
+// out_j[m][c] = sum over the blocks' partials (four consecutive ranges of
+// blocks, each summed in block order as eight interleaved running sums, all
+// combined in a fixed order), scattered to
 // dst[m * ldw + c] (c < NW), bias[m] (c == NW with a bias), or with
 // transposed = 1 to dst[c * ldw + m].
 struct WgDest {
@@ -966,34 +967,43 @@ struct WgDests {
     WgDest d[kWgMaxJobs];
 };
 
+// A block takes 64 entries; its four waves sum the partials of four
+// consecutive ranges of blocks for them (eight interleaved running sums per
+// range, 32 loads in flight), combined through LDS in a fixed order.
+constexpr int kWgRedEntries = 64;
 __global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float *__restrict__ partial,
                                                            WgDests dests, int nblk)
 {
+    __shared__ float part[4][kWgRedEntries];
     const WgDest d = dests.d[blockIdx.y];
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= d.MA * d.NC)
-        return;
-    const int m = e / d.NC, c = e % d.NC;
+    const int seg = threadIdx.x >> 6;
+    const int e = blockIdx.x * kWgRedEntries + (threadIdx.x & 63);
+    const bool live = e < d.MA * d.NC;
+    const int m = live ? e / d.NC : 0, c = live ? e % d.NC : 0;
+    const int per = (nblk + 3) >> 2;
+    const int b0 = seg * per, b1 = min(nblk, b0 + per);
     const float *p = partial + (size_t)blockIdx.y * nblk * (kWgMaxM * kWgMaxC) + m * kWgMaxC + c;
     float r[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    int b = 0;
-    // 32 loads in flight, added in the same order as the loop below
-    for (; b + 32 <= nblk; b += 32) {
-        float v[32];
+    if (live) {
+        int b = b0;
+        for (; b + 32 <= b1; b += 32) {
+            float v[32];
 #pragma unroll
-        for (int k = 0; k < 32; k++)
-            v[k] = p[(size_t)(b + k) * (kWgMaxM * kWgMaxC)];
+            for (int k = 0; k < 32; k++)
+                v[k] = p[(size_t)(b + k) * (kWgMaxM * kWgMaxC)];
 #pragma unroll
-        for (int k = 0; k < 32; k++)
-            r[k & 7] += v[k];
+            for (int k = 0; k < 32; k++)
+                r[k & 7] += v[k];
+        }
+        for (; b < b1; b++)
+            r[(b - b0) & 7] += p[(size_t)b * (kWgMaxM * kWgMaxC)];
     }
-    for (; b + 8 <= nblk; b += 8)
-#pragma unroll
-        for (int k = 0; k < 8; k++)
-            r[k] += p[(size_t)(b + k) * (kWgMaxM * kWgMaxC)];
-    for (; b < nblk; b++)
-        r[b & 7] += p[(size_t)b * (kWgMaxM * kWgMaxC)];
-    const float acc = ((r[0] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7]));
+    part[seg][threadIdx.x & 63] = ((r[0] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7]));
+    __syncthreads();
+    if (seg != 0 || !live)
+        return;
+    const int i = threadIdx.x;
+    const float acc = (part[0][i] + part[1][i]) + (part[2][i] + part[3][i]);
     if (d.transposed)
         d.dst[c * d.ldw + m] = acc;
     else if (c < d.NW)
@@ -1240,7 +1250,8 @@ hipError_t decoder_weight_grads_bf16(TrainScratch &s, const fabric_gbuffer &g, i
     per_block = (per_block + 63) / 64 * 64;
     hipLaunchKernelGGL(wgrad_bf16_kernel, dim3(kWgBlocks, nj), dim3(256), 0, stream, jobs, n,
                        (const __bf16 *)s.acts, per_block, s.partials);
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((kWgMaxM * kWgMaxC + 255) / 256, nj), dim3(256), 0,
+    hipLaunchKernelGGL(wgrad_reduce_kernel,
+                       dim3((kWgMaxM * kWgMaxC + kWgRedEntries - 1) / kWgRedEntries, nj), dim3(256), 0,
                        stream, (const float *)s.partials, dests, kWgBlocks);
     return hipGetLastError();
 }
@@ -1311,7 +1322,8 @@ hipError_t train_bf16_fused(TrainScratch &s, const fabric_gbuffer &g, const DevF
                        fabrics, n_fabrics, (const float *)s.cfold, ffr, fb,
                        (const bf16x8 *)s.bwd_image, targets, s.loss_part, err, jobs, n_chunks,
                        s.partials);
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((kWgMaxM * kWgMaxC + 255) / 256, nj), dim3(256), 0,
+    hipLaunchKernelGGL(wgrad_reduce_kernel,
+                       dim3((kWgMaxM * kWgMaxC + kWgRedEntries - 1) / kWgRedEntries, nj), dim3(256), 0,
                        stream, (const float *)s.partials, dests, grid);
     return hipGetLastError();
 }
@@ -1348,7 +1360,8 @@ hipError_t decoder_weight_grads(TrainScratch &s, const fabric_gbuffer &g, int n_
     per_block = (per_block + 63) / 64 * 64;
     hipLaunchKernelGGL(wgrad_kernel, dim3(kWgBlocks, nj), dim3(256), 0, stream, jobs, n, per_block,
                        s.partials);
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((kWgMaxM * kWgMaxC + 255) / 256, nj), dim3(256), 0,
+    hipLaunchKernelGGL(wgrad_reduce_kernel,
+                       dim3((kWgMaxM * kWgMaxC + kWgRedEntries - 1) / kWgRedEntries, nj), dim3(256), 0,
                        stream, (const float *)s.partials, dests, kWgBlocks);
     return hipGetLastError();
 }
