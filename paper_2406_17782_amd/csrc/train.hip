@@ -210,7 +210,7 @@ __device__ inline TileSample load_tile_sample(const fabric_gbuffer &g,
 // come from `lw` (a copy in LDS: the L2 and L3 fragments, then the backward
 // ones, [fragment][lane]) instead of the packed images in global memory.
 template <int P, bool GIVEN_DY, typename Sink, bool LDSW = false>
-__device__ inline void fwd_bwd_tile(
+__device__ inline float fwd_bwd_tile(
     const fabric_gbuffer &g, const DevFabric *__restrict__ fabrics, int n_fabrics,
     const float *__restrict__ cfold, const typename Mfma<P>::Frag *__restrict__ ffr,
     const f32x4 *__restrict__ fbias, const typename Mfma<P>::Frag *__restrict__ bfr,
@@ -289,10 +289,11 @@ __device__ inline void fwd_bwd_tile(
         }
     }
     if (!GIVEN_DY) {
-        // Fixed-order sum of the 16 samples' terms; lane 0 stores the tile's part.
+        // Fixed-order sum of the 16 samples' terms (in lanes 0..15); lane 0
+        // stores the tile's part unless the caller sums the tiles itself.
         for (int off = 8; off > 0; off >>= 1)
             loss += __shfl_xor(loss, off, 64);
-        if (lane == 0)
+        if (loss_part && lane == 0)
             loss_part[tile] = loss;
     }
     // Every lane fetches its pixel's dy from lane group 0.
@@ -355,6 +356,7 @@ __device__ inline void fwd_bwd_tile(
             d1[mb][i] = a1[mb][i] > 0.0f ? d1[mb][i] : 0.0f;
 
     sink(p, valid, live, s1, a1, a2, a3, d1, d2, d3, dy, wi, wo);
+    return loss;
 }
 
 // Fused forward, loss and activation backward: one 16-sample tile per wave;
@@ -829,6 +831,8 @@ __global__ __launch_bounds__(64 * kFWaves) void train_bf16_fused_kernel(
 #pragma unroll
     for (int k = 0; k < kFMaxSlots; k++)
         acc[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // The loss terms of the wave's tiles, summed in chunk order (lane 0).
+    float wave_loss = 0.0f;
 
     // The samples of the wave's next tile, loaded one chunk ahead (during the
     // previous chunk's weight-gradient phase).
@@ -882,9 +886,9 @@ __global__ __launch_bounds__(64 * kFWaves) void train_bf16_fused_kernel(
         // registers for all chunks (they would not fit beside the tiles' sums).
         int wofs = 0;
         asm volatile("" : "+s"(wofs));
-        fwd_bwd_tile<FABRIC_BF16, false, decltype(sink) &, true>(
+        wave_loss += fwd_bwd_tile<FABRIC_BF16, false, decltype(sink) &, true>(
             g, fabrics, n_fabrics, cfold, ffr + wofs, fbias + wofs, bfr + wofs, targets, tile,
-            loss_part, err, sink, s_w + wofs, &cur);
+            nullptr, err, sink, s_w + wofs, &cur);
         __syncthreads();
         if (chunk + gridDim.x < n_chunks)
             next = load_tile_sample(g, targets, (chunk + gridDim.x) * kFWaves + w);
@@ -928,6 +932,18 @@ __global__ __launch_bounds__(64 * kFWaves) void train_bf16_fused_kernel(
             }
         }
         __syncthreads();
+    }
+
+    // ---- the block's loss part: its waves' sums in wave order ----
+    __shared__ float s_wave_loss[kFWaves];
+    if (lane == 0)
+        s_wave_loss[w] = wave_loss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float l = 0.0f;
+        for (int k = 0; k < kFWaves; k++)
+            l += s_wave_loss[k];
+        loss_part[blockIdx.x] = l;
     }
 
     // ---- the block's partial sums: register i of a tile holds row 4 q + i, column c ----
@@ -1275,7 +1291,7 @@ bool fused_fits(int n_fabrics) { return fused_tile_count(n_fabrics) <= kFMaxSlot
 // columns, and dcf.
 hipError_t train_bf16_fused(TrainScratch &s, const fabric_gbuffer &g, const DevFabric *fabrics,
                             int n_fabrics, const float *targets, unsigned long long *err,
-                            float *grad_dec, hipStream_t stream)
+                            float *grad_dec, int64_t *loss_parts, hipStream_t stream)
 {
     FusedJobs jobs{};
     WgDests dests{};
@@ -1314,6 +1330,7 @@ hipError_t train_bf16_fused(TrainScratch &s, const fabric_gbuffer &g, const DevF
     const int grid = (int)(n_chunks < s.n_cu ? n_chunks : s.n_cu);   // one block per CU
     if ((e = ensure_partials(s, nj, grid)) != hipSuccess)
         return e;
+    *loss_parts = grid;          // one loss part per block
     using M = Mfma<FABRIC_BF16>;
     using S = DecShape<M::KPL>;
     const auto *ffr = (const bf16x8 *)s.fwd_image;
@@ -1513,12 +1530,12 @@ hipError_t loss_and_grad(TrainScratch &s, const TrainArgs &a, hipStream_t stream
         // BF16 with at most 16 fabrics: one fused launch, the activations kept
         // on chip; otherwise the blocked BF16 planes through HBM.
         const bool fused = cfg.prec == FABRIC_BF16 && fused_fits(a.n_fabrics);
+        int64_t parts = (n + 15) / 16;       // one loss part per 16-sample tile
         e = cfg.prec == FABRIC_FP32
                 ? launch_fwd_bwd<FABRIC_FP32, false>(s, g, a.fabrics, a.n_fabrics, s.cfold, targets, err, stream)
-            : fused ? train_bf16_fused(s, g, a.fabrics, a.n_fabrics, targets, err, s.grad, stream)
+            : fused ? train_bf16_fused(s, g, a.fabrics, a.n_fabrics, targets, err, s.grad, &parts, stream)
                     : launch_fwd_bwd<FABRIC_BF16, false>(s, g, a.fabrics, a.n_fabrics, s.cfold, targets, err, stream);
         if (e != hipSuccess) return e;
-        const int64_t parts = (n + 15) / 16;
         if (parts <= 4096) {
             hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, stream,
                                (const float *)s.loss_part, parts, 1.0f / (float)n, s.loss);
